@@ -1,0 +1,602 @@
+/*
+ * CPU FP64 oracle for the coordinate-transformed Poisson multigrid
+ * (arXiv 2602.01888).  TEST INFRASTRUCTURE ONLY: the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg are its only users.
+ *
+ * It follows the paper's statement directly:
+ *   Section 2   : J = dx'/dxi (eq. 1), eps = det J J^-1 eps' J^-T (eq. 10,
+ *                 components eq. 12-15), rho = rho' det J (eq. 11);
+ *   Section 2.1 : the expanded equation eq. 17 discretised by central
+ *                 differences into the 9-point update eq. 18 with k1..k6;
+ *                 Gauss-Seidel at omega = 1 is the multigrid smoother;
+ *   Section 3   : residual correction eq. 19-24 on a hierarchy of grids;
+ *   Section 4   : error norms eq. 25-27; numeric Jacobian eq. 39-42.
+ * Where the paper leaves a choice open, the reading taken is stated at the
+ * function that makes it.  Loops are plain and unblocked on purpose.
+ */
+#include "tomg_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ID(i, j, nx) ((size_t)(j) * (size_t)(nx) + (size_t)(i))
+#define PLANE(st, k, n) ((st) + (size_t)(k) * (n))
+#define ORC_MAXL 16
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 2: Jacobian, permittivity, charge                                 */
+/* ------------------------------------------------------------------------ */
+
+/* d/dxi of a node field along i: eq. 39/41 in the interior; at i = 0 and
+ * i = nx-1 the second-order one-sided formulas (the paper does not say what
+ * it does on the edges). */
+static double d_along_i(const double *a, int nx, int i, int j, double h) {
+  if (i == 0)
+    return (-3.0 * a[ID(0, j, nx)] + 4.0 * a[ID(1, j, nx)] - a[ID(2, j, nx)]) / (2.0 * h);
+  if (i == nx - 1)
+    return (3.0 * a[ID(nx - 1, j, nx)] - 4.0 * a[ID(nx - 2, j, nx)] + a[ID(nx - 3, j, nx)]) /
+           (2.0 * h);
+  return (a[ID(i + 1, j, nx)] - a[ID(i - 1, j, nx)]) / (2.0 * h);
+}
+
+/* d/deta along j: eq. 40/42, same edge treatment. */
+static double d_along_j(const double *a, int nx, int ny, int i, int j, double h) {
+  if (j == 0)
+    return (-3.0 * a[ID(i, 0, nx)] + 4.0 * a[ID(i, 1, nx)] - a[ID(i, 2, nx)]) / (2.0 * h);
+  if (j == ny - 1)
+    return (3.0 * a[ID(i, ny - 1, nx)] - 4.0 * a[ID(i, ny - 2, nx)] + a[ID(i, ny - 3, nx)]) /
+           (2.0 * h);
+  return (a[ID(i, j + 1, nx)] - a[ID(i, j - 1, nx)]) / (2.0 * h);
+}
+
+int orc_jacobian_numeric(int nx, int ny, double dx, double dy, const double *xp,
+                         const double *yp, double *jxx, double *jxy, double *jyx,
+                         double *jyy) {
+  if (nx < 3 || ny < 3) return -1;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t c = ID(i, j, nx);
+      jxx[c] = d_along_i(xp, nx, i, j, dx);     /* dx'/dxi  (eq. 39) */
+      jxy[c] = d_along_j(xp, nx, ny, i, j, dy); /* dx'/deta (eq. 40) */
+      jyx[c] = d_along_i(yp, nx, i, j, dx);     /* dy'/dxi  (eq. 41) */
+      jyy[c] = d_along_j(yp, nx, ny, i, j, dy); /* dy'/deta (eq. 42) */
+    }
+  return 0;
+}
+
+void orc_permittivity(size_t n, const double *jxx, const double *jxy,
+                      const double *jyx, const double *jyy,
+                      const double *eps_phys, double *exx, double *exy,
+                      double *eyy, double *det) {
+  for (size_t c = 0; c < n; ++c) {
+    double D = jxx[c] * jyy[c] - jxy[c] * jyx[c];
+    double s = eps_phys ? eps_phys[c] : 1.0;
+    /* eq. 12, 13 (= eq. 14), 15 */
+    exx[c] = s * (jyy[c] * jyy[c] + jxy[c] * jxy[c]) / D;
+    exy[c] = s * (-jyy[c] * jyx[c] - jxy[c] * jxx[c]) / D;
+    eyy[c] = s * (jyx[c] * jyx[c] + jxx[c] * jxx[c]) / D;
+    det[c] = D;
+  }
+}
+
+int orc_geometry_ok(int nx, int ny, const double *det) {
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      int corner = (i == 0 || i == nx - 1) && (j == 0 || j == ny - 1);
+      if (corner) continue;
+      double D = det[ID(i, j, nx)];
+      if (!(D > 0.0)) return 0;
+    }
+  return 1;
+}
+
+void orc_rhs(size_t n, const double *rho_phys, const double *det, double *f) {
+  /* eq. 11 gives rho = rho' det J; the equation solved is
+   * div(eps grad phi) = -rho (eq. 7 and 17 with E = -grad phi). */
+  for (size_t c = 0; c < n; ++c) f[c] = -rho_phys[c] * det[c];
+}
+
+void orc_dirichlet_set(int nx, int ny, const uint8_t *mask, uint8_t *dir) {
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      int ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+      dir[ID(i, j, nx)] = (uint8_t)(ring || (mask && mask[ID(i, j, nx)]));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 2.1: the 9-point operator                                         */
+/* ------------------------------------------------------------------------ */
+
+/* At a free node the discrete equation is
+ *   k1 phi_E + k3 phi_W + k4 phi_N + k5 phi_S
+ *     + k6 (phi_NE - phi_NW - phi_SE + phi_SW) - k2 phi_C = f,
+ * i.e. eq. 18 before the division by k2 (the printed update omits that
+ * division from the neighbour terms; expanding eq. 17 by central differences
+ * puts it on every term).  eps_yx = eps_xy (eq. 13 = eq. 14). */
+void orc_fine_stencil(int nx, int ny, double dx, double dy, const double *exx,
+                      const double *exy, const double *eyy, const uint8_t *dir,
+                      double *st) {
+  size_t n = (size_t)nx * ny;
+  memset(st, 0, 9 * n * sizeof(double));
+  double idx2 = 1.0 / (dx * dx), idy2 = 1.0 / (dy * dy), idxy = 1.0 / (dx * dy);
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t c = ID(i, j, nx);
+      if (dir[c]) {
+        PLANE(st, 4, n)[c] = 1.0;
+        continue;
+      }
+      size_t e = ID(i + 1, j, nx), w = ID(i - 1, j, nx);
+      size_t no = ID(i, j + 1, nx), so = ID(i, j - 1, nx);
+      double k2 = 2.0 * (exx[c] * idx2 + eyy[c] * idy2);
+      double gx = (exx[e] - exx[w]) * idx2 / 4.0 + (exy[no] - exy[so]) * idxy / 4.0;
+      double gy = (eyy[no] - eyy[so]) * idy2 / 4.0 + (exy[e] - exy[w]) * idxy / 4.0;
+      double k1 = exx[c] * idx2 + gx;
+      double k3 = exx[c] * idx2 - gx;
+      double k4 = eyy[c] * idy2 + gy;
+      double k5 = eyy[c] * idy2 - gy;
+      double k6 = exy[c] * idxy / 2.0;
+      PLANE(st, 0, n)[c] = k6;  /* SW */
+      PLANE(st, 1, n)[c] = k5;  /* S  */
+      PLANE(st, 2, n)[c] = -k6; /* SE */
+      PLANE(st, 3, n)[c] = k3;  /* W  */
+      PLANE(st, 4, n)[c] = -k2; /* C  */
+      PLANE(st, 5, n)[c] = k1;  /* E  */
+      PLANE(st, 6, n)[c] = -k6; /* NW */
+      PLANE(st, 7, n)[c] = k4;  /* N  */
+      PLANE(st, 8, n)[c] = k6;  /* NE */
+    }
+}
+
+/* Sum of the off-centre stencil terms at (i, j). */
+static double offcentre(int nx, size_t n, const double *st, const double *x, int i, int j) {
+  double s = 0.0;
+  for (int dj = -1; dj <= 1; ++dj)
+    for (int di = -1; di <= 1; ++di) {
+      if (di == 0 && dj == 0) continue;
+      int k = (dj + 1) * 3 + (di + 1);
+      s += PLANE(st, k, n)[ID(i, j, nx)] * x[ID(i + di, j + dj, nx)];
+    }
+  return s;
+}
+
+void orc_apply(int nx, int ny, const double *st, const uint8_t *dir,
+               const double *x, double *y) {
+  size_t n = (size_t)nx * ny;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t c = ID(i, j, nx);
+      y[c] = dir[c] ? 0.0 : offcentre(nx, n, st, x, i, j) + PLANE(st, 4, n)[c] * x[c];
+    }
+}
+
+/* Residual of eq. 20, r = b - A x, on free nodes; zero on Dirichlet nodes. */
+void orc_residual(int nx, int ny, const double *st, const uint8_t *dir,
+                  const double *x, const double *b, double *r) {
+  size_t n = (size_t)nx * ny;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t c = ID(i, j, nx);
+      r[c] = dir[c] ? 0.0 : b[c] - (offcentre(nx, n, st, x, i, j) + PLANE(st, 4, n)[c] * x[c]);
+    }
+}
+
+double orc_norm2_free(int nx, int ny, const uint8_t *dir, const double *r) {
+  double s = 0.0;
+  for (size_t c = 0; c < (size_t)nx * ny; ++c)
+    if (!dir[c]) s += r[c] * r[c];
+  return sqrt(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Smoothers (Section 2.1: Gauss-Seidel, i.e. omega = 1, smooths)            */
+/* ------------------------------------------------------------------------ */
+
+static void relax(int nx, size_t n, const double *st, double *x, const double *b, int i, int j) {
+  size_t c = ID(i, j, nx);
+  x[c] = (b[c] - offcentre(nx, n, st, x, i, j)) / PLANE(st, 4, n)[c];
+}
+
+/* Paper-faithful ordering: eq. 18 reads new values at i-1 (every j) and at
+ * (i, j-1), i.e. an outer loop over i and an inner loop over j. */
+static void sweep_lex(int nx, int ny, const double *st, const uint8_t *dir, double *x,
+                      const double *b) {
+  size_t n = (size_t)nx * ny;
+  for (int i = 1; i < nx - 1; ++i)
+    for (int j = 1; j < ny - 1; ++j)
+      if (!dir[ID(i, j, nx)]) relax(nx, n, st, x, b, i, j);
+}
+
+/* Four-colour ordering: colour (i mod 2) + 2 (j mod 2), colours 0,1,2,3 in
+ * turn.  No two nodes of one colour are 9-point neighbours, so each colour
+ * is an independent set and the result does not depend on the order inside
+ * a colour. */
+static void sweep_gs4(int nx, int ny, const double *st, const uint8_t *dir, double *x,
+                      const double *b) {
+  size_t n = (size_t)nx * ny;
+  for (int colour = 0; colour < 4; ++colour) {
+    int pi = colour & 1, pj = colour >> 1;
+#pragma omp parallel for schedule(static)
+    for (int j = 1 + ((1 + pj) & 1); j < ny - 1; j += 2)
+      for (int i = 1 + ((1 + pi) & 1); i < nx - 1; i += 2)
+        if (!dir[ID(i, j, nx)]) relax(nx, n, st, x, b, i, j);
+  }
+}
+
+/* Damped Jacobi: x <- x + omega (b - A x) / A_CC. */
+static void sweep_jacobi(int nx, int ny, const double *st, const uint8_t *dir, double *x,
+                         const double *b, double omega) {
+  size_t n = (size_t)nx * ny;
+  double *r = (double *)malloc(n * sizeof(double));
+  orc_residual(nx, ny, st, dir, x, b, r);
+  for (size_t c = 0; c < n; ++c)
+    if (!dir[c]) x[c] += omega * r[c] / PLANE(st, 4, n)[c];
+  free(r);
+}
+
+void orc_smooth(int nx, int ny, const double *st, const uint8_t *dir, double *x,
+                const double *b, int kind, int sweeps, double omega) {
+  for (int s = 0; s < sweeps; ++s) {
+    if (kind == ORC_GS_LEX)
+      sweep_lex(nx, ny, st, dir, x, b);
+    else if (kind == ORC_JACOBI)
+      sweep_jacobi(nx, ny, st, dir, x, b, omega);
+    else
+      sweep_gs4(nx, ny, st, dir, x, b);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3: grid transfers and the coarse operator                         */
+/* ------------------------------------------------------------------------ */
+
+/* Bilinear interpolation weight of a coarse node for a fine node at offset
+ * d = fine index - 2 * coarse index along one axis. */
+static double pw(int d) { return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0; }
+
+/* Full-weighting restriction I_h^H (the paper does not name one):
+ * r_H(I,J) = (1/16) [4 r(2I,2J) + 2 (edge neighbours) + (corner neighbours)],
+ * at coarse interior nodes; zero on the coarse outer ring.  This is the
+ * transpose of bilinear prolongation divided by 4. */
+void orc_restrict_fw(int nxf, int nyf, const double *rf, int nxc, int nyc, double *fc) {
+  (void)nyf;
+  for (int J = 0; J < nyc; ++J)
+    for (int I = 0; I < nxc; ++I) {
+      double s = 0.0;
+      if (I > 0 && J > 0 && I < nxc - 1 && J < nyc - 1)
+        for (int dj = -1; dj <= 1; ++dj)
+          for (int di = -1; di <= 1; ++di)
+            s += pw(di) * pw(dj) / 4.0 * rf[ID(2 * I + di, 2 * J + dj, nxf)];
+      fc[ID(I, J, nxc)] = s;
+    }
+}
+
+/* Bilinear prolongation I_H^h and the correction of eq. 24, applied at free
+ * fine nodes only (Dirichlet values are never changed). */
+void orc_prolong_add(int nxc, int nyc, const double *ec, int nxf, int nyf,
+                     const uint8_t *dirf, double *xf) {
+  (void)nyc;
+  for (int j = 0; j < nyf; ++j)
+    for (int i = 0; i < nxf; ++i) {
+      if (dirf[ID(i, j, nxf)]) continue;
+      double s = 0.0;
+      for (int J = j / 2; J <= (j + 1) / 2; ++J)
+        for (int I = i / 2; I <= (i + 1) / 2; ++I)
+          s += pw(i - 2 * I) * pw(j - 2 * J) * ec[ID(I, J, nxc)];
+      xf[ID(i, j, nxf)] += s;
+    }
+}
+
+/* Coarse operator of eq. 23.  The paper does not say how A_H is formed; the
+ * reading taken is the Galerkin product A_H = (1/4) P^T A_h P with P the
+ * bilinear prolongation restricted to the unknowns: rows of P at fine
+ * Dirichlet nodes are zero, and only coarse nodes that are not Dirichlet
+ * carry a column.  A coarse node is Dirichlet when it lies on the coarse
+ * outer ring or when every fine node it interpolates to is Dirichlet (its
+ * column of P would be empty); such nodes get an identity row. */
+void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
+                  int nxc, int nyc, double *stc, uint8_t *dirc) {
+  size_t nf = (size_t)nxf * nyf, nc = (size_t)nxc * nyc;
+  for (int J = 0; J < nyc; ++J)
+    for (int I = 0; I < nxc; ++I) {
+      int d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
+      if (!d) {
+        int any_free = 0;
+        for (int dj = -1; dj <= 1; ++dj)
+          for (int di = -1; di <= 1; ++di)
+            if (!dirf[ID(2 * I + di, 2 * J + dj, nxf)]) any_free = 1;
+        d = !any_free;
+      }
+      dirc[ID(I, J, nxc)] = (uint8_t)d;
+    }
+  memset(stc, 0, 9 * nc * sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int J = 0; J < nyc; ++J)
+    for (int I = 0; I < nxc; ++I) {
+      size_t C = ID(I, J, nxc);
+      if (dirc[C]) {
+        PLANE(stc, 4, nc)[C] = 1.0;
+        continue;
+      }
+      double acc[9] = {0};
+      /* row I of P^T: fine nodes f = (2I+a, 2J+b) with weight pw(a) pw(b) */
+      for (int b = -1; b <= 1; ++b)
+        for (int a = -1; a <= 1; ++a) {
+          int fi = 2 * I + a, fj = 2 * J + b;
+          size_t f = ID(fi, fj, nxf);
+          if (dirf[f]) continue;
+          double wf = pw(a) * pw(b);
+          /* row f of A_h: neighbours g = f + (p, q) */
+          for (int q = -1; q <= 1; ++q)
+            for (int p = -1; p <= 1; ++p) {
+              int gi = fi + p, gj = fj + q;
+              size_t g = ID(gi, gj, nxf);
+              if (dirf[g]) continue;
+              double a_fg = PLANE(stf, (q + 1) * 3 + (p + 1), nf)[f];
+              /* column K of P: coarse nodes K with |g - 2K| <= 1 */
+              for (int KJ = gj / 2; KJ <= (gj + 1) / 2; ++KJ)
+                for (int KI = gi / 2; KI <= (gi + 1) / 2; ++KI) {
+                  int oi = KI - I, oj = KJ - J;
+                  if (oi < -1 || oi > 1 || oj < -1 || oj > 1) continue;
+                  if (dirc[ID(KI, KJ, nxc)]) continue;
+                  double wg = pw(gi - 2 * KI) * pw(gj - 2 * KJ);
+                  acc[(oj + 1) * 3 + (oi + 1)] += wf * a_fg * wg;
+                }
+            }
+        }
+      for (int k = 0; k < 9; ++k) PLANE(stc, k, nc)[C] = acc[k] / 4.0;
+    }
+}
+
+int orc_dense_solve(int m, double *A, double *b) {
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int r = k + 1; r < m; ++r)
+      if (fabs(A[(size_t)r * m + k]) > fabs(A[(size_t)p * m + k])) p = r;
+    if (A[(size_t)p * m + k] == 0.0) return -1;
+    if (p != k) {
+      for (int c = 0; c < m; ++c) {
+        double t = A[(size_t)k * m + c];
+        A[(size_t)k * m + c] = A[(size_t)p * m + c];
+        A[(size_t)p * m + c] = t;
+      }
+      double t = b[k];
+      b[k] = b[p];
+      b[p] = t;
+    }
+    for (int r = k + 1; r < m; ++r) {
+      double l = A[(size_t)r * m + k] / A[(size_t)k * m + k];
+      for (int c = k; c < m; ++c) A[(size_t)r * m + c] -= l * A[(size_t)k * m + c];
+      b[r] -= l * b[k];
+    }
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int c = k + 1; c < m; ++c) s -= A[(size_t)k * m + c] * b[c];
+    b[k] = s / A[(size_t)k * m + k];
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3: the V-cycle                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Grid hierarchy: halve while both node counts minus one are even and each
+ * side keeps at least 3 nodes; always coarsen at least once, then keep
+ * coarsening while either side exceeds 9 nodes.  Returns the number of
+ * levels, or 0 when the grid cannot reach a coarsest level of at most 9x9
+ * nodes. */
+int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl) {
+  int L = 1;
+  nxs[0] = nx;
+  nys[0] = ny;
+  if (nx < 5 || ny < 5) return 0;
+  while (L < maxl) {
+    int cx = nxs[L - 1], cy = nys[L - 1];
+    int can = ((cx - 1) % 2 == 0) && ((cy - 1) % 2 == 0) && cx >= 5 && cy >= 5;
+    int want = (L == 1) || cx > 9 || cy > 9;
+    if (!(can && want)) break;
+    nxs[L] = (cx - 1) / 2 + 1;
+    nys[L] = (cy - 1) / 2 + 1;
+    ++L;
+  }
+  if (L < 2 || nxs[L - 1] > 9 || nys[L - 1] > 9) return 0;
+  return L;
+}
+
+struct orc_mg {
+  int L, nu1, nu2, smoother;
+  double omega;
+  int nx[ORC_MAXL], ny[ORC_MAXL];
+  double *st[ORC_MAXL];
+  uint8_t *dir[ORC_MAXL];
+  double *x[ORC_MAXL], *b[ORC_MAXL], *r[ORC_MAXL];
+  int m;        /* unknowns on the coarsest level */
+  int *cidx;    /* coarsest node -> unknown index, or -1 */
+  double *Ac;   /* coarsest matrix, m*m */
+  double *work; /* m*m + m scratch */
+};
+
+orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
+                      const double *exy, const double *eyy, const uint8_t *mask,
+                      int nu1, int nu2, int smoother, double omega) {
+  orc_mg *mg = (orc_mg *)calloc(1, sizeof(orc_mg));
+  mg->L = orc_levels(nx, ny, mg->nx, mg->ny, ORC_MAXL);
+  if (mg->L == 0) {
+    free(mg);
+    return NULL;
+  }
+  mg->nu1 = nu1;
+  mg->nu2 = nu2;
+  mg->smoother = smoother;
+  mg->omega = omega;
+  for (int l = 0; l < mg->L; ++l) {
+    size_t n = (size_t)mg->nx[l] * mg->ny[l];
+    mg->st[l] = (double *)calloc(9 * n, sizeof(double));
+    mg->dir[l] = (uint8_t *)calloc(n, 1);
+    mg->x[l] = (double *)calloc(n, sizeof(double));
+    mg->b[l] = (double *)calloc(n, sizeof(double));
+    mg->r[l] = (double *)calloc(n, sizeof(double));
+  }
+  orc_dirichlet_set(nx, ny, mask, mg->dir[0]);
+  orc_fine_stencil(nx, ny, dx, dy, exx, exy, eyy, mg->dir[0], mg->st[0]);
+  for (int l = 1; l < mg->L; ++l)
+    orc_galerkin(mg->nx[l - 1], mg->ny[l - 1], mg->st[l - 1], mg->dir[l - 1], mg->nx[l],
+                 mg->ny[l], mg->st[l], mg->dir[l]);
+  /* coarsest dense system over its free nodes */
+  int l = mg->L - 1, cx = mg->nx[l], cy = mg->ny[l];
+  size_t nc = (size_t)cx * cy;
+  mg->cidx = (int *)malloc(nc * sizeof(int));
+  mg->m = 0;
+  for (size_t c = 0; c < nc; ++c) mg->cidx[c] = mg->dir[l][c] ? -1 : mg->m++;
+  mg->Ac = (double *)calloc((size_t)mg->m * mg->m + 1, sizeof(double));
+  mg->work = (double *)calloc((size_t)mg->m * mg->m + mg->m + 1, sizeof(double));
+  for (int J = 0; J < cy; ++J)
+    for (int I = 0; I < cx; ++I) {
+      int row = mg->cidx[ID(I, J, cx)];
+      if (row < 0) continue;
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          int col = mg->cidx[ID(I + di, J + dj, cx)];
+          if (col < 0) continue;
+          mg->Ac[(size_t)row * mg->m + col] =
+              PLANE(mg->st[l], (dj + 1) * 3 + (di + 1), nc)[ID(I, J, cx)];
+        }
+    }
+  return mg;
+}
+
+void orc_mg_destroy(orc_mg *mg) {
+  if (!mg) return;
+  for (int l = 0; l < mg->L; ++l) {
+    free(mg->st[l]);
+    free(mg->dir[l]);
+    free(mg->x[l]);
+    free(mg->b[l]);
+    free(mg->r[l]);
+  }
+  free(mg->cidx);
+  free(mg->Ac);
+  free(mg->work);
+  free(mg);
+}
+
+int orc_mg_num_levels(const orc_mg *mg) { return mg->L; }
+void orc_mg_level_shape(const orc_mg *mg, int l, int *nx, int *ny) {
+  *nx = mg->nx[l];
+  *ny = mg->ny[l];
+}
+const double *orc_mg_stencil(const orc_mg *mg, int l) { return mg->st[l]; }
+const uint8_t *orc_mg_dir(const orc_mg *mg, int l) { return mg->dir[l]; }
+const double *orc_mg_level_rhs(const orc_mg *mg, int l) { return mg->b[l]; }
+const double *orc_mg_level_x(const orc_mg *mg, int l) { return mg->x[l]; }
+
+/* Coarsest level: solve A_H x = b exactly (the paper leaves the coarse
+ * solver open; a direct solve is taken). */
+static void coarsest_solve(orc_mg *mg, double *x, const double *b) {
+  int l = mg->L - 1, cx = mg->nx[l], cy = mg->ny[l], m = mg->m;
+  size_t nc = (size_t)cx * cy;
+  double *A = mg->work, *rhs = mg->work + (size_t)m * m;
+  memcpy(A, mg->Ac, (size_t)m * m * sizeof(double));
+  for (size_t c = 0; c < nc; ++c)
+    if (mg->cidx[c] >= 0) rhs[mg->cidx[c]] = b[c];
+  orc_dense_solve(m, A, rhs);
+  for (size_t c = 0; c < nc; ++c) x[c] = mg->cidx[c] >= 0 ? rhs[mg->cidx[c]] : 0.0;
+}
+
+/* One V(nu1, nu2) cycle at level l on (x, b): pre-smoothing, residual
+ * (eq. 20), restriction to the coarse right-hand side (eq. 23), recursive
+ * coarse solve from a zero guess, prolongation and correction (eq. 24),
+ * post-smoothing. */
+static void vcycle_level(orc_mg *mg, int l, double *x, const double *b) {
+  int nx = mg->nx[l], ny = mg->ny[l];
+  if (l == mg->L - 1) {
+    coarsest_solve(mg, x, b);
+    return;
+  }
+  orc_smooth(nx, ny, mg->st[l], mg->dir[l], x, b, mg->smoother, mg->nu1, mg->omega);
+  orc_residual(nx, ny, mg->st[l], mg->dir[l], x, b, mg->r[l]);
+  orc_restrict_fw(nx, ny, mg->r[l], mg->nx[l + 1], mg->ny[l + 1], mg->b[l + 1]);
+  memset(mg->x[l + 1], 0, (size_t)mg->nx[l + 1] * mg->ny[l + 1] * sizeof(double));
+  vcycle_level(mg, l + 1, mg->x[l + 1], mg->b[l + 1]);
+  orc_prolong_add(mg->nx[l + 1], mg->ny[l + 1], mg->x[l + 1], nx, ny, mg->dir[l], x);
+  orc_smooth(nx, ny, mg->st[l], mg->dir[l], x, b, mg->smoother, mg->nu2, mg->omega);
+}
+
+void orc_mg_vcycle(orc_mg *mg, double *phi, const double *f) { vcycle_level(mg, 0, phi, f); }
+
+/* ||f - A phi0||_2 over free nodes with phi0 = phi on Dirichlet nodes and 0
+ * on free nodes: the norm the stopping test divides by. */
+double orc_mg_initial_residual(orc_mg *mg, const double *phi, const double *f) {
+  int nx = mg->nx[0], ny = mg->ny[0];
+  size_t n = (size_t)nx * ny;
+  double *z = mg->x[0];
+  for (size_t c = 0; c < n; ++c) z[c] = mg->dir[0][c] ? phi[c] : 0.0;
+  orc_residual(nx, ny, mg->st[0], mg->dir[0], z, f, mg->r[0]);
+  return orc_norm2_free(nx, ny, mg->dir[0], mg->r[0]);
+}
+
+int orc_mg_solve(orc_mg *mg, double *phi, const double *f, double rel_tol,
+                 int max_cycles, int *cycles_out, double *rel_out, double *hist,
+                 int hist_len) {
+  int nx = mg->nx[0], ny = mg->ny[0];
+  double b0 = orc_mg_initial_residual(mg, phi, f);
+  int cycles = 0;
+  double rel;
+  orc_residual(nx, ny, mg->st[0], mg->dir[0], phi, f, mg->r[0]);
+  double rn = orc_norm2_free(nx, ny, mg->dir[0], mg->r[0]);
+  rel = b0 > 0.0 ? rn / b0 : 0.0;
+  if (hist && hist_len > 0) hist[0] = rel;
+  int status = 1;
+  while (1) {
+    if (!isfinite(rel)) {
+      status = 2;
+      break;
+    }
+    if (rel <= rel_tol) {
+      status = 0;
+      break;
+    }
+    if (cycles >= max_cycles) break;
+    orc_mg_vcycle(mg, phi, f);
+    ++cycles;
+    orc_residual(nx, ny, mg->st[0], mg->dir[0], phi, f, mg->r[0]);
+    rn = orc_norm2_free(nx, ny, mg->dir[0], mg->r[0]);
+    rel = rn / b0;
+    if (hist && cycles < hist_len) hist[cycles] = rel;
+  }
+  *cycles_out = cycles;
+  *rel_out = rel;
+  return status;
+}
+
+void orc_error_norms(size_t n, const double *a, const double *b, double *out) {
+  double linf = 0.0, s2 = 0.0, s1 = 0.0;
+  for (size_t c = 0; c < n; ++c) {
+    double e = fabs(a[c] - b[c]);
+    if (e > linf) linf = e;
+    s2 += e * e;
+    s1 += e;
+  }
+  out[0] = linf;                    /* eq. 25 */
+  out[1] = sqrt(s2 / (double)n);    /* eq. 26, N^2 = number of nodes */
+  out[2] = s1 / (double)n;          /* eq. 27 */
+}
