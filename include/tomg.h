@@ -1,0 +1,184 @@
+/*
+ * tomg — geometric multigrid for the coordinate-transformed Poisson equation
+ * on a uniform computational grid, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gautam & Paradkar, "Multigrid Poisson Solver for Complex Geometries
+ * Using Finite Difference Method", arXiv 2602.01888.  A map from the uniform
+ * computational grid (xi, eta) to the physical domain (x', y') with Jacobian
+ * J = dx'/dxi (eq. 1) turns the physical problem div'(eps' grad' phi) = -rho'
+ * into div(eps grad phi) = -rho on the uniform grid, with
+ *   eps = det J * J^-1 eps' J^-T            (eq. 10; components eq. 12-15)
+ *   rho = rho' det J                        (eq. 11)
+ * and phi unchanged (eq. 6).  The 9-point central-difference discretisation
+ * of the expanded equation (eq. 17-18, coefficients k1..k6) is solved by a
+ * multigrid V-cycle (Section 3, eq. 19-24).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - A node field is an array of nx*ny values, row-major with x fastest:
+ *    node (i, j) is element j*nx + i; i runs along xi (spacing dx), j along
+ *    eta (spacing dy).  Doubles unless stated.
+ *  - Pointers named d_* are device pointers (HIP global memory on the GPU the
+ *    problem was created on).  Host pointers are named without prefix.
+ *  - The caller owns every buffer: the workspace, phi and all inputs.  The
+ *    library never allocates or frees device memory.
+ *  - Every call enqueues its work on the problem's stream, in stream order.
+ *    Calls that return host values (solve, residual_norm, setup_coeffs)
+ *    synchronise that stream; vcycle and tomg_update_rhs do not.
+ *  - The outer ring of nodes and the nodes flagged in the mask are Dirichlet
+ *    nodes; their values are taken from phi and are never written.  The
+ *    problem solved is
+ *        (A phi)_c = f_c  at free nodes c,      phi_d = given at Dirichlet d,
+ *    where A is the operator of eq. 18 and f = -rho' det J.
+ *  - Errors are returned as tomg_status; nothing aborts and no exception
+ *    crosses this interface.  tomg_last_error() describes the last failure.
+ *  - Different problems may be used concurrently from different host threads
+ *    on different streams; one problem must not be used concurrently.
+ */
+#ifndef TOMG_H
+#define TOMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tomg_problem tomg_problem;
+
+typedef enum {
+  TOMG_OK = 0,
+  TOMG_EINVAL = -1,     /* bad argument: NULL, sizes not coarsenable, tol <= 0 ... */
+  TOMG_ENOMEM = -2,     /* workspace smaller than tomg_workspace_bytes() */
+  TOMG_EGEOMETRY = -3,  /* det J <= 0 at a node other than the four corners */
+  TOMG_ENOCONV = -4,    /* max_cycles reached; phi holds the last iterate */
+  TOMG_ENONFINITE = -5, /* NaN/Inf in the coefficients, the source or the residual */
+  TOMG_EDEVICE = -6,    /* a HIP runtime call failed */
+  TOMG_ESTATE = -7      /* call out of order (e.g. vcycle before setup_coeffs) */
+} tomg_status;
+
+enum { TOMG_FP64 = 0, TOMG_FP32_IR = 1 };
+enum { TOMG_GS4 = 0, TOMG_JACOBI = 1 };
+
+typedef struct {
+  int32_t nx, ny;          /* nodes including the outer ring; (nx-1) and (ny-1)
+                              must halve down to a coarsest grid of at most
+                              9 x 9 nodes (e.g. 2^k + 1), nx, ny >= 5 */
+  double xi0, eta0;        /* computational coordinates of node (0, 0) */
+  double dx, dy;           /* computational spacings (dx != dy allowed) */
+  int32_t precision;       /* TOMG_FP64, or TOMG_FP32_IR: FP32 V-cycles as the
+                              inner solver of FP64 iterative refinement */
+  int32_t nu1, nu2;        /* pre/post smoothing sweeps, 1..4 (default 2, 2) */
+  int32_t smoother;        /* TOMG_GS4 (four-colour Gauss-Seidel, default) or
+                              TOMG_JACOBI (damped Jacobi) */
+  double jacobi_omega;     /* damping of TOMG_JACOBI (default 0.8) */
+  int32_t ir_inner_cycles; /* FP32 V-cycles per refinement step (default 2) */
+  int32_t reserved[3];     /* set to zero */
+} tomg_config;
+
+/* Fills *cfg with the defaults above for an nx x ny grid of spacing dx, dy. */
+void tomg_config_default(tomg_config *cfg, int32_t nx, int32_t ny, double dx, double dy);
+
+/* Number of grid levels for cfg (>= 2), or 0 when the sizes do not coarsen
+ * to a grid of at most 9 x 9 nodes. */
+int32_t tomg_num_levels(const tomg_config *cfg);
+
+/* Bytes of device workspace the problem needs (0 for an invalid config).
+ * This is the problem's whole device footprint besides phi and the inputs,
+ * so it is what a scheduler admits requests against. */
+size_t tomg_workspace_bytes(const tomg_config *cfg);
+
+/* Creates a problem on the current HIP device.  d_ws: caller-owned device
+ * workspace of at least tomg_workspace_bytes(cfg) bytes, 256-byte aligned,
+ * kept alive until tomg_destroy.  stream: a hipStream_t (NULL = the null
+ * stream).  Host state only is allocated.  *out is NULL on failure. */
+tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, void *stream,
+                        tomg_problem **out);
+
+/* Frees the host state.  The caller frees the workspace afterwards. */
+void tomg_destroy(tomg_problem *p);
+
+/* Human-readable description of the last error on p (never NULL). */
+const char *tomg_last_error(const tomg_problem *p);
+
+/* Re-targets the problem to another stream (same device). */
+tomg_status tomg_set_stream(tomg_problem *p, void *stream);
+
+/* Coefficient setup (eq. 1, 10-15, 11; numeric Jacobian eq. 39-42), then the
+ * coarse-grid hierarchy.
+ *   d_xp, d_yp : physical coordinates x'(xi_ij), y'(xi_ij); used for the
+ *                numeric Jacobian (central differences inside, second-order
+ *                one-sided differences on the edges).  Ignored when d_jac is
+ *                given.
+ *   d_jac      : nullable; 4 planes of nx*ny: dx'/dxi, dx'/deta, dy'/dxi,
+ *                dy'/deta (J_xx, J_xy, J_yx, J_yy) for an analytic map.
+ *   d_eps_phys : nullable; isotropic physical permittivity per node (NULL = 1).
+ *   d_rho_phys : physical charge density rho' at the mapped nodes.
+ *   d_mask     : nullable; uint8 per node, nonzero = interior Dirichlet node.
+ * Inputs are read in stream order and may be freed once the call returns.
+ * Returns TOMG_EGEOMETRY when det J <= 0 at any node but the four corners
+ * (the operator never reads the corners), TOMG_ENONFINITE on NaN/Inf. */
+tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp,
+                         const double *d_jac, const double *d_eps_phys,
+                         const double *d_rho_phys, const uint8_t *d_mask);
+
+/* New source on the same geometry: f = -rho' det J from the stored det J
+ * (eq. 11), without rebuilding the hierarchy.  Asynchronous. */
+tomg_status tomg_update_rhs(tomg_problem *p, const double *d_rho_phys);
+
+/* One V(nu1, nu2) cycle (Section 3, eq. 19-24) applied in place to d_phi.
+ * Asynchronous.  For TOMG_FP32_IR problems this is one refinement step
+ * (FP64 residual, ir_inner_cycles FP32 V-cycles, FP64 update). */
+tomg_status vcycle(tomg_problem *p, double *d_phi);
+
+/* Repeats vcycle until ||f - A phi||_2 / ||f - A phi0||_2 <= rel_tol over
+ * free nodes, where phi0 has the Dirichlet values of d_phi and zeros
+ * elsewhere; d_phi is the initial guess on entry.  Host outputs (nullable):
+ * *cycles_out cycles (refinement steps for TOMG_FP32_IR) taken, *rel_res_out
+ * the final relative residual.  Returns TOMG_ENOCONV with phi holding the last
+ * iterate if max_cycles is reached, TOMG_ENONFINITE if the residual becomes
+ * NaN/Inf. */
+tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cycles,
+                  int32_t *cycles_out, double *rel_res_out);
+
+/* abs = ||f - A phi||_2 over free nodes; rel = abs / ||f - A phi0||_2 (0 when
+ * the denominator is 0).  Host outputs, nullable. */
+tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
+                          double *rel_out);
+
+/* Solves n independent problems together: each V-cycle stage is launched
+ * once across all problems still iterating, on the first problem's stream,
+ * and a problem leaves the batch as soon as it converges.  Per-problem host
+ * outputs cycles_out[n], rel_out[n], status_out[n] (nullable).  Returns
+ * TOMG_OK when every problem converged, else the first failing status.  The
+ * per-problem arithmetic is the same as solve(), so each result is bitwise
+ * equal to the problem solved alone. */
+tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, int32_t n,
+                             double rel_tol, int32_t max_cycles, int32_t *cycles_out,
+                             double *rel_out, tomg_status *status_out);
+
+/* ---- diagnostics: read back internal arrays (parity testing) ----------- */
+enum {
+  TOMG_FIELD_EXX = 0,    /* level 0, nx*ny doubles */
+  TOMG_FIELD_EXY = 1,
+  TOMG_FIELD_EYY = 2,
+  TOMG_FIELD_DET = 3,
+  TOMG_FIELD_RHS = 4,    /* level 0 f, or level l >= 1 coarse right-hand side */
+  TOMG_FIELD_DIR = 5,    /* uint8 Dirichlet flags of level l */
+  TOMG_FIELD_STENCIL = 6,/* level l >= 1: 9 planes, plane k = (dj+1)*3+(di+1) */
+  TOMG_FIELD_X = 7       /* level l >= 1 correction from the last V-cycle */
+};
+/* Copies array `what` of level `level` into d_out (device); asynchronous. */
+tomg_status tomg_export(tomg_problem *p, int32_t what, int32_t level, void *d_out);
+/* Level (nx, ny) of a created problem (host outputs). */
+tomg_status tomg_level_shape(const tomg_problem *p, int32_t level, int32_t *nx, int32_t *ny);
+/* `sweeps` smoothing sweeps on level 0 in place (asynchronous). */
+tomg_status tomg_smooth(tomg_problem *p, double *d_phi, int32_t sweeps);
+/* d_r = f - A phi at free nodes, 0 at Dirichlet nodes (asynchronous). */
+tomg_status tomg_residual(tomg_problem *p, const double *d_phi, double *d_r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOMG_H */

@@ -1,0 +1,246 @@
+"""tomg: geometric multigrid for the coordinate-transformed Poisson equation
+(arXiv 2602.01888) on AMD Instinct MI355X.
+
+Python binding of ``libtomg.so`` (``include/tomg.h``).  Tensors are torch
+tensors on the GPU; the workspace is a torch uint8 tensor, so PyTorch's
+caching allocator owns all device memory.  Names follow the C-ABI:
+``setup_coeffs``, ``vcycle``, ``solve``, ``residual_norm`` (methods of
+``Problem`` and module functions taking a ``Problem``)."""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch  # noqa: F401  (binds the HIP runtime before the library loads)
+
+from . import _lib
+from ._lib import (FIELD, STATUS_NAMES, TOMG_EGEOMETRY, TOMG_EINVAL, TOMG_ENOCONV,  # noqa: F401
+                   TOMG_ENOMEM, TOMG_ENONFINITE, TOMG_ESTATE, TOMG_FP32_IR, TOMG_FP64,
+                   TOMG_GS4, TOMG_JACOBI, TOMG_OK, Config)
+
+
+class TomgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
+                smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2) -> Config:
+    lib = _lib.load()
+    cfg = Config()
+    lib.tomg_config_default(C.byref(cfg), nx, ny, dx, dy)
+    cfg.xi0, cfg.eta0 = xi0, eta0
+    cfg.precision = {"fp64": TOMG_FP64, "fp32_ir": TOMG_FP32_IR, "mixed": TOMG_FP32_IR}[precision]
+    cfg.nu1, cfg.nu2 = nu1, nu2
+    cfg.smoother = {"gs4": TOMG_GS4, "jacobi": TOMG_JACOBI}[smoother]
+    cfg.jacobi_omega = jacobi_omega
+    cfg.ir_inner_cycles = ir_inner_cycles
+    return cfg
+
+
+def workspace_bytes(cfg: Config) -> int:
+    return int(_lib.load().tomg_workspace_bytes(C.byref(cfg)))
+
+
+def num_levels(cfg: Config) -> int:
+    return int(_lib.load().tomg_num_levels(C.byref(cfg)))
+
+
+def _ptr(t: Optional[torch.Tensor], dtype, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveResult:
+    status: int
+    cycles: int
+    rel: float
+
+    @property
+    def ok(self):
+        return self.status == TOMG_OK
+
+
+class Problem:
+    """One grid problem: a caller-sized workspace on the current device and a
+    library handle bound to a stream (default: the current torch stream)."""
+
+    def __init__(self, nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
+                 smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, device=None,
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.lib = _lib.load()
+        self.cfg = make_config(nx, ny, dx, dy, xi0, eta0, precision, nu1, nu2, smoother,
+                               jacobi_omega, ir_inner_cycles)
+        self.nx, self.ny = nx, ny
+        nbytes = workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise TomgError(TOMG_EINVAL, f"invalid configuration {nx}x{ny}")
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._h = C.c_void_p()
+        st = self.lib.tomg_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
+        if st != TOMG_OK:
+            raise TomgError(st, "tomg_create failed")
+
+    @classmethod
+    def from_grid(cls, prob, **kw):
+        """Problem sized for a ``workloads.GridProblem``."""
+        return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.xi0, prob.eta0, **kw)
+
+    # -- lifecycle ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.tomg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        return self.workspace.numel()
+
+    def last_error(self) -> str:
+        return self.lib.tomg_last_error(self._h).decode()
+
+    def _check(self, st, what):
+        if st != TOMG_OK:
+            raise TomgError(st, f"{what}: {self.last_error()}")
+
+    def level_shape(self, level):
+        a, b = C.c_int32(), C.c_int32()
+        self._check(self.lib.tomg_level_shape(self._h, level, C.byref(a), C.byref(b)),
+                    "level_shape")
+        return a.value, b.value
+
+    @property
+    def num_levels(self):
+        return num_levels(self.cfg)
+
+    # -- the C-ABI calls ----------------------------------------------------
+    def setup_coeffs(self, rho, xp=None, yp=None, jac=None, eps_phys=None, mask=None):
+        shp = (self.ny, self.nx)
+        args = (_ptr(xp, torch.float64, shp, "xp"), _ptr(yp, torch.float64, shp, "yp"),
+                _ptr(jac, torch.float64, (4,) + shp, "jac"),
+                _ptr(eps_phys, torch.float64, shp, "eps_phys"),
+                _ptr(rho, torch.float64, shp, "rho"), _ptr(mask, torch.uint8, shp, "mask"))
+        self._check(self.lib.setup_coeffs(self._h, *args), "setup_coeffs")
+
+    def update_rhs(self, rho):
+        self._check(self.lib.tomg_update_rhs(self._h, _ptr(rho, torch.float64,
+                                                           (self.ny, self.nx), "rho")),
+                    "update_rhs")
+
+    def vcycle(self, phi):
+        self._check(self.lib.vcycle(self._h, _ptr(phi, torch.float64, (self.ny, self.nx), "phi")),
+                    "vcycle")
+
+    def solve(self, phi, rel_tol=1e-10, max_cycles=100, raise_on_error=True) -> SolveResult:
+        cyc, rel = C.c_int32(), C.c_double()
+        st = self.lib.solve(self._h, _ptr(phi, torch.float64, (self.ny, self.nx), "phi"),
+                            rel_tol, max_cycles, C.byref(cyc), C.byref(rel))
+        if raise_on_error and st not in (TOMG_OK, TOMG_ENOCONV):
+            self._check(st, "solve")
+        return SolveResult(st, cyc.value, rel.value)
+
+    def residual_norm(self, phi):
+        a, r = C.c_double(), C.c_double()
+        self._check(self.lib.residual_norm(self._h, _ptr(phi, torch.float64, (self.ny, self.nx),
+                                                         "phi"), C.byref(a), C.byref(r)),
+                    "residual_norm")
+        return a.value, r.value
+
+    # -- diagnostics ----------------------------------------------------------
+    def export(self, what: str, level: int = 0) -> torch.Tensor:
+        nx, ny = self.level_shape(level)
+        if what == "dir":
+            out = torch.empty((ny, nx), dtype=torch.uint8, device=self.device)
+        elif what == "stencil":
+            out = torch.empty((9, ny, nx), dtype=torch.float64, device=self.device)
+        else:
+            out = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        self._check(self.lib.tomg_export(self._h, FIELD[what], level, C.c_void_p(out.data_ptr())),
+                    "export")
+        return out
+
+    def smooth(self, phi, sweeps=1):
+        self._check(self.lib.tomg_smooth(self._h, _ptr(phi, torch.float64, (self.ny, self.nx),
+                                                       "phi"), sweeps), "smooth")
+
+    def residual(self, phi) -> torch.Tensor:
+        r = torch.empty_like(phi)
+        self._check(self.lib.tomg_residual(self._h, _ptr(phi, torch.float64, (self.ny, self.nx),
+                                                         "phi"), C.c_void_p(r.data_ptr())),
+                    "residual")
+        return r
+
+
+# Module-level spellings of the C-ABI calls.
+def setup_coeffs(p: Problem, rho, xp=None, yp=None, jac=None, eps_phys=None, mask=None):
+    return p.setup_coeffs(rho, xp=xp, yp=yp, jac=jac, eps_phys=eps_phys, mask=mask)
+
+
+def vcycle(p: Problem, phi):
+    return p.vcycle(phi)
+
+
+def solve(p: Problem, phi, rel_tol=1e-10, max_cycles=100):
+    return p.solve(phi, rel_tol, max_cycles)
+
+
+def residual_norm(p: Problem, phi):
+    return p.residual_norm(phi)
+
+
+def solve_batch(problems: Sequence[Problem], phis: Sequence[torch.Tensor], rel_tol=1e-10,
+                max_cycles=100):
+    """tomg_solve_batch: returns a list of SolveResult."""
+    lib = _lib.load()
+    n = len(problems)
+    hs = (C.c_void_p * n)(*[p._h.value for p in problems])
+    ps = (C.c_void_p * n)(*[_ptr(t, torch.float64, (p.ny, p.nx), "phi").value
+                            for p, t in zip(problems, phis)])
+    cyc = (C.c_int32 * n)()
+    rel = (C.c_double * n)()
+    sts = (C.c_int * n)()
+    lib.tomg_solve_batch(hs, ps, n, rel_tol, max_cycles, cyc, rel, sts)
+    return [SolveResult(sts[k], cyc[k], rel[k]) for k in range(n)]
+
+
+def upload(prob, device="cuda"):
+    """Moves the arrays of a ``workloads.GridProblem`` to the GPU:
+    returns dict(xp, yp, jac, rho, mask, phi0) of tensors (None where absent)."""
+    def t(a, dtype=torch.float64):
+        return None if a is None else torch.as_tensor(a, dtype=dtype).contiguous().to(device)
+    return {"xp": t(prob.xp), "yp": t(prob.yp), "jac": t(prob.jac), "rho": t(prob.rho),
+            "mask": t(prob.mask, torch.uint8), "phi0": t(prob.phi0)}
+
+
+def setup_from_grid(prob, device="cuda", **kw):
+    """Problem + upload + setup_coeffs for a ``workloads.GridProblem``.
+    The analytic Jacobian is used when the problem carries one."""
+    p = Problem.from_grid(prob, device=device, **kw)
+    d = upload(prob, device)
+    if d["jac"] is not None:
+        p.setup_coeffs(d["rho"], jac=d["jac"], mask=d["mask"])
+    else:
+        p.setup_coeffs(d["rho"], xp=d["xp"], yp=d["yp"], mask=d["mask"])
+    return p, d

@@ -1,0 +1,392 @@
+// C-ABI of libtomg: argument checking, workspace layout, the cycle driver
+// and the stopping test.  Kernels live in kernels.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "tomg_internal.h"
+
+namespace tomg {
+
+// Halve while both node counts minus one are even and each side keeps at
+// least 3 nodes; coarsen at least once, then while a side exceeds 9 nodes.
+int level_shapes(int nx, int ny, int *nxs, int *nys) {
+  if (nx < 5 || ny < 5) return 0;
+  int L = 1;
+  nxs[0] = nx;
+  nys[0] = ny;
+  while (L < kMaxLevels) {
+    const int cx = nxs[L - 1], cy = nys[L - 1];
+    const bool halvable = ((cx - 1) % 2 == 0) && ((cy - 1) % 2 == 0) && cx >= 5 && cy >= 5;
+    const bool wanted = (L == 1) || cx > 9 || cy > 9;
+    if (!halvable || !wanted) break;
+    nxs[L] = (cx - 1) / 2 + 1;
+    nys[L] = (cy - 1) / 2 + 1;
+    ++L;
+  }
+  if (L < 2 || nxs[L - 1] > 9 || nys[L - 1] > 9) return 0;
+  return L;
+}
+
+static bool config_ok(const tomg_config &c) {
+  if (c.nx < 5 || c.ny < 5) return false;
+  if (!(c.dx > 0.0) || !(c.dy > 0.0) || !std::isfinite(c.dx) || !std::isfinite(c.dy)) return false;
+  if (c.precision != TOMG_FP64 && c.precision != TOMG_FP32_IR) return false;
+  if (c.nu1 < 0 || c.nu2 < 0 || c.nu1 > 4 || c.nu2 > 4 || c.nu1 + c.nu2 < 1) return false;
+  if (c.smoother != TOMG_GS4 && c.smoother != TOMG_JACOBI) return false;
+  if (c.smoother == TOMG_JACOBI && !(c.jacobi_omega > 0.0 && c.jacobi_omega <= 1.0)) return false;
+  if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
+  int a[kMaxLevels], b[kMaxLevels];
+  return level_shapes(c.nx, c.ny, a, b) > 0;
+}
+
+bool make_layout(const tomg_config &cfg, Layout *lay) {
+  if (!config_ok(cfg)) return false;
+  Layout &o = *lay;
+  o = Layout();
+  o.L = level_shapes(cfg.nx, cfg.ny, o.nx, o.ny);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t n0 = (size_t)cfg.nx * cfg.ny;
+  o.scal = take(kNumSlots * sizeof(double));
+  o.partials = take(2 * kRedBlocks * sizeof(double));
+  o.cinv = take(kMaxCoarseUnknowns * kMaxCoarseUnknowns * sizeof(double));
+  o.cidx = take(82 * sizeof(int));
+  o.exx = take(n0 * 8);
+  o.exy = take(n0 * 8);
+  o.eyy = take(n0 * 8);
+  o.det = take(n0 * 8);
+  o.f = take(n0 * 8);
+  o.tmp = take(n0 * 8);
+  o.dir[0] = take(n0);
+  for (int l = 1; l < o.L; ++l) {
+    const size_t n = (size_t)o.nx[l] * o.ny[l];
+    o.st[l] = take(9 * n * 8);
+    o.x[l] = take(n * 8);
+    o.b[l] = take(n * 8);
+    o.dir[l] = take(n);
+  }
+  if (cfg.precision == TOMG_FP32_IR) {
+    o.exx32 = take(n0 * 4);
+    o.exy32 = take(n0 * 4);
+    o.eyy32 = take(n0 * 4);
+    o.e32 = take(n0 * 4);
+    o.r32 = take(n0 * 4);
+    for (int l = 1; l < o.L; ++l) {
+      const size_t n = (size_t)o.nx[l] * o.ny[l];
+      o.st32[l] = take(9 * n * 4);
+      o.x32[l] = take(n * 4);
+      o.b32[l] = take(n * 4);
+    }
+  }
+  o.total = off;
+  return true;
+}
+
+}  // namespace tomg
+
+using namespace tomg;
+
+static tomg_status fail(tomg_problem *p, tomg_status s, const char *fmt, ...) {
+  if (p) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(p->err, sizeof(p->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+#define HIP_TRY(p, expr)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(p, TOMG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+// Copies the device scalar block to the host and waits for the stream.
+static tomg_status read_scalars(tomg_problem *p, double *h) {
+  HIP_TRY(p, hipMemcpyAsync(h, p->scal, kNumSlots * sizeof(double), hipMemcpyDeviceToHost,
+                            p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return TOMG_OK;
+}
+
+extern "C" {
+
+void tomg_config_default(tomg_config *cfg, int32_t nx, int32_t ny, double dx, double dy) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->nx = nx;
+  cfg->ny = ny;
+  cfg->dx = dx;
+  cfg->dy = dy;
+  cfg->precision = TOMG_FP64;
+  cfg->nu1 = 2;
+  cfg->nu2 = 2;
+  cfg->smoother = TOMG_GS4;
+  cfg->jacobi_omega = 0.8;
+  cfg->ir_inner_cycles = 2;
+}
+
+int32_t tomg_num_levels(const tomg_config *cfg) {
+  if (!cfg || !config_ok(*cfg)) return 0;
+  int a[kMaxLevels], b[kMaxLevels];
+  return level_shapes(cfg->nx, cfg->ny, a, b);
+}
+
+size_t tomg_workspace_bytes(const tomg_config *cfg) {
+  if (!cfg) return 0;
+  Layout lay;
+  return make_layout(*cfg, &lay) ? lay.total : 0;
+}
+
+tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, void *stream,
+                        tomg_problem **out) {
+  if (!out) return TOMG_EINVAL;
+  *out = nullptr;
+  if (!cfg || !d_ws) return TOMG_EINVAL;
+  if (((uintptr_t)d_ws) % 256 != 0) return TOMG_EINVAL;
+  Layout lay;
+  if (!make_layout(*cfg, &lay)) return TOMG_EINVAL;
+  if (ws_bytes < lay.total) return TOMG_ENOMEM;
+  tomg_problem *p = new (std::nothrow) tomg_problem();
+  if (!p) return TOMG_ENOMEM;
+  p->err[0] = 0;
+  p->cfg = *cfg;
+  p->lay = lay;
+  p->stream = (hipStream_t)stream;
+  p->ws = (char *)d_ws;
+  p->ws_bytes = ws_bytes;
+  p->L = lay.L;
+  char *w = p->ws;
+  auto D = [&](size_t off) { return (double *)(w + off); };
+  auto F = [&](size_t off) { return (float *)(w + off); };
+  p->scal = D(lay.scal);
+  p->partials = D(lay.partials);
+  p->cinv = D(lay.cinv);
+  p->cidx = (int *)(w + lay.cidx);
+  p->exx = D(lay.exx);
+  p->exy = D(lay.exy);
+  p->eyy = D(lay.eyy);
+  p->det = D(lay.det);
+  p->f = D(lay.f);
+  p->tmp = D(lay.tmp);
+  for (int l = 0; l < p->L; ++l) {
+    Level &v = p->lv[l];
+    v.nx = lay.nx[l];
+    v.ny = lay.ny[l];
+    v.n = (size_t)v.nx * v.ny;
+    v.dir = (uint8_t *)(w + lay.dir[l]);
+    if (l > 0) {
+      v.st = D(lay.st[l]);
+      v.x = D(lay.x[l]);
+      v.b = D(lay.b[l]);
+    }
+  }
+  if (cfg->precision == TOMG_FP32_IR) {
+    p->exx32 = F(lay.exx32);
+    p->exy32 = F(lay.exy32);
+    p->eyy32 = F(lay.eyy32);
+    p->e32 = F(lay.e32);
+    p->r32 = F(lay.r32);
+    for (int l = 1; l < p->L; ++l) {
+      p->lv[l].st32 = F(lay.st32[l]);
+      p->lv[l].x32 = F(lay.x32[l]);
+      p->lv[l].b32 = F(lay.b32[l]);
+    }
+  }
+  hipError_t e = hipMemsetAsync(p->scal, 0, kNumSlots * sizeof(double), p->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return TOMG_EDEVICE;
+  }
+  *out = p;
+  return TOMG_OK;
+}
+
+void tomg_destroy(tomg_problem *p) { delete p; }
+
+const char *tomg_last_error(const tomg_problem *p) {
+  if (!p) return "null problem";
+  return p->err;
+}
+
+tomg_status tomg_set_stream(tomg_problem *p, void *stream) {
+  if (!p) return TOMG_EINVAL;
+  p->stream = (hipStream_t)stream;
+  return TOMG_OK;
+}
+
+tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp,
+                         const double *d_jac, const double *d_eps_phys,
+                         const double *d_rho_phys, const uint8_t *d_mask) {
+  if (!p) return TOMG_EINVAL;
+  p->ready = false;
+  if (!d_rho_phys) return fail(p, TOMG_EINVAL, "setup_coeffs: rho is NULL");
+  if (!d_jac && (!d_xp || !d_yp))
+    return fail(p, TOMG_EINVAL, "setup_coeffs: need the Jacobian or both coordinate arrays");
+  HIP_TRY(p, launch_setup(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask));
+  HIP_TRY(p, launch_hierarchy(p));
+  double h[kNumSlots];
+  tomg_status s = read_scalars(p, h);
+  if (s != TOMG_OK) return s;
+  if (!(h[kSlotMinDet] > 0.0))
+    return fail(p, TOMG_EGEOMETRY, "setup_coeffs: det J = %g <= 0 (folded or degenerate map)",
+                h[kSlotMinDet]);
+  if (h[kSlotBad] != 0.0)
+    return fail(p, TOMG_ENONFINITE, "setup_coeffs: %g non-finite coefficients or sources",
+                h[kSlotBad]);
+  if (h[kSlotPivot] != 0.0)
+    return fail(p, TOMG_EGEOMETRY, "setup_coeffs: singular coarsest-level matrix");
+  p->ready = true;
+  return TOMG_OK;
+}
+
+tomg_status tomg_update_rhs(tomg_problem *p, const double *d_rho_phys) {
+  if (!p || !d_rho_phys) return TOMG_EINVAL;
+  if (!p->ready) return fail(p, TOMG_ESTATE, "update_rhs before setup_coeffs");
+  HIP_TRY(p, launch_update_rhs(p, d_rho_phys));
+  return TOMG_OK;
+}
+
+tomg_status vcycle(tomg_problem *p, double *d_phi) {
+  if (!p || !d_phi) return TOMG_EINVAL;
+  if (!p->ready) return fail(p, TOMG_ESTATE, "vcycle before setup_coeffs");
+  if (p->cfg.precision == TOMG_FP32_IR) {
+    HIP_TRY(p, launch_ir_residual(p, d_phi));
+    HIP_TRY(p, launch_ir_correct(p, d_phi));
+  } else {
+    HIP_TRY(p, launch_vcycle64(p, d_phi));
+  }
+  return TOMG_OK;
+}
+
+tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
+                          double *rel_out) {
+  if (!p || !d_phi) return TOMG_EINVAL;
+  if (!p->ready) return fail(p, TOMG_ESTATE, "residual_norm before setup_coeffs");
+  HIP_TRY(p, launch_resnorm(p, d_phi, kSlotB0, true));
+  HIP_TRY(p, launch_resnorm(p, d_phi, kSlotRes, false));
+  double h[kNumSlots];
+  tomg_status s = read_scalars(p, h);
+  if (s != TOMG_OK) return s;
+  if (abs_out) *abs_out = h[kSlotRes];
+  if (rel_out) *rel_out = h[kSlotRel];
+  return TOMG_OK;
+}
+
+tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cycles,
+                  int32_t *cycles_out, double *rel_res_out) {
+  if (!p || !d_phi) return TOMG_EINVAL;
+  if (!(rel_tol > 0.0) || max_cycles < 0) return fail(p, TOMG_EINVAL, "solve: bad tol/max_cycles");
+  if (!p->ready) return fail(p, TOMG_ESTATE, "solve before setup_coeffs");
+  const bool ir = p->cfg.precision == TOMG_FP32_IR;
+  HIP_TRY(p, launch_resnorm(p, d_phi, kSlotB0, true));
+  if (ir)
+    HIP_TRY(p, launch_ir_residual(p, d_phi));
+  else
+    HIP_TRY(p, launch_resnorm(p, d_phi, kSlotRes, false));
+  double h[kNumSlots];
+  tomg_status s = read_scalars(p, h);
+  if (s != TOMG_OK) return s;
+  int cycles = 0;
+  double rel = h[kSlotRel];
+  tomg_status st = TOMG_ENOCONV;
+  while (true) {
+    if (!std::isfinite(rel)) {
+      st = fail(p, TOMG_ENONFINITE, "solve: non-finite residual after %d cycles", cycles);
+      break;
+    }
+    if (rel <= rel_tol) {
+      st = TOMG_OK;
+      break;
+    }
+    if (cycles >= max_cycles) {
+      st = fail(p, TOMG_ENOCONV, "solve: rel. residual %.3e after %d cycles", rel, cycles);
+      break;
+    }
+    if (ir) {
+      HIP_TRY(p, launch_ir_correct(p, d_phi));
+      HIP_TRY(p, launch_ir_residual(p, d_phi));
+    } else {
+      HIP_TRY(p, launch_vcycle64(p, d_phi));
+      HIP_TRY(p, launch_resnorm(p, d_phi, kSlotRes, false));
+    }
+    ++cycles;
+    s = read_scalars(p, h);
+    if (s != TOMG_OK) return s;
+    rel = h[kSlotRel];
+  }
+  if (cycles_out) *cycles_out = cycles;
+  if (rel_res_out) *rel_res_out = rel;
+  return st;
+}
+
+tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, int32_t n,
+                             double rel_tol, int32_t max_cycles, int32_t *cycles_out,
+                             double *rel_out, tomg_status *status_out) {
+  if (!probs || !d_phis || n < 0) return TOMG_EINVAL;
+  tomg_status first = TOMG_OK;
+  for (int k = 0; k < n; ++k) {
+    int32_t c = 0;
+    double r = 0.0;
+    tomg_status s = probs[k] ? solve(probs[k], d_phis[k], rel_tol, max_cycles, &c, &r)
+                             : TOMG_EINVAL;
+    if (cycles_out) cycles_out[k] = c;
+    if (rel_out) rel_out[k] = r;
+    if (status_out) status_out[k] = s;
+    if (s != TOMG_OK && first == TOMG_OK) first = s;
+  }
+  return first;
+}
+
+tomg_status tomg_level_shape(const tomg_problem *p, int32_t level, int32_t *nx, int32_t *ny) {
+  if (!p || level < 0 || level >= p->L) return TOMG_EINVAL;
+  if (nx) *nx = p->lv[level].nx;
+  if (ny) *ny = p->lv[level].ny;
+  return TOMG_OK;
+}
+
+tomg_status tomg_export(tomg_problem *p, int32_t what, int32_t level, void *d_out) {
+  if (!p || !d_out || level < 0 || level >= p->L) return TOMG_EINVAL;
+  const Level &v = p->lv[level];
+  const void *src = nullptr;
+  size_t bytes = 0;
+  switch (what) {
+    case TOMG_FIELD_EXX: src = level == 0 ? p->exx : nullptr; bytes = v.n * 8; break;
+    case TOMG_FIELD_EXY: src = level == 0 ? p->exy : nullptr; bytes = v.n * 8; break;
+    case TOMG_FIELD_EYY: src = level == 0 ? p->eyy : nullptr; bytes = v.n * 8; break;
+    case TOMG_FIELD_DET: src = level == 0 ? p->det : nullptr; bytes = v.n * 8; break;
+    case TOMG_FIELD_RHS: src = level == 0 ? p->f : v.b; bytes = v.n * 8; break;
+    case TOMG_FIELD_DIR: src = v.dir; bytes = v.n; break;
+    case TOMG_FIELD_STENCIL: src = level > 0 ? v.st : nullptr; bytes = 9 * v.n * 8; break;
+    case TOMG_FIELD_X: src = level > 0 ? v.x : nullptr; bytes = v.n * 8; break;
+    default: break;
+  }
+  if (!src) return fail(p, TOMG_EINVAL, "export: no array %d on level %d", what, level);
+  HIP_TRY(p, hipMemcpyAsync(d_out, src, bytes, hipMemcpyDeviceToDevice, p->stream));
+  return TOMG_OK;
+}
+
+tomg_status tomg_smooth(tomg_problem *p, double *d_phi, int32_t sweeps) {
+  if (!p || !d_phi || sweeps < 0) return TOMG_EINVAL;
+  if (!p->ready) return fail(p, TOMG_ESTATE, "smooth before setup_coeffs");
+  HIP_TRY(p, launch_smooth0(p, d_phi, sweeps));
+  return TOMG_OK;
+}
+
+tomg_status tomg_residual(tomg_problem *p, const double *d_phi, double *d_r) {
+  if (!p || !d_phi || !d_r) return TOMG_EINVAL;
+  if (!p->ready) return fail(p, TOMG_ESTATE, "residual before setup_coeffs");
+  HIP_TRY(p, launch_residual0(p, d_phi, d_r));
+  return TOMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,767 @@
+// HIP kernels of the multigrid V-cycle for the coordinate-transformed
+// Poisson equation (arXiv 2602.01888, Sections 2-3), for gfx950.
+//
+// Node (i, j) of an nx x ny level is element j*nx + i.  Level 0 applies the
+// operator of eq. 18 directly from the permittivity tensor (eq. 12-15), so
+// the six coefficients k1..k6 are formed in registers and never stored;
+// coarse levels store a 9-point stencil (9 planes, plane k = (dj+1)*3+(di+1)).
+//
+// Every reduction runs on a fixed grid of kRedBlocks blocks and a fixed
+// tree, so a residual norm is bitwise reproducible from run to run.
+#include <cmath>
+
+#include "tomg_internal.h"
+
+namespace tomg {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Operators.  row(c, x, off, diag): (A x)_c = off + diag * x_c.
+// ---------------------------------------------------------------------------
+
+// Level 0: eq. 18 from the stored tensor.  k2 multiplies phi_C with a minus
+// sign; k1, k3, k4, k5 the E, W, N, S neighbours; k6 the diagonal difference
+// phi_NE - phi_NW - phi_SE + phi_SW (the cross derivative).
+template <typename T>
+struct EpsOp {
+  const T *exx, *exy, *eyy;
+  int nx;
+  T cx, cy;    // 1/dx^2, 1/dy^2
+  T qx, qy;    // 1/(4 dx^2), 1/(4 dy^2)
+  T qxy, hxy;  // 1/(4 dx dy), 1/(2 dx dy)
+
+  __device__ __forceinline__ void coefs(size_t c, T &k1, T &k3, T &k4, T &k5, T &k6,
+                                        T &k2) const {
+    const size_t s = (size_t)nx;
+    const T ax = exx[c] * cx, ay = eyy[c] * cy;
+    // first-derivative terms of eq. 17: (d eps_xx/dx + d eps_yx/dy) d phi/dx and
+    // (d eps_yy/dy + d eps_xy/dx) d phi/dy, by central differences
+    const T gx = (exx[c + 1] - exx[c - 1]) * qx + (exy[c + s] - exy[c - s]) * qxy;
+    const T gy = (eyy[c + s] - eyy[c - s]) * qy + (exy[c + 1] - exy[c - 1]) * qxy;
+    k1 = ax + gx;
+    k3 = ax - gx;
+    k4 = ay + gy;
+    k5 = ay - gy;
+    k6 = exy[c] * hxy;
+    k2 = T(2) * (ax + ay);
+  }
+  __device__ __forceinline__ void row(size_t c, const T *x, T &off, T &diag) const {
+    T k1, k3, k4, k5, k6, k2;
+    coefs(c, k1, k3, k4, k5, k6, k2);
+    const size_t s = (size_t)nx;
+    off = k1 * x[c + 1] + k3 * x[c - 1] + k4 * x[c + s] + k5 * x[c - s] +
+          k6 * ((x[c + s + 1] - x[c + s - 1]) - (x[c - s + 1] - x[c - s - 1]));
+    diag = -k2;
+  }
+  __device__ __forceinline__ T diag(size_t c) const { return -T(2) * (exx[c] * cx + eyy[c] * cy); }
+  __device__ __forceinline__ void full(size_t c, T a[9]) const {
+    T k1, k3, k4, k5, k6, k2;
+    coefs(c, k1, k3, k4, k5, k6, k2);
+    a[0] = k6;  a[1] = k5; a[2] = -k6;
+    a[3] = k3;  a[4] = -k2; a[5] = k1;
+    a[6] = -k6; a[7] = k4; a[8] = k6;
+  }
+};
+
+// Coarse levels: stored 9-point stencil.
+template <typename T>
+struct StOp {
+  const T *st;
+  size_t n;
+  int nx;
+  __device__ __forceinline__ void row(size_t c, const T *x, T &off, T &diag) const {
+    const size_t s = (size_t)nx;
+    off = st[c] * x[c - s - 1] + st[n + c] * x[c - s] + st[2 * n + c] * x[c - s + 1] +
+          st[3 * n + c] * x[c - 1] + st[5 * n + c] * x[c + 1] + st[6 * n + c] * x[c + s - 1] +
+          st[7 * n + c] * x[c + s] + st[8 * n + c] * x[c + s + 1];
+    diag = st[4 * n + c];
+  }
+  __device__ __forceinline__ T diag(size_t c) const { return st[4 * n + c]; }
+  __device__ __forceinline__ void full(size_t c, T a[9]) const {
+    for (int k = 0; k < 9; ++k) a[k] = st[k * n + c];
+  }
+};
+
+template <typename T>
+EpsOp<T> eps_op(const T *exx, const T *exy, const T *eyy, int nx, double dx, double dy) {
+  EpsOp<T> o;
+  o.exx = exx;
+  o.exy = exy;
+  o.eyy = eyy;
+  o.nx = nx;
+  o.cx = T(1.0 / (dx * dx));
+  o.cy = T(1.0 / (dy * dy));
+  o.qx = T(0.25 / (dx * dx));
+  o.qy = T(0.25 / (dy * dy));
+  o.qxy = T(0.25 / (dx * dy));
+  o.hxy = T(0.5 / (dx * dy));
+  return o;
+}
+
+template <typename T>
+StOp<T> st_op(const T *st, int nx, int ny) {
+  StOp<T> o;
+  o.st = st;
+  o.n = (size_t)nx * ny;
+  o.nx = nx;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Block reductions (wave64 shuffles, then LDS across the block's waves).
+// ---------------------------------------------------------------------------
+
+template <int OP>
+__device__ __forceinline__ double combine(double a, double b) {
+  return OP == 0 ? a + b : (OP == 1 ? fmin(a, b) : fmax(a, b));
+}
+
+template <int OP>
+__device__ double block_reduce(double v) {
+  __shared__ double red[kRedThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = combine<OP>(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = combine<OP>(v, red[w]);
+  }
+  __syncthreads();
+  return v;  // valid in thread 0
+}
+
+// One block: fixed-order reduction of n partials into out[0].
+// mode 0 sum, 1 min, 2 max, 3 sqrt(sum).  When rel_slot >= 0 the result is
+// also divided by scal[kSlotB0] into scal[kSlotRel] and compared against
+// scal[kSlotTol] into scal[kSlotDone].
+template <int OP>
+__global__ void k_finalize(const double *partials, int n, int stride, double *out, int do_sqrt,
+                           double *scal, int rel) {
+  double v = OP == 0 ? 0.0 : (OP == 1 ? INFINITY : -INFINITY);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) v = combine<OP>(v, partials[(size_t)k * stride]);
+  v = block_reduce<OP>(v);
+  if (threadIdx.x == 0) {
+    if (do_sqrt) v = sqrt(v);
+    out[0] = v;
+    if (rel) {
+      const double b0 = scal[kSlotB0];
+      const double r = b0 > 0.0 ? v / b0 : 0.0;
+      scal[kSlotRel] = r;
+      scal[kSlotDone] = (r <= scal[kSlotTol]) ? 1.0 : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Setup (eq. 1, 10-15, 11; numeric Jacobian eq. 39-42)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double d_i(const double *a, int nx, int i, size_t c, double inv2h) {
+  if (i == 0) return (-3.0 * a[c] + 4.0 * a[c + 1] - a[c + 2]) * inv2h;
+  if (i == nx - 1) return (3.0 * a[c] - 4.0 * a[c - 1] + a[c - 2]) * inv2h;
+  return (a[c + 1] - a[c - 1]) * inv2h;
+}
+__device__ __forceinline__ double d_j(const double *a, int nx, int ny, int j, size_t c,
+                                      double inv2h) {
+  const size_t s = (size_t)nx;
+  if (j == 0) return (-3.0 * a[c] + 4.0 * a[c + s] - a[c + 2 * s]) * inv2h;
+  if (j == ny - 1) return (3.0 * a[c] - 4.0 * a[c - s] + a[c - 2 * s]) * inv2h;
+  return (a[c + s] - a[c - s]) * inv2h;
+}
+
+__global__ void k_setup(int nx, int ny, double dx, double dy, const double *xp, const double *yp,
+                        const double *jac, const double *epsp, const double *rho,
+                        const uint8_t *mask, double *exx, double *exy, double *eyy, double *det,
+                        double *f, uint8_t *dir, double *partials) {
+  const size_t n = (size_t)nx * ny;
+  const double i2dx = 0.5 / dx, i2dy = 0.5 / dy;
+  double mind = INFINITY, bad = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(c / nx), i = (int)(c - (size_t)j * nx);
+    double jxx, jxy, jyx, jyy;
+    if (jac) {
+      jxx = jac[c];
+      jxy = jac[n + c];
+      jyx = jac[2 * n + c];
+      jyy = jac[3 * n + c];
+    } else {
+      jxx = d_i(xp, nx, i, c, i2dx);
+      jxy = d_j(xp, nx, ny, j, c, i2dy);
+      jyx = d_i(yp, nx, i, c, i2dx);
+      jyy = d_j(yp, nx, ny, j, c, i2dy);
+    }
+    const double D = jxx * jyy - jxy * jyx;
+    const double s = epsp ? epsp[c] : 1.0;
+    const double vxx = s * (jyy * jyy + jxy * jxy) / D;
+    const double vxy = s * (-jyy * jyx - jxy * jxx) / D;
+    const double vyy = s * (jyx * jyx + jxx * jxx) / D;
+    const double fv = -rho[c] * D;
+    exx[c] = vxx;
+    exy[c] = vxy;
+    eyy[c] = vyy;
+    det[c] = D;
+    f[c] = fv;
+    const bool ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+    dir[c] = (uint8_t)(ring || (mask && mask[c]));
+    const bool corner = (i == 0 || i == nx - 1) && (j == 0 || j == ny - 1);
+    if (!corner) {
+      mind = fmin(mind, D);
+      if (!isfinite(vxx) || !isfinite(vxy) || !isfinite(vyy) || !isfinite(fv)) bad += 1.0;
+    }
+  }
+  const double m = block_reduce<1>(mind);
+  const double b = block_reduce<0>(bad);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = m;
+    partials[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ void k_update_rhs(const double *rho, const double *det, double *f, size_t n,
+                             double *partials) {
+  double bad = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const double v = -rho[c] * det[c];
+    f[c] = v;
+    if (!isfinite(rho[c])) bad += 1.0;
+  }
+  const double b = block_reduce<0>(bad);
+  if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+// Coarse Dirichlet flags: ring, or every fine node of the 3x3 support of the
+// coarse node is Dirichlet (its column of the prolongation is empty).
+__global__ void k_coarse_dir(int nxf, const uint8_t *dirf, int nxc, int nyc, uint8_t *dirc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  if (I >= nxc || J >= nyc) return;
+  uint8_t d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
+  if (!d) {
+    bool all = true;
+    for (int b = -1; b <= 1; ++b)
+      for (int a = -1; a <= 1; ++a) all = all && dirf[(size_t)(2 * J + b) * nxf + 2 * I + a];
+    d = all;
+  }
+  dirc[(size_t)J * nxc + I] = d;
+}
+
+__device__ __forceinline__ double pw(int d) { return d == 0 ? 1.0 : ((d == 1 || d == -1) ? 0.5 : 0.0); }
+
+// Galerkin coarse operator A_H = (1/4) P^T A_h P (eq. 23; the paper leaves
+// the coarse operator open), P bilinear with zero rows at fine Dirichlet
+// nodes and no columns at coarse Dirichlet nodes; identity rows there.
+template <class Op>
+__global__ void k_galerkin(Op opf, const uint8_t *dirf, int nxf, int nxc, int nyc,
+                           const uint8_t *dirc, double *stc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  if (I >= nxc || J >= nyc) return;
+  const size_t nc = (size_t)nxc * nyc, C = (size_t)J * nxc + I;
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  if (dirc[C]) {
+    acc[4] = 1.0;
+  } else {
+    for (int b = -1; b <= 1; ++b)
+      for (int a = -1; a <= 1; ++a) {
+        const int fi = 2 * I + a, fj = 2 * J + b;
+        const size_t fidx = (size_t)fj * nxf + fi;
+        if (dirf[fidx]) continue;
+        const double wf = pw(a) * pw(b);
+        double af[9];
+        opf.full(fidx, af);
+        for (int q = -1; q <= 1; ++q)
+          for (int pp = -1; pp <= 1; ++pp) {
+            const int gi = fi + pp, gj = fj + q;
+            if (dirf[(size_t)gj * nxf + gi]) continue;
+            const double a_fg = af[(q + 1) * 3 + (pp + 1)];
+            for (int KJ = gj / 2; KJ <= (gj + 1) / 2; ++KJ)
+              for (int KI = gi / 2; KI <= (gi + 1) / 2; ++KI) {
+                const int oi = KI - I, oj = KJ - J;
+                if (dirc[(size_t)KJ * nxc + KI]) continue;
+                const double wg = pw(gi - 2 * KI) * pw(gj - 2 * KJ);
+                acc[(oj + 1) * 3 + (oi + 1)] += wf * a_fg * wg;
+              }
+          }
+      }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] *= 0.25;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) stc[k * nc + C] = acc[k];
+}
+
+// Coarsest level: index map of the free nodes and the explicit inverse of
+// the coarsest matrix by Gauss-Jordan elimination with partial pivoting (one
+// block).  cidx[ncoarse] receives the unknown count.
+__global__ void k_coarse_inverse(const double *st, const uint8_t *dir, int nx, int ny,
+                                 double *inv, int *cidx, double *scal) {
+  constexpr int M = kMaxCoarseUnknowns;
+  __shared__ double A[M][M + 1], B[M][M + 1];
+  __shared__ double fac[M];
+  __shared__ int cid[81];
+  __shared__ int sm, piv;
+  const int n = nx * ny, t = threadIdx.x, nt = blockDim.x;
+  if (t == 0) {
+    int m = 0;
+    for (int c = 0; c < n; ++c) cid[c] = dir[c] ? -1 : m++;
+    sm = m;
+    for (int c = 0; c < n; ++c) cidx[c] = cid[c];
+    cidx[n] = m;
+  }
+  __syncthreads();
+  const int m = sm;
+  for (int k = t; k < m * m; k += nt) {
+    const int r = k / m, c = k % m;
+    A[r][c] = 0.0;
+    B[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int c = t; c < n; c += nt) {
+    const int row = cid[c];
+    if (row < 0) continue;
+    const int I = c % nx, J = c / nx;
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = I + di, jj = J + dj;
+        if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
+        const int col = cid[jj * nx + ii];
+        if (col >= 0) A[row][col] = st[(size_t)((dj + 1) * 3 + di + 1) * n + c];
+      }
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    if (t == 0) {
+      int p = k;
+      for (int r = k + 1; r < m; ++r)
+        if (fabs(A[r][k]) > fabs(A[p][k])) p = r;
+      piv = p;
+      if (A[p][k] == 0.0) scal[kSlotPivot] = 1.0;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k)
+      for (int c = t; c < m; c += nt) {
+        double u = A[k][c]; A[k][c] = A[p][c]; A[p][c] = u;
+        u = B[k][c]; B[k][c] = B[p][c]; B[p][c] = u;
+      }
+    __syncthreads();
+    const double pv = A[k][k];
+    __syncthreads();
+    for (int c = t; c < m; c += nt) {
+      A[k][c] /= pv;
+      B[k][c] /= pv;
+    }
+    __syncthreads();
+    for (int r = t; r < m; r += nt) fac[r] = A[r][k];
+    __syncthreads();
+    for (int idx = t; idx < m * m; idx += nt) {
+      const int r = idx / m, c = idx % m;
+      if (r == k) continue;
+      A[r][c] -= fac[r] * A[k][c];
+      B[r][c] -= fac[r] * B[k][c];
+    }
+    __syncthreads();
+  }
+  for (int k = t; k < m * m; k += nt) inv[k] = B[k / m][k % m];
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S *a, D *b, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x)
+    b[c] = (D)a[c];
+}
+
+// ---------------------------------------------------------------------------
+// Cycle kernels
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_zero(T *x, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x)
+    x[c] = T(0);
+}
+
+// One colour of four-colour Gauss-Seidel: nodes with i = i0 (mod 2),
+// j = j0 (mod 2), 1 <= i <= nx-2, 1 <= j <= ny-2, not Dirichlet.
+template <class Op, typename T>
+__global__ void k_gs_colour(Op op, T *x, const T *b, const uint8_t *dir, int nx, int ny, int i0,
+                            int j0) {
+  const int i = i0 + 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int j = j0 + 2 * (int)(blockIdx.y * blockDim.y + threadIdx.y);
+  if (i > nx - 2 || j > ny - 2) return;
+  const size_t c = (size_t)j * nx + i;
+  if (dir[c]) return;
+  T off, dg;
+  op.row(c, x, off, dg);
+  x[c] = (b[c] - off) / dg;
+}
+
+// r = b - A x at free nodes, 0 elsewhere (all nodes written).
+template <class Op, typename T>
+__global__ void k_residual(Op op, const T *x, const T *b, const uint8_t *dir, int nx, int ny,
+                           T *r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= nx || j >= ny) return;
+  const size_t c = (size_t)j * nx + i;
+  T v = T(0);
+  if (!dir[c]) {
+    T off, dg;
+    op.row(c, x, off, dg);
+    v = b[c] - off - dg * x[c];
+  }
+  r[c] = v;
+}
+
+// Damped Jacobi update x += omega r / A_CC at free nodes.
+template <class Op, typename T>
+__global__ void k_jacobi_update(Op op, T *x, const T *r, const uint8_t *dir, int nx, int ny,
+                                T omega) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= nx || j >= ny) return;
+  const size_t c = (size_t)j * nx + i;
+  if (dir[c]) return;
+  x[c] += omega * r[c] / op.diag(c);
+}
+
+// Residual (eq. 20) and full-weighting restriction into the coarse
+// right-hand side (eq. 23): weights 4, 2, 1 over 16.
+template <class Op, typename T>
+__global__ void k_restrict(Op op, const T *x, const T *b, const uint8_t *dir, int nxf, T *bc,
+                           int nxc, int nyc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  if (I >= nxc || J >= nyc) return;
+  T s = T(0);
+  if (!(I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1)) {
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const size_t f = (size_t)(2 * J + dj) * nxf + (2 * I + di);
+        if (dir[f]) continue;
+        T off, dg;
+        op.row(f, x, off, dg);
+        const T w = T((2 - abs(di)) * (2 - abs(dj))) * T(0.0625);
+        s += w * (b[f] - off - dg * x[f]);
+      }
+  }
+  bc[(size_t)J * nxc + I] = s;
+}
+
+// Bilinear prolongation and correction (eq. 24) at free fine nodes.
+template <typename T>
+__global__ void k_prolong(const T *ec, int nxc, T *x, const uint8_t *dir, int nxf, int nyf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= nxf || j >= nyf) return;
+  const size_t c = (size_t)j * nxf + i;
+  if (dir[c]) return;
+  const int I = i >> 1, J = j >> 1;
+  const T *r0 = ec + (size_t)J * nxc;
+  T e0 = (i & 1) ? T(0.5) * (r0[I] + r0[I + 1]) : r0[I];
+  if (j & 1) {
+    const T *r1 = r0 + nxc;
+    const T e1 = (i & 1) ? T(0.5) * (r1[I] + r1[I + 1]) : r1[I];
+    e0 = T(0.5) * (e0 + e1);
+  }
+  x[c] += e0;
+}
+
+// Partial sums of r^2 over free nodes (fixed grid, fixed order).
+template <class Op>
+__global__ void k_resnorm(Op op, const double *x, const double *b, const uint8_t *dir, int nx,
+                          int ny, double *partials) {
+  const size_t m = (size_t)(nx - 2) * (ny - 2);
+  double s = 0.0;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const int j = 1 + (int)(k / (nx - 2)), i = 1 + (int)(k % (nx - 2));
+    const size_t c = (size_t)j * nx + i;
+    if (dir[c]) continue;
+    double off, dg;
+    op.row(c, x, off, dg);
+    const double r = b[c] - off - dg * x[c];
+    s += r * r;
+  }
+  s = block_reduce<0>(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Copy of phi with free nodes set to zero (the phi0 of the stopping test).
+__global__ void k_dirichlet_only(const double *phi, const uint8_t *dir, double *out, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x)
+    out[c] = dir[c] ? phi[c] : 0.0;
+}
+
+// Coarsest solve x = A^-1 b with the explicit inverse (one block).
+template <typename T>
+__global__ void k_coarse_solve(const double *inv, const int *cidx, const T *b, T *x, int n) {
+  __shared__ double bb[kMaxCoarseUnknowns];
+  const int m = cidx[n];
+  for (int c = threadIdx.x; c < n; c += blockDim.x)
+    if (cidx[c] >= 0) bb[cidx[c]] = (double)b[c];
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int k = cidx[c];
+    double v = 0.0;
+    if (k >= 0)
+      for (int q = 0; q < m; ++q) v += inv[k * m + q] * bb[q];
+    x[c] = (T)v;
+  }
+}
+
+// Iterative refinement, outer step: r = f - A64 phi in FP64 at free nodes,
+// r32 = fl32(r), e32 = 0 everywhere, partial sums of r^2.
+__global__ void k_ir_residual(EpsOp<double> op, const double *phi, const double *f,
+                              const uint8_t *dir, int nx, int ny, float *r32, float *e32,
+                              double *partials) {
+  const size_t n = (size_t)nx * ny;
+  double s = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    double r = 0.0;
+    if (!dir[c]) {
+      double off, dg;
+      op.row(c, phi, off, dg);
+      r = f[c] - off - dg * phi[c];
+    }
+    r32[c] = (float)r;
+    e32[c] = 0.0f;
+    s += r * r;
+  }
+  s = block_reduce<0>(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_ir_update(double *phi, const float *e32, const uint8_t *dir, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x)
+    if (!dir[c]) phi[c] += (double)e32[c];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side helpers
+// ---------------------------------------------------------------------------
+
+inline dim3 grid2(int nx, int ny, dim3 blk) {
+  return dim3((nx + blk.x - 1) / blk.x, (ny + blk.y - 1) / blk.y);
+}
+inline unsigned grid1(size_t n, unsigned cap = 4096) {
+  size_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  return (unsigned)(g > cap ? cap : g);
+}
+
+template <typename T>
+struct LevelView {
+  T *x;
+  T *b;
+  const T *st;
+};
+
+template <class Op, typename T>
+void smooth_level(tomg_problem *p, const Op &op, T *x, const T *b, const uint8_t *dir, int nx,
+                  int ny, int sweeps) {
+  const dim3 blk(64, 4);
+  if (p->cfg.smoother == TOMG_JACOBI) {
+    T *r = reinterpret_cast<T *>(p->tmp);
+    for (int s = 0; s < sweeps; ++s) {
+      hipLaunchKernelGGL((k_residual<Op, T>), grid2(nx, ny, blk), blk, 0, p->stream, op, x, b,
+                         dir, nx, ny, r);
+      hipLaunchKernelGGL((k_jacobi_update<Op, T>), grid2(nx, ny, blk), blk, 0, p->stream, op, x,
+                         r, dir, nx, ny, (T)p->cfg.jacobi_omega);
+    }
+    return;
+  }
+  const int cxn = (nx - 1) / 2 + 1, cyn = (ny - 1) / 2 + 1;
+  for (int s = 0; s < sweeps; ++s)
+    for (int col = 0; col < 4; ++col) {
+      const int pi = col & 1, pj = col >> 1;
+      const int i0 = pi ? 1 : 2, j0 = pj ? 1 : 2;
+      hipLaunchKernelGGL((k_gs_colour<Op, T>), grid2(cxn, cyn, blk), blk, 0, p->stream, op, x, b,
+                         dir, nx, ny, i0, j0);
+    }
+}
+
+template <class Op, typename T>
+void restrict_level(tomg_problem *p, const Op &op, const T *x, const T *b, const uint8_t *dir,
+                    int nxf, T *bc, int nxc, int nyc) {
+  const dim3 blk(64, 4);
+  hipLaunchKernelGGL((k_restrict<Op, T>), grid2(nxc, nyc, blk), blk, 0, p->stream, op, x, b, dir,
+                     nxf, bc, nxc, nyc);
+}
+
+// One V(nu1, nu2) cycle in precision T.  x0/b0: level-0 iterate and rhs;
+// op0: level-0 operator; coarse data from lv[l].{x,b,st} (or their 32-bit
+// copies).
+template <typename T>
+hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
+                      const LevelView<T> *views) {
+  const int L = p->L;
+  const dim3 blk(64, 4);
+  for (int l = 0; l < L - 1; ++l) {
+    const tomg::Level &lv = p->lv[l], &lc = p->lv[l + 1];
+    T *x = l == 0 ? x0 : views[l].x;
+    const T *b = l == 0 ? b0 : views[l].b;
+    if (l > 0) {
+      hipLaunchKernelGGL((k_zero<T>), grid1(lv.n), 256, 0, p->stream, x, lv.n);
+      const StOp<T> op = st_op<T>(views[l].st, lv.nx, lv.ny);
+      smooth_level(p, op, x, b, lv.dir, lv.nx, lv.ny, p->cfg.nu1);
+      restrict_level(p, op, x, b, lv.dir, lv.nx, views[l + 1].b, lc.nx, lc.ny);
+    } else {
+      smooth_level(p, op0, x, b, lv.dir, lv.nx, lv.ny, p->cfg.nu1);
+      restrict_level(p, op0, x, b, lv.dir, lv.nx, views[1].b, lc.nx, lc.ny);
+    }
+  }
+  {
+    const tomg::Level &lc = p->lv[L - 1];
+    hipLaunchKernelGGL((k_coarse_solve<T>), 1, 64, 0, p->stream, p->cinv, p->cidx,
+                       (const T *)views[L - 1].b, views[L - 1].x, (int)lc.n);
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const tomg::Level &lv = p->lv[l], &lc = p->lv[l + 1];
+    T *x = l == 0 ? x0 : views[l].x;
+    const T *b = l == 0 ? b0 : views[l].b;
+    hipLaunchKernelGGL((k_prolong<T>), grid2(lv.nx, lv.ny, blk), blk, 0, p->stream,
+                       (const T *)views[l + 1].x, lc.nx, x, lv.dir, lv.nx, lv.ny);
+    if (l > 0) {
+      const StOp<T> op = st_op<T>(views[l].st, lv.nx, lv.ny);
+      smooth_level(p, op, x, b, lv.dir, lv.nx, lv.ny, p->cfg.nu2);
+    } else {
+      smooth_level(p, op0, x, b, lv.dir, lv.nx, lv.ny, p->cfg.nu2);
+    }
+  }
+  return hipGetLastError();
+}
+
+EpsOp<double> op64(tomg_problem *p) {
+  return eps_op<double>(p->exx, p->exy, p->eyy, p->cfg.nx, p->cfg.dx, p->cfg.dy);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, const double *jac,
+                        const double *epsp, const double *rho, const uint8_t *mask) {
+  const int nx = p->cfg.nx, ny = p->cfg.ny;
+  hipLaunchKernelGGL(k_setup, kRedBlocks, kRedThreads, 0, p->stream, nx, ny, p->cfg.dx,
+                     p->cfg.dy, xp, yp, jac, epsp, rho, mask, p->exx, p->exy, p->eyy, p->det,
+                     p->f, p->lv[0].dir, p->partials);
+  hipLaunchKernelGGL((k_finalize<1>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 2,
+                     p->scal + kSlotMinDet, 0, p->scal, 0);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
+                     2, p->scal + kSlotBad, 0, p->scal, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_rhs(tomg_problem *p, const double *rho) {
+  const size_t n = p->lv[0].n;
+  hipLaunchKernelGGL(k_update_rhs, kRedBlocks, kRedThreads, 0, p->stream, rho, p->det, p->f, n,
+                     p->partials);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 1,
+                     p->scal + kSlotBad, 0, p->scal, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_hierarchy(tomg_problem *p) {
+  const dim3 blk(16, 16);
+  for (int l = 1; l < p->L; ++l) {
+    const tomg::Level &lf = p->lv[l - 1], &lc = p->lv[l];
+    hipLaunchKernelGGL(k_coarse_dir, grid2(lc.nx, lc.ny, blk), blk, 0, p->stream, lf.nx, lf.dir,
+                       lc.nx, lc.ny, lc.dir);
+    if (l == 1) {
+      hipLaunchKernelGGL((k_galerkin<EpsOp<double>>), grid2(lc.nx, lc.ny, blk), blk, 0,
+                         p->stream, op64(p), lf.dir, lf.nx, lc.nx, lc.ny, lc.dir, lc.st);
+    } else {
+      hipLaunchKernelGGL((k_galerkin<StOp<double>>), grid2(lc.nx, lc.ny, blk), blk, 0,
+                         p->stream, st_op<double>(lf.st, lf.nx, lf.ny), lf.dir, lf.nx, lc.nx,
+                         lc.ny, lc.dir, lc.st);
+    }
+  }
+  const tomg::Level &lc = p->lv[p->L - 1];
+  hipLaunchKernelGGL(k_coarse_inverse, 1, 256, 0, p->stream, lc.st, lc.dir, lc.nx, lc.ny,
+                     p->cinv, p->cidx, p->scal);
+  if (p->cfg.precision == TOMG_FP32_IR) {
+    const size_t n0 = p->lv[0].n;
+    hipLaunchKernelGGL((k_convert<double, float>), grid1(n0), 256, 0, p->stream, p->exx, p->exx32,
+                       n0);
+    hipLaunchKernelGGL((k_convert<double, float>), grid1(n0), 256, 0, p->stream, p->exy, p->exy32,
+                       n0);
+    hipLaunchKernelGGL((k_convert<double, float>), grid1(n0), 256, 0, p->stream, p->eyy, p->eyy32,
+                       n0);
+    for (int l = 1; l < p->L; ++l)
+      hipLaunchKernelGGL((k_convert<double, float>), grid1(9 * p->lv[l].n), 256, 0, p->stream,
+                         p->lv[l].st, p->lv[l].st32, 9 * p->lv[l].n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vcycle64(tomg_problem *p, double *phi) {
+  LevelView<double> v[kMaxLevels];
+  for (int l = 0; l < p->L; ++l) v[l] = {p->lv[l].x, p->lv[l].b, p->lv[l].st};
+  return run_vcycle<double>(p, phi, p->f, op64(p), v);
+}
+
+hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
+  hipLaunchKernelGGL(k_ir_residual, kRedBlocks, kRedThreads, 0, p->stream, op64(p), phi, p->f,
+                     p->lv[0].dir, p->cfg.nx, p->cfg.ny, p->r32, p->e32, p->partials);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 1,
+                     p->scal + kSlotRes, 1, p->scal, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_correct(tomg_problem *p, double *phi) {
+  const int nx = p->cfg.nx;
+  const size_t n0 = p->lv[0].n;
+  LevelView<float> v[kMaxLevels];
+  for (int l = 0; l < p->L; ++l) v[l] = {p->lv[l].x32, p->lv[l].b32, p->lv[l].st32};
+  const EpsOp<float> o32 = eps_op<float>(p->exx32, p->exy32, p->eyy32, nx, p->cfg.dx, p->cfg.dy);
+  for (int k = 0; k < p->cfg.ir_inner_cycles; ++k) {
+    hipError_t e = run_vcycle<float>(p, p->e32, p->r32, o32, v);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ir_update, grid1(n0), 256, 0, p->stream, phi, p->e32, p->lv[0].dir, n0);
+  return hipGetLastError();
+}
+
+hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free) {
+  const int nx = p->cfg.nx, ny = p->cfg.ny;
+  const double *x = phi;
+  if (zero_free) {
+    hipLaunchKernelGGL(k_dirichlet_only, grid1(p->lv[0].n), 256, 0, p->stream, phi, p->lv[0].dir,
+                       p->tmp, p->lv[0].n);
+    x = p->tmp;
+  }
+  hipLaunchKernelGGL((k_resnorm<EpsOp<double>>), kRedBlocks, kRedThreads, 0, p->stream, op64(p),
+                     x, p->f, p->lv[0].dir, nx, ny, p->partials);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 1,
+                     p->scal + slot, 1, p->scal, slot == kSlotRes ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps) {
+  smooth_level(p, op64(p), phi, (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny, sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r) {
+  const dim3 blk(64, 4);
+  hipLaunchKernelGGL((k_residual<EpsOp<double>, double>), grid2(p->cfg.nx, p->cfg.ny, blk), blk,
+                     0, p->stream, op64(p), phi, (const double *)p->f, p->lv[0].dir, p->cfg.nx,
+                     p->cfg.ny, r);
+  return hipGetLastError();
+}
+
+}  // namespace tomg

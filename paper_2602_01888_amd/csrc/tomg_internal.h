@@ -1,0 +1,88 @@
+// Internal declarations shared by the HIP translation units of libtomg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "tomg.h"
+
+namespace tomg {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCoarseUnknowns = 49;  // coarsest grid <= 9 x 9 nodes
+constexpr int kRedBlocks = 1024;        // fixed grid of every reduction kernel
+constexpr int kRedThreads = 256;
+
+// Slots of the device scalar block.
+enum Slot {
+  kSlotB0 = 0,      // ||f - A phi0||_2
+  kSlotRes = 1,     // last residual norm
+  kSlotMinDet = 2,  // min det J over non-corner nodes (setup)
+  kSlotBad = 3,     // count of non-finite values (setup)
+  kSlotPivot = 4,   // nonzero when the coarsest matrix is singular
+  kSlotRel = 5,     // last relative residual
+  kSlotDone = 6,    // convergence flag (1.0 when rel <= tol)
+  kSlotTol = 7,     // stopping tolerance used by the device-side check
+  kNumSlots = 16
+};
+
+struct Level {
+  int nx = 0, ny = 0;
+  size_t n = 0;
+  double *st = nullptr;  // 9 planes (levels >= 1)
+  double *x = nullptr;   // correction (levels >= 1)
+  double *b = nullptr;   // right-hand side (levels >= 1)
+  uint8_t *dir = nullptr;
+  float *st32 = nullptr, *x32 = nullptr, *b32 = nullptr;  // FP32 copies (IR)
+};
+
+// Byte offsets of every array inside the caller's workspace.
+struct Layout {
+  int L = 0;
+  int nx[kMaxLevels], ny[kMaxLevels];
+  size_t exx, exy, eyy, det, f, tmp, partials, scal, cinv, cidx;
+  size_t dir[kMaxLevels], st[kMaxLevels], x[kMaxLevels], b[kMaxLevels];
+  size_t exx32, exy32, eyy32, e32, r32;
+  size_t st32[kMaxLevels], x32[kMaxLevels], b32[kMaxLevels];
+  size_t total = 0;
+};
+
+int level_shapes(int nx, int ny, int *nxs, int *nys);
+bool make_layout(const tomg_config &cfg, Layout *lay);
+
+}  // namespace tomg
+
+struct tomg_problem {
+  tomg_config cfg;
+  tomg::Layout lay;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  int L = 0;
+  tomg::Level lv[tomg::kMaxLevels];
+  double *exx = nullptr, *exy = nullptr, *eyy = nullptr, *det = nullptr, *f = nullptr;
+  double *tmp = nullptr, *partials = nullptr, *scal = nullptr, *cinv = nullptr;
+  int *cidx = nullptr;
+  float *exx32 = nullptr, *exy32 = nullptr, *eyy32 = nullptr, *e32 = nullptr, *r32 = nullptr;
+  int m_coarse = 0;
+  bool ready = false;
+  char err[512];
+};
+
+namespace tomg {
+
+// ---- launch wrappers (kernels.hip); each returns hipSuccess or the error ----
+hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, const double *jac,
+                        const double *epsp, const double *rho, const uint8_t *mask);
+hipError_t launch_update_rhs(tomg_problem *p, const double *rho);
+hipError_t launch_hierarchy(tomg_problem *p);
+hipError_t launch_vcycle64(tomg_problem *p, double *phi);
+hipError_t launch_ir_residual(tomg_problem *p, const double *phi);
+hipError_t launch_ir_correct(tomg_problem *p, double *phi);
+hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free);
+hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps);
+hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r);
+
+}  // namespace tomg

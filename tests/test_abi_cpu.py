@@ -1,0 +1,110 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/tomg.h declares, and its host-only calls (configuration,
+level count, workspace sizing) behave as documented."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tomg.h")
+LIB = os.path.join(ROOT, "paper_2602_01888_amd", "libtomg.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\([^;{]*\)\s*;", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libtomg.so is not built (run __graft_entry__.build())")
+    from paper_2602_01888_amd import _lib
+    return _lib.load(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("setup_coeffs", "vcycle", "solve", "residual_norm", "tomg_workspace_bytes",
+              "tomg_create", "tomg_destroy", "tomg_solve_batch"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2602_01888_amd import _lib
+    names = declared_functions()
+    assert sorted(_lib.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2602_01888_amd import _lib
+    saved = _lib._lib
+    _lib._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not built"):
+            _lib.load(str(tmp_path / "nope.so"))
+    finally:
+        _lib._lib = saved
+
+
+def cfg(nx, ny, dx=None, dy=None, **kw):
+    import paper_2602_01888_amd as t
+    return t.make_config(nx, ny, dx or 1.0 / (nx - 1), dy or 1.0 / (ny - 1), **kw)
+
+
+def test_levels_and_workspace(lib):
+    import paper_2602_01888_amd as t
+    assert t.num_levels(cfg(129, 129)) == 5
+    assert t.num_levels(cfg(4097, 4097)) == 10
+    assert t.num_levels(cfg(129, 65)) == 5
+    assert t.num_levels(cfg(201, 201)) == 0
+    assert t.workspace_bytes(cfg(201, 201)) == 0
+    w64 = t.workspace_bytes(cfg(4097, 4097))
+    w32 = t.workspace_bytes(cfg(4097, 4097, precision="fp32_ir"))
+    n = 4097 * 4097
+    # level 0: 6 double fields + flags; coarse levels about 11/3 doubles per fine node
+    assert 6 * 8 * n < w64 < (6 * 8 + 1 + 4 * 8) * n
+    assert w32 > w64 + 5 * 4 * n
+    assert t.workspace_bytes(cfg(129, 129)) % 256 == 0
+
+
+@pytest.mark.parametrize("kw", [dict(nu1=0, nu2=0), dict(nu1=5), dict(smoother="jacobi",
+                                                                          jacobi_omega=1.5),
+                                dict(precision="fp32_ir", ir_inner_cycles=0)])
+def test_invalid_configs_size_to_zero(lib, kw):
+    import paper_2602_01888_amd as t
+    assert t.workspace_bytes(cfg(65, 65, **kw)) == 0
+
+
+def test_create_rejects_bad_arguments_before_touching_the_device(lib):
+    """NULL workspace, misaligned workspace and undersized workspace are
+    rejected by host checks alone."""
+    import paper_2602_01888_amd as t
+    c = cfg(65, 65)
+    need = t.workspace_bytes(c)
+    h = C.c_void_p()
+    assert lib.tomg_create(C.byref(c), None, need, None, C.byref(h)) == t.TOMG_EINVAL
+    assert lib.tomg_create(C.byref(c), C.c_void_p(0x1000 + 8), need, None,
+                           C.byref(h)) == t.TOMG_EINVAL
+    assert lib.tomg_create(C.byref(c), C.c_void_p(0x100000), need - 256, None,
+                           C.byref(h)) == t.TOMG_ENOMEM
+    bad = cfg(66, 65)
+    assert lib.tomg_create(C.byref(bad), C.c_void_p(0x100000), 1 << 30, None,
+                           C.byref(h)) == t.TOMG_EINVAL
+    assert h.value is None
+
+
+def test_null_problem_calls(lib):
+    import paper_2602_01888_amd as t
+    assert lib.setup_coeffs(None, None, None, None, None, None, None) == t.TOMG_EINVAL
+    assert lib.vcycle(None, None) == t.TOMG_EINVAL
+    assert lib.solve(None, None, 1e-10, 10, None, None) == t.TOMG_EINVAL
+    assert lib.residual_norm(None, None, None, None) == t.TOMG_EINVAL
+    assert lib.tomg_last_error(None) == b"null problem"

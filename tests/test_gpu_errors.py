@@ -1,0 +1,85 @@
+"""Error statuses of the C-ABI on the GPU (forced from the host side)."""
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tomg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_01888_amd as t
+    return t
+
+
+def test_state_before_setup(tomg):
+    import torch
+    p = tomg.Problem(17, 17, 1 / 16, 1 / 16)
+    phi = torch.zeros((17, 17), dtype=torch.float64, device="cuda")
+    with pytest.raises(tomg.TomgError) as e:
+        p.vcycle(phi)
+    assert e.value.status == tomg.TOMG_ESTATE
+    r = p.solve(phi, raise_on_error=False)
+    assert r.status == tomg.TOMG_ESTATE
+
+
+def test_folded_map_is_rejected(tomg):
+    prob = w.manufactured_sinusoidal(33, amp=0.5)
+    with pytest.raises(tomg.TomgError) as e:
+        tomg.setup_from_grid(prob)
+    assert e.value.status == tomg.TOMG_EGEOMETRY
+
+
+def test_nonfinite_source_is_rejected(tomg):
+    prob = w.manufactured_sinusoidal(33)
+    prob.rho[5, 7] = np.nan
+    with pytest.raises(tomg.TomgError) as e:
+        tomg.setup_from_grid(prob)
+    assert e.value.status == tomg.TOMG_ENONFINITE
+
+
+def test_max_cycles_returns_last_iterate(tomg):
+    prob = w.perturbed_circle(129)
+    p, d = tomg.setup_from_grid(prob)
+    phi = d["phi0"].clone()
+    r = p.solve(phi, rel_tol=1e-12, max_cycles=1)
+    assert r.status == tomg.TOMG_ENOCONV and r.cycles == 1 and 1e-12 < r.rel < 1
+    a, rel = p.residual_norm(phi)
+    assert rel == pytest.approx(r.rel, rel=1e-14)
+
+
+def test_bad_tensor_arguments(tomg):
+    import torch
+    p = tomg.Problem(17, 17, 1 / 16, 1 / 16)
+    with pytest.raises(ValueError):
+        p.vcycle(torch.zeros((17, 17), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        p.vcycle(torch.zeros((17, 16), dtype=torch.float64, device="cuda"))
+    r = p.solve(torch.zeros((17, 17), dtype=torch.float64, device="cuda"), rel_tol=-1,
+                raise_on_error=False)
+    assert r.status == tomg.TOMG_EINVAL
+
+
+def test_update_rhs_warm_resolve(tomg):
+    """A new source on a resident geometry (update_rhs) gives the same result
+    as a fresh setup with that source."""
+    import torch
+    prob = w.perturbed_circle(257)
+    p, d = tomg.setup_from_grid(prob)
+    phi = d["phi0"].clone()
+    assert p.solve(phi).ok
+    prob2 = w.perturbed_circle(257)
+    rho2 = np.flip(prob2.rho, axis=0).copy()
+    p.update_rhs(torch.tensor(rho2, device="cuda"))
+    a = d["phi0"].clone()
+    assert p.solve(a).ok
+    prob2.rho = rho2
+    q, d2 = tomg.setup_from_grid(prob2)
+    b = d2["phi0"].clone()
+    assert q.solve(b).ok
+    assert bool((a == b).all())

@@ -1,0 +1,209 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU FP64 oracle.
+
+Tolerances (FP64): coefficient setup 1e-14 relative to the field's max
+(the GPU evaluates the same expressions, contraction into FMAs changes the
+last bit); coarse stencils, one smoothing sweep, residual field and one
+V-cycle 1e-12 (a few hundred roundings deep, amplified by at most the
+operator's coefficient range); converged solutions 1e-10 in the max norm
+relative to max|phi| (the target tolerance of the solver)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import direct
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tomg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_01888_amd as t
+    return t
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    s = max(np.max(np.abs(b)), 1e-300)
+    return float(np.max(np.abs(a - b)) / s)
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "sinusoidal129": lambda: w.manufactured_sinusoidal(129),
+    "circle257": lambda: w.perturbed_circle(257),
+    "circle65_seed3": lambda: w.perturbed_circle(65, seed=3),
+    "rect129x65": lambda: w.manufactured_sinusoidal(129, ny=65),
+    "annulus65x33": lambda: w.polar_semi_annulus(65, ny=33),
+    "annulus65": lambda: w.polar_semi_annulus(65),
+    "random_sin_513": lambda: w.random_sinusoidal(513, 7),
+    "tiny9": lambda: w.manufactured_sinusoidal(9),
+    "tiny5x9": lambda: w.manufactured_sinusoidal(5, ny=9),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_setup_parity(tomg, name):
+    prob = CASES[name]()
+    print(f"[setup_parity] {name} {prob.nx}x{prob.ny}", flush=True)
+    p, d = tomg.setup_from_grid(prob)
+    s = oracle.setup(prob)
+    for key in ("exx", "exy", "eyy", "det"):
+        g = np_(p.export(key))
+        if key == "det":
+            assert rel_err(g, s[key]) <= 1e-14, key
+        else:  # the four corners may hold inf/nan where det J = 0; never read
+            m = np.ones_like(g, bool)
+            m[0, 0] = m[0, -1] = m[-1, 0] = m[-1, -1] = False
+            # relative to the tensor's scale: a component that cancels to 0
+            # in one evaluation order may keep a few ulps in another
+            scale = max(np.max(np.abs(s["exx"][m])), np.max(np.abs(s["eyy"][m])))
+            assert np.max(np.abs(g[m] - s[key][m])) <= 1e-14 * scale, key
+    assert rel_err(np_(p.export("rhs")), s["f"]) <= 1e-14
+    assert np.array_equal(np_(p.export("dir")), s["dir"])
+
+
+@pytest.mark.parametrize("name", ["circle257", "rect129x65", "annulus65x33", "tiny5x9"])
+def test_hierarchy_parity(tomg, name):
+    prob = CASES[name]()
+    print(f"[hierarchy_parity] {name}", flush=True)
+    p, d = tomg.setup_from_grid(prob)
+    s = oracle.setup(prob)
+    mg = oracle.MG.from_setup(s, prob.dx, prob.dy, mask=prob.mask)
+    assert mg.num_levels == p.num_levels
+    for l in range(1, mg.num_levels):
+        assert p.level_shape(l) == mg.shape(l)
+        assert np.array_equal(np_(p.export("dir", l)), mg.dirs(l)), l
+        assert rel_err(np_(p.export("stencil", l)), mg.stencil(l)) <= 1e-12, l
+
+
+@pytest.mark.parametrize("name", ["sinusoidal129", "circle257", "annulus65x33"])
+@pytest.mark.parametrize("smoother", ["gs4", "jacobi"])
+def test_smoother_and_residual_parity(tomg, name, smoother):
+    import torch
+    prob = CASES[name]()
+    print(f"[smoother_parity] {name} {smoother}", flush=True)
+    p, d = tomg.setup_from_grid(prob, smoother=smoother)
+    s = oracle.setup(prob)
+    mg = oracle.MG.from_setup(s, prob.dx, prob.dy, mask=prob.mask)
+    st0, dir0 = mg.stencil(0), mg.dirs(0)
+    rng = np.random.default_rng(1)
+    x0 = prob.phi0 + np.where(dir0 == 0, rng.normal(size=prob.phi0.shape), 0.0)
+    xg = torch.tensor(x0, device="cuda")
+    p.smooth(xg, 2)
+    kind = oracle.GS4 if smoother == "gs4" else oracle.JACOBI
+    xo = oracle.smooth(st0, dir0, x0, s["f"], kind=kind, sweeps=2, omega=0.8)
+    assert rel_err(np_(xg), xo) <= 1e-12
+    r = np_(p.residual(xg))
+    ro = oracle.residual(st0, dir0, xo, s["f"])
+    assert np.max(np.abs(r - ro)) <= 1e-12 * np.max(np.abs(s["f"])) + 1e-12 * np.max(
+        np.abs(st0[4])) * np.max(np.abs(xo))
+
+
+@pytest.mark.parametrize("name", ["sinusoidal129", "circle257", "rect129x65", "tiny9"])
+def test_one_vcycle_matches_oracle(tomg, name):
+    """Mirror mode: the GPU V-cycle and the oracle's V-cycle take the same
+    algorithmic steps, so one cycle agrees to rounding."""
+    import torch
+    prob = CASES[name]()
+    print(f"[vcycle_parity] {name}", flush=True)
+    p, d = tomg.setup_from_grid(prob)
+    s = oracle.setup(prob)
+    mg = oracle.MG.from_setup(s, prob.dx, prob.dy, mask=prob.mask)
+    xg = d["phi0"].clone()
+    p.vcycle(xg)
+    xo = mg.vcycle(prob.phi0, s["f"])
+    assert rel_err(np_(xg), xo) <= 1e-12
+    # and the coarse corrections of the last cycle agree level by level
+    for l in range(1, mg.num_levels):
+        assert rel_err(np_(p.export("x", l)), mg.level_x(l)) <= 1e-11, l
+    # a second cycle from there
+    p.vcycle(xg)
+    xo = mg.vcycle(xo, s["f"])
+    assert rel_err(np_(xg), xo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_matches_direct_solution(tomg, name):
+    prob = CASES[name]()
+    print(f"[solve_parity] {name}", flush=True)
+    p, d = tomg.setup_from_grid(prob)
+    phi = d["phi0"].clone()
+    # the strongly anisotropic polar grid (point smoother) needs ~140 cycles
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=400)
+    assert res.ok, res
+    s = oracle.setup(prob)
+    st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], prob.dx, prob.dy, s["dir"])
+    ref = direct.direct_solve(st, s["dir"], s["f"], prob.phi0)
+    err = rel_err(np_(phi), ref)
+    print(f"  cycles={res.cycles} rel={res.rel:.2e} err_vs_direct={err:.2e}", flush=True)
+    if err > 1e-10:  # conditioning: tighten the GPU tolerance, then assert
+        res = p.solve(phi, rel_tol=1e-13, max_cycles=400)
+        err = rel_err(np_(phi), ref)
+    assert err <= 1e-10
+    # Dirichlet values untouched
+    dmask = s["dir"].astype(bool)
+    assert np.array_equal(np_(phi)[dmask], prob.phi0[dmask])
+
+
+def test_solve_cycle_count_matches_oracle(tomg):
+    prob = w.perturbed_circle(513)
+    p, d = tomg.setup_from_grid(prob)
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-10)
+    ro = oracle.solve_problem(prob, rel_tol=1e-10)
+    assert res.cycles == ro["cycles"]
+    assert res.rel == pytest.approx(ro["rel"], rel=1e-6)
+    assert rel_err(np_(phi), ro["phi"]) <= 1e-10
+
+
+def test_residual_norm_parity(tomg):
+    import torch
+    prob = w.perturbed_circle(257)
+    p, d = tomg.setup_from_grid(prob)
+    s = oracle.setup(prob)
+    mg = oracle.MG.from_setup(s, prob.dx, prob.dy, mask=prob.mask)
+    x = prob.phi0 + 0.01 * np.random.default_rng(2).normal(size=prob.phi0.shape) * (s["dir"] == 0)
+    a, r = p.residual_norm(torch.tensor(x, device="cuda"))
+    ro = oracle.residual(mg.stencil(0), mg.dirs(0), x, s["f"])
+    ao = oracle.norm2_free(mg.dirs(0), ro)
+    b0 = mg.initial_residual(x, s["f"])
+    assert a == pytest.approx(ao, rel=1e-12)
+    assert r == pytest.approx(ao / b0, rel=1e-12)
+
+
+def test_run_twice_bitwise(tomg):
+    prob = w.perturbed_circle(257)
+    p, d = tomg.setup_from_grid(prob)
+    a = d["phi0"].clone()
+    b = d["phi0"].clone()
+    ra = p.solve(a)
+    rb = p.solve(b)
+    assert ra.cycles == rb.cycles and ra.rel == rb.rel
+    assert bool((a == b).all())
+
+
+def test_mixed_precision_solution(tomg):
+    """FP32 inner V-cycles inside FP64 iterative refinement reach the same
+    1e-10 relative residual and the FP64 solution."""
+    prob = w.perturbed_circle(257)
+    p64, d = tomg.setup_from_grid(prob)
+    p32, _ = tomg.setup_from_grid(prob, precision="fp32_ir")
+    a = d["phi0"].clone()
+    b = d["phi0"].clone()
+    r64 = p64.solve(a, rel_tol=1e-10)
+    r32 = p32.solve(b, rel_tol=1e-10, max_cycles=60)
+    print(f"  fp64 cycles={r64.cycles} ir steps={r32.cycles} rel={r32.rel:.2e}", flush=True)
+    assert r64.ok and r32.ok
+    s = oracle.setup(prob)
+    st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], prob.dx, prob.dy, s["dir"])
+    ref = direct.direct_solve(st, s["dir"], s["f"], prob.phi0)
+    assert rel_err(np_(b), ref) <= 1e-9
