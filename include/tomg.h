@@ -69,7 +69,7 @@ typedef struct {
   double dx, dy;           /* computational spacings (dx != dy allowed) */
   int32_t precision;       /* TOMG_FP64, or TOMG_FP32_IR: FP32 V-cycles as the
                               inner solver of FP64 iterative refinement */
-  int32_t nu1, nu2;        /* pre/post smoothing sweeps, 1..4 (default 2, 2) */
+  int32_t nu1, nu2;        /* pre/post smoothing sweeps, 1..4 each (default 2, 2) */
   int32_t smoother;        /* TOMG_GS4 (four-colour Gauss-Seidel, default) or
                               TOMG_JACOBI (damped Jacobi) */
   double jacobi_omega;     /* damping of TOMG_JACOBI (default 0.8) */

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 #include "tomg_internal.h"
@@ -34,7 +35,7 @@ static bool config_ok(const tomg_config &c) {
   if (c.nx < 5 || c.ny < 5) return false;
   if (!(c.dx > 0.0) || !(c.dy > 0.0) || !std::isfinite(c.dx) || !std::isfinite(c.dy)) return false;
   if (c.precision != TOMG_FP64 && c.precision != TOMG_FP32_IR) return false;
-  if (c.nu1 < 0 || c.nu2 < 0 || c.nu1 > 4 || c.nu2 > 4 || c.nu1 + c.nu2 < 1) return false;
+  if (c.nu1 < 1 || c.nu2 < 1 || c.nu1 > 4 || c.nu2 > 4) return false;
   if (c.smoother != TOMG_GS4 && c.smoother != TOMG_JACOBI) return false;
   if (c.smoother == TOMG_JACOBI && !(c.jacobi_omega > 0.0 && c.jacobi_omega <= 1.0)) return false;
   if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
@@ -55,7 +56,8 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
   };
   const size_t n0 = (size_t)cfg.nx * cfg.ny;
   o.scal = take(kNumSlots * sizeof(double));
-  o.partials = take(2 * kRedBlocks * sizeof(double));
+  const size_t nparts = std::max((size_t)2 * kRedBlocks, fused_max_blocks(cfg.nx, cfg.ny));
+  o.partials = take(nparts * sizeof(double));
   o.cinv = take(kMaxCoarseUnknowns * kMaxCoarseUnknowns * sizeof(double));
   o.cidx = take(82 * sizeof(int));
   o.exx = take(n0 * 8);
@@ -69,6 +71,7 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
     const size_t n = (size_t)o.nx[l] * o.ny[l];
     o.st[l] = take(9 * n * 8);
     o.x[l] = take(n * 8);
+    o.x2[l] = take(n * 8);
     o.b[l] = take(n * 8);
     o.dir[l] = take(n);
   }
@@ -77,11 +80,13 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
     o.exy32 = take(n0 * 4);
     o.eyy32 = take(n0 * 4);
     o.e32 = take(n0 * 4);
+    o.e32b = take(n0 * 4);
     o.r32 = take(n0 * 4);
     for (int l = 1; l < o.L; ++l) {
       const size_t n = (size_t)o.nx[l] * o.ny[l];
       o.st32[l] = take(9 * n * 4);
       o.x32[l] = take(n * 4);
+      o.x2_32[l] = take(n * 4);
       o.b32[l] = take(n * 4);
     }
   }
@@ -187,6 +192,7 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
     if (l > 0) {
       v.st = D(lay.st[l]);
       v.x = D(lay.x[l]);
+      v.x2 = D(lay.x2[l]);
       v.b = D(lay.b[l]);
     }
   }
@@ -195,10 +201,12 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
     p->exy32 = F(lay.exy32);
     p->eyy32 = F(lay.eyy32);
     p->e32 = F(lay.e32);
+    p->e32b = F(lay.e32b);
     p->r32 = F(lay.r32);
     for (int l = 1; l < p->L; ++l) {
       p->lv[l].st32 = F(lay.st32[l]);
       p->lv[l].x32 = F(lay.x32[l]);
+      p->lv[l].x2_32 = F(lay.x2_32[l]);
       p->lv[l].b32 = F(lay.b32[l]);
     }
   }
@@ -263,7 +271,7 @@ tomg_status vcycle(tomg_problem *p, double *d_phi) {
     HIP_TRY(p, launch_ir_residual(p, d_phi));
     HIP_TRY(p, launch_ir_correct(p, d_phi));
   } else {
-    HIP_TRY(p, launch_vcycle64(p, d_phi));
+    HIP_TRY(p, launch_vcycle64(p, d_phi, false));
   }
   return TOMG_OK;
 }
@@ -316,8 +324,7 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
       HIP_TRY(p, launch_ir_correct(p, d_phi));
       HIP_TRY(p, launch_ir_residual(p, d_phi));
     } else {
-      HIP_TRY(p, launch_vcycle64(p, d_phi));
-      HIP_TRY(p, launch_resnorm(p, d_phi, kSlotRes, false));
+      HIP_TRY(p, launch_vcycle64(p, d_phi, true));
     }
     ++cycles;
     s = read_scalars(p, h);

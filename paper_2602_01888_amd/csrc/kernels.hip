@@ -566,6 +566,7 @@ struct LevelView {
   T *x;
   T *b;
   const T *st;
+  T *pong;  // second iterate buffer of the fused passes
 };
 
 template <class Op, typename T>
@@ -601,19 +602,29 @@ void restrict_level(tomg_problem *p, const Op &op, const T *x, const T *b, const
 }
 
 // One V(nu1, nu2) cycle in precision T.  x0/b0: level-0 iterate and rhs;
-// op0: level-0 operator; coarse data from lv[l].{x,b,st} (or their 32-bit
-// copies).
+// op0: level-0 operator; coarse data from views[l].{x,b,st}.  zero0: the
+// level-0 iterate starts at zero (not read).  With the four-colour smoother
+// each level is one fused down pass and one fused up pass; when partials is
+// given, the level-0 up pass also leaves per-block sums of the squared final
+// residual there (block count in *nblocks).
 template <typename T>
 hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
-                      const LevelView<T> *views) {
+                      const LevelView<T> *views, bool zero0, double *partials, int *nblocks) {
   const int L = p->L;
   const dim3 blk(64, 4);
+  const bool fused = p->cfg.smoother == TOMG_GS4;
+  if (nblocks) *nblocks = 0;
   for (int l = 0; l < L - 1; ++l) {
     const tomg::Level &lv = p->lv[l], &lc = p->lv[l + 1];
     T *x = l == 0 ? x0 : views[l].x;
     const T *b = l == 0 ? b0 : views[l].b;
+    if (fused) {
+      fused_down<T>(p, l, x, views[l].pong, b, op0.exx, op0.exy, op0.eyy, views[l].st,
+                    views[l + 1].b, l > 0 || zero0);
+      continue;
+    }
+    if (l > 0 || zero0) hipLaunchKernelGGL((k_zero<T>), grid1(lv.n), 256, 0, p->stream, x, lv.n);
     if (l > 0) {
-      hipLaunchKernelGGL((k_zero<T>), grid1(lv.n), 256, 0, p->stream, x, lv.n);
       const StOp<T> op = st_op<T>(views[l].st, lv.nx, lv.ny);
       smooth_level(p, op, x, b, lv.dir, lv.nx, lv.ny, p->cfg.nu1);
       restrict_level(p, op, x, b, lv.dir, lv.nx, views[l + 1].b, lc.nx, lc.ny);
@@ -631,6 +642,12 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
     const tomg::Level &lv = p->lv[l], &lc = p->lv[l + 1];
     T *x = l == 0 ? x0 : views[l].x;
     const T *b = l == 0 ? b0 : views[l].b;
+    if (fused) {
+      const int nb = fused_up<T>(p, l, views[l].pong, x, b, op0.exx, op0.exy, op0.eyy,
+                                 views[l].st, views[l + 1].x, l == 0 ? partials : nullptr);
+      if (l == 0 && nblocks) *nblocks = partials ? nb : 0;
+      continue;
+    }
     hipLaunchKernelGGL((k_prolong<T>), grid2(lv.nx, lv.ny, blk), blk, 0, p->stream,
                        (const T *)views[l + 1].x, lc.nx, x, lv.dir, lv.nx, lv.ny);
     if (l > 0) {
@@ -708,10 +725,20 @@ hipError_t launch_hierarchy(tomg_problem *p) {
   return hipGetLastError();
 }
 
-hipError_t launch_vcycle64(tomg_problem *p, double *phi) {
+hipError_t launch_vcycle64(tomg_problem *p, double *phi, bool with_norm) {
   LevelView<double> v[kMaxLevels];
-  for (int l = 0; l < p->L; ++l) v[l] = {p->lv[l].x, p->lv[l].b, p->lv[l].st};
-  return run_vcycle<double>(p, phi, p->f, op64(p), v);
+  for (int l = 0; l < p->L; ++l) v[l] = {p->lv[l].x, p->lv[l].b, p->lv[l].st, p->lv[l].x2};
+  v[0].pong = p->tmp;
+  int nb = 0;
+  hipError_t e = run_vcycle<double>(p, phi, p->f, op64(p), v, false,
+                                    with_norm ? p->partials : nullptr, &nb);
+  if (e != hipSuccess || !with_norm) return e;
+  if (nb > 0) {
+    hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, nb, 1,
+                       p->scal + kSlotRes, 1, p->scal, 1);
+    return hipGetLastError();
+  }
+  return launch_resnorm(p, phi, kSlotRes, false);
 }
 
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
@@ -726,10 +753,12 @@ hipError_t launch_ir_correct(tomg_problem *p, double *phi) {
   const int nx = p->cfg.nx;
   const size_t n0 = p->lv[0].n;
   LevelView<float> v[kMaxLevels];
-  for (int l = 0; l < p->L; ++l) v[l] = {p->lv[l].x32, p->lv[l].b32, p->lv[l].st32};
+  for (int l = 0; l < p->L; ++l)
+    v[l] = {p->lv[l].x32, p->lv[l].b32, p->lv[l].st32, p->lv[l].x2_32};
+  v[0].pong = p->e32b;
   const EpsOp<float> o32 = eps_op<float>(p->exx32, p->exy32, p->eyy32, nx, p->cfg.dx, p->cfg.dy);
   for (int k = 0; k < p->cfg.ir_inner_cycles; ++k) {
-    hipError_t e = run_vcycle<float>(p, p->e32, p->r32, o32, v);
+    hipError_t e = run_vcycle<float>(p, p->e32, p->r32, o32, v, k == 0, nullptr, nullptr);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_ir_update, grid1(n0), 256, 0, p->stream, phi, p->e32, p->lv[0].dir, n0);

@@ -34,8 +34,9 @@ struct Level {
   double *st = nullptr;  // 9 planes (levels >= 1)
   double *x = nullptr;   // correction (levels >= 1)
   double *b = nullptr;   // right-hand side (levels >= 1)
+  double *x2 = nullptr;  // second iterate buffer of the fused passes (levels >= 1)
   uint8_t *dir = nullptr;
-  float *st32 = nullptr, *x32 = nullptr, *b32 = nullptr;  // FP32 copies (IR)
+  float *st32 = nullptr, *x32 = nullptr, *b32 = nullptr, *x2_32 = nullptr;  // FP32 (IR)
 };
 
 // Byte offsets of every array inside the caller's workspace.
@@ -43,9 +44,9 @@ struct Layout {
   int L = 0;
   int nx[kMaxLevels], ny[kMaxLevels];
   size_t exx, exy, eyy, det, f, tmp, partials, scal, cinv, cidx;
-  size_t dir[kMaxLevels], st[kMaxLevels], x[kMaxLevels], b[kMaxLevels];
-  size_t exx32, exy32, eyy32, e32, r32;
-  size_t st32[kMaxLevels], x32[kMaxLevels], b32[kMaxLevels];
+  size_t dir[kMaxLevels], st[kMaxLevels], x[kMaxLevels], b[kMaxLevels], x2[kMaxLevels];
+  size_t exx32, exy32, eyy32, e32, e32b, r32;
+  size_t st32[kMaxLevels], x32[kMaxLevels], b32[kMaxLevels], x2_32[kMaxLevels];
   size_t total = 0;
 };
 
@@ -66,6 +67,7 @@ struct tomg_problem {
   double *tmp = nullptr, *partials = nullptr, *scal = nullptr, *cinv = nullptr;
   int *cidx = nullptr;
   float *exx32 = nullptr, *exy32 = nullptr, *eyy32 = nullptr, *e32 = nullptr, *r32 = nullptr;
+  float *e32b = nullptr;
   int m_coarse = 0;
   bool ready = false;
   char err[512];
@@ -78,7 +80,16 @@ hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, con
                         const double *epsp, const double *rho, const uint8_t *mask);
 hipError_t launch_update_rhs(tomg_problem *p, const double *rho);
 hipError_t launch_hierarchy(tomg_problem *p);
-hipError_t launch_vcycle64(tomg_problem *p, double *phi);
+hipError_t launch_vcycle64(tomg_problem *p, double *phi, bool with_norm);
+
+// fused level passes (fused.hip)
+template <typename T>
+void fused_down(tomg_problem *p, int l, const T *x, T *pong, const T *b, const T *exx,
+                const T *exy, const T *eyy, const T *st, T *bc, bool zero_start);
+template <typename T>
+int fused_up(tomg_problem *p, int l, const T *pong, T *x, const T *b, const T *exx,
+             const T *exy, const T *eyy, const T *st, const T *xc, double *partials);
+size_t fused_max_blocks(int nx, int ny);
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi);
 hipError_t launch_ir_correct(tomg_problem *p, double *phi);
 hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free);
