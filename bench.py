@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Benchmark of the transformed-Poisson multigrid on one MI355X.
+
+Workload (one "step"): the 4097 x 4097 perturbed-circle conductor problem
+(radial stretch of the annulus 0.15 <= r <= 0.35 onto a seed-perturbed
+circle, conductor phi = 1, outer phi = 0, 8 Gaussian sources of width
+0.02), numeric Jacobian; coefficient setup + Galerkin hierarchy
+(setup_coeffs) and an FP64 V(2,2) solve from the zero interior guess to a
+1e-10 relative residual (solve).  Inputs are resident in HBM before the
+timed region starts.  Prints one JSON line.
+
+Also measured in the same run (extra keys of the line):
+  solve_only  : the solve without setup, same problem;
+  mixed       : the same problem with FP32 V(2,2) cycles inside FP64
+                iterative refinement;
+  roofline    : the level-0 down pass (the dominant kernel) timed with HIP
+                events over the timed steps, against 8 TB/s;
+  cpu_baseline: the CPU oracle on the same input (bounded sample).
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "solves/sec & DOF/sec to 1e-10 rel. residual (FP64 vs mixed); p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level0_passes_4097.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def level0_pass_bytes(nx, ny, nxc, nyc, elem=8, dir_bytes=1):
+    """Algorithmic HBM bytes of one level-0 pass: read iterate, rhs, three
+    tensor components and the Dirichlet flags once, write the iterate once,
+    and move the coarse array (written by the down pass, read by the up pass)
+    once."""
+    n, nc = nx * ny, nxc * nyc
+    return n * (5 * elem + dir_bytes + elem) + nc * elem
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2602_01888_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """Per-launch HBM traffic of the level-0 passes from the committed
+    rocprofv3 counter summary, if it was taken on the current sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d
+
+
+def cpu_baseline(prob, gpu_cycles, budget_s=30.0):
+    """The oracle as it stands on the host cores: setup, then V-cycles; the
+    full solve when it fits the budget, else extrapolated from the cycles
+    run (same algorithm, so the same cycle count as the GPU)."""
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    s = oracle.setup(prob)
+    mg = oracle.MG.from_setup(s, prob.dx, prob.dy, mask=prob.mask)
+    t_setup = time.perf_counter() - t0
+    phi = prob.phi0.copy()
+    t1 = time.perf_counter()
+    phi = mg.vcycle(phi, s["f"])
+    t_cycle = time.perf_counter() - t1
+    est = t_setup + t_cycle * max(gpu_cycles, 1)
+    out = {"cores": oracle.num_threads(), "kind": "oracle"}
+    phi_ref = None
+    if est <= budget_s:
+        t2 = time.perf_counter()
+        phi_ref, st, cyc, rel, _ = mg.solve(prob.phi0, s["f"], 1e-10, 100)
+        t_solve = time.perf_counter() - t2
+        total = t_setup + t_solve
+        out.update(value=1.0 / total, unit="solves/s",
+                   sample=f"one full oracle setup + solve ({cyc} V(2,2) cycles, four-colour "
+                          f"ordering, {t_setup:.2f} s setup + {t_solve:.2f} s solve)")
+    else:
+        done, tc = 1, t_cycle
+        while done < gpu_cycles and t_setup + tc < budget_s:
+            t3 = time.perf_counter()
+            phi = mg.vcycle(phi, s["f"])
+            tc += time.perf_counter() - t3
+            done += 1
+        per = tc / done
+        total = t_setup + per * gpu_cycles
+        out.update(value=1.0 / total, unit="solves/s",
+                   sample=f"oracle setup + {done} of {gpu_cycles} V(2,2) cycles timed "
+                          f"({t_setup:.2f} s + {per:.2f} s/cycle), extrapolated to the full "
+                          f"solve")
+    out["seconds_per_solve"] = total
+    return out, phi_ref, (np.asarray(phi_ref) if phi_ref is not None else None)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=4097, help="grid side (default 4097)")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--probe", action="store_true",
+                    help="short run for counter collection: warmup + 2 solves + one copy probe")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: --gpus {args.gpus} requested; this solver runs on one GPU only "
+              f"(no multi-GPU path is built). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2602_01888_amd as tomg
+    import workloads as w
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t = time.time()
+    prob = w.perturbed_circle(args.n, seed=args.seed)
+    log(f"[bench] generated {prob.name} in {time.time() - t:.1f}s")
+    d = tomg.upload(prob, dev)
+    phi = d["phi0"].clone()
+    n0 = prob.nx * prob.ny
+
+    def make(precision):
+        return tomg.Problem.from_grid(prob, precision=precision, device=dev)
+
+    def step(p):
+        p.setup_coeffs(d["rho"], xp=d["xp"], yp=d["yp"], mask=d["mask"])
+        phi.copy_(d["phi0"])
+        r = p.solve(phi, rel_tol=1e-10, max_cycles=100)
+        if not r.ok:
+            raise RuntimeError(f"solve failed: {r}")
+        return r
+
+    p64 = make("fp64")
+    if args.probe:
+        for _ in range(2):
+            step(p64)
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        tomg.copy_probe(a, b)
+        torch.cuda.synchronize()
+        log("[bench] probe run done")
+        return 0
+
+    # ------------------------------------------------------------ FP64 ----
+    for _ in range(args.warmup):
+        r = step(p64)
+    torch.cuda.synchronize()
+    p64.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step(p64)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = p64.profile_read()
+    p64.profile(False)
+    cycles = r.cycles
+    log(f"[bench] fp64: {elapsed / args.steps * 1e3:.3f} ms/step, {cycles} cycles, "
+        f"rel {r.rel:.3e}")
+    phi64 = phi.detach().cpu().numpy()
+
+    # solve only (hierarchy resident)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        phi.copy_(d["phi0"])
+        p64.solve(phi, rel_tol=1e-10, max_cycles=100)
+    torch.cuda.synchronize()
+    solve_only = (time.perf_counter() - t1) / args.steps
+
+    # HBM copy ceiling beside the solver
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    tomg.copy_probe(a, b)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(10):
+        tomg.copy_probe(a, b)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 10 / (time.perf_counter() - t2) / 1e9
+    del a, b
+
+    nxc, nyc = p64.level_shape(1)
+    down_ms = prof[0] / max(prof[1], 1)
+    up_ms = prof[2] / max(prof[3], 1)
+    bytes_pass = level0_pass_bytes(prob.nx, prob.ny, nxc, nyc)
+    achieved = bytes_pass / (down_ms * 1e-3) / 1e9
+    tr = committed_traffic()
+    roofline = {"bound": "hbm", "kernel": "level-0 down pass (2 GS4 sweeps + residual + "
+                                          "full weighting)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr["down_bytes_per_launch"] if tr else None,
+                "algorithmic_bytes_per_launch": bytes_pass,
+                "avg_launch_ms": round(down_ms, 4), "launches": int(prof[1]),
+                "up_pass_avg_ms": round(up_ms, 4),
+                "up_pass_GBs": round(bytes_pass / (up_ms * 1e-3) / 1e9, 1),
+                "copy_probe_GBs": round(copy_gbs, 1)}
+
+    # ----------------------------------------------------------- mixed ----
+    mixed = None
+    if not args.no_extras:
+        p32 = make("fp32_ir")
+        for _ in range(max(1, args.warmup)):
+            r32 = step(p32)
+        torch.cuda.synchronize()
+        k32 = max(3, args.steps)
+        t3 = time.perf_counter()
+        for _ in range(k32):
+            r32 = step(p32)
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t3
+        phi32 = phi.detach().cpu().numpy()
+        mixed = {"value": k32 / el32, "unit": "solves/s", "dof_per_s": k32 * n0 / el32,
+                 "ms_per_step": el32 / k32 * 1e3, "refinement_steps": r32.cycles,
+                 "inner_cycles_per_step": 2, "rel_residual": r32.rel,
+                 "speedup_vs_fp64": (k32 / el32) / (args.steps / elapsed),
+                 "diff_vs_fp64_gpu": float(np.max(np.abs(phi32 - phi64)) /
+                                           np.max(np.abs(phi64)))}
+        del p32
+
+    # ------------------------------------------------------ CPU oracle ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, _, ref = cpu_baseline(prob, cycles)
+        if ref is not None:
+            scale = float(np.max(np.abs(ref)))
+            err64 = float(np.max(np.abs(phi64 - ref)) / scale)
+            cpu["gpu_fp64_error_vs_oracle"] = err64
+            if mixed is not None:
+                mixed["error_vs_oracle"] = float(np.max(np.abs(phi32 - ref)) / scale)
+
+    value = args.steps / elapsed
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"perturbed-circle conductor {prob.nx}x{prob.ny} (seed "
+                               f"{args.seed}), 8 Gaussians, numeric map; setup_coeffs + FP64 "
+                               f"V(2,2) solve to 1e-10 relative residual",
+                   "nx": prob.nx, "ny": prob.ny, "dof": n0, "rel_tol": 1e-10},
+        "dof_per_s": value * n0,
+        "cycles": cycles,
+        "rel_residual": r.rel,
+        "solve_only": {"ms": solve_only * 1e3, "solves_per_s": 1.0 / solve_only,
+                       "dof_per_s": n0 / solve_only},
+        "mixed": mixed,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -178,6 +178,19 @@ tomg_status tomg_smooth(tomg_problem *p, double *d_phi, int32_t sweeps);
 /* d_r = f - A phi at free nodes, 0 at Dirichlet nodes (asynchronous). */
 tomg_status tomg_residual(tomg_problem *p, const double *d_phi, double *d_r);
 
+/* ---- measurement ----------------------------------------------------- */
+/* enable != 0: bracket every level-0 down pass and up pass with HIP events
+ * on the problem's stream; 0: stop.  Enabling resets the accumulators. */
+tomg_status tomg_profile(tomg_problem *p, int32_t enable);
+/* Synchronises the stream and returns out[4] = {total ms of level-0 down
+ * passes, their count, total ms of level-0 up passes, their count} since
+ * tomg_profile(p, 1). */
+tomg_status tomg_profile_read(tomg_problem *p, double *out);
+/* STREAM-style device copy of `bytes` bytes (multiple of 16, 16-byte aligned
+ * pointers) on `stream`: the practical HBM ceiling measured beside the
+ * solver. */
+tomg_status tomg_copy_probe(const void *d_src, void *d_dst, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -185,6 +185,15 @@ class Problem:
         self._check(self.lib.tomg_smooth(self._h, _ptr(phi, torch.float64, (self.ny, self.nx),
                                                        "phi"), sweeps), "smooth")
 
+    def profile(self, enable: bool = True):
+        self._check(self.lib.tomg_profile(self._h, 1 if enable else 0), "profile")
+
+    def profile_read(self):
+        """(down_ms_total, down_count, up_ms_total, up_count) of level-0 passes."""
+        out = (C.c_double * 4)()
+        self._check(self.lib.tomg_profile_read(self._h, out), "profile_read")
+        return tuple(out)
+
     def residual(self, phi) -> torch.Tensor:
         r = torch.empty_like(phi)
         self._check(self.lib.tomg_residual(self._h, _ptr(phi, torch.float64, (self.ny, self.nx),
@@ -223,6 +232,17 @@ def solve_batch(problems: Sequence[Problem], phis: Sequence[torch.Tensor], rel_t
     sts = (C.c_int * n)()
     lib.tomg_solve_batch(hs, ps, n, rel_tol, max_cycles, cyc, rel, sts)
     return [SolveResult(sts[k], cyc[k], rel[k]) for k in range(n)]
+
+
+def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """Device copy of src into dst with the library's STREAM-style kernel."""
+    lib = _lib.load()
+    nbytes = src.numel() * src.element_size()
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    st = lib.tomg_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                             C.c_void_p(s.cuda_stream))
+    if st != TOMG_OK:
+        raise TomgError(st, "copy_probe")
 
 
 def upload(prob, device="cuda"):

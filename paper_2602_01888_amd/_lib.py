@@ -22,7 +22,8 @@ FIELD = {"exx": 0, "exy": 1, "eyy": 2, "det": 3, "rhs": 4, "dir": 5, "stencil": 
 EXPORTS = ["tomg_config_default", "tomg_num_levels", "tomg_workspace_bytes", "tomg_create",
            "tomg_destroy", "tomg_last_error", "tomg_set_stream", "setup_coeffs",
            "tomg_update_rhs", "vcycle", "solve", "residual_norm", "tomg_solve_batch",
-           "tomg_export", "tomg_level_shape", "tomg_smooth", "tomg_residual"]
+           "tomg_export", "tomg_level_shape", "tomg_smooth", "tomg_residual", "tomg_profile",
+           "tomg_profile_read", "tomg_copy_probe"]
 
 
 class Config(C.Structure):
@@ -66,6 +67,9 @@ def load(path: str = LIB_PATH):
         "tomg_level_shape": (C.c_int, [P, I32, C.POINTER(I32), C.POINTER(I32)]),
         "tomg_smooth": (C.c_int, [P, VP, I32]),
         "tomg_residual": (C.c_int, [P, VP, VP]),
+        "tomg_profile": (C.c_int, [P, I32]),
+        "tomg_profile_read": (C.c_int, [P, C.POINTER(D)]),
+        "tomg_copy_probe": (C.c_int, [VP, VP, C.c_size_t, VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

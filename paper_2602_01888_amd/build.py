@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtomg.so")
-SOURCES = ["api.hip", "kernels.hip", "fused.hip"]
+SOURCES = ["api.hip", "kernels.hip", "fused.hip", "tail.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -120,7 +120,18 @@ static tomg_status read_scalars(tomg_problem *p, double *h) {
   HIP_TRY(p, hipMemcpyAsync(h, p->scal, kNumSlots * sizeof(double), hipMemcpyDeviceToHost,
                             p->stream));
   HIP_TRY(p, hipStreamSynchronize(p->stream));
+  prof_harvest(p);
   return TOMG_OK;
+}
+
+static void destroy_events(tomg_problem *p) {
+  for (int kind = 0; kind < 2; ++kind)
+    for (int e = 0; e < tomg_problem::kMaxEv; ++e)
+      for (int q = 0; q < 2; ++q)
+        if (p->ev[kind][e][q]) {
+          (void)hipEventDestroy(p->ev[kind][e][q]);
+          p->ev[kind][e][q] = nullptr;
+        }
 }
 
 extern "C" {
@@ -219,7 +230,11 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
   return TOMG_OK;
 }
 
-void tomg_destroy(tomg_problem *p) { delete p; }
+void tomg_destroy(tomg_problem *p) {
+  if (!p) return;
+  destroy_events(p);
+  delete p;
+}
 
 const char *tomg_last_error(const tomg_problem *p) {
   if (!p) return "null problem";
@@ -394,6 +409,43 @@ tomg_status tomg_residual(tomg_problem *p, const double *d_phi, double *d_r) {
   if (!p->ready) return fail(p, TOMG_ESTATE, "residual before setup_coeffs");
   HIP_TRY(p, launch_residual0(p, d_phi, d_r));
   return TOMG_OK;
+}
+
+tomg_status tomg_profile(tomg_problem *p, int32_t enable) {
+  if (!p) return TOMG_EINVAL;
+  if (enable) {
+    for (int kind = 0; kind < 2; ++kind)
+      for (int e = 0; e < tomg_problem::kMaxEv; ++e)
+        for (int q = 0; q < 2; ++q)
+          if (!p->ev[kind][e][q]) HIP_TRY(p, hipEventCreate(&p->ev[kind][e][q]));
+    p->nev[0] = p->nev[1] = 0;
+    p->prof_ms[0] = p->prof_ms[1] = 0.0;
+    p->prof_cnt[0] = p->prof_cnt[1] = 0.0;
+    p->prof = true;
+  } else {
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    prof_harvest(p);
+    p->prof = false;
+  }
+  return TOMG_OK;
+}
+
+tomg_status tomg_profile_read(tomg_problem *p, double *out) {
+  if (!p || !out) return TOMG_EINVAL;
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  prof_harvest(p);
+  out[0] = p->prof_ms[0];
+  out[1] = p->prof_cnt[0];
+  out[2] = p->prof_ms[1];
+  out[3] = p->prof_cnt[1];
+  return TOMG_OK;
+}
+
+tomg_status tomg_copy_probe(const void *d_src, void *d_dst, size_t bytes, void *stream) {
+  if (!d_src || !d_dst || bytes % 16 || ((uintptr_t)d_src % 16) || ((uintptr_t)d_dst % 16))
+    return TOMG_EINVAL;
+  return launch_copy_probe(d_src, d_dst, bytes, (hipStream_t)stream) == hipSuccess ? TOMG_OK
+                                                                                 : TOMG_EDEVICE;
 }
 
 }  // extern "C"

@@ -25,13 +25,20 @@
 // ends in a barrier.  Each sweep invalidates at most 4 halo columns and 2
 // halo rows at the edges of the block, which is what H and HV cover.
 #include <cmath>
+#include <cstdlib>
 
 #include "tomg_internal.h"
 
 namespace tomg {
 namespace {
 
-constexpr int kBW = 256;
+#ifndef TOMG_BW
+#define TOMG_BW 256
+#endif
+#ifndef TOMG_MIN_WAVES
+#define TOMG_MIN_WAVES 1
+#endif
+constexpr int kBW = TOMG_BW;
 
 template <typename T>
 struct PassArgs {
@@ -51,24 +58,38 @@ struct PassArgs {
   int CH, W;
 };
 
+// Per-thread values of one row as loaded from global memory.
+template <typename T, bool EPS>
+struct Raw;
+template <typename T>
+struct Raw<T, true> {
+  T x, f, xx, xy, yy, c00, c01, c10, c11;
+  int d;
+};
+template <typename T>
+struct Raw<T, false> {
+  T x, f, a[9], c00, c01, c10, c11;
+  int d;
+};
+
+// Coefficients of one row held in registers.  ik = 1 / diagonal, and 0 at
+// Dirichlet nodes (which are never relaxed).
 template <typename T, bool EPS>
 struct Rec;
 template <typename T>
 struct Rec<T, true> {
-  T ax, ay, gx, gy, k6, f;
-  int d;
+  T ax, ay, gx, gy, k6, f, ik;
 };
 template <typename T>
 struct Rec<T, false> {
   T a[9];
-  T f;
-  int d;
+  T f, ik;
 };
 
 __device__ __forceinline__ int ring_slot(int o, int n) { return ((o % n) + n) % n; }
 
-// Off-centre sum and diagonal of the row at LDS column t+1 of rows
-// (lo, mid, hi) = (r-1, r, r+1).
+// Off-centre sum and diagonal of the node at LDS column t+1 of rows
+// (lo, mid, hi) = (r-1, r, r+1): (A x)_c = off + dg x_c.
 template <typename T>
 __device__ __forceinline__ void apply_eps(const Rec<T, true> &c, const T *lo, const T *mid,
                                           const T *hi, int t, T &off, T &dg) {
@@ -106,12 +127,15 @@ __device__ __forceinline__ T block_sum(T v, T *red) {
   return v;
 }
 
+// Level 0 (EPS) prefetches the next row pair while it works on the current
+// one; the stored-stencil levels load the current pair at the start of the
+// step (their nine coefficient planes leave no registers for a second pair).
 template <typename T, bool EPS, int NU, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
-__global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
+__global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
   constexpr int H = 4 * NU + 2;
   constexpr int HV = 2 * NU + 3;
   constexpr int NS = 2 * NU + 2;  // coefficient rows in flight: 2k-2NU .. 2k+1
-  constexpr int NR = 2 * NU + 4;  // value rows in flight:       2k-2NU-1 .. 2k+1
+  constexpr int NR = 2 * NU + 4;  // value rows in LDS:          2k-2NU-2 .. 2k+1
   __shared__ T L[NR][kBW + 2];
   __shared__ T xch[4][kBW + 2];
   __shared__ double red[kBW / 64];
@@ -120,6 +144,7 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * a.W;
   const int gi = x0 - H + t;
+  const int gc = min(max(gi, 0), nx - 1);  // clamped column: loads never leave the array
   const bool inr = gi >= 0 && gi < nx;
   const bool updc = gi >= 1 && gi <= nx - 2;
   const bool outc = t >= H && t < H + a.W && gi < nx;
@@ -131,6 +156,8 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
   const int k0 = ys >> 1;
   const int k1 = (y1 - 1 + 2 * NU) >> 1;
   const size_t n = (size_t)nx * ny;
+  const int Ic = gc >> 1;
+  const int Ic1 = PROLONG ? min(Ic + 1, a.nxc - 1) : 0;
 
   for (int r = 0; r < NR; ++r) {
     L[r][t + 1] = T(0);
@@ -138,6 +165,48 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
   }
   if (t < 2)
     for (int r = 0; r < 4; ++r) xch[r][t * (kBW + 1)] = T(0);
+
+  // all loads of a row are issued unconditionally from clamped addresses
+  auto load_row = [&](int r, Raw<T, EPS> &w) {
+    const int rc = min(max(r, 0), ny - 1);
+    const size_t c = (size_t)rc * nx + gc;
+    w.x = ZERO ? T(0) : a.xin[c];
+    w.f = a.b[c];
+    w.d = a.dir[c];
+    if constexpr (EPS) {
+      w.xx = a.exx[c];
+      w.xy = a.exy[c];
+      w.yy = a.eyy[c];
+    } else {
+#pragma unroll
+      for (int z = 0; z < 9; ++z) w.a[z] = a.st[z * n + c];
+    }
+    if constexpr (PROLONG) {
+      const int J = rc >> 1, J1 = min(J + 1, a.nyc - 1);
+      const T *r0 = a.xc + (size_t)J * a.nxc;
+      const T *r1 = a.xc + (size_t)J1 * a.nxc;
+      w.c00 = r0[Ic];
+      w.c01 = r0[Ic1];
+      w.c10 = r1[Ic];
+      w.c11 = r1[Ic1];
+    }
+  };
+  // node value of a loaded row (plus the prolongated correction) into LDS
+  auto commit_row = [&](int r, const Raw<T, EPS> &w) {
+    const bool ld = r >= ys && r <= ye && inr;
+    T v = ld ? w.x : T(0);
+    if constexpr (PROLONG) {
+      if (ld && !w.d && updc && r > 0 && r < ny - 1) {
+        T e = odd ? T(0.5) * (w.c00 + w.c01) : w.c00;
+        if (r & 1) {
+          const T e1 = odd ? T(0.5) * (w.c10 + w.c11) : w.c10;
+          e = T(0.5) * (e + e1);
+        }
+        v += e;
+      }
+    }
+    L[ring_slot(r, NR)][t + 1] = v;
+  };
 
   Rec<T, EPS> rec[NS];
 #pragma unroll
@@ -149,17 +218,22 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
       for (int q = 0; q < 9; ++q) rec[s].a[q] = T(0);
       rec[s].f = T(0);
     }
-    rec[s].d = 1;
+    rec[s].ik = T(0);
   }
-  // raw tensor values carried between steps (level 0): row 2k-2 (eyy, exy)
+  Raw<T, EPS> cur[2], nxt[2];
+  // level 0: tensor values carried from earlier rows: row 2k-2 (eyy, exy)
   // and row 2k-1 (exx, exy, eyy, f, dir)
-  T c_yy2 = T(0), c_xy2 = T(0);
-  T c_xx1 = T(0), c_xy1 = T(0), c_yy1 = T(0), c_f1 = T(0);
+  T c_yy2 = T(0), c_xy2 = T(0), c_xx1 = T(0), c_xy1 = T(0), c_yy1 = T(0), c_f1 = T(0);
   int c_d1 = 1;
-  T rprev = T(0);
-  T acc = T(0);
   (void)c_yy2; (void)c_xy2; (void)c_xx1; (void)c_xy1; (void)c_yy1; (void)c_f1; (void)c_d1;
+  T rprev = T(0), acc = T(0);
 
+  if constexpr (EPS) {  // prologue: the first row pair
+    load_row(2 * k0, cur[0]);
+    load_row(2 * k0 + 1, cur[1]);
+    commit_row(2 * k0, cur[0]);
+    commit_row(2 * k0 + 1, cur[1]);
+  }
   __syncthreads();
 
   for (int kb = k0; kb <= k1; kb += NU + 1) {
@@ -167,93 +241,50 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
     for (int ph = 0; ph <= NU; ++ph) {
       const int k = kb + ph;
       if (k <= k1) {
-        const int ra = 2 * k;  // rows ra, ra+1 enter the window
-        // ---------------- load ----------------
-        T vxx[2], vxy[2], vyy[2], vf[2];
-        int vd[2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int r = ra + q;
-          const bool ld = r >= ys && r <= ye;
-          T v = T(0);
-          vxx[q] = vxy[q] = vyy[q] = vf[q] = T(0);
-          vd[q] = 1;
-          if (ld && inr) {
-            const size_t c = (size_t)r * nx + gi;
-            if (!ZERO) v = a.xin[c];
-            const int dflag = a.dir[c];
-            vd[q] = dflag;
-            vf[q] = a.b[c];
-            if constexpr (PROLONG) {
-              if (!dflag && updc && r > 0 && r < ny - 1) {
-                const T *c0 = a.xc + (size_t)(r >> 1) * a.nxc;
-                const int I = gi >> 1;
-                T e = odd ? T(0.5) * (c0[I] + c0[I + 1]) : c0[I];
-                if (r & 1) {
-                  const T *c1 = c0 + a.nxc;
-                  const T e1 = odd ? T(0.5) * (c1[I] + c1[I + 1]) : c1[I];
-                  e = T(0.5) * (e + e1);
-                }
-                v += e;
-              }
-            }
-            if constexpr (EPS) {
-              vxx[q] = a.exx[c];
-              vxy[q] = a.exy[c];
-              vyy[q] = a.eyy[c];
-            } else {
-              Rec<T, false> &R = rec[ring_slot(2 * ph + q, NS)];
-#pragma unroll
-              for (int z = 0; z < 9; ++z) R.a[z] = a.st[z * n + c];
-            }
-          }
-          if constexpr (!EPS) {
-            Rec<T, false> &R = rec[ring_slot(2 * ph + q, NS)];
-            R.f = vf[q];
-            R.d = vd[q];
-            if (!(ld && inr)) {
-#pragma unroll
-              for (int z = 0; z < 9; ++z) R.a[z] = T(0);
-            }
-          }
-          L[ring_slot(r, NR)][t + 1] = v;
-        }
-        // ------------- coefficients of rows ra-1 and ra (level 0) -------------
+        const int ra = 2 * k;  // rows ra, ra+1 are the newest in the window
         if constexpr (EPS) {
+          // prefetch the next pair; committed at the end of this step
+          load_row(ra + 2, nxt[0]);
+          load_row(ra + 3, nxt[1]);
+          // coefficients of rows ra-1 and ra
           xch[0][t + 1] = c_xx1;
           xch[1][t + 1] = c_xy1;
-          xch[2][t + 1] = vxx[0];
-          xch[3][t + 1] = vxy[0];
-        }
-        __syncthreads();
-        if constexpr (EPS) {
-          {  // row ra-1: neighbours rows ra-2 (carry) and ra
+          xch[2][t + 1] = cur[0].xx;
+          xch[3][t + 1] = cur[0].xy;
+          __syncthreads();
+          {
             Rec<T, true> &R = rec[ring_slot(2 * ph - 1, NS)];
             R.ax = c_xx1 * a.cx;
             R.ay = c_yy1 * a.cy;
-            R.gx = (xch[0][t + 2] - xch[0][t]) * a.qx + (vxy[0] - c_xy2) * a.qxy;
-            R.gy = (vyy[0] - c_yy2) * a.qy + (xch[1][t + 2] - xch[1][t]) * a.qxy;
+            R.gx = (xch[0][t + 2] - xch[0][t]) * a.qx + (cur[0].xy - c_xy2) * a.qxy;
+            R.gy = (cur[0].yy - c_yy2) * a.qy + (xch[1][t + 2] - xch[1][t]) * a.qxy;
             R.k6 = c_xy1 * a.hxy;
             R.f = c_f1;
-            R.d = c_d1;
+            R.ik = c_d1 ? T(0) : T(-1) / (T(2) * (R.ax + R.ay));
           }
-          {  // row ra: neighbours ra-1 (carry) and ra+1
+          {
             Rec<T, true> &R = rec[ring_slot(2 * ph, NS)];
-            R.ax = vxx[0] * a.cx;
-            R.ay = vyy[0] * a.cy;
-            R.gx = (xch[2][t + 2] - xch[2][t]) * a.qx + (vxy[1] - c_xy1) * a.qxy;
-            R.gy = (vyy[1] - c_yy1) * a.qy + (xch[3][t + 2] - xch[3][t]) * a.qxy;
-            R.k6 = vxy[0] * a.hxy;
-            R.f = vf[0];
-            R.d = vd[0];
+            R.ax = cur[0].xx * a.cx;
+            R.ay = cur[0].yy * a.cy;
+            R.gx = (xch[2][t + 2] - xch[2][t]) * a.qx + (cur[1].xy - c_xy1) * a.qxy;
+            R.gy = (cur[1].yy - c_yy1) * a.qy + (xch[3][t + 2] - xch[3][t]) * a.qxy;
+            R.k6 = cur[0].xy * a.hxy;
+            R.f = cur[0].f;
+            R.ik = cur[0].d ? T(0) : T(-1) / (T(2) * (R.ax + R.ay));
           }
-          c_yy2 = vyy[0];
-          c_xy2 = vxy[0];
-          c_xx1 = vxx[1];
-          c_xy1 = vxy[1];
-          c_yy1 = vyy[1];
-          c_f1 = vf[1];
-          c_d1 = vd[1];
+        } else {
+          load_row(ra, cur[0]);
+          load_row(ra + 1, cur[1]);
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            Rec<T, false> &R = rec[ring_slot(2 * ph + q, NS)];
+#pragma unroll
+            for (int z = 0; z < 9; ++z) R.a[z] = cur[q].a[z];
+            R.f = cur[q].f;
+            R.ik = cur[q].d ? T(0) : T(1) / cur[q].a[4];
+            commit_row(ra + q, cur[q]);
+          }
+          __syncthreads();
         }
         // ---------------- sweeps ----------------
 #pragma unroll
@@ -268,10 +299,10 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
             const T *hi = L[ring_slot(r + 1, NR)];
 #pragma unroll
             for (int cp = 0; cp < 2; ++cp) {
-              if (rowok && updc && odd == cp && !R.d) {
+              if (rowok && updc && odd == cp && R.ik != T(0)) {
                 T off, dg;
                 apply<T, EPS>(R, lo, mid, hi, t, off, dg);
-                mid[t + 1] = (R.f - off) / dg;
+                mid[t + 1] = (R.f - off) * R.ik;
               }
               __syncthreads();
             }
@@ -288,7 +319,7 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
           res[q] = T(0);
           if (RESTRICT || NORM) {
             const bool rowok = r >= 1 && r <= ny - 2 && r > ys && r < ye;
-            if (rowok && updc && !R.d) {
+            if (rowok && updc && R.ik != T(0)) {
               T off, dg;
               apply<T, EPS>(R, L[ring_slot(r - 1, NR)], mid, L[ring_slot(r + 1, NR)], t, off,
                             dg);
@@ -315,6 +346,20 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
           }
         }
         __syncthreads();
+        if constexpr (EPS) {
+          // the prefetched pair enters the window; shift the carried rows
+          commit_row(ra + 2, nxt[0]);
+          commit_row(ra + 3, nxt[1]);
+          c_yy2 = cur[0].yy;
+          c_xy2 = cur[0].xy;
+          c_xx1 = cur[1].xx;
+          c_xy1 = cur[1].xy;
+          c_yy1 = cur[1].yy;
+          c_f1 = cur[1].f;
+          c_d1 = cur[1].d;
+          cur[0] = nxt[0];
+          cur[1] = nxt[1];
+        }
       }
     }
   }
@@ -330,11 +375,21 @@ __global__ __launch_bounds__(kBW) void k_pass(PassArgs<T> a) {
 // Host side
 // ---------------------------------------------------------------------------
 
-// Rows per block: enough blocks to fill the chip, bands of at least 32 rows.
+static int env_int(const char *name, int dflt) {
+  const char *s = getenv(name);
+  return (s && *s) ? atoi(s) : dflt;
+}
+
+// Rows per block: the tallest band (<= 128 rows) that still gives
+// band_target blocks; never below band_min rows (halo rows are recomputed,
+// so short bands cost redundant work).  TOMG_BAND_TARGET / TOMG_BAND_MIN
+// override the defaults (tuning only).
 static int pick_band(int nx, int ny, int W) {
+  static const int target = env_int("TOMG_BAND_TARGET", 1024);
+  static const int cmin = env_int("TOMG_BAND_MIN", 16);
   const int bx = (nx + W - 1) / W;
   int CH = 128;
-  while (CH > 32 && (long)bx * ((ny + CH - 1) / CH) < 1024) CH >>= 1;
+  while (CH > cmin && CH > 8 && (long)bx * ((ny + CH - 1) / CH) < target) CH >>= 1;
   return CH;
 }
 
@@ -342,7 +397,7 @@ static int pick_band(int nx, int ny, int W) {
 // partial-sum buffer).
 size_t fused_max_blocks(int nx, int ny) {
   const int Wmin = kBW - 2 * (4 * 4 + 2);
-  return (size_t)((nx + Wmin - 1) / Wmin) * (size_t)((ny + 31) / 32);
+  return (size_t)((nx + Wmin - 1) / Wmin) * (size_t)((ny + 7) / 8);
 }
 
 template <typename T, bool EPS, int NU, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>

@@ -9,6 +9,7 @@
 // Every reduction runs on a fixed grid of kRedBlocks blocks and a fixed
 // tree, so a residual norm is bitwise reproducible from run to run.
 #include <cmath>
+#include <cstdlib>
 
 #include "tomg_internal.h"
 
@@ -548,6 +549,13 @@ __global__ void k_ir_update(double *phi, const float *e32, const uint8_t *dir, s
     if (!dir[c]) phi[c] += (double)e32[c];
 }
 
+// STREAM-style copy, 16 bytes per lane per iteration.
+__global__ void k_copy16(const double2 *__restrict__ src, double2 *__restrict__ dst, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x)
+    dst[c] = src[c];
+}
+
 // ---------------------------------------------------------------------------
 // Host-side helpers
 // ---------------------------------------------------------------------------
@@ -607,22 +615,62 @@ void restrict_level(tomg_problem *p, const Op &op, const T *x, const T *b, const
 // each level is one fused down pass and one fused up pass; when partials is
 // given, the level-0 up pass also leaves per-block sums of the squared final
 // residual there (block count in *nblocks).
+// First level handed to the single-workgroup tail: the first coarse level
+// with at most tail_max_nodes() nodes and at most 4 levels below it.
+static int tail_level(const tomg_problem *p) {
+  for (int l = 1; l < p->L; ++l)
+    if ((long)p->lv[l].nx * p->lv[l].ny <= tail_max_nodes() && p->L - l <= 4) return l;
+  return p->L - 1;
+}
+
+// One V(nu1, nu2) cycle in precision T.  x0/b0: level-0 iterate and rhs;
+// op0: level-0 operator; coarse data from views[l].{x,b,st}.  zero0: the
+// level-0 iterate starts at zero (not read).  With the four-colour smoother,
+// every level above the tail is one fused down pass and one fused up pass
+// and the small levels run in one workgroup; when partials is given, the
+// level-0 up pass also leaves per-block sums of the squared final residual
+// there (block count in *nblocks).
 template <typename T>
 hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
                       const LevelView<T> *views, bool zero0, double *partials, int *nblocks) {
   const int L = p->L;
   const dim3 blk(64, 4);
-  const bool fused = p->cfg.smoother == TOMG_GS4;
   if (nblocks) *nblocks = 0;
+  if (p->cfg.smoother == TOMG_GS4) {
+    const int lc = tail_level(p);
+    for (int l = 0; l < lc; ++l) {
+      T *x = l == 0 ? x0 : views[l].x;
+      const T *b = l == 0 ? b0 : views[l].b;
+      if (l == 0) prof_begin(p, 0);
+      fused_down<T>(p, l, x, views[l].pong, b, op0.exx, op0.exy, op0.eyy, views[l].st,
+                    views[l + 1].b, l > 0 || zero0);
+      if (l == 0) prof_end(p, 0);
+    }
+    T *xs[kMaxLevels];
+    T *bs[kMaxLevels];
+    const T *sts[kMaxLevels];
+    for (int l = 0; l < L; ++l) {
+      xs[l] = views[l].x;
+      bs[l] = views[l].b;
+      sts[l] = views[l].st;
+    }
+    tail_cycle<T>(p, lc, xs, bs, sts);
+    for (int l = lc - 1; l >= 0; --l) {
+      T *x = l == 0 ? x0 : views[l].x;
+      const T *b = l == 0 ? b0 : views[l].b;
+      if (l == 0) prof_begin(p, 1);
+      const int nb = fused_up<T>(p, l, views[l].pong, x, b, op0.exx, op0.exy, op0.eyy,
+                                 views[l].st, views[l + 1].x, l == 0 ? partials : nullptr);
+      if (l == 0) prof_end(p, 1);
+      if (l == 0 && nblocks) *nblocks = partials ? nb : 0;
+    }
+    return hipGetLastError();
+  }
+  // damped Jacobi: one launch per step
   for (int l = 0; l < L - 1; ++l) {
     const tomg::Level &lv = p->lv[l], &lc = p->lv[l + 1];
     T *x = l == 0 ? x0 : views[l].x;
     const T *b = l == 0 ? b0 : views[l].b;
-    if (fused) {
-      fused_down<T>(p, l, x, views[l].pong, b, op0.exx, op0.exy, op0.eyy, views[l].st,
-                    views[l + 1].b, l > 0 || zero0);
-      continue;
-    }
     if (l > 0 || zero0) hipLaunchKernelGGL((k_zero<T>), grid1(lv.n), 256, 0, p->stream, x, lv.n);
     if (l > 0) {
       const StOp<T> op = st_op<T>(views[l].st, lv.nx, lv.ny);
@@ -642,12 +690,6 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
     const tomg::Level &lv = p->lv[l], &lc = p->lv[l + 1];
     T *x = l == 0 ? x0 : views[l].x;
     const T *b = l == 0 ? b0 : views[l].b;
-    if (fused) {
-      const int nb = fused_up<T>(p, l, views[l].pong, x, b, op0.exx, op0.exy, op0.eyy,
-                                 views[l].st, views[l + 1].x, l == 0 ? partials : nullptr);
-      if (l == 0 && nblocks) *nblocks = partials ? nb : 0;
-      continue;
-    }
     hipLaunchKernelGGL((k_prolong<T>), grid2(lv.nx, lv.ny, blk), blk, 0, p->stream,
                        (const T *)views[l + 1].x, lc.nx, x, lv.dir, lv.nx, lv.ny);
     if (l > 0) {
@@ -783,6 +825,38 @@ hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zer
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps) {
   smooth_level(p, op64(p), phi, (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny, sweeps);
   return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 16;
+  hipLaunchKernelGGL(k_copy16, 8192, 256, 0, s, (const double2 *)src, (double2 *)dst, n);
+  return hipGetLastError();
+}
+
+void prof_begin(tomg_problem *p, int kind) {
+  if (!p->prof || p->nev[kind] >= tomg_problem::kMaxEv) return;
+  (void)hipEventRecord(p->ev[kind][p->nev[kind]][0], p->stream);
+}
+
+void prof_end(tomg_problem *p, int kind) {
+  if (!p->prof || p->nev[kind] >= tomg_problem::kMaxEv) return;
+  (void)hipEventRecord(p->ev[kind][p->nev[kind]][1], p->stream);
+  ++p->nev[kind];
+}
+
+// Called after the stream has been synchronised.
+void prof_harvest(tomg_problem *p) {
+  if (!p->prof) return;
+  for (int kind = 0; kind < 2; ++kind) {
+    for (int e = 0; e < p->nev[kind]; ++e) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, p->ev[kind][e][0], p->ev[kind][e][1]) == hipSuccess) {
+        p->prof_ms[kind] += ms;
+        p->prof_cnt[kind] += 1.0;
+      }
+    }
+    p->nev[kind] = 0;
+  }
 }
 
 hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r) {

@@ -1,0 +1,234 @@
+// The smallest levels of the V-cycle in one workgroup (arXiv 2602.01888,
+// Section 3).
+//
+// Below about a thousand nodes per level, a level pass is bound by latency:
+// a launch per pass would cost more than its work.  One 1024-thread
+// workgroup runs the sub-cycle from level lc (zero start, right-hand side
+// from the level above) down to the coarsest level and back.  Each thread
+// owns at most one node per level and keeps their stencil rows and
+// right-hand sides in registers; the iterates of all tail levels and one
+// residual array live in LDS, so a colour phase is an LDS read-modify-write
+// between two barriers.  Arithmetic per node is that of the other kernels:
+// four-colour Gauss-Seidel on the stored 9-point stencil, full weighting,
+// bilinear prolongation, explicit coarsest inverse.
+#include "tomg_internal.h"
+
+namespace tomg {
+namespace {
+
+constexpr int kTailThreads = 1024;
+constexpr int kOwn = 1;        // nodes per thread and level
+constexpr int kTailLevels = 4; // levels of at most kTailThreads nodes
+
+template <typename T>
+struct TailLevel {
+  int nx, ny;
+  const T *st;
+  T *x;
+  const T *b;
+  const uint8_t *dir;
+  int off;  // offset of the level's iterate in the LDS array
+};
+
+template <typename T>
+struct TailArgs {
+  int lc, nl, nu1, nu2;  // levels lc .. lc+nl-1 (the last is the coarsest)
+  const double *cinv;
+  const int *cidx;
+  TailLevel<T> lv[kTailLevels];
+};
+
+template <typename T>
+struct Own {
+  T a[9];
+  T b, ik;  // ik = 1 / diagonal, 0 where the node is not relaxed
+  int c;    // node index in the level, -1 when not owned
+  int col;  // colour (i mod 2) + 2 (j mod 2)
+};
+
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T *X = reinterpret_cast<T *>(smem_raw);
+  __shared__ double bb[kMaxCoarseUnknowns];
+  const int t = threadIdx.x;
+  const int nl = a.nl;
+  int total = 0, rmax = 0;
+  for (int q = 0; q < nl; ++q) {
+    total += a.lv[q].nx * a.lv[q].ny;
+    rmax = max(rmax, a.lv[q].nx * a.lv[q].ny);
+  }
+  T *Rb = X + total;  // residual of the level being restricted
+
+  Own<T> own[kTailLevels][kOwn];
+#pragma unroll
+  for (int q = 0; q < kTailLevels; ++q)
+#pragma unroll
+    for (int m = 0; m < kOwn; ++m) {
+      Own<T> &o = own[q][m];
+      o.c = -1;
+      o.b = o.ik = T(0);
+      o.col = 0;
+#pragma unroll
+      for (int z = 0; z < 9; ++z) o.a[z] = T(0);
+      if (q >= nl) continue;
+      const TailLevel<T> &v = a.lv[q];
+      const int n = v.nx * v.ny;
+      const int c = t + m * kTailThreads;
+      if (c >= n) continue;
+      const int i = c % v.nx, j = c / v.nx;
+      o.c = c;
+      o.col = (i & 1) + 2 * (j & 1);
+      const bool interior = i > 0 && j > 0 && i < v.nx - 1 && j < v.ny - 1;
+      if (q < nl - 1 && interior && !v.dir[c]) {
+#pragma unroll
+        for (int z = 0; z < 9; ++z) o.a[z] = v.st[(size_t)z * n + c];
+        o.ik = T(1) / o.a[4];
+      }
+      if (q == 0) o.b = v.b[c];
+      X[v.off + c] = T(0);
+    }
+  __syncthreads();
+
+  // A x at an owned node of level q (reads X)
+  auto offc = [&](const TailLevel<T> &v, const Own<T> &o) -> T {
+    const T *x = X + v.off;
+    const int c = o.c, s = v.nx;
+    return o.a[0] * x[c - s - 1] + o.a[1] * x[c - s] + o.a[2] * x[c - s + 1] + o.a[3] * x[c - 1] +
+           o.a[5] * x[c + 1] + o.a[6] * x[c + s - 1] + o.a[7] * x[c + s] + o.a[8] * x[c + s + 1];
+  };
+  auto smooth = [&](int q, int sweeps) {
+    const TailLevel<T> &v = a.lv[q];
+    for (int s = 0; s < sweeps; ++s)
+      for (int col = 0; col < 4; ++col) {
+#pragma unroll
+        for (int m = 0; m < kOwn; ++m) {
+          const Own<T> &o = own[q][m];
+          if (o.c >= 0 && o.col == col && o.ik != T(0))
+            X[v.off + o.c] = (o.b - offc(v, o)) * o.ik;
+        }
+        __syncthreads();
+      }
+  };
+
+#pragma unroll
+  for (int q = 0; q < kTailLevels - 1; ++q) {
+    if (q >= nl - 1) break;
+    const TailLevel<T> &v = a.lv[q], &cv = a.lv[q + 1];
+    smooth(q, a.nu1);
+    // residual into Rb, then full weighting into the coarse owners' rhs
+#pragma unroll
+    for (int m = 0; m < kOwn; ++m) {
+      const Own<T> &o = own[q][m];
+      if (o.c >= 0) Rb[o.c] = o.ik != T(0) ? o.b - offc(v, o) - o.a[4] * X[v.off + o.c] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kOwn; ++m) {
+      Own<T> &o = own[q + 1][m];
+      if (o.c < 0) continue;
+      const int I = o.c % cv.nx, J = o.c / cv.nx;
+      T s = T(0);
+      if (I > 0 && J > 0 && I < cv.nx - 1 && J < cv.ny - 1) {
+        const int f = (2 * J) * v.nx + 2 * I, w = v.nx;
+        const T e = Rb[f - w] + T(2) * Rb[f] + Rb[f + w];
+        const T ww = Rb[f - w - 1] + T(2) * Rb[f - 1] + Rb[f + w - 1];
+        const T ee = Rb[f - w + 1] + T(2) * Rb[f + 1] + Rb[f + w + 1];
+        s = (ww + T(2) * e + ee) * T(0.0625);
+      }
+      o.b = s;
+    }
+    __syncthreads();
+  }
+  {  // coarsest level: x = A^-1 b
+    const int q = nl - 1;
+    const TailLevel<T> &v = a.lv[q];
+    const int n = v.nx * v.ny, m = a.cidx[n];
+    // owners of the coarsest level hold their rhs in own[q]
+#pragma unroll
+    for (int qq = 0; qq < kTailLevels; ++qq)
+      if (qq == q && t < n) {
+        const int k = a.cidx[t];
+        if (k >= 0) bb[k] = (double)own[qq][0].b;
+      }
+    __syncthreads();
+    if (t < n) {
+      const int k = a.cidx[t];
+      double s = 0.0;
+      if (k >= 0)
+        for (int r = 0; r < m; ++r) s += a.cinv[k * m + r] * bb[r];
+      X[v.off + t] = (T)s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = kTailLevels - 2; q >= 0; --q) {
+    if (q > nl - 2) continue;
+    const TailLevel<T> &v = a.lv[q], &cv = a.lv[q + 1];
+    const T *xc = X + cv.off;
+#pragma unroll
+    for (int m = 0; m < kOwn; ++m) {
+      const Own<T> &o = own[q][m];
+      if (o.c < 0) continue;
+      const int i = o.c % v.nx, j = o.c / v.nx;
+      if (i == 0 || j == 0 || i == v.nx - 1 || j == v.ny - 1 || v.dir[o.c]) continue;
+      const int I = i >> 1, J = j >> 1;
+      const T *r0 = xc + J * cv.nx;
+      T e0 = (i & 1) ? T(0.5) * (r0[I] + r0[I + 1]) : r0[I];
+      if (j & 1) {
+        const T *r1 = r0 + cv.nx;
+        const T e1 = (i & 1) ? T(0.5) * (r1[I] + r1[I + 1]) : r1[I];
+        e0 = T(0.5) * (e0 + e1);
+      }
+      X[v.off + o.c] += e0;
+    }
+    __syncthreads();
+    smooth(q, a.nu2);
+  }
+  // iterates of every tail level back to global memory
+  for (int q = 0; q < nl; ++q) {
+    const TailLevel<T> &v = a.lv[q];
+    for (int c = t; c < v.nx * v.ny; c += kTailThreads) v.x[c] = X[v.off + c];
+  }
+}
+
+}  // namespace
+
+// Number of nodes a level may have to be handled by the tail.
+int tail_max_nodes() { return kTailThreads * kOwn; }
+
+// Levels lc..L-1 in one workgroup; xs/bs/sts give the per-level correction,
+// right-hand side and stencil arrays of precision T (indexed by level).
+template <typename T>
+void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *const *sts) {
+  TailArgs<T> a{};
+  a.lc = lc;
+  a.nl = p->L - lc;
+  a.nu1 = p->cfg.nu1;
+  a.nu2 = p->cfg.nu2;
+  a.cinv = p->cinv;
+  a.cidx = p->cidx;
+  int off = 0, rmax = 0;
+  for (int q = 0; q < a.nl; ++q) {
+    const int l = lc + q;
+    a.lv[q].nx = p->lv[l].nx;
+    a.lv[q].ny = p->lv[l].ny;
+    a.lv[q].st = sts[l];
+    a.lv[q].x = xs[l];
+    a.lv[q].b = bs[l];
+    a.lv[q].dir = p->lv[l].dir;
+    a.lv[q].off = off;
+    const int n = p->lv[l].nx * p->lv[l].ny;
+    off += n;
+    rmax = rmax > n ? rmax : n;
+  }
+  const size_t shmem = (size_t)(off + rmax) * sizeof(T);
+  hipLaunchKernelGGL((k_tail<T>), 1, kTailThreads, shmem, p->stream, a);
+}
+
+template void tail_cycle<double>(tomg_problem *, int, double *const *, double *const *,
+                                 const double *const *);
+template void tail_cycle<float>(tomg_problem *, int, float *const *, float *const *,
+                                const float *const *);
+
+}  // namespace tomg

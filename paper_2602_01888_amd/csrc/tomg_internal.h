@@ -70,6 +70,14 @@ struct tomg_problem {
   float *e32b = nullptr;
   int m_coarse = 0;
   bool ready = false;
+  // level-0 pass timing (tomg_profile): event pairs recorded since the last
+  // harvest, per kind (0 down, 1 up)
+  static constexpr int kMaxEv = 64;
+  bool prof = false;
+  hipEvent_t ev[2][kMaxEv][2] = {};
+  int nev[2] = {0, 0};
+  double prof_ms[2] = {0, 0};
+  double prof_cnt[2] = {0, 0};
   char err[512];
 };
 
@@ -90,10 +98,21 @@ template <typename T>
 int fused_up(tomg_problem *p, int l, const T *pong, T *x, const T *b, const T *exx,
              const T *exy, const T *eyy, const T *st, const T *xc, double *partials);
 size_t fused_max_blocks(int nx, int ny);
+
+// levels lc..L-1 of the cycle in one workgroup (tail.hip)
+template <typename T>
+void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *const *sts);
+int tail_max_nodes();
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi);
 hipError_t launch_ir_correct(tomg_problem *p, double *phi);
 hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free);
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps);
 hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r);
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// Pass timing around level-0 passes (no-ops unless p->prof).
+void prof_begin(tomg_problem *p, int kind);
+void prof_end(tomg_problem *p, int kind);
+void prof_harvest(tomg_problem *p);
 
 }  // namespace tomg
