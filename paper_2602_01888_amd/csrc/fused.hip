@@ -127,17 +127,25 @@ __device__ __forceinline__ T block_sum(T v, T *red) {
   return v;
 }
 
-// Level 0 (EPS) prefetches the next row pair while it works on the current
-// one; the stored-stencil levels load the current pair at the start of the
-// step (their nine coefficient planes leave no registers for a second pair).
-template <typename T, bool EPS, int NU, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
+// One level pass.  A step takes P new row pairs: sweep s relaxes the even
+// rows of the P pairs m-s, ..., m-s-P+1 (colours 0 then 1; even rows only
+// read odd rows, so the P rows of a phase are independent) and then their
+// odd rows (colours 2 then 3).  Four barriers per sweep and step, whatever
+// P.  With P = 1 the level-0 pass prefetches the next pair while it works on
+// the current one; otherwise a step's loads are issued together at its start.
+template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
 __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
+  constexpr bool PF = EPS && P == 1;
   constexpr int H = 4 * NU + 2;
   constexpr int HV = 2 * NU + 3;
-  constexpr int NS = 2 * NU + 2;  // coefficient rows in flight: 2k-2NU .. 2k+1
-  constexpr int NR = 2 * NU + 4;  // value rows in LDS:          2k-2NU-2 .. 2k+1
+  constexpr int NS = 2 * NU + 2 * P;               // coefficient rows: R0 .. 2m+1
+  constexpr int NR = NS + 2;                       // value rows in LDS
+  constexpr int PER = NS / cgcd(2 * P, NS);        // steps until the slot ring repeats
+  constexpr int NX = (4 * P > P + 1) ? 4 * P : P + 1;
   __shared__ T L[NR][kBW + 2];
-  __shared__ T xch[4][kBW + 2];
+  __shared__ T xch[NX][kBW + 2];
   __shared__ double red[kBW / 64];
 
   const int nx = a.nx, ny = a.ny;
@@ -153,8 +161,7 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
   const int y1 = min(ny, y0 + a.CH);
   const int ys = max(0, y0 - HV) & ~1;
   const int ye = min(ny - 1, y1 - 1 + HV);
-  const int k0 = ys >> 1;
-  const int k1 = (y1 - 1 + 2 * NU) >> 1;
+  const int m0 = (ys >> 1) + P - 1;  // newest pair of the first step
   const size_t n = (size_t)nx * ny;
   const int Ic = gc >> 1;
   const int Ic1 = PROLONG ? min(Ic + 1, a.nxc - 1) : 0;
@@ -164,7 +171,10 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
     if (t < 2) L[r][t * (kBW + 1)] = T(0);
   }
   if (t < 2)
-    for (int r = 0; r < 4; ++r) xch[r][t * (kBW + 1)] = T(0);
+    for (int r = 0; r < NX; ++r) xch[r][t * (kBW + 1)] = T(0);
+
+  auto slot = [&](int rel) { return ((rel % NS) + NS) % NS; };
+  auto lrow = [&](int r) -> T * { return L[((r % NR) + NR) % NR]; };
 
   // all loads of a row are issued unconditionally from clamped addresses
   auto load_row = [&](int r, Raw<T, EPS> &w) {
@@ -205,7 +215,7 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
         v += e;
       }
     }
-    L[ring_slot(r, NR)][t + 1] = v;
+    lrow(r)[t + 1] = v;
   };
 
   Rec<T, EPS> rec[NS];
@@ -220,69 +230,92 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
     }
     rec[s].ik = T(0);
   }
-  Raw<T, EPS> cur[2], nxt[2];
-  // level 0: tensor values carried from earlier rows: row 2k-2 (eyy, exy)
-  // and row 2k-1 (exx, exy, eyy, f, dir)
+  Raw<T, EPS> cur[2 * P];
+  Raw<T, EPS> nxt[PF ? 2 : 1];
+  // level 0: tensor values carried from the two rows below the step's first
+  // new row: row base-2 (eyy, exy) and row base-1 (exx, exy, eyy, f, dir)
   T c_yy2 = T(0), c_xy2 = T(0), c_xx1 = T(0), c_xy1 = T(0), c_yy1 = T(0), c_f1 = T(0);
   int c_d1 = 1;
   (void)c_yy2; (void)c_xy2; (void)c_xx1; (void)c_xy1; (void)c_yy1; (void)c_f1; (void)c_d1;
+  (void)nxt;
   T rprev = T(0), acc = T(0);
 
-  if constexpr (EPS) {  // prologue: the first row pair
-    load_row(2 * k0, cur[0]);
-    load_row(2 * k0 + 1, cur[1]);
-    commit_row(2 * k0, cur[0]);
-    commit_row(2 * k0 + 1, cur[1]);
+  if constexpr (PF) {  // prologue: the first row pair
+    load_row(2 * m0, cur[0]);
+    load_row(2 * m0 + 1, cur[1]);
+    commit_row(2 * m0, cur[0]);
+    commit_row(2 * m0 + 1, cur[1]);
   }
   __syncthreads();
 
-  for (int kb = k0; kb <= k1; kb += NU + 1) {
+  for (int sb = 0;; sb += PER) {
+    bool more = true;
 #pragma unroll
-    for (int ph = 0; ph <= NU; ++ph) {
-      const int k = kb + ph;
-      if (k <= k1) {
-        const int ra = 2 * k;  // rows ra, ra+1 are the newest in the window
+    for (int ph = 0; ph < PER; ++ph) {
+      const int m = m0 + P * (sb + ph);
+      const int R0 = 2 * (m - NU + 1 - P);  // first row of the residual batch
+      if (more && R0 <= y1 - 1) {
+        const int base = 2 * (m - P + 1);   // first new row of the step
+        // relative row index of row 2m + o is rel0 + o
+        const int rel0 = 2 * P * ph + 2 * P - 2;
+        if constexpr (PF) {
+          load_row(2 * m + 2, nxt[0]);
+          load_row(2 * m + 3, nxt[1]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) load_row(base + q, cur[q]);
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) commit_row(base + q, cur[q]);
+        }
         if constexpr (EPS) {
-          // prefetch the next pair; committed at the end of this step
-          load_row(ra + 2, nxt[0]);
-          load_row(ra + 3, nxt[1]);
-          // coefficients of rows ra-1 and ra
-          xch[0][t + 1] = c_xx1;
-          xch[1][t + 1] = c_xy1;
-          xch[2][t + 1] = cur[0].xx;
-          xch[3][t + 1] = cur[0].xy;
-          __syncthreads();
-          {
-            Rec<T, true> &R = rec[ring_slot(2 * ph - 1, NS)];
-            R.ax = c_xx1 * a.cx;
-            R.ay = c_yy1 * a.cy;
-            R.gx = (xch[0][t + 2] - xch[0][t]) * a.qx + (cur[0].xy - c_xy2) * a.qxy;
-            R.gy = (cur[0].yy - c_yy2) * a.qy + (xch[1][t + 2] - xch[1][t]) * a.qxy;
-            R.k6 = c_xy1 * a.hxy;
-            R.f = c_f1;
-            R.ik = c_d1 ? T(0) : T(-1) / (T(2) * (R.ax + R.ay));
+          // coefficients of rows base-1 .. 2m (row 2m + 1 - 2P + v for v < 2P);
+          // raw row u = 0 .. 2P+1 is row base-2+u: u = 0, 1 carried, u >= 2
+          // loaded this step (cur[u-2])
+          T ryy[2 * P + 2], rxy[2 * P + 2], rxx[2 * P + 2], rff[2 * P + 2];
+          int rdd[2 * P + 2];
+          ryy[0] = c_yy2;
+          rxy[0] = c_xy2;
+          rxx[0] = T(0);
+          rff[0] = T(0);
+          rdd[0] = 1;
+          ryy[1] = c_yy1;
+          rxy[1] = c_xy1;
+          rxx[1] = c_xx1;
+          rff[1] = c_f1;
+          rdd[1] = c_d1;
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) {
+            ryy[q + 2] = cur[q].yy;
+            rxy[q + 2] = cur[q].xy;
+            rxx[q + 2] = cur[q].xx;
+            rff[q + 2] = cur[q].f;
+            rdd[q + 2] = cur[q].d;
           }
-          {
-            Rec<T, true> &R = rec[ring_slot(2 * ph, NS)];
-            R.ax = cur[0].xx * a.cx;
-            R.ay = cur[0].yy * a.cy;
-            R.gx = (xch[2][t + 2] - xch[2][t]) * a.qx + (cur[1].xy - c_xy1) * a.qxy;
-            R.gy = (cur[1].yy - c_yy1) * a.qy + (xch[3][t + 2] - xch[3][t]) * a.qxy;
-            R.k6 = cur[0].xy * a.hxy;
-            R.f = cur[0].f;
-            R.ik = cur[0].d ? T(0) : T(-1) / (T(2) * (R.ax + R.ay));
+#pragma unroll
+          for (int v = 0; v < 2 * P; ++v) {
+            xch[2 * v][t + 1] = rxx[v + 1];
+            xch[2 * v + 1][t + 1] = rxy[v + 1];
+          }
+          __syncthreads();
+#pragma unroll
+          for (int v = 0; v < 2 * P; ++v) {
+            Rec<T, true> &R = rec[slot(rel0 + 1 - 2 * P + v)];
+            R.ax = rxx[v + 1] * a.cx;
+            R.ay = ryy[v + 1] * a.cy;
+            R.gx = (xch[2 * v][t + 2] - xch[2 * v][t]) * a.qx + (rxy[v + 2] - rxy[v]) * a.qxy;
+            R.gy = (ryy[v + 2] - ryy[v]) * a.qy + (xch[2 * v + 1][t + 2] - xch[2 * v + 1][t]) * a.qxy;
+            R.k6 = rxy[v + 1] * a.hxy;
+            R.f = rff[v + 1];
+            R.ik = rdd[v + 1] ? T(0) : T(-1) / (T(2) * (R.ax + R.ay));
           }
         } else {
-          load_row(ra, cur[0]);
-          load_row(ra + 1, cur[1]);
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            Rec<T, false> &R = rec[ring_slot(2 * ph + q, NS)];
+          for (int q = 0; q < 2 * P; ++q) {
+            Rec<T, false> &R = rec[slot(rel0 + 2 - 2 * P + q)];
 #pragma unroll
             for (int z = 0; z < 9; ++z) R.a[z] = cur[q].a[z];
             R.f = cur[q].f;
             R.ik = cur[q].d ? T(0) : T(1) / cur[q].a[4];
-            commit_row(ra + q, cur[q]);
           }
           __syncthreads();
         }
@@ -291,38 +324,38 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
         for (int s = 0; s < NU; ++s) {
 #pragma unroll
           for (int half = 0; half < 2; ++half) {
-            const int r = ra - 2 * s - half;  // even row first, then the odd row below
-            const bool rowok = r >= 1 && r <= ny - 2 && r > ys && r < ye;
-            const Rec<T, EPS> &R = rec[ring_slot(2 * ph - 2 * s - half, NS)];
-            T *mid = L[ring_slot(r, NR)];
-            const T *lo = L[ring_slot(r - 1, NR)];
-            const T *hi = L[ring_slot(r + 1, NR)];
 #pragma unroll
             for (int cp = 0; cp < 2; ++cp) {
-              if (rowok && updc && odd == cp && R.ik != T(0)) {
-                T off, dg;
-                apply<T, EPS>(R, lo, mid, hi, t, off, dg);
-                mid[t + 1] = (R.f - off) * R.ik;
+#pragma unroll
+              for (int p = 0; p < P; ++p) {
+                const int o = -2 * s - 2 * p - half;  // row 2m + o
+                const int r = 2 * m + o;
+                const bool rowok = r >= 1 && r <= ny - 2 && r > ys && r < ye;
+                const Rec<T, EPS> &R = rec[slot(rel0 + o)];
+                if (rowok && updc && odd == cp && R.ik != T(0)) {
+                  T *mid = lrow(r);
+                  T off, dg;
+                  apply<T, EPS>(R, lrow(r - 1), mid, lrow(r + 1), t, off, dg);
+                  mid[t + 1] = (R.f - off) * R.ik;
+                }
               }
               __syncthreads();
             }
           }
         }
         // ------------- residual, output, restriction, norm -------------
-        const int R0 = ra - 2 * NU;
-        T res[2];
+        T res[2 * P];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < 2 * P; ++q) {
           const int r = R0 + q;
-          const Rec<T, EPS> &R = rec[ring_slot(2 * ph - 2 * NU + q, NS)];
-          const T *mid = L[ring_slot(r, NR)];
+          const Rec<T, EPS> &R = rec[slot(rel0 + 2 - 2 * NU - 2 * P + q)];
+          const T *mid = lrow(r);
           res[q] = T(0);
           if (RESTRICT || NORM) {
             const bool rowok = r >= 1 && r <= ny - 2 && r > ys && r < ye;
             if (rowok && updc && R.ik != T(0)) {
               T off, dg;
-              apply<T, EPS>(R, L[ring_slot(r - 1, NR)], mid, L[ring_slot(r + 1, NR)], t, off,
-                            dg);
+              apply<T, EPS>(R, lrow(r - 1), mid, lrow(r + 1), t, off, dg);
               res[q] = R.f - off - dg * mid[t + 1];
             }
           }
@@ -332,36 +365,49 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
           }
         }
         if constexpr (RESTRICT) {
-          const T rv = rprev + T(2) * res[0] + res[1];
-          rprev = res[1];
-          xch[0][t + 1] = rv;
+          T below[2 * P + 1];
+          below[0] = rprev;
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) below[q + 1] = res[q];
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            xch[p][t + 1] = below[2 * p] + T(2) * res[2 * p] + res[2 * p + 1];
+          rprev = res[2 * P - 1];
           __syncthreads();
-          const int J = k - NU;
-          if (2 * J >= y0 && 2 * J < y1 && J < a.nyc && outc && !odd) {
-            const int I = gi >> 1;
-            const bool ring = I == 0 || J == 0 || I == a.nxc - 1 || J == a.nyc - 1;
-            const T v = ring ? T(0)
-                             : (xch[0][t] + T(2) * xch[0][t + 1] + xch[0][t + 2]) * T(0.0625);
-            a.bc[(size_t)J * a.nxc + I] = v;
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const int J = (R0 >> 1) + p;
+            if (2 * J >= y0 && 2 * J < y1 && J < a.nyc && outc && !odd) {
+              const int I = gi >> 1;
+              const bool ring = I == 0 || J == 0 || I == a.nxc - 1 || J == a.nyc - 1;
+              const T v = ring ? T(0)
+                               : (xch[p][t] + T(2) * xch[p][t + 1] + xch[p][t + 2]) * T(0.0625);
+              a.bc[(size_t)J * a.nxc + I] = v;
+            }
           }
         }
         __syncthreads();
         if constexpr (EPS) {
-          // the prefetched pair enters the window; shift the carried rows
-          commit_row(ra + 2, nxt[0]);
-          commit_row(ra + 3, nxt[1]);
-          c_yy2 = cur[0].yy;
-          c_xy2 = cur[0].xy;
-          c_xx1 = cur[1].xx;
-          c_xy1 = cur[1].xy;
-          c_yy1 = cur[1].yy;
-          c_f1 = cur[1].f;
-          c_d1 = cur[1].d;
+          // rows 2m and 2m+1 become the carried rows of the next step
+          c_yy2 = cur[2 * P - 2].yy;
+          c_xy2 = cur[2 * P - 2].xy;
+          c_xx1 = cur[2 * P - 1].xx;
+          c_xy1 = cur[2 * P - 1].xy;
+          c_yy1 = cur[2 * P - 1].yy;
+          c_f1 = cur[2 * P - 1].f;
+          c_d1 = cur[2 * P - 1].d;
+        }
+        if constexpr (PF) {
+          commit_row(2 * m + 2, nxt[0]);
+          commit_row(2 * m + 3, nxt[1]);
           cur[0] = nxt[0];
           cur[1] = nxt[1];
         }
+      } else {
+        more = false;
       }
     }
+    if (!more) break;
   }
   if constexpr (NORM) {
     const double s = block_sum<double>((double)acc, red);
@@ -400,15 +446,23 @@ size_t fused_max_blocks(int nx, int ny) {
   return (size_t)((nx + Wmin - 1) / Wmin) * (size_t)((ny + 7) / 8);
 }
 
+#ifndef TOMG_PAIRS_EPS
+#define TOMG_PAIRS_EPS 1
+#endif
+#ifndef TOMG_PAIRS_ST
+#define TOMG_PAIRS_ST 1
+#endif
+
 template <typename T, bool EPS, int NU, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
 static void launch_pass_t(PassArgs<T> a, hipStream_t s, int *nblocks) {
   constexpr int H = 4 * NU + 2;
+  constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
   a.W = kBW - 2 * H;
   a.CH = pick_band(a.nx, a.ny, a.W);
   dim3 grid((a.nx + a.W - 1) / a.W, (a.ny + a.CH - 1) / a.CH);
   if (nblocks) *nblocks = grid.x * grid.y;
-  hipLaunchKernelGGL((k_pass<T, EPS, NU, ZERO, PROLONG, RESTRICT, NORM>), grid, dim3(kBW), 0, s,
-                     a);
+  hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>), grid, dim3(kBW), 0,
+                     s, a);
 }
 
 // Dispatch on the runtime sweep count (1..4).
