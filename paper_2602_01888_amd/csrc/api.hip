@@ -6,6 +6,7 @@
 #include <cstring>
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "tomg_internal.h"
 
@@ -60,6 +61,8 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
   o.partials = take(nparts * sizeof(double));
   o.cinv = take(kMaxCoarseUnknowns * kMaxCoarseUnknowns * sizeof(double));
   o.cidx = take(82 * sizeof(int));
+  o.args = take(sizeof(ArgsBlob));
+  o.bout = take(kMaxBatch * sizeof(double));
   o.exx = take(n0 * 8);
   o.exy = take(n0 * 8);
   o.eyy = take(n0 * 8);
@@ -221,7 +224,16 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
       p->lv[l].b32 = F(lay.b32[l]);
     }
   }
+  p->dargs = (ArgsBlob *)(w + lay.args);
+  p->bout = D(lay.bout);
+  p->lc = tail_level(p);
+  build_pass_args(p);
+  build_tail_args(p);
+  build_red_args(p);
   hipError_t e = hipMemsetAsync(p->scal, 0, kNumSlots * sizeof(double), p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->dargs, &p->hargs, sizeof(ArgsBlob), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) {
     delete p;
     return TOMG_EDEVICE;
@@ -351,20 +363,122 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
   return st;
 }
 
+// Batched solve.  Every stage of a cycle is one launch (per kBatchMax
+// problems) across the problems still iterating; stages are aligned from
+// the finest level, each problem taking part in the levels it has.  Each
+// problem runs exactly the blocks and reductions it runs alone, so its
+// result is bitwise that of solve().
 tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, int32_t n,
                              double rel_tol, int32_t max_cycles, int32_t *cycles_out,
                              double *rel_out, tomg_status *status_out) {
-  if (!probs || !d_phis || n < 0) return TOMG_EINVAL;
+  if (!probs || !d_phis || n < 0 || n > kMaxBatch) return TOMG_EINVAL;
+  if (n == 0) return TOMG_OK;
+  if (!(rel_tol > 0.0) || max_cycles < 0) return TOMG_EINVAL;
+  std::vector<tomg_status> st(n, TOMG_OK);
+  std::vector<int> cyc(n, 0);
+  std::vector<double> rel(n, 0.0);
+  tomg_problem *lead = probs[0];
+  bool uniform = lead != nullptr;
+  for (int k = 0; k < n && uniform; ++k) {
+    tomg_problem *p = probs[k];
+    if (!p || !d_phis[k] || !p->ready) { uniform = false; break; }
+    uniform = p->cfg.precision == lead->cfg.precision && p->cfg.nu1 == lead->cfg.nu1 &&
+              p->cfg.nu2 == lead->cfg.nu2 && p->cfg.smoother == TOMG_GS4 &&
+              p->cfg.ir_inner_cycles == lead->cfg.ir_inner_cycles;
+  }
+  if (!uniform) {
+    // mixed configurations: solve one after another
+    tomg_status first = TOMG_OK;
+    for (int k = 0; k < n; ++k) {
+      int32_t c = 0;
+      double r = 0.0;
+      tomg_status s = probs[k] ? solve(probs[k], d_phis[k], rel_tol, max_cycles, &c, &r)
+                               : TOMG_EINVAL;
+      if (cycles_out) cycles_out[k] = c;
+      if (rel_out) rel_out[k] = r;
+      if (status_out) status_out[k] = s;
+      if (s != TOMG_OK && first == TOMG_OK) first = s;
+    }
+    return first;
+  }
+  hipStream_t s = lead->stream;
+  const bool ir = lead->cfg.precision == TOMG_FP32_IR;
+  std::vector<int> act(n);
+  for (int k = 0; k < n; ++k) act[k] = k;
+  std::vector<double> hrel(n);
+  auto read_rel = [&](int cnt) -> bool {
+    if (hipMemcpyAsync(hrel.data(), lead->bout, cnt * sizeof(double), hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+      return false;
+    return hipStreamSynchronize(s) == hipSuccess;
+  };
+  const int *A = act.data();
+  int na = n;
+  batch_resnorm(probs, A, na, true, d_phis, s);
+  batch_finalize(probs, A, na, 0, kSlotB0, false, lead->bout, s);
+  if (ir) {
+    batch_ir_residual(probs, A, na, d_phis, s);
+  } else {
+    batch_resnorm(probs, A, na, false, d_phis, s);
+  }
+  batch_finalize(probs, A, na, 0, kSlotRes, true, lead->bout, s);
+  if (hipGetLastError() != hipSuccess || !read_rel(na)) return TOMG_EDEVICE;
+  int maxlc = 0;
+  for (int k = 0; k < n; ++k) maxlc = std::max(maxlc, probs[k]->lc);
+  std::vector<int> lvl;
+  while (true) {
+    // retire finished problems
+    int w = 0;
+    for (int q = 0; q < na; ++q) {
+      const int k = act[q];
+      const double r = hrel[q];
+      rel[k] = r;
+      if (!std::isfinite(r)) {
+        st[k] = TOMG_ENONFINITE;
+      } else if (r <= rel_tol) {
+        st[k] = TOMG_OK;
+      } else if (cyc[k] >= max_cycles) {
+        st[k] = TOMG_ENOCONV;
+      } else {
+        act[w++] = k;
+      }
+    }
+    na = w;
+    if (na == 0) break;
+    A = act.data();
+    auto participants = [&](int l) {  // active problems with level l above their tail
+      lvl.clear();
+      for (int q = 0; q < na; ++q)
+        if (l < probs[act[q]]->lc) lvl.push_back(act[q]);
+      return (int)lvl.size();
+    };
+    const int inner = ir ? lead->cfg.ir_inner_cycles : 1;
+    for (int it = 0; it < inner; ++it) {
+      for (int l = 0; l < maxlc; ++l)
+        if (participants(l)) batch_down(probs, lvl.data(), (int)lvl.size(), l, ir, ir && it == 0,
+                                        d_phis, s);
+      batch_tail(probs, A, na, ir, s);
+      for (int l = maxlc - 1; l >= 0; --l)
+        if (participants(l)) batch_up(probs, lvl.data(), (int)lvl.size(), l, ir, !ir, d_phis, s);
+    }
+    if (ir) {
+      batch_ir_update(probs, A, na, d_phis, s);
+      batch_ir_residual(probs, A, na, d_phis, s);
+      batch_finalize(probs, A, na, 0, kSlotRes, true, lead->bout, s);
+    } else {
+      batch_finalize(probs, A, na, 1, kSlotRes, true, lead->bout, s);
+    }
+    for (int q = 0; q < na; ++q) ++cyc[act[q]];
+    if (hipGetLastError() != hipSuccess || !read_rel(na)) return TOMG_EDEVICE;
+  }
   tomg_status first = TOMG_OK;
   for (int k = 0; k < n; ++k) {
-    int32_t c = 0;
-    double r = 0.0;
-    tomg_status s = probs[k] ? solve(probs[k], d_phis[k], rel_tol, max_cycles, &c, &r)
-                             : TOMG_EINVAL;
-    if (cycles_out) cycles_out[k] = c;
-    if (rel_out) rel_out[k] = r;
-    if (status_out) status_out[k] = s;
-    if (s != TOMG_OK && first == TOMG_OK) first = s;
+    if (cycles_out) cycles_out[k] = cyc[k];
+    if (rel_out) rel_out[k] = rel[k];
+    if (status_out) status_out[k] = st[k];
+    if (st[k] == TOMG_ENOCONV)
+      fail(probs[k], TOMG_ENOCONV, "solve_batch: rel. residual %.3e after %d cycles", rel[k], cyc[k]);
+    if (st[k] != TOMG_OK && first == TOMG_OK) first = st[k];
   }
   return first;
 }

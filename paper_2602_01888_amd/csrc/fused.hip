@@ -26,6 +26,7 @@
 // halo rows at the edges of the block, which is what H and HV cover.
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "tomg_internal.h"
 
@@ -39,24 +40,6 @@ namespace {
 #define TOMG_MIN_WAVES 1
 #endif
 constexpr int kBW = TOMG_BW;
-
-template <typename T>
-struct PassArgs {
-  int nx, ny;
-  const T *xin;             // level iterate read (unless ZERO)
-  T *xout;                  // level iterate written (never the array read:
-                            // neighbouring blocks read their halo from xin)
-  const T *b;               // level right-hand side
-  const uint8_t *dir;       // Dirichlet flags of the level
-  const T *exx, *exy, *eyy; // level 0: permittivity tensor
-  const T *st;              // coarse levels: 9-point stencil planes
-  T cx, cy, qx, qy, qxy, hxy;
-  const T *xc;              // up pass: coarse correction
-  T *bc;                    // down pass: coarse right-hand side
-  int nxc, nyc;
-  double *partials;         // up pass with norm: one double per block
-  int CH, W;
-};
 
 // Per-thread values of one row as loaded from global memory.
 template <typename T, bool EPS>
@@ -136,7 +119,7 @@ constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 // P.  With P = 1 the level-0 pass prefetches the next pair while it works on
 // the current one; otherwise a step's loads are issued together at its start.
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
-__global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
+__device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, const int by) {
   constexpr bool PF = EPS && P == 1;
   constexpr int H = 4 * NU + 2;
   constexpr int HV = 2 * NU + 3;
@@ -150,14 +133,14 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
 
   const int nx = a.nx, ny = a.ny;
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * a.W;
+  const int x0 = bx * a.W;
   const int gi = x0 - H + t;
   const int gc = min(max(gi, 0), nx - 1);  // clamped column: loads never leave the array
   const bool inr = gi >= 0 && gi < nx;
   const bool updc = gi >= 1 && gi <= nx - 2;
   const bool outc = t >= H && t < H + a.W && gi < nx;
   const int odd = gi & 1;
-  const int y0 = blockIdx.y * a.CH;
+  const int y0 = by * a.CH;
   const int y1 = min(ny, y0 + a.CH);
   const int ys = max(0, y0 - HV) & ~1;
   const int ye = min(ny - 1, y1 - 1 + HV);
@@ -411,8 +394,34 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
   }
   if constexpr (NORM) {
     const double s = block_sum<double>((double)acc, red);
-    if (t == 0) a.partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    if (t == 0) a.partials[(size_t)by * a.nbx + bx] = s;
   }
+}
+
+template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+__global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
+  pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, blockIdx.x, blockIdx.y);
+}
+
+// Entry of a batched launch holding block b (entries sorted by start).
+__device__ __forceinline__ const BatchEntry &batch_locate(const BatchTab &tab, int b) {
+  int lo = 0, hi = tab.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab.e[mid].start <= b) lo = mid; else hi = mid - 1;
+  }
+  return tab.e[lo];
+}
+
+// Batched form: each problem runs exactly the blocks it would run alone.
+template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+__global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
+  const BatchEntry &e = batch_locate(tab, blockIdx.x);
+  PassArgs<T> a = *static_cast<const PassArgs<T> *>(e.args);
+  if (e.role == 1) a.xin = static_cast<const T *>(e.phi);
+  if (e.role == 2) a.xout = static_cast<T *>(e.phi);
+  const int local = blockIdx.x - e.start;
+  pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, local % e.nbx, local / e.nbx);
 }
 
 }  // namespace
@@ -453,43 +462,49 @@ size_t fused_max_blocks(int nx, int ny) {
 #define TOMG_PAIRS_ST 1
 #endif
 
-template <typename T, bool EPS, int NU, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
-static void launch_pass_t(PassArgs<T> a, hipStream_t s, int *nblocks) {
-  constexpr int H = 4 * NU + 2;
-  constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
-  a.W = kBW - 2 * H;
-  a.CH = pick_band(a.nx, a.ny, a.W);
-  dim3 grid((a.nx + a.W - 1) / a.W, (a.ny + a.CH - 1) / a.CH);
-  if (nblocks) *nblocks = grid.x * grid.y;
-  hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>), grid, dim3(kBW), 0,
-                     s, a);
-}
-
-// Dispatch on the runtime sweep count (1..4).
+// Sweep count and pair count are compile-time; dispatch on the runtime nu.
 template <typename T, bool EPS, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
-static void launch_pass_nu(int nu, const PassArgs<T> &a, hipStream_t s, int *nb) {
+static void launch_pass(int nu, const PassArgs<T> &a, hipStream_t s, const BatchTab *tab,
+                        int nblocks) {
+  constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
+#define TOMG_LAUNCH(NU)                                                                          \
+  do {                                                                                           \
+    if (tab)                                                                                     \
+      hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>),              \
+                         dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>),                \
+                         dim3(a.nbx, a.nby), dim3(kBW), 0, s, a);                                \
+  } while (0)
   switch (nu) {
-    case 1: launch_pass_t<T, EPS, 1, ZERO, PROLONG, RESTRICT, NORM>(a, s, nb); break;
-    case 2: launch_pass_t<T, EPS, 2, ZERO, PROLONG, RESTRICT, NORM>(a, s, nb); break;
-    case 3: launch_pass_t<T, EPS, 3, ZERO, PROLONG, RESTRICT, NORM>(a, s, nb); break;
-    default: launch_pass_t<T, EPS, 4, ZERO, PROLONG, RESTRICT, NORM>(a, s, nb); break;
+    case 1: TOMG_LAUNCH(1); break;
+    case 2: TOMG_LAUNCH(2); break;
+    case 3: TOMG_LAUNCH(3); break;
+    default: TOMG_LAUNCH(4); break;
   }
+#undef TOMG_LAUNCH
 }
 
+// Arguments of the down (up) pass of level l in precision T: the level
+// iterate x_l is read (written) and its second buffer written (read).
 template <typename T>
-static PassArgs<T> base_args(tomg_problem *p, int l, const T *xin, T *xout, const T *b,
-                             const T *exx, const T *exy, const T *eyy, const T *st) {
+static PassArgs<T> make_args(tomg_problem *p, int l, bool up, T *x0, T *pong0, const T *b0,
+                             const T *exx, const T *exy, const T *eyy) {
   PassArgs<T> a{};
-  a.nx = p->lv[l].nx;
-  a.ny = p->lv[l].ny;
-  a.xin = xin;
-  a.xout = xout;
-  a.b = b;
-  a.dir = p->lv[l].dir;
+  const Level &v = p->lv[l];
+  const bool f32 = std::is_same<T, float>::value;
+  a.nx = v.nx;
+  a.ny = v.ny;
+  T *x = l == 0 ? x0 : (T *)(f32 ? (void *)v.x32 : (void *)v.x);
+  T *pong = l == 0 ? pong0 : (T *)(f32 ? (void *)v.x2_32 : (void *)v.x2);
+  a.xin = up ? pong : x;
+  a.xout = up ? x : pong;
+  a.b = l == 0 ? b0 : (const T *)(f32 ? (void *)v.b32 : (void *)v.b);
+  a.dir = v.dir;
   a.exx = exx;
   a.exy = exy;
   a.eyy = eyy;
-  a.st = st;
+  a.st = l == 0 ? nullptr : (const T *)(f32 ? (void *)v.st32 : (void *)v.st);
   const double dx = p->cfg.dx, dy = p->cfg.dy;
   a.cx = T(1.0 / (dx * dx));
   a.cy = T(1.0 / (dy * dy));
@@ -497,30 +512,76 @@ static PassArgs<T> base_args(tomg_problem *p, int l, const T *xin, T *xout, cons
   a.qy = T(0.25 / (dy * dy));
   a.qxy = T(0.25 / (dx * dy));
   a.hxy = T(0.5 / (dx * dy));
+  const Level &c = p->lv[l + 1];
+  a.nxc = c.nx;
+  a.nyc = c.ny;
+  a.xc = up ? (const T *)(f32 ? (void *)c.x32 : (void *)c.x) : nullptr;
+  a.bc = up ? nullptr : (T *)(f32 ? (void *)c.b32 : (void *)c.b);
+  a.partials = (up && l == 0) ? p->partials : nullptr;
+  const int nu = up ? p->cfg.nu2 : p->cfg.nu1;
+  a.W = kBW - 2 * (4 * nu + 2);
+  a.CH = pick_band(a.nx, a.ny, a.W);
+  a.nbx = (a.nx + a.W - 1) / a.W;
+  a.nby = (a.ny + a.CH - 1) / a.CH;
   return a;
 }
 
+// Pass arguments of every level, both directions (and FP32 copies for
+// refinement problems).  The level-0 FP64 iterate is the caller's phi, set
+// per launch (nullptr here).
+void build_pass_args(tomg_problem *p) {
+  ArgsBlob &g = p->hargs;
+  for (int l = 0; l + 1 < p->L; ++l) {
+    g.down64[l] = make_args<double>(p, l, false, nullptr, p->tmp, p->f, p->exx, p->exy, p->eyy);
+    g.up64[l] = make_args<double>(p, l, true, nullptr, p->tmp, p->f, p->exx, p->exy, p->eyy);
+    if (p->cfg.precision == TOMG_FP32_IR) {
+      g.down32[l] = make_args<float>(p, l, false, p->e32, p->e32b, p->r32, p->exx32, p->exy32,
+                                     p->eyy32);
+      g.up32[l] = make_args<float>(p, l, true, p->e32, p->e32b, p->r32, p->exx32, p->exy32,
+                                   p->eyy32);
+    }
+  }
+}
+
+template <typename T>
+static void launch_down(int nu, bool eps, bool zero, const PassArgs<T> &a, hipStream_t s,
+                        const BatchTab *tab, int nb) {
+  if (eps) {
+    if (zero) launch_pass<T, true, true, false, true, false>(nu, a, s, tab, nb);
+    else launch_pass<T, true, false, false, true, false>(nu, a, s, tab, nb);
+  } else {
+    if (zero) launch_pass<T, false, true, false, true, false>(nu, a, s, tab, nb);
+    else launch_pass<T, false, false, false, true, false>(nu, a, s, tab, nb);
+  }
+}
+
+template <typename T>
+static void launch_up(int nu, bool eps, bool norm, const PassArgs<T> &a, hipStream_t s,
+                      const BatchTab *tab, int nb) {
+  if (eps) {
+    if (norm) launch_pass<T, true, false, true, false, true>(nu, a, s, tab, nb);
+    else launch_pass<T, true, false, true, false, false>(nu, a, s, tab, nb);
+  } else {
+    launch_pass<T, false, false, true, false, false>(nu, a, s, tab, nb);
+  }
+}
+
 // Down pass on level l: nu1 sweeps of x (from zero when zero_start) written
-// to pong, residual and restriction into bc (level l+1).
+// to pong, residual and restriction into the level l+1 right-hand side.
 template <typename T>
 void fused_down(tomg_problem *p, int l, const T *x, T *pong, const T *b, const T *exx,
                 const T *exy, const T *eyy, const T *st, T *bc, bool zero_start) {
-  PassArgs<T> a = base_args<T>(p, l, x, pong, b, exx, exy, eyy, st);
+  PassArgs<T> a = std::is_same<T, float>::value ? *(PassArgs<T> *)(void *)&p->hargs.down32[l]
+                                                : *(PassArgs<T> *)(void *)&p->hargs.down64[l];
+  a.xin = x;
+  a.xout = pong;
+  a.b = b;
+  a.exx = exx;
+  a.exy = exy;
+  a.eyy = eyy;
+  a.st = st;
   a.bc = bc;
-  a.nxc = p->lv[l + 1].nx;
-  a.nyc = p->lv[l + 1].ny;
-  const int nu = p->cfg.nu1;
-  if (l == 0) {
-    if (zero_start)
-      launch_pass_nu<T, true, true, false, true, false>(nu, a, p->stream, nullptr);
-    else
-      launch_pass_nu<T, true, false, false, true, false>(nu, a, p->stream, nullptr);
-  } else {
-    if (zero_start)
-      launch_pass_nu<T, false, true, false, true, false>(nu, a, p->stream, nullptr);
-    else
-      launch_pass_nu<T, false, false, false, true, false>(nu, a, p->stream, nullptr);
-  }
+  launch_down<T>(p->cfg.nu1, l == 0, zero_start, a, p->stream, nullptr, 0);
 }
 
 // Up pass on level l: pong plus the prolongation of xc (level l+1), nu2
@@ -529,22 +590,19 @@ void fused_down(tomg_problem *p, int l, const T *x, T *pong, const T *b, const T
 template <typename T>
 int fused_up(tomg_problem *p, int l, const T *pong, T *x, const T *b, const T *exx,
              const T *exy, const T *eyy, const T *st, const T *xc, double *partials) {
-  PassArgs<T> a = base_args<T>(p, l, pong, x, b, exx, exy, eyy, st);
+  PassArgs<T> a = std::is_same<T, float>::value ? *(PassArgs<T> *)(void *)&p->hargs.up32[l]
+                                                : *(PassArgs<T> *)(void *)&p->hargs.up64[l];
+  a.xin = pong;
+  a.xout = x;
+  a.b = b;
+  a.exx = exx;
+  a.exy = exy;
+  a.eyy = eyy;
+  a.st = st;
   a.xc = xc;
-  a.nxc = p->lv[l + 1].nx;
-  a.nyc = p->lv[l + 1].ny;
   a.partials = partials;
-  const int nu = p->cfg.nu2;
-  int nb = 0;
-  if (l == 0) {
-    if (partials)
-      launch_pass_nu<T, true, false, true, false, true>(nu, a, p->stream, &nb);
-    else
-      launch_pass_nu<T, true, false, true, false, false>(nu, a, p->stream, &nb);
-  } else {
-    launch_pass_nu<T, false, false, true, false, false>(nu, a, p->stream, &nb);
-  }
-  return nb;
+  launch_up<T>(p->cfg.nu2, l == 0, partials != nullptr, a, p->stream, nullptr, 0);
+  return a.nbx * a.nby;
 }
 
 template void fused_down<double>(tomg_problem *, int, const double *, double *, const double *,
@@ -559,5 +617,65 @@ template int fused_up<double>(tomg_problem *, int, const double *, double *, con
 template int fused_up<float>(tomg_problem *, int, const float *, float *, const float *,
                              const float *, const float *, const float *, const float *,
                              const float *, double *);
+
+// ---------------------------------------------------------------------------
+// Batched passes: one launch covers level l of up to kBatchMax problems.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static void batch_pass(tomg_problem *const *probs, const int *idx, int cnt, int l, bool up,
+                       bool flag, double *const *phis, hipStream_t s) {
+  const bool f32 = std::is_same<T, float>::value;
+  BatchTab tab;
+  for (int k0 = 0; k0 < cnt; k0 += kBatchMax) {
+    tab.count = 0;
+    int nb = 0;
+    const PassArgs<T> *first = nullptr;
+    for (int k = k0; k < cnt && k < k0 + kBatchMax; ++k) {
+      tomg_problem *p = probs[idx[k]];
+      const PassArgs<T> *h = f32 ? (const PassArgs<T> *)(void *)(up ? &p->hargs.up32[l]
+                                                                      : &p->hargs.down32[l])
+                                 : (const PassArgs<T> *)(void *)(up ? &p->hargs.up64[l]
+                                                                      : &p->hargs.down64[l]);
+      const PassArgs<T> *d = f32 ? (const PassArgs<T> *)(void *)(up ? &p->dargs->up32[l]
+                                                                      : &p->dargs->down32[l])
+                                 : (const PassArgs<T> *)(void *)(up ? &p->dargs->up64[l]
+                                                                      : &p->dargs->down64[l]);
+      if (!first) first = h;
+      BatchEntry &e = tab.e[tab.count++];
+      e.args = d;
+      e.phi = (!f32 && l == 0) ? (void *)phis[idx[k]] : nullptr;
+      e.role = (!f32 && l == 0) ? (up ? 2 : 1) : 0;
+      e.nbx = h->nbx;
+      e.nby = h->nby;
+      e.start = nb;
+      e.slot = e.out = 0;
+      nb += h->nbx * h->nby;
+    }
+    if (!tab.count) continue;
+    const int nu = up ? probs[idx[k0]]->cfg.nu2 : probs[idx[k0]]->cfg.nu1;
+    if (up)
+      launch_up<T>(nu, l == 0, flag, *first, s, &tab, nb);
+    else
+      launch_down<T>(nu, l == 0, flag, *first, s, &tab, nb);
+  }
+}
+
+void batch_down(tomg_problem *const *probs, const int *idx, int cnt, int l, bool fp32, bool zero0,
+                double *const *phis, hipStream_t s) {
+  const bool zero = l > 0 || zero0;
+  if (fp32)
+    batch_pass<float>(probs, idx, cnt, l, false, zero, phis, s);
+  else
+    batch_pass<double>(probs, idx, cnt, l, false, zero, phis, s);
+}
+
+void batch_up(tomg_problem *const *probs, const int *idx, int cnt, int l, bool fp32, bool norm,
+              double *const *phis, hipStream_t s) {
+  if (fp32)
+    batch_pass<float>(probs, idx, cnt, l, true, norm && l == 0, phis, s);
+  else
+    batch_pass<double>(probs, idx, cnt, l, true, norm && l == 0, phis, s);
+}
 
 }  // namespace tomg

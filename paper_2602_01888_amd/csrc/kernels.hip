@@ -10,6 +10,7 @@
 // tree, so a residual norm is bitwise reproducible from run to run.
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "tomg_internal.h"
 
@@ -476,31 +477,120 @@ __global__ void k_prolong(const T *ec, int nxc, T *x, const uint8_t *dir, int nx
   x[c] += e0;
 }
 
-// Partial sums of r^2 over free nodes (fixed grid, fixed order).
-template <class Op>
-__global__ void k_resnorm(Op op, const double *x, const double *b, const uint8_t *dir, int nx,
-                          int ny, double *partials) {
-  const size_t m = (size_t)(nx - 2) * (ny - 2);
+// ---------------------------------------------------------------------------
+// Level-0 reductions and the refinement kernels.  The block count of a
+// reduction depends only on the grid size (red_blocks), so a problem reduces
+// in the same order alone and in a batch.
+// ---------------------------------------------------------------------------
+
+// Residual at free node (i, j) of level 0 from the stored tensor; with ZF the
+// values at free nodes are taken as zero (the phi0 of the stopping test).
+template <bool ZF>
+__device__ __forceinline__ double resid0(const RedArgs &a, const double *x, int i, int j) {
+  const size_t s = (size_t)a.nx, c = (size_t)j * a.nx + i;
+  auto v = [&](size_t q) -> double { return (ZF && !a.dir[q]) ? 0.0 : x[q]; };
+  const double ax = a.exx[c] * a.cx, ay = a.eyy[c] * a.cy;
+  const double gx = (a.exx[c + 1] - a.exx[c - 1]) * a.qx + (a.exy[c + s] - a.exy[c - s]) * a.qxy;
+  const double gy = (a.eyy[c + s] - a.eyy[c - s]) * a.qy + (a.exy[c + 1] - a.exy[c - 1]) * a.qxy;
+  const double k1 = ax + gx, k3 = ax - gx, k4 = ay + gy, k5 = ay - gy;
+  const double k6 = a.exy[c] * a.hxy, k2 = 2.0 * (ax + ay);
+  const double off = k1 * v(c + 1) + k3 * v(c - 1) + k4 * v(c + s) + k5 * v(c - s) +
+                     k6 * ((v(c + s + 1) - v(c + s - 1)) - (v(c - s + 1) - v(c - s - 1)));
+  return a.f[c] - off + k2 * v(c);
+}
+
+// Partial sums of r^2 over free nodes: block blk of nblk, fixed order.
+template <bool ZF>
+__device__ __forceinline__ void resnorm_body(const RedArgs &a, const double *x, int blk) {
+  const size_t m = (size_t)(a.nx - 2) * (a.ny - 2);
   double s = 0.0;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const int j = 1 + (int)(k / (nx - 2)), i = 1 + (int)(k % (nx - 2));
-    const size_t c = (size_t)j * nx + i;
-    if (dir[c]) continue;
-    double off, dg;
-    op.row(c, x, off, dg);
-    const double r = b[c] - off - dg * x[c];
+  for (size_t k = (size_t)blk * blockDim.x + threadIdx.x; k < m;
+       k += (size_t)a.nblk * blockDim.x) {
+    const int j = 1 + (int)(k / (a.nx - 2)), i = 1 + (int)(k % (a.nx - 2));
+    if (a.dir[(size_t)j * a.nx + i]) continue;
+    const double r = resid0<ZF>(a, x, i, j);
     s += r * r;
   }
   s = block_reduce<0>(s);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) a.partials[blk] = s;
 }
 
-// Copy of phi with free nodes set to zero (the phi0 of the stopping test).
-__global__ void k_dirichlet_only(const double *phi, const uint8_t *dir, double *out, size_t n) {
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)gridDim.x * blockDim.x)
-    out[c] = dir[c] ? phi[c] : 0.0;
+// Refinement, outer step: r = f - A64 phi at free nodes (FP64), r32 =
+// fl32(r), partial sums of r^2.
+__device__ __forceinline__ void ir_residual_body(const RedArgs &a, const double *phi, int blk) {
+  const size_t n = (size_t)a.nx * a.ny;
+  double s = 0.0;
+  for (size_t c = (size_t)blk * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)a.nblk * blockDim.x) {
+    double r = 0.0;
+    if (!a.dir[c]) {
+      const int j = (int)(c / a.nx), i = (int)(c - (size_t)j * a.nx);
+      r = resid0<false>(a, phi, i, j);
+    }
+    a.r32[c] = (float)r;
+    s += r * r;
+  }
+  s = block_reduce<0>(s);
+  if (threadIdx.x == 0) a.partials[blk] = s;
+}
+
+// Refinement, update: phi += e32 at free nodes.
+__device__ __forceinline__ void ir_update_body(const RedArgs &a, double *phi, int blk) {
+  const size_t n = (size_t)a.nx * a.ny;
+  for (size_t c = (size_t)blk * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)a.nblk * blockDim.x)
+    if (!a.dir[c]) phi[c] += (double)a.e32[c];
+}
+
+template <bool ZF>
+__global__ void k_resnorm(RedArgs a, const double *x) { resnorm_body<ZF>(a, x, blockIdx.x); }
+__global__ void k_ir_residual(RedArgs a, const double *phi) {
+  ir_residual_body(a, phi, blockIdx.x);
+}
+__global__ void k_ir_update(RedArgs a, double *phi) { ir_update_body(a, phi, blockIdx.x); }
+
+__device__ __forceinline__ const BatchEntry &locate(const BatchTab &tab, int b) {
+  int lo = 0, hi = tab.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab.e[mid].start <= b) lo = mid; else hi = mid - 1;
+  }
+  return tab.e[lo];
+}
+
+// kind 0: resnorm (ZF), 1: resnorm, 2: refinement residual, 3: refinement update
+template <int KIND>
+__global__ void k_red_b(BatchTab tab) {
+  const BatchEntry &e = locate(tab, blockIdx.x);
+  const RedArgs a = *static_cast<const RedArgs *>(e.args);
+  const int blk = blockIdx.x - e.start;
+  double *phi = static_cast<double *>(e.phi);
+  if constexpr (KIND == 0) resnorm_body<true>(a, phi, blk);
+  if constexpr (KIND == 1) resnorm_body<false>(a, phi, blk);
+  if constexpr (KIND == 2) ir_residual_body(a, phi, blk);
+  if constexpr (KIND == 3) ir_update_body(a, phi, blk);
+}
+
+// Batched finalize: one block per problem; sqrt of the fixed-order sum into
+// scal[slot]; with rel, the relative residual and the convergence flag too,
+// and a copy into out[e.out].
+__global__ void k_finalize_b(BatchTab tab, int rel, double *out) {
+  const BatchEntry &e = tab.e[blockIdx.x];
+  const FinArgs a = *static_cast<const FinArgs *>(e.args);
+  double v = 0.0;
+  for (int k = threadIdx.x; k < a.n; k += blockDim.x) v += a.partials[k];
+  v = block_reduce<0>(v);
+  if (threadIdx.x == 0) {
+    v = sqrt(v);
+    a.scal[e.slot] = v;
+    if (rel) {
+      const double b0 = a.scal[kSlotB0];
+      const double r = b0 > 0.0 ? v / b0 : 0.0;
+      a.scal[kSlotRel] = r;
+      a.scal[kSlotDone] = (r <= a.scal[kSlotTol]) ? 1.0 : 0.0;
+      out[e.out] = r;
+    }
+  }
 }
 
 // Coarsest solve x = A^-1 b with the explicit inverse (one block).
@@ -518,35 +608,6 @@ __global__ void k_coarse_solve(const double *inv, const int *cidx, const T *b, T
       for (int q = 0; q < m; ++q) v += inv[k * m + q] * bb[q];
     x[c] = (T)v;
   }
-}
-
-// Iterative refinement, outer step: r = f - A64 phi in FP64 at free nodes,
-// r32 = fl32(r), e32 = 0 everywhere, partial sums of r^2.
-__global__ void k_ir_residual(EpsOp<double> op, const double *phi, const double *f,
-                              const uint8_t *dir, int nx, int ny, float *r32, float *e32,
-                              double *partials) {
-  const size_t n = (size_t)nx * ny;
-  double s = 0.0;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)gridDim.x * blockDim.x) {
-    double r = 0.0;
-    if (!dir[c]) {
-      double off, dg;
-      op.row(c, phi, off, dg);
-      r = f[c] - off - dg * phi[c];
-    }
-    r32[c] = (float)r;
-    e32[c] = 0.0f;
-    s += r * r;
-  }
-  s = block_reduce<0>(s);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-__global__ void k_ir_update(double *phi, const float *e32, const uint8_t *dir, size_t n) {
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)gridDim.x * blockDim.x)
-    if (!dir[c]) phi[c] += (double)e32[c];
 }
 
 // STREAM-style copy, 16 bytes per lane per iteration.
@@ -617,11 +678,13 @@ void restrict_level(tomg_problem *p, const Op &op, const T *x, const T *b, const
 // residual there (block count in *nblocks).
 // First level handed to the single-workgroup tail: the first coarse level
 // with at most tail_max_nodes() nodes and at most 4 levels below it.
-static int tail_level(const tomg_problem *p) {
+}  // namespace
+int tail_level(const tomg_problem *p) {
   for (int l = 1; l < p->L; ++l)
     if ((long)p->lv[l].nx * p->lv[l].ny <= tail_max_nodes() && p->L - l <= 4) return l;
   return p->L - 1;
 }
+namespace {
 
 // One V(nu1, nu2) cycle in precision T.  x0/b0: level-0 iterate and rhs;
 // op0: level-0 operator; coarse data from views[l].{x,b,st}.  zero0: the
@@ -783,17 +846,47 @@ hipError_t launch_vcycle64(tomg_problem *p, double *phi, bool with_norm) {
   return launch_resnorm(p, phi, kSlotRes, false);
 }
 
+int red_blocks(size_t n) {
+  const size_t b = (n + 4095) / 4096;
+  return (int)(b < 1 ? 1 : (b > (size_t)kRedBlocks ? kRedBlocks : b));
+}
+
+void build_red_args(tomg_problem *p) {
+  RedArgs &r = p->hargs.red;
+  r.exx = p->exx;
+  r.exy = p->exy;
+  r.eyy = p->eyy;
+  const double dx = p->cfg.dx, dy = p->cfg.dy;
+  r.cx = 1.0 / (dx * dx);
+  r.cy = 1.0 / (dy * dy);
+  r.qx = 0.25 / (dx * dx);
+  r.qy = 0.25 / (dy * dy);
+  r.qxy = 0.25 / (dx * dy);
+  r.hxy = 0.5 / (dx * dy);
+  r.nx = p->cfg.nx;
+  r.ny = p->cfg.ny;
+  r.f = p->f;
+  r.dir = p->lv[0].dir;
+  r.partials = p->partials;
+  r.r32 = p->r32;
+  r.e32 = p->e32;
+  r.tmp = p->tmp;
+  r.nblk = red_blocks(p->lv[0].n);
+  p->hargs.fin_red = {p->partials, p->scal, r.nblk};
+  const PassArgs<double> &u = p->hargs.up64[0];
+  p->hargs.fin_norm = {p->partials, p->scal, u.nbx * u.nby};
+}
+
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
-  hipLaunchKernelGGL(k_ir_residual, kRedBlocks, kRedThreads, 0, p->stream, op64(p), phi, p->f,
-                     p->lv[0].dir, p->cfg.nx, p->cfg.ny, p->r32, p->e32, p->partials);
-  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 1,
+  const RedArgs &r = p->hargs.red;
+  hipLaunchKernelGGL(k_ir_residual, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
                      p->scal + kSlotRes, 1, p->scal, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_ir_correct(tomg_problem *p, double *phi) {
   const int nx = p->cfg.nx;
-  const size_t n0 = p->lv[0].n;
   LevelView<float> v[kMaxLevels];
   for (int l = 0; l < p->L; ++l)
     v[l] = {p->lv[l].x32, p->lv[l].b32, p->lv[l].st32, p->lv[l].x2_32};
@@ -803,23 +896,85 @@ hipError_t launch_ir_correct(tomg_problem *p, double *phi) {
     hipError_t e = run_vcycle<float>(p, p->e32, p->r32, o32, v, k == 0, nullptr, nullptr);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_ir_update, grid1(n0), 256, 0, p->stream, phi, p->e32, p->lv[0].dir, n0);
+  const RedArgs &r = p->hargs.red;
+  hipLaunchKernelGGL(k_ir_update, r.nblk, kRedThreads, 0, p->stream, r, phi);
   return hipGetLastError();
 }
 
 hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free) {
-  const int nx = p->cfg.nx, ny = p->cfg.ny;
-  const double *x = phi;
-  if (zero_free) {
-    hipLaunchKernelGGL(k_dirichlet_only, grid1(p->lv[0].n), 256, 0, p->stream, phi, p->lv[0].dir,
-                       p->tmp, p->lv[0].n);
-    x = p->tmp;
-  }
-  hipLaunchKernelGGL((k_resnorm<EpsOp<double>>), kRedBlocks, kRedThreads, 0, p->stream, op64(p),
-                     x, p->f, p->lv[0].dir, nx, ny, p->partials);
-  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 1,
+  const RedArgs &r = p->hargs.red;
+  if (zero_free)
+    hipLaunchKernelGGL(k_resnorm<true>, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  else
+    hipLaunchKernelGGL(k_resnorm<false>, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
                      p->scal + slot, 1, p->scal, slot == kSlotRes ? 1 : 0);
   return hipGetLastError();
+}
+
+// ---- batched reductions ----------------------------------------------------
+
+template <int KIND>
+static void batch_red(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                      hipStream_t s) {
+  BatchTab tab;
+  for (int k0 = 0; k0 < cnt; k0 += kBatchMax) {
+    tab.count = 0;
+    int nb = 0;
+    for (int k = k0; k < cnt && k < k0 + kBatchMax; ++k) {
+      tomg_problem *p = probs[idx[k]];
+      BatchEntry &e = tab.e[tab.count++];
+      e.args = &p->dargs->red;
+      e.phi = phis[idx[k]];
+      e.role = 0;
+      e.nbx = p->hargs.red.nblk;
+      e.nby = 1;
+      e.start = nb;
+      e.slot = e.out = 0;
+      nb += e.nbx;
+    }
+    if (tab.count) hipLaunchKernelGGL(k_red_b<KIND>, nb, kRedThreads, 0, s, tab);
+  }
+}
+
+void batch_resnorm(tomg_problem *const *probs, const int *idx, int cnt, bool zero_free,
+                   double *const *phis, hipStream_t s) {
+  if (zero_free)
+    batch_red<0>(probs, idx, cnt, phis, s);
+  else
+    batch_red<1>(probs, idx, cnt, phis, s);
+}
+
+void batch_ir_residual(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                       hipStream_t s) {
+  batch_red<2>(probs, idx, cnt, phis, s);
+}
+
+void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                     hipStream_t s) {
+  batch_red<3>(probs, idx, cnt, phis, s);
+}
+
+void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kind, int slot,
+                    bool rel, double *out, hipStream_t s) {
+  BatchTab tab;
+  for (int k0 = 0; k0 < cnt; k0 += kBatchMax) {
+    tab.count = 0;
+    for (int k = k0; k < cnt && k < k0 + kBatchMax; ++k) {
+      tomg_problem *p = probs[idx[k]];
+      BatchEntry &e = tab.e[tab.count];
+      e.args = kind == 0 ? (const void *)&p->dargs->fin_red : (const void *)&p->dargs->fin_norm;
+      e.phi = nullptr;
+      e.role = 0;
+      e.nbx = e.nby = 1;
+      e.start = tab.count;
+      e.slot = slot;
+      e.out = k;
+      ++tab.count;
+    }
+    if (tab.count)
+      hipLaunchKernelGGL(k_finalize_b, tab.count, kRedThreads, 0, s, tab, rel ? 1 : 0, out);
+  }
 }
 
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps) {

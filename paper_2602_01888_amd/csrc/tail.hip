@@ -11,32 +11,15 @@
 // between two barriers.  Arithmetic per node is that of the other kernels:
 // four-colour Gauss-Seidel on the stored 9-point stencil, full weighting,
 // bilinear prolongation, explicit coarsest inverse.
+#include <type_traits>
+
 #include "tomg_internal.h"
 
 namespace tomg {
 namespace {
 
 constexpr int kTailThreads = 1024;
-constexpr int kOwn = 1;        // nodes per thread and level
-constexpr int kTailLevels = 4; // levels of at most kTailThreads nodes
-
-template <typename T>
-struct TailLevel {
-  int nx, ny;
-  const T *st;
-  T *x;
-  const T *b;
-  const uint8_t *dir;
-  int off;  // offset of the level's iterate in the LDS array
-};
-
-template <typename T>
-struct TailArgs {
-  int lc, nl, nu1, nu2;  // levels lc .. lc+nl-1 (the last is the coarsest)
-  const double *cinv;
-  const int *cidx;
-  TailLevel<T> lv[kTailLevels];
-};
+constexpr int kOwn = 1;  // nodes per thread and level
 
 template <typename T>
 struct Own {
@@ -47,7 +30,7 @@ struct Own {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
+__device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
   extern __shared__ unsigned char smem_raw[];
   T *X = reinterpret_cast<T *>(smem_raw);
   __shared__ double bb[kMaxCoarseUnknowns];
@@ -192,16 +175,27 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
+  tail_body<T>(a);
+}
+
+// Batched form: one workgroup per problem.
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail_b(BatchTab tab) {
+  const TailArgs<T> a = *static_cast<const TailArgs<T> *>(tab.e[blockIdx.x].args);
+  tail_body<T>(a);
+}
+
 }  // namespace
 
 // Number of nodes a level may have to be handled by the tail.
 int tail_max_nodes() { return kTailThreads * kOwn; }
 
-// Levels lc..L-1 in one workgroup; xs/bs/sts give the per-level correction,
-// right-hand side and stencil arrays of precision T (indexed by level).
 template <typename T>
-void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *const *sts) {
+static TailArgs<T> make_tail_args(tomg_problem *p, int lc) {
   TailArgs<T> a{};
+  const bool f32 = std::is_same<T, float>::value;
   a.lc = lc;
   a.nl = p->L - lc;
   a.nu1 = p->cfg.nu1;
@@ -210,25 +204,69 @@ void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *co
   a.cidx = p->cidx;
   int off = 0, rmax = 0;
   for (int q = 0; q < a.nl; ++q) {
-    const int l = lc + q;
-    a.lv[q].nx = p->lv[l].nx;
-    a.lv[q].ny = p->lv[l].ny;
-    a.lv[q].st = sts[l];
-    a.lv[q].x = xs[l];
-    a.lv[q].b = bs[l];
-    a.lv[q].dir = p->lv[l].dir;
+    const Level &v = p->lv[lc + q];
+    a.lv[q].nx = v.nx;
+    a.lv[q].ny = v.ny;
+    a.lv[q].st = (const T *)(f32 ? (void *)v.st32 : (void *)v.st);
+    a.lv[q].x = (T *)(f32 ? (void *)v.x32 : (void *)v.x);
+    a.lv[q].b = (const T *)(f32 ? (void *)v.b32 : (void *)v.b);
+    a.lv[q].dir = v.dir;
     a.lv[q].off = off;
-    const int n = p->lv[l].nx * p->lv[l].ny;
+    const int n = v.nx * v.ny;
     off += n;
     rmax = rmax > n ? rmax : n;
   }
-  const size_t shmem = (size_t)(off + rmax) * sizeof(T);
-  hipLaunchKernelGGL((k_tail<T>), 1, kTailThreads, shmem, p->stream, a);
+  a.shmem = (off + rmax) * (int)sizeof(T);
+  return a;
+}
+
+void build_tail_args(tomg_problem *p) {
+  p->hargs.tail64 = make_tail_args<double>(p, p->lc);
+  if (p->cfg.precision == TOMG_FP32_IR) p->hargs.tail32 = make_tail_args<float>(p, p->lc);
+}
+
+// Levels lc..L-1 in one workgroup; xs/bs/sts give the per-level correction,
+// right-hand side and stencil arrays of precision T (indexed by level).
+template <typename T>
+void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *const *sts) {
+  TailArgs<T> a = make_tail_args<T>(p, lc);
+  for (int q = 0; q < a.nl; ++q) {
+    a.lv[q].st = sts[lc + q];
+    a.lv[q].x = xs[lc + q];
+    a.lv[q].b = bs[lc + q];
+  }
+  hipLaunchKernelGGL((k_tail<T>), 1, kTailThreads, a.shmem, p->stream, a);
 }
 
 template void tail_cycle<double>(tomg_problem *, int, double *const *, double *const *,
                                  const double *const *);
 template void tail_cycle<float>(tomg_problem *, int, float *const *, float *const *,
                                 const float *const *);
+
+void batch_tail(tomg_problem *const *probs, const int *idx, int cnt, bool fp32, hipStream_t s) {
+  BatchTab tab;
+  for (int k0 = 0; k0 < cnt; k0 += kBatchMax) {
+    tab.count = 0;
+    int shmem = 0;
+    for (int k = k0; k < cnt && k < k0 + kBatchMax; ++k) {
+      tomg_problem *p = probs[idx[k]];
+      BatchEntry &e = tab.e[tab.count];
+      e.args = fp32 ? (const void *)&p->dargs->tail32 : (const void *)&p->dargs->tail64;
+      e.phi = nullptr;
+      e.role = 0;
+      e.nbx = e.nby = 1;
+      e.start = tab.count;
+      e.slot = e.out = 0;
+      const int sh = fp32 ? p->hargs.tail32.shmem : p->hargs.tail64.shmem;
+      shmem = shmem > sh ? shmem : sh;
+      ++tab.count;
+    }
+    if (!tab.count) continue;
+    if (fp32)
+      hipLaunchKernelGGL(k_tail_b<float>, tab.count, kTailThreads, shmem, s, tab);
+    else
+      hipLaunchKernelGGL(k_tail_b<double>, tab.count, kTailThreads, shmem, s, tab);
+  }
+}
 
 }  // namespace tomg

@@ -39,6 +39,91 @@ struct Level {
   float *st32 = nullptr, *x32 = nullptr, *b32 = nullptr, *x2_32 = nullptr;  // FP32 (IR)
 };
 
+// ---- per-problem launch arguments (device copies live in the workspace) ----
+
+// One fused level pass (fused.hip).
+template <typename T>
+struct PassArgs {
+  int nx, ny;
+  const T *xin;              // level iterate read (unless the pass starts at zero)
+  T *xout;                   // level iterate written (never the array read)
+  const T *b;                // level right-hand side
+  const uint8_t *dir;        // Dirichlet flags of the level
+  const T *exx, *exy, *eyy;  // level 0: permittivity tensor
+  const T *st;               // coarse levels: 9-point stencil planes
+  T cx, cy, qx, qy, qxy, hxy;
+  const T *xc;               // up pass: coarse correction
+  T *bc;                     // down pass: coarse right-hand side
+  int nxc, nyc;
+  double *partials;          // up pass with norm: one double per block
+  int CH, W;                 // band height, owned columns per block
+  int nbx, nby;              // block grid
+};
+
+// One level of the single-workgroup tail (tail.hip).
+template <typename T>
+struct TailLevel {
+  int nx, ny;
+  const T *st;
+  T *x;
+  const T *b;
+  const uint8_t *dir;
+  int off;  // offset of the level's iterate in the LDS array
+};
+constexpr int kTailLevels = 4;
+template <typename T>
+struct TailArgs {
+  int lc, nl, nu1, nu2;  // levels lc .. lc+nl-1 (the last is the coarsest)
+  const double *cinv;
+  const int *cidx;
+  int shmem;             // dynamic LDS bytes
+  TailLevel<T> lv[kTailLevels];
+};
+
+// Level-0 residual reductions and the refinement kernels (kernels.hip).
+struct RedArgs {
+  const double *exx, *exy, *eyy;
+  double cx, cy, qx, qy, qxy, hxy;
+  int nx, ny;
+  const double *f;
+  const uint8_t *dir;
+  double *partials;
+  float *r32, *e32;
+  double *tmp;
+  int nblk;  // blocks of the reduction (a function of the grid size only)
+};
+
+// Fixed-order reduction of partials into the scalar block.
+struct FinArgs {
+  const double *partials;
+  double *scal;
+  int n;
+};
+
+struct ArgsBlob {
+  PassArgs<double> down64[kMaxLevels], up64[kMaxLevels];
+  PassArgs<float> down32[kMaxLevels], up32[kMaxLevels];
+  TailArgs<double> tail64;
+  TailArgs<float> tail32;
+  RedArgs red;
+  FinArgs fin_red, fin_norm;
+};
+
+// One problem's share of a batched launch: blocks [start, start + nbx*nby).
+// phi/role: the level-0 iterate of this solve (role 1: the array the pass
+// reads, 2: the array it writes).  slot/out: where a finalize writes.
+struct BatchEntry {
+  const void *args;
+  void *phi;
+  int role, nbx, nby, start, slot, out;
+};
+constexpr int kBatchMax = 96;
+struct BatchTab {
+  int count;
+  BatchEntry e[kBatchMax];
+};
+constexpr int kMaxBatch = 4096;  // problems per tomg_solve_batch call
+
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
   int L = 0;
@@ -47,6 +132,7 @@ struct Layout {
   size_t dir[kMaxLevels], st[kMaxLevels], x[kMaxLevels], b[kMaxLevels], x2[kMaxLevels];
   size_t exx32, exy32, eyy32, e32, e32b, r32;
   size_t st32[kMaxLevels], x32[kMaxLevels], b32[kMaxLevels], x2_32[kMaxLevels];
+  size_t args, bout;  // device copy of the launch arguments; batch results
   size_t total = 0;
 };
 
@@ -68,6 +154,10 @@ struct tomg_problem {
   int *cidx = nullptr;
   float *exx32 = nullptr, *exy32 = nullptr, *eyy32 = nullptr, *e32 = nullptr, *r32 = nullptr;
   float *e32b = nullptr;
+  tomg::ArgsBlob *dargs = nullptr;  // device copy of hargs
+  tomg::ArgsBlob hargs;             // host copy (source of the upload)
+  double *bout = nullptr;           // batch results (used when this problem leads a batch)
+  int lc = 0;                       // first level of the tail
   int m_coarse = 0;
   bool ready = false;
   // level-0 pass timing (tomg_profile): event pairs recorded since the last
@@ -109,6 +199,34 @@ hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zer
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps);
 hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// launch arguments of every stage, built once per problem (fused.hip,
+// tail.hip, kernels.hip) and uploaded by tomg_create
+void build_pass_args(tomg_problem *p);
+void build_tail_args(tomg_problem *p);
+void build_red_args(tomg_problem *p);
+int red_blocks(size_t n);
+int tail_level(const tomg_problem *p);
+
+// batched stages over problems probs[idx[0..cnt-1]] (one launch per up to
+// kBatchMax problems); phis: the level-0 iterate of each problem (indexed
+// like probs)
+void batch_down(tomg_problem *const *probs, const int *idx, int cnt, int l, bool fp32, bool zero0,
+                double *const *phis, hipStream_t s);
+void batch_up(tomg_problem *const *probs, const int *idx, int cnt, int l, bool fp32, bool norm,
+              double *const *phis, hipStream_t s);
+void batch_tail(tomg_problem *const *probs, const int *idx, int cnt, bool fp32, hipStream_t s);
+void batch_resnorm(tomg_problem *const *probs, const int *idx, int cnt, bool zero_free,
+                   double *const *phis, hipStream_t s);
+void batch_ir_residual(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                       hipStream_t s);
+void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                     hipStream_t s);
+// kind 0: the reduction partials (fin_red), 1: the level-0 up-pass partials
+// (fin_norm); slot: scalar slot written; rel: also write rel and done, and
+// copy the value into out[k] for entry k (out = the leading problem's bout)
+void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kind, int slot,
+                    bool rel, double *out, hipStream_t s);
 
 // Pass timing around level-0 passes (no-ops unless p->prof).
 void prof_begin(tomg_problem *p, int kind);
