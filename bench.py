@@ -15,7 +15,11 @@ Also measured in the same run (extra keys of the line):
                 iterative refinement;
   roofline    : the level-0 down pass (the dominant kernel) timed with HIP
                 events over the timed steps, against 8 TB/s;
-  cpu_baseline: the CPU oracle on the same input (bounded sample).
+  cpu_baseline: the CPU oracle on the same input (bounded sample);
+  batch       : 256 independent sinusoidal-map problems of sides 65..1025
+                solved together by one tomg_solve_batch call (mixed
+                precision, and FP64 beside it), against solving them one
+                after another.
 """
 
 import argparse
@@ -109,7 +113,111 @@ def cpu_baseline(prob, gpu_cycles, budget_s=30.0):
                           f"({t_setup:.2f} s + {per:.2f} s/cycle), extrapolated to the full "
                           f"solve")
     out["seconds_per_solve"] = total
-    return out, phi_ref, (np.asarray(phi_ref) if phi_ref is not None else None)
+    tight = None
+    if phi_ref is not None:
+        # the reference solution: the oracle's iterate continued to the FP64
+        # floor (relative residual 1e-13 or 30 more cycles)
+        tight, _, cyc2, rel2, _ = mg.solve(phi_ref, s["f"], 1e-13, 30)
+        out["reference"] = f"oracle multigrid continued {cyc2} cycles to relative residual " \
+                           f"{rel2:.2e}"
+    return out, phi_ref, tight
+
+
+def batch_leg(tomg, w, torch, dev, steps, warmup, count=256):
+    """Batched workload: problem p has seed 1000 + p, side drawn from
+    {65, 129, 257, 513, 1025}, a sinusoidal map of random amplitude and four
+    Gaussian sources.  Times one tomg_solve_batch over all problems (iterates
+    reset to zero before each timed call), in mixed precision and in FP64,
+    and the same problems solved one after another; checks every result
+    with the oracle's residual and the small ones against the oracle's
+    solution."""
+    import numpy as np
+
+    import oracle
+    t = time.time()
+    probs = w.batch_mixed(count)
+    gen_s = time.time() - t
+    dof = sum(q.nx * q.ny for q in probs)
+    log(f"[bench] batch: generated {count} problems ({dof / 1e6:.1f} M nodes) in {gen_s:.1f}s")
+    ups = [tomg.upload(q, dev) for q in probs]
+    out = {"problems": count, "dof": dof,
+           "sides": {str(s): sum(q.nx == s for q in probs) for s in sorted({q.nx for q in probs})}}
+
+    def build(precision):
+        ps = [tomg.Problem.from_grid(q, precision=precision, device=dev) for q in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p, d in zip(ps, ups):
+            p.setup_coeffs(d["rho"], jac=d["jac"])
+        torch.cuda.synchronize()
+        return ps, time.perf_counter() - t0
+
+    def run_batch(ps, phis, k):
+        lat = []
+        res = None
+        for it in range(k):
+            for f in phis:
+                f.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = tomg.solve_batch(ps, phis, rel_tol=1e-10, max_cycles=100)
+            lat.append(time.perf_counter() - t0)
+        bad = [r for r in res if not r.ok]
+        if bad:
+            raise RuntimeError(f"batch solve failed: {bad[:3]}")
+        return lat, res
+
+    for precision in ("fp32_ir", "fp64"):
+        ps, setup_s = build(precision)
+        phis = [d["phi0"].clone() for d in ups]
+        run_batch(ps, phis, max(1, warmup))
+        lat, res = run_batch(ps, phis, max(3, steps))
+        med = float(np.median(lat))
+        leg = {"batch_latency_ms": med * 1e3, "latency_min_ms": min(lat) * 1e3,
+               "solves_per_s": count / med, "dof_per_s": dof / med,
+               "setup_all_ms": setup_s * 1e3,
+               "cycles_max": max(r.cycles for r in res),
+               "cycles_mean": float(np.mean([r.cycles for r in res])),
+               "rel_residual_max": max(r.rel for r in res),
+               "workspace_GB": sum(p.workspace_bytes for p in ps) / 1e9}
+        # the same problems one after another
+        for f in phis:
+            f.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p, f in zip(ps, phis):
+            p.solve(f, rel_tol=1e-10, max_cycles=100)
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t0
+        leg["one_after_another_ms"] = seq * 1e3
+        leg["batch_speedup_vs_one_after_another"] = seq / med
+        if precision == "fp32_ir":
+            # re-run the batch so that phis hold its results, then check them
+            run_batch(ps, phis, 1)
+            worst_res, worst_err, n_err = 0.0, 0.0, 0
+            for q, f in zip(probs, phis):
+                g = f.cpu().numpy()
+                s = oracle.setup(q)
+                st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], q.dx, q.dy, s["dir"])
+                b0 = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], q.phi0, s["f"]))
+                rr = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], g, s["f"])) / b0
+                worst_res = max(worst_res, rr)
+                if q.nx <= 257:
+                    mg = oracle.MG.from_setup(s, q.dx, q.dy)
+                    ref = mg.solve(q.phi0, s["f"], 1e-13, 60)[0]
+                    worst_err = max(worst_err, float(np.max(np.abs(g - ref)) /
+                                                     np.max(np.abs(ref))))
+                    n_err += 1
+            leg["oracle_rel_residual_max"] = worst_res
+            leg["error_vs_oracle_max"] = worst_err
+            leg["error_checked_problems"] = f"{n_err} problems of side <= 257 against the " \
+                                            f"oracle's solution at 1e-13 relative residual"
+        out["mixed" if precision == "fp32_ir" else "fp64"] = leg
+        log(f"[bench] batch {precision}: {med * 1e3:.2f} ms per batch, "
+            f"{count / med:.0f} solves/s, one after another {seq * 1e3:.1f} ms")
+        del ps, phis
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -121,7 +229,9 @@ def main():
     ap.add_argument("--n", type=int, default=4097, help="grid side (default 4097)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision and batch legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch leg")
     ap.add_argument("--probe", action="store_true",
                     help="short run for counter collection: warmup + 2 solves + one copy probe")
     args = ap.parse_args()
@@ -227,37 +337,82 @@ def main():
                 "copy_probe_GBs": round(copy_gbs, 1)}
 
     # ----------------------------------------------------------- mixed ----
+    # FP32 V(2,2) cycles inside FP64 iterative refinement, k inner cycles per
+    # refinement step for k = 1, 2, 3; the fastest k is reported.
     mixed = None
+    phi32 = None
     if not args.no_extras:
-        p32 = make("fp32_ir")
-        for _ in range(max(1, args.warmup)):
-            r32 = step(p32)
-        torch.cuda.synchronize()
-        k32 = max(3, args.steps)
-        t3 = time.perf_counter()
-        for _ in range(k32):
-            r32 = step(p32)
-        torch.cuda.synchronize()
-        el32 = time.perf_counter() - t3
-        phi32 = phi.detach().cpu().numpy()
-        mixed = {"value": k32 / el32, "unit": "solves/s", "dof_per_s": k32 * n0 / el32,
-                 "ms_per_step": el32 / k32 * 1e3, "refinement_steps": r32.cycles,
-                 "inner_cycles_per_step": 2, "rel_residual": r32.rel,
-                 "speedup_vs_fp64": (k32 / el32) / (args.steps / elapsed),
+        sweep = {}
+        best = None
+        for k in (1, 2, 3):
+            p32 = tomg.Problem.from_grid(prob, precision="fp32_ir", ir_inner_cycles=k, device=dev)
+            for _ in range(max(1, args.warmup)):
+                r32 = step(p32)
+            torch.cuda.synchronize()
+            k32 = max(3, args.steps)
+            t3 = time.perf_counter()
+            for _ in range(k32):
+                r32 = step(p32)
+            torch.cuda.synchronize()
+            el32 = time.perf_counter() - t3
+            sweep[k] = {"ms_per_step": el32 / k32 * 1e3, "refinement_steps": r32.cycles,
+                        "rel_residual": r32.rel}
+            log(f"[bench] mixed k={k}: {el32 / k32 * 1e3:.3f} ms/step, {r32.cycles} steps")
+            if best is None or el32 / k32 < best[1]:
+                best = (k, el32 / k32, r32)
+                phi32 = phi.detach().cpu().numpy()
+                # solve only, and the same solve continued to a tight tolerance
+                t4 = time.perf_counter()
+                for _ in range(k32):
+                    phi.copy_(d["phi0"])
+                    p32.solve(phi, rel_tol=1e-10, max_cycles=100)
+                torch.cuda.synchronize()
+                so32 = (time.perf_counter() - t4) / k32
+                phi.copy_(d["phi0"])
+                rt = p32.solve(phi, rel_tol=1e-13, max_cycles=60, raise_on_error=False)
+                phi32_tight = (phi.detach().cpu().numpy(), rt)
+            del p32
+        k, per, r32 = best
+        mixed = {"value": 1.0 / per, "unit": "solves/s", "dof_per_s": n0 / per,
+                 "ms_per_step": per * 1e3, "inner_cycles_per_step": k,
+                 "refinement_steps": r32.cycles, "rel_residual": r32.rel,
+                 "speedup_vs_fp64": (1.0 / per) / (args.steps / elapsed),
+                 "solve_only_ms": so32 * 1e3,
+                 "solve_only_speedup_vs_fp64": solve_only / so32,
                  "diff_vs_fp64_gpu": float(np.max(np.abs(phi32 - phi64)) /
-                                           np.max(np.abs(phi64)))}
-        del p32
+                                           np.max(np.abs(phi64))),
+                 "inner_cycle_sweep": sweep}
+
+    # FP64 continued to a tight tolerance (accuracy reference on the GPU side)
+    phi.copy_(d["phi0"])
+    rt64 = p64.solve(phi, rel_tol=1e-13, max_cycles=60, raise_on_error=False)
+    phi64_tight = phi.detach().cpu().numpy()
+
+    # ----------------------------------------------------------- batch ----
+    batch = None
+    if not args.no_extras and not args.no_batch:
+        batch = batch_leg(tomg, w, torch, dev, args.steps, args.warmup)
 
     # ------------------------------------------------------ CPU oracle ----
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
-        cpu, _, ref = cpu_baseline(prob, cycles)
+        cpu, ref10, ref = cpu_baseline(prob, cycles)
         if ref is not None:
             scale = float(np.max(np.abs(ref)))
-            err64 = float(np.max(np.abs(phi64 - ref)) / scale)
-            cpu["gpu_fp64_error_vs_oracle"] = err64
+
+            def err(x):
+                return float(np.max(np.abs(x - ref)) / scale)
+            accuracy = {"reference": cpu.pop("reference"),
+                        "fp64_at_1e-10": err(phi64),
+                        "fp64_tight": err(phi64_tight), "fp64_tight_rel": rt64.rel,
+                        "oracle_at_1e-10": err(ref10)}
             if mixed is not None:
-                mixed["error_vs_oracle"] = float(np.max(np.abs(phi32 - ref)) / scale)
+                accuracy["mixed_at_1e-10"] = err(phi32)
+                accuracy["mixed_tight"] = err(phi32_tight[0])
+                accuracy["mixed_tight_rel"] = phi32_tight[1].rel
+                mixed["error_vs_oracle"] = accuracy["mixed_at_1e-10"]
+            cpu["gpu_fp64_error_vs_oracle"] = accuracy["fp64_at_1e-10"]
 
     value = args.steps / elapsed
     line = {
@@ -283,6 +438,8 @@ def main():
         "solve_only": {"ms": solve_only * 1e3, "solves_per_s": 1.0 / solve_only,
                        "dof_per_s": n0 / solve_only},
         "mixed": mixed,
+        "batch": batch,
+        "accuracy": accuracy,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

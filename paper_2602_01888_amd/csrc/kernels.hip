@@ -173,45 +173,56 @@ __device__ __forceinline__ double d_j(const double *a, int nx, int ny, int j, si
   return (a[c + s] - a[c - s]) * inv2h;
 }
 
+// One workgroup per row (grid-stride over rows), threads along the row.
+// When exx32 is given the FP32 copies of the tensor used by the inner solver
+// of iterative refinement are written beside the FP64 fields.
 __global__ void k_setup(int nx, int ny, double dx, double dy, const double *xp, const double *yp,
                         const double *jac, const double *epsp, const double *rho,
                         const uint8_t *mask, double *exx, double *exy, double *eyy, double *det,
-                        double *f, uint8_t *dir, double *partials) {
+                        double *f, uint8_t *dir, float *exx32, float *exy32, float *eyy32,
+                        double *partials) {
   const size_t n = (size_t)nx * ny;
   const double i2dx = 0.5 / dx, i2dy = 0.5 / dy;
   double mind = INFINITY, bad = 0.0;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)gridDim.x * blockDim.x) {
-    const int j = (int)(c / nx), i = (int)(c - (size_t)j * nx);
-    double jxx, jxy, jyx, jyy;
-    if (jac) {
-      jxx = jac[c];
-      jxy = jac[n + c];
-      jyx = jac[2 * n + c];
-      jyy = jac[3 * n + c];
-    } else {
-      jxx = d_i(xp, nx, i, c, i2dx);
-      jxy = d_j(xp, nx, ny, j, c, i2dy);
-      jyx = d_i(yp, nx, i, c, i2dx);
-      jyy = d_j(yp, nx, ny, j, c, i2dy);
-    }
-    const double D = jxx * jyy - jxy * jyx;
-    const double s = epsp ? epsp[c] : 1.0;
-    const double vxx = s * (jyy * jyy + jxy * jxy) / D;
-    const double vxy = s * (-jyy * jyx - jxy * jxx) / D;
-    const double vyy = s * (jyx * jyx + jxx * jxx) / D;
-    const double fv = -rho[c] * D;
-    exx[c] = vxx;
-    exy[c] = vxy;
-    eyy[c] = vyy;
-    det[c] = D;
-    f[c] = fv;
-    const bool ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
-    dir[c] = (uint8_t)(ring || (mask && mask[c]));
-    const bool corner = (i == 0 || i == nx - 1) && (j == 0 || j == ny - 1);
-    if (!corner) {
-      mind = fmin(mind, D);
-      if (!isfinite(vxx) || !isfinite(vxy) || !isfinite(vyy) || !isfinite(fv)) bad += 1.0;
+  for (int j = blockIdx.x; j < ny; j += gridDim.x) {
+    const size_t row = (size_t)j * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      const size_t c = row + i;
+      double jxx, jxy, jyx, jyy;
+      if (jac) {
+        jxx = jac[c];
+        jxy = jac[n + c];
+        jyx = jac[2 * n + c];
+        jyy = jac[3 * n + c];
+      } else {
+        jxx = d_i(xp, nx, i, c, i2dx);
+        jxy = d_j(xp, nx, ny, j, c, i2dy);
+        jyx = d_i(yp, nx, i, c, i2dx);
+        jyy = d_j(yp, nx, ny, j, c, i2dy);
+      }
+      const double D = jxx * jyy - jxy * jyx;
+      const double s = epsp ? epsp[c] : 1.0;
+      const double vxx = s * (jyy * jyy + jxy * jxy) / D;
+      const double vxy = s * (-jyy * jyx - jxy * jxx) / D;
+      const double vyy = s * (jyx * jyx + jxx * jxx) / D;
+      const double fv = -rho[c] * D;
+      exx[c] = vxx;
+      exy[c] = vxy;
+      eyy[c] = vyy;
+      det[c] = D;
+      f[c] = fv;
+      if (exx32) {
+        exx32[c] = (float)vxx;
+        exy32[c] = (float)vxy;
+        eyy32[c] = (float)vyy;
+      }
+      const bool ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+      dir[c] = (uint8_t)(ring || (mask && mask[c]));
+      const bool corner = (i == 0 || i == nx - 1) && (j == 0 || j == ny - 1);
+      if (!corner) {
+        mind = fmin(mind, D);
+        if (!isfinite(vxx) || !isfinite(vxy) || !isfinite(vyy) || !isfinite(fv)) bad += 1.0;
+      }
     }
   }
   const double m = block_reduce<1>(mind);
@@ -235,67 +246,127 @@ __global__ void k_update_rhs(const double *rho, const double *det, double *f, si
   if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
-// Coarse Dirichlet flags: ring, or every fine node of the 3x3 support of the
-// coarse node is Dirichlet (its column of the prolongation is empty).
-__global__ void k_coarse_dir(int nxf, const uint8_t *dirf, int nxc, int nyc, uint8_t *dirc) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y * blockDim.y + threadIdx.y;
-  if (I >= nxc || J >= nyc) return;
-  uint8_t d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
-  if (!d) {
-    bool all = true;
-    for (int b = -1; b <= 1; ++b)
-      for (int a = -1; a <= 1; ++a) all = all && dirf[(size_t)(2 * J + b) * nxf + 2 * I + a];
-    d = all;
-  }
-  dirc[(size_t)J * nxc + I] = d;
-}
+__host__ __device__ constexpr double pw(int d) { return d == 0 ? 1.0 : ((d == 1 || d == -1) ? 0.5 : 0.0); }
 
-__device__ __forceinline__ double pw(int d) { return d == 0 ? 1.0 : ((d == 1 || d == -1) ? 0.5 : 0.0); }
+// Galerkin coarsening of one level (eq. 23; the paper leaves the coarse
+// operator open): A_H = (1/4) P^T A_h P with P bilinear, zero rows at fine
+// Dirichlet nodes and no columns at coarse Dirichlet nodes, identity rows
+// there.  A coarse node is Dirichlet on the ring and where all nine fine
+// nodes of its support are Dirichlet (its column of P is empty).
+//
+// A workgroup owns kGX x kGY coarse nodes.  It stages the fine Dirichlet
+// flags of its window, derives the coarse flags of the tile and its one-node
+// halo, and computes each fine stencil of the window once into LDS with the
+// couplings to Dirichlet fine nodes already zeroed; each thread then sums
+// the 81 (fine node, neighbour) products of its coarse node with
+// compile-time weights.  The summation order is that of the triple sum
+// (fine row b, a; neighbour q, p; coarse column).
+constexpr int kGX = 32, kGY = 4;
+constexpr int kGFX = 2 * kGX + 1, kGFY = 2 * kGY + 1;  // fine stencil window
+constexpr int kGDX = 2 * kGX + 5, kGDY = 2 * kGY + 5;  // fine flag window
+constexpr int kGCX = kGX + 2, kGCY = kGY + 2;          // coarse flag window
 
-// Galerkin coarse operator A_H = (1/4) P^T A_h P (eq. 23; the paper leaves
-// the coarse operator open), P bilinear with zero rows at fine Dirichlet
-// nodes and no columns at coarse Dirichlet nodes; identity rows there.
 template <class Op>
-__global__ void k_galerkin(Op opf, const uint8_t *dirf, int nxf, int nxc, int nyc,
-                           const uint8_t *dirc, double *stc) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+__global__ __launch_bounds__(kGX *kGY) void k_coarsen(Op opf, const uint8_t *dirf, int nxf,
+                                                      int nyf, int nxc, int nyc, uint8_t *dirc,
+                                                      double *stc, float *stc32) {
+  __shared__ double S[9][kGFY][kGFX];
+  __shared__ uint8_t DF[kGDY][kGDX];
+  __shared__ uint8_t DC[kGCY][kGCX];
+  constexpr int NT = kGX * kGY;
+  const int t = threadIdx.x;
+  const int I0 = blockIdx.x * kGX, J0 = blockIdx.y * kGY;
+  // fine flags at (2 I0 - 3 + x, 2 J0 - 3 + y); outside the grid counts as Dirichlet
+  for (int k = t; k < kGDX * kGDY; k += NT) {
+    const int x = k % kGDX, y = k / kGDX;
+    const int fi = 2 * I0 - 3 + x, fj = 2 * J0 - 3 + y;
+    DF[y][x] = (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) ? 1 : dirf[(size_t)fj * nxf + fi];
+  }
+  __syncthreads();
+  // coarse flags at (I0 - 1 + x, J0 - 1 + y); support of coarse x at fine 2x + 1 + a
+  for (int k = t; k < kGCX * kGCY; k += NT) {
+    const int x = k % kGCX, y = k / kGCX;
+    const int I = I0 - 1 + x, J = J0 - 1 + y;
+    uint8_t d = 1;
+    if (I >= 0 && J >= 0 && I < nxc && J < nyc) {
+      d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
+      if (!d) {
+        bool all = true;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) all = all && DF[2 * y + 1 + b][2 * x + 1 + a];
+        d = all;
+      }
+      if (x >= 1 && y >= 1 && x <= kGX && y <= kGY) dirc[(size_t)J * nxc + I] = d;
+    }
+    DC[y][x] = d;
+  }
+  // fine stencils at (2 I0 - 1 + x, 2 J0 - 1 + y) = flag window (x + 2, y + 2);
+  // a non-Dirichlet fine node is interior, so its stencil is defined
+  for (int k = t; k < kGFX * kGFY; k += NT) {
+    const int x = k % kGFX, y = k / kGFX;
+    double s[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s[q] = 0.0;
+    if (!DF[y + 2][x + 2]) {
+      const int fi = 2 * I0 - 1 + x, fj = 2 * J0 - 1 + y;
+      opf.full((size_t)fj * nxf + fi, s);
+#pragma unroll
+      for (int q = -1; q <= 1; ++q)
+#pragma unroll
+        for (int pp = -1; pp <= 1; ++pp)
+          if (DF[y + 2 + q][x + 2 + pp]) s[(q + 1) * 3 + pp + 1] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) S[q][y][x] = s[q];
+  }
+  __syncthreads();
+  const int tx = t % kGX, ty = t / kGX;
+  const int I = I0 + tx, J = J0 + ty;
   if (I >= nxc || J >= nyc) return;
   const size_t nc = (size_t)nxc * nyc, C = (size_t)J * nxc + I;
   double acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-  if (dirc[C]) {
+  if (DC[ty + 1][tx + 1]) {
     acc[4] = 1.0;
   } else {
+#pragma unroll
     for (int b = -1; b <= 1; ++b)
+#pragma unroll
       for (int a = -1; a <= 1; ++a) {
-        const int fi = 2 * I + a, fj = 2 * J + b;
-        const size_t fidx = (size_t)fj * nxf + fi;
-        if (dirf[fidx]) continue;
-        const double wf = pw(a) * pw(b);
-        double af[9];
-        opf.full(fidx, af);
+        const int wx = 2 * tx + 1 + a, wy = 2 * ty + 1 + b;  // fine node 2C + (a, b)
+#pragma unroll
         for (int q = -1; q <= 1; ++q)
+#pragma unroll
           for (int pp = -1; pp <= 1; ++pp) {
-            const int gi = fi + pp, gj = fj + q;
-            if (dirf[(size_t)gj * nxf + gi]) continue;
-            const double a_fg = af[(q + 1) * 3 + (pp + 1)];
-            for (int KJ = gj / 2; KJ <= (gj + 1) / 2; ++KJ)
-              for (int KI = gi / 2; KI <= (gi + 1) / 2; ++KI) {
-                const int oi = KI - I, oj = KJ - J;
-                if (dirc[(size_t)KJ * nxc + KI]) continue;
-                const double wg = pw(gi - 2 * KI) * pw(gj - 2 * KJ);
-                acc[(oj + 1) * 3 + (oi + 1)] += wf * a_fg * wg;
+            const double s = S[(q + 1) * 3 + pp + 1][wy][wx];
+            const int u = a + pp, v = b + q;  // neighbour 2C + (u, v)
+#pragma unroll
+            for (int oj = -1; oj <= 1; ++oj)
+#pragma unroll
+              for (int oi = -1; oi <= 1; ++oi) {
+                const int du = u - 2 * oi, dv = v - 2 * oj;
+                if (du >= -1 && du <= 1 && dv >= -1 && dv <= 1)
+                  acc[(oj + 1) * 3 + oi + 1] += (pw(a) * pw(b) * pw(du) * pw(dv)) * s;
               }
           }
       }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] *= 0.25;
+    for (int oj = -1; oj <= 1; ++oj)
+#pragma unroll
+      for (int oi = -1; oi <= 1; ++oi) {
+        double &v = acc[(oj + 1) * 3 + oi + 1];
+        v = DC[ty + 1 + oj][tx + 1 + oi] ? 0.0 : v * 0.25;
+      }
   }
 #pragma unroll
   for (int k = 0; k < 9; ++k) stc[k * nc + C] = acc[k];
+  if (stc32) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) stc32[k * nc + C] = (float)acc[k];
+  }
 }
 
 // Coarsest level: index map of the free nodes and the explicit inverse of
@@ -371,13 +442,6 @@ __global__ void k_coarse_inverse(const double *st, const uint8_t *dir, int nx, i
     __syncthreads();
   }
   for (int k = t; k < m * m; k += nt) inv[k] = B[k / m][k % m];
-}
-
-template <typename S, typename D>
-__global__ void k_convert(const S *a, D *b, size_t n) {
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)gridDim.x * blockDim.x)
-    b[c] = (D)a[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -778,9 +842,11 @@ EpsOp<double> op64(tomg_problem *p) {
 hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, const double *jac,
                         const double *epsp, const double *rho, const uint8_t *mask) {
   const int nx = p->cfg.nx, ny = p->cfg.ny;
+  const bool f32 = p->cfg.precision == TOMG_FP32_IR;
   hipLaunchKernelGGL(k_setup, kRedBlocks, kRedThreads, 0, p->stream, nx, ny, p->cfg.dx,
                      p->cfg.dy, xp, yp, jac, epsp, rho, mask, p->exx, p->exy, p->eyy, p->det,
-                     p->f, p->lv[0].dir, p->partials);
+                     p->f, p->lv[0].dir, f32 ? p->exx32 : nullptr, f32 ? p->exy32 : nullptr,
+                     f32 ? p->eyy32 : nullptr, p->partials);
   hipLaunchKernelGGL((k_finalize<1>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 2,
                      p->scal + kSlotMinDet, 0, p->scal, 0);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
@@ -798,35 +864,22 @@ hipError_t launch_update_rhs(tomg_problem *p, const double *rho) {
 }
 
 hipError_t launch_hierarchy(tomg_problem *p) {
-  const dim3 blk(16, 16);
+  const bool f32 = p->cfg.precision == TOMG_FP32_IR;
   for (int l = 1; l < p->L; ++l) {
     const tomg::Level &lf = p->lv[l - 1], &lc = p->lv[l];
-    hipLaunchKernelGGL(k_coarse_dir, grid2(lc.nx, lc.ny, blk), blk, 0, p->stream, lf.nx, lf.dir,
-                       lc.nx, lc.ny, lc.dir);
-    if (l == 1) {
-      hipLaunchKernelGGL((k_galerkin<EpsOp<double>>), grid2(lc.nx, lc.ny, blk), blk, 0,
-                         p->stream, op64(p), lf.dir, lf.nx, lc.nx, lc.ny, lc.dir, lc.st);
-    } else {
-      hipLaunchKernelGGL((k_galerkin<StOp<double>>), grid2(lc.nx, lc.ny, blk), blk, 0,
-                         p->stream, st_op<double>(lf.st, lf.nx, lf.ny), lf.dir, lf.nx, lc.nx,
-                         lc.ny, lc.dir, lc.st);
-    }
+    const dim3 grid((lc.nx + kGX - 1) / kGX, (lc.ny + kGY - 1) / kGY);
+    float *st32 = f32 ? lc.st32 : nullptr;
+    if (l == 1)
+      hipLaunchKernelGGL((k_coarsen<EpsOp<double>>), grid, kGX * kGY, 0, p->stream, op64(p),
+                         lf.dir, lf.nx, lf.ny, lc.nx, lc.ny, lc.dir, lc.st, st32);
+    else
+      hipLaunchKernelGGL((k_coarsen<StOp<double>>), grid, kGX * kGY, 0, p->stream,
+                         st_op<double>(lf.st, lf.nx, lf.ny), lf.dir, lf.nx, lf.ny, lc.nx, lc.ny,
+                         lc.dir, lc.st, st32);
   }
   const tomg::Level &lc = p->lv[p->L - 1];
   hipLaunchKernelGGL(k_coarse_inverse, 1, 256, 0, p->stream, lc.st, lc.dir, lc.nx, lc.ny,
                      p->cinv, p->cidx, p->scal);
-  if (p->cfg.precision == TOMG_FP32_IR) {
-    const size_t n0 = p->lv[0].n;
-    hipLaunchKernelGGL((k_convert<double, float>), grid1(n0), 256, 0, p->stream, p->exx, p->exx32,
-                       n0);
-    hipLaunchKernelGGL((k_convert<double, float>), grid1(n0), 256, 0, p->stream, p->exy, p->exy32,
-                       n0);
-    hipLaunchKernelGGL((k_convert<double, float>), grid1(n0), 256, 0, p->stream, p->eyy, p->eyy32,
-                       n0);
-    for (int l = 1; l < p->L; ++l)
-      hipLaunchKernelGGL((k_convert<double, float>), grid1(9 * p->lv[l].n), 256, 0, p->stream,
-                         p->lv[l].st, p->lv[l].st32, 9 * p->lv[l].n);
-  }
   return hipGetLastError();
 }
 
