@@ -19,7 +19,12 @@ Also measured in the same run (extra keys of the line):
   batch       : 256 independent sinusoidal-map problems of sides 65..1025
                 solved together by one tomg_solve_batch call (mixed
                 precision, and FP64 beside it), against solving them one
-                after another.
+                after another;
+  serving     : a stream of requests (sides 129..2049, perturbed-circle or
+                sinusoidal geometries, 30% warm re-solves of a resident
+                geometry with new sources) served by continuous batching:
+                capacity measured closed-loop, then Poisson arrivals at 0.5,
+                0.8 and 0.95 of it, with p50/p99 latency.
 """
 
 import argparse
@@ -220,6 +225,65 @@ def batch_leg(tomg, w, torch, dev, steps, warmup, count=256):
     return out
 
 
+def serving_leg(torch, dev, n_timed=2000, n_warm=200, loads=(0.5, 0.8, 0.95),
+                budget=64 << 30):
+    """Continuous-batching server on the serving stream (arrival seed 7).
+    Request inputs are evaluated on the device at admission (part of the
+    latency); latency = completion (host clock after the step that retired
+    the request) - arrival."""
+    import numpy as np
+
+    import workloads as w
+    from paper_2602_01888_amd import serve
+    from workloads import device as D
+    backend = serve.TomgBackend(precision="fp32_ir", device=dev)
+
+    def requests(rate, count):
+        return [serve.Request(**D.request_fields(d, dev))
+                for d in w.serving_stream(count, rate, seed=7)]
+
+    # closed loop: every request queued at once, capacity = completions / makespan
+    srv = serve.Server(backend, budget_bytes=budget)
+    reqs = requests(1.0, max(200, n_timed // 5))
+    for r in reqs:
+        srv.submit(r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = srv.drain()
+    cap = len(done) / (time.perf_counter() - t0)
+    bad = [c for c in done if not c.ok]
+    out = {"precision": "mixed (FP32 inner V(2,2) x2, FP64 refinement)",
+           "budget_GB": budget / 2 ** 30, "closed_loop_capacity_solves_per_s": cap,
+           "closed_loop_requests": len(done), "failed": len(bad), "loads": []}
+    log(f"[bench] serving: closed-loop capacity {cap:.0f} solves/s")
+    del srv
+    for f in loads:
+        rate = f * cap
+        srv = serve.Server(backend, budget_bytes=budget)
+        reqs = requests(rate, n_warm + n_timed)
+        dofs = {r.rid: r.nx * r.ny for r in reqs}
+        done = srv.run_open_loop(reqs)
+        timed = [c for c in done if c.rid >= n_warm]
+        lat = [c.latency for c in timed]
+        span = max(c.done for c in timed) - min(c.arrival for c in timed)
+        leg = {"load": f, "rate_per_s": rate, "requests": len(timed),
+               "p50_ms": serve.percentile(lat, 50) * 1e3,
+               "p99_ms": serve.percentile(lat, 99) * 1e3,
+               "mean_ms": float(np.mean(lat)) * 1e3,
+               "solves_per_s": len(timed) / span,
+               "dof_per_s": sum(dofs[c.rid] for c in timed) / span,
+               "warm_started": sum(c.warm_start for c in timed),
+               "failed": sum(not c.ok for c in done),
+               "max_cycles": max(c.cycles for c in timed),
+               "steps": srv.stats["steps"], "evicted": srv.stats["evicted"]}
+        out["loads"].append(leg)
+        log(f"[bench] serving at {f:.2f} x capacity: p50 {leg['p50_ms']:.1f} ms, "
+            f"p99 {leg['p99_ms']:.1f} ms, {leg['solves_per_s']:.0f} solves/s")
+        del srv
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -232,6 +296,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision and batch legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="timed requests per load level of the serving leg")
     ap.add_argument("--probe", action="store_true",
                     help="short run for counter collection: warmup + 2 solves + one copy probe")
     args = ap.parse_args()
@@ -393,6 +460,12 @@ def main():
     if not args.no_extras and not args.no_batch:
         batch = batch_leg(tomg, w, torch, dev, args.steps, args.warmup)
 
+    # --------------------------------------------------------- serving ----
+    serving = None
+    if not args.no_extras and not args.no_serving:
+        serving = serving_leg(torch, dev, n_timed=args.serve_requests,
+                              n_warm=max(20, args.serve_requests // 10))
+
     # ------------------------------------------------------ CPU oracle ----
     cpu = None
     accuracy = None
@@ -439,6 +512,7 @@ def main():
                        "dof_per_s": n0 / solve_only},
         "mixed": mixed,
         "batch": batch,
+        "serving": serving,
         "accuracy": accuracy,
         "roofline": roofline,
         "cpu_baseline": cpu,

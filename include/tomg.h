@@ -153,10 +153,29 @@ tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
  * outputs cycles_out[n], rel_out[n], status_out[n] (nullable).  Returns
  * TOMG_OK when every problem converged, else the first failing status.  The
  * per-problem arithmetic is the same as solve(), so each result is bitwise
- * equal to the problem solved alone. */
+ * equal to the problem solved alone.  1 <= n <= 4096.  Batched launches need
+ * one cycle configuration (precision, nu1, nu2, four-colour smoother,
+ * ir_inner_cycles); other mixes are solved one after another.  Work the
+ * caller queued for a problem on another stream must be ordered before the
+ * call (the batch runs on the stream of probs[0]). */
 tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, int32_t n,
                              double rel_tol, int32_t max_cycles, int32_t *cycles_out,
                              double *rel_out, tomg_status *status_out);
+
+/* One step of continuous batching (Section 3's V-cycle applied to a set of
+ * problems that may change between steps).  For every k with fresh[k] != 0
+ * the step only evaluates the initial norms: ||f - A phi0|| (phi0 = the
+ * Dirichlet values of d_phis[k] and zero elsewhere) and the residual of the
+ * iterate in d_phis[k].  Every other problem advances by one V-cycle
+ * (TOMG_FP64) or one refinement step (TOMG_FP32_IR), in the same batched
+ * launches as tomg_solve_batch.  rel_out[k] (host) receives each problem's
+ * relative residual after the step; the caller decides when a problem
+ * leaves.  A problem's sequence of steps gives bitwise the iterates of
+ * solve() whatever other problems share the steps.  All problems need one
+ * cycle configuration (else TOMG_EINVAL) and a completed setup_coeffs (else
+ * TOMG_ESTATE); runs on the stream of probs[0] and synchronises it. */
+tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,
+                            const int32_t *fresh, double *rel_out);
 
 /* ---- diagnostics: read back internal arrays (parity testing) ----------- */
 enum {

@@ -234,6 +234,24 @@ def solve_batch(problems: Sequence[Problem], phis: Sequence[torch.Tensor], rel_t
     return [SolveResult(sts[k], cyc[k], rel[k]) for k in range(n)]
 
 
+def batch_step(problems: Sequence[Problem], phis: Sequence[torch.Tensor], fresh: Sequence[bool]):
+    """tomg_batch_step: returns the relative residual of every problem after
+    the step (initial norms for fresh ones, one cycle for the others)."""
+    lib = _lib.load()
+    n = len(problems)
+    if n == 0:
+        return []
+    hs = (C.c_void_p * n)(*[p._h.value for p in problems])
+    ps = (C.c_void_p * n)(*[_ptr(t, torch.float64, (p.ny, p.nx), "phi").value
+                            for p, t in zip(problems, phis)])
+    fr = (C.c_int32 * n)(*[1 if f else 0 for f in fresh])
+    rel = (C.c_double * n)()
+    st = lib.tomg_batch_step(hs, ps, n, fr, rel)
+    if st != TOMG_OK:
+        raise TomgError(st, "tomg_batch_step")
+    return list(rel)
+
+
 def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None):
     """Device copy of src into dst with the library's STREAM-style kernel."""
     lib = _lib.load()

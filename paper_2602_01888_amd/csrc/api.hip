@@ -368,6 +368,82 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
 // the finest level, each problem taking part in the levels it has.  Each
 // problem runs exactly the blocks and reductions it runs alone, so its
 // result is bitwise that of solve().
+}  // extern "C"
+
+namespace {
+
+// Batched execution needs one configuration of the cycle for all problems.
+bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
+  const tomg_problem *lead = probs[0];
+  if (!lead) return false;
+  for (int k = 0; k < n; ++k) {
+    const tomg_problem *p = probs[k];
+    if (!p || !d_phis[k] || !p->ready) return false;
+    if (p->cfg.precision != lead->cfg.precision || p->cfg.nu1 != lead->cfg.nu1 ||
+        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 ||
+        p->cfg.ir_inner_cycles != lead->cfg.ir_inner_cycles)
+      return false;
+  }
+  return true;
+}
+
+// Initial norms of the problems idx[0..cnt): |b| from the zero interior
+// start and the residual of the given iterate; relative residuals to out[q].
+void batch_begin(tomg_problem *const *probs, const int *idx, int cnt, double *const *d_phis,
+                 bool ir, double *out, hipStream_t s) {
+  batch_resnorm(probs, idx, cnt, true, d_phis, s);
+  batch_finalize(probs, idx, cnt, 0, kSlotB0, false, out, s);
+  if (ir)
+    batch_ir_residual(probs, idx, cnt, d_phis, s);
+  else
+    batch_resnorm(probs, idx, cnt, false, d_phis, s);
+  batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s);
+}
+
+// One V-cycle (FP64) or one refinement step (FP32 inner cycles) of the
+// problems idx[0..cnt), then their residuals; relative residuals to out[q].
+// Each stage is one launch over all problems that have that level above
+// their single-workgroup tail.
+void batch_cycle(tomg_problem *const *probs, const int *idx, int cnt, double *const *d_phis,
+                 bool ir, int inner, double *out, hipStream_t s) {
+  int maxlc = 0;
+  for (int q = 0; q < cnt; ++q) maxlc = std::max(maxlc, probs[idx[q]]->lc);
+  std::vector<int> lvl;
+  auto participants = [&](int l) {
+    lvl.clear();
+    for (int q = 0; q < cnt; ++q)
+      if (l < probs[idx[q]]->lc) lvl.push_back(idx[q]);
+    return (int)lvl.size();
+  };
+  for (int it = 0; it < (ir ? inner : 1); ++it) {
+    for (int l = 0; l < maxlc; ++l)
+      if (participants(l))
+        batch_down(probs, lvl.data(), (int)lvl.size(), l, ir, ir && it == 0, d_phis, s);
+    batch_tail(probs, idx, cnt, ir, s);
+    for (int l = maxlc - 1; l >= 0; --l)
+      if (participants(l)) batch_up(probs, lvl.data(), (int)lvl.size(), l, ir, !ir, d_phis, s);
+  }
+  if (ir) {
+    batch_ir_update(probs, idx, cnt, d_phis, s);
+    batch_ir_residual(probs, idx, cnt, d_phis, s);
+    batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s);
+  } else {
+    batch_finalize(probs, idx, cnt, 1, kSlotRes, true, out, s);
+  }
+}
+
+bool read_back(double *host, const double *dev, int cnt, hipStream_t s) {
+  if (cnt == 0) return true;
+  if (hipGetLastError() != hipSuccess) return false;
+  if (hipMemcpyAsync(host, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return false;
+  return hipStreamSynchronize(s) == hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
 tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, int32_t n,
                              double rel_tol, int32_t max_cycles, int32_t *cycles_out,
                              double *rel_out, tomg_status *status_out) {
@@ -377,16 +453,7 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
   std::vector<tomg_status> st(n, TOMG_OK);
   std::vector<int> cyc(n, 0);
   std::vector<double> rel(n, 0.0);
-  tomg_problem *lead = probs[0];
-  bool uniform = lead != nullptr;
-  for (int k = 0; k < n && uniform; ++k) {
-    tomg_problem *p = probs[k];
-    if (!p || !d_phis[k] || !p->ready) { uniform = false; break; }
-    uniform = p->cfg.precision == lead->cfg.precision && p->cfg.nu1 == lead->cfg.nu1 &&
-              p->cfg.nu2 == lead->cfg.nu2 && p->cfg.smoother == TOMG_GS4 &&
-              p->cfg.ir_inner_cycles == lead->cfg.ir_inner_cycles;
-  }
-  if (!uniform) {
+  if (!batch_uniform(probs, d_phis, n)) {
     // mixed configurations: solve one after another
     tomg_status first = TOMG_OK;
     for (int k = 0; k < n; ++k) {
@@ -401,31 +468,15 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
     }
     return first;
   }
+  tomg_problem *lead = probs[0];
   hipStream_t s = lead->stream;
   const bool ir = lead->cfg.precision == TOMG_FP32_IR;
   std::vector<int> act(n);
   for (int k = 0; k < n; ++k) act[k] = k;
   std::vector<double> hrel(n);
-  auto read_rel = [&](int cnt) -> bool {
-    if (hipMemcpyAsync(hrel.data(), lead->bout, cnt * sizeof(double), hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-      return false;
-    return hipStreamSynchronize(s) == hipSuccess;
-  };
-  const int *A = act.data();
   int na = n;
-  batch_resnorm(probs, A, na, true, d_phis, s);
-  batch_finalize(probs, A, na, 0, kSlotB0, false, lead->bout, s);
-  if (ir) {
-    batch_ir_residual(probs, A, na, d_phis, s);
-  } else {
-    batch_resnorm(probs, A, na, false, d_phis, s);
-  }
-  batch_finalize(probs, A, na, 0, kSlotRes, true, lead->bout, s);
-  if (hipGetLastError() != hipSuccess || !read_rel(na)) return TOMG_EDEVICE;
-  int maxlc = 0;
-  for (int k = 0; k < n; ++k) maxlc = std::max(maxlc, probs[k]->lc);
-  std::vector<int> lvl;
+  batch_begin(probs, act.data(), na, d_phis, ir, lead->bout, s);
+  if (!read_back(hrel.data(), lead->bout, na, s)) return TOMG_EDEVICE;
   while (true) {
     // retire finished problems
     int w = 0;
@@ -445,31 +496,9 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
     }
     na = w;
     if (na == 0) break;
-    A = act.data();
-    auto participants = [&](int l) {  // active problems with level l above their tail
-      lvl.clear();
-      for (int q = 0; q < na; ++q)
-        if (l < probs[act[q]]->lc) lvl.push_back(act[q]);
-      return (int)lvl.size();
-    };
-    const int inner = ir ? lead->cfg.ir_inner_cycles : 1;
-    for (int it = 0; it < inner; ++it) {
-      for (int l = 0; l < maxlc; ++l)
-        if (participants(l)) batch_down(probs, lvl.data(), (int)lvl.size(), l, ir, ir && it == 0,
-                                        d_phis, s);
-      batch_tail(probs, A, na, ir, s);
-      for (int l = maxlc - 1; l >= 0; --l)
-        if (participants(l)) batch_up(probs, lvl.data(), (int)lvl.size(), l, ir, !ir, d_phis, s);
-    }
-    if (ir) {
-      batch_ir_update(probs, A, na, d_phis, s);
-      batch_ir_residual(probs, A, na, d_phis, s);
-      batch_finalize(probs, A, na, 0, kSlotRes, true, lead->bout, s);
-    } else {
-      batch_finalize(probs, A, na, 1, kSlotRes, true, lead->bout, s);
-    }
+    batch_cycle(probs, act.data(), na, d_phis, ir, lead->cfg.ir_inner_cycles, lead->bout, s);
     for (int q = 0; q < na; ++q) ++cyc[act[q]];
-    if (hipGetLastError() != hipSuccess || !read_rel(na)) return TOMG_EDEVICE;
+    if (!read_back(hrel.data(), lead->bout, na, s)) return TOMG_EDEVICE;
   }
   tomg_status first = TOMG_OK;
   for (int k = 0; k < n; ++k) {
@@ -481,6 +510,31 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
     if (st[k] != TOMG_OK && first == TOMG_OK) first = st[k];
   }
   return first;
+}
+
+tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,
+                            const int32_t *fresh, double *rel_out) {
+  if (!probs || !d_phis || !fresh || !rel_out || n < 0 || n > kMaxBatch) return TOMG_EINVAL;
+  if (n == 0) return TOMG_OK;
+  if (!batch_uniform(probs, d_phis, n)) {
+    for (int k = 0; k < n; ++k)
+      if (probs[k] && !probs[k]->ready) return fail(probs[k], TOMG_ESTATE, "batch_step before setup_coeffs");
+    return TOMG_EINVAL;
+  }
+  tomg_problem *lead = probs[0];
+  hipStream_t s = lead->stream;
+  const bool ir = lead->cfg.precision == TOMG_FP32_IR;
+  std::vector<int> fr, cy;
+  for (int k = 0; k < n; ++k) (fresh[k] ? fr : cy).push_back(k);
+  const int nf = (int)fr.size(), nc = (int)cy.size();
+  if (nf) batch_begin(probs, fr.data(), nf, d_phis, ir, lead->bout, s);
+  if (nc)
+    batch_cycle(probs, cy.data(), nc, d_phis, ir, lead->cfg.ir_inner_cycles, lead->bout + nf, s);
+  std::vector<double> h(n);
+  if (!read_back(h.data(), lead->bout, n, s)) return TOMG_EDEVICE;
+  for (int q = 0; q < nf; ++q) rel_out[fr[q]] = h[q];
+  for (int q = 0; q < nc; ++q) rel_out[cy[q]] = h[nf + q];
+  return TOMG_OK;
 }
 
 tomg_status tomg_level_shape(const tomg_problem *p, int32_t level, int32_t *nx, int32_t *ny) {

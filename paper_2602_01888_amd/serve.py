@@ -1,0 +1,333 @@
+"""Continuous-batching solve server on one GPU.
+
+Requests (a grid, a geometry, a source) arrive over time.  The server keeps
+the set of problems being solved on the device and advances all of them
+together, one V-cycle (or refinement step) per ``tomg_batch_step``; between
+two steps it retires problems that reached the tolerance and admits queued
+requests, so a request that arrives while others are being solved joins the
+next step instead of waiting for the batch to drain.
+
+Memory.  Every geometry the server holds (being solved, or idle and kept for
+a later warm re-solve) costs its library workspace plus its solution array;
+a request is admitted only if that footprint, plus the transient input
+arrays of its setup, fits in the budget after idle geometries have been
+evicted, least recently used first.  Admission is first-come first-served:
+a request that does not fit stops admission (later requests do not overtake
+it), except that a request whose geometry is still being solved is passed
+over until that solve ends.
+
+Warm re-solves.  A request marked warm whose geometry is resident and idle
+skips the coefficient setup and the hierarchy build: only the right-hand
+side is recomputed (``tomg_update_rhs``), and the iteration starts from the
+geometry's last solution.  If the geometry has been evicted the request is
+served cold.
+
+The arithmetic of each problem does not depend on the others in the batch or
+on when it joined: a request's result is bitwise the result of solving it
+alone from the same initial guess.
+
+The server is host logic only; every solver step runs in the library's
+kernels through the backend (``TomgBackend``).
+"""
+
+from __future__ import annotations
+
+import math
+import time
+from collections import OrderedDict, deque
+from dataclasses import dataclass, field
+from typing import Callable, Hashable, List, Optional
+
+TOMG_OK, TOMG_ENOCONV, TOMG_ENONFINITE = 0, -4, -5
+
+
+@dataclass
+class Request:
+    """One solve request.
+
+    ``geometry()`` returns the device arrays of the map (dict with xp, yp,
+    jac, mask, phi0; None where absent) and ``source()`` the charge density
+    rho' at the nodes; both are called only when needed (cold start, or a new
+    right-hand side).  ``geom`` identifies the geometry: a warm request with
+    the key of a resident geometry re-uses its hierarchy and last solution."""
+    rid: int
+    geom: Hashable
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    geometry: Callable[[], dict]
+    source: Callable[[], object]
+    warm: bool = False
+    arrival: float = 0.0
+    xi0: float = 0.0
+    eta0: float = 0.0
+
+
+@dataclass
+class Completion:
+    rid: int
+    status: int
+    cycles: int
+    rel: float
+    arrival: float
+    admitted: float
+    done: float
+    warm_start: bool          # started from a resident geometry's last solution
+    phi: object = None        # copy of the solution (keep_results=True)
+    phi_start: object = None  # copy of the initial guess (keep_results=True)
+    error: str = ""           # why a request failed before its first step
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+    @property
+    def ok(self):
+        return self.status == TOMG_OK
+
+
+@dataclass
+class _Resident:
+    key: Hashable
+    problem: object
+    phi: object
+    nbytes: int
+    busy: bool = False
+
+
+@dataclass
+class _Active:
+    req: Request
+    res: _Resident
+    admitted: float
+    warm_start: bool
+    fresh: bool = True
+    cycles: int = 0
+    rel: float = math.inf
+    phi_start: object = None
+
+
+class TomgBackend:
+    """The library as seen by the server: problem creation and setup, warm
+    right-hand-side updates and the batched step."""
+
+    def __init__(self, precision="fp32_ir", nu1=2, nu2=2, ir_inner_cycles=2, device=None):
+        import torch
+
+        import paper_2602_01888_amd as tomg
+        self.tomg, self.torch = tomg, torch
+        self.kw = dict(precision=precision, nu1=nu1, nu2=nu2, ir_inner_cycles=ir_inner_cycles)
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+
+    def footprint(self, req: Request) -> int:
+        cfg = self.tomg.make_config(req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0, **self.kw)
+        return self.tomg.workspace_bytes(cfg) + 8 * req.nx * req.ny
+
+    def transient(self, req: Request) -> int:
+        # coordinates, analytic partials or mask, initial guess and source
+        return 8 * req.nx * req.ny * 8
+
+    def create(self, req: Request):
+        """New problem with coefficients set up; returns (problem, phi)."""
+        p = self.tomg.Problem(req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0,
+                              device=self.device, **self.kw)
+        g = req.geometry()
+        rho = req.source()
+        if g.get("jac") is not None:
+            p.setup_coeffs(rho, jac=g["jac"], mask=g.get("mask"))
+        else:
+            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g.get("mask"))
+        return p, g["phi0"].clone()
+
+    def new_source(self, problem, req: Request):
+        problem.update_rhs(req.source())
+
+    def step(self, problems, phis, fresh):
+        return self.tomg.batch_step(problems, phis, fresh)
+
+    def copy(self, phi):
+        return phi.clone()
+
+
+class Server:
+    def __init__(self, backend, budget_bytes: int = 64 << 30, rel_tol: float = 1e-10,
+                 max_cycles: int = 100, max_active: int = 256, keep_results: bool = False,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.rel_tol = rel_tol
+        self.max_cycles = max_cycles
+        self.max_active = max_active
+        self.keep = keep_results
+        self.clock = clock
+        self.queue: deque = deque()
+        self.active: List[_Active] = []
+        self.resident: "OrderedDict[Hashable, _Resident]" = OrderedDict()  # LRU order
+        self.used = 0
+        self.stats = {"admitted": 0, "warm": 0, "cold": 0, "evicted": 0, "steps": 0,
+                      "rejected": 0}
+
+    # -- queue ------------------------------------------------------------
+    def submit(self, req: Request):
+        self.queue.append(req)
+
+    @property
+    def idle(self):
+        return not self.active and not self.queue
+
+    # -- memory -----------------------------------------------------------
+    def _evict_for(self, need: int) -> bool:
+        """Evicts idle geometries (least recently used first) until `need`
+        more bytes fit; False if they cannot be made to fit."""
+        if self.used + need <= self.budget:
+            return True
+        idle = [r for r in self.resident.values() if not r.busy]
+        free = sum(r.nbytes for r in idle)
+        if self.used - free + need > self.budget:
+            return False
+        for r in idle:
+            if self.used + need <= self.budget:
+                break
+            self._drop(r)
+            self.stats["evicted"] += 1
+        return True
+
+    def _drop(self, r: _Resident):
+        del self.resident[r.key]
+        self.used -= r.nbytes
+        r.problem = r.phi = None
+
+    # -- admission ---------------------------------------------------------
+    def _admit(self, now: float, done: list):
+        passed = deque()
+        while self.queue and len(self.active) < self.max_active:
+            req = self.queue.popleft()
+            res = self.resident.get(req.geom)
+            if res is not None and res.busy:
+                passed.append(req)  # its geometry is being solved: try again later
+                continue
+            if req.warm and res is not None:
+                self.resident.move_to_end(req.geom)
+                res.busy = True
+                try:
+                    self.backend.new_source(res.problem, req)
+                except Exception as e:  # a failed update leaves the geometry usable
+                    res.busy = False
+                    done.append(self._failed(req, now, e))
+                    continue
+                act = _Active(req, res, now, warm_start=True)
+                self.stats["warm"] += 1
+            else:
+                if res is not None:  # a cold request rebuilds its geometry
+                    self._drop(res)
+                need = self.backend.footprint(req)
+                if need + self.backend.transient(req) > self.budget:
+                    done.append(self._failed(req, now, MemoryError(
+                        f"request needs {need} bytes, budget {self.budget}")))
+                    self.stats["rejected"] += 1
+                    continue
+                if not self._evict_for(need + self.backend.transient(req)):
+                    self.queue.appendleft(req)  # first come, first served: wait
+                    break
+                try:
+                    prob, phi = self.backend.create(req)
+                except Exception as e:
+                    done.append(self._failed(req, now, e))
+                    continue
+                res = _Resident(req.geom, prob, phi, need, busy=True)
+                self.resident[req.geom] = res
+                self.used += need
+                act = _Active(req, res, now, warm_start=False)
+                self.stats["cold"] += 1
+            if self.keep:
+                act.phi_start = self.backend.copy(res.phi)
+            self.active.append(act)
+            self.stats["admitted"] += 1
+        while passed:
+            self.queue.appendleft(passed.pop())
+
+    def _failed(self, req, now, exc):
+        status = getattr(exc, "status", -1)
+        return Completion(req.rid, status, 0, math.nan, req.arrival, now, now, False,
+                          error=str(exc))
+
+    # -- one step ------------------------------------------------------------
+    def step(self) -> List[Completion]:
+        """Admits what fits, advances every active problem by one step and
+        returns the requests that completed."""
+        done: List[Completion] = []
+        self._admit(self.clock(), done)
+        if not self.active:
+            return done
+        acts = self.active
+        rels = self.backend.step([a.res.problem for a in acts], [a.res.phi for a in acts],
+                                 [a.fresh for a in acts])
+        t = self.clock()
+        self.stats["steps"] += 1
+        keep = []
+        for a, r in zip(acts, rels):
+            if a.fresh:
+                a.fresh = False
+            else:
+                a.cycles += 1
+            a.rel = r
+            if not math.isfinite(r):
+                st = TOMG_ENONFINITE
+            elif r <= self.rel_tol:
+                st = TOMG_OK
+            elif a.cycles >= self.max_cycles:
+                st = TOMG_ENOCONV
+            else:
+                keep.append(a)
+                continue
+            a.res.busy = False
+            self.resident.move_to_end(a.res.key)
+            c = Completion(a.req.rid, st, a.cycles, r, a.req.arrival, a.admitted, t,
+                           a.warm_start)
+            if self.keep:
+                c.phi = self.backend.copy(a.res.phi)
+                c.phi_start = a.phi_start
+            done.append(c)
+        self.active = keep
+        return done
+
+    # -- drivers ---------------------------------------------------------------
+    def drain(self) -> List[Completion]:
+        """Steps until every submitted request has completed."""
+        out = []
+        while not self.idle:
+            out += self.step()
+        return out
+
+    def run_open_loop(self, requests: List[Request], t0: Optional[float] = None,
+                      sleep=time.sleep) -> List[Completion]:
+        """Submits each request when the clock passes t0 + request.arrival
+        (requests sorted by arrival) and steps until all have completed;
+        completion times and arrivals are reported on the same clock."""
+        t0 = self.clock() if t0 is None else t0
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        for r in pending:
+            r.arrival = t0 + r.arrival
+        out = []
+        total = len(pending)
+        while len(out) < total:
+            now = self.clock()
+            while pending and pending[0].arrival <= now:
+                self.submit(pending.popleft())
+            if self.idle:
+                if pending:
+                    sleep(max(0.0, pending[0].arrival - self.clock()))
+                continue
+            out += self.step()
+        return out
+
+
+def percentile(xs, q):
+    """q-th percentile (0..100) by linear interpolation between order statistics."""
+    s = sorted(xs)
+    if not s:
+        return math.nan
+    k = (len(s) - 1) * q / 100.0
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)

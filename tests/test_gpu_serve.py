@@ -1,0 +1,80 @@
+"""Continuous batching on the GPU: requests of different sizes and
+geometries, cold and warm, admitted while others are being solved.  Each
+result must be bitwise the result of solving the same request alone from the
+same initial guess, and meet the tolerance by the oracle's residual."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_01888_amd as tomg
+    from paper_2602_01888_amd import serve
+    from workloads import device as D
+    return torch, tomg, serve, D
+
+
+def stream(D, serve, count, sides):
+    descs = w.serving_stream(count, rate=1000.0, seed=11, sides=sides)
+    return [serve.Request(**D.request_fields(d, "cuda")) for d in descs], descs
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir", "fp64"])
+def test_served_results_equal_alone(env, precision):
+    torch, tomg, serve, D = env
+    reqs, descs = stream(D, serve, 20, (65, 129, 257, 513))
+    print(f"[serve] {len(reqs)} requests {precision}, "
+          f"{sum(d['warm'] for d in descs)} warm", flush=True)
+    srv = serve.Server(serve.TomgBackend(precision=precision), budget_bytes=8 << 30,
+                       max_active=6, keep_results=True)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.drain()
+    assert len(done) == len(reqs) and all(c.ok for c in done), [c for c in done if not c.ok]
+    assert srv.stats["warm"] > 0 and srv.stats["steps"] > 0
+    by = {r.rid: r for r in reqs}
+    for c in done:
+        r = by[c.rid]
+        g = r.geometry()
+        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, precision=precision)
+        rho = r.source()
+        if g["jac"] is not None:
+            p.setup_coeffs(rho, jac=g["jac"], mask=g["mask"])
+        else:
+            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g["mask"])
+        phi = c.phi_start.clone()
+        ra = p.solve(phi, rel_tol=1e-10, max_cycles=100)
+        assert ra.cycles == c.cycles, (c.rid, ra, c)
+        assert bool((phi == c.phi).all()), c.rid
+
+
+def test_served_results_meet_tolerance_by_oracle(env):
+    torch, tomg, serve, D = env
+    reqs, descs = stream(D, serve, 8, (65, 129))
+    srv = serve.Server(serve.TomgBackend(), budget_bytes=1 << 30, max_active=4,
+                       keep_results=True)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.drain()
+    by = {r.rid: r for r in reqs}
+    for c in done:
+        assert c.ok
+        r = by[c.rid]
+        g = {k: (None if v is None else v.cpu().numpy()) for k, v in r.geometry().items()}
+        q = w.GridProblem("served", r.nx, r.ny, 0.0, 0.0, r.dx, r.dy, g["xp"], g["yp"],
+                          r.source().cpu().numpy(), g["phi0"], jac=g["jac"], mask=g["mask"])
+        s = oracle.setup(q)
+        st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], q.dx, q.dy, s["dir"])
+        b0 = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], q.phi0, s["f"]))
+        rel = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], c.phi.cpu().numpy(),
+                                                          s["f"])) / b0
+        assert rel <= 1e-10 * (1 + 1e-3), (c.rid, rel, c.rel)

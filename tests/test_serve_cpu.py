@@ -1,0 +1,235 @@
+"""Host logic of the continuous-batching server (admission, memory budget,
+eviction, warm re-solves, retirement, latency) with a fake backend: no GPU,
+no solver arithmetic.  The fake problem's relative residual falls by a
+fixed factor per step, so cycle counts are known in advance."""
+
+import math
+
+import pytest
+
+from paper_2602_01888_amd import serve as S
+
+
+class FakeProblem:
+    def __init__(self, req, rate):
+        self.req = req
+        self.rate = rate
+        self.rhs_updates = 0
+
+
+class FakeBackend:
+    def __init__(self, rate=0.1, bytes_per_node=10, fail_on=()):
+        self.rate = rate
+        self.bpn = bytes_per_node
+        self.created = []
+        self.steps = []
+        self.fail_on = set(fail_on)
+
+    def footprint(self, req):
+        return self.bpn * req.nx * req.ny
+
+    def transient(self, req):
+        return 0
+
+    def create(self, req):
+        if req.rid in self.fail_on:
+            raise RuntimeError("bad geometry")
+        self.created.append(req.rid)
+        p = FakeProblem(req, self.rate)
+        return p, {"rel": 1.0}
+
+    def new_source(self, problem, req):
+        problem.rhs_updates += 1
+
+    def step(self, problems, phis, fresh):
+        self.steps.append([p.req.rid for p in problems])
+        out = []
+        for p, phi, f in zip(problems, phis, fresh):
+            if f:
+                phi["rel0"] = phi["rel"]
+            else:
+                phi["rel"] *= p.rate
+            out.append(phi["rel"])
+        return out
+
+    def copy(self, phi):
+        return dict(phi)
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1.0
+        return self.t
+
+
+def req(rid, n=10, geom=None, warm=False, arrival=0.0):
+    return S.Request(rid, geom if geom is not None else f"g{rid}", n, n, 0.1, 0.1,
+                     geometry=lambda: {}, source=lambda: None, warm=warm, arrival=arrival)
+
+
+def test_cycles_and_completion_order():
+    be = FakeBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    s.submit(req(0))
+    s.submit(req(1))
+    done = s.drain()
+    # first step evaluates norms only, then 3 cycles: 1e-1, 1e-2, 1e-3
+    assert [c.rid for c in done] == [0, 1]
+    assert all(c.ok and c.cycles == 3 for c in done)
+    assert len(be.steps) == 4 and be.steps[0] == [0, 1]
+
+
+def test_late_arrival_joins_next_step():
+    be = FakeBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    s.submit(req(0))
+    s.step()
+    s.step()
+    s.submit(req(1))
+    s.step()
+    assert be.steps[-1] == [0, 1]  # admitted while 0 is still iterating
+
+
+def test_memory_budget_is_first_come_first_served():
+    be = FakeBackend(rate=0.1, bytes_per_node=10)
+    # budget fits two 10x10 problems (1000 B each) but not three
+    s = S.Server(be, budget_bytes=2500, rel_tol=2e-3, clock=Clock())
+    for k in range(3):
+        s.submit(req(k))
+    s.step()
+    assert be.steps[0] == [0, 1]
+    assert [r.rid for r in s.queue] == [2]
+    done = s.drain()
+    assert sorted(c.rid for c in done) == [0, 1, 2]
+    assert s.stats["evicted"] >= 1  # an idle geometry made room for request 2
+    assert s.used <= 2500
+
+
+def test_no_overtaking_when_head_does_not_fit():
+    be = FakeBackend(rate=0.1, bytes_per_node=10)
+    s = S.Server(be, budget_bytes=2500, rel_tol=2e-3, clock=Clock())
+    s.submit(req(0, n=10))   # 1000 B
+    s.submit(req(1, n=14))   # 1960 B: does not fit beside 0
+    s.submit(req(2, n=5))    # 250 B: would fit, but must not overtake 1
+    s.step()
+    assert be.steps[0] == [0]
+    assert [r.rid for r in s.queue] == [1, 2]
+
+
+def test_request_larger_than_budget_is_rejected():
+    be = FakeBackend(bytes_per_node=10)
+    s = S.Server(be, budget_bytes=500, clock=Clock())
+    s.submit(req(0, n=10))
+    (c,) = s.step()
+    assert not c.ok and "budget" in c.error
+    assert s.idle
+
+
+def test_warm_request_reuses_resident_geometry():
+    be = FakeBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    s.submit(req(0, geom="A"))
+    (c0,) = s.drain()
+    s.submit(req(1, geom="A", warm=True))
+    (c1,) = s.drain()
+    assert be.created == [0]                 # no second setup
+    assert c1.warm_start and not c0.warm_start
+    assert s.resident["A"].problem.rhs_updates == 1
+    # warm start from the last solution: already below tolerance after the norms
+    assert c1.cycles == 0 and c1.ok
+
+
+def test_warm_request_after_eviction_is_served_cold():
+    be = FakeBackend(rate=0.1, bytes_per_node=10)
+    s = S.Server(be, budget_bytes=1500, rel_tol=2e-3, clock=Clock())
+    s.submit(req(0, geom="A"))
+    s.drain()
+    s.submit(req(1, geom="B"))  # evicts A
+    s.drain()
+    s.submit(req(2, geom="A", warm=True))
+    (c,) = s.drain()
+    assert not c.warm_start and be.created == [0, 1, 2]
+
+
+def test_busy_geometry_is_passed_over_not_blocking():
+    be = FakeBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    s.submit(req(0, geom="A"))
+    s.step()
+    s.submit(req(1, geom="A", warm=True))  # A is busy
+    s.submit(req(2, geom="B"))
+    s.step()
+    assert be.steps[-1] == [0, 2]
+    assert [r.rid for r in s.queue] == [1]
+    done = s.drain()
+    assert sorted(c.rid for c in done) == [0, 1, 2]
+
+
+def test_nonconvergence_and_nonfinite():
+    be = FakeBackend(rate=0.5)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=1e-9, max_cycles=5, clock=Clock())
+    s.submit(req(0))
+    (c,) = s.drain()
+    assert c.status == S.TOMG_ENOCONV and c.cycles == 5
+
+    class NanBackend(FakeBackend):
+        def step(self, problems, phis, fresh):
+            return [math.nan for _ in problems]
+    s = S.Server(NanBackend(), budget_bytes=10 ** 6, clock=Clock())
+    s.submit(req(1))
+    (c,) = s.drain()
+    assert c.status == S.TOMG_ENONFINITE
+
+
+def test_failed_setup_is_reported_and_others_continue():
+    be = FakeBackend(rate=0.1, fail_on={1})
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    for k in range(3):
+        s.submit(req(k))
+    done = s.drain()
+    by = {c.rid: c for c in done}
+    assert not by[1].ok and "bad geometry" in by[1].error
+    assert by[0].ok and by[2].ok
+
+
+def test_max_active():
+    be = FakeBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, max_active=2, clock=Clock())
+    for k in range(5):
+        s.submit(req(k))
+    s.step()
+    assert len(be.steps[0]) == 2
+    assert len(s.drain()) == 5
+
+
+def test_open_loop_latency():
+    class T:
+        t = 0.0
+    t = T()
+
+    def clock():
+        return t.t
+
+    def sleep(dt):
+        t.t += dt
+
+    class TimedBackend(FakeBackend):
+        def step(self, problems, phis, fresh):
+            t.t += 0.01  # every step takes 10 ms
+            return super().step(problems, phis, fresh)
+
+    s = S.Server(TimedBackend(rate=0.1), budget_bytes=10 ** 6, rel_tol=2e-3, clock=clock)
+    reqs = [req(0, arrival=0.0), req(1, arrival=1.0)]
+    done = s.run_open_loop(reqs, t0=0.0, sleep=sleep)
+    lat = {c.rid: c.latency for c in done}
+    # four steps of 10 ms each (norms + 3 cycles), no queueing
+    assert lat[0] == pytest.approx(0.04) and lat[1] == pytest.approx(0.04)
+
+
+def test_percentile():
+    xs = list(range(101))
+    assert S.percentile(xs, 50) == 50 and S.percentile(xs, 99) == 99
+    assert S.percentile([1.0, 2.0], 50) == 1.5

@@ -1,0 +1,128 @@
+"""Serving-workload inputs evaluated on the GPU with torch (float64).
+
+A serving request names a geometry (kind, side, geometry seed) and a source
+seed.  Its parameters are drawn on the host with the same draws, in the same
+order, as ``gen.perturbed_circle`` and ``gen.random_sinusoidal``; the node
+arrays (coordinates, analytic partials, mask, Dirichlet data, charge
+density) are then evaluated on the device, so that a request needs no
+host-to-device copy of its arrays.  Up to rounding of the elementary
+functions these are the arrays the numpy generators build.  Like the rest of
+this package it holds none of the solver's arithmetic.
+
+Request semantics:
+  * cold request: geometry and sources from default_rng(geometry seed), as
+    ``gen.perturbed_circle(side, seed)`` (8 sources) or
+    ``gen.random_sinusoidal(side, seed)`` (4 sources);
+  * warm request: the geometry of an earlier request, with sources drawn
+    from default_rng(source seed): ``draw_circle_sources`` for a circle,
+    ``draw_box_sources`` for a sinusoidal map.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from .gen import draw_box_sources, draw_circle, draw_circle_sources, draw_sinusoidal
+
+SIGMA = 0.02
+
+
+def _grid(n, device):
+    d = 1.0 / (n - 1)
+    v = torch.arange(n, dtype=torch.float64, device=device) * d
+    ETA, XI = torch.meshgrid(v, v, indexing="ij")  # (ny, nx), XI varies along axis 1
+    return XI, ETA, d
+
+
+def geometry_params(kind, geom_seed):
+    """Host-side draws of a cold request: (map parameters, amps, centres)."""
+    rng = np.random.default_rng(geom_seed)
+    if kind == "circle":
+        acoef = draw_circle(rng)
+        amps, centres = draw_circle_sources(rng, acoef, 8)
+        return {"acoef": acoef}, amps, np.asarray(centres)
+    amp, amps, centres = draw_sinusoidal(rng, 4, 0.15)
+    return {"amp": amp}, amps, np.asarray(centres)
+
+
+def source_params(kind, map_params, source_seed):
+    """Host-side draws of a warm request's sources."""
+    rng = np.random.default_rng(source_seed)
+    if kind == "circle":
+        amps, centres = draw_circle_sources(rng, map_params["acoef"], 8)
+        return amps, np.asarray(centres)
+    amps, centres = draw_box_sources(rng, 4)
+    return amps, np.asarray(centres)
+
+
+def circle_geometry(n, acoef, device):
+    """Perturbed-circle conductor map (see ``gen.perturbed_circle``):
+    dict(xp, yp, mask, phi0)."""
+    XI, ETA, d = _grid(n, device)
+    ux, uy = XI - 0.5, ETA - 0.5
+    r = torch.hypot(ux, uy)
+    th = torch.atan2(uy, ux)
+    R = torch.full_like(th, 0.2)
+    for k, a in zip(range(2, 6), acoef):
+        R = R + 0.03 * float(a) * torch.cos(k * th)
+    inner = (r >= 0.15) & (r <= 0.2)
+    outer = (r > 0.2) & (r <= 0.35)
+    rp = torch.where(inner, 0.15 + (r - 0.15) * (R - 0.15) / 0.05, r)
+    rp = torch.where(outer, R + (r - 0.2) * (0.35 - R) / 0.15, rp)
+    xp = (0.5 + rp * torch.cos(th)).contiguous()
+    yp = (0.5 + rp * torch.sin(th)).contiguous()
+    cond = r <= 0.2
+    return {"xp": xp, "yp": yp, "jac": None, "mask": cond.to(torch.uint8).contiguous(),
+            "phi0": cond.to(torch.float64).contiguous()}
+
+
+def sinusoidal_geometry(n, amp, device):
+    """Sinusoidal map with analytic partials (see ``gen.sinusoidal_map``):
+    dict(xp, yp, jac, phi0)."""
+    XI, ETA, d = _grid(n, device)
+    sx, sy = torch.sin(math.pi * XI), torch.sin(math.pi * ETA)
+    s = sx * sy
+    a = amp * math.pi * torch.cos(math.pi * XI) * sy
+    b = amp * math.pi * sx * torch.cos(math.pi * ETA)
+    jac = torch.stack([1.0 + a, b, a, 1.0 + b]).contiguous()
+    return {"xp": (XI + amp * s).contiguous(), "yp": (ETA + amp * s).contiguous(), "jac": jac,
+            "mask": None, "phi0": torch.zeros_like(XI)}
+
+
+def gaussian_rho(xp, yp, amps, centres, sigma=SIGMA):
+    """rho'(x') = sum_m A_m exp(-|x' - c_m|^2 / (2 sigma^2)) on the device."""
+    rho = torch.zeros_like(xp)
+    inv = 1.0 / (2.0 * sigma * sigma)
+    for A, (cx, cy) in zip(amps, centres):
+        rho += float(A) * torch.exp(-((xp - float(cx)) ** 2 + (yp - float(cy)) ** 2) * inv)
+    return rho.contiguous()
+
+
+def geometry(kind, n, map_params, device):
+    if kind == "circle":
+        return circle_geometry(n, map_params["acoef"], device)
+    return sinusoidal_geometry(n, map_params["amp"], device)
+
+
+def request_fields(desc, device):
+    """Fields of a serving request built from a ``gen.serving_stream``
+    descriptor: geometry() and source() evaluate the arrays on `device` when
+    the server asks for them."""
+    kind, n = desc["kind"], desc["side"]
+    mp, amps, centres = geometry_params(kind, desc["geom_seed"])
+    if desc["warm"]:
+        amps, centres = source_params(kind, mp, desc["source_seed"])
+    d = 1.0 / (n - 1)
+
+    def geom():
+        return geometry(kind, n, mp, device)
+
+    def source():
+        g = geometry(kind, n, mp, device)
+        return gaussian_rho(g["xp"], g["yp"], amps, centres)
+
+    return {"rid": desc["id"], "geom": desc["geom"], "nx": n, "ny": n, "dx": d, "dy": d,
+            "geometry": geom, "source": source, "warm": desc["warm"], "arrival": desc["t"]}

@@ -223,6 +223,47 @@ def _boundary_radius(theta, acoef):
     return 0.2 + 0.03 * np.sum(acoef[None, :] * np.cos(np.outer(theta, k)), axis=1)
 
 
+def draw_circle(rng):
+    """Perturbation coefficients a_2..a_5 of the conductor boundary, drawn
+    uniform in [-1, 1] and redrawn until 0.16 <= R(theta) <= 0.34 on 4096
+    equispaced angles."""
+    tt = np.linspace(0.0, 2 * np.pi, 4096, endpoint=False)
+    while True:
+        acoef = rng.uniform(-1.0, 1.0, 4)
+        Rs = _boundary_radius(tt, acoef)
+        if Rs.min() >= 0.16 and Rs.max() <= 0.34:
+            return acoef
+
+
+def draw_circle_sources(rng, acoef, n_gauss):
+    """Amplitudes (standard normal) and centres (uniform on the unit square,
+    each redrawn while inside the physical conductor) of the Gaussians."""
+    amps = rng.standard_normal(n_gauss)
+    centres = []
+    for _ in range(n_gauss):
+        while True:
+            c = rng.uniform(0.0, 1.0, 2)
+            tc = math.atan2(c[1] - 0.5, c[0] - 0.5)
+            if math.hypot(c[0] - 0.5, c[1] - 0.5) > _boundary_radius(np.array([tc]), acoef)[0]:
+                break
+        centres.append(c)
+    return amps, centres
+
+
+def draw_sinusoidal(rng, n_gauss=4, amp_max=0.15):
+    """Map amplitude U(0, amp_max), then the sources (see draw_box_sources)."""
+    amp = float(rng.uniform(0.0, amp_max))
+    amps, centres = draw_box_sources(rng, n_gauss)
+    return amp, amps, centres
+
+
+def draw_box_sources(rng, n_gauss=4):
+    """Amplitudes (standard normal) and centres uniform in [0.1, 0.9]^2."""
+    amps = rng.standard_normal(n_gauss)
+    centres = rng.uniform(0.1, 0.9, (n_gauss, 2))
+    return amps, centres
+
+
 def perturbed_circle(n: int = 4097, seed: int = 0, n_gauss: int = 8, sigma: float = 0.02,
                      draw_sources: bool = True) -> GridProblem:
     """Perturbed-circle conductor on the unit square (the 4097^2 workload).
@@ -244,12 +285,7 @@ def perturbed_circle(n: int = 4097, seed: int = 0, n_gauss: int = 8, sigma: floa
     phi = 1, a staircase in the computational grid); the outer ring is phi = 0.
     The map is numeric: only node coordinates are supplied (no ``jac``)."""
     rng = np.random.default_rng(seed)
-    tt = np.linspace(0.0, 2 * np.pi, 4096, endpoint=False)
-    while True:
-        acoef = rng.uniform(-1.0, 1.0, 4)
-        Rs = _boundary_radius(tt, acoef)
-        if Rs.min() >= 0.16 and Rs.max() <= 0.34:
-            break
+    acoef = draw_circle(rng)
     d = 1.0 / (n - 1)
     XI, ETA = _grid(n, n, 0.0, 0.0, d, d)
     ux = XI - 0.5
@@ -266,15 +302,7 @@ def perturbed_circle(n: int = 4097, seed: int = 0, n_gauss: int = 8, sigma: floa
     yp = 0.5 + rp * np.sin(th)
     mask = (r <= 0.2).astype(np.uint8)
     if draw_sources:
-        amps = rng.standard_normal(n_gauss)
-        centres = []
-        for _ in range(n_gauss):
-            while True:
-                c = rng.uniform(0.0, 1.0, 2)
-                tc = math.atan2(c[1] - 0.5, c[0] - 0.5)
-                if math.hypot(c[0] - 0.5, c[1] - 0.5) > _boundary_radius(np.array([tc]), acoef)[0]:
-                    break
-            centres.append(c)
+        amps, centres = draw_circle_sources(rng, acoef, n_gauss)
         rho = gaussian_sources(xp, yp, amps, centres, sigma)
     else:
         amps, centres = np.zeros(0), []
@@ -294,9 +322,7 @@ def random_sinusoidal(n: int, seed: int, n_gauss: int = 4, sigma: float = 0.02,
     amplitudes rng.standard_normal(n_gauss); centres rng.uniform(0.1, 0.9,
     (n_gauss, 2)).  Outer phi = 0, no interior mask, analytic Jacobian."""
     rng = np.random.default_rng(seed)
-    amp = float(rng.uniform(0.0, amp_max))
-    amps = rng.standard_normal(n_gauss)
-    centres = rng.uniform(0.1, 0.9, (n_gauss, 2))
+    amp, amps, centres = draw_sinusoidal(rng, n_gauss, amp_max)
     XI, ETA, xp, yp, jac = sinusoidal_map(n, amp)
     rho = gaussian_sources(xp, yp, amps, centres, sigma)
     d = 1.0 / (n - 1)
