@@ -1,16 +1,22 @@
 // The smallest levels of the V-cycle in one workgroup (arXiv 2602.01888,
 // Section 3).
 //
-// Below about a thousand nodes per level, a level pass is bound by latency:
-// a launch per pass would cost more than its work.  One 1024-thread
-// workgroup runs the sub-cycle from level lc (zero start, right-hand side
-// from the level above) down to the coarsest level and back.  Each thread
-// owns at most one node per level and keeps their stencil rows and
-// right-hand sides in registers; the iterates of all tail levels and one
-// residual array live in LDS, so a colour phase is an LDS read-modify-write
-// between two barriers.  Arithmetic per node is that of the other kernels:
-// four-colour Gauss-Seidel on the stored 9-point stencil, full weighting,
-// bilinear prolongation, explicit coarsest inverse.
+// Below a few thousand nodes per level, a level pass is bound by latency: a
+// launch per pass, or a band-marching pass with a barrier per colour phase
+// and row pair, costs far more than its work.  One 1024-thread workgroup
+// runs the sub-cycle from level lc (zero start, right-hand side from the
+// level above) down to the coarsest level and back, with the iterates of
+// all tail levels and one residual array in LDS, so a colour phase is an
+// LDS read-modify-write between two barriers.
+//
+// A level with at most 1024 nodes gives each thread one node whose stencil
+// row and right-hand side stay in registers.  A bigger level (at most four
+// nodes per thread) streams its stencil rows from global memory (they stay
+// in the L2 cache) in each phase; its right-hand side is the global array
+// for the first tail level and an LDS array for a later one.  Arithmetic
+// per node is that of the other kernels: four-colour Gauss-Seidel on the
+// stored 9-point stencil, full weighting, bilinear prolongation, explicit
+// coarsest inverse.
 #include <type_traits>
 
 #include "tomg_internal.h"
@@ -19,7 +25,8 @@ namespace tomg {
 namespace {
 
 constexpr int kTailThreads = 1024;
-constexpr int kOwn = 1;  // nodes per thread and level
+constexpr int kTailMaxNodes = 65 * 65;  // per level: at most five nodes per thread
+constexpr int kTailLdsMax = 160 * 1024 - 1024;  // LDS per workgroup, less the static arrays
 
 template <typename T>
 struct Own {
@@ -38,57 +45,77 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
   const int nl = a.nl;
   int total = 0, rmax = 0;
   for (int q = 0; q < nl; ++q) {
-    total += a.lv[q].nx * a.lv[q].ny;
-    rmax = max(rmax, a.lv[q].nx * a.lv[q].ny);
+    const int n = a.lv[q].nx * a.lv[q].ny;
+    total += n;
+    if (q < nl - 1) rmax = max(rmax, n);
   }
-  T *Rb = X + total;  // residual of the level being restricted
+  T *Rb = X + total;         // residual of the level being restricted
+  T *Bs = Rb + rmax;         // right-hand sides of streamed levels after the first
 
-  Own<T> own[kTailLevels][kOwn];
+  Own<T> own[kTailLevels];
 #pragma unroll
-  for (int q = 0; q < kTailLevels; ++q)
+  for (int q = 0; q < kTailLevels; ++q) {
+    Own<T> &o = own[q];
+    o.c = -1;
+    o.b = o.ik = T(0);
+    o.col = 0;
 #pragma unroll
-    for (int m = 0; m < kOwn; ++m) {
-      Own<T> &o = own[q][m];
-      o.c = -1;
-      o.b = o.ik = T(0);
-      o.col = 0;
+    for (int z = 0; z < 9; ++z) o.a[z] = T(0);
+    if (q >= nl) continue;
+    const TailLevel<T> &v = a.lv[q];
+    const int n = v.nx * v.ny;
+    for (int c = t; c < n; c += kTailThreads) X[v.off + c] = T(0);
+    if (n > kTailThreads || t >= n) continue;
+    const int i = t % v.nx, j = t / v.nx;
+    o.c = t;
+    o.col = (i & 1) + 2 * (j & 1);
+    const bool interior = i > 0 && j > 0 && i < v.nx - 1 && j < v.ny - 1;
+    if (q < nl - 1 && interior && !v.dir[t]) {
 #pragma unroll
-      for (int z = 0; z < 9; ++z) o.a[z] = T(0);
-      if (q >= nl) continue;
-      const TailLevel<T> &v = a.lv[q];
-      const int n = v.nx * v.ny;
-      const int c = t + m * kTailThreads;
-      if (c >= n) continue;
-      const int i = c % v.nx, j = c / v.nx;
-      o.c = c;
-      o.col = (i & 1) + 2 * (j & 1);
-      const bool interior = i > 0 && j > 0 && i < v.nx - 1 && j < v.ny - 1;
-      if (q < nl - 1 && interior && !v.dir[c]) {
-#pragma unroll
-        for (int z = 0; z < 9; ++z) o.a[z] = v.st[(size_t)z * n + c];
-        o.ik = T(1) / o.a[4];
-      }
-      if (q == 0) o.b = v.b[c];
-      X[v.off + c] = T(0);
+      for (int z = 0; z < 9; ++z) o.a[z] = v.st[(size_t)z * n + t];
+      o.ik = T(1) / o.a[4];
     }
+    if (q == 0) o.b = v.b[t];
+  }
   __syncthreads();
 
-  // A x at an owned node of level q (reads X)
-  auto offc = [&](const TailLevel<T> &v, const Own<T> &o) -> T {
+  // off-centre part of A x at node c of level v, from a stencil row s
+  auto offc = [&](const TailLevel<T> &v, const T *s9, int c) -> T {
     const T *x = X + v.off;
-    const int c = o.c, s = v.nx;
-    return o.a[0] * x[c - s - 1] + o.a[1] * x[c - s] + o.a[2] * x[c - s + 1] + o.a[3] * x[c - 1] +
-           o.a[5] * x[c + 1] + o.a[6] * x[c + s - 1] + o.a[7] * x[c + s] + o.a[8] * x[c + s + 1];
+    const int w = v.nx;
+    return s9[0] * x[c - w - 1] + s9[1] * x[c - w] + s9[2] * x[c - w + 1] + s9[3] * x[c - 1] +
+           s9[5] * x[c + 1] + s9[6] * x[c + w - 1] + s9[7] * x[c + w] + s9[8] * x[c + w + 1];
   };
+  auto load_row = [&](const TailLevel<T> &v, int c, T s9[9]) {
+    const size_t n = (size_t)v.nx * v.ny;
+#pragma unroll
+    for (int z = 0; z < 9; ++z) s9[z] = v.st[z * n + c];
+  };
+  auto rhs = [&](const TailLevel<T> &v, int c) -> T { return v.boff < 0 ? v.b[c] : Bs[v.boff + c]; };
+  auto streamed = [&](const TailLevel<T> &v) { return v.nx * v.ny > kTailThreads; };
+
   auto smooth = [&](int q, int sweeps) {
     const TailLevel<T> &v = a.lv[q];
+    const Own<T> &o = own[q];
+    const bool str = streamed(v);
     for (int s = 0; s < sweeps; ++s)
       for (int col = 0; col < 4; ++col) {
-#pragma unroll
-        for (int m = 0; m < kOwn; ++m) {
-          const Own<T> &o = own[q][m];
-          if (o.c >= 0 && o.col == col && o.ik != T(0))
-            X[v.off + o.c] = (o.b - offc(v, o)) * o.ik;
+        if (str) {
+          // interior nodes of this colour: i = pi + 2 u, j = pj + 2 w
+          const int pi = col & 1, pj = col >> 1;
+          const int i0 = pi ? 1 : 2, j0 = pj ? 1 : 2;
+          const int cu = v.nx - 2 >= i0 ? (v.nx - 2 - i0) / 2 + 1 : 0;
+          const int cw = v.ny - 2 >= j0 ? (v.ny - 2 - j0) / 2 + 1 : 0;
+          for (int k = t; k < cu * cw; k += kTailThreads) {
+            const int i = i0 + 2 * (k % cu), j = j0 + 2 * (k / cu);
+            const int c = j * v.nx + i;
+            if (v.dir[c]) continue;
+            T s9[9];
+            load_row(v, c, s9);
+            X[v.off + c] = (rhs(v, c) - offc(v, s9, c)) * (T(1) / s9[4]);
+          }
+        } else if (o.c >= 0 && o.col == col && o.ik != T(0)) {
+          X[v.off + o.c] = (o.b - offc(v, o.a, o.c)) * o.ik;
         }
         __syncthreads();
       }
@@ -99,18 +126,28 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
     if (q >= nl - 1) break;
     const TailLevel<T> &v = a.lv[q], &cv = a.lv[q + 1];
     smooth(q, a.nu1);
-    // residual into Rb, then full weighting into the coarse owners' rhs
-#pragma unroll
-    for (int m = 0; m < kOwn; ++m) {
-      const Own<T> &o = own[q][m];
-      if (o.c >= 0) Rb[o.c] = o.ik != T(0) ? o.b - offc(v, o) - o.a[4] * X[v.off + o.c] : T(0);
+    // residual into Rb, then full weighting into the coarse right-hand side
+    if (streamed(v)) {
+      const int n = v.nx * v.ny;
+      for (int c = t; c < n; c += kTailThreads) {
+        const int i = c % v.nx, j = c / v.nx;
+        T r = T(0);
+        if (i > 0 && j > 0 && i < v.nx - 1 && j < v.ny - 1 && !v.dir[c]) {
+          T s9[9];
+          load_row(v, c, s9);
+          r = rhs(v, c) - offc(v, s9, c) - s9[4] * X[v.off + c];
+        }
+        Rb[c] = r;
+      }
+    } else {
+      const Own<T> &o = own[q];
+      if (o.c >= 0)
+        Rb[o.c] = o.ik != T(0) ? o.b - offc(v, o.a, o.c) - o.a[4] * X[v.off + o.c] : T(0);
     }
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < kOwn; ++m) {
-      Own<T> &o = own[q + 1][m];
-      if (o.c < 0) continue;
-      const int I = o.c % cv.nx, J = o.c / cv.nx;
+    const int nc = cv.nx * cv.ny;
+    for (int C = t; C < nc; C += kTailThreads) {
+      const int I = C % cv.nx, J = C / cv.nx;
       T s = T(0);
       if (I > 0 && J > 0 && I < cv.nx - 1 && J < cv.ny - 1) {
         const int f = (2 * J) * v.nx + 2 * I, w = v.nx;
@@ -119,7 +156,10 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
         const T ee = Rb[f - w + 1] + T(2) * Rb[f + 1] + Rb[f + w + 1];
         s = (ww + T(2) * e + ee) * T(0.0625);
       }
-      o.b = s;
+      if (streamed(cv))
+        Bs[cv.boff + C] = s;
+      else
+        own[q + 1].b = s;  // C == t here
     }
     __syncthreads();
   }
@@ -132,7 +172,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
     for (int qq = 0; qq < kTailLevels; ++qq)
       if (qq == q && t < n) {
         const int k = a.cidx[t];
-        if (k >= 0) bb[k] = (double)own[qq][0].b;
+        if (k >= 0) bb[k] = (double)own[qq].b;
       }
     __syncthreads();
     if (t < n) {
@@ -149,12 +189,10 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
     if (q > nl - 2) continue;
     const TailLevel<T> &v = a.lv[q], &cv = a.lv[q + 1];
     const T *xc = X + cv.off;
-#pragma unroll
-    for (int m = 0; m < kOwn; ++m) {
-      const Own<T> &o = own[q][m];
-      if (o.c < 0) continue;
-      const int i = o.c % v.nx, j = o.c / v.nx;
-      if (i == 0 || j == 0 || i == v.nx - 1 || j == v.ny - 1 || v.dir[o.c]) continue;
+    const int n = v.nx * v.ny;
+    for (int c = t; c < n; c += kTailThreads) {
+      const int i = c % v.nx, j = c / v.nx;
+      if (i == 0 || j == 0 || i == v.nx - 1 || j == v.ny - 1 || v.dir[c]) continue;
       const int I = i >> 1, J = j >> 1;
       const T *r0 = xc + J * cv.nx;
       T e0 = (i & 1) ? T(0.5) * (r0[I] + r0[I + 1]) : r0[I];
@@ -163,7 +201,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
         const T e1 = (i & 1) ? T(0.5) * (r1[I] + r1[I + 1]) : r1[I];
         e0 = T(0.5) * (e0 + e1);
       }
-      X[v.off + o.c] += e0;
+      X[v.off + c] += e0;
     }
     __syncthreads();
     smooth(q, a.nu2);
@@ -183,14 +221,20 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
 // Batched form: one workgroup per problem.
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail_b(BatchTab tab) {
-  const TailArgs<T> a = *static_cast<const TailArgs<T> *>(tab.e[blockIdx.x].args);
+  const TailArgs<T> &a = *static_cast<const TailArgs<T> *>(tab.e[blockIdx.x].args);
   tail_body<T>(a);
 }
 
 }  // namespace
 
 // Number of nodes a level may have to be handled by the tail.
-int tail_max_nodes() { return kTailThreads * kOwn; }
+int tail_max_nodes() { return kTailMaxNodes; }
+
+// Largest tail LDS footprint for the node limits above: the first level at
+// kTailMaxNodes, three more each at most a quarter of the previous plus a
+// ring, one residual array and the streamed right-hand sides.
+static_assert((kTailMaxNodes * 2 + 1100 + 300 + 100 + 1100) * 8 <= kTailLdsMax,
+              "tail LDS exceeds the workgroup limit");
 
 template <typename T>
 static TailArgs<T> make_tail_args(tomg_problem *p, int lc) {
@@ -202,7 +246,7 @@ static TailArgs<T> make_tail_args(tomg_problem *p, int lc) {
   a.nu2 = p->cfg.nu2;
   a.cinv = p->cinv;
   a.cidx = p->cidx;
-  int off = 0, rmax = 0;
+  int off = 0, rmax = 0, boff = 0;
   for (int q = 0; q < a.nl; ++q) {
     const Level &v = p->lv[lc + q];
     a.lv[q].nx = v.nx;
@@ -213,10 +257,15 @@ static TailArgs<T> make_tail_args(tomg_problem *p, int lc) {
     a.lv[q].dir = v.dir;
     a.lv[q].off = off;
     const int n = v.nx * v.ny;
+    a.lv[q].boff = -1;
+    if (q > 0 && n > kTailThreads) {
+      a.lv[q].boff = boff;
+      boff += n;
+    }
     off += n;
-    rmax = rmax > n ? rmax : n;
+    if (q < a.nl - 1) rmax = rmax > n ? rmax : n;
   }
-  a.shmem = (off + rmax) * (int)sizeof(T);
+  a.shmem = (off + rmax + boff) * (int)sizeof(T);
   return a;
 }
 

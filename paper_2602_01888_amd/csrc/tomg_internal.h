@@ -68,7 +68,9 @@ struct TailLevel {
   T *x;
   const T *b;
   const uint8_t *dir;
-  int off;  // offset of the level's iterate in the LDS array
+  int off;   // offset of the level's iterate in the LDS array
+  int boff;  // offset of its right-hand side in LDS (levels after the first
+             // with more nodes than the tail has threads), else -1
 };
 constexpr int kTailLevels = 4;
 template <typename T>
