@@ -25,6 +25,7 @@
 // ends in a barrier.  Each sweep invalidates at most 4 halo columns and 2
 // halo rows at the edges of the block, which is what H and HV cover.
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <type_traits>
 
@@ -435,24 +436,31 @@ static int env_int(const char *name, int dflt) {
   return (s && *s) ? atoi(s) : dflt;
 }
 
-// Rows per block: the tallest band (<= 128 rows) that still gives
-// band_target blocks; never below band_min rows (halo rows are recomputed,
-// so short bands cost redundant work).  TOMG_BAND_TARGET / TOMG_BAND_MIN
-// override the defaults (tuning only).
-static int pick_band(int nx, int ny, int W) {
-  static const int target = env_int("TOMG_BAND_TARGET", 1024);
-  static const int cmin = env_int("TOMG_BAND_MIN", 16);
-  const int bx = (nx + W - 1) / W;
-  int CH = 128;
-  while (CH > cmin && CH > 8 && (long)bx * ((ny + CH - 1) / CH) < target) CH >>= 1;
-  return CH;
+// Rows per block.  A pass is a set of blocks that each march up their band
+// two rows per step, so its time is about (steps per block) x (rounds of
+// blocks the device needs); halo rows are recomputed by both neighbours.
+// The band is the shortest (fewest steps) that still lets all blocks of the
+// pass be resident at once (slots = resident blocks per CU x CUs), and on
+// levels above 2M nodes, where the pass is bound by memory traffic, at least
+// three halo depths tall so that halo rows add at most two thirds to it.
+// TOMG_CH_L<level> forces the band of one level (tuning only).
+constexpr int kMinBand = 2;
+static int pick_band(int nx, int ny, int W, int level, long slots, int hv) {
+  char name[32];
+  snprintf(name, sizeof name, "TOMG_CH_L%d", level);
+  const int forced = env_int(name, 0);
+  if (forced > 0) return forced < kMinBand ? kMinBand : forced;
+  const long bx = (nx + W - 1) / W;
+  int CH = (long)nx * ny > (2L << 20) ? 3 * hv + (3 * hv & 1) : kMinBand;
+  while (CH < ny && bx * ((ny + CH - 1) / CH) > slots) CH += 2;
+  return CH < ny ? CH : ny;
 }
 
 // Upper bound of the block count of any pass on an nx x ny level (sizes the
 // partial-sum buffer).
 size_t fused_max_blocks(int nx, int ny) {
   const int Wmin = kBW - 2 * (4 * 4 + 2);
-  return (size_t)((nx + Wmin - 1) / Wmin) * (size_t)((ny + 7) / 8);
+  return (size_t)((nx + Wmin - 1) / Wmin) * (size_t)((ny + kMinBand - 1) / kMinBand);
 }
 
 #ifndef TOMG_PAIRS_EPS
@@ -483,6 +491,50 @@ static void launch_pass(int nu, const PassArgs<T> &a, hipStream_t s, const Batch
     default: TOMG_LAUNCH(4); break;
   }
 #undef TOMG_LAUNCH
+}
+
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  return cus;
+}
+
+// Blocks of one pass kernel that fit on a CU at once.
+template <typename T, bool EPS, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+static int pass_blocks_per_cu(int nu) {
+  constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
+  const void *f;
+  switch (nu) {
+    case 1: f = reinterpret_cast<const void *>(k_pass<T, EPS, 1, P, ZERO, PROLONG, RESTRICT, NORM>); break;
+    case 2: f = reinterpret_cast<const void *>(k_pass<T, EPS, 2, P, ZERO, PROLONG, RESTRICT, NORM>); break;
+    case 3: f = reinterpret_cast<const void *>(k_pass<T, EPS, 3, P, ZERO, PROLONG, RESTRICT, NORM>); break;
+    default: f = reinterpret_cast<const void *>(k_pass<T, EPS, 4, P, ZERO, PROLONG, RESTRICT, NORM>); break;
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBW, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+// Resident-block slots of the pass of level l (the variant a solve launches).
+template <typename T>
+static long pass_slots(int l, bool up, int nu) {
+  constexpr bool F64 = std::is_same<T, double>::value;
+  int nb;
+  if (l == 0) {
+    if (up)
+      nb = F64 ? pass_blocks_per_cu<T, true, false, true, false, F64>(nu)
+               : pass_blocks_per_cu<T, true, false, true, false, false>(nu);
+    else
+      nb = pass_blocks_per_cu<T, true, false, false, true, false>(nu);
+  } else {
+    nb = up ? pass_blocks_per_cu<T, false, false, true, false, false>(nu)
+            : pass_blocks_per_cu<T, false, true, false, true, false>(nu);
+  }
+  static const int cus = device_cus();
+  return (long)nb * cus;
 }
 
 // Arguments of the down (up) pass of level l in precision T: the level
@@ -520,7 +572,7 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, T *x0, T *pong0, c
   a.partials = (up && l == 0) ? p->partials : nullptr;
   const int nu = up ? p->cfg.nu2 : p->cfg.nu1;
   a.W = kBW - 2 * (4 * nu + 2);
-  a.CH = pick_band(a.nx, a.ny, a.W);
+  a.CH = pick_band(a.nx, a.ny, a.W, l, pass_slots<T>(l, up, nu), 2 * nu + 3);
   a.nbx = (a.nx + a.W - 1) / a.W;
   a.nby = (a.ny + a.CH - 1) / a.CH;
   return a;
