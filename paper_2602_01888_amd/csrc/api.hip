@@ -307,8 +307,7 @@ tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
                           double *rel_out) {
   if (!p || !d_phi) return TOMG_EINVAL;
   if (!p->ready) return fail(p, TOMG_ESTATE, "residual_norm before setup_coeffs");
-  HIP_TRY(p, launch_resnorm(p, d_phi, kSlotB0, true));
-  HIP_TRY(p, launch_resnorm(p, d_phi, kSlotRes, false));
+  HIP_TRY(p, launch_begin(p, d_phi, false));
   double h[kNumSlots];
   tomg_status s = read_scalars(p, h);
   if (s != TOMG_OK) return s;
@@ -323,11 +322,7 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
   if (!(rel_tol > 0.0) || max_cycles < 0) return fail(p, TOMG_EINVAL, "solve: bad tol/max_cycles");
   if (!p->ready) return fail(p, TOMG_ESTATE, "solve before setup_coeffs");
   const bool ir = p->cfg.precision == TOMG_FP32_IR;
-  HIP_TRY(p, launch_resnorm(p, d_phi, kSlotB0, true));
-  if (ir)
-    HIP_TRY(p, launch_ir_residual(p, d_phi));
-  else
-    HIP_TRY(p, launch_resnorm(p, d_phi, kSlotRes, false));
+  HIP_TRY(p, launch_begin(p, d_phi, ir));
   double h[kNumSlots];
   tomg_status s = read_scalars(p, h);
   if (s != TOMG_OK) return s;
@@ -391,12 +386,8 @@ bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
 // start and the residual of the given iterate; relative residuals to out[q].
 void batch_begin(tomg_problem *const *probs, const int *idx, int cnt, double *const *d_phis,
                  bool ir, double *out, hipStream_t s) {
-  batch_resnorm(probs, idx, cnt, true, d_phis, s);
-  batch_finalize(probs, idx, cnt, 0, kSlotB0, false, out, s);
-  if (ir)
-    batch_ir_residual(probs, idx, cnt, d_phis, s);
-  else
-    batch_resnorm(probs, idx, cnt, false, d_phis, s);
+  batch_begin_norms(probs, idx, cnt, ir, d_phis, s);
+  batch_finalize(probs, idx, cnt, 2, kSlotB0, false, out, s);
   batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s);
 }
 

@@ -563,54 +563,87 @@ __device__ __forceinline__ double resid0(const RedArgs &a, const double *x, int 
   return a.f[c] - off + k2 * v(c);
 }
 
-// Partial sums of r^2 over free nodes: block blk of nblk, fixed order.
+// Level-0 reductions.  Block blk of nblk takes rows blk, blk + nblk, ...
+// (threads along the row), so every partial sum has a fixed order.
+
+// Partial sums of r^2 over free nodes.
 template <bool ZF>
 __device__ __forceinline__ void resnorm_body(const RedArgs &a, const double *x, int blk) {
-  const size_t m = (size_t)(a.nx - 2) * (a.ny - 2);
   double s = 0.0;
-  for (size_t k = (size_t)blk * blockDim.x + threadIdx.x; k < m;
-       k += (size_t)a.nblk * blockDim.x) {
-    const int j = 1 + (int)(k / (a.nx - 2)), i = 1 + (int)(k % (a.nx - 2));
-    if (a.dir[(size_t)j * a.nx + i]) continue;
-    const double r = resid0<ZF>(a, x, i, j);
-    s += r * r;
-  }
+  for (int j = 1 + blk; j < a.ny - 1; j += a.nblk)
+    for (int i = 1 + threadIdx.x; i < a.nx - 1; i += blockDim.x) {
+      if (a.dir[(size_t)j * a.nx + i]) continue;
+      const double r = resid0<ZF>(a, x, i, j);
+      s += r * r;
+    }
   s = block_reduce<0>(s);
   if (threadIdx.x == 0) a.partials[blk] = s;
 }
 
 // Refinement, outer step: r = f - A64 phi at free nodes (FP64), r32 =
-// fl32(r), partial sums of r^2.
+// fl32(r) (zero at Dirichlet nodes), partial sums of r^2.  With B0 also the
+// partial sums of the zero-interior residual |f - A phi0|^2 into
+// partials[nblk + blk].
+template <bool B0>
 __device__ __forceinline__ void ir_residual_body(const RedArgs &a, const double *phi, int blk) {
-  const size_t n = (size_t)a.nx * a.ny;
-  double s = 0.0;
-  for (size_t c = (size_t)blk * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)a.nblk * blockDim.x) {
-    double r = 0.0;
-    if (!a.dir[c]) {
-      const int j = (int)(c / a.nx), i = (int)(c - (size_t)j * a.nx);
-      r = resid0<false>(a, phi, i, j);
+  double s = 0.0, s0 = 0.0;
+  for (int j = blk; j < a.ny; j += a.nblk) {
+    const size_t row = (size_t)j * a.nx;
+    for (int i = threadIdx.x; i < a.nx; i += blockDim.x) {
+      double r = 0.0;
+      if (!a.dir[row + i]) {
+        r = resid0<false>(a, phi, i, j);
+        if constexpr (B0) {
+          const double r0 = resid0<true>(a, phi, i, j);
+          s0 += r0 * r0;
+        }
+      }
+      a.r32[row + i] = (float)r;
+      s += r * r;
     }
-    a.r32[c] = (float)r;
-    s += r * r;
   }
   s = block_reduce<0>(s);
   if (threadIdx.x == 0) a.partials[blk] = s;
+  if constexpr (B0) {
+    s0 = block_reduce<0>(s0);
+    if (threadIdx.x == 0) a.partials[a.nblk + blk] = s0;
+  }
+}
+
+// Both initial norms in one pass: partials[blk] = sum of r^2 of the given
+// iterate, partials[nblk + blk] = sum of r^2 of the zero-interior start.
+__device__ __forceinline__ void begin_body(const RedArgs &a, const double *x, int blk) {
+  double s = 0.0, s0 = 0.0;
+  for (int j = 1 + blk; j < a.ny - 1; j += a.nblk)
+    for (int i = 1 + threadIdx.x; i < a.nx - 1; i += blockDim.x) {
+      if (a.dir[(size_t)j * a.nx + i]) continue;
+      const double r = resid0<false>(a, x, i, j);
+      const double r0 = resid0<true>(a, x, i, j);
+      s += r * r;
+      s0 += r0 * r0;
+    }
+  s = block_reduce<0>(s);
+  if (threadIdx.x == 0) a.partials[blk] = s;
+  s0 = block_reduce<0>(s0);
+  if (threadIdx.x == 0) a.partials[a.nblk + blk] = s0;
 }
 
 // Refinement, update: phi += e32 at free nodes.
 __device__ __forceinline__ void ir_update_body(const RedArgs &a, double *phi, int blk) {
-  const size_t n = (size_t)a.nx * a.ny;
-  for (size_t c = (size_t)blk * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)a.nblk * blockDim.x)
-    if (!a.dir[c]) phi[c] += (double)a.e32[c];
+  for (int j = blk; j < a.ny; j += a.nblk) {
+    const size_t row = (size_t)j * a.nx;
+    for (int i = threadIdx.x; i < a.nx; i += blockDim.x)
+      if (!a.dir[row + i]) phi[row + i] += (double)a.e32[row + i];
+  }
 }
 
 template <bool ZF>
 __global__ void k_resnorm(RedArgs a, const double *x) { resnorm_body<ZF>(a, x, blockIdx.x); }
+template <bool B0>
 __global__ void k_ir_residual(RedArgs a, const double *phi) {
-  ir_residual_body(a, phi, blockIdx.x);
+  ir_residual_body<B0>(a, phi, blockIdx.x);
 }
+__global__ void k_begin(RedArgs a, const double *x) { begin_body(a, x, blockIdx.x); }
 __global__ void k_ir_update(RedArgs a, double *phi) { ir_update_body(a, phi, blockIdx.x); }
 
 __device__ __forceinline__ const BatchEntry &locate(const BatchTab &tab, int b) {
@@ -622,17 +655,20 @@ __device__ __forceinline__ const BatchEntry &locate(const BatchTab &tab, int b) 
   return tab.e[lo];
 }
 
-// kind 0: resnorm (ZF), 1: resnorm, 2: refinement residual, 3: refinement update
+// kind 0: resnorm (ZF), 1: resnorm, 2: refinement residual, 3: refinement
+// update, 4: both initial norms, 5: refinement residual and zero-interior norm
 template <int KIND>
 __global__ void k_red_b(BatchTab tab) {
   const BatchEntry &e = locate(tab, blockIdx.x);
-  const RedArgs a = *static_cast<const RedArgs *>(e.args);
+  const RedArgs &a = *static_cast<const RedArgs *>(e.args);
   const int blk = blockIdx.x - e.start;
   double *phi = static_cast<double *>(e.phi);
   if constexpr (KIND == 0) resnorm_body<true>(a, phi, blk);
   if constexpr (KIND == 1) resnorm_body<false>(a, phi, blk);
-  if constexpr (KIND == 2) ir_residual_body(a, phi, blk);
+  if constexpr (KIND == 2) ir_residual_body<false>(a, phi, blk);
   if constexpr (KIND == 3) ir_update_body(a, phi, blk);
+  if constexpr (KIND == 4) begin_body(a, phi, blk);
+  if constexpr (KIND == 5) ir_residual_body<true>(a, phi, blk);
 }
 
 // Batched finalize: one block per problem; sqrt of the fixed-order sum into
@@ -926,13 +962,30 @@ void build_red_args(tomg_problem *p) {
   r.tmp = p->tmp;
   r.nblk = red_blocks(p->lv[0].n);
   p->hargs.fin_red = {p->partials, p->scal, r.nblk};
+  p->hargs.fin_red0 = {p->partials + r.nblk, p->scal, r.nblk};
   const PassArgs<double> &u = p->hargs.up64[0];
   p->hargs.fin_norm = {p->partials, p->scal, u.nbx * u.nby};
 }
 
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
   const RedArgs &r = p->hargs.red;
-  hipLaunchKernelGGL(k_ir_residual, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  hipLaunchKernelGGL(k_ir_residual<false>, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
+                     p->scal + kSlotRes, 1, p->scal, 1);
+  return hipGetLastError();
+}
+
+// Initial norms of a solve in one pass over level 0: |f - A phi0| into
+// scal[kSlotB0] and the residual of phi into scal[kSlotRes] (and the
+// relative residual); with ir also r32 (the refinement residual).
+hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir) {
+  const RedArgs &r = p->hargs.red;
+  if (ir)
+    hipLaunchKernelGGL(k_ir_residual<true>, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  else
+    hipLaunchKernelGGL(k_begin, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + r.nblk,
+                     r.nblk, 1, p->scal + kSlotB0, 1, p->scal, 0);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
                      p->scal + kSlotRes, 1, p->scal, 1);
   return hipGetLastError();
@@ -1003,6 +1056,14 @@ void batch_ir_residual(tomg_problem *const *probs, const int *idx, int cnt, doub
   batch_red<2>(probs, idx, cnt, phis, s);
 }
 
+void batch_begin_norms(tomg_problem *const *probs, const int *idx, int cnt, bool ir,
+                       double *const *phis, hipStream_t s) {
+  if (ir)
+    batch_red<5>(probs, idx, cnt, phis, s);
+  else
+    batch_red<4>(probs, idx, cnt, phis, s);
+}
+
 void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
                      hipStream_t s) {
   batch_red<3>(probs, idx, cnt, phis, s);
@@ -1016,7 +1077,9 @@ void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kin
     for (int k = k0; k < cnt && k < k0 + kBatchMax; ++k) {
       tomg_problem *p = probs[idx[k]];
       BatchEntry &e = tab.e[tab.count];
-      e.args = kind == 0 ? (const void *)&p->dargs->fin_red : (const void *)&p->dargs->fin_norm;
+      e.args = kind == 0   ? (const void *)&p->dargs->fin_red
+               : kind == 1 ? (const void *)&p->dargs->fin_norm
+                           : (const void *)&p->dargs->fin_red0;
       e.phi = nullptr;
       e.role = 0;
       e.nbx = e.nby = 1;

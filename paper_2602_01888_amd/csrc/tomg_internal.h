@@ -108,7 +108,8 @@ struct ArgsBlob {
   TailArgs<double> tail64;
   TailArgs<float> tail32;
   RedArgs red;
-  FinArgs fin_red, fin_norm;
+  FinArgs fin_red, fin_norm, fin_red0;  // partials of the reductions, the up pass,
+                                        // and the second half of a two-norm pass
 };
 
 // One problem's share of a batched launch: blocks [start, start + nbx*nby).
@@ -198,6 +199,7 @@ int tail_max_nodes();
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi);
 hipError_t launch_ir_correct(tomg_problem *p, double *phi);
 hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free);
+hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir);
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps);
 hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
@@ -222,10 +224,14 @@ void batch_resnorm(tomg_problem *const *probs, const int *idx, int cnt, bool zer
                    double *const *phis, hipStream_t s);
 void batch_ir_residual(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
                        hipStream_t s);
+// both initial norms (and r32 with ir) in one pass: partials of the iterate's
+// residual in fin_red, of the zero-interior residual in fin_red0
+void batch_begin_norms(tomg_problem *const *probs, const int *idx, int cnt, bool ir,
+                       double *const *phis, hipStream_t s);
 void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
                      hipStream_t s);
 // kind 0: the reduction partials (fin_red), 1: the level-0 up-pass partials
-// (fin_norm); slot: scalar slot written; rel: also write rel and done, and
+// (fin_norm), 2: the second half of a two-norm pass (fin_red0); slot: scalar slot written; rel: also write rel and done, and
 // copy the value into out[k] for entry k (out = the leading problem's bout)
 void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kind, int slot,
                     bool rel, double *out, hipStream_t s);
