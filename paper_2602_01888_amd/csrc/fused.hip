@@ -42,6 +42,31 @@ namespace {
 #endif
 constexpr int kBW = TOMG_BW;
 
+// Streaming stores: the pass outputs are read back by the next pass, long
+// after the caches have turned over, so they are written with the
+// non-temporal hint.  Loads keep the default policy (halo rows are read
+// again by the neighbouring band).
+#ifndef TOMG_NT_STORE
+#define TOMG_NT_STORE 1
+#endif
+#ifndef TOMG_NT_LOAD
+#define TOMG_NT_LOAD 0
+#endif
+template <typename T>
+__device__ __forceinline__ void st_out(T *p, T v) {
+  if constexpr (TOMG_NT_STORE)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+template <typename T>
+__device__ __forceinline__ T ld_in(const T *p) {
+  if constexpr (TOMG_NT_LOAD)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
 // Per-thread values of one row as loaded from global memory.
 template <typename T, bool EPS>
 struct Raw;
@@ -117,11 +142,11 @@ constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 // rows of the P pairs m-s, ..., m-s-P+1 (colours 0 then 1; even rows only
 // read odd rows, so the P rows of a phase are independent) and then their
 // odd rows (colours 2 then 3).  Four barriers per sweep and step, whatever
-// P.  With P = 1 the level-0 pass prefetches the next pair while it works on
-// the current one; otherwise a step's loads are issued together at its start.
+// P.  The level-0 pass loads the next step's rows while it works on the
+// current ones; coarse levels issue a step's loads together at its start.
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
 __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, const int by) {
-  constexpr bool PF = EPS && P == 1;
+  constexpr bool PF = EPS;  // level 0: the next step's rows are loaded during this step
   constexpr int H = 4 * NU + 2;
   constexpr int HV = 2 * NU + 3;
   constexpr int NS = 2 * NU + 2 * P;               // coefficient rows: R0 .. 2m+1
@@ -164,16 +189,16 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   auto load_row = [&](int r, Raw<T, EPS> &w) {
     const int rc = min(max(r, 0), ny - 1);
     const size_t c = (size_t)rc * nx + gc;
-    w.x = ZERO ? T(0) : a.xin[c];
-    w.f = a.b[c];
-    w.d = a.dir[c];
+    w.x = ZERO ? T(0) : ld_in(a.xin + c);
+    w.f = ld_in(a.b + c);
+    w.d = ld_in(a.dir + c);
     if constexpr (EPS) {
-      w.xx = a.exx[c];
-      w.xy = a.exy[c];
-      w.yy = a.eyy[c];
+      w.xx = ld_in(a.exx + c);
+      w.xy = ld_in(a.exy + c);
+      w.yy = ld_in(a.eyy + c);
     } else {
 #pragma unroll
-      for (int z = 0; z < 9; ++z) w.a[z] = a.st[z * n + c];
+      for (int z = 0; z < 9; ++z) w.a[z] = ld_in(a.st + z * n + c);
     }
     if constexpr (PROLONG) {
       const int J = rc >> 1, J1 = min(J + 1, a.nyc - 1);
@@ -215,7 +240,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
     rec[s].ik = T(0);
   }
   Raw<T, EPS> cur[2 * P];
-  Raw<T, EPS> nxt[PF ? 2 : 1];
+  Raw<T, EPS> nxt[PF ? 2 * P : 1];
   // level 0: tensor values carried from the two rows below the step's first
   // new row: row base-2 (eyy, exy) and row base-1 (exx, exy, eyy, f, dir)
   T c_yy2 = T(0), c_xy2 = T(0), c_xx1 = T(0), c_xy1 = T(0), c_yy1 = T(0), c_f1 = T(0);
@@ -224,11 +249,12 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   (void)nxt;
   T rprev = T(0), acc = T(0);
 
-  if constexpr (PF) {  // prologue: the first row pair
-    load_row(2 * m0, cur[0]);
-    load_row(2 * m0 + 1, cur[1]);
-    commit_row(2 * m0, cur[0]);
-    commit_row(2 * m0 + 1, cur[1]);
+  if constexpr (PF) {  // prologue: the rows of the first step
+    const int base0 = 2 * (m0 - P + 1);
+#pragma unroll
+    for (int q = 0; q < 2 * P; ++q) load_row(base0 + q, cur[q]);
+#pragma unroll
+    for (int q = 0; q < 2 * P; ++q) commit_row(base0 + q, cur[q]);
   }
   __syncthreads();
 
@@ -243,8 +269,8 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
         // relative row index of row 2m + o is rel0 + o
         const int rel0 = 2 * P * ph + 2 * P - 2;
         if constexpr (PF) {
-          load_row(2 * m + 2, nxt[0]);
-          load_row(2 * m + 3, nxt[1]);
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) load_row(2 * m + 2 + q, nxt[q]);
         } else {
 #pragma unroll
           for (int q = 0; q < 2 * P; ++q) load_row(base + q, cur[q]);
@@ -344,7 +370,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
             }
           }
           if (r >= y0 && r < y1 && outc) {
-            a.xout[(size_t)r * nx + gi] = mid[t + 1];
+            st_out(a.xout + (size_t)r * nx + gi, mid[t + 1]);
             if constexpr (NORM) acc += res[q] * res[q];
           }
         }
@@ -366,7 +392,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
               const bool ring = I == 0 || J == 0 || I == a.nxc - 1 || J == a.nyc - 1;
               const T v = ring ? T(0)
                                : (xch[p][t] + T(2) * xch[p][t + 1] + xch[p][t + 2]) * T(0.0625);
-              a.bc[(size_t)J * a.nxc + I] = v;
+              st_out(a.bc + (size_t)J * a.nxc + I, v);
             }
           }
         }
@@ -382,10 +408,11 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
           c_d1 = cur[2 * P - 1].d;
         }
         if constexpr (PF) {
-          commit_row(2 * m + 2, nxt[0]);
-          commit_row(2 * m + 3, nxt[1]);
-          cur[0] = nxt[0];
-          cur[1] = nxt[1];
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) {
+            commit_row(2 * m + 2 + q, nxt[q]);
+            cur[q] = nxt[q];
+          }
         }
       } else {
         more = false;

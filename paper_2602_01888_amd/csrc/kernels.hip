@@ -372,76 +372,93 @@ __global__ __launch_bounds__(kGX *kGY) void k_coarsen(Op opf, const uint8_t *dir
 // Coarsest level: index map of the free nodes and the explicit inverse of
 // the coarsest matrix by Gauss-Jordan elimination with partial pivoting (one
 // block).  cidx[ncoarse] receives the unknown count.
-__global__ void k_coarse_inverse(const double *st, const uint8_t *dir, int nx, int ny,
-                                 double *inv, int *cidx, double *scal) {
+__global__ __launch_bounds__(256) void k_coarse_inverse(const double *st, const uint8_t *dir,
+                                                        int nx, int ny, double *inv, int *cidx,
+                                                        double *scal) {
+  // Gauss-Jordan with partial pivoting on m <= kMaxCoarseUnknowns < 64
+  // unknowns: lane t & 63 owns a column, wave t >> 6 every fourth row; the
+  // pivot search is a shuffle reduction in wave 0
   constexpr int M = kMaxCoarseUnknowns;
   __shared__ double A[M][M + 1], B[M][M + 1];
-  __shared__ double fac[M];
+  __shared__ double fac[M], rowa[M], rowb[M];
   __shared__ int cid[81];
-  __shared__ int sm, piv;
-  const int n = nx * ny, t = threadIdx.x, nt = blockDim.x;
+  __shared__ int sm, spiv;
+  const int n = nx * ny, t = threadIdx.x, c = t & 63, w = t >> 6;
   if (t == 0) {
     int m = 0;
-    for (int c = 0; c < n; ++c) cid[c] = dir[c] ? -1 : m++;
+    for (int q = 0; q < n; ++q) cid[q] = dir[q] ? -1 : m++;
     sm = m;
-    for (int c = 0; c < n; ++c) cidx[c] = cid[c];
+    for (int q = 0; q < n; ++q) cidx[q] = cid[q];
     cidx[n] = m;
   }
   __syncthreads();
   const int m = sm;
-  for (int k = t; k < m * m; k += nt) {
-    const int r = k / m, c = k % m;
-    A[r][c] = 0.0;
-    B[r][c] = (r == c) ? 1.0 : 0.0;
-  }
+  if (c < m)
+    for (int r = w; r < m; r += 4) {
+      A[r][c] = 0.0;
+      B[r][c] = (r == c) ? 1.0 : 0.0;
+    }
   __syncthreads();
-  for (int c = t; c < n; c += nt) {
-    const int row = cid[c];
+  for (int q = t; q < n; q += 256) {
+    const int row = cid[q];
     if (row < 0) continue;
-    const int I = c % nx, J = c / nx;
+    const int I = q % nx, J = q / nx;
     for (int dj = -1; dj <= 1; ++dj)
       for (int di = -1; di <= 1; ++di) {
         const int ii = I + di, jj = J + dj;
         if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
         const int col = cid[jj * nx + ii];
-        if (col >= 0) A[row][col] = st[(size_t)((dj + 1) * 3 + di + 1) * n + c];
+        if (col >= 0) A[row][col] = st[(size_t)((dj + 1) * 3 + di + 1) * n + q];
       }
   }
   __syncthreads();
   for (int k = 0; k < m; ++k) {
-    if (t == 0) {
-      int p = k;
-      for (int r = k + 1; r < m; ++r)
-        if (fabs(A[r][k]) > fabs(A[p][k])) p = r;
-      piv = p;
-      if (A[p][k] == 0.0) scal[kSlotPivot] = 1.0;
-    }
-    __syncthreads();
-    const int p = piv;
-    if (p != k)
-      for (int c = t; c < m; c += nt) {
+    if (w == 0) {
+      // largest |A[r][k]| for r >= k, the first on ties
+      double v = (c >= k && c < m) ? fabs(A[c][k]) : -1.0;
+      int p = c;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int op = __shfl_xor(p, off, 64);
+        if (ov > v || (ov == v && op < p)) {
+          v = ov;
+          p = op;
+        }
+      }
+      if (c == 0) {
+        spiv = p;
+        if (v == 0.0) scal[kSlotPivot] = 1.0;
+      }
+      if (p != k && c < m) {
         double u = A[k][c]; A[k][c] = A[p][c]; A[p][c] = u;
         u = B[k][c]; B[k][c] = B[p][c]; B[p][c] = u;
       }
-    __syncthreads();
-    const double pv = A[k][k];
-    __syncthreads();
-    for (int c = t; c < m; c += nt) {
-      A[k][c] /= pv;
-      B[k][c] /= pv;
     }
     __syncthreads();
-    for (int r = t; r < m; r += nt) fac[r] = A[r][k];
+    if (w == 0 && c < m) {
+      const double pv = A[k][k];
+      rowa[c] = A[k][c] / pv;
+      rowb[c] = B[k][c] / pv;
+      fac[c] = A[c][k];
+    }
     __syncthreads();
-    for (int idx = t; idx < m * m; idx += nt) {
-      const int r = idx / m, c = idx % m;
-      if (r == k) continue;
-      A[r][c] -= fac[r] * A[k][c];
-      B[r][c] -= fac[r] * B[k][c];
+    if (c < m) {
+      const double ra = rowa[c], rb = rowb[c];
+      for (int r = w; r < m; r += 4) {
+        if (r == k) {
+          A[k][c] = ra;
+          B[k][c] = rb;
+        } else {
+          A[r][c] -= fac[r] * ra;
+          B[r][c] -= fac[r] * rb;
+        }
+      }
     }
     __syncthreads();
   }
-  for (int k = t; k < m * m; k += nt) inv[k] = B[k / m][k % m];
+  if (c < m)
+    for (int r = w; r < m; r += 4) inv[r * m + c] = B[r][c];
 }
 
 // ---------------------------------------------------------------------------

@@ -9,14 +9,16 @@
 // all tail levels and one residual array in LDS, so a colour phase is an
 // LDS read-modify-write between two barriers.
 //
-// A level with at most 1024 nodes gives each thread one node whose stencil
-// row and right-hand side stay in registers.  A bigger level (at most four
-// nodes per thread) streams its stencil rows from global memory (they stay
-// in the L2 cache) in each phase; its right-hand side is the global array
-// for the first tail level and an LDS array for a later one.  Arithmetic
-// per node is that of the other kernels: four-colour Gauss-Seidel on the
-// stored 9-point stencil, full weighting, bilinear prolongation, explicit
-// coarsest inverse.
+// Levels are counted from the coarsest (r = 0).  The two coarsest (at most
+// 17 x 17 nodes) give each thread one node whose stencil row and right-hand
+// side stay in registers.  Levels r >= 2 (at most 65 x 65 nodes, five nodes
+// per thread) stream their stencil rows from global memory, where they stay
+// in the L2 cache; in each colour phase a thread already loads the stencil
+// of its node of the next phase, so the load latency overlaps the barrier.
+// Their right-hand side is the global array for the first tail level and an
+// LDS array below it.  Arithmetic per node is that of the other kernels:
+// four-colour Gauss-Seidel on the stored 9-point stencil, full weighting,
+// bilinear prolongation, explicit coarsest inverse.
 #include <type_traits>
 
 #include "tomg_internal.h"
@@ -36,6 +38,15 @@ struct Own {
   int col;  // colour (i mod 2) + 2 (j mod 2)
 };
 
+// Interior node k of colour col (i = pi + 2u, j = pj + 2w), or -1.
+__device__ __forceinline__ int colour_node(int nx, int ny, int col, int k) {
+  const int i0 = (col & 1) ? 1 : 2, j0 = (col >> 1) ? 1 : 2;
+  const int cu = nx - 2 >= i0 ? (nx - 2 - i0) / 2 + 1 : 0;
+  const int cw = ny - 2 >= j0 ? (ny - 2 - j0) / 2 + 1 : 0;
+  if (k >= cu * cw) return -1;
+  return (j0 + 2 * (k / cu)) * nx + i0 + 2 * (k % cu);
+}
+
 template <typename T>
 __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
   extern __shared__ unsigned char smem_raw[];
@@ -49,37 +60,41 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
     total += n;
     if (q < nl - 1) rmax = max(rmax, n);
   }
-  T *Rb = X + total;         // residual of the level being restricted
-  T *Bs = Rb + rmax;         // right-hand sides of streamed levels after the first
+  T *Rb = X + total;  // residual of the level being restricted
+  T *Bs = Rb + rmax;  // right-hand sides of streamed levels below the first
+  auto lvl = [&](int r) -> const TailLevel<T> & { return a.lv[nl - 1 - r]; };
 
-  Own<T> own[kTailLevels];
+  for (int q = 0; q < nl; ++q) {
+    const TailLevel<T> &v = a.lv[q];
+    for (int c = t; c < v.nx * v.ny; c += kTailThreads) X[v.off + c] = T(0);
+  }
+  Own<T> own[2];  // levels r = 0 (coarsest) and r = 1
 #pragma unroll
-  for (int q = 0; q < kTailLevels; ++q) {
-    Own<T> &o = own[q];
+  for (int r = 0; r < 2; ++r) {
+    Own<T> &o = own[r];
     o.c = -1;
     o.b = o.ik = T(0);
     o.col = 0;
 #pragma unroll
     for (int z = 0; z < 9; ++z) o.a[z] = T(0);
-    if (q >= nl) continue;
-    const TailLevel<T> &v = a.lv[q];
+    if (r >= nl) continue;
+    const TailLevel<T> &v = lvl(r);
     const int n = v.nx * v.ny;
-    for (int c = t; c < n; c += kTailThreads) X[v.off + c] = T(0);
-    if (n > kTailThreads || t >= n) continue;
+    if (t >= n) continue;
     const int i = t % v.nx, j = t / v.nx;
     o.c = t;
     o.col = (i & 1) + 2 * (j & 1);
     const bool interior = i > 0 && j > 0 && i < v.nx - 1 && j < v.ny - 1;
-    if (q < nl - 1 && interior && !v.dir[t]) {
+    if (r > 0 && interior && !v.dir[t]) {
 #pragma unroll
       for (int z = 0; z < 9; ++z) o.a[z] = v.st[(size_t)z * n + t];
       o.ik = T(1) / o.a[4];
     }
-    if (q == 0) o.b = v.b[t];
+    if (r == nl - 1) o.b = v.b[t];
   }
   __syncthreads();
 
-  // off-centre part of A x at node c of level v, from a stencil row s
+  // off-centre part of A x at node c of level v, from a stencil row s9
   auto offc = [&](const TailLevel<T> &v, const T *s9, int c) -> T {
     const T *x = X + v.off;
     const int w = v.nx;
@@ -92,55 +107,72 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
     for (int z = 0; z < 9; ++z) s9[z] = v.st[z * n + c];
   };
   auto rhs = [&](const TailLevel<T> &v, int c) -> T { return v.boff < 0 ? v.b[c] : Bs[v.boff + c]; };
-  auto streamed = [&](const TailLevel<T> &v) { return v.nx * v.ny > kTailThreads; };
 
-  auto smooth = [&](int q, int sweeps) {
-    const TailLevel<T> &v = a.lv[q];
-    const Own<T> &o = own[q];
-    const bool str = streamed(v);
-    for (int s = 0; s < sweeps; ++s)
-      for (int col = 0; col < 4; ++col) {
-        if (str) {
-          // interior nodes of this colour: i = pi + 2 u, j = pj + 2 w
-          const int pi = col & 1, pj = col >> 1;
-          const int i0 = pi ? 1 : 2, j0 = pj ? 1 : 2;
-          const int cu = v.nx - 2 >= i0 ? (v.nx - 2 - i0) / 2 + 1 : 0;
-          const int cw = v.ny - 2 >= j0 ? (v.ny - 2 - j0) / 2 + 1 : 0;
-          for (int k = t; k < cu * cw; k += kTailThreads) {
-            const int i = i0 + 2 * (k % cu), j = j0 + 2 * (k / cu);
-            const int c = j * v.nx + i;
-            if (v.dir[c]) continue;
-            T s9[9];
-            load_row(v, c, s9);
-            X[v.off + c] = (rhs(v, c) - offc(v, s9, c)) * (T(1) / s9[4]);
-          }
-        } else if (o.c >= 0 && o.col == col && o.ik != T(0)) {
-          X[v.off + o.c] = (o.b - offc(v, o.a, o.c)) * o.ik;
-        }
-        __syncthreads();
+  auto smooth = [&](int r, int sweeps) {
+    const TailLevel<T> &v = lvl(r);
+    if (r >= 2) {
+      // the node k = t of each colour, its stencil loaded one phase ahead
+      T s9n[9];
+      int cn = colour_node(v.nx, v.ny, 0, t), dn = 1;
+      if (cn >= 0) {
+        dn = v.dir[cn];
+        load_row(v, cn, s9n);
       }
+      for (int s = 0; s < sweeps; ++s)
+        for (int col = 0; col < 4; ++col) {
+          T s9[9];
+#pragma unroll
+          for (int z = 0; z < 9; ++z) s9[z] = s9n[z];
+          const int c = cn, d = dn;
+          if (s + 1 < sweeps || col < 3) {
+            cn = colour_node(v.nx, v.ny, (col + 1) & 3, t);
+            if (cn >= 0) {
+              dn = v.dir[cn];
+              load_row(v, cn, s9n);
+            }
+          }
+          if (c >= 0 && !d) X[v.off + c] = (rhs(v, c) - offc(v, s9, c)) * (T(1) / s9[4]);
+          for (int k = t + kTailThreads;; k += kTailThreads) {  // nodes beyond the first
+            const int c2 = colour_node(v.nx, v.ny, col, k);
+            if (c2 < 0) break;
+            if (v.dir[c2]) continue;
+            T s2[9];
+            load_row(v, c2, s2);
+            X[v.off + c2] = (rhs(v, c2) - offc(v, s2, c2)) * (T(1) / s2[4]);
+          }
+          __syncthreads();
+        }
+    } else {
+      const Own<T> &o = own[r & 1];
+      for (int s = 0; s < sweeps; ++s)
+        for (int col = 0; col < 4; ++col) {
+          if (o.c >= 0 && o.col == col && o.ik != T(0))
+            X[v.off + o.c] = (o.b - offc(v, o.a, o.c)) * o.ik;
+          __syncthreads();
+        }
+    }
   };
 
 #pragma unroll
-  for (int q = 0; q < kTailLevels - 1; ++q) {
-    if (q >= nl - 1) break;
-    const TailLevel<T> &v = a.lv[q], &cv = a.lv[q + 1];
-    smooth(q, a.nu1);
+  for (int r = kTailLevels - 1; r >= 1; --r) {
+    if (r > nl - 1) continue;
+    const TailLevel<T> &v = lvl(r), &cv = lvl(r - 1);
+    smooth(r, a.nu1);
     // residual into Rb, then full weighting into the coarse right-hand side
-    if (streamed(v)) {
+    if (r >= 2) {
       const int n = v.nx * v.ny;
       for (int c = t; c < n; c += kTailThreads) {
         const int i = c % v.nx, j = c / v.nx;
-        T r = T(0);
+        T res = T(0);
         if (i > 0 && j > 0 && i < v.nx - 1 && j < v.ny - 1 && !v.dir[c]) {
           T s9[9];
           load_row(v, c, s9);
-          r = rhs(v, c) - offc(v, s9, c) - s9[4] * X[v.off + c];
+          res = rhs(v, c) - offc(v, s9, c) - s9[4] * X[v.off + c];
         }
-        Rb[c] = r;
+        Rb[c] = res;
       }
     } else {
-      const Own<T> &o = own[q];
+      const Own<T> &o = own[r & 1];
       if (o.c >= 0)
         Rb[o.c] = o.ik != T(0) ? o.b - offc(v, o.a, o.c) - o.a[4] * X[v.off + o.c] : T(0);
     }
@@ -156,38 +188,34 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
         const T ee = Rb[f - w + 1] + T(2) * Rb[f + 1] + Rb[f + w + 1];
         s = (ww + T(2) * e + ee) * T(0.0625);
       }
-      if (streamed(cv))
+      if (r - 1 >= 2)
         Bs[cv.boff + C] = s;
       else
-        own[q + 1].b = s;  // C == t here
+        own[(r - 1) & 1].b = s;  // C == t: the level has at most 289 nodes
     }
     __syncthreads();
   }
   {  // coarsest level: x = A^-1 b
-    const int q = nl - 1;
-    const TailLevel<T> &v = a.lv[q];
+    const TailLevel<T> &v = lvl(0);
     const int n = v.nx * v.ny, m = a.cidx[n];
-    // owners of the coarsest level hold their rhs in own[q]
-#pragma unroll
-    for (int qq = 0; qq < kTailLevels; ++qq)
-      if (qq == q && t < n) {
-        const int k = a.cidx[t];
-        if (k >= 0) bb[k] = (double)own[qq].b;
-      }
+    if (t < n) {
+      const int k = a.cidx[t];
+      if (k >= 0) bb[k] = (double)own[0].b;
+    }
     __syncthreads();
     if (t < n) {
       const int k = a.cidx[t];
       double s = 0.0;
       if (k >= 0)
-        for (int r = 0; r < m; ++r) s += a.cinv[k * m + r] * bb[r];
+        for (int q = 0; q < m; ++q) s += a.cinv[k * m + q] * bb[q];
       X[v.off + t] = (T)s;
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = kTailLevels - 2; q >= 0; --q) {
-    if (q > nl - 2) continue;
-    const TailLevel<T> &v = a.lv[q], &cv = a.lv[q + 1];
+  for (int r = 1; r < kTailLevels; ++r) {
+    if (r > nl - 1) continue;
+    const TailLevel<T> &v = lvl(r), &cv = lvl(r - 1);
     const T *xc = X + cv.off;
     const int n = v.nx * v.ny;
     for (int c = t; c < n; c += kTailThreads) {
@@ -204,7 +232,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
       X[v.off + c] += e0;
     }
     __syncthreads();
-    smooth(q, a.nu2);
+    smooth(r, a.nu2);
   }
   // iterates of every tail level back to global memory
   for (int q = 0; q < nl; ++q) {
@@ -258,7 +286,7 @@ static TailArgs<T> make_tail_args(tomg_problem *p, int lc) {
     a.lv[q].off = off;
     const int n = v.nx * v.ny;
     a.lv[q].boff = -1;
-    if (q > 0 && n > kTailThreads) {
+    if (q > 0 && q < a.nl - 2) {  // streamed level below the first
       a.lv[q].boff = boff;
       boff += n;
     }
