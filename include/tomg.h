@@ -152,8 +152,11 @@ tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
  * and a problem leaves the batch as soon as it converges.  Per-problem host
  * outputs cycles_out[n], rel_out[n], status_out[n] (nullable).  Returns
  * TOMG_OK when every problem converged, else the first failing status.  The
- * per-problem arithmetic is the same as solve(), so each result is bitwise
- * equal to the problem solved alone.  1 <= n <= 4096.  Batched launches need
+ * per-node arithmetic is that of solve(), so after the same number of cycles
+ * each iterate is bitwise the one solve() gives; a batched pass uses taller
+ * row bands, so the level-0 residual norm is summed in another order and the
+ * reported relative residual may differ from solve()'s in the last bits.
+ * 1 <= n <= 4096.  Batched launches need
  * one cycle configuration (precision, nu1, nu2, four-colour smoother,
  * ir_inner_cycles); other mixes are solved one after another.  Work the
  * caller queued for a problem on another stream must be ordered before the
@@ -171,7 +174,7 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
  * launches as tomg_solve_batch.  rel_out[k] (host) receives each problem's
  * relative residual after the step; the caller decides when a problem
  * leaves.  A problem's sequence of steps gives bitwise the iterates of
- * solve() whatever other problems share the steps.  All problems need one
+ * solve() whatever other problems share the steps (and when they joined).  All problems need one
  * cycle configuration (else TOMG_EINVAL) and a completed setup_coeffs (else
  * TOMG_ESTATE); runs on the stream of probs[0] and synchronises it. */
 tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,

@@ -360,9 +360,10 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
 
 // Batched solve.  Every stage of a cycle is one launch (per kBatchMax
 // problems) across the problems still iterating; stages are aligned from
-// the finest level, each problem taking part in the levels it has.  Each
-// problem runs exactly the blocks and reductions it runs alone, so its
-// result is bitwise that of solve().
+// the finest level, each problem taking part in the levels it has.  Every
+// node sees the arithmetic of solve(), so each iterate is bitwise that of
+// solve() after the same number of cycles (a batched pass uses taller row
+// bands, so its residual norm is summed in another order).
 }  // extern "C"
 
 namespace {

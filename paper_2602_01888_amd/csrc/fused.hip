@@ -471,7 +471,18 @@ static int env_int(const char *name, int dflt) {
 // levels above 2M nodes, where the pass is bound by memory traffic, at least
 // three halo depths tall so that halo rows add at most two thirds to it.
 // TOMG_CH_L<level> forces the band of one level (tuning only).
+//
+// In a batch the other problems fill the device, so a problem's passes use
+// taller bands (less halo work): the tallest band up to 128 rows that still
+// gives 1024 blocks, and at least 16 rows.
 constexpr int kMinBand = 2;
+static int pick_band_batch(int nx, int ny, int W) {
+  const int bx = (nx + W - 1) / W;
+  int CH = 128;
+  while (CH > 16 && (long)bx * ((ny + CH - 1) / CH) < 1024) CH >>= 1;
+  return CH;
+}
+
 static int pick_band(int nx, int ny, int W, int level, long slots, int hv) {
   char name[32];
   snprintf(name, sizeof name, "TOMG_CH_L%d", level);
@@ -567,8 +578,8 @@ static long pass_slots(int l, bool up, int nu) {
 // Arguments of the down (up) pass of level l in precision T: the level
 // iterate x_l is read (written) and its second buffer written (read).
 template <typename T>
-static PassArgs<T> make_args(tomg_problem *p, int l, bool up, T *x0, T *pong0, const T *b0,
-                             const T *exx, const T *exy, const T *eyy) {
+static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0, T *pong0,
+                             const T *b0, const T *exx, const T *exy, const T *eyy) {
   PassArgs<T> a{};
   const Level &v = p->lv[l];
   const bool f32 = std::is_same<T, float>::value;
@@ -599,7 +610,8 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, T *x0, T *pong0, c
   a.partials = (up && l == 0) ? p->partials : nullptr;
   const int nu = up ? p->cfg.nu2 : p->cfg.nu1;
   a.W = kBW - 2 * (4 * nu + 2);
-  a.CH = pick_band(a.nx, a.ny, a.W, l, pass_slots<T>(l, up, nu), 2 * nu + 3);
+  a.CH = batch ? pick_band_batch(a.nx, a.ny, a.W)
+              : pick_band(a.nx, a.ny, a.W, l, pass_slots<T>(l, up, nu), 2 * nu + 3);
   a.nbx = (a.nx + a.W - 1) / a.W;
   a.nby = (a.ny + a.CH - 1) / a.CH;
   return a;
@@ -610,16 +622,21 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, T *x0, T *pong0, c
 // per launch (nullptr here).
 void build_pass_args(tomg_problem *p) {
   ArgsBlob &g = p->hargs;
-  for (int l = 0; l + 1 < p->L; ++l) {
-    g.down64[l] = make_args<double>(p, l, false, nullptr, p->tmp, p->f, p->exx, p->exy, p->eyy);
-    g.up64[l] = make_args<double>(p, l, true, nullptr, p->tmp, p->f, p->exx, p->exy, p->eyy);
-    if (p->cfg.precision == TOMG_FP32_IR) {
-      g.down32[l] = make_args<float>(p, l, false, p->e32, p->e32b, p->r32, p->exx32, p->exy32,
-                                     p->eyy32);
-      g.up32[l] = make_args<float>(p, l, true, p->e32, p->e32b, p->r32, p->exx32, p->exy32,
-                                   p->eyy32);
+  for (int l = 0; l + 1 < p->L; ++l)
+    for (int batch = 0; batch < 2; ++batch) {
+      PassArgs<double> *d64 = batch ? g.down64b : g.down64, *u64 = batch ? g.up64b : g.up64;
+      PassArgs<float> *d32 = batch ? g.down32b : g.down32, *u32 = batch ? g.up32b : g.up32;
+      d64[l] = make_args<double>(p, l, false, batch, nullptr, p->tmp, p->f, p->exx, p->exy,
+                                 p->eyy);
+      u64[l] = make_args<double>(p, l, true, batch, nullptr, p->tmp, p->f, p->exx, p->exy,
+                                 p->eyy);
+      if (p->cfg.precision == TOMG_FP32_IR) {
+        d32[l] = make_args<float>(p, l, false, batch, p->e32, p->e32b, p->r32, p->exx32,
+                                  p->exy32, p->eyy32);
+        u32[l] = make_args<float>(p, l, true, batch, p->e32, p->e32b, p->r32, p->exx32,
+                                  p->exy32, p->eyy32);
+      }
     }
-  }
 }
 
 template <typename T>
@@ -712,14 +729,14 @@ static void batch_pass(tomg_problem *const *probs, const int *idx, int cnt, int 
     const PassArgs<T> *first = nullptr;
     for (int k = k0; k < cnt && k < k0 + kBatchMax; ++k) {
       tomg_problem *p = probs[idx[k]];
-      const PassArgs<T> *h = f32 ? (const PassArgs<T> *)(void *)(up ? &p->hargs.up32[l]
-                                                                      : &p->hargs.down32[l])
-                                 : (const PassArgs<T> *)(void *)(up ? &p->hargs.up64[l]
-                                                                      : &p->hargs.down64[l]);
-      const PassArgs<T> *d = f32 ? (const PassArgs<T> *)(void *)(up ? &p->dargs->up32[l]
-                                                                      : &p->dargs->down32[l])
-                                 : (const PassArgs<T> *)(void *)(up ? &p->dargs->up64[l]
-                                                                      : &p->dargs->down64[l]);
+      const PassArgs<T> *h = f32 ? (const PassArgs<T> *)(void *)(up ? &p->hargs.up32b[l]
+                                                                      : &p->hargs.down32b[l])
+                                 : (const PassArgs<T> *)(void *)(up ? &p->hargs.up64b[l]
+                                                                      : &p->hargs.down64b[l]);
+      const PassArgs<T> *d = f32 ? (const PassArgs<T> *)(void *)(up ? &p->dargs->up32b[l]
+                                                                      : &p->dargs->down32b[l])
+                                 : (const PassArgs<T> *)(void *)(up ? &p->dargs->up64b[l]
+                                                                      : &p->dargs->down64b[l]);
       if (!first) first = h;
       BatchEntry &e = tab.e[tab.count++];
       e.args = d;

@@ -728,10 +728,30 @@ __global__ void k_coarse_solve(const double *inv, const int *cidx, const T *b, T
 }
 
 // STREAM-style copy, 16 bytes per lane per iteration.
+// Streaming copy used as the bandwidth reference beside the solver: four
+// 16-byte loads in flight per thread, non-temporal loads and stores.
 __global__ void k_copy16(const double2 *__restrict__ src, double2 *__restrict__ dst, size_t n) {
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)gridDim.x * blockDim.x)
-    dst[c] = src[c];
+  constexpr int U = 4;
+  const size_t stride = (size_t)gridDim.x * blockDim.x * U;
+  for (size_t b = (size_t)blockIdx.x * blockDim.x * U + threadIdx.x; b < n; b += stride) {
+    double2 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const size_t c = b + (size_t)k * blockDim.x;
+      if (c < n) {
+        v[k].x = __builtin_nontemporal_load(&src[c].x);
+        v[k].y = __builtin_nontemporal_load(&src[c].y);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const size_t c = b + (size_t)k * blockDim.x;
+      if (c < n) {
+        __builtin_nontemporal_store(v[k].x, &dst[c].x);
+        __builtin_nontemporal_store(v[k].y, &dst[c].y);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -980,8 +1000,9 @@ void build_red_args(tomg_problem *p) {
   r.nblk = red_blocks(p->lv[0].n);
   p->hargs.fin_red = {p->partials, p->scal, r.nblk};
   p->hargs.fin_red0 = {p->partials + r.nblk, p->scal, r.nblk};
-  const PassArgs<double> &u = p->hargs.up64[0];
+  const PassArgs<double> &u = p->hargs.up64[0], &ub = p->hargs.up64b[0];
   p->hargs.fin_norm = {p->partials, p->scal, u.nbx * u.nby};
+  p->hargs.fin_normb = {p->partials, p->scal, ub.nbx * ub.nby};
 }
 
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
@@ -1095,7 +1116,7 @@ void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kin
       tomg_problem *p = probs[idx[k]];
       BatchEntry &e = tab.e[tab.count];
       e.args = kind == 0   ? (const void *)&p->dargs->fin_red
-               : kind == 1 ? (const void *)&p->dargs->fin_norm
+               : kind == 1 ? (const void *)&p->dargs->fin_normb
                            : (const void *)&p->dargs->fin_red0;
       e.phi = nullptr;
       e.role = 0;
@@ -1117,7 +1138,7 @@ hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps) {
 
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 16;
-  hipLaunchKernelGGL(k_copy16, 8192, 256, 0, s, (const double2 *)src, (double2 *)dst, n);
+  hipLaunchKernelGGL(k_copy16, 2048, 256, 0, s, (const double2 *)src, (double2 *)dst, n);
   return hipGetLastError();
 }
 

@@ -105,11 +105,16 @@ struct FinArgs {
 struct ArgsBlob {
   PassArgs<double> down64[kMaxLevels], up64[kMaxLevels];
   PassArgs<float> down32[kMaxLevels], up32[kMaxLevels];
+  // the same passes as launched in a batch: taller bands, since the other
+  // problems of the batch fill the device
+  PassArgs<double> down64b[kMaxLevels], up64b[kMaxLevels];
+  PassArgs<float> down32b[kMaxLevels], up32b[kMaxLevels];
   TailArgs<double> tail64;
   TailArgs<float> tail32;
   RedArgs red;
   FinArgs fin_red, fin_norm, fin_red0;  // partials of the reductions, the up pass,
                                         // and the second half of a two-norm pass
+  FinArgs fin_normb;                    // the up pass as launched in a batch
 };
 
 // One problem's share of a batched launch: blocks [start, start + nbx*nby).

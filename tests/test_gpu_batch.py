@@ -1,6 +1,7 @@
 """Batched execution (tomg_solve_batch): every problem's result is bitwise
-the result of solving it alone, in both precisions, and a problem that fails
-leaves the others untouched."""
+the result of solving it alone (same cycles, same iterate; the residual norm
+may differ in the last bits since a batched pass sums it over other blocks),
+in both precisions, and a problem that fails leaves the others untouched."""
 
 import numpy as np
 import pytest
@@ -36,7 +37,8 @@ def test_batch_equals_alone(tomg, precision):
     for p, d, phi, r in zip(ps, ds, phis, res):
         alone = d["phi0"].clone()
         ra = p.solve(alone, rel_tol=1e-10, max_cycles=60)
-        assert ra.cycles == r.cycles and ra.rel == r.rel
+        # same iterate; the batched norm sums its partials in another order
+        assert ra.cycles == r.cycles and abs(ra.rel - r.rel) <= 1e-12 * ra.rel
         assert bool((alone == phi).all())
 
 
