@@ -173,21 +173,33 @@ __device__ __forceinline__ double d_j(const double *a, int nx, int ny, int j, si
   return (a[c + s] - a[c - s]) * inv2h;
 }
 
-// One workgroup per row (grid-stride over rows), threads along the row.
-// When exx32 is given the FP32 copies of the tensor used by the inner solver
+// Grid-stride over the nodes in memory order, so that the whole grid of
+// threads sweeps one contiguous window of the arrays.  When exx32 is given the FP32 copies of the tensor used by the inner solver
 // of iterative refinement are written beside the FP64 fields.
-__global__ void k_setup(int nx, int ny, double dx, double dy, const double *xp, const double *yp,
-                        const double *jac, const double *epsp, const double *rho,
-                        const uint8_t *mask, double *exx, double *exy, double *eyy, double *det,
-                        double *f, uint8_t *dir, float *exx32, float *exy32, float *eyy32,
-                        double *partials) {
+__global__ void k_setup(int nx, int ny, double dx, double dy, const double *__restrict__ xp,
+                        const double *__restrict__ yp, const double *__restrict__ jac,
+                        const double *__restrict__ epsp, const double *__restrict__ rho,
+                        const uint8_t *__restrict__ mask, double *__restrict__ exx,
+                        double *__restrict__ exy, double *__restrict__ eyy,
+                        double *__restrict__ det, double *__restrict__ f,
+                        uint8_t *__restrict__ dir, float *__restrict__ exx32,
+                        float *__restrict__ exy32, float *__restrict__ eyy32,
+                        double *__restrict__ partials) {
   const size_t n = (size_t)nx * ny;
   const double i2dx = 0.5 / dx, i2dy = 0.5 / dy;
   double mind = INFINITY, bad = 0.0;
-  for (int j = blockIdx.x; j < ny; j += gridDim.x) {
-    const size_t row = (size_t)j * nx;
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-      const size_t c = row + i;
+  const bool small = n < (size_t(1) << 32);
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    {
+      int i, j;
+      if (small) {
+        j = (int)((unsigned)c / (unsigned)nx);
+        i = (int)((unsigned)c - (unsigned)j * (unsigned)nx);
+      } else {
+        j = (int)(c / nx);
+        i = (int)(c - (size_t)j * nx);
+      }
       double jxx, jxy, jyx, jyy;
       if (jac) {
         jxx = jac[c];
@@ -206,11 +218,11 @@ __global__ void k_setup(int nx, int ny, double dx, double dy, const double *xp, 
       const double vxy = s * (-jyy * jyx - jxy * jxx) / D;
       const double vyy = s * (jyx * jyx + jxx * jxx) / D;
       const double fv = -rho[c] * D;
-      exx[c] = vxx;
-      exy[c] = vxy;
-      eyy[c] = vyy;
-      det[c] = D;
-      f[c] = fv;
+      __builtin_nontemporal_store(vxx, exx + c);
+      __builtin_nontemporal_store(vxy, exy + c);
+      __builtin_nontemporal_store(vyy, eyy + c);
+      __builtin_nontemporal_store(D, det + c);
+      __builtin_nontemporal_store(fv, f + c);
       if (exx32) {
         exx32[c] = (float)vxx;
         exy32[c] = (float)vxy;
@@ -350,6 +362,124 @@ __global__ __launch_bounds__(kGX *kGY) void k_coarsen(Op opf, const uint8_t *dir
                 const int du = u - 2 * oi, dv = v - 2 * oj;
                 if (du >= -1 && du <= 1 && dv >= -1 && dv <= 1)
                   acc[(oj + 1) * 3 + oi + 1] += (pw(a) * pw(b) * pw(du) * pw(dv)) * s;
+              }
+          }
+      }
+#pragma unroll
+    for (int oj = -1; oj <= 1; ++oj)
+#pragma unroll
+      for (int oi = -1; oi <= 1; ++oi) {
+        double &v = acc[(oj + 1) * 3 + oi + 1];
+        v = DC[ty + 1 + oj][tx + 1 + oi] ? 0.0 : v * 0.25;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) stc[k * nc + C] = acc[k];
+  if (stc32) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) stc32[k * nc + C] = (float)acc[k];
+  }
+}
+
+// Level-1 coarsening straight from the tensor: the workgroup stages ε_xx,
+// ε_xy, ε_yy of its fine window in LDS (one coalesced load per value instead
+// of nine per fine stencil), and each thread forms the nine fine stencils of
+// its coarse node from LDS with the level-0 formula (the same expressions as
+// EpsOp::coefs, so the products and their order are those of k_coarsen).
+constexpr int kGEX = 2 * kGX + 3, kGEY = 2 * kGY + 3;  // tensor window, origin 2 I0 - 2
+
+__global__ __launch_bounds__(kGX *kGY) void k_coarsen_eps(EpsOp<double> op, const uint8_t *dirf,
+                                                          int nxf, int nyf, int nxc, int nyc,
+                                                          uint8_t *dirc, double *stc,
+                                                          float *stc32) {
+  __shared__ double E[3][kGEY][kGEX];
+  __shared__ uint8_t DF[kGDY][kGDX];
+  __shared__ uint8_t DC[kGCY][kGCX];
+  constexpr int NT = kGX * kGY;
+  const int t = threadIdx.x;
+  const int I0 = blockIdx.x * kGX, J0 = blockIdx.y * kGY;
+  for (int k = t; k < kGDX * kGDY; k += NT) {
+    const int x = k % kGDX, y = k / kGDX;
+    const int fi = 2 * I0 - 3 + x, fj = 2 * J0 - 3 + y;
+    DF[y][x] = (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) ? 1 : dirf[(size_t)fj * nxf + fi];
+  }
+  for (int k = t; k < kGEX * kGEY; k += NT) {
+    const int x = k % kGEX, y = k / kGEX;
+    const int fi = min(max(2 * I0 - 2 + x, 0), nxf - 1), fj = min(max(2 * J0 - 2 + y, 0), nyf - 1);
+    const size_t c = (size_t)fj * nxf + fi;
+    E[0][y][x] = op.exx[c];
+    E[1][y][x] = op.exy[c];
+    E[2][y][x] = op.eyy[c];
+  }
+  __syncthreads();
+  for (int k = t; k < kGCX * kGCY; k += NT) {
+    const int x = k % kGCX, y = k / kGCX;
+    const int I = I0 - 1 + x, J = J0 - 1 + y;
+    uint8_t d = 1;
+    if (I >= 0 && J >= 0 && I < nxc && J < nyc) {
+      d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
+      if (!d) {
+        bool all = true;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) all = all && DF[2 * y + 1 + b][2 * x + 1 + a];
+        d = all;
+      }
+      if (x >= 1 && y >= 1 && x <= kGX && y <= kGY) dirc[(size_t)J * nxc + I] = d;
+    }
+    DC[y][x] = d;
+  }
+  __syncthreads();
+  const int tx = t % kGX, ty = t / kGX;
+  const int I = I0 + tx, J = J0 + ty;
+  if (I >= nxc || J >= nyc) return;
+  const size_t nc = (size_t)nxc * nyc, C = (size_t)J * nxc + I;
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  if (DC[ty + 1][tx + 1]) {
+    acc[4] = 1.0;
+  } else {
+#pragma unroll
+    for (int b = -1; b <= 1; ++b)
+#pragma unroll
+      for (int a = -1; a <= 1; ++a) {
+        const int dx = 2 * tx + a + 3, dy = 2 * ty + b + 3;  // fine node in the flag window
+        const int ex = dx - 1, ey = dy - 1;                 // and in the tensor window
+        double s[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s[q] = 0.0;
+        if (!DF[dy][dx]) {
+          const double ax = E[0][ey][ex] * op.cx, ay = E[2][ey][ex] * op.cy;
+          const double gx = (E[0][ey][ex + 1] - E[0][ey][ex - 1]) * op.qx +
+                            (E[1][ey + 1][ex] - E[1][ey - 1][ex]) * op.qxy;
+          const double gy = (E[2][ey + 1][ex] - E[2][ey - 1][ex]) * op.qy +
+                            (E[1][ey][ex + 1] - E[1][ey][ex - 1]) * op.qxy;
+          const double k1 = ax + gx, k3 = ax - gx, k4 = ay + gy, k5 = ay - gy;
+          const double k6 = E[1][ey][ex] * op.hxy, k2 = 2.0 * (ax + ay);
+          s[0] = k6;  s[1] = k5; s[2] = -k6;
+          s[3] = k3;  s[4] = -k2; s[5] = k1;
+          s[6] = -k6; s[7] = k4; s[8] = k6;
+#pragma unroll
+          for (int q = -1; q <= 1; ++q)
+#pragma unroll
+            for (int pp = -1; pp <= 1; ++pp)
+              if (DF[dy + q][dx + pp]) s[(q + 1) * 3 + pp + 1] = 0.0;
+        }
+#pragma unroll
+        for (int q = -1; q <= 1; ++q)
+#pragma unroll
+          for (int pp = -1; pp <= 1; ++pp) {
+            const double v = s[(q + 1) * 3 + pp + 1];
+            const int u = a + pp, w = b + q;
+#pragma unroll
+            for (int oj = -1; oj <= 1; ++oj)
+#pragma unroll
+              for (int oi = -1; oi <= 1; ++oi) {
+                const int du = u - 2 * oi, dv = w - 2 * oj;
+                if (du >= -1 && du <= 1 && dv >= -1 && dv <= 1)
+                  acc[(oj + 1) * 3 + oi + 1] += (pw(a) * pw(b) * pw(du) * pw(dv)) * v;
               }
           }
       }
@@ -943,8 +1073,8 @@ hipError_t launch_hierarchy(tomg_problem *p) {
     const dim3 grid((lc.nx + kGX - 1) / kGX, (lc.ny + kGY - 1) / kGY);
     float *st32 = f32 ? lc.st32 : nullptr;
     if (l == 1)
-      hipLaunchKernelGGL((k_coarsen<EpsOp<double>>), grid, kGX * kGY, 0, p->stream, op64(p),
-                         lf.dir, lf.nx, lf.ny, lc.nx, lc.ny, lc.dir, lc.st, st32);
+      hipLaunchKernelGGL(k_coarsen_eps, grid, kGX * kGY, 0, p->stream, op64(p), lf.dir, lf.nx,
+                         lf.ny, lc.nx, lc.ny, lc.dir, lc.st, st32);
     else
       hipLaunchKernelGGL((k_coarsen<StOp<double>>), grid, kGX * kGY, 0, p->stream,
                          st_op<double>(lf.st, lf.nx, lf.ny), lf.dir, lf.nx, lf.ny, lc.nx, lc.ny,
