@@ -30,6 +30,7 @@ def _load():
     sig = {
         "orc_num_threads": (i, []),
         "orc_jacobian_numeric": (i, [i, i, d, d, _D, _D, _D, _D, _D, _D]),
+        "orc_field": (None, [i, i, d, d, _D, _D, _D, _D, _D, _D, _D]),
         "orc_permittivity": (None, [sz, _D, _D, _D, _D, _D, _D, _D, _D, _D]),
         "orc_geometry_ok": (i, [i, i, _D]),
         "orc_rhs": (None, [sz, _D, _D, _D]),
@@ -98,6 +99,18 @@ def jacobian_numeric(xp, yp, dx, dy):
     if rc != 0:
         raise ValueError("grid too small for the numeric Jacobian")
     return J
+
+
+def field(phi, jac, dx, dy):
+    """Physical electric field E' = (J^T)^-1 (-grad phi) at every node (eq. 2);
+    grad phi by the differences of eq. 39-42 (one-sided on the edges).
+    Returns (Ex', Ey')."""
+    phi, jac = _f64(phi), _f64(jac)
+    ny, nx = phi.shape
+    ex, ey = np.empty_like(phi), np.empty_like(phi)
+    _load().orc_field(nx, ny, dx, dy, _d(phi), _d(jac[0]), _d(jac[1]), _d(jac[2]), _d(jac[3]),
+                      _d(ex), _d(ey))
+    return ex, ey
 
 
 def permittivity(jac, eps_phys=None):

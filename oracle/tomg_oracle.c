@@ -62,6 +62,25 @@ static double d_along_j(const double *a, int nx, int ny, int i, int j, double h)
   return (a[ID(i, j + 1, nx)] - a[ID(i, j - 1, nx)]) / (2.0 * h);
 }
 
+/* Field recovery (eq. 2 with E = -grad phi on the computational grid):
+ * E' = (J^T)^-1 E.  grad phi by the same differences as the Jacobian (eq.
+ * 39-42 in the interior, one-sided second order on the edges).  J given as
+ * four planes jxx = dx'/dxi, jxy = dx'/deta, jyx = dy'/dxi, jyy = dy'/deta.
+ * (J^T)^-1 = [[jyy, -jyx], [-jxy, jxx]] / det J. */
+void orc_field(int nx, int ny, double dx, double dy, const double *phi, const double *jxx,
+               const double *jxy, const double *jyx, const double *jyy, double *ex,
+               double *ey) {
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t c = ID(i, j, nx);
+      const double e1 = -d_along_i(phi, nx, i, j, dx); /* E = -grad phi */
+      const double e2 = -d_along_j(phi, nx, ny, i, j, dy);
+      const double det = jxx[c] * jyy[c] - jxy[c] * jyx[c];
+      ex[c] = (jyy[c] * e1 - jyx[c] * e2) / det;
+      ey[c] = (-jxy[c] * e1 + jxx[c] * e2) / det;
+    }
+}
+
 int orc_jacobian_numeric(int nx, int ny, double dx, double dy, const double *xp,
                          const double *yp, double *jxx, double *jxy, double *jyx,
                          double *jyy) {

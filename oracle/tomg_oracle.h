@@ -31,6 +31,10 @@ int orc_num_threads(void);
 
 /* Jacobian by central differences (eq. 39-42) in the interior and
  * second-order one-sided differences on the grid edges.  Needs nx, ny >= 3. */
+/* E' = (J^T)^-1 (-grad phi) at every node (eq. 2). */
+void orc_field(int nx, int ny, double dx, double dy, const double *phi, const double *jxx,
+               const double *jxy, const double *jyx, const double *jyy, double *ex,
+               double *ey);
 int orc_jacobian_numeric(int nx, int ny, double dx, double dy, const double *xp,
                          const double *yp, double *jxx, double *jxy, double *jyx,
                          double *jyy);
