@@ -20,6 +20,7 @@ Also measured in the same run (extra keys of the line):
                 solved together by one tomg_solve_batch call (mixed
                 precision, and FP64 beside it), against solving them one
                 after another;
+  field       : field recovery E' = (J^T)^-1 (-grad phi) of the solution;
   serving     : a stream of requests (sides 129..2049, perturbed-circle or
                 sinusoidal geometries, 30% warm re-solves of a resident
                 geometry with new sources) served by continuous batching:
@@ -374,6 +375,19 @@ def main():
     torch.cuda.synchronize()
     solve_only = (time.perf_counter() - t1) / args.steps
 
+    # field recovery (eq. 2) of the solution: E' from phi and the numeric map
+    p64.field(phi, xp=d["xp"], yp=d["yp"])
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        p64.field(phi, xp=d["xp"], yp=d["yp"])
+    ev1.record()
+    torch.cuda.synchronize()
+    field_ms = ev0.elapsed_time(ev1) / 10
+    field = {"kernel": "tomg_field (E' = J^-T (-grad phi), numeric Jacobian)",
+             "ms": field_ms, "algorithmic_bytes": 40 * n0,
+             "GBs": 40 * n0 / (field_ms * 1e-3) / 1e9}
+
     # HBM copy ceiling beside the solver
     a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     b = torch.empty_like(a)
@@ -522,6 +536,7 @@ def main():
         "mixed": mixed,
         "batch": batch,
         "serving": serving,
+        "field": field,
         "accuracy": accuracy,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -180,6 +180,18 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
 tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,
                             const int32_t *fresh, double *rel_out);
 
+/* Field recovery (eq. 2): the physical electric field E' = (J^T)^-1 E with
+ * E = -grad phi on the uniform grid, at every node of the problem's grid.
+ * grad phi uses the differences of eq. 39-42 (central inside, one-sided
+ * second order on the edges).  The map is given as for setup_coeffs: d_jac
+ * ([4][ny][nx] analytic partials, nullable) or the node coordinates d_xp,
+ * d_yp (numeric Jacobian).  d_phi, d_ex, d_ey: double[ny][nx] on the device
+ * (d_ex, d_ey written).  Does not need setup_coeffs.  Where det J = 0 (for
+ * example the corner nodes of a square-to-disc map) the result is not
+ * finite.  Asynchronous on the problem's stream. */
+tomg_status tomg_field(tomg_problem *p, const double *d_phi, const double *d_xp,
+                       const double *d_yp, const double *d_jac, double *d_ex, double *d_ey);
+
 /* ---- diagnostics: read back internal arrays (parity testing) ----------- */
 enum {
   TOMG_FIELD_EXX = 0,    /* level 0, nx*ny doubles */

@@ -168,6 +168,20 @@ class Problem:
                     "residual_norm")
         return a.value, r.value
 
+    def field(self, phi, xp=None, yp=None, jac=None):
+        """tomg_field: (Ex', Ey') of the potential phi under the map given by
+        jac or by the node coordinates xp, yp."""
+        shp = (self.ny, self.nx)
+        ex = torch.empty(shp, dtype=torch.float64, device=self.device)
+        ey = torch.empty_like(ex)
+        self._check(self.lib.tomg_field(self._h, _ptr(phi, torch.float64, shp, "phi"),
+                                        _ptr(xp, torch.float64, shp, "xp"),
+                                        _ptr(yp, torch.float64, shp, "yp"),
+                                        _ptr(jac, torch.float64, (4,) + shp, "jac"),
+                                        C.c_void_p(ex.data_ptr()), C.c_void_p(ey.data_ptr())),
+                    "field")
+        return ex, ey
+
     # -- diagnostics ----------------------------------------------------------
     def export(self, what: str, level: int = 0) -> torch.Tensor:
         nx, ny = self.level_shape(level)

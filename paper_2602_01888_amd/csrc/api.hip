@@ -529,6 +529,17 @@ tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, i
   return TOMG_OK;
 }
 
+tomg_status tomg_field(tomg_problem *p, const double *d_phi, const double *d_xp,
+                       const double *d_yp, const double *d_jac, double *d_ex, double *d_ey) {
+  if (!p || !d_phi || !d_ex || !d_ey) return TOMG_EINVAL;
+  if (!d_jac && (!d_xp || !d_yp))
+    return fail(p, TOMG_EINVAL, "field: need the node coordinates or the Jacobian");
+  if (!d_jac && (p->cfg.nx < 3 || p->cfg.ny < 3))
+    return fail(p, TOMG_EINVAL, "field: numeric Jacobian needs 3 nodes per side");
+  HIP_TRY(p, launch_field(p, d_phi, d_xp, d_yp, d_jac, d_ex, d_ey));
+  return TOMG_OK;
+}
+
 tomg_status tomg_level_shape(const tomg_problem *p, int32_t level, int32_t *nx, int32_t *ny) {
   if (!p || level < 0 || level >= p->L) return TOMG_EINVAL;
   if (nx) *nx = p->lv[level].nx;

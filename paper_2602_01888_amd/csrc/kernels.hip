@@ -245,6 +245,46 @@ __global__ void k_setup(int nx, int ny, double dx, double dy, const double *__re
   }
 }
 
+// Field recovery (eq. 2): E' = (J^T)^-1 E with E = -grad phi on the uniform
+// grid, at every node.  grad phi and the numeric Jacobian use the same
+// differences (eq. 39-42, one-sided second order on the edges); an analytic
+// Jacobian is taken from jac when given.  Memory-order grid stride.
+__global__ void k_field(int nx, int ny, double dx, double dy, const double *__restrict__ phi,
+                        const double *__restrict__ xp, const double *__restrict__ yp,
+                        const double *__restrict__ jac, double *__restrict__ ex,
+                        double *__restrict__ ey) {
+  const size_t n = (size_t)nx * ny;
+  const double i2dx = 0.5 / dx, i2dy = 0.5 / dy;
+  const bool small = n < (size_t(1) << 32);
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    int i, j;
+    if (small) {
+      j = (int)((unsigned)c / (unsigned)nx);
+      i = (int)((unsigned)c - (unsigned)j * (unsigned)nx);
+    } else {
+      j = (int)(c / nx);
+      i = (int)(c - (size_t)j * nx);
+    }
+    double jxx, jxy, jyx, jyy;
+    if (jac) {
+      jxx = jac[c];
+      jxy = jac[n + c];
+      jyx = jac[2 * n + c];
+      jyy = jac[3 * n + c];
+    } else {
+      jxx = d_i(xp, nx, i, c, i2dx);
+      jxy = d_j(xp, nx, ny, j, c, i2dy);
+      jyx = d_i(yp, nx, i, c, i2dx);
+      jyy = d_j(yp, nx, ny, j, c, i2dy);
+    }
+    const double e1 = -d_i(phi, nx, i, c, i2dx), e2 = -d_j(phi, nx, ny, j, c, i2dy);
+    const double D = jxx * jyy - jxy * jyx;
+    __builtin_nontemporal_store((jyy * e1 - jyx * e2) / D, ex + c);
+    __builtin_nontemporal_store((-jxy * e1 + jxx * e2) / D, ey + c);
+  }
+}
+
 __global__ void k_update_rhs(const double *rho, const double *det, double *f, size_t n,
                              double *partials) {
   double bad = 0.0;
@@ -1054,6 +1094,13 @@ hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, con
                      p->scal + kSlotMinDet, 0, p->scal, 0);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
                      2, p->scal + kSlotBad, 0, p->scal, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, const double *yp,
+                        const double *jac, double *ex, double *ey) {
+  hipLaunchKernelGGL(k_field, 2048, 256, 0, p->stream, p->cfg.nx, p->cfg.ny, p->cfg.dx, p->cfg.dy,
+                     phi, xp, yp, jac, ex, ey);
   return hipGetLastError();
 }
 

@@ -205,6 +205,8 @@ hipError_t launch_ir_residual(tomg_problem *p, const double *phi);
 hipError_t launch_ir_correct(tomg_problem *p, double *phi);
 hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free);
 hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir);
+hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, const double *yp,
+                        const double *jac, double *ex, double *ey);
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps);
 hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
