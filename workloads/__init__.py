@@ -20,6 +20,8 @@ from .gen import (  # noqa: F401
     polar_semi_annulus,
     sinh_stretch,
     square_to_disc,
+    disc_boundary,
+    disc_on_grid,
     gaussian_sources,
     random_sinusoidal,
     batch_mixed,

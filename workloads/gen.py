@@ -205,6 +205,49 @@ def square_to_disc(n: int, b: float, kind: str) -> GridProblem:
                        _phi0_from(phi, ring), jac=jac, phi_exact=phi, meta={"b": b})
 
 
+def disc_boundary(n: int, b: float):
+    """Boundary data of the numerically generated circular grid of Section
+    4.2 (eq. 44) on the computational square [-b, b]^2: returns (xb, yb), node
+    arrays holding x'(xi, eta), y'(xi, eta) of eq. 44 on the outer ring and
+    zero elsewhere (the interior is found by solving eq. 36-37)."""
+    d = 2.0 * b / (n - 1)
+    XI, ETA = _grid(n, n, -b, -b, d, d)
+    xb, yb = np.zeros((n, n)), np.zeros((n, n))
+    # bottom (eta = -b) and top (eta = b): x' = xi / sqrt 2, y' = -+b sqrt(1 - xi^2/(2b^2))
+    for row, sgn in ((0, -1.0), (n - 1, 1.0)):
+        xb[row] = XI[row] / math.sqrt(2.0)
+        yb[row] = sgn * b * np.sqrt(1.0 - XI[row] ** 2 / (2 * b * b))
+    # left (xi = -b) and right (xi = b): x' = -+b sqrt(1 - eta^2/(2b^2)), y' = eta / sqrt 2
+    for col, sgn in ((0, -1.0), (n - 1, 1.0)):
+        xb[:, col] = sgn * b * np.sqrt(1.0 - ETA[:, col] ** 2 / (2 * b * b))
+        yb[:, col] = ETA[:, col] / math.sqrt(2.0)
+    return xb, yb
+
+
+def disc_on_grid(xp, yp, b: float, kind: str) -> GridProblem:
+    """The circular-domain problems of Section 4.2 on a given (for example
+    numerically generated) grid of the square [-b, b]^2, numeric Jacobian.
+    kind = "source": rho' = -1 in this library's convention, exact phi =
+    (x'^2 + y'^2)/4 (eq. 43); kind = "harmonic8": rho' = 0, exact
+    phi = r^8 sin(8 theta) (eq. 45)."""
+    n = xp.shape[0]
+    d = 2.0 * b / (n - 1)
+    if kind == "source":
+        phi = (xp ** 2 + yp ** 2) / 4.0
+        rho = -np.ones_like(xp)
+    elif kind == "harmonic8":
+        r = np.hypot(xp, yp)
+        th = np.arctan2(yp, xp)
+        phi = r ** 8 * np.sin(8 * th)
+        rho = np.zeros_like(xp)
+    else:
+        raise ValueError(kind)
+    ring = _outer_ring(n, n)
+    return GridProblem(f"generated_disc_{kind}_{n}", n, n, -b, -b, d, d, np.ascontiguousarray(xp),
+                       np.ascontiguousarray(yp), rho, _phi0_from(phi, ring), jac=None,
+                       phi_exact=phi, meta={"b": b})
+
+
 # ----------------------------------------------------------------------------
 # Benchmark workloads
 # ----------------------------------------------------------------------------
