@@ -168,6 +168,16 @@ class Problem:
                     "residual_norm")
         return a.value, r.value
 
+    def laplace_grid(self, xp, yp, rel_tol=1e-12, max_cycles=200) -> int:
+        """tomg_laplace_grid: fills the interior of xp, yp (boundary map on the
+        ring) with the solution of Laplace's equation; returns the cycles."""
+        shp = (self.ny, self.nx)
+        cyc = C.c_int32()
+        self._check(self.lib.tomg_laplace_grid(self._h, _ptr(xp, torch.float64, shp, "xp"),
+                                               _ptr(yp, torch.float64, shp, "yp"), rel_tol,
+                                               max_cycles, C.byref(cyc)), "laplace_grid")
+        return cyc.value
+
     def field(self, phi, xp=None, yp=None, jac=None):
         """tomg_field: (Ex', Ey') of the potential phi under the map given by
         jac or by the node coordinates xp, yp."""

@@ -22,7 +22,7 @@ FIELD = {"exx": 0, "exy": 1, "eyy": 2, "det": 3, "rhs": 4, "dir": 5, "stencil": 
 EXPORTS = ["tomg_config_default", "tomg_num_levels", "tomg_workspace_bytes", "tomg_create",
            "tomg_destroy", "tomg_last_error", "tomg_set_stream", "setup_coeffs",
            "tomg_update_rhs", "vcycle", "solve", "residual_norm", "tomg_solve_batch",
-           "tomg_batch_step", "tomg_field",
+           "tomg_batch_step", "tomg_field", "tomg_laplace_grid",
            "tomg_export", "tomg_level_shape", "tomg_smooth", "tomg_residual", "tomg_profile",
            "tomg_profile_read", "tomg_copy_probe"]
 
@@ -67,6 +67,7 @@ def load(path: str = LIB_PATH):
         "tomg_batch_step": (C.c_int, [C.POINTER(P), C.POINTER(VP), I32, C.POINTER(I32),
                                       C.POINTER(D)]),
         "tomg_field": (C.c_int, [P, VP, VP, VP, VP, VP, VP]),
+        "tomg_laplace_grid": (C.c_int, [P, VP, VP, D, I32, C.POINTER(I32)]),
         "tomg_export": (C.c_int, [P, I32, I32, VP]),
         "tomg_level_shape": (C.c_int, [P, I32, C.POINTER(I32), C.POINTER(I32)]),
         "tomg_smooth": (C.c_int, [P, VP, I32]),

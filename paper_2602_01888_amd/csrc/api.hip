@@ -529,6 +529,27 @@ tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, i
   return TOMG_OK;
 }
 
+tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, double rel_tol,
+                              int32_t max_cycles, int32_t *cycles_out) {
+  if (!p || !d_xp || !d_yp) return TOMG_EINVAL;
+  if (!(rel_tol > 0.0) || max_cycles < 0)
+    return fail(p, TOMG_EINVAL, "laplace_grid: bad tol/max_cycles");
+  p->ready = false;
+  HIP_TRY(p, launch_setup_identity(p));
+  HIP_TRY(p, launch_hierarchy(p));
+  double h[kNumSlots];
+  tomg_status s = read_scalars(p, h);
+  if (s != TOMG_OK) return s;
+  if (h[kSlotPivot] != 0.0) return fail(p, TOMG_EGEOMETRY, "laplace_grid: singular coarsest matrix");
+  p->ready = true;
+  int32_t c1 = 0, c2 = 0;
+  double r1 = 0.0, r2 = 0.0;
+  s = solve(p, d_xp, rel_tol, max_cycles, &c1, &r1);
+  if (s == TOMG_OK) s = solve(p, d_yp, rel_tol, max_cycles, &c2, &r2);
+  if (cycles_out) *cycles_out = c1 > c2 ? c1 : c2;
+  return s;
+}
+
 tomg_status tomg_field(tomg_problem *p, const double *d_phi, const double *d_xp,
                        const double *d_yp, const double *d_jac, double *d_ex, double *d_ey) {
   if (!p || !d_phi || !d_ex || !d_ey) return TOMG_EINVAL;

@@ -285,6 +285,38 @@ __global__ void k_field(int nx, int ny, double dx, double dy, const double *__re
   }
 }
 
+// The identity tensor (eps = I, det J = 1, f = 0; outer ring Dirichlet): the
+// operator of eq. 18 becomes the 5-point Laplacian, which the numerical grid
+// generation of Section 4.2 (eq. 36-37) solves for x' and y'.  Writes the
+// setup partials (min det 1, no non-finite values) like k_setup.
+__global__ void k_setup_identity(int nx, int ny, double *__restrict__ exx,
+                                 double *__restrict__ exy, double *__restrict__ eyy,
+                                 double *__restrict__ det, double *__restrict__ f,
+                                 uint8_t *__restrict__ dir, float *__restrict__ exx32,
+                                 float *__restrict__ exy32, float *__restrict__ eyy32,
+                                 double *__restrict__ partials) {
+  const size_t n = (size_t)nx * ny;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const size_t j = c / nx, i = c - j * nx;
+    exx[c] = 1.0;
+    exy[c] = 0.0;
+    eyy[c] = 1.0;
+    det[c] = 1.0;
+    f[c] = 0.0;
+    if (exx32) {
+      exx32[c] = 1.0f;
+      exy32[c] = 0.0f;
+      eyy32[c] = 1.0f;
+    }
+    dir[c] = (uint8_t)(i == 0 || j == 0 || i == (size_t)nx - 1 || j == (size_t)ny - 1);
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = 1.0;
+    partials[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
 __global__ void k_update_rhs(const double *rho, const double *det, double *f, size_t n,
                              double *partials) {
   double bad = 0.0;
@@ -1101,6 +1133,19 @@ hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, co
                         const double *jac, double *ex, double *ey) {
   hipLaunchKernelGGL(k_field, 2048, 256, 0, p->stream, p->cfg.nx, p->cfg.ny, p->cfg.dx, p->cfg.dy,
                      phi, xp, yp, jac, ex, ey);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_identity(tomg_problem *p) {
+  const bool f32 = p->cfg.precision == TOMG_FP32_IR;
+  hipLaunchKernelGGL(k_setup_identity, kRedBlocks, kRedThreads, 0, p->stream, p->cfg.nx,
+                     p->cfg.ny, p->exx, p->exy, p->eyy, p->det, p->f, p->lv[0].dir,
+                     f32 ? p->exx32 : nullptr, f32 ? p->exy32 : nullptr,
+                     f32 ? p->eyy32 : nullptr, p->partials);
+  hipLaunchKernelGGL((k_finalize<1>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 2,
+                     p->scal + kSlotMinDet, 0, p->scal, 0);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
+                     2, p->scal + kSlotBad, 0, p->scal, 0);
   return hipGetLastError();
 }
 

@@ -1,0 +1,74 @@
+"""Numerical grid generation on the GPU (tomg_laplace_grid, Section 4.2,
+eq. 36-37) against the oracle's generated grid, and the paper's
+circular-domain problem (eq. 43) solved on GPU-generated grids."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_01888_amd as tomg
+    return torch, tomg
+
+
+def gpu_grid(torch, tomg, n, b, precision="fp64"):
+    xb, yb = w.disc_boundary(n, b)
+    d = 2.0 * b / (n - 1)
+    p = tomg.Problem(n, n, d, d, -b, -b, precision=precision)
+    xp = torch.as_tensor(xb).cuda()
+    yp = torch.as_tensor(yb).cuda()
+    cyc = p.laplace_grid(xp, yp, rel_tol=1e-13, max_cycles=200)
+    return p, xp, yp, cyc, (xb, yb, d)
+
+
+@pytest.mark.parametrize("n", [65, 129])
+def test_generated_grid_matches_oracle(env, n):
+    torch, tomg = env
+    b = 2.0
+    print(f"[gridgen] {n}", flush=True)
+    p, xp, yp, cyc, (xb, yb, d) = gpu_grid(torch, tomg, n, b)
+    rx, ry = oracle.generate_grid(xb, yb, d, d, rel_tol=1e-13)
+    assert np.max(np.abs(xp.cpu().numpy() - rx)) <= 1e-11 * b
+    assert np.max(np.abs(yp.cpu().numpy() - ry)) <= 1e-11 * b
+    assert cyc > 0
+
+
+def test_harmonic_quadratic_map_is_reproduced(env):
+    torch, tomg = env
+    n = 65
+    q = w.identity_map(n)
+    x, y = q.xp, q.yp
+    xt, yt = x + 0.1 * (x ** 2 - y ** 2), y + 0.2 * x * y
+    xb, yb = xt.copy(), yt.copy()
+    xb[1:-1, 1:-1] = yb[1:-1, 1:-1] = 0.0
+    p = tomg.Problem(n, n, q.dx, q.dy)
+    xp, yp = torch.as_tensor(xb).cuda(), torch.as_tensor(yb).cuda()
+    p.laplace_grid(xp, yp, rel_tol=1e-13)
+    assert np.max(np.abs(xp.cpu().numpy() - xt)) <= 1e-11
+    assert np.max(np.abs(yp.cpu().numpy() - yt)) <= 1e-11
+
+
+def test_disc_with_source_on_generated_grid_is_second_order(env):
+    torch, tomg = env
+    b = 2.0
+    l2 = []
+    for n in (65, 129, 257):
+        p, xp, yp, _, _ = gpu_grid(torch, tomg, n, b)
+        q = w.disc_on_grid(xp.cpu().numpy(), yp.cpu().numpy(), b, "source")
+        d = tomg.upload(q)
+        p.setup_coeffs(d["rho"], xp=xp, yp=yp)
+        phi = d["phi0"].clone()
+        assert p.solve(phi, rel_tol=1e-12, max_cycles=100).ok
+        e = phi.cpu().numpy() - q.phi_exact
+        l2.append(float(np.sqrt(np.sum(e * e)) / n))
+    print(f"  L2 errors {l2}", flush=True)
+    assert 3.5 <= l2[0] / l2[1] <= 4.5 and 3.5 <= l2[1] / l2[2] <= 4.5
