@@ -322,13 +322,25 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
   if (!(rel_tol > 0.0) || max_cycles < 0) return fail(p, TOMG_EINVAL, "solve: bad tol/max_cycles");
   if (!p->ready) return fail(p, TOMG_ESTATE, "solve before setup_coeffs");
   const bool ir = p->cfg.precision == TOMG_FP32_IR;
+  // the device-side stopping test compares with this tolerance; the cycle
+  // counter starts at zero
+  p->up[0] = rel_tol;
+  p->up[1] = 0.0;
+  HIP_TRY(p, hipMemcpyAsync(p->scal + kSlotTol, p->up, 2 * sizeof(double),
+                            hipMemcpyHostToDevice, p->stream));
   HIP_TRY(p, launch_begin(p, d_phi, ir));
   double h[kNumSlots];
   tomg_status s = read_scalars(p, h);
   if (s != TOMG_OK) return s;
   int cycles = 0;
-  double rel = h[kSlotRel];
+  double rel = h[kSlotRel], prev = NAN;
+  int queued = 0;
   tomg_status st = TOMG_ENOCONV;
+  // Cycles are queued several at a time between host checks.  Each cycle's
+  // norm sets the device convergence flag; the launches of cycles queued
+  // past convergence see it and do nothing, so the iterate, the residual and
+  // the cycle count are those of checking after every cycle.  The batch size
+  // is the number of cycles the observed contraction predicts (at least 1).
   while (true) {
     if (!std::isfinite(rel)) {
       st = fail(p, TOMG_ENONFINITE, "solve: non-finite residual after %d cycles", cycles);
@@ -342,15 +354,35 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
       st = fail(p, TOMG_ENOCONV, "solve: rel. residual %.3e after %d cycles", rel, cycles);
       break;
     }
-    if (ir) {
-      HIP_TRY(p, launch_ir_correct(p, d_phi));
-      HIP_TRY(p, launch_ir_residual(p, d_phi));
-    } else {
-      HIP_TRY(p, launch_vcycle64(p, d_phi, true));
+    int k = 1;
+    const bool queue = p->cfg.smoother == TOMG_GS4;  // the Jacobi path checks every cycle
+    if (queue) {
+      const double rate = queued > 0 ? std::pow(rel / prev, 1.0 / queued) : NAN;
+      if (std::isfinite(rate) && rate > 0.0 && rate < 1.0)
+        k = (int)std::ceil(std::log(rel_tol / rel) / std::log(rate));
+      else if (cycles == 0)
+        k = 2;
+      k = std::max(1, std::min(k, 16));
     }
-    ++cycles;
+    k = std::min(k, max_cycles - cycles);
+    p->skip = queue ? p->scal + kSlotDone : nullptr;
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < k && e == hipSuccess; ++q) {
+      if (ir) {
+        e = launch_ir_correct(p, d_phi);
+        if (e == hipSuccess) e = launch_ir_residual(p, d_phi);
+      } else {
+        e = launch_vcycle64(p, d_phi, true);
+      }
+    }
+    p->skip = nullptr;
+    if (e != hipSuccess) return fail(p, TOMG_EDEVICE, "solve: cycle launch failed: %s",
+                                     hipGetErrorString(e));
     s = read_scalars(p, h);
     if (s != TOMG_OK) return s;
+    prev = rel;
+    queued = (int)h[kSlotCycles] - cycles;
+    cycles = (int)h[kSlotCycles];
     rel = h[kSlotRel];
   }
   if (cycles_out) *cycles_out = cycles;

@@ -428,6 +428,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
 
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
 __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
+  if (a.skip && *a.skip != 0.0) return;
   pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, blockIdx.x, blockIdx.y);
 }
 
@@ -677,6 +678,7 @@ void fused_down(tomg_problem *p, int l, const T *x, T *pong, const T *b, const T
   a.eyy = eyy;
   a.st = st;
   a.bc = bc;
+  a.skip = p->skip;
   launch_down<T>(p->cfg.nu1, l == 0, zero_start, a, p->stream, nullptr, 0);
 }
 
@@ -697,6 +699,7 @@ int fused_up(tomg_problem *p, int l, const T *pong, T *x, const T *b, const T *e
   a.st = st;
   a.xc = xc;
   a.partials = partials;
+  a.skip = p->skip;
   launch_up<T>(p->cfg.nu2, l == 0, partials != nullptr, a, p->stream, nullptr, 0);
   return a.nbx * a.nby;
 }

@@ -137,10 +137,12 @@ __device__ double block_reduce(double v) {
 // One block: fixed-order reduction of n partials into out[0].
 // mode 0 sum, 1 min, 2 max, 3 sqrt(sum).  When rel_slot >= 0 the result is
 // also divided by scal[kSlotB0] into scal[kSlotRel] and compared against
-// scal[kSlotTol] into scal[kSlotDone].
+// scal[kSlotTol] into scal[kSlotDone]; rel == 2 also counts a cycle.  A
+// nonzero *skip makes the launch a no-op.
 template <int OP>
 __global__ void k_finalize(const double *partials, int n, int stride, double *out, int do_sqrt,
-                           double *scal, int rel) {
+                           double *scal, int rel, const double *skip) {
+  if (skip && *skip != 0.0) return;
   double v = OP == 0 ? 0.0 : (OP == 1 ? INFINITY : -INFINITY);
   for (int k = threadIdx.x; k < n; k += blockDim.x) v = combine<OP>(v, partials[(size_t)k * stride]);
   v = block_reduce<OP>(v);
@@ -152,6 +154,7 @@ __global__ void k_finalize(const double *partials, int n, int stride, double *ou
       const double r = b0 > 0.0 ? v / b0 : 0.0;
       scal[kSlotRel] = r;
       scal[kSlotDone] = (r <= scal[kSlotTol]) ? 1.0 : 0.0;
+      if (rel == 2) scal[kSlotCycles] += 1.0;
     }
   }
 }
@@ -859,11 +862,15 @@ __device__ __forceinline__ void ir_update_body(const RedArgs &a, double *phi, in
 template <bool ZF>
 __global__ void k_resnorm(RedArgs a, const double *x) { resnorm_body<ZF>(a, x, blockIdx.x); }
 template <bool B0>
-__global__ void k_ir_residual(RedArgs a, const double *phi) {
+__global__ void k_ir_residual(RedArgs a, const double *phi, const double *skip) {
+  if (skip && *skip != 0.0) return;
   ir_residual_body<B0>(a, phi, blockIdx.x);
 }
 __global__ void k_begin(RedArgs a, const double *x) { begin_body(a, x, blockIdx.x); }
-__global__ void k_ir_update(RedArgs a, double *phi) { ir_update_body(a, phi, blockIdx.x); }
+__global__ void k_ir_update(RedArgs a, double *phi, const double *skip) {
+  if (skip && *skip != 0.0) return;
+  ir_update_body(a, phi, blockIdx.x);
+}
 
 __device__ __forceinline__ const BatchEntry &locate(const BatchTab &tab, int b) {
   int lo = 0, hi = tab.count - 1;
@@ -1123,9 +1130,9 @@ hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, con
                      p->f, p->lv[0].dir, f32 ? p->exx32 : nullptr, f32 ? p->exy32 : nullptr,
                      f32 ? p->eyy32 : nullptr, p->partials);
   hipLaunchKernelGGL((k_finalize<1>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 2,
-                     p->scal + kSlotMinDet, 0, p->scal, 0);
+                     p->scal + kSlotMinDet, 0, p->scal, 0, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
-                     2, p->scal + kSlotBad, 0, p->scal, 0);
+                     2, p->scal + kSlotBad, 0, p->scal, 0, nullptr);
   return hipGetLastError();
 }
 
@@ -1143,9 +1150,9 @@ hipError_t launch_setup_identity(tomg_problem *p) {
                      f32 ? p->exx32 : nullptr, f32 ? p->exy32 : nullptr,
                      f32 ? p->eyy32 : nullptr, p->partials);
   hipLaunchKernelGGL((k_finalize<1>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 2,
-                     p->scal + kSlotMinDet, 0, p->scal, 0);
+                     p->scal + kSlotMinDet, 0, p->scal, 0, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
-                     2, p->scal + kSlotBad, 0, p->scal, 0);
+                     2, p->scal + kSlotBad, 0, p->scal, 0, nullptr);
   return hipGetLastError();
 }
 
@@ -1154,7 +1161,7 @@ hipError_t launch_update_rhs(tomg_problem *p, const double *rho) {
   hipLaunchKernelGGL(k_update_rhs, kRedBlocks, kRedThreads, 0, p->stream, rho, p->det, p->f, n,
                      p->partials);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 1,
-                     p->scal + kSlotBad, 0, p->scal, 0);
+                     p->scal + kSlotBad, 0, p->scal, 0, nullptr);
   return hipGetLastError();
 }
 
@@ -1188,10 +1195,15 @@ hipError_t launch_vcycle64(tomg_problem *p, double *phi, bool with_norm) {
   if (e != hipSuccess || !with_norm) return e;
   if (nb > 0) {
     hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, nb, 1,
-                       p->scal + kSlotRes, 1, p->scal, 1);
+                       p->scal + kSlotRes, 1, p->scal, 2, p->skip);
     return hipGetLastError();
   }
-  return launch_resnorm(p, phi, kSlotRes, false);
+  // no level-0 pass left norm partials (the Jacobi path): a separate norm
+  const RedArgs &r = p->hargs.red;
+  hipLaunchKernelGGL(k_resnorm<false>, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
+                     p->scal + kSlotRes, 1, p->scal, 2, nullptr);
+  return hipGetLastError();
 }
 
 int red_blocks(size_t n) {
@@ -1229,9 +1241,9 @@ void build_red_args(tomg_problem *p) {
 
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
   const RedArgs &r = p->hargs.red;
-  hipLaunchKernelGGL(k_ir_residual<false>, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  hipLaunchKernelGGL(k_ir_residual<false>, r.nblk, kRedThreads, 0, p->stream, r, phi, p->skip);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
-                     p->scal + kSlotRes, 1, p->scal, 1);
+                     p->scal + kSlotRes, 1, p->scal, 2, p->skip);
   return hipGetLastError();
 }
 
@@ -1241,13 +1253,13 @@ hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
 hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir) {
   const RedArgs &r = p->hargs.red;
   if (ir)
-    hipLaunchKernelGGL(k_ir_residual<true>, r.nblk, kRedThreads, 0, p->stream, r, phi);
+    hipLaunchKernelGGL(k_ir_residual<true>, r.nblk, kRedThreads, 0, p->stream, r, phi, nullptr);
   else
     hipLaunchKernelGGL(k_begin, r.nblk, kRedThreads, 0, p->stream, r, phi);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + r.nblk,
-                     r.nblk, 1, p->scal + kSlotB0, 1, p->scal, 0);
+                     r.nblk, 1, p->scal + kSlotB0, 1, p->scal, 0, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
-                     p->scal + kSlotRes, 1, p->scal, 1);
+                     p->scal + kSlotRes, 1, p->scal, 1, nullptr);
   return hipGetLastError();
 }
 
@@ -1263,7 +1275,7 @@ hipError_t launch_ir_correct(tomg_problem *p, double *phi) {
     if (e != hipSuccess) return e;
   }
   const RedArgs &r = p->hargs.red;
-  hipLaunchKernelGGL(k_ir_update, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  hipLaunchKernelGGL(k_ir_update, r.nblk, kRedThreads, 0, p->stream, r, phi, p->skip);
   return hipGetLastError();
 }
 
@@ -1274,7 +1286,7 @@ hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zer
   else
     hipLaunchKernelGGL(k_resnorm<false>, r.nblk, kRedThreads, 0, p->stream, r, phi);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
-                     p->scal + slot, 1, p->scal, slot == kSlotRes ? 1 : 0);
+                     p->scal + slot, 1, p->scal, slot == kSlotRes ? 1 : 0, nullptr);
   return hipGetLastError();
 }
 

@@ -243,6 +243,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
 
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
+  if (a.skip && *a.skip != 0.0) return;
   tail_body<T>(a);
 }
 
@@ -312,6 +313,7 @@ void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *co
     a.lv[q].x = xs[lc + q];
     a.lv[q].b = bs[lc + q];
   }
+  a.skip = p->skip;
   hipLaunchKernelGGL((k_tail<T>), 1, kTailThreads, a.shmem, p->stream, a);
 }
 

@@ -25,6 +25,7 @@ enum Slot {
   kSlotRel = 5,     // last relative residual
   kSlotDone = 6,    // convergence flag (1.0 when rel <= tol)
   kSlotTol = 7,     // stopping tolerance used by the device-side check
+  kSlotCycles = 8,  // cycles whose norm was finalized (counted on the device)
   kNumSlots = 16
 };
 
@@ -58,6 +59,8 @@ struct PassArgs {
   double *partials;          // up pass with norm: one double per block
   int CH, W;                 // band height, owned columns per block
   int nbx, nby;              // block grid
+  const double *skip;        // nonzero *skip: the launch does nothing (solve()
+                             // queues cycles past convergence as no-ops)
 };
 
 // One level of the single-workgroup tail (tail.hip).
@@ -79,6 +82,7 @@ struct TailArgs {
   const double *cinv;
   const int *cidx;
   int shmem;             // dynamic LDS bytes
+  const double *skip;    // as in PassArgs
   TailLevel<T> lv[kTailLevels];
 };
 
@@ -167,6 +171,8 @@ struct tomg_problem {
   double *bout = nullptr;           // batch results (used when this problem leads a batch)
   int lc = 0;                       // first level of the tail
   int m_coarse = 0;
+  const double *skip = nullptr;     // device convergence flag while solve() queues cycles
+  double up[2] = {0.0, 0.0};        // source of the tolerance/cycle-count upload
   bool ready = false;
   // level-0 pass timing (tomg_profile): event pairs recorded since the last
   // harvest, per kind (0 down, 1 up)
