@@ -117,11 +117,15 @@ def request_fields(desc, device):
         amps, centres = source_params(kind, mp, desc["source_seed"])
     d = 1.0 / (n - 1)
 
+    held = {}
+
     def geom():
-        return geometry(kind, n, mp, device)
+        held["g"] = geometry(kind, n, mp, device)
+        return held["g"]
 
     def source():
-        g = geometry(kind, n, mp, device)
+        # a cold request asks for the geometry first: reuse its coordinates
+        g = held.pop("g", None) or geometry(kind, n, mp, device)
         return gaussian_rho(g["xp"], g["yp"], amps, centres)
 
     return {"rid": desc["id"], "geom": desc["geom"], "nx": n, "ny": n, "dx": d, "dy": d,
