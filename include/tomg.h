@@ -123,6 +123,25 @@ tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp
                          const double *d_jac, const double *d_eps_phys,
                          const double *d_rho_phys, const uint8_t *d_mask);
 
+/* setup_coeffs without its host synchronisation: the same kernels are queued
+ * on the problem's stream and the call returns at once, so that a caller
+ * admitting new geometries while other solves run does not wait for the
+ * device.  Argument errors are reported at once; the geometry checks
+ * (det J, non-finite values, singular coarsest matrix) stay on the device and
+ * are reported later: by the next solve (same status setup_coeffs would have
+ * returned), by tomg_setup_check, and by tomg_solve_batch / tomg_batch_step,
+ * which write a NaN relative residual for a problem whose setup failed.
+ * Inputs must stay valid until the queued work has run (stream order). */
+tomg_status tomg_setup_coeffs_async(tomg_problem *p, const double *d_xp, const double *d_yp,
+                                    const double *d_jac, const double *d_eps_phys,
+                                    const double *d_rho_phys, const uint8_t *d_mask);
+
+/* Synchronises the problem's stream and returns the status of the checks of
+ * the last setup (TOMG_OK, TOMG_EGEOMETRY or TOMG_ENONFINITE, as
+ * setup_coeffs); a failed check makes the problem unusable until the next
+ * setup, as for setup_coeffs.  TOMG_ESTATE before any setup. */
+tomg_status tomg_setup_check(tomg_problem *p);
+
 /* New source on the same geometry: f = -rho' det J from the stored det J
  * (eq. 11), without rebuilding the hierarchy.  Asynchronous. */
 tomg_status tomg_update_rhs(tomg_problem *p, const double *d_rho_phys);

@@ -136,13 +136,25 @@ class Problem:
         return num_levels(self.cfg)
 
     # -- the C-ABI calls ----------------------------------------------------
-    def setup_coeffs(self, rho, xp=None, yp=None, jac=None, eps_phys=None, mask=None):
+    def setup_coeffs(self, rho, xp=None, yp=None, jac=None, eps_phys=None, mask=None,
+                     check=True):
+        """Coefficient setup and hierarchy.  With check=False the work is
+        queued without a host synchronisation and the geometry checks are
+        reported later (``setup_check``, the next ``solve``, or a NaN
+        residual from ``batch_step``); torch tensors passed here stay valid
+        for the queued work as long as they were made on this problem's
+        stream."""
         shp = (self.ny, self.nx)
         args = (_ptr(xp, torch.float64, shp, "xp"), _ptr(yp, torch.float64, shp, "yp"),
                 _ptr(jac, torch.float64, (4,) + shp, "jac"),
                 _ptr(eps_phys, torch.float64, shp, "eps_phys"),
                 _ptr(rho, torch.float64, shp, "rho"), _ptr(mask, torch.uint8, shp, "mask"))
-        self._check(self.lib.setup_coeffs(self._h, *args), "setup_coeffs")
+        fn = self.lib.setup_coeffs if check else self.lib.tomg_setup_coeffs_async
+        self._check(fn(self._h, *args), "setup_coeffs")
+
+    def setup_check(self):
+        """Raises TomgError if the last (asynchronous) setup failed its checks."""
+        self._check(self.lib.tomg_setup_check(self._h), "setup_check")
 
     def update_rhs(self, rho):
         self._check(self.lib.tomg_update_rhs(self._h, _ptr(rho, torch.float64,
@@ -296,13 +308,14 @@ def upload(prob, device="cuda"):
             "mask": t(prob.mask, torch.uint8), "phi0": t(prob.phi0)}
 
 
-def setup_from_grid(prob, device="cuda", **kw):
+def setup_from_grid(prob, device="cuda", check=True, **kw):
     """Problem + upload + setup_coeffs for a ``workloads.GridProblem``.
-    The analytic Jacobian is used when the problem carries one."""
+    The analytic Jacobian is used when the problem carries one; check=False
+    queues the setup with its checks deferred."""
     p = Problem.from_grid(prob, device=device, **kw)
     d = upload(prob, device)
     if d["jac"] is not None:
-        p.setup_coeffs(d["rho"], jac=d["jac"], mask=d["mask"])
+        p.setup_coeffs(d["rho"], jac=d["jac"], mask=d["mask"], check=check)
     else:
-        p.setup_coeffs(d["rho"], xp=d["xp"], yp=d["yp"], mask=d["mask"])
+        p.setup_coeffs(d["rho"], xp=d["xp"], yp=d["yp"], mask=d["mask"], check=check)
     return p, d

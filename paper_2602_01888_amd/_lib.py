@@ -21,6 +21,7 @@ FIELD = {"exx": 0, "exy": 1, "eyy": 2, "det": 3, "rhs": 4, "dir": 5, "stencil": 
 # Every symbol include/tomg.h declares.
 EXPORTS = ["tomg_config_default", "tomg_num_levels", "tomg_workspace_bytes", "tomg_create",
            "tomg_destroy", "tomg_last_error", "tomg_set_stream", "setup_coeffs",
+           "tomg_setup_coeffs_async", "tomg_setup_check",
            "tomg_update_rhs", "vcycle", "solve", "residual_norm", "tomg_solve_batch",
            "tomg_batch_step", "tomg_field", "tomg_laplace_grid",
            "tomg_export", "tomg_level_shape", "tomg_smooth", "tomg_residual", "tomg_profile",
@@ -58,6 +59,8 @@ def load(path: str = LIB_PATH):
         "tomg_last_error": (C.c_char_p, [P]),
         "tomg_set_stream": (C.c_int, [P, VP]),
         "setup_coeffs": (C.c_int, [P, VP, VP, VP, VP, VP, VP]),
+        "tomg_setup_coeffs_async": (C.c_int, [P, VP, VP, VP, VP, VP, VP]),
+        "tomg_setup_check": (C.c_int, [P]),
         "tomg_update_rhs": (C.c_int, [P, VP]),
         "vcycle": (C.c_int, [P, VP]),
         "solve": (C.c_int, [P, VP, D, I32, C.POINTER(I32), C.POINTER(D)]),

@@ -259,19 +259,10 @@ tomg_status tomg_set_stream(tomg_problem *p, void *stream) {
   return TOMG_OK;
 }
 
-tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp,
-                         const double *d_jac, const double *d_eps_phys,
-                         const double *d_rho_phys, const uint8_t *d_mask) {
-  if (!p) return TOMG_EINVAL;
-  p->ready = false;
-  if (!d_rho_phys) return fail(p, TOMG_EINVAL, "setup_coeffs: rho is NULL");
-  if (!d_jac && (!d_xp || !d_yp))
-    return fail(p, TOMG_EINVAL, "setup_coeffs: need the Jacobian or both coordinate arrays");
-  HIP_TRY(p, launch_setup(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask));
-  HIP_TRY(p, launch_hierarchy(p));
-  double h[kNumSlots];
-  tomg_status s = read_scalars(p, h);
-  if (s != TOMG_OK) return s;
+}  // extern "C"
+
+// Status of the checks a setup leaves in the scalar block.
+static tomg_status setup_status(tomg_problem *p, const double *h) {
   if (!(h[kSlotMinDet] > 0.0))
     return fail(p, TOMG_EGEOMETRY, "setup_coeffs: det J = %g <= 0 (folded or degenerate map)",
                 h[kSlotMinDet]);
@@ -280,8 +271,73 @@ tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp
                 h[kSlotBad]);
   if (h[kSlotPivot] != 0.0)
     return fail(p, TOMG_EGEOMETRY, "setup_coeffs: singular coarsest-level matrix");
+  return TOMG_OK;
+}
+
+// After a read of the scalar block: reports the checks of an asynchronous
+// setup that no call has reported yet.
+static tomg_status pending_setup_status(tomg_problem *p, const double *h) {
+  if (!p->unchecked) return TOMG_OK;
+  tomg_status s = setup_status(p, h);
+  if (s != TOMG_OK) {
+    p->ready = false;
+    return s;
+  }
+  p->unchecked = false;
+  return TOMG_OK;
+}
+
+static tomg_status setup_launch(tomg_problem *p, const double *d_xp, const double *d_yp,
+                                const double *d_jac, const double *d_eps_phys,
+                                const double *d_rho_phys, const uint8_t *d_mask) {
+  p->ready = false;
+  p->unchecked = false;
+  if (!d_rho_phys) return fail(p, TOMG_EINVAL, "setup_coeffs: rho is NULL");
+  if (!d_jac && (!d_xp || !d_yp))
+    return fail(p, TOMG_EINVAL, "setup_coeffs: need the Jacobian or both coordinate arrays");
+  // the setup's own source check replaces that of any earlier update_rhs
+  HIP_TRY(p, hipMemsetAsync(p->scal + kSlotBadRhs, 0, sizeof(double), p->stream));
+  HIP_TRY(p, launch_setup(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask));
+  HIP_TRY(p, launch_hierarchy(p));
+  return TOMG_OK;
+}
+
+extern "C" {
+
+tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp,
+                         const double *d_jac, const double *d_eps_phys,
+                         const double *d_rho_phys, const uint8_t *d_mask) {
+  if (!p) return TOMG_EINVAL;
+  tomg_status s = setup_launch(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask);
+  if (s != TOMG_OK) return s;
+  double h[kNumSlots];
+  s = read_scalars(p, h);
+  if (s != TOMG_OK) return s;
+  s = setup_status(p, h);
+  if (s != TOMG_OK) return s;
   p->ready = true;
   return TOMG_OK;
+}
+
+tomg_status tomg_setup_coeffs_async(tomg_problem *p, const double *d_xp, const double *d_yp,
+                                    const double *d_jac, const double *d_eps_phys,
+                                    const double *d_rho_phys, const uint8_t *d_mask) {
+  if (!p) return TOMG_EINVAL;
+  tomg_status s = setup_launch(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask);
+  if (s != TOMG_OK) return s;
+  p->ready = true;
+  p->unchecked = true;
+  return TOMG_OK;
+}
+
+tomg_status tomg_setup_check(tomg_problem *p) {
+  if (!p) return TOMG_EINVAL;
+  if (!p->ready) return fail(p, TOMG_ESTATE, "setup_check before setup_coeffs");
+  if (!p->unchecked) return TOMG_OK;
+  double h[kNumSlots];
+  tomg_status s = read_scalars(p, h);
+  if (s != TOMG_OK) return s;
+  return pending_setup_status(p, h);
 }
 
 tomg_status tomg_update_rhs(tomg_problem *p, const double *d_rho_phys) {
@@ -311,6 +367,8 @@ tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
   double h[kNumSlots];
   tomg_status s = read_scalars(p, h);
   if (s != TOMG_OK) return s;
+  s = pending_setup_status(p, h);
+  if (s != TOMG_OK) return s;
   if (abs_out) *abs_out = h[kSlotRes];
   if (rel_out) *rel_out = h[kSlotRel];
   return TOMG_OK;
@@ -331,6 +389,8 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
   HIP_TRY(p, launch_begin(p, d_phi, ir));
   double h[kNumSlots];
   tomg_status s = read_scalars(p, h);
+  if (s != TOMG_OK) return s;
+  s = pending_setup_status(p, h);
   if (s != TOMG_OK) return s;
   int cycles = 0;
   double rel = h[kSlotRel], prev = NAN;
@@ -567,6 +627,8 @@ tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, doubl
   if (!(rel_tol > 0.0) || max_cycles < 0)
     return fail(p, TOMG_EINVAL, "laplace_grid: bad tol/max_cycles");
   p->ready = false;
+  p->unchecked = false;
+  HIP_TRY(p, hipMemsetAsync(p->scal + kSlotBadRhs, 0, sizeof(double), p->stream));
   HIP_TRY(p, launch_setup_identity(p));
   HIP_TRY(p, launch_hierarchy(p));
   double h[kNumSlots];

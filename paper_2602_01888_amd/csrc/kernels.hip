@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void k_coarse_inverse(const double *st, const 
   __shared__ double A[M][M + 1], B[M][M + 1];
   __shared__ double fac[M], rowa[M], rowb[M];
   __shared__ int cid[81];
-  __shared__ int sm, spiv;
+  __shared__ int sm;
   const int n = nx * ny, t = threadIdx.x, c = t & 63, w = t >> 6;
   if (t == 0) {
     int m = 0;
@@ -631,10 +631,7 @@ __global__ __launch_bounds__(256) void k_coarse_inverse(const double *st, const 
           p = op;
         }
       }
-      if (c == 0) {
-        spiv = p;
-        if (v == 0.0) scal[kSlotPivot] = 1.0;
-      }
+      if (c == 0 && v == 0.0) scal[kSlotPivot] = 1.0;
       if (p != k && c < m) {
         double u = A[k][c]; A[k][c] = A[p][c]; A[p][c] = u;
         u = B[k][c]; B[k][c] = B[p][c]; B[p][c] = u;
@@ -911,7 +908,13 @@ __global__ void k_finalize_b(BatchTab tab, int rel, double *out) {
     a.scal[e.slot] = v;
     if (rel) {
       const double b0 = a.scal[kSlotB0];
-      const double r = b0 > 0.0 ? v / b0 : 0.0;
+      double r = b0 > 0.0 ? v / b0 : 0.0;
+      // a setup that failed its checks (folded map, non-finite input,
+      // singular coarsest matrix) or a non-finite new right-hand side
+      // reports a non-finite residual
+      if (!(a.scal[kSlotMinDet] > 0.0) || a.scal[kSlotBad] != 0.0 ||
+          a.scal[kSlotPivot] != 0.0 || a.scal[kSlotBadRhs] != 0.0)
+        r = NAN;
       a.scal[kSlotRel] = r;
       a.scal[kSlotDone] = (r <= a.scal[kSlotTol]) ? 1.0 : 0.0;
       out[e.out] = r;
@@ -1161,7 +1164,7 @@ hipError_t launch_update_rhs(tomg_problem *p, const double *rho) {
   hipLaunchKernelGGL(k_update_rhs, kRedBlocks, kRedThreads, 0, p->stream, rho, p->det, p->f, n,
                      p->partials);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 1,
-                     p->scal + kSlotBad, 0, p->scal, 0, nullptr);
+                     p->scal + kSlotBadRhs, 0, p->scal, 0, nullptr);
   return hipGetLastError();
 }
 

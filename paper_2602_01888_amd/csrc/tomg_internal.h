@@ -26,6 +26,7 @@ enum Slot {
   kSlotDone = 6,    // convergence flag (1.0 when rel <= tol)
   kSlotTol = 7,     // stopping tolerance used by the device-side check
   kSlotCycles = 8,  // cycles whose norm was finalized (counted on the device)
+  kSlotBadRhs = 9,  // count of non-finite right-hand-side values (update_rhs)
   kNumSlots = 16
 };
 
@@ -173,6 +174,7 @@ struct tomg_problem {
   int m_coarse = 0;
   const double *skip = nullptr;     // device convergence flag while solve() queues cycles
   double up[2] = {0.0, 0.0};        // source of the tolerance/cycle-count upload
+  bool unchecked = false;           // setup issued without its host-side check
   bool ready = false;
   // level-0 pass timing (tomg_profile): event pairs recorded since the last
   // harvest, per kind (0 down, 1 up)

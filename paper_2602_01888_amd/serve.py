@@ -16,6 +16,12 @@ a request that does not fit stops admission (later requests do not overtake
 it), except that a request whose geometry is still being solved is passed
 over until that solve ends.
 
+Cold setups are queued without waiting for the device: the geometry checks
+of a setup (folded map, non-finite input, singular coarsest matrix) come
+back with the request's first step, whose residual is then non-finite; the
+server asks the backend for the reason, reports it in the completion and
+drops the geometry.
+
 Warm re-solves.  A request marked warm whose geometry is resident and idle
 skips the coefficient setup and the hierarchy build: only the right-hand
 side is recomputed (``tomg_update_rhs``), and the iteration starts from the
@@ -129,16 +135,27 @@ class TomgBackend:
         return 8 * req.nx * req.ny * 8
 
     def create(self, req: Request):
-        """New problem with coefficients set up; returns (problem, phi)."""
+        """New problem with its coefficient setup queued (checks deferred);
+        returns (problem, phi)."""
         p = self.tomg.Problem(req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0,
                               device=self.device, **self.kw)
         g = req.geometry()
         rho = req.source()
         if g.get("jac") is not None:
-            p.setup_coeffs(rho, jac=g["jac"], mask=g.get("mask"))
+            p.setup_coeffs(rho, jac=g["jac"], mask=g.get("mask"), check=False)
         else:
-            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g.get("mask"))
+            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g.get("mask"), check=False)
         return p, g["phi0"].clone()
+
+    def diagnose(self, problem):
+        """(status, message) for a problem whose step gave a non-finite
+        residual: the deferred setup checks if they failed, else
+        non-finite values in the iteration."""
+        try:
+            problem.setup_check()
+        except self.tomg.TomgError as e:
+            return e.status, str(e)
+        return TOMG_ENONFINITE, "non-finite residual"
 
     def new_source(self, problem, req: Request):
         problem.update_rhs(req.source())
@@ -272,8 +289,12 @@ class Server:
             else:
                 a.cycles += 1
             a.rel = r
+            err = ""
             if not math.isfinite(r):
-                st = TOMG_ENONFINITE
+                st, err = TOMG_ENONFINITE, "non-finite residual"
+                diagnose = getattr(self.backend, "diagnose", None)
+                if diagnose is not None:
+                    st, err = diagnose(a.res.problem)
             elif r <= self.rel_tol:
                 st = TOMG_OK
             elif a.cycles >= self.max_cycles:
@@ -281,13 +302,16 @@ class Server:
             else:
                 keep.append(a)
                 continue
-            a.res.busy = False
-            self.resident.move_to_end(a.res.key)
             c = Completion(a.req.rid, st, a.cycles, r, a.req.arrival, a.admitted, t,
-                           a.warm_start)
+                           a.warm_start, error=err)
             if self.keep:
                 c.phi = self.backend.copy(a.res.phi)
                 c.phi_start = a.phi_start
+            a.res.busy = False
+            if err:  # a failed setup or a diverged iterate is not kept for re-use
+                self._drop(a.res)
+            else:
+                self.resident.move_to_end(a.res.key)
             done.append(c)
         self.active = keep
         return done

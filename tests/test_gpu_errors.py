@@ -83,3 +83,73 @@ def test_update_rhs_warm_resolve(tomg):
     b = d2["phi0"].clone()
     assert q.solve(b).ok
     assert bool((a == b).all())
+
+
+# -- setup with deferred checks (tomg_setup_coeffs_async) ----------------------
+
+def test_async_setup_reports_folded_map_later(tomg):
+    prob = w.manufactured_sinusoidal(33, amp=0.5)
+    p, d = tomg.setup_from_grid(prob, check=False)  # returns without the check
+    with pytest.raises(tomg.TomgError) as e:
+        p.setup_check()
+    assert e.value.status == tomg.TOMG_EGEOMETRY
+    # a failed check leaves the problem unusable, as a failed setup_coeffs
+    r = p.solve(d["phi0"].clone(), raise_on_error=False)
+    assert r.status == tomg.TOMG_ESTATE
+
+
+def test_async_setup_failure_surfaces_in_solve(tomg):
+    prob = w.manufactured_sinusoidal(33)
+    prob.rho[5, 7] = np.nan
+    p, d = tomg.setup_from_grid(prob, check=False)
+    r = p.solve(d["phi0"].clone(), raise_on_error=False)
+    assert r.status == tomg.TOMG_ENONFINITE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_async_setup_equals_sync_setup(tomg, precision):
+    prob = w.perturbed_circle(129, seed=3)
+    pa, da = tomg.setup_from_grid(prob, check=False, precision=precision)
+    ps, ds = tomg.setup_from_grid(prob, precision=precision)
+    fa, fs = da["phi0"].clone(), ds["phi0"].clone()
+    ra = pa.solve(fa, rel_tol=1e-10)
+    rs = ps.solve(fs, rel_tol=1e-10)
+    assert ra.cycles == rs.cycles and ra.rel == rs.rel
+    assert bool((fa == fs).all())
+    pa.setup_check()  # already reported by the solve: nothing pending
+
+
+def test_batch_step_marks_failed_setup_nan(tomg):
+    import math
+    good = [w.perturbed_circle(65, seed=s) for s in (1, 2)]
+    bad = w.manufactured_sinusoidal(65, amp=0.5)
+    probs, phis = [], []
+    for g in (good[0], bad, good[1]):
+        p, d = tomg.setup_from_grid(g, check=False)
+        probs.append(p)
+        phis.append(d["phi0"].clone())
+    rel = tomg.batch_step(probs, phis, [True] * 3)
+    assert math.isnan(rel[1]) and abs(rel[0] - 1) < 1e-12 and abs(rel[2] - 1) < 1e-12
+    rel = tomg.batch_step(probs, phis, [False] * 3)
+    assert math.isnan(rel[1]) and 0 < rel[0] < 1 and 0 < rel[2] < 1
+    with pytest.raises(tomg.TomgError) as e:
+        probs[1].setup_check()
+    assert e.value.status == tomg.TOMG_EGEOMETRY
+
+
+def test_nonfinite_update_rhs_marks_batch_nan_until_next_setup(tomg):
+    import math
+    import torch
+    prob = w.perturbed_circle(65, seed=4)
+    p, d = tomg.setup_from_grid(prob)
+    rho = d["rho"].clone()
+    rho[3, 9] = float("inf")
+    p.update_rhs(rho)
+    phi = d["phi0"].clone()
+    (r,) = tomg.batch_step([p], [phi], [True])
+    assert math.isnan(r)
+    p.setup_coeffs(d["rho"], xp=d["xp"], yp=d["yp"], mask=d["mask"])
+    phi = d["phi0"].clone()
+    (r,) = tomg.batch_step([p], [phi], [True])
+    assert abs(r - 1) < 1e-12
+    assert torch.isfinite(phi).all()

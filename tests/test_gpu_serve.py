@@ -78,3 +78,28 @@ def test_served_results_meet_tolerance_by_oracle(env):
         rel = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], c.phi.cpu().numpy(),
                                                           s["f"])) / b0
         assert rel <= 1e-10 * (1 + 1e-3), (c.rid, rel, c.rel)
+
+
+def test_served_folded_map_fails_alone(env):
+    """A request whose map folds (det J <= 0) is set up without a host check;
+    its first step reports the geometry error and the other requests in the
+    same batch are served as usual."""
+    torch, tomg, serve, D = env
+    reqs, _ = stream(D, serve, 6, (65, 129))
+    bad = w.manufactured_sinusoidal(65, amp=0.5)
+    dev = tomg.upload(bad)
+    folded = serve.Request(rid=999, geom="folded", nx=65, ny=65, dx=bad.dx, dy=bad.dy,
+                           geometry=lambda: {"xp": dev["xp"], "yp": dev["yp"], "jac": dev["jac"],
+                                             "mask": None, "phi0": dev["phi0"]},
+                           source=lambda: dev["rho"])
+    srv = serve.Server(serve.TomgBackend(), budget_bytes=1 << 30, max_active=8)
+    srv.submit(reqs[0])
+    srv.submit(folded)
+    for r in reqs[1:]:
+        srv.submit(r)
+    done = {c.rid: c for c in srv.drain()}
+    assert len(done) == len(reqs) + 1
+    f = done[999]
+    assert f.status == tomg.TOMG_EGEOMETRY and "det J" in f.error and f.cycles == 0
+    assert "folded" not in srv.resident
+    assert all(done[r.rid].ok for r in reqs)

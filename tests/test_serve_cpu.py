@@ -233,3 +233,26 @@ def test_percentile():
     xs = list(range(101))
     assert S.percentile(xs, 50) == 50 and S.percentile(xs, 99) == 99
     assert S.percentile([1.0, 2.0], 50) == 1.5
+
+
+def test_deferred_setup_failure_is_diagnosed_and_dropped():
+    """A setup whose checks fail on the device shows up as a non-finite first
+    residual; the server reports the backend's diagnosis and does not keep
+    the geometry for warm re-use."""
+    class DeferredBackend(FakeBackend):
+        def step(self, problems, phis, fresh):
+            out = super().step(problems, phis, fresh)
+            return [math.nan if p.req.rid == 1 else r for p, r in zip(problems, out)]
+
+        def diagnose(self, problem):
+            return -3, f"det J <= 0 in request {problem.req.rid}"
+
+    be = DeferredBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    for k in range(3):
+        s.submit(req(k))
+    by = {c.rid: c for c in s.drain()}
+    assert by[1].status == -3 and "request 1" in by[1].error and by[1].cycles == 0
+    assert by[0].ok and by[2].ok
+    assert "g1" not in s.resident and "g0" in s.resident and "g2" in s.resident
+    assert s.used == sum(r.nbytes for r in s.resident.values())
