@@ -58,16 +58,18 @@ def source_params(kind, map_params, source_seed):
     return amps, np.asarray(centres)
 
 
-def circle_geometry(n, acoef, device):
+def circle_geometry(n, acoef, device, phase=0.0):
     """Perturbed-circle conductor map (see ``gen.perturbed_circle``):
-    dict(xp, yp, mask, phi0)."""
+    dict(xp, yp, mask, phi0).  `phase` rotates the perturbation of the
+    conductor boundary, R(theta - phase), for a geometry that moves in time;
+    phase 0 is the static map."""
     XI, ETA, d = _grid(n, device)
     ux, uy = XI - 0.5, ETA - 0.5
     r = torch.hypot(ux, uy)
     th = torch.atan2(uy, ux)
     R = torch.full_like(th, 0.2)
     for k, a in zip(range(2, 6), acoef):
-        R = R + 0.03 * float(a) * torch.cos(k * th)
+        R = R + 0.03 * float(a) * torch.cos(k * (th - phase))
     inner = (r >= 0.15) & (r <= 0.2)
     outer = (r > 0.2) & (r <= 0.35)
     rp = torch.where(inner, 0.15 + (r - 0.15) * (R - 0.15) / 0.05, r)
