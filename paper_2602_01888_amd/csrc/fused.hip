@@ -426,10 +426,25 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   }
 }
 
+// Tile of a block of a one-dimensional launch.  Workgroups go to the eight
+// XCDs in turn (XCD = linear id mod 8); each XCD is given one contiguous run
+// of tiles in strip-fastest order, so the neighbouring strips of a band --
+// which read each other's halo columns at about the same time -- share that
+// XCD's L2 instead of fetching the halo twice from memory.
+__device__ __forceinline__ void xcd_tile(int id, int nbx, int nby, int &bx, int &by) {
+  const int n = nbx * nby, per = n >> 3, rem = n & 7;
+  const int xcd = id & 7, q = id >> 3;
+  const int tile = xcd * per + min(xcd, rem) + q;
+  bx = tile % nbx;
+  by = tile / nbx;
+}
+
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
 __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
   if (a.skip && *a.skip != 0.0) return;
-  pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, blockIdx.x, blockIdx.y);
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (a.xcd_order) xcd_tile(blockIdx.x, a.nbx, a.nby, bx, by);
+  pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, bx, by);
 }
 
 // Entry of a batched launch holding block b (entries sorted by start).
@@ -521,7 +536,8 @@ static void launch_pass(int nu, const PassArgs<T> &a, hipStream_t s, const Batch
                          dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
     else                                                                                         \
       hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>),                \
-                         dim3(a.nbx, a.nby), dim3(kBW), 0, s, a);                                \
+                         a.xcd_order ? dim3(a.nbx * a.nby) : dim3(a.nbx, a.nby), dim3(kBW), 0,   \
+                         s, a);                                                                  \
   } while (0)
   switch (nu) {
     case 1: TOMG_LAUNCH(1); break;
@@ -615,6 +631,8 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0,
               : pick_band(a.nx, a.ny, a.W, l, pass_slots<T>(l, up, nu), 2 * nu + 3);
   a.nbx = (a.nx + a.W - 1) / a.W;
   a.nby = (a.ny + a.CH - 1) / a.CH;
+  // TOMG_XCD_ORDER=0 keeps the two-dimensional launch order (tuning only)
+  a.xcd_order = (!batch && a.nbx > 1 && env_int("TOMG_XCD_ORDER", 1) != 0) ? 1 : 0;
   return a;
 }
 

@@ -60,6 +60,7 @@ struct PassArgs {
   double *partials;          // up pass with norm: one double per block
   int CH, W;                 // band height, owned columns per block
   int nbx, nby;              // block grid
+  int xcd_order;             // tiles in XCD-contiguous order (one-dimensional grid)
   const double *skip;        // nonzero *skip: the launch does nothing (solve()
                              // queues cycles past convergence as no-ops)
 };
