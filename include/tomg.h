@@ -128,9 +128,11 @@ tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp
  * admitting new geometries while other solves run does not wait for the
  * device.  Argument errors are reported at once; the geometry checks
  * (det J, non-finite values, singular coarsest matrix) stay on the device and
- * are reported later: by the next solve (same status setup_coeffs would have
- * returned), by tomg_setup_check, and by tomg_solve_batch / tomg_batch_step,
- * which write a NaN relative residual for a problem whose setup failed.
+ * are reported later: by the next solve or residual_norm (the status
+ * setup_coeffs would have returned), by tomg_setup_check, and by
+ * tomg_solve_batch / tomg_batch_step, which write a NaN relative residual for
+ * a problem whose setup failed (tomg_solve_batch: status TOMG_ENONFINITE for
+ * it; tomg_setup_check then names the cause).
  * Inputs must stay valid until the queued work has run (stream order). */
 tomg_status tomg_setup_coeffs_async(tomg_problem *p, const double *d_xp, const double *d_yp,
                                     const double *d_jac, const double *d_eps_phys,

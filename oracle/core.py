@@ -14,6 +14,8 @@ import numpy as np
 from . import build as _build
 
 GS4, GS_LEX, JACOBI = 0, 1, 2
+# edges with a homogeneous Neumann condition (bit mask)
+NEU_W, NEU_E, NEU_S, NEU_N = 1, 2, 4, 8
 
 _lib = None
 _D = C.POINTER(C.c_double)
@@ -35,17 +37,20 @@ def _load():
         "orc_geometry_ok": (i, [i, i, _D]),
         "orc_rhs": (None, [sz, _D, _D, _D]),
         "orc_dirichlet_set": (None, [i, i, _U8, _U8]),
+        "orc_dirichlet_set_bc": (None, [i, i, _U8, i, _U8]),
         "orc_fine_stencil": (None, [i, i, d, d, _D, _D, _D, _U8, _D]),
         "orc_apply": (None, [i, i, _D, _U8, _D, _D]),
         "orc_residual": (None, [i, i, _D, _U8, _D, _D, _D]),
         "orc_norm2_free": (d, [i, i, _U8, _D]),
         "orc_smooth": (None, [i, i, _D, _U8, _D, _D, i, i, d]),
         "orc_restrict_fw": (None, [i, i, _D, i, i, _D]),
+        "orc_restrict_fw_bc": (None, [i, i, _D, i, i, _U8, _D]),
         "orc_prolong_add": (None, [i, i, _D, i, i, _U8, _D]),
         "orc_galerkin": (None, [i, i, _D, _U8, i, i, _D, _U8]),
         "orc_dense_solve": (i, [i, _D, _D]),
         "orc_levels": (i, [i, i, C.POINTER(i), C.POINTER(i), i]),
         "orc_mg_create": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, d]),
+        "orc_mg_create_bc": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, i, d]),
         "orc_mg_destroy": (None, [p]),
         "orc_mg_num_levels": (i, [p]),
         "orc_mg_level_shape": (None, [p, i, C.POINTER(i), C.POINTER(i)]),
@@ -136,10 +141,12 @@ def rhs(rho, det):
     return f
 
 
-def dirichlet_set(nx, ny, mask=None):
+def dirichlet_set(nx, ny, mask=None, neumann=0):
+    """Dirichlet flags: the outer ring except the edges in `neumann` (NEU_*
+    bits, zero normal derivative), plus the mask."""
     d = np.empty((ny, nx), dtype=np.uint8)
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
-    _load().orc_dirichlet_set(nx, ny, _u8(m), _u8(d))
+    _load().orc_dirichlet_set_bc(nx, ny, _u8(m), int(neumann), _u8(d))
     return d
 
 
@@ -161,9 +168,10 @@ def setup(prob, eps_phys=None):
         J = jacobian_numeric(prob.xp, prob.yp, prob.dx, prob.dy)
     exx, exy, eyy, det = permittivity(J, eps_phys)
     f = rhs(prob.rho, det)
-    dirs = dirichlet_set(prob.nx, prob.ny, prob.mask)
+    neumann = getattr(prob, "neumann", 0)
+    dirs = dirichlet_set(prob.nx, prob.ny, prob.mask, neumann)
     return {"jac": J, "exx": exx, "exy": exy, "eyy": eyy, "det": det, "f": f, "dir": dirs,
-            "geometry_ok": geometry_ok(det)}
+            "geometry_ok": geometry_ok(det), "neumann": neumann}
 
 
 # ------------------------------------------------------------- operator ----
@@ -204,6 +212,17 @@ def restrict_fw(rf, nxc, nyc):
     nyf, nxf = rf.shape
     fc = np.empty((nyc, nxc))
     _load().orc_restrict_fw(nxf, nyf, _d(rf), nxc, nyc, _d(fc))
+    return fc
+
+
+def restrict_fw_bc(rf, dirc):
+    """Full weighting where the coarse ring may hold free (Neumann) nodes."""
+    rf = _f64(rf)
+    nyf, nxf = rf.shape
+    nyc, nxc = dirc.shape
+    fc = np.empty((nyc, nxc))
+    _load().orc_restrict_fw_bc(nxf, nyf, _d(rf), nxc, nyc, _u8(np.ascontiguousarray(dirc)),
+                               _d(fc))
     return fc
 
 
@@ -257,18 +276,20 @@ class MG:
     mode"), GS_LEX (the paper's lexicographic ordering) or JACOBI."""
 
     def __init__(self, exx, exy, eyy, dx, dy, mask=None, nu1=2, nu2=2, smoother=GS4,
-                 omega=0.8):
+                 omega=0.8, neumann=0):
         self._keep = [_f64(exx), _f64(exy), _f64(eyy)]
         ny, nx = self._keep[0].shape
         m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         self.nx, self.ny = nx, ny
-        self._h = _load().orc_mg_create(nx, ny, dx, dy, _d(self._keep[0]), _d(self._keep[1]),
-                                        _d(self._keep[2]), _u8(m), nu1, nu2, smoother, omega)
+        self._h = _load().orc_mg_create_bc(nx, ny, dx, dy, _d(self._keep[0]),
+                                           _d(self._keep[1]), _d(self._keep[2]), _u8(m),
+                                           int(neumann), nu1, nu2, smoother, omega)
         if not self._h:
             raise ValueError(f"grid {nx}x{ny} does not coarsen to <= 9x9 nodes")
 
     @classmethod
     def from_setup(cls, s, dx, dy, mask=None, **kw):
+        kw.setdefault("neumann", s.get("neumann", 0))
         return cls(s["exx"], s["exy"], s["eyy"], dx, dy, mask=mask, **kw)
 
     def __del__(self):

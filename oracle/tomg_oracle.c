@@ -129,9 +129,20 @@ void orc_rhs(size_t n, const double *rho_phys, const double *det, double *f) {
 }
 
 void orc_dirichlet_set(int nx, int ny, const uint8_t *mask, uint8_t *dir) {
+  orc_dirichlet_set_bc(nx, ny, mask, 0, dir);
+}
+
+/* Boundary conditions of Section 4.1: the paper's semi-annulus has a zero
+ * normal derivative on its two straight sides.  An edge named in `neumann`
+ * (ORC_NEU_W: i = 0, ORC_NEU_E: i = nx-1, ORC_NEU_S: j = 0, ORC_NEU_N:
+ * j = ny-1) carries free nodes; a node is Dirichlet when it lies on an edge
+ * that is not Neumann (so a corner shared with a Dirichlet edge is
+ * Dirichlet) or under the mask. */
+void orc_dirichlet_set_bc(int nx, int ny, const uint8_t *mask, int neumann, uint8_t *dir) {
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      int ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+      int ring = (i == 0 && !(neumann & ORC_NEU_W)) || (i == nx - 1 && !(neumann & ORC_NEU_E)) ||
+                 (j == 0 && !(neumann & ORC_NEU_S)) || (j == ny - 1 && !(neumann & ORC_NEU_N));
       dir[ID(i, j, nx)] = (uint8_t)(ring || (mask && mask[ID(i, j, nx)]));
     }
 }
@@ -146,6 +157,42 @@ void orc_dirichlet_set(int nx, int ny, const uint8_t *mask, uint8_t *dir) {
  * i.e. eq. 18 before the division by k2 (the printed update omits that
  * division from the neighbour terms; expanding eq. 17 by central differences
  * puts it on every term).  eps_yx = eps_xy (eq. 13 = eq. 14). */
+/* Index reflected about the grid edge: -k below 0, 2(n-1) - k above n-1. */
+static int reflect(int k, int n) { return k < 0 ? -k : (k > n - 1 ? 2 * (n - 1) - k : k); }
+
+/* Tensor component at a node that may lie one node outside the grid: the
+ * mirror image across the edge.  Under a reflection of one axis eps_xx and
+ * eps_yy are even and eps_xy changes sign (odd = 1 for eps_xy). */
+static double mirrored(const double *a, int nx, int ny, int i, int j, int odd) {
+  int ri = reflect(i, nx), rj = reflect(j, ny);
+  double s = (odd && (ri != i) != (rj != j)) ? -1.0 : 1.0;
+  return s * a[ID(ri, rj, nx)];
+}
+
+/* Free node on the outer ring (a Neumann edge).  A zero normal derivative
+ * is imposed by a mirror ghost layer: the ghost values of phi and of the
+ * tensor are those of the node's mirror image across the edge (eps_xy with
+ * its sign changed), eq. 18 is written with them, and each ghost
+ * coefficient is then added to the coefficient of the mirror node. */
+static void edge_stencil(int nx, int ny, double idx2, double idy2, double idxy,
+                         const double *exx, const double *exy, const double *eyy, int i, int j,
+                         double a[9]) {
+  double k2 = 2.0 * (mirrored(exx, nx, ny, i, j, 0) * idx2 + mirrored(eyy, nx, ny, i, j, 0) * idy2);
+  double gx = (mirrored(exx, nx, ny, i + 1, j, 0) - mirrored(exx, nx, ny, i - 1, j, 0)) * idx2 / 4.0 +
+              (mirrored(exy, nx, ny, i, j + 1, 1) - mirrored(exy, nx, ny, i, j - 1, 1)) * idxy / 4.0;
+  double gy = (mirrored(eyy, nx, ny, i, j + 1, 0) - mirrored(eyy, nx, ny, i, j - 1, 0)) * idy2 / 4.0 +
+              (mirrored(exy, nx, ny, i + 1, j, 1) - mirrored(exy, nx, ny, i - 1, j, 1)) * idxy / 4.0;
+  double ax = mirrored(exx, nx, ny, i, j, 0) * idx2, ay = mirrored(eyy, nx, ny, i, j, 0) * idy2;
+  double k6 = mirrored(exy, nx, ny, i, j, 1) * idxy / 2.0;
+  double g[9] = {k6, ay - gy, -k6, ax - gx, -k2, ax + gx, -k6, ay + gy, k6};
+  for (int k = 0; k < 9; ++k) a[k] = 0.0;
+  for (int dj = -1; dj <= 1; ++dj)
+    for (int di = -1; di <= 1; ++di) {
+      int ti = reflect(i + di, nx) - i, tj = reflect(j + dj, ny) - j;
+      a[(tj + 1) * 3 + (ti + 1)] += g[(dj + 1) * 3 + (di + 1)];
+    }
+}
+
 void orc_fine_stencil(int nx, int ny, double dx, double dy, const double *exx,
                       const double *exy, const double *eyy, const uint8_t *dir,
                       double *st) {
@@ -158,6 +205,12 @@ void orc_fine_stencil(int nx, int ny, double dx, double dy, const double *exx,
       size_t c = ID(i, j, nx);
       if (dir[c]) {
         PLANE(st, 4, n)[c] = 1.0;
+        continue;
+      }
+      if (i == 0 || j == 0 || i == nx - 1 || j == ny - 1) {
+        double a[9];
+        edge_stencil(nx, ny, idx2, idy2, idxy, exx, exy, eyy, i, j, a);
+        for (int k = 0; k < 9; ++k) PLANE(st, k, n)[c] = a[k];
         continue;
       }
       size_t e = ID(i + 1, j, nx), w = ID(i - 1, j, nx);
@@ -185,9 +238,12 @@ void orc_fine_stencil(int nx, int ny, double dx, double dy, const double *exx,
 /* Sum of the off-centre stencil terms at (i, j). */
 static double offcentre(int nx, size_t n, const double *st, const double *x, int i, int j) {
   double s = 0.0;
+  int ny = (int)(n / (size_t)nx);
   for (int dj = -1; dj <= 1; ++dj)
     for (int di = -1; di <= 1; ++di) {
       if (di == 0 && dj == 0) continue;
+      /* a free node on a Neumann edge has no coefficient outside the grid */
+      if (i + di < 0 || i + di >= nx || j + dj < 0 || j + dj >= ny) continue;
       int k = (dj + 1) * 3 + (di + 1);
       s += PLANE(st, k, n)[ID(i, j, nx)] * x[ID(i + di, j + dj, nx)];
     }
@@ -238,8 +294,8 @@ static void relax(int nx, size_t n, const double *st, double *x, const double *b
 static void sweep_lex(int nx, int ny, const double *st, const uint8_t *dir, double *x,
                       const double *b) {
   size_t n = (size_t)nx * ny;
-  for (int i = 1; i < nx - 1; ++i)
-    for (int j = 1; j < ny - 1; ++j)
+  for (int i = 0; i < nx; ++i)
+    for (int j = 0; j < ny; ++j)
       if (!dir[ID(i, j, nx)]) relax(nx, n, st, x, b, i, j);
 }
 
@@ -253,8 +309,8 @@ static void sweep_gs4(int nx, int ny, const double *st, const uint8_t *dir, doub
   for (int colour = 0; colour < 4; ++colour) {
     int pi = colour & 1, pj = colour >> 1;
 #pragma omp parallel for schedule(static)
-    for (int j = 1 + ((1 + pj) & 1); j < ny - 1; j += 2)
-      for (int i = 1 + ((1 + pi) & 1); i < nx - 1; i += 2)
+    for (int j = pj; j < ny; j += 2)
+      for (int i = pi; i < nx; i += 2)
         if (!dir[ID(i, j, nx)]) relax(nx, n, st, x, b, i, j);
   }
 }
@@ -307,6 +363,27 @@ void orc_restrict_fw(int nxf, int nyf, const double *rf, int nxc, int nyc, doubl
     }
 }
 
+/* The same restriction where the coarse outer ring may hold free nodes (a
+ * Neumann edge): at a free ring node the sum runs over the fine nodes of its
+ * support that lie inside the grid (the transpose of the prolongation, which
+ * has no fine nodes outside); Dirichlet ring nodes get zero. */
+void orc_restrict_fw_bc(int nxf, int nyf, const double *rf, int nxc, int nyc,
+                        const uint8_t *dirc, double *fc) {
+  for (int J = 0; J < nyc; ++J)
+    for (int I = 0; I < nxc; ++I) {
+      double s = 0.0;
+      int ring = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
+      if (!ring || !dirc[ID(I, J, nxc)])
+        for (int dj = -1; dj <= 1; ++dj)
+          for (int di = -1; di <= 1; ++di) {
+            int fi = 2 * I + di, fj = 2 * J + dj;
+            if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
+            s += pw(di) * pw(dj) / 4.0 * rf[ID(fi, fj, nxf)];
+          }
+      fc[ID(I, J, nxc)] = s;
+    }
+}
+
 /* Bilinear prolongation I_H^h and the correction of eq. 24, applied at free
  * fine nodes only (Dirichlet values are never changed). */
 void orc_prolong_add(int nxc, int nyc, const double *ec, int nxf, int nyf,
@@ -335,12 +412,17 @@ void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
   size_t nf = (size_t)nxf * nyf, nc = (size_t)nxc * nyc;
   for (int J = 0; J < nyc; ++J)
     for (int I = 0; I < nxc; ++I) {
-      int d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
+      /* on the ring the coarse node keeps the kind of the fine node it sits
+       * on (Dirichlet, or free on a Neumann edge) */
+      int d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1) && dirf[ID(2 * I, 2 * J, nxf)];
       if (!d) {
         int any_free = 0;
         for (int dj = -1; dj <= 1; ++dj)
-          for (int di = -1; di <= 1; ++di)
-            if (!dirf[ID(2 * I + di, 2 * J + dj, nxf)]) any_free = 1;
+          for (int di = -1; di <= 1; ++di) {
+            int fi = 2 * I + di, fj = 2 * J + dj;
+            if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
+            if (!dirf[ID(fi, fj, nxf)]) any_free = 1;
+          }
         d = !any_free;
       }
       dirc[ID(I, J, nxc)] = (uint8_t)d;
@@ -359,6 +441,7 @@ void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
       for (int b = -1; b <= 1; ++b)
         for (int a = -1; a <= 1; ++a) {
           int fi = 2 * I + a, fj = 2 * J + b;
+          if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
           size_t f = ID(fi, fj, nxf);
           if (dirf[f]) continue;
           double wf = pw(a) * pw(b);
@@ -366,6 +449,7 @@ void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
           for (int q = -1; q <= 1; ++q)
             for (int p = -1; p <= 1; ++p) {
               int gi = fi + p, gj = fj + q;
+              if (gi < 0 || gj < 0 || gi >= nxf || gj >= nyf) continue;
               size_t g = ID(gi, gj, nxf);
               if (dirf[g]) continue;
               double a_fg = PLANE(stf, (q + 1) * 3 + (p + 1), nf)[f];
@@ -457,6 +541,12 @@ struct orc_mg {
 orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
                       const double *exy, const double *eyy, const uint8_t *mask,
                       int nu1, int nu2, int smoother, double omega) {
+  return orc_mg_create_bc(nx, ny, dx, dy, exx, exy, eyy, mask, 0, nu1, nu2, smoother, omega);
+}
+
+orc_mg *orc_mg_create_bc(int nx, int ny, double dx, double dy, const double *exx,
+                         const double *exy, const double *eyy, const uint8_t *mask,
+                         int neumann, int nu1, int nu2, int smoother, double omega) {
   orc_mg *mg = (orc_mg *)calloc(1, sizeof(orc_mg));
   mg->L = orc_levels(nx, ny, mg->nx, mg->ny, ORC_MAXL);
   if (mg->L == 0) {
@@ -475,7 +565,7 @@ orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
     mg->b[l] = (double *)calloc(n, sizeof(double));
     mg->r[l] = (double *)calloc(n, sizeof(double));
   }
-  orc_dirichlet_set(nx, ny, mask, mg->dir[0]);
+  orc_dirichlet_set_bc(nx, ny, mask, neumann, mg->dir[0]);
   orc_fine_stencil(nx, ny, dx, dy, exx, exy, eyy, mg->dir[0], mg->st[0]);
   for (int l = 1; l < mg->L; ++l)
     orc_galerkin(mg->nx[l - 1], mg->ny[l - 1], mg->st[l - 1], mg->dir[l - 1], mg->nx[l],
@@ -494,6 +584,7 @@ orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
       if (row < 0) continue;
       for (int dj = -1; dj <= 1; ++dj)
         for (int di = -1; di <= 1; ++di) {
+          if (I + di < 0 || J + dj < 0 || I + di >= cx || J + dj >= cy) continue;
           int col = mg->cidx[ID(I + di, J + dj, cx)];
           if (col < 0) continue;
           mg->Ac[(size_t)row * mg->m + col] =
@@ -553,7 +644,8 @@ static void vcycle_level(orc_mg *mg, int l, double *x, const double *b) {
   }
   orc_smooth(nx, ny, mg->st[l], mg->dir[l], x, b, mg->smoother, mg->nu1, mg->omega);
   orc_residual(nx, ny, mg->st[l], mg->dir[l], x, b, mg->r[l]);
-  orc_restrict_fw(nx, ny, mg->r[l], mg->nx[l + 1], mg->ny[l + 1], mg->b[l + 1]);
+  orc_restrict_fw_bc(nx, ny, mg->r[l], mg->nx[l + 1], mg->ny[l + 1], mg->dir[l + 1],
+                     mg->b[l + 1]);
   memset(mg->x[l + 1], 0, (size_t)mg->nx[l + 1] * mg->ny[l + 1] * sizeof(double));
   vcycle_level(mg, l + 1, mg->x[l + 1], mg->b[l + 1]);
   orc_prolong_add(mg->nx[l + 1], mg->ny[l + 1], mg->x[l + 1], nx, ny, mg->dir[l], x);

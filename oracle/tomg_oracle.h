@@ -26,6 +26,8 @@ extern "C" {
 #endif
 
 enum { ORC_GS4 = 0, ORC_GS_LEX = 1, ORC_JACOBI = 2 };
+/* Edges with a homogeneous Neumann condition (bit mask). */
+enum { ORC_NEU_W = 1, ORC_NEU_E = 2, ORC_NEU_S = 4, ORC_NEU_N = 8 };
 
 int orc_num_threads(void);
 
@@ -54,10 +56,13 @@ void orc_rhs(size_t n, const double *rho_phys, const double *det, double *f);
 
 /* Dirichlet set: outer ring plus mask (nullable). */
 void orc_dirichlet_set(int nx, int ny, const uint8_t *mask, uint8_t *dir);
+/* The same with the edges in `neumann` left free (zero normal derivative). */
+void orc_dirichlet_set_bc(int nx, int ny, const uint8_t *mask, int neumann, uint8_t *dir);
 
 /* The paper's 9-point operator (eq. 18 and its coefficients k1..k6) written
  * as an explicit stencil at every free node; identity rows at Dirichlet
- * nodes. */
+ * nodes.  A free node on the outer ring (Neumann edge) takes eq. 18 with a
+ * mirror ghost layer, folded onto the mirror nodes. */
 void orc_fine_stencil(int nx, int ny, double dx, double dy, const double *exx,
                       const double *exy, const double *eyy, const uint8_t *dir,
                       double *st);
@@ -73,6 +78,8 @@ void orc_smooth(int nx, int ny, const double *st, const uint8_t *dir, double *x,
 
 void orc_restrict_fw(int nxf, int nyf, const double *rf, int nxc, int nyc,
                      double *fc);
+void orc_restrict_fw_bc(int nxf, int nyf, const double *rf, int nxc, int nyc,
+                        const uint8_t *dirc, double *fc);
 void orc_prolong_add(int nxc, int nyc, const double *ec, int nxf, int nyf,
                      const uint8_t *dirf, double *xf);
 void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
@@ -89,6 +96,9 @@ int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl);
 orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
                       const double *exy, const double *eyy, const uint8_t *mask,
                       int nu1, int nu2, int smoother, double omega);
+orc_mg *orc_mg_create_bc(int nx, int ny, double dx, double dy, const double *exx,
+                         const double *exy, const double *eyy, const uint8_t *mask,
+                         int neumann, int nu1, int nu2, int smoother, double omega);
 void orc_mg_destroy(orc_mg *mg);
 int orc_mg_num_levels(const orc_mg *mg);
 void orc_mg_level_shape(const orc_mg *mg, int l, int *nx, int *ny);

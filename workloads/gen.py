@@ -11,7 +11,8 @@ Conventions shared with both solvers:
 * ``rho`` is the physical charge density rho' sampled at (xp, yp); the problem
   solved is div'(grad' phi) = -rho' in the physical domain;
 * ``mask`` (uint8, or None) marks interior nodes held at a Dirichlet value;
-  the outer ring of nodes is always Dirichlet;
+  the outer ring of nodes is Dirichlet except on the edges named by
+  ``neumann`` (zero normal derivative there);
 * ``phi0`` carries the Dirichlet data on the outer ring and on masked nodes,
   and zero on every free node;
 * ``phi_exact`` (when a closed form exists) is the continuous solution at the
@@ -47,6 +48,9 @@ class GridProblem:
     mask: Optional[np.ndarray] = None
     phi_exact: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
+    # edges with a zero normal derivative instead of Dirichlet data, bits
+    # 1: i = 0, 2: i = nx-1, 4: j = 0, 8: j = ny-1
+    neumann: int = 0
 
     @property
     def dof(self) -> int:
@@ -133,12 +137,13 @@ def manufactured_sinusoidal(n: int = 129, amp: float = 0.1, ny: Optional[int] = 
 
 
 def polar_semi_annulus(n: int, a: float = 2.0, R: float = 5.0, phi_a: float = 1.0,
-                       ny: Optional[int] = None) -> GridProblem:
+                       ny: Optional[int] = None, neumann: bool = False) -> GridProblem:
     """Polar map x' = xi cos(eta), y' = xi sin(eta) with xi in [a, R] and eta in
     [0, pi] (the paper's semi-annulus, Section 4.1, with a = 2, R = 5).
     rho' = 0; exact phi = phi_a ln(R/r)/ln(R/a).  Dirichlet data from the exact
-    solution on the whole outer ring (the paper uses Neumann data on the two
-    straight sides; the exact solution satisfies both)."""
+    solution on the whole outer ring, or, with neumann=True, as in the paper:
+    Dirichlet data on the arcs r = a, R only and a zero normal derivative on the
+    two straight sides eta = 0, pi (the exact solution satisfies both)."""
     ny = n if ny is None else ny
     dx = (R - a) / (n - 1)
     dy = math.pi / (ny - 1)
@@ -148,9 +153,13 @@ def polar_semi_annulus(n: int, a: float = 2.0, R: float = 5.0, phi_a: float = 1.
     jac = np.stack([np.cos(ETA), -XI * np.sin(ETA), np.sin(ETA), XI * np.cos(ETA)])
     phi = phi_a * np.log(R / XI) / math.log(R / a)
     ring = _outer_ring(ny, n)
-    return GridProblem(f"semi_annulus_{n}", n, ny, a, 0.0, dx, dy, xp, yp,
-                       np.zeros((ny, n)), _phi0_from(phi, ring), jac=jac,
-                       phi_exact=phi, meta={"a": a, "R": R})
+    if neumann:
+        ring[1:-1, :] = False
+        ring[:, 1:-1] = False
+        ring[:, 0] = ring[:, -1] = True
+    return GridProblem(f"semi_annulus_{n}" + ("_neumann" if neumann else ""), n, ny, a, 0.0,
+                       dx, dy, xp, yp, np.zeros((ny, n)), _phi0_from(phi, ring), jac=jac,
+                       phi_exact=phi, meta={"a": a, "R": R}, neumann=12 if neumann else 0)
 
 
 def sinh_stretch(n: int = 129, s: float = 5.0, alpha: float = 0.6, L: float = 6.0,
