@@ -74,8 +74,22 @@ typedef struct {
                               TOMG_JACOBI (damped Jacobi) */
   double jacobi_omega;     /* damping of TOMG_JACOBI (default 0.8) */
   int32_t ir_inner_cycles; /* FP32 V-cycles per refinement step (default 2) */
-  int32_t reserved[3];     /* set to zero */
+  int32_t neumann;         /* edges with a homogeneous Neumann condition
+                              (Section 4.1: zero normal derivative), a mask of
+                              TOMG_NEU_W (i = 0), TOMG_NEU_E (i = nx-1),
+                              TOMG_NEU_S (j = 0), TOMG_NEU_N (j = ny-1); default
+                              0 (Dirichlet all round).  Nodes of these edges are
+                              unknowns (a corner shared with a Dirichlet edge is
+                              Dirichlet); eq. 18 is applied there with a mirror
+                              ghost layer (phi and the tensor mirrored across
+                              the edge, eps_xy with its sign changed) folded onto
+                              the mirror nodes.  Requires TOMG_FP64; such a
+                              problem runs the unfused cycle (one launch per
+                              colour, residual, transfer) and cannot be batched */
+  int32_t reserved[2];     /* set to zero */
 } tomg_config;
+
+enum { TOMG_NEU_W = 1, TOMG_NEU_E = 2, TOMG_NEU_S = 4, TOMG_NEU_N = 8 };
 
 /* Fills *cfg with the defaults above for an nx x ny grid of spacing dx, dy. */
 void tomg_config_default(tomg_config *cfg, int32_t nx, int32_t ny, double dx, double dy);
@@ -234,7 +248,8 @@ enum {
   TOMG_FIELD_DET = 3,
   TOMG_FIELD_RHS = 4,    /* level 0 f, or level l >= 1 coarse right-hand side */
   TOMG_FIELD_DIR = 5,    /* uint8 Dirichlet flags of level l */
-  TOMG_FIELD_STENCIL = 6,/* level l >= 1: 9 planes, plane k = (dj+1)*3+(di+1) */
+  TOMG_FIELD_STENCIL = 6,/* level l >= 1, and level 0 with Neumann edges (the folded
+                            operator): 9 planes, plane k = (dj+1)*3+(di+1) */
   TOMG_FIELD_X = 7       /* level l >= 1 correction from the last V-cycle */
 };
 /* Copies array `what` of level `level` into d_out (device); asynchronous. */

@@ -49,6 +49,7 @@ def _load():
         "orc_galerkin": (None, [i, i, _D, _U8, i, i, _D, _U8]),
         "orc_dense_solve": (i, [i, _D, _D]),
         "orc_levels": (i, [i, i, C.POINTER(i), C.POINTER(i), i]),
+        "orc_levels_lim": (i, [i, i, C.POINTER(i), C.POINTER(i), i, i]),
         "orc_mg_create": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, d]),
         "orc_mg_create_bc": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, i, d]),
         "orc_mg_destroy": (None, [p]),
@@ -253,10 +254,11 @@ def dense_solve(A, b):
     return b
 
 
-def levels(nx, ny, maxl=16):
+def levels(nx, ny, maxl=16, neumann=0):
+    """Level shapes; with Neumann edges the coarsest is at most 5 x 5."""
     a = (C.c_int * maxl)()
     b = (C.c_int * maxl)()
-    L = _load().orc_levels(nx, ny, a, b, maxl)
+    L = _load().orc_levels_lim(nx, ny, a, b, maxl, 5 if neumann else 9)
     return [(a[k], b[k]) for k in range(L)]
 
 

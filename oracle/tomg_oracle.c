@@ -508,6 +508,15 @@ int orc_dense_solve(int m, double *A, double *b) {
  * levels, or 0 when the grid cannot reach a coarsest level of at most 9x9
  * nodes. */
 int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl) {
+  return orc_levels_lim(nx, ny, nxs, nys, maxl, 9);
+}
+
+/* The same with the coarsest side bounded by `lim` nodes.  With Neumann
+ * edges the coarsest ring holds unknowns too, so the hierarchy is taken one
+ * halving further, to at most 5 x 5 nodes, which keeps the direct coarsest
+ * system as small as the all-Dirichlet 9 x 9 one (at most 49 unknowns
+ * there, at most 25 here). */
+int orc_levels_lim(int nx, int ny, int *nxs, int *nys, int maxl, int lim) {
   int L = 1;
   nxs[0] = nx;
   nys[0] = ny;
@@ -515,13 +524,13 @@ int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl) {
   while (L < maxl) {
     int cx = nxs[L - 1], cy = nys[L - 1];
     int can = ((cx - 1) % 2 == 0) && ((cy - 1) % 2 == 0) && cx >= 5 && cy >= 5;
-    int want = (L == 1) || cx > 9 || cy > 9;
+    int want = (L == 1) || cx > lim || cy > lim;
     if (!(can && want)) break;
     nxs[L] = (cx - 1) / 2 + 1;
     nys[L] = (cy - 1) / 2 + 1;
     ++L;
   }
-  if (L < 2 || nxs[L - 1] > 9 || nys[L - 1] > 9) return 0;
+  if (L < 2 || nxs[L - 1] > lim || nys[L - 1] > lim) return 0;
   return L;
 }
 
@@ -548,7 +557,7 @@ orc_mg *orc_mg_create_bc(int nx, int ny, double dx, double dy, const double *exx
                          const double *exy, const double *eyy, const uint8_t *mask,
                          int neumann, int nu1, int nu2, int smoother, double omega) {
   orc_mg *mg = (orc_mg *)calloc(1, sizeof(orc_mg));
-  mg->L = orc_levels(nx, ny, mg->nx, mg->ny, ORC_MAXL);
+  mg->L = orc_levels_lim(nx, ny, mg->nx, mg->ny, ORC_MAXL, neumann ? 5 : 9);
   if (mg->L == 0) {
     free(mg);
     return NULL;

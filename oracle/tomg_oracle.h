@@ -93,6 +93,7 @@ int orc_dense_solve(int m, double *A, double *b);
 /* Multigrid hierarchy. */
 typedef struct orc_mg orc_mg;
 int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl);
+int orc_levels_lim(int nx, int ny, int *nxs, int *nys, int maxl, int lim);
 orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
                       const double *exy, const double *eyy, const uint8_t *mask,
                       int nu1, int nu2, int smoother, double omega);

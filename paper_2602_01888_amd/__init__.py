@@ -18,7 +18,8 @@ import torch  # noqa: F401  (binds the HIP runtime before the library loads)
 from . import _lib
 from ._lib import (FIELD, STATUS_NAMES, TOMG_EGEOMETRY, TOMG_EINVAL, TOMG_ENOCONV,  # noqa: F401
                    TOMG_ENOMEM, TOMG_ENONFINITE, TOMG_ESTATE, TOMG_FP32_IR, TOMG_FP64,
-                   TOMG_GS4, TOMG_JACOBI, TOMG_OK, Config)
+                   TOMG_GS4, TOMG_JACOBI, TOMG_NEU_E, TOMG_NEU_N, TOMG_NEU_S, TOMG_NEU_W,
+                   TOMG_OK, Config)
 
 
 class TomgError(RuntimeError):
@@ -28,7 +29,7 @@ class TomgError(RuntimeError):
 
 
 def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
-                smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2) -> Config:
+                smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, neumann=0) -> Config:
     lib = _lib.load()
     cfg = Config()
     lib.tomg_config_default(C.byref(cfg), nx, ny, dx, dy)
@@ -38,6 +39,7 @@ def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=
     cfg.smoother = {"gs4": TOMG_GS4, "jacobi": TOMG_JACOBI}[smoother]
     cfg.jacobi_omega = jacobi_omega
     cfg.ir_inner_cycles = ir_inner_cycles
+    cfg.neumann = int(neumann)
     return cfg
 
 
@@ -80,10 +82,10 @@ class Problem:
 
     def __init__(self, nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
                  smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, device=None,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, neumann=0):
         self.lib = _lib.load()
         self.cfg = make_config(nx, ny, dx, dy, xi0, eta0, precision, nu1, nu2, smoother,
-                               jacobi_omega, ir_inner_cycles)
+                               jacobi_omega, ir_inner_cycles, neumann)
         self.nx, self.ny = nx, ny
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:
@@ -99,7 +101,9 @@ class Problem:
 
     @classmethod
     def from_grid(cls, prob, **kw):
-        """Problem sized for a ``workloads.GridProblem``."""
+        """Problem sized for a ``workloads.GridProblem`` (its Neumann edges
+        included)."""
+        kw.setdefault("neumann", getattr(prob, "neumann", 0))
         return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.xi0, prob.eta0, **kw)
 
     # -- lifecycle ----------------------------------------------------------

@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "TOMG_OK", -1: "TOMG_EINVAL", -2: "TOMG_ENOMEM", -3: "TOMG_EG
                 -7: "TOMG_ESTATE"}
 TOMG_FP64, TOMG_FP32_IR = 0, 1
 TOMG_GS4, TOMG_JACOBI = 0, 1
+TOMG_NEU_W, TOMG_NEU_E, TOMG_NEU_S, TOMG_NEU_N = 1, 2, 4, 8
 FIELD = {"exx": 0, "exy": 1, "eyy": 2, "det": 3, "rhs": 4, "dir": 5, "stencil": 6, "x": 7}
 
 # Every symbol include/tomg.h declares.
@@ -33,7 +34,7 @@ class Config(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("precision", C.c_int32),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32),
                 ("jacobi_omega", C.c_double), ("ir_inner_cycles", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("neumann", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 _lib = None

@@ -13,8 +13,11 @@
 namespace tomg {
 
 // Halve while both node counts minus one are even and each side keeps at
-// least 3 nodes; coarsen at least once, then while a side exceeds 9 nodes.
-int level_shapes(int nx, int ny, int *nxs, int *nys) {
+// least 3 nodes; coarsen at least once, then while a side exceeds 9 nodes
+// (5 with Neumann edges, whose ring nodes are unknowns on the coarsest
+// level too: at most 25 coarsest unknowns instead of 49).
+int level_shapes(int nx, int ny, int *nxs, int *nys, int neumann) {
+  const int lim = neumann ? 5 : 9;
   if (nx < 5 || ny < 5) return 0;
   int L = 1;
   nxs[0] = nx;
@@ -22,13 +25,13 @@ int level_shapes(int nx, int ny, int *nxs, int *nys) {
   while (L < kMaxLevels) {
     const int cx = nxs[L - 1], cy = nys[L - 1];
     const bool halvable = ((cx - 1) % 2 == 0) && ((cy - 1) % 2 == 0) && cx >= 5 && cy >= 5;
-    const bool wanted = (L == 1) || cx > 9 || cy > 9;
+    const bool wanted = (L == 1) || cx > lim || cy > lim;
     if (!halvable || !wanted) break;
     nxs[L] = (cx - 1) / 2 + 1;
     nys[L] = (cy - 1) / 2 + 1;
     ++L;
   }
-  if (L < 2 || nxs[L - 1] > 9 || nys[L - 1] > 9) return 0;
+  if (L < 2 || nxs[L - 1] > lim || nys[L - 1] > lim) return 0;
   return L;
 }
 
@@ -40,15 +43,17 @@ static bool config_ok(const tomg_config &c) {
   if (c.smoother != TOMG_GS4 && c.smoother != TOMG_JACOBI) return false;
   if (c.smoother == TOMG_JACOBI && !(c.jacobi_omega > 0.0 && c.jacobi_omega <= 1.0)) return false;
   if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
+  if (c.neumann < 0 || c.neumann > 15) return false;
+  if (c.neumann && c.precision != TOMG_FP64) return false;
   int a[kMaxLevels], b[kMaxLevels];
-  return level_shapes(c.nx, c.ny, a, b) > 0;
+  return level_shapes(c.nx, c.ny, a, b, c.neumann) > 0;
 }
 
 bool make_layout(const tomg_config &cfg, Layout *lay) {
   if (!config_ok(cfg)) return false;
   Layout &o = *lay;
   o = Layout();
-  o.L = level_shapes(cfg.nx, cfg.ny, o.nx, o.ny);
+  o.L = level_shapes(cfg.nx, cfg.ny, o.nx, o.ny, cfg.neumann);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -70,6 +75,8 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
   o.f = take(n0 * 8);
   o.tmp = take(n0 * 8);
   o.dir[0] = take(n0);
+  // Neumann edges: the level-0 stencil with the ghost layer folded in
+  if (cfg.neumann) o.st[0] = take(9 * n0 * 8);
   for (int l = 1; l < o.L; ++l) {
     const size_t n = (size_t)o.nx[l] * o.ny[l];
     o.st[l] = take(9 * n * 8);
@@ -157,7 +164,7 @@ void tomg_config_default(tomg_config *cfg, int32_t nx, int32_t ny, double dx, do
 int32_t tomg_num_levels(const tomg_config *cfg) {
   if (!cfg || !config_ok(*cfg)) return 0;
   int a[kMaxLevels], b[kMaxLevels];
-  return level_shapes(cfg->nx, cfg->ny, a, b);
+  return level_shapes(cfg->nx, cfg->ny, a, b, cfg->neumann);
 }
 
 size_t tomg_workspace_bytes(const tomg_config *cfg) {
@@ -203,6 +210,7 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
     v.ny = lay.ny[l];
     v.n = (size_t)v.nx * v.ny;
     v.dir = (uint8_t *)(w + lay.dir[l]);
+    if (l == 0 && cfg->neumann) v.st = D(lay.st[0]);
     if (l > 0) {
       v.st = D(lay.st[l]);
       v.x = D(lay.x[l]);
@@ -415,7 +423,9 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
       break;
     }
     int k = 1;
-    const bool queue = p->cfg.smoother == TOMG_GS4;  // the Jacobi path checks every cycle
+    // the unfused cycles (Jacobi, Neumann edges) have no convergence check of
+    // their own and are checked after every cycle
+    const bool queue = p->cfg.smoother == TOMG_GS4 && !p->cfg.neumann;
     if (queue) {
       const double rate = queued > 0 ? std::pow(rel / prev, 1.0 / queued) : NAN;
       if (std::isfinite(rate) && rate > 0.0 && rate < 1.0)
@@ -468,7 +478,7 @@ bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
     const tomg_problem *p = probs[k];
     if (!p || !d_phis[k] || !p->ready) return false;
     if (p->cfg.precision != lead->cfg.precision || p->cfg.nu1 != lead->cfg.nu1 ||
-        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 ||
+        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 || p->cfg.neumann ||
         p->cfg.ir_inner_cycles != lead->cfg.ir_inner_cycles)
       return false;
   }
@@ -626,6 +636,7 @@ tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, doubl
   if (!p || !d_xp || !d_yp) return TOMG_EINVAL;
   if (!(rel_tol > 0.0) || max_cycles < 0)
     return fail(p, TOMG_EINVAL, "laplace_grid: bad tol/max_cycles");
+  if (p->cfg.neumann) return fail(p, TOMG_EINVAL, "laplace_grid: needs Dirichlet edges");
   p->ready = false;
   p->unchecked = false;
   HIP_TRY(p, hipMemsetAsync(p->scal + kSlotBadRhs, 0, sizeof(double), p->stream));
@@ -674,7 +685,7 @@ tomg_status tomg_export(tomg_problem *p, int32_t what, int32_t level, void *d_ou
     case TOMG_FIELD_DET: src = level == 0 ? p->det : nullptr; bytes = v.n * 8; break;
     case TOMG_FIELD_RHS: src = level == 0 ? p->f : v.b; bytes = v.n * 8; break;
     case TOMG_FIELD_DIR: src = v.dir; bytes = v.n; break;
-    case TOMG_FIELD_STENCIL: src = level > 0 ? v.st : nullptr; bytes = 9 * v.n * 8; break;
+    case TOMG_FIELD_STENCIL: src = v.st; bytes = 9 * v.n * 8; break;  // level 0: Neumann only
     case TOMG_FIELD_X: src = level > 0 ? v.x : nullptr; bytes = v.n * 8; break;
     default: break;
   }

@@ -84,6 +84,41 @@ struct StOp {
   }
 };
 
+// Stored stencil on a level whose outer ring may hold free nodes (Neumann
+// edges).  A free ring node has no coefficient outside the grid, so the
+// neighbours it would read there are replaced by in-range nodes (the
+// products with the zero coefficients vanish); loads never leave the array.
+template <typename T>
+struct StOpB {
+  const T *st;
+  size_t n;
+  int nx, ny;
+  __device__ __forceinline__ void row(size_t c, const T *x, T &off, T &diag) const {
+    const int j = (int)(c / (size_t)nx), i = (int)(c - (size_t)j * nx);
+    const size_t s = (size_t)nx;
+    const size_t w = i > 0 ? c - 1 : c, e = i < nx - 1 ? c + 1 : c;
+    const size_t ds = j > 0 ? s : 0, us = j < ny - 1 ? s : 0;
+    off = st[c] * x[w - ds] + st[n + c] * x[c - ds] + st[2 * n + c] * x[e - ds] +
+          st[3 * n + c] * x[w] + st[5 * n + c] * x[e] + st[6 * n + c] * x[w + us] +
+          st[7 * n + c] * x[c + us] + st[8 * n + c] * x[e + us];
+    diag = st[4 * n + c];
+  }
+  __device__ __forceinline__ T diag(size_t c) const { return st[4 * n + c]; }
+  __device__ __forceinline__ void full(size_t c, T a[9]) const {
+    for (int k = 0; k < 9; ++k) a[k] = st[k * n + c];
+  }
+};
+
+template <typename T>
+StOpB<T> st_op_b(const T *st, int nx, int ny) {
+  StOpB<T> o;
+  o.st = st;
+  o.n = (size_t)nx * ny;
+  o.nx = nx;
+  o.ny = ny;
+  return o;
+}
+
 template <typename T>
 EpsOp<T> eps_op(const T *exx, const T *exy, const T *eyy, int nx, double dx, double dy) {
   EpsOp<T> o;
@@ -187,7 +222,7 @@ __global__ void k_setup(int nx, int ny, double dx, double dy, const double *__re
                         double *__restrict__ det, double *__restrict__ f,
                         uint8_t *__restrict__ dir, float *__restrict__ exx32,
                         float *__restrict__ exy32, float *__restrict__ eyy32,
-                        double *__restrict__ partials) {
+                        double *__restrict__ partials, int neumann) {
   const size_t n = (size_t)nx * ny;
   const double i2dx = 0.5 / dx, i2dy = 0.5 / dy;
   double mind = INFINITY, bad = 0.0;
@@ -231,9 +266,16 @@ __global__ void k_setup(int nx, int ny, double dx, double dy, const double *__re
         exy32[c] = (float)vxy;
         eyy32[c] = (float)vyy;
       }
-      const bool ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+      // the ring is Dirichlet except on Neumann edges (a corner shared with
+      // a Dirichlet edge stays Dirichlet)
+      const bool ring = (i == 0 && !(neumann & TOMG_NEU_W)) ||
+                        (i == nx - 1 && !(neumann & TOMG_NEU_E)) ||
+                        (j == 0 && !(neumann & TOMG_NEU_S)) ||
+                        (j == ny - 1 && !(neumann & TOMG_NEU_N));
       dir[c] = (uint8_t)(ring || (mask && mask[c]));
-      const bool corner = (i == 0 || i == nx - 1) && (j == 0 || j == ny - 1);
+      // the operator never reads a Dirichlet corner; a corner between two
+      // Neumann edges is an unknown and is checked like any other node
+      const bool corner = ring && (i == 0 || i == nx - 1) && (j == 0 || j == ny - 1);
       if (!corner) {
         mind = fmin(mind, D);
         if (!isfinite(vxx) || !isfinite(vxy) || !isfinite(vyy) || !isfinite(fv)) bad += 1.0;
@@ -245,6 +287,56 @@ __global__ void k_setup(int nx, int ny, double dx, double dy, const double *__re
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = m;
     partials[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// Neumann edges: the level-0 operator written out as a 9-point stencil at
+// every node (identity rows at Dirichlet nodes).  At a free node the
+// coefficients are those of eq. 18 (k1..k6); at a free node of the outer
+// ring the values outside the grid are ghosts, the mirror images across the
+// edge (eps_xx, eps_yy mirrored, eps_xy mirrored with its sign changed, phi
+// mirrored), so the coefficient of each ghost is added to that of the node
+// it mirrors.  Memory-order grid stride.
+__device__ __forceinline__ int mirror_index(int k, int n) {
+  return k < 0 ? -k : (k > n - 1 ? 2 * (n - 1) - k : k);
+}
+
+__global__ void k_fold_stencil(EpsOp<double> op, int ny, const uint8_t *__restrict__ dir,
+                               double *__restrict__ st) {
+  const int nx = op.nx;
+  const size_t n = (size_t)nx * ny;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(c / (size_t)nx), i = (int)(c - (size_t)j * nx);
+    double a[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = 0.0;
+    if (dir[c]) {
+      a[4] = 1.0;
+    } else {
+      // tensor component at (ii, jj), one node outside the grid at most
+      auto ev = [&](const double *v, int ii, int jj, bool odd) {
+        const int ri = mirror_index(ii, nx), rj = mirror_index(jj, ny);
+        const double s = (odd && ((ri != ii) != (rj != jj))) ? -1.0 : 1.0;
+        return s * v[(size_t)rj * nx + ri];
+      };
+      const double ax = op.exx[c] * op.cx, ay = op.eyy[c] * op.cy;
+      const double gx = (ev(op.exx, i + 1, j, false) - ev(op.exx, i - 1, j, false)) * op.qx +
+                        (ev(op.exy, i, j + 1, true) - ev(op.exy, i, j - 1, true)) * op.qxy;
+      const double gy = (ev(op.eyy, i, j + 1, false) - ev(op.eyy, i, j - 1, false)) * op.qy +
+                        (ev(op.exy, i + 1, j, true) - ev(op.exy, i - 1, j, true)) * op.qxy;
+      const double k6 = op.exy[c] * op.hxy;
+      const double g[9] = {k6, ay - gy, -k6, ax - gx, -2.0 * (ax + ay), ax + gx, -k6, ay + gy, k6};
+#pragma unroll
+      for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+        for (int di = -1; di <= 1; ++di) {
+          const int ti = mirror_index(i + di, nx) - i, tj = mirror_index(j + dj, ny) - j;
+          a[(tj + 1) * 3 + ti + 1] += g[(dj + 1) * 3 + di + 1];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) st[k * n + c] = a[k];
   }
 }
 
@@ -376,7 +468,9 @@ __global__ __launch_bounds__(kGX *kGY) void k_coarsen(Op opf, const uint8_t *dir
     const int I = I0 - 1 + x, J = J0 - 1 + y;
     uint8_t d = 1;
     if (I >= 0 && J >= 0 && I < nxc && J < nyc) {
-      d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
+      // on the ring the coarse node keeps the kind of the fine node under it
+      // (Dirichlet, or free on a Neumann edge)
+      d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1) && DF[2 * y + 1][2 * x + 1];
       if (!d) {
         bool all = true;
 #pragma unroll
@@ -390,7 +484,8 @@ __global__ __launch_bounds__(kGX *kGY) void k_coarsen(Op opf, const uint8_t *dir
     DC[y][x] = d;
   }
   // fine stencils at (2 I0 - 1 + x, 2 J0 - 1 + y) = flag window (x + 2, y + 2);
-  // a non-Dirichlet fine node is interior, so its stencil is defined
+  // a non-Dirichlet fine node is interior or on a Neumann edge, where the
+  // stored stencil has no coefficient outside the grid
   for (int k = t; k < kGFX * kGFY; k += NT) {
     const int x = k % kGFX, y = k / kGFX;
     double s[9];
@@ -492,7 +587,9 @@ __global__ __launch_bounds__(kGX *kGY) void k_coarsen_eps(EpsOp<double> op, cons
     const int I = I0 - 1 + x, J = J0 - 1 + y;
     uint8_t d = 1;
     if (I >= 0 && J >= 0 && I < nxc && J < nyc) {
-      d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
+      // on the ring the coarse node keeps the kind of the fine node under it
+      // (Dirichlet, or free on a Neumann edge)
+      d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1) && DF[2 * y + 1][2 * x + 1];
       if (!d) {
         bool all = true;
 #pragma unroll
@@ -675,13 +772,13 @@ __global__ void k_zero(T *x, size_t n) {
 }
 
 // One colour of four-colour Gauss-Seidel: nodes with i = i0 (mod 2),
-// j = j0 (mod 2), 1 <= i <= nx-2, 1 <= j <= ny-2, not Dirichlet.
+// j = j0 (mod 2) that are not Dirichlet (ring nodes only on Neumann edges).
 template <class Op, typename T>
 __global__ void k_gs_colour(Op op, T *x, const T *b, const uint8_t *dir, int nx, int ny, int i0,
                             int j0) {
   const int i = i0 + 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
   const int j = j0 + 2 * (int)(blockIdx.y * blockDim.y + threadIdx.y);
-  if (i > nx - 2 || j > ny - 2) return;
+  if (i > nx - 1 || j > ny - 1) return;
   const size_t c = (size_t)j * nx + i;
   if (dir[c]) return;
   T off, dg;
@@ -720,17 +817,23 @@ __global__ void k_jacobi_update(Op op, T *x, const T *r, const uint8_t *dir, int
 
 // Residual (eq. 20) and full-weighting restriction into the coarse
 // right-hand side (eq. 23): weights 4, 2, 1 over 16.
+// dirc (Neumann edges, else null): the coarse flags; a free coarse ring node
+// sums the fine nodes of its support that lie inside the grid.
 template <class Op, typename T>
 __global__ void k_restrict(Op op, const T *x, const T *b, const uint8_t *dir, int nxf, T *bc,
-                           int nxc, int nyc) {
+                           int nxc, int nyc, const uint8_t *dirc) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   const int J = blockIdx.y * blockDim.y + threadIdx.y;
   if (I >= nxc || J >= nyc) return;
+  const int nyf = 2 * (nyc - 1) + 1;
   T s = T(0);
-  if (!(I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1)) {
+  const bool ring = I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1;
+  if (!ring || (dirc && !dirc[(size_t)J * nxc + I])) {
     for (int dj = -1; dj <= 1; ++dj)
       for (int di = -1; di <= 1; ++di) {
-        const size_t f = (size_t)(2 * J + dj) * nxf + (2 * I + di);
+        const int fi = 2 * I + di, fj = 2 * J + dj;
+        if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
+        const size_t f = (size_t)fj * nxf + fi;
         if (dir[f]) continue;
         T off, dg;
         op.row(f, x, off, dg);
@@ -782,6 +885,22 @@ __device__ __forceinline__ double resid0(const RedArgs &a, const double *x, int 
   return a.f[c] - off + k2 * v(c);
 }
 
+// The same from the stored level-0 stencil (Neumann edges: free nodes on the
+// ring; neighbours outside the grid carry zero coefficients and are read at
+// in-range nodes instead).
+template <bool ZF>
+__device__ __forceinline__ double resid_st(const RedArgs &a, const double *x, int i, int j) {
+  const size_t s = (size_t)a.nx, c = (size_t)j * a.nx + i, n = s * a.ny;
+  auto v = [&](size_t q) -> double { return (ZF && !a.dir[q]) ? 0.0 : x[q]; };
+  const size_t w = i > 0 ? c - 1 : c, e = i < a.nx - 1 ? c + 1 : c;
+  const size_t ds = j > 0 ? s : 0, us = j < a.ny - 1 ? s : 0;
+  const double *st = a.st0;
+  const double off = st[c] * v(w - ds) + st[n + c] * v(c - ds) + st[2 * n + c] * v(e - ds) +
+                     st[3 * n + c] * v(w) + st[5 * n + c] * v(e) + st[6 * n + c] * v(w + us) +
+                     st[7 * n + c] * v(c + us) + st[8 * n + c] * v(e + us);
+  return a.f[c] - off - st[4 * n + c] * v(c);
+}
+
 // Level-0 reductions.  Block blk of nblk takes rows blk, blk + nblk, ...
 // (threads along the row), so every partial sum has a fixed order.
 
@@ -789,7 +908,15 @@ __device__ __forceinline__ double resid0(const RedArgs &a, const double *x, int 
 template <bool ZF>
 __device__ __forceinline__ void resnorm_body(const RedArgs &a, const double *x, int blk) {
   double s = 0.0;
-  for (int j = 1 + blk; j < a.ny - 1; j += a.nblk)
+  if (a.st0) {  // Neumann edges: every free node, ring included
+    for (int j = blk; j < a.ny; j += a.nblk)
+      for (int i = threadIdx.x; i < a.nx; i += blockDim.x) {
+        if (a.dir[(size_t)j * a.nx + i]) continue;
+        const double r = resid_st<ZF>(a, x, i, j);
+        s += r * r;
+      }
+  }
+  for (int j = 1 + blk; !a.st0 && j < a.ny - 1; j += a.nblk)
     for (int i = 1 + threadIdx.x; i < a.nx - 1; i += blockDim.x) {
       if (a.dir[(size_t)j * a.nx + i]) continue;
       const double r = resid0<ZF>(a, x, i, j);
@@ -833,7 +960,17 @@ __device__ __forceinline__ void ir_residual_body(const RedArgs &a, const double 
 // iterate, partials[nblk + blk] = sum of r^2 of the zero-interior start.
 __device__ __forceinline__ void begin_body(const RedArgs &a, const double *x, int blk) {
   double s = 0.0, s0 = 0.0;
-  for (int j = 1 + blk; j < a.ny - 1; j += a.nblk)
+  if (a.st0) {  // Neumann edges: every free node, ring included
+    for (int j = blk; j < a.ny; j += a.nblk)
+      for (int i = threadIdx.x; i < a.nx; i += blockDim.x) {
+        if (a.dir[(size_t)j * a.nx + i]) continue;
+        const double r = resid_st<false>(a, x, i, j);
+        const double r0 = resid_st<true>(a, x, i, j);
+        s += r * r;
+        s0 += r0 * r0;
+      }
+  }
+  for (int j = 1 + blk; !a.st0 && j < a.ny - 1; j += a.nblk)
     for (int i = 1 + threadIdx.x; i < a.nx - 1; i += blockDim.x) {
       if (a.dir[(size_t)j * a.nx + i]) continue;
       const double r = resid0<false>(a, x, i, j);
@@ -1005,7 +1142,7 @@ void smooth_level(tomg_problem *p, const Op &op, T *x, const T *b, const uint8_t
   for (int s = 0; s < sweeps; ++s)
     for (int col = 0; col < 4; ++col) {
       const int pi = col & 1, pj = col >> 1;
-      const int i0 = pi ? 1 : 2, j0 = pj ? 1 : 2;
+      const int i0 = pi, j0 = pj;
       hipLaunchKernelGGL((k_gs_colour<Op, T>), grid2(cxn, cyn, blk), blk, 0, p->stream, op, x, b,
                          dir, nx, ny, i0, j0);
     }
@@ -1013,10 +1150,10 @@ void smooth_level(tomg_problem *p, const Op &op, T *x, const T *b, const uint8_t
 
 template <class Op, typename T>
 void restrict_level(tomg_problem *p, const Op &op, const T *x, const T *b, const uint8_t *dir,
-                    int nxf, T *bc, int nxc, int nyc) {
+                    int nxf, T *bc, int nxc, int nyc, const uint8_t *dirc = nullptr) {
   const dim3 blk(64, 4);
   hipLaunchKernelGGL((k_restrict<Op, T>), grid2(nxc, nyc, blk), blk, 0, p->stream, op, x, b, dir,
-                     nxf, bc, nxc, nyc);
+                     nxf, bc, nxc, nyc, dirc);
 }
 
 // One V(nu1, nu2) cycle in precision T.  x0/b0: level-0 iterate and rhs;
@@ -1035,6 +1172,44 @@ int tail_level(const tomg_problem *p) {
 }
 namespace {
 
+// One V(nu1, nu2) cycle of a problem with Neumann edges: every level uses
+// its stored stencil (level 0 included, with the ghost layer folded in) and
+// its ring may hold free nodes, so the smoother covers the ring, the
+// restriction fills free coarse ring nodes and the operator reads no node
+// outside the grid.  One launch per colour, residual-restriction and
+// prolongation.
+template <typename T>
+hipError_t run_vcycle_neumann(tomg_problem *p, T *x0, const T *b0, const LevelView<T> *views,
+                              bool zero0) {
+  const int L = p->L;
+  const dim3 blk(64, 4);
+  for (int l = 0; l < L - 1; ++l) {
+    const tomg::Level &lv = p->lv[l], &lc = p->lv[l + 1];
+    T *x = l == 0 ? x0 : views[l].x;
+    const T *b = l == 0 ? b0 : views[l].b;
+    if (l > 0 || zero0) hipLaunchKernelGGL((k_zero<T>), grid1(lv.n), 256, 0, p->stream, x, lv.n);
+    const StOpB<T> op = st_op_b<T>(views[l].st, lv.nx, lv.ny);
+    smooth_level(p, op, x, b, lv.dir, lv.nx, lv.ny, p->cfg.nu1);
+    restrict_level(p, op, x, b, lv.dir, lv.nx, views[l + 1].b, lc.nx, lc.ny,
+                   (const uint8_t *)lc.dir);
+  }
+  {
+    const tomg::Level &lc = p->lv[L - 1];
+    hipLaunchKernelGGL((k_coarse_solve<T>), 1, 64, 0, p->stream, p->cinv, p->cidx,
+                       (const T *)views[L - 1].b, views[L - 1].x, (int)lc.n);
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const tomg::Level &lv = p->lv[l], &lc = p->lv[l + 1];
+    T *x = l == 0 ? x0 : views[l].x;
+    const T *b = l == 0 ? b0 : views[l].b;
+    hipLaunchKernelGGL((k_prolong<T>), grid2(lv.nx, lv.ny, blk), blk, 0, p->stream,
+                       (const T *)views[l + 1].x, lc.nx, x, lv.dir, lv.nx, lv.ny);
+    smooth_level(p, st_op_b<T>(views[l].st, lv.nx, lv.ny), x, b, lv.dir, lv.nx, lv.ny,
+                 p->cfg.nu2);
+  }
+  return hipGetLastError();
+}
+
 // One V(nu1, nu2) cycle in precision T.  x0/b0: level-0 iterate and rhs;
 // op0: level-0 operator; coarse data from views[l].{x,b,st}.  zero0: the
 // level-0 iterate starts at zero (not read).  With the four-colour smoother,
@@ -1048,6 +1223,7 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
   const int L = p->L;
   const dim3 blk(64, 4);
   if (nblocks) *nblocks = 0;
+  if (p->cfg.neumann) return run_vcycle_neumann(p, x0, b0, views, zero0);
   if (p->cfg.smoother == TOMG_GS4) {
     const int lc = tail_level(p);
     for (int l = 0; l < lc; ++l) {
@@ -1131,11 +1307,14 @@ hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, con
   hipLaunchKernelGGL(k_setup, kRedBlocks, kRedThreads, 0, p->stream, nx, ny, p->cfg.dx,
                      p->cfg.dy, xp, yp, jac, epsp, rho, mask, p->exx, p->exy, p->eyy, p->det,
                      p->f, p->lv[0].dir, f32 ? p->exx32 : nullptr, f32 ? p->exy32 : nullptr,
-                     f32 ? p->eyy32 : nullptr, p->partials);
+                     f32 ? p->eyy32 : nullptr, p->partials, p->cfg.neumann);
   hipLaunchKernelGGL((k_finalize<1>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 2,
                      p->scal + kSlotMinDet, 0, p->scal, 0, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
                      2, p->scal + kSlotBad, 0, p->scal, 0, nullptr);
+  if (p->cfg.neumann)
+    hipLaunchKernelGGL(k_fold_stencil, kRedBlocks, kRedThreads, 0, p->stream, op64(p), ny,
+                       (const uint8_t *)p->lv[0].dir, p->lv[0].st);
   return hipGetLastError();
 }
 
@@ -1174,7 +1353,7 @@ hipError_t launch_hierarchy(tomg_problem *p) {
     const tomg::Level &lf = p->lv[l - 1], &lc = p->lv[l];
     const dim3 grid((lc.nx + kGX - 1) / kGX, (lc.ny + kGY - 1) / kGY);
     float *st32 = f32 ? lc.st32 : nullptr;
-    if (l == 1)
+    if (l == 1 && !p->cfg.neumann)
       hipLaunchKernelGGL(k_coarsen_eps, grid, kGX * kGY, 0, p->stream, op64(p), lf.dir, lf.nx,
                          lf.ny, lc.nx, lc.ny, lc.dir, lc.st, st32);
     else
@@ -1234,6 +1413,7 @@ void build_red_args(tomg_problem *p) {
   r.r32 = p->r32;
   r.e32 = p->e32;
   r.tmp = p->tmp;
+  r.st0 = p->cfg.neumann ? p->lv[0].st : nullptr;
   r.nblk = red_blocks(p->lv[0].n);
   p->hargs.fin_red = {p->partials, p->scal, r.nblk};
   p->hargs.fin_red0 = {p->partials + r.nblk, p->scal, r.nblk};
@@ -1369,7 +1549,12 @@ void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kin
 }
 
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps) {
-  smooth_level(p, op64(p), phi, (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny, sweeps);
+  if (p->cfg.neumann)
+    smooth_level(p, st_op_b<double>(p->lv[0].st, p->cfg.nx, p->cfg.ny), phi,
+                 (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny, sweeps);
+  else
+    smooth_level(p, op64(p), phi, (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny,
+                 sweeps);
   return hipGetLastError();
 }
 
@@ -1407,6 +1592,12 @@ void prof_harvest(tomg_problem *p) {
 
 hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r) {
   const dim3 blk(64, 4);
+  if (p->cfg.neumann) {
+    hipLaunchKernelGGL((k_residual<StOpB<double>, double>), grid2(p->cfg.nx, p->cfg.ny, blk), blk,
+                       0, p->stream, st_op_b<double>(p->lv[0].st, p->cfg.nx, p->cfg.ny), phi,
+                       (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny, r);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_residual<EpsOp<double>, double>), grid2(p->cfg.nx, p->cfg.ny, blk), blk,
                      0, p->stream, op64(p), phi, (const double *)p->f, p->lv[0].dir, p->cfg.nx,
                      p->cfg.ny, r);

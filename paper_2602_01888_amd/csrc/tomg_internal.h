@@ -98,6 +98,7 @@ struct RedArgs {
   double *partials;
   float *r32, *e32;
   double *tmp;
+  const double *st0;  // level-0 stencil (Neumann edges only, else null)
   int nblk;  // blocks of the reduction (a function of the grid size only)
 };
 
@@ -150,7 +151,7 @@ struct Layout {
   size_t total = 0;
 };
 
-int level_shapes(int nx, int ny, int *nxs, int *nys);
+int level_shapes(int nx, int ny, int *nxs, int *nys, int neumann);
 bool make_layout(const tomg_config &cfg, Layout *lay);
 
 }  // namespace tomg

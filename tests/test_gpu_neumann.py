@@ -1,0 +1,148 @@
+"""Neumann edges on the GPU (zero normal derivative, Section 4.1) against the
+oracle, through the C-ABI.
+
+The HIP side writes the folded level-0 stencil once at setup and runs the
+unfused cycle (one launch per colour, residual-restriction, prolongation)
+with operators that cover the ring.  Parity: flags and the folded level-0
+stencil to a few roundings (1e-14 of the coefficient scale); the Galerkin
+hierarchy, two smoothing sweeps, the residual and V-cycles to 1e-12 (the
+bounds of the all-Dirichlet parity tests); the solve reaches the oracle's
+solution to 1e-10 with the same cycle count; the paper's semi-annulus
+converges at second order to ln(R/r)/ln(R/a)."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tomg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_01888_amd as t
+    return t
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def _circle(n, neu, seed=2):
+    q = w.perturbed_circle(n, seed=seed)
+    q.neumann = neu
+    return q
+
+
+S, N, W, E = 4, 8, 1, 2
+CASES = {
+    "annulus65": lambda: w.polar_semi_annulus(65, neumann=True),
+    "annulus129x65": lambda: w.polar_semi_annulus(129, ny=65, neumann=True),
+    "circle65_SE": lambda: _circle(65, S | E),
+    "circle129_WES": lambda: _circle(129, W | E | S, seed=5),
+    "circle33_all": lambda: _circle(33, W | E | S | N, seed=1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_setup_and_hierarchy_parity(tomg, name):
+    q = CASES[name]()
+    print(f"[neumann_setup] {name} {q.nx}x{q.ny} edges {q.neumann}", flush=True)
+    p, d = tomg.setup_from_grid(q)
+    s = oracle.setup(q)
+    mg = oracle.MG.from_setup(s, q.dx, q.dy, mask=q.mask)
+    assert np.array_equal(np_(p.export("dir")), s["dir"])
+    st0 = mg.stencil(0)
+    g0 = np_(p.export("stencil", 0))
+    assert np.max(np.abs(g0 - st0)) <= 1e-14 * np.max(np.abs(st0))
+    assert mg.num_levels == p.num_levels
+    assert p.level_shape(p.num_levels - 1)[0] <= 5
+    for l in range(1, mg.num_levels):
+        assert p.level_shape(l) == mg.shape(l)
+        assert np.array_equal(np_(p.export("dir", l)), mg.dirs(l)), l
+        assert rel_err(np_(p.export("stencil", l)), mg.stencil(l)) <= 1e-12, l
+
+
+@pytest.mark.parametrize("name", ["annulus65", "circle65_SE", "circle129_WES"])
+@pytest.mark.parametrize("smoother", ["gs4", "jacobi"])
+def test_smoother_residual_and_vcycle_parity(tomg, name, smoother):
+    import torch
+    q = CASES[name]()
+    print(f"[neumann_cycle] {name} {smoother}", flush=True)
+    p, d = tomg.setup_from_grid(q, smoother=smoother)
+    s = oracle.setup(q)
+    kind = oracle.GS4 if smoother == "gs4" else oracle.JACOBI
+    mg = oracle.MG.from_setup(s, q.dx, q.dy, mask=q.mask, smoother=kind)
+    st0, dir0 = mg.stencil(0), mg.dirs(0)
+    rng = np.random.default_rng(1)
+    x0 = q.phi0 + np.where(dir0 == 0, rng.normal(size=q.phi0.shape), 0.0)
+    xg = torch.tensor(x0, device="cuda")
+    p.smooth(xg, 2)
+    xo = oracle.smooth(st0, dir0, x0, s["f"], kind=kind, sweeps=2, omega=0.8)
+    assert rel_err(np_(xg), xo) <= 1e-12
+    r = np_(p.residual(xg))
+    ro = oracle.residual(st0, dir0, xo, s["f"])
+    assert np.max(np.abs(r - ro)) <= 1e-12 * np.max(np.abs(s["f"])) + 1e-12 * np.max(
+        np.abs(st0[4])) * np.max(np.abs(xo))
+    # V-cycles from the Dirichlet start
+    xg = d["phi0"].clone()
+    p.vcycle(xg)
+    xo = mg.vcycle(q.phi0, s["f"])
+    assert rel_err(np_(xg), xo) <= 1e-12
+    for l in range(1, mg.num_levels):
+        assert rel_err(np_(p.export("x", l)), mg.level_x(l)) <= 1e-11, l
+    p.vcycle(xg)
+    xo = mg.vcycle(xo, s["f"])
+    assert rel_err(np_(xg), xo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_matches_oracle(tomg, name):
+    import torch
+    q = CASES[name]()
+    print(f"[neumann_solve] {name}", flush=True)
+    p, d = tomg.setup_from_grid(q)
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=400)
+    ro = oracle.solve_problem(q, rel_tol=1e-10, max_cycles=400)
+    print(f"  cycles gpu {res.cycles} oracle {ro['cycles']} rel {res.rel:.3e}", flush=True)
+    assert res.ok and ro["status"] == 0
+    assert res.cycles == ro["cycles"]
+    assert res.rel == pytest.approx(ro["rel"], rel=1e-6)
+    assert rel_err(np_(phi), ro["phi"]) <= 1e-10
+    # residual_norm agrees with the oracle's norm over every free node
+    s = ro["setup"]
+    mg = ro["mg"]
+    a, _ = p.residual_norm(phi)
+    ao = oracle.norm2_free(s["dir"], oracle.residual(mg.stencil(0), s["dir"], np_(phi), s["f"]))
+    assert a == pytest.approx(ao, rel=1e-9, abs=1e-14 * mg.initial_residual(q.phi0, s["f"]))
+    dmask = s["dir"].astype(bool)
+    assert np.array_equal(np_(phi)[dmask], q.phi0[dmask])
+
+
+def test_semi_annulus_second_order(tomg):
+    errs = []
+    for n in (65, 129, 257):
+        q = w.polar_semi_annulus(n, neumann=True)
+        p, d = tomg.setup_from_grid(q)
+        phi = d["phi0"].clone()
+        assert p.solve(phi, rel_tol=1e-12, max_cycles=400).ok
+        errs.append(np.max(np.abs(np_(phi) - q.phi_exact)))
+    print(f"[neumann_order] errors {errs}", flush=True)
+    assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2, errs
+
+
+def test_neumann_problem_is_not_batched(tomg):
+    q = CASES["circle65_SE"]()
+    p, d = tomg.setup_from_grid(q)
+    with pytest.raises(tomg.TomgError) as e:
+        tomg.batch_step([p], [d["phi0"].clone()], [True])
+    assert e.value.status == tomg.TOMG_EINVAL
