@@ -146,3 +146,28 @@ def test_neumann_problem_is_not_batched(tomg):
     with pytest.raises(tomg.TomgError) as e:
         tomg.batch_step([p], [d["phi0"].clone()], [True])
     assert e.value.status == tomg.TOMG_EINVAL
+
+
+def test_fullsize_semi_annulus(tomg):
+    """4097 x 4097 with the Neumann sides, in the configuration the benchmark
+    times: the oracle's own residual of the GPU solution meets the stopping
+    tolerance, and the error against the closed form is the discretisation
+    error (second order from the sizes above: about 2.9e-7 / 256)."""
+    n = 4097
+    q = w.polar_semi_annulus(n, neumann=True)
+    print(f"[neumann_fullsize] {n}", flush=True)
+    p, d = tomg.setup_from_grid(q)
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=600)
+    print(f"  cycles {res.cycles} rel {res.rel:.3e}", flush=True)
+    assert res.ok
+    x = np_(phi)
+    s = oracle.setup(q)
+    st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], q.dx, q.dy, s["dir"])
+    b0 = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], q.phi0, s["f"]))
+    rel = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], x, s["f"])) / b0
+    assert rel <= 1e-10 * (1 + 1e-3), rel
+    res = p.solve(phi, rel_tol=1e-12, max_cycles=600)
+    err = np.max(np.abs(np_(phi) - q.phi_exact))
+    print(f"  error vs closed form {err:.3e}", flush=True)
+    assert err <= 2.5e-9
