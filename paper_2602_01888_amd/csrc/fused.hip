@@ -144,7 +144,8 @@ constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 // odd rows (colours 2 then 3).  Four barriers per sweep and step, whatever
 // P.  The level-0 pass loads the next step's rows while it works on the
 // current ones; coarse levels issue a step's loads together at its start.
-template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM,
+          bool MIR>
 __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, const int by) {
   constexpr bool PF = EPS;  // level 0: the next step's rows are loaded during this step
   constexpr int H = 4 * NU + 2;
@@ -166,8 +167,13 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   const bool updc = gi >= 1 && gi <= nx - 2;
   const bool outc = t >= H && t < H + a.W && gi < nx;
   const int odd = gi & 1;
-  const int y0 = by * a.CH;
-  const int y1 = min(ny, y0 + a.CH);
+  // MIR: the block marches down its band.  It works in flipped row
+  // coordinates (row r is grid row ny-1-r; ny is odd, so every row keeps its
+  // parity and colour) and evaluates every sum in the order of the upward
+  // march, so each node's arithmetic is the same either way.
+  const int ya = by * a.CH, yb = min(ny, ya + a.CH);
+  const int y0 = MIR ? ny - yb : ya;
+  const int y1 = MIR ? ny - ya : yb;
   const int ys = max(0, y0 - HV) & ~1;
   const int ye = min(ny - 1, y1 - 1 + HV);
   const int m0 = (ys >> 1) + P - 1;  // newest pair of the first step
@@ -184,10 +190,14 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
 
   auto slot = [&](int rel) { return ((rel % NS) + NS) % NS; };
   auto lrow = [&](int r) -> T * { return L[((r % NR) + NR) % NR]; };
+  auto grow = [&](int r) { return MIR ? ny - 1 - r : r; };  // grid row of row r
+  // the rows below and above row r on the grid
+  auto below_row = [&](int r) -> T * { return lrow(MIR ? r + 1 : r - 1); };
+  auto above_row = [&](int r) -> T * { return lrow(MIR ? r - 1 : r + 1); };
 
   // all loads of a row are issued unconditionally from clamped addresses
   auto load_row = [&](int r, Raw<T, EPS> &w) {
-    const int rc = min(max(r, 0), ny - 1);
+    const int rc = grow(min(max(r, 0), ny - 1));
     const size_t c = (size_t)rc * nx + gc;
     w.x = ZERO ? T(0) : ld_in(a.xin + c);
     w.f = ld_in(a.b + c);
@@ -312,8 +322,11 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
             Rec<T, true> &R = rec[slot(rel0 + 1 - 2 * P + v)];
             R.ax = rxx[v + 1] * a.cx;
             R.ay = ryy[v + 1] * a.cy;
-            R.gx = (xch[2 * v][t + 2] - xch[2 * v][t]) * a.qx + (rxy[v + 2] - rxy[v]) * a.qxy;
-            R.gy = (ryy[v + 2] - ryy[v]) * a.qy + (xch[2 * v + 1][t + 2] - xch[2 * v + 1][t]) * a.qxy;
+            // raw row v + 2 is the grid row above v + 1 (below it when MIR)
+            const T dxy = MIR ? rxy[v] - rxy[v + 2] : rxy[v + 2] - rxy[v];
+            const T dyy = MIR ? ryy[v] - ryy[v + 2] : ryy[v + 2] - ryy[v];
+            R.gx = (xch[2 * v][t + 2] - xch[2 * v][t]) * a.qx + dxy * a.qxy;
+            R.gy = dyy * a.qy + (xch[2 * v + 1][t + 2] - xch[2 * v + 1][t]) * a.qxy;
             R.k6 = rxy[v + 1] * a.hxy;
             R.f = rff[v + 1];
             R.ik = rdd[v + 1] ? T(0) : T(-1) / (T(2) * (R.ax + R.ay));
@@ -345,7 +358,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
                 if (rowok && updc && odd == cp && R.ik != T(0)) {
                   T *mid = lrow(r);
                   T off, dg;
-                  apply<T, EPS>(R, lrow(r - 1), mid, lrow(r + 1), t, off, dg);
+                  apply<T, EPS>(R, below_row(r), mid, above_row(r), t, off, dg);
                   mid[t + 1] = (R.f - off) * R.ik;
                 }
               }
@@ -365,12 +378,12 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
             const bool rowok = r >= 1 && r <= ny - 2 && r > ys && r < ye;
             if (rowok && updc && R.ik != T(0)) {
               T off, dg;
-              apply<T, EPS>(R, lrow(r - 1), mid, lrow(r + 1), t, off, dg);
+              apply<T, EPS>(R, below_row(r), mid, above_row(r), t, off, dg);
               res[q] = R.f - off - dg * mid[t + 1];
             }
           }
           if (r >= y0 && r < y1 && outc) {
-            st_out(a.xout + (size_t)r * nx + gi, mid[t + 1]);
+            st_out(a.xout + (size_t)grow(r) * nx + gi, mid[t + 1]);
             if constexpr (NORM) acc += res[q] * res[q];
           }
         }
@@ -380,19 +393,20 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
 #pragma unroll
           for (int q = 0; q < 2 * P; ++q) below[q + 1] = res[q];
 #pragma unroll
-          for (int p = 0; p < P; ++p)
-            xch[p][t + 1] = below[2 * p] + T(2) * res[2 * p] + res[2 * p + 1];
+          for (int p = 0; p < P; ++p)  // grid rows 2J-1, 2J, 2J+1 in that order
+            xch[p][t + 1] = MIR ? res[2 * p + 1] + T(2) * res[2 * p] + below[2 * p]
+                                : below[2 * p] + T(2) * res[2 * p] + res[2 * p + 1];
           rprev = res[2 * P - 1];
           __syncthreads();
 #pragma unroll
           for (int p = 0; p < P; ++p) {
             const int J = (R0 >> 1) + p;
             if (2 * J >= y0 && 2 * J < y1 && J < a.nyc && outc && !odd) {
-              const int I = gi >> 1;
-              const bool ring = I == 0 || J == 0 || I == a.nxc - 1 || J == a.nyc - 1;
+              const int I = gi >> 1, Jg = MIR ? a.nyc - 1 - J : J;
+              const bool ring = I == 0 || Jg == 0 || I == a.nxc - 1 || Jg == a.nyc - 1;
               const T v = ring ? T(0)
                                : (xch[p][t] + T(2) * xch[p][t + 1] + xch[p][t + 2]) * T(0.0625);
-              st_out(a.bc + (size_t)J * a.nxc + I, v);
+              st_out(a.bc + (size_t)Jg * a.nxc + I, v);
             }
           }
         }
@@ -426,6 +440,19 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   }
 }
 
+// Odd bands march down (TOMG_MIRROR): then two neighbouring bands reach
+// their common boundary at the same time -- at the start of the pass for one
+// pair, at its end for the other -- and the halo rows both read are served
+// by the cache instead of being fetched from memory twice.  FP64 passes
+// only: the FP32 passes move half the bytes and gain nothing from it.
+#ifndef TOMG_MIRROR
+#define TOMG_MIRROR 1
+#endif
+template <typename T>
+__device__ __forceinline__ bool mirrored(int by, int ny) {
+  return TOMG_MIRROR && std::is_same<T, double>::value && (by & 1) && (ny & 1);
+}
+
 // Tile of a block of a one-dimensional launch.  Workgroups go to the eight
 // XCDs in turn (XCD = linear id mod 8); each XCD is given one contiguous run
 // of tiles in strip-fastest order, so the neighbouring strips of a band --
@@ -444,7 +471,10 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
   if (a.skip && *a.skip != 0.0) return;
   int bx = blockIdx.x, by = blockIdx.y;
   if (a.xcd_order) xcd_tile(blockIdx.x, a.nbx, a.nby, bx, by);
-  pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, bx, by);
+  if (mirrored<T>(by, a.ny))
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true>(a, bx, by);
+  else
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false>(a, bx, by);
 }
 
 // Entry of a batched launch holding block b (entries sorted by start).
@@ -464,8 +494,11 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
   PassArgs<T> a = *static_cast<const PassArgs<T> *>(e.args);
   if (e.role == 1) a.xin = static_cast<const T *>(e.phi);
   if (e.role == 2) a.xout = static_cast<T *>(e.phi);
-  const int local = blockIdx.x - e.start;
-  pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, local % e.nbx, local / e.nbx);
+  const int local = blockIdx.x - e.start, bx = local % e.nbx, by = local / e.nbx;
+  if (mirrored<T>(by, a.ny))
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true>(a, bx, by);
+  else
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false>(a, bx, by);
 }
 
 }  // namespace
