@@ -844,6 +844,30 @@ __global__ void k_restrict(Op op, const T *x, const T *b, const uint8_t *dir, in
   bc[(size_t)J * nxc + I] = s;
 }
 
+// Full weighting (eq. 23) of a residual field already formed (zero at
+// Dirichlet nodes) into the coarse right-hand side; a free coarse ring node
+// (Neumann edge) sums the fine nodes of its support inside the grid, other
+// ring nodes get zero.
+template <typename T>
+__global__ void k_full_weighting(const T *r, int nxf, int nyf, T *bc, int nxc, int nyc,
+                                 const uint8_t *dirc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  if (I >= nxc || J >= nyc) return;
+  T s = T(0);
+  const bool ring = I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1;
+  if (!ring || !dirc[(size_t)J * nxc + I]) {
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const int fi = 2 * I + di, fj = 2 * J + dj;
+        if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
+        const T w = T((2 - abs(di)) * (2 - abs(dj))) * T(0.0625);
+        s += w * r[(size_t)fj * nxf + fi];
+      }
+  }
+  bc[(size_t)J * nxc + I] = s;
+}
+
 // Bilinear prolongation and correction (eq. 24) at free fine nodes.
 template <typename T>
 __global__ void k_prolong(const T *ec, int nxc, T *x, const uint8_t *dir, int nxf, int nyf) {
@@ -1190,8 +1214,13 @@ hipError_t run_vcycle_neumann(tomg_problem *p, T *x0, const T *b0, const LevelVi
     if (l > 0 || zero0) hipLaunchKernelGGL((k_zero<T>), grid1(lv.n), 256, 0, p->stream, x, lv.n);
     const StOpB<T> op = st_op_b<T>(views[l].st, lv.nx, lv.ny);
     smooth_level(p, op, x, b, lv.dir, lv.nx, lv.ny, p->cfg.nu1);
-    restrict_level(p, op, x, b, lv.dir, lv.nx, views[l + 1].b, lc.nx, lc.ny,
-                   (const uint8_t *)lc.dir);
+    // residual once per fine node, then its full weighting
+    T *r = reinterpret_cast<T *>(p->tmp);
+    hipLaunchKernelGGL((k_residual<StOpB<T>, T>), grid2(lv.nx, lv.ny, blk), blk, 0, p->stream, op,
+                       (const T *)x, b, lv.dir, lv.nx, lv.ny, r);
+    hipLaunchKernelGGL((k_full_weighting<T>), grid2(lc.nx, lc.ny, blk), blk, 0, p->stream,
+                       (const T *)r, lv.nx, lv.ny, views[l + 1].b, lc.nx, lc.ny,
+                       (const uint8_t *)lc.dir);
   }
   {
     const tomg::Level &lc = p->lv[L - 1];
