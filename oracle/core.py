@@ -13,7 +13,7 @@ import numpy as np
 
 from . import build as _build
 
-GS4, GS_LEX, JACOBI = 0, 1, 2
+GS4, GS_LEX, JACOBI, ZEBRA_X = 0, 1, 2, 3
 # edges with a homogeneous Neumann condition (bit mask)
 NEU_W, NEU_E, NEU_S, NEU_N = 1, 2, 4, 8
 
@@ -275,7 +275,8 @@ def error_norms(a, b):
 class MG:
     """Oracle multigrid hierarchy (Galerkin coarse operators, V(nu1, nu2),
     direct coarsest solve).  smoother: GS4 (the GPU's ordering, "mirror
-    mode"), GS_LEX (the paper's lexicographic ordering) or JACOBI."""
+    mode"), GS_LEX (the paper's lexicographic ordering), JACOBI or ZEBRA_X
+    (x-line Gauss-Seidel, even rows then odd rows)."""
 
     def __init__(self, exx, exy, eyy, dx, dy, mask=None, nu1=2, nu2=2, smoother=GS4,
                  omega=0.8, neumann=0):

@@ -326,11 +326,67 @@ static void sweep_jacobi(int nx, int ny, const double *st, const uint8_t *dir, d
   free(r);
 }
 
+/* Zebra line Gauss-Seidel along x (an extension for anisotropic grids,
+ * where the coupling along i dominates): the even rows j are relaxed first,
+ * each solved exactly for its own nodes with the rows above and below held,
+ * then the odd rows.  A row is a tridiagonal system over all its nodes: a
+ * free node keeps its W, C, E coefficients and moves the six off-row terms
+ * to the right-hand side; a Dirichlet node is the identity row holding its
+ * value.  Solved by Thomas elimination (the rows are diagonally dominant). */
+static void sweep_zebra_x(int nx, int ny, const double *st, const uint8_t *dir, double *x,
+                          const double *b) {
+  size_t n = (size_t)nx * ny;
+  for (int parity = 0; parity < 2; ++parity) {
+#pragma omp parallel
+    {
+      double *a = (double *)malloc(4 * (size_t)nx * sizeof(double));
+      double *c = a + nx, *e = c + nx, *d = e + nx;
+#pragma omp for schedule(static)
+      for (int j = parity; j < ny; j += 2) {
+        for (int i = 0; i < nx; ++i) {
+          size_t q = ID(i, j, nx);
+          if (dir[q]) {
+            a[i] = 0.0;
+            c[i] = 1.0;
+            e[i] = 0.0;
+            d[i] = x[q];
+            continue;
+          }
+          a[i] = i > 0 ? PLANE(st, 3, n)[q] : 0.0;
+          c[i] = PLANE(st, 4, n)[q];
+          e[i] = i < nx - 1 ? PLANE(st, 5, n)[q] : 0.0;
+          double s = b[q];
+          for (int dj = -1; dj <= 1; dj += 2) {
+            if (j + dj < 0 || j + dj >= ny) continue;
+            for (int di = -1; di <= 1; ++di) {
+              if (i + di < 0 || i + di >= nx) continue;
+              s -= PLANE(st, (dj + 1) * 3 + (di + 1), n)[q] * x[ID(i + di, j + dj, nx)];
+            }
+          }
+          d[i] = s;
+        }
+        /* Thomas: forward elimination, back substitution */
+        for (int i = 1; i < nx; ++i) {
+          double m = a[i] / c[i - 1];
+          c[i] -= m * e[i - 1];
+          d[i] -= m * d[i - 1];
+        }
+        x[ID(nx - 1, j, nx)] = d[nx - 1] / c[nx - 1];
+        for (int i = nx - 2; i >= 0; --i)
+          x[ID(i, j, nx)] = (d[i] - e[i] * x[ID(i + 1, j, nx)]) / c[i];
+      }
+      free(a);
+    }
+  }
+}
+
 void orc_smooth(int nx, int ny, const double *st, const uint8_t *dir, double *x,
                 const double *b, int kind, int sweeps, double omega) {
   for (int s = 0; s < sweeps; ++s) {
     if (kind == ORC_GS_LEX)
       sweep_lex(nx, ny, st, dir, x, b);
+    else if (kind == ORC_ZEBRA_X)
+      sweep_zebra_x(nx, ny, st, dir, x, b);
     else if (kind == ORC_JACOBI)
       sweep_jacobi(nx, ny, st, dir, x, b, omega);
     else
