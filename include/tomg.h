@@ -59,7 +59,7 @@ typedef enum {
 } tomg_status;
 
 enum { TOMG_FP64 = 0, TOMG_FP32_IR = 1 };
-enum { TOMG_GS4 = 0, TOMG_JACOBI = 1 };
+enum { TOMG_GS4 = 0, TOMG_JACOBI = 1, TOMG_ZEBRA_X = 2 };
 
 typedef struct {
   int32_t nx, ny;          /* nodes including the outer ring; (nx-1) and (ny-1)
@@ -70,8 +70,13 @@ typedef struct {
   int32_t precision;       /* TOMG_FP64, or TOMG_FP32_IR: FP32 V-cycles as the
                               inner solver of FP64 iterative refinement */
   int32_t nu1, nu2;        /* pre/post smoothing sweeps, 1..4 each (default 2, 2) */
-  int32_t smoother;        /* TOMG_GS4 (four-colour Gauss-Seidel, default) or
-                              TOMG_JACOBI (damped Jacobi) */
+  int32_t smoother;        /* TOMG_GS4 (four-colour Gauss-Seidel, default),
+                              TOMG_JACOBI (damped Jacobi), or TOMG_ZEBRA_X
+                              (zebra x-line Gauss-Seidel: even rows, then odd
+                              rows, each solved exactly for its nodes with its
+                              neighbours held -- for grids whose coupling along
+                              i dominates; nx <= 4225).  The latter two run the
+                              unfused cycle and cannot be batched */
   double jacobi_omega;     /* damping of TOMG_JACOBI (default 0.8) */
   int32_t ir_inner_cycles; /* FP32 V-cycles per refinement step (default 2) */
   int32_t neumann;         /* edges with a homogeneous Neumann condition

@@ -40,7 +40,9 @@ static bool config_ok(const tomg_config &c) {
   if (!(c.dx > 0.0) || !(c.dy > 0.0) || !std::isfinite(c.dx) || !std::isfinite(c.dy)) return false;
   if (c.precision != TOMG_FP64 && c.precision != TOMG_FP32_IR) return false;
   if (c.nu1 < 1 || c.nu2 < 1 || c.nu1 > 4 || c.nu2 > 4) return false;
-  if (c.smoother != TOMG_GS4 && c.smoother != TOMG_JACOBI) return false;
+  if (c.smoother != TOMG_GS4 && c.smoother != TOMG_JACOBI && c.smoother != TOMG_ZEBRA_X)
+    return false;
+  if (c.smoother == TOMG_ZEBRA_X && c.nx > 4225) return false;  // the row in LDS
   if (c.smoother == TOMG_JACOBI && !(c.jacobi_omega > 0.0 && c.jacobi_omega <= 1.0)) return false;
   if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
   if (c.neumann < 0 || c.neumann > 15) return false;

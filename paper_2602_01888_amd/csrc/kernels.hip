@@ -786,6 +786,185 @@ __global__ void k_gs_colour(Op op, T *x, const T *b, const uint8_t *dir, int nx,
   x[c] = (b[c] - off) / dg;
 }
 
+// Zebra x-line Gauss-Seidel, one parity of rows: block blk solves row
+// j = parity + 2 blk exactly for its own nodes, the rows above and below
+// held.  The row is a tridiagonal system: a free node keeps its W, C, E
+// coefficients and moves b and the six off-row terms to the right; a
+// Dirichlet node is the identity row holding its value.  It is cut into
+// chunks of consecutive nodes, one per thread (2 to kZebraChunk nodes):
+// each thread eliminates its chunk's other nodes in terms of the last node
+// of the previous chunk and the last node of its own (Thomas elimination
+// with three right-hand sides, in registers); the last nodes then satisfy
+// one tridiagonal equation per chunk, solved by parallel cyclic reduction
+// in LDS (one equation per thread, log2 of the chunk count steps), and each
+// thread substitutes back (the partition method for tridiagonal systems).
+// The row's equations are first formed with coalesced loads (consecutive
+// threads, consecutive nodes) into LDS, padded by one element per 16 so
+// that the chunk-strided reads spread over the banks; the new row goes back
+// through LDS and is stored coalesced.  All reads of the row happen before
+// the first barrier and all writes after the last, so the row is updated in
+// place.
+constexpr int kZebraThreads = 256, kZebraChunk = 17;
+constexpr int kZebraMaxNx = 4225;  // four padded FP64 rows of LDS fit in 160 KB
+__host__ __device__ constexpr int zebra_pad(int i) { return i + (i >> 4); }
+inline size_t zebra_shmem(int nx, size_t elem) { return 4 * (size_t)(zebra_pad(nx) + 1) * elem; }
+
+template <class Op, typename T>
+__global__ __launch_bounds__(kZebraThreads) void k_zebra_x(Op op, T *x, const T *b,
+                                                           const uint8_t *dir, int nx, int ny,
+                                                           int parity) {
+  __shared__ T Fy[kZebraThreads], Fu[kZebraThreads], Fw[kZebraThreads];
+  __shared__ T ra[kZebraThreads], rb[kZebraThreads], rc[kZebraThreads], rd[kZebraThreads];
+  __shared__ T Ls[kZebraThreads + 1];  // Ls[t + 1]: last node of chunk t; Ls[0] = 0
+  extern __shared__ unsigned char zebra_raw[];
+  const int j = parity + 2 * (int)blockIdx.x;
+  if (j > ny - 1) return;
+  const int np = zebra_pad(nx) + 1;
+  T *A = reinterpret_cast<T *>(zebra_raw), *C = A + np, *E = C + np, *D = E + np;
+  const int t = threadIdx.x;
+  const int nch = min(kZebraThreads, nx / 2);
+  const int q = nx / nch, rem = nx % nch;
+  const bool act = t < nch;
+  const int m = act ? q + (t < rem ? 1 : 0) : 0;
+  const int s = t * q + min(t, rem);
+  const size_t row = (size_t)j * nx;
+  const size_t dn = j > 0 ? (size_t)nx : 0, up = j < ny - 1 ? (size_t)nx : 0;
+
+  // line equation of node i of the row: a x[i-1] + c x[i] + e x[i+1] = d
+  auto coef = [&](int i, T &a, T &c, T &e, T &d) {
+    const size_t ci = row + i;
+    if (dir[ci]) {
+      a = T(0);
+      c = T(1);
+      e = T(0);
+      d = x[ci];
+      return;
+    }
+    T s9[9];
+    op.full(ci, s9);
+    const size_t w = i > 0 ? ci - 1 : ci, ea = i < nx - 1 ? ci + 1 : ci;
+    a = i > 0 ? s9[3] : T(0);
+    c = s9[4];
+    e = i < nx - 1 ? s9[5] : T(0);
+    d = b[ci] - (s9[0] * x[w - dn] + s9[1] * x[ci - dn] + s9[2] * x[ea - dn]) -
+        (s9[6] * x[w + up] + s9[7] * x[ci + up] + s9[8] * x[ea + up]);
+  };
+
+  for (int i = t; i < nx; i += kZebraThreads) {
+    T a, c, e, d;
+    coef(i, a, c, e, d);
+    const int pi = zebra_pad(i);
+    A[pi] = a;
+    C[pi] = c;
+    E[pi] = e;
+    D[pi] = d;
+  }
+  __syncthreads();
+  auto lds_coef = [&](int i, T &a, T &c, T &e, T &d) {
+    const int pi = zebra_pad(i);
+    a = A[pi];
+    c = C[pi];
+    e = E[pi];
+    d = D[pi];
+  };
+
+  // chunk nodes k = 0 .. m-2 in terms of the outside unknowns:
+  // x_k = Y_k + U_k Ls[t] + W_k Ls[t + 1]
+  T cp[kZebraChunk], Y[kZebraChunk], U[kZebraChunk], W[kZebraChunk];
+#pragma unroll
+  for (int k = 0; k < kZebraChunk; ++k) cp[k] = Y[k] = U[k] = W[k] = T(0);
+  T ym = T(0), um = T(0), wm = T(0);
+  T aL = T(0), cL = T(1), eL = T(0), dL = T(0);
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < kZebraChunk - 1; ++k) {
+      if (k < m - 1) {
+        T a, c, e, d;
+        lds_coef(s + k, a, c, e, d);
+        const T ai = k == 0 ? T(0) : a;  // the first node's W neighbour is outside
+        const T den = c - (k == 0 ? T(0) : ai * cp[k - 1]);
+        const bool last = k == m - 2;    // its E neighbour is outside
+        cp[k] = (last ? T(0) : e) / den;
+        Y[k] = (d - (k == 0 ? T(0) : ai * Y[k - 1])) / den;
+        U[k] = ((k == 0 ? -a : T(0)) - (k == 0 ? T(0) : ai * U[k - 1])) / den;
+        W[k] = ((last ? -e : T(0)) - (k == 0 ? T(0) : ai * W[k - 1])) / den;
+        if (last) {
+          ym = Y[k];
+          um = U[k];
+          wm = W[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = kZebraChunk - 3; k >= 0; --k) {
+      if (k <= m - 3) {
+        Y[k] -= cp[k] * Y[k + 1];
+        U[k] -= cp[k] * U[k + 1];
+        W[k] -= cp[k] * W[k + 1];
+      }
+    }
+    lds_coef(s + m - 1, aL, cL, eL, dL);
+    Fy[t] = Y[0];
+    Fu[t] = U[0];
+    Fw[t] = W[0];
+  }
+  __syncthreads();
+  if (act) {
+    // equation of the chunk's last node with x[m-2] and the next chunk's
+    // first node substituted: ra Ls[t] + rb Ls[t+1] + rc Ls[t+2] = rd
+    const bool nxt = t + 1 < nch;
+    ra[t] = aL * um;
+    rb[t] = aL * wm + cL + (nxt ? eL * Fu[t + 1] : T(0));
+    rc[t] = nxt ? eL * Fw[t + 1] : T(0);
+    rd[t] = dL - aL * ym - (nxt ? eL * Fy[t + 1] : T(0));
+  }
+  __syncthreads();
+  // parallel cyclic reduction: each step eliminates the couplings to the
+  // equations sft away (outside the system: identity rows, zero right side)
+  T pa = act ? ra[t] : T(0), pb = act ? rb[t] : T(1), pc = act ? rc[t] : T(0);
+  T pd = act ? rd[t] : T(0);
+  for (int sft = 1; sft < nch; sft <<= 1) {
+    T am = T(0), bm = T(1), cm = T(0), dm = T(0), ap = T(0), bp = T(1), cq = T(0), dp = T(0);
+    if (act && t - sft >= 0) {
+      am = ra[t - sft];
+      bm = rb[t - sft];
+      cm = rc[t - sft];
+      dm = rd[t - sft];
+    }
+    if (act && t + sft < nch) {
+      ap = ra[t + sft];
+      bp = rb[t + sft];
+      cq = rc[t + sft];
+      dp = rd[t + sft];
+    }
+    const T k1 = pa / bm, k2 = pc / bp;
+    pb = pb - cm * k1 - ap * k2;
+    pd = pd - dm * k1 - dp * k2;
+    pa = -am * k1;
+    pc = -cq * k2;
+    __syncthreads();
+    if (act) {
+      ra[t] = pa;
+      rb[t] = pb;
+      rc[t] = pc;
+      rd[t] = pd;
+    }
+    __syncthreads();
+  }
+  if (act) Ls[t + 1] = pd / pb;
+  if (t == 0) Ls[0] = T(0);
+  __syncthreads();
+  if (act) {  // the new row into LDS (A is free since the forward sweep)
+    const T lp = Ls[t], lt = Ls[t + 1];
+#pragma unroll
+    for (int k = 0; k < kZebraChunk - 1; ++k)
+      if (k < m - 1) A[zebra_pad(s + k)] = Y[k] + U[k] * lp + W[k] * lt;
+    A[zebra_pad(s + m - 1)] = lt;
+  }
+  __syncthreads();
+  for (int i = t; i < nx; i += kZebraThreads) x[row + i] = A[zebra_pad(i)];
+}
+
 // r = b - A x at free nodes, 0 elsewhere (all nodes written).
 template <class Op, typename T>
 __global__ void k_residual(Op op, const T *x, const T *b, const uint8_t *dir, int nx, int ny,
@@ -1152,6 +1331,13 @@ template <class Op, typename T>
 void smooth_level(tomg_problem *p, const Op &op, T *x, const T *b, const uint8_t *dir, int nx,
                   int ny, int sweeps) {
   const dim3 blk(64, 4);
+  if (p->cfg.smoother == TOMG_ZEBRA_X) {
+    for (int s = 0; s < sweeps; ++s)
+      for (int parity = 0; parity < 2; ++parity)
+        hipLaunchKernelGGL((k_zebra_x<Op, T>), (ny - parity + 1) / 2, kZebraThreads,
+                           zebra_shmem(nx, sizeof(T)), p->stream, op, x, b, dir, nx, ny, parity);
+    return;
+  }
   if (p->cfg.smoother == TOMG_JACOBI) {
     T *r = reinterpret_cast<T *>(p->tmp);
     for (int s = 0; s < sweeps; ++s) {
