@@ -39,6 +39,7 @@ def _load():
         "orc_dirichlet_set": (None, [i, i, _U8, _U8]),
         "orc_dirichlet_set_bc": (None, [i, i, _U8, i, _U8]),
         "orc_fine_stencil": (None, [i, i, d, d, _D, _D, _D, _U8, _D]),
+        "orc_flux_stencil": (None, [i, i, d, d, _D, _D, _D, _U8, _D]),
         "orc_apply": (None, [i, i, _D, _U8, _D, _D]),
         "orc_residual": (None, [i, i, _D, _U8, _D, _D, _D]),
         "orc_norm2_free": (d, [i, i, _U8, _D]),
@@ -52,6 +53,7 @@ def _load():
         "orc_levels_lim": (i, [i, i, C.POINTER(i), C.POINTER(i), i, i]),
         "orc_mg_create": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, d]),
         "orc_mg_create_bc": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, i, d]),
+        "orc_mg_create_op": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, i, i, d]),
         "orc_mg_destroy": (None, [p]),
         "orc_mg_num_levels": (i, [p]),
         "orc_mg_level_shape": (None, [p, i, C.POINTER(i), C.POINTER(i)]),
@@ -156,6 +158,15 @@ def fine_stencil(exx, exy, eyy, dx, dy, dirs):
     ny, nx = exx.shape
     st = np.empty((9, ny, nx))
     _load().orc_fine_stencil(nx, ny, dx, dy, _d(exx), _d(exy), _d(eyy), _u8(dirs), _d(st))
+    return st
+
+
+def flux_stencil(exx, exy, eyy, dx, dy, dirs):
+    """The symmetric flux (energy) form of the operator as a 9-point stencil."""
+    exx, exy, eyy = _f64(exx), _f64(exy), _f64(eyy)
+    ny, nx = exx.shape
+    st = np.empty((9, ny, nx))
+    _load().orc_flux_stencil(nx, ny, dx, dy, _d(exx), _d(exy), _d(eyy), _u8(dirs), _d(st))
     return st
 
 
@@ -279,14 +290,15 @@ class MG:
     (x-line Gauss-Seidel, even rows then odd rows)."""
 
     def __init__(self, exx, exy, eyy, dx, dy, mask=None, nu1=2, nu2=2, smoother=GS4,
-                 omega=0.8, neumann=0):
+                 omega=0.8, neumann=0, flux=False):
         self._keep = [_f64(exx), _f64(exy), _f64(eyy)]
         ny, nx = self._keep[0].shape
         m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         self.nx, self.ny = nx, ny
-        self._h = _load().orc_mg_create_bc(nx, ny, dx, dy, _d(self._keep[0]),
+        self._h = _load().orc_mg_create_op(nx, ny, dx, dy, _d(self._keep[0]),
                                            _d(self._keep[1]), _d(self._keep[2]), _u8(m),
-                                           int(neumann), nu1, nu2, smoother, omega)
+                                           int(neumann), 1 if flux else 0, nu1, nu2, smoother,
+                                           omega)
         if not self._h:
             raise ValueError(f"grid {nx}x{ny} does not coarsen to <= 9x9 nodes")
 
@@ -376,12 +388,12 @@ def generate_grid(xb, yb, dx, dy, rel_tol=1e-13, max_cycles=200):
 
 
 def solve_problem(prob, rel_tol=1e-10, max_cycles=200, smoother=GS4, nu1=2, nu2=2,
-                  eps_phys=None, hist_len=0):
+                  eps_phys=None, hist_len=0, flux=False):
     """Setup plus multigrid solve of a ``workloads.GridProblem`` from its
     ``phi0``.  Returns a dict with phi, cycles, rel, status and the setup."""
     s = setup(prob, eps_phys)
     mg = MG.from_setup(s, prob.dx, prob.dy, mask=prob.mask, nu1=nu1, nu2=nu2,
-                       smoother=smoother)
+                       smoother=smoother, flux=flux)
     phi, status, cycles, rel, hist = mg.solve(prob.phi0, s["f"], rel_tol, max_cycles, hist_len)
     return {"phi": phi, "status": status, "cycles": cycles, "rel": rel, "hist": hist,
             "setup": s, "mg": mg}

@@ -235,6 +235,70 @@ void orc_fine_stencil(int nx, int ny, double dx, double dy, const double *exx,
     }
 }
 
+/* Symmetric flux (energy) form of div(eps grad phi), an alternative to the
+ * expanded eq. 18.  The operator is minus the gradient of the discrete
+ * energy
+ *   1/2 sum_xfaces exx_f (dphi)^2 / dx^2 + 1/2 sum_yfaces eyy_f (dphi)^2 / dy^2
+ *     + sum_cells exy_c gx_c gy_c,
+ * with face values the mean of the two nodes, cell values the mean of the
+ * four corners and gx_c, gy_c the cell-centred differences of phi; its
+ * matrix is therefore symmetric, and for constant eps it is eq. 18.  Free
+ * ring nodes (Neumann edges) use the mirror ghost layer of edge_stencil. */
+static void flux_stencil_at(int nx, int ny, double dx, double dy, const double *exx,
+                            const double *exy, const double *eyy, int i, int j, double a[9]) {
+  double g[9] = {0};
+  double ixx = 1.0 / (dx * dx), iyy = 1.0 / (dy * dy), ixy = 1.0 / (dx * dy);
+  double c0 = mirrored(exx, nx, ny, i, j, 0), d0 = mirrored(eyy, nx, ny, i, j, 0);
+  double aw = 0.5 * (c0 + mirrored(exx, nx, ny, i - 1, j, 0)) * ixx;
+  double ae = 0.5 * (c0 + mirrored(exx, nx, ny, i + 1, j, 0)) * ixx;
+  double as = 0.5 * (d0 + mirrored(eyy, nx, ny, i, j - 1, 0)) * iyy;
+  double an = 0.5 * (d0 + mirrored(eyy, nx, ny, i, j + 1, 0)) * iyy;
+  g[3] += aw;
+  g[5] += ae;
+  g[1] += as;
+  g[7] += an;
+  g[4] -= aw + ae + as + an;
+  /* the four cells with a corner at (i, j): x in [i+ci, i+ci+1], y in [j+cj, j+cj+1] */
+  for (int cj = -1; cj <= 0; ++cj)
+    for (int ci = -1; ci <= 0; ++ci) {
+      double bxy = 0.25 * (mirrored(exy, nx, ny, i + ci, j + cj, 1) +
+                           mirrored(exy, nx, ny, i + ci + 1, j + cj, 1) +
+                           mirrored(exy, nx, ny, i + ci, j + cj + 1, 1) +
+                           mirrored(exy, nx, ny, i + ci + 1, j + cj + 1, 1));
+      int pn = -ci, qn = -cj; /* corner of (i, j) in the cell */
+      for (int qm = 0; qm <= 1; ++qm)
+        for (int pm = 0; pm <= 1; ++pm) {
+          /* d^2 (gx gy) / d phi_n d phi_m, with d gx / d phi_(p,q) = (2p-1)/(2 dx) */
+          double h = ((2 * pn - 1) * (2 * qm - 1) + (2 * pm - 1) * (2 * qn - 1)) * 0.25 * ixy;
+          g[(cj + qm + 1) * 3 + (ci + pm + 1)] -= bxy * h;
+        }
+    }
+  for (int k = 0; k < 9; ++k) a[k] = 0.0;
+  for (int dj = -1; dj <= 1; ++dj)
+    for (int di = -1; di <= 1; ++di) {
+      int ti = reflect(i + di, nx) - i, tj = reflect(j + dj, ny) - j;
+      a[(tj + 1) * 3 + (ti + 1)] += g[(dj + 1) * 3 + (di + 1)];
+    }
+}
+
+void orc_flux_stencil(int nx, int ny, double dx, double dy, const double *exx,
+                      const double *exy, const double *eyy, const uint8_t *dir, double *st) {
+  size_t n = (size_t)nx * ny;
+  memset(st, 0, 9 * n * sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t c = ID(i, j, nx);
+      if (dir[c]) {
+        PLANE(st, 4, n)[c] = 1.0;
+        continue;
+      }
+      double a[9];
+      flux_stencil_at(nx, ny, dx, dy, exx, exy, eyy, i, j, a);
+      for (int k = 0; k < 9; ++k) PLANE(st, k, n)[c] = a[k];
+    }
+}
+
 /* Sum of the off-centre stencil terms at (i, j). */
 static double offcentre(int nx, size_t n, const double *st, const double *x, int i, int j) {
   double s = 0.0;
@@ -612,6 +676,13 @@ orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
 orc_mg *orc_mg_create_bc(int nx, int ny, double dx, double dy, const double *exx,
                          const double *exy, const double *eyy, const uint8_t *mask,
                          int neumann, int nu1, int nu2, int smoother, double omega) {
+  return orc_mg_create_op(nx, ny, dx, dy, exx, exy, eyy, mask, neumann, 0, nu1, nu2, smoother,
+                          omega);
+}
+
+orc_mg *orc_mg_create_op(int nx, int ny, double dx, double dy, const double *exx,
+                         const double *exy, const double *eyy, const uint8_t *mask,
+                         int neumann, int flux, int nu1, int nu2, int smoother, double omega) {
   orc_mg *mg = (orc_mg *)calloc(1, sizeof(orc_mg));
   mg->L = orc_levels_lim(nx, ny, mg->nx, mg->ny, ORC_MAXL, neumann ? 5 : 9);
   if (mg->L == 0) {
@@ -631,7 +702,10 @@ orc_mg *orc_mg_create_bc(int nx, int ny, double dx, double dy, const double *exx
     mg->r[l] = (double *)calloc(n, sizeof(double));
   }
   orc_dirichlet_set_bc(nx, ny, mask, neumann, mg->dir[0]);
-  orc_fine_stencil(nx, ny, dx, dy, exx, exy, eyy, mg->dir[0], mg->st[0]);
+  if (flux)
+    orc_flux_stencil(nx, ny, dx, dy, exx, exy, eyy, mg->dir[0], mg->st[0]);
+  else
+    orc_fine_stencil(nx, ny, dx, dy, exx, exy, eyy, mg->dir[0], mg->st[0]);
   for (int l = 1; l < mg->L; ++l)
     orc_galerkin(mg->nx[l - 1], mg->ny[l - 1], mg->st[l - 1], mg->dir[l - 1], mg->nx[l],
                  mg->ny[l], mg->st[l], mg->dir[l]);

@@ -67,6 +67,12 @@ void orc_fine_stencil(int nx, int ny, double dx, double dy, const double *exx,
                       const double *exy, const double *eyy, const uint8_t *dir,
                       double *st);
 
+/* Symmetric flux (energy) form of the same operator (face means of eps_xx,
+ * eps_yy; cell means of eps_xy with cell-centred differences); equal to
+ * eq. 18 for constant eps.  Neumann ring nodes as orc_fine_stencil. */
+void orc_flux_stencil(int nx, int ny, double dx, double dy, const double *exx,
+                      const double *exy, const double *eyy, const uint8_t *dir, double *st);
+
 void orc_apply(int nx, int ny, const double *st, const uint8_t *dir,
                const double *x, double *y);
 void orc_residual(int nx, int ny, const double *st, const uint8_t *dir,
@@ -100,6 +106,9 @@ orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
 orc_mg *orc_mg_create_bc(int nx, int ny, double dx, double dy, const double *exx,
                          const double *exy, const double *eyy, const uint8_t *mask,
                          int neumann, int nu1, int nu2, int smoother, double omega);
+orc_mg *orc_mg_create_op(int nx, int ny, double dx, double dy, const double *exx,
+                         const double *exy, const double *eyy, const uint8_t *mask,
+                         int neumann, int flux, int nu1, int nu2, int smoother, double omega);
 void orc_mg_destroy(orc_mg *mg);
 int orc_mg_num_levels(const orc_mg *mg);
 void orc_mg_level_shape(const orc_mg *mg, int l, int *nx, int *ny);
