@@ -91,7 +91,15 @@ typedef struct {
                               the mirror nodes.  Requires TOMG_FP64; such a
                               problem runs the unfused cycle (one launch per
                               colour, residual, transfer) and cannot be batched */
-  int32_t reserved[2];     /* set to zero */
+  int32_t flux;            /* operator form: 0 (default) the paper's expanded
+                              eq. 18; 1 the symmetric flux (energy) form --
+                              minus the gradient of a discrete energy with face
+                              means of eps_xx, eps_yy and cell means of eps_xy
+                              times cell-centred differences; symmetric, equal
+                              to eq. 18 for constant eps, second order.  Like
+                              Neumann edges it stores the level-0 stencil,
+                              runs the unfused FP64 cycle and is not batched */
+  int32_t reserved[1];     /* set to zero */
 } tomg_config;
 
 enum { TOMG_NEU_W = 1, TOMG_NEU_E = 2, TOMG_NEU_S = 4, TOMG_NEU_N = 8 };

@@ -29,7 +29,8 @@ class TomgError(RuntimeError):
 
 
 def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
-                smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, neumann=0) -> Config:
+                smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, neumann=0,
+                flux=False) -> Config:
     lib = _lib.load()
     cfg = Config()
     lib.tomg_config_default(C.byref(cfg), nx, ny, dx, dy)
@@ -40,6 +41,7 @@ def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=
     cfg.jacobi_omega = jacobi_omega
     cfg.ir_inner_cycles = ir_inner_cycles
     cfg.neumann = int(neumann)
+    cfg.flux = 1 if flux else 0
     return cfg
 
 
@@ -82,10 +84,10 @@ class Problem:
 
     def __init__(self, nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
                  smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, device=None,
-                 stream: Optional[torch.cuda.Stream] = None, neumann=0):
+                 stream: Optional[torch.cuda.Stream] = None, neumann=0, flux=False):
         self.lib = _lib.load()
         self.cfg = make_config(nx, ny, dx, dy, xi0, eta0, precision, nu1, nu2, smoother,
-                               jacobi_omega, ir_inner_cycles, neumann)
+                               jacobi_omega, ir_inner_cycles, neumann, flux)
         self.nx, self.ny = nx, ny
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:

@@ -34,7 +34,7 @@ class Config(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("precision", C.c_int32),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32),
                 ("jacobi_omega", C.c_double), ("ir_inner_cycles", C.c_int32),
-                ("neumann", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("neumann", C.c_int32), ("flux", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 _lib = None

@@ -47,6 +47,8 @@ static bool config_ok(const tomg_config &c) {
   if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
   if (c.neumann < 0 || c.neumann > 15) return false;
   if (c.neumann && c.precision != TOMG_FP64) return false;
+  if (c.flux != 0 && c.flux != 1) return false;
+  if (c.flux && c.precision != TOMG_FP64) return false;
   int a[kMaxLevels], b[kMaxLevels];
   return level_shapes(c.nx, c.ny, a, b, c.neumann) > 0;
 }
@@ -78,7 +80,7 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
   o.tmp = take(n0 * 8);
   o.dir[0] = take(n0);
   // Neumann edges: the level-0 stencil with the ghost layer folded in
-  if (cfg.neumann) o.st[0] = take(9 * n0 * 8);
+  if (stored_level0(cfg)) o.st[0] = take(9 * n0 * 8);
   for (int l = 1; l < o.L; ++l) {
     const size_t n = (size_t)o.nx[l] * o.ny[l];
     o.st[l] = take(9 * n * 8);
@@ -212,7 +214,7 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
     v.ny = lay.ny[l];
     v.n = (size_t)v.nx * v.ny;
     v.dir = (uint8_t *)(w + lay.dir[l]);
-    if (l == 0 && cfg->neumann) v.st = D(lay.st[0]);
+    if (l == 0 && stored_level0(*cfg)) v.st = D(lay.st[0]);
     if (l > 0) {
       v.st = D(lay.st[l]);
       v.x = D(lay.x[l]);
@@ -427,7 +429,7 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
     int k = 1;
     // the unfused cycles (Jacobi, Neumann edges) have no convergence check of
     // their own and are checked after every cycle
-    const bool queue = p->cfg.smoother == TOMG_GS4 && !p->cfg.neumann;
+    const bool queue = p->cfg.smoother == TOMG_GS4 && !stored_level0(p->cfg);
     if (queue) {
       const double rate = queued > 0 ? std::pow(rel / prev, 1.0 / queued) : NAN;
       if (std::isfinite(rate) && rate > 0.0 && rate < 1.0)
@@ -480,7 +482,7 @@ bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
     const tomg_problem *p = probs[k];
     if (!p || !d_phis[k] || !p->ready) return false;
     if (p->cfg.precision != lead->cfg.precision || p->cfg.nu1 != lead->cfg.nu1 ||
-        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 || p->cfg.neumann ||
+        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 || stored_level0(p->cfg) ||
         p->cfg.ir_inner_cycles != lead->cfg.ir_inner_cycles)
       return false;
   }
@@ -638,7 +640,8 @@ tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, doubl
   if (!p || !d_xp || !d_yp) return TOMG_EINVAL;
   if (!(rel_tol > 0.0) || max_cycles < 0)
     return fail(p, TOMG_EINVAL, "laplace_grid: bad tol/max_cycles");
-  if (p->cfg.neumann) return fail(p, TOMG_EINVAL, "laplace_grid: needs Dirichlet edges");
+  if (stored_level0(p->cfg))
+    return fail(p, TOMG_EINVAL, "laplace_grid: needs Dirichlet edges and the eq. 18 form");
   p->ready = false;
   p->unchecked = false;
   HIP_TRY(p, hipMemsetAsync(p->scal + kSlotBadRhs, 0, sizeof(double), p->stream));

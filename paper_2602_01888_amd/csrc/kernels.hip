@@ -302,7 +302,7 @@ __device__ __forceinline__ int mirror_index(int k, int n) {
 }
 
 __global__ void k_fold_stencil(EpsOp<double> op, int ny, const uint8_t *__restrict__ dir,
-                               double *__restrict__ st) {
+                               double *__restrict__ st, int flux) {
   const int nx = op.nx;
   const size_t n = (size_t)nx * ny;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
@@ -320,13 +320,59 @@ __global__ void k_fold_stencil(EpsOp<double> op, int ny, const uint8_t *__restri
         const double s = (odd && ((ri != ii) != (rj != jj))) ? -1.0 : 1.0;
         return s * v[(size_t)rj * nx + ri];
       };
-      const double ax = op.exx[c] * op.cx, ay = op.eyy[c] * op.cy;
-      const double gx = (ev(op.exx, i + 1, j, false) - ev(op.exx, i - 1, j, false)) * op.qx +
-                        (ev(op.exy, i, j + 1, true) - ev(op.exy, i, j - 1, true)) * op.qxy;
-      const double gy = (ev(op.eyy, i, j + 1, false) - ev(op.eyy, i, j - 1, false)) * op.qy +
-                        (ev(op.exy, i + 1, j, true) - ev(op.exy, i - 1, j, true)) * op.qxy;
-      const double k6 = op.exy[c] * op.hxy;
-      const double g[9] = {k6, ay - gy, -k6, ax - gx, -2.0 * (ax + ay), ax + gx, -k6, ay + gy, k6};
+      double g[9];
+      if (flux) {
+        // minus the gradient of the discrete energy: face means of eps_xx and
+        // eps_yy on squared face differences, cell means of eps_xy on the
+        // product of cell-centred differences (d gx / d phi at cell corner
+        // (p, q) is (2p - 1) / (2 dx), d gy is (2q - 1) / (2 dy))
+        const double c0 = op.exx[c], d0 = op.eyy[c];
+        const double aw = 0.5 * (c0 + ev(op.exx, i - 1, j, false)) * op.cx;
+        const double ae = 0.5 * (c0 + ev(op.exx, i + 1, j, false)) * op.cx;
+        const double as = 0.5 * (d0 + ev(op.eyy, i, j - 1, false)) * op.cy;
+        const double an = 0.5 * (d0 + ev(op.eyy, i, j + 1, false)) * op.cy;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) g[k] = 0.0;
+        g[3] = aw;
+        g[5] = ae;
+        g[1] = as;
+        g[7] = an;
+        g[4] = -(aw + ae + as + an);
+#pragma unroll
+        for (int cj = -1; cj <= 0; ++cj)
+#pragma unroll
+          for (int ci = -1; ci <= 0; ++ci) {
+            const double bxy =
+                0.25 * (ev(op.exy, i + ci, j + cj, true) + ev(op.exy, i + ci + 1, j + cj, true) +
+                        ev(op.exy, i + ci, j + cj + 1, true) +
+                        ev(op.exy, i + ci + 1, j + cj + 1, true));
+            const int pn = -ci, qn = -cj;
+#pragma unroll
+            for (int qm = 0; qm <= 1; ++qm)
+#pragma unroll
+              for (int pm = 0; pm <= 1; ++pm) {
+                const double h =
+                    ((2 * pn - 1) * (2 * qm - 1) + (2 * pm - 1) * (2 * qn - 1)) * op.qxy;
+                g[(cj + qm + 1) * 3 + ci + pm + 1] -= bxy * h;
+              }
+          }
+      } else {
+        const double ax = op.exx[c] * op.cx, ay = op.eyy[c] * op.cy;
+        const double gx = (ev(op.exx, i + 1, j, false) - ev(op.exx, i - 1, j, false)) * op.qx +
+                          (ev(op.exy, i, j + 1, true) - ev(op.exy, i, j - 1, true)) * op.qxy;
+        const double gy = (ev(op.eyy, i, j + 1, false) - ev(op.eyy, i, j - 1, false)) * op.qy +
+                          (ev(op.exy, i + 1, j, true) - ev(op.exy, i - 1, j, true)) * op.qxy;
+        const double k6 = op.exy[c] * op.hxy;
+        g[0] = k6;
+        g[1] = ay - gy;
+        g[2] = -k6;
+        g[3] = ax - gx;
+        g[4] = -2.0 * (ax + ay);
+        g[5] = ax + gx;
+        g[6] = -k6;
+        g[7] = ay + gy;
+        g[8] = k6;
+      }
 #pragma unroll
       for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
@@ -1382,14 +1428,14 @@ int tail_level(const tomg_problem *p) {
 }
 namespace {
 
-// One V(nu1, nu2) cycle of a problem with Neumann edges: every level uses
-// its stored stencil (level 0 included, with the ghost layer folded in) and
-// its ring may hold free nodes, so the smoother covers the ring, the
+// One V(nu1, nu2) cycle on stored stencils (Neumann edges or the flux form):
+// every level uses its stored stencil (level 0 included, with any Neumann
+// ghost layer folded in) and its ring may hold free nodes, so the smoother covers the ring, the
 // restriction fills free coarse ring nodes and the operator reads no node
 // outside the grid.  One launch per colour, residual-restriction and
 // prolongation.
 template <typename T>
-hipError_t run_vcycle_neumann(tomg_problem *p, T *x0, const T *b0, const LevelView<T> *views,
+hipError_t run_vcycle_stored(tomg_problem *p, T *x0, const T *b0, const LevelView<T> *views,
                               bool zero0) {
   const int L = p->L;
   const dim3 blk(64, 4);
@@ -1438,7 +1484,7 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
   const int L = p->L;
   const dim3 blk(64, 4);
   if (nblocks) *nblocks = 0;
-  if (p->cfg.neumann) return run_vcycle_neumann(p, x0, b0, views, zero0);
+  if (stored_level0(p->cfg)) return run_vcycle_stored(p, x0, b0, views, zero0);
   if (p->cfg.smoother == TOMG_GS4) {
     const int lc = tail_level(p);
     for (int l = 0; l < lc; ++l) {
@@ -1527,9 +1573,9 @@ hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, con
                      p->scal + kSlotMinDet, 0, p->scal, 0, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
                      2, p->scal + kSlotBad, 0, p->scal, 0, nullptr);
-  if (p->cfg.neumann)
+  if (stored_level0(p->cfg))
     hipLaunchKernelGGL(k_fold_stencil, kRedBlocks, kRedThreads, 0, p->stream, op64(p), ny,
-                       (const uint8_t *)p->lv[0].dir, p->lv[0].st);
+                       (const uint8_t *)p->lv[0].dir, p->lv[0].st, p->cfg.flux);
   return hipGetLastError();
 }
 
@@ -1568,7 +1614,7 @@ hipError_t launch_hierarchy(tomg_problem *p) {
     const tomg::Level &lf = p->lv[l - 1], &lc = p->lv[l];
     const dim3 grid((lc.nx + kGX - 1) / kGX, (lc.ny + kGY - 1) / kGY);
     float *st32 = f32 ? lc.st32 : nullptr;
-    if (l == 1 && !p->cfg.neumann)
+    if (l == 1 && !stored_level0(p->cfg))
       hipLaunchKernelGGL(k_coarsen_eps, grid, kGX * kGY, 0, p->stream, op64(p), lf.dir, lf.nx,
                          lf.ny, lc.nx, lc.ny, lc.dir, lc.st, st32);
     else
@@ -1628,7 +1674,7 @@ void build_red_args(tomg_problem *p) {
   r.r32 = p->r32;
   r.e32 = p->e32;
   r.tmp = p->tmp;
-  r.st0 = p->cfg.neumann ? p->lv[0].st : nullptr;
+  r.st0 = stored_level0(p->cfg) ? p->lv[0].st : nullptr;
   r.nblk = red_blocks(p->lv[0].n);
   p->hargs.fin_red = {p->partials, p->scal, r.nblk};
   p->hargs.fin_red0 = {p->partials + r.nblk, p->scal, r.nblk};
@@ -1764,7 +1810,7 @@ void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kin
 }
 
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps) {
-  if (p->cfg.neumann)
+  if (stored_level0(p->cfg))
     smooth_level(p, st_op_b<double>(p->lv[0].st, p->cfg.nx, p->cfg.ny), phi,
                  (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny, sweeps);
   else
@@ -1807,7 +1853,7 @@ void prof_harvest(tomg_problem *p) {
 
 hipError_t launch_residual0(tomg_problem *p, const double *phi, double *r) {
   const dim3 blk(64, 4);
-  if (p->cfg.neumann) {
+  if (stored_level0(p->cfg)) {
     hipLaunchKernelGGL((k_residual<StOpB<double>, double>), grid2(p->cfg.nx, p->cfg.ny, blk), blk,
                        0, p->stream, st_op_b<double>(p->lv[0].st, p->cfg.nx, p->cfg.ny), phi,
                        (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny, r);

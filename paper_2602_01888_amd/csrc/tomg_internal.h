@@ -152,6 +152,10 @@ struct Layout {
 };
 
 int level_shapes(int nx, int ny, int *nxs, int *nys, int neumann);
+
+// The level-0 operator is stored as a 9-point stencil (Neumann edges, or the
+// flux form) and every cycle runs the unfused kernels on stored stencils.
+inline bool stored_level0(const tomg_config &c) { return c.neumann != 0 || c.flux != 0; }
 bool make_layout(const tomg_config &cfg, Layout *lay);
 
 }  // namespace tomg
