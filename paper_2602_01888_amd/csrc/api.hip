@@ -238,7 +238,10 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
   }
   p->dargs = (ArgsBlob *)(w + lay.args);
   p->bout = D(lay.bout);
-  p->lc = tail_level(p);
+  // the single-workgroup tail assumes Dirichlet rings; problems with a
+  // stored level-0 stencil (Neumann edges, flux form) run the level passes
+  // down to the coarsest solve
+  p->lc = stored_level0(*cfg) ? p->L - 1 : tail_level(p);
   build_pass_args(p);
   build_tail_args(p);
   build_red_args(p);
@@ -429,7 +432,7 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
     int k = 1;
     // the unfused cycles (Jacobi, Neumann edges) have no convergence check of
     // their own and are checked after every cycle
-    const bool queue = p->cfg.smoother == TOMG_GS4 && !stored_level0(p->cfg);
+    const bool queue = p->cfg.smoother == TOMG_GS4;
     if (queue) {
       const double rate = queued > 0 ? std::pow(rel / prev, 1.0 / queued) : NAN;
       if (std::isfinite(rate) && rate > 0.0 && rate < 1.0)

@@ -164,7 +164,9 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   const int gi = x0 - H + t;
   const int gc = min(max(gi, 0), nx - 1);  // clamped column: loads never leave the array
   const bool inr = gi >= 0 && gi < nx;
-  const bool updc = gi >= 1 && gi <= nx - 2;
+  // every grid column may hold unknowns (a Neumann edge); Dirichlet nodes
+  // are skipped by their zero 1/diagonal
+  const bool updc = inr;
   const bool outc = t >= H && t < H + a.W && gi < nx;
   const int odd = gi & 1;
   // MIR: the block marches down its band.  It works in flipped row
@@ -191,6 +193,12 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   auto slot = [&](int rel) { return ((rel % NS) + NS) % NS; };
   auto lrow = [&](int r) -> T * { return L[((r % NR) + NR) % NR]; };
   auto grow = [&](int r) { return MIR ? ny - 1 - r : r; };  // grid row of row r
+  // rows with both neighbours loaded, and the grid's first and last rows
+  // (their outer neighbour has a zero coefficient: Neumann, or Dirichlet
+  // rows that are never relaxed)
+  auto relaxable = [&](int r) {
+    return r >= ys && r <= ye && (r > ys || r == 0) && (r < ye || r == ny - 1);
+  };
   // the rows below and above row r on the grid
   auto below_row = [&](int r) -> T * { return lrow(MIR ? r + 1 : r - 1); };
   auto above_row = [&](int r) -> T * { return lrow(MIR ? r - 1 : r + 1); };
@@ -225,7 +233,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
     const bool ld = r >= ys && r <= ye && inr;
     T v = ld ? w.x : T(0);
     if constexpr (PROLONG) {
-      if (ld && !w.d && updc && r > 0 && r < ny - 1) {
+      if (ld && !w.d && updc) {
         T e = odd ? T(0.5) * (w.c00 + w.c01) : w.c00;
         if (r & 1) {
           const T e1 = odd ? T(0.5) * (w.c10 + w.c11) : w.c10;
@@ -353,7 +361,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
               for (int p = 0; p < P; ++p) {
                 const int o = -2 * s - 2 * p - half;  // row 2m + o
                 const int r = 2 * m + o;
-                const bool rowok = r >= 1 && r <= ny - 2 && r > ys && r < ye;
+                const bool rowok = relaxable(r);
                 const Rec<T, EPS> &R = rec[slot(rel0 + o)];
                 if (rowok && updc && odd == cp && R.ik != T(0)) {
                   T *mid = lrow(r);
@@ -375,7 +383,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
           const T *mid = lrow(r);
           res[q] = T(0);
           if (RESTRICT || NORM) {
-            const bool rowok = r >= 1 && r <= ny - 2 && r > ys && r < ye;
+            const bool rowok = relaxable(r);
             if (rowok && updc && R.ik != T(0)) {
               T off, dg;
               apply<T, EPS>(R, below_row(r), mid, above_row(r), t, off, dg);
@@ -404,7 +412,9 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
             if (2 * J >= y0 && 2 * J < y1 && J < a.nyc && outc && !odd) {
               const int I = gi >> 1, Jg = MIR ? a.nyc - 1 - J : J;
               const bool ring = I == 0 || Jg == 0 || I == a.nxc - 1 || Jg == a.nyc - 1;
-              const T v = ring ? T(0)
+              // a coarse ring node is Dirichlet unless its edge is Neumann
+              const bool fixed = ring && (!a.dirc || a.dirc[(size_t)Jg * a.nxc + I]);
+              const T v = fixed ? T(0)
                                : (xch[p][t] + T(2) * xch[p][t + 1] + xch[p][t + 2]) * T(0.0625);
               st_out(a.bc + (size_t)Jg * a.nxc + I, v);
             }
@@ -606,12 +616,16 @@ static int pass_blocks_per_cu(int nu) {
   return nb;
 }
 
-// Resident-block slots of the pass of level l (the variant a solve launches).
+// Resident-block slots of the pass of level l (the variant a solve launches;
+// eps0: level 0 forms its coefficients from the tensor).
 template <typename T>
-static long pass_slots(int l, bool up, int nu) {
+static long pass_slots(int l, bool up, int nu, bool eps0) {
   constexpr bool F64 = std::is_same<T, double>::value;
   int nb;
-  if (l == 0) {
+  if (l == 0 && !eps0) {
+    nb = up ? pass_blocks_per_cu<T, false, false, true, false, F64>(nu)
+            : pass_blocks_per_cu<T, false, false, false, true, false>(nu);
+  } else if (l == 0) {
     if (up)
       nb = F64 ? pass_blocks_per_cu<T, true, false, true, false, F64>(nu)
                : pass_blocks_per_cu<T, true, false, true, false, false>(nu);
@@ -644,7 +658,9 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0,
   a.exx = exx;
   a.exy = exy;
   a.eyy = eyy;
-  a.st = l == 0 ? nullptr : (const T *)(f32 ? (void *)v.st32 : (void *)v.st);
+  const bool stored = stored_level0(p->cfg);  // level 0 stencil stored (FP64 only)
+  a.st = l == 0 ? (stored ? (const T *)(void *)v.st : nullptr)
+                : (const T *)(f32 ? (void *)v.st32 : (void *)v.st);
   const double dx = p->cfg.dx, dy = p->cfg.dy;
   a.cx = T(1.0 / (dx * dx));
   a.cy = T(1.0 / (dy * dy));
@@ -657,11 +673,12 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0,
   a.nyc = c.ny;
   a.xc = up ? (const T *)(f32 ? (void *)c.x32 : (void *)c.x) : nullptr;
   a.bc = up ? nullptr : (T *)(f32 ? (void *)c.b32 : (void *)c.b);
+  a.dirc = stored ? c.dir : nullptr;
   a.partials = (up && l == 0) ? p->partials : nullptr;
   const int nu = up ? p->cfg.nu2 : p->cfg.nu1;
   a.W = kBW - 2 * (4 * nu + 2);
   a.CH = batch ? pick_band_batch(a.nx, a.ny, a.W)
-              : pick_band(a.nx, a.ny, a.W, l, pass_slots<T>(l, up, nu), 2 * nu + 3);
+              : pick_band(a.nx, a.ny, a.W, l, pass_slots<T>(l, up, nu, !stored), 2 * nu + 3);
   a.nbx = (a.nx + a.W - 1) / a.W;
   a.nby = (a.ny + a.CH - 1) / a.CH;
   // TOMG_XCD_ORDER=0 keeps the two-dimensional launch order (tuning only)
@@ -710,7 +727,8 @@ static void launch_up(int nu, bool eps, bool norm, const PassArgs<T> &a, hipStre
     if (norm) launch_pass<T, true, false, true, false, true>(nu, a, s, tab, nb);
     else launch_pass<T, true, false, true, false, false>(nu, a, s, tab, nb);
   } else {
-    launch_pass<T, false, false, true, false, false>(nu, a, s, tab, nb);
+    if (norm) launch_pass<T, false, false, true, false, true>(nu, a, s, tab, nb);
+    else launch_pass<T, false, false, true, false, false>(nu, a, s, tab, nb);
   }
 }
 
@@ -730,7 +748,8 @@ void fused_down(tomg_problem *p, int l, const T *x, T *pong, const T *b, const T
   a.st = st;
   a.bc = bc;
   a.skip = p->skip;
-  launch_down<T>(p->cfg.nu1, l == 0, zero_start, a, p->stream, nullptr, 0);
+  launch_down<T>(p->cfg.nu1, l == 0 && !stored_level0(p->cfg), zero_start, a, p->stream,
+                 nullptr, 0);
 }
 
 // Up pass on level l: pong plus the prolongation of xc (level l+1), nu2
@@ -751,7 +770,8 @@ int fused_up(tomg_problem *p, int l, const T *pong, T *x, const T *b, const T *e
   a.xc = xc;
   a.partials = partials;
   a.skip = p->skip;
-  launch_up<T>(p->cfg.nu2, l == 0, partials != nullptr, a, p->stream, nullptr, 0);
+  launch_up<T>(p->cfg.nu2, l == 0 && !stored_level0(p->cfg), partials != nullptr, a, p->stream,
+               nullptr, 0);
   return a.nbx * a.nby;
 }
 

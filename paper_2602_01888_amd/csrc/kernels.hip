@@ -1484,9 +1484,10 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
   const int L = p->L;
   const dim3 blk(64, 4);
   if (nblocks) *nblocks = 0;
-  if (stored_level0(p->cfg)) return run_vcycle_stored(p, x0, b0, views, zero0);
+  if (stored_level0(p->cfg) && p->cfg.smoother != TOMG_GS4)
+    return run_vcycle_stored(p, x0, b0, views, zero0);
   if (p->cfg.smoother == TOMG_GS4) {
-    const int lc = tail_level(p);
+    const int lc = p->lc;  // first level of the tail (the coarsest alone: no tail)
     for (int l = 0; l < lc; ++l) {
       T *x = l == 0 ? x0 : views[l].x;
       const T *b = l == 0 ? b0 : views[l].b;
@@ -1503,7 +1504,11 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
       bs[l] = views[l].b;
       sts[l] = views[l].st;
     }
-    tail_cycle<T>(p, lc, xs, bs, sts);
+    if (lc == L - 1)  // no tail (stored level-0 stencil): the coarsest solve alone
+      hipLaunchKernelGGL((k_coarse_solve<T>), 1, 64, 0, p->stream, p->cinv, p->cidx,
+                         (const T *)views[L - 1].b, views[L - 1].x, (int)p->lv[L - 1].n);
+    else
+      tail_cycle<T>(p, lc, xs, bs, sts);
     for (int l = lc - 1; l >= 0; --l) {
       T *x = l == 0 ? x0 : views[l].x;
       const T *b = l == 0 ? b0 : views[l].b;

@@ -56,6 +56,8 @@ struct PassArgs {
   T cx, cy, qx, qy, qxy, hxy;
   const T *xc;               // up pass: coarse correction
   T *bc;                     // down pass: coarse right-hand side
+  const uint8_t *dirc;       // coarse flags where the coarse ring may hold
+                             // unknowns (Neumann edges), else null
   int nxc, nyc;
   double *partials;          // up pass with norm: one double per block
   int CH, W;                 // band height, owned columns per block
