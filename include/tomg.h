@@ -88,9 +88,11 @@ typedef struct {
                               Dirichlet); eq. 18 is applied there with a mirror
                               ghost layer (phi and the tensor mirrored across
                               the edge, eps_xy with its sign changed) folded onto
-                              the mirror nodes.  Requires TOMG_FP64; such a
-                              problem runs the unfused cycle (one launch per
-                              colour, residual, transfer) and cannot be batched */
+                              the mirror nodes.  Requires TOMG_FP64; the level-0
+                              stencil is stored (9 planes more workspace), the
+                              level passes run on it and the hierarchy ends in
+                              a coarsest grid of at most 5 x 5 nodes; such a
+                              problem cannot be batched */
   int32_t flux;            /* operator form: 0 (default) the paper's expanded
                               eq. 18; 1 the symmetric flux (energy) form --
                               minus the gradient of a discrete energy with face
@@ -98,7 +100,7 @@ typedef struct {
                               times cell-centred differences; symmetric, equal
                               to eq. 18 for constant eps, second order.  Like
                               Neumann edges it stores the level-0 stencil,
-                              runs the unfused FP64 cycle and is not batched */
+                              requires TOMG_FP64 and is not batched */
   int32_t reserved[1];     /* set to zero */
 } tomg_config;
 
