@@ -13,7 +13,7 @@ import numpy as np
 
 from . import build as _build
 
-GS4, GS_LEX, JACOBI, ZEBRA_X = 0, 1, 2, 3
+GS4, GS_LEX, JACOBI, ZEBRA_X, ZEBRA_XY = 0, 1, 2, 3, 4
 # edges with a homogeneous Neumann condition (bit mask)
 NEU_W, NEU_E, NEU_S, NEU_N = 1, 2, 4, 8
 

@@ -444,6 +444,55 @@ static void sweep_zebra_x(int nx, int ny, const double *st, const uint8_t *dir, 
   }
 }
 
+/* The same along y: the even columns i, then the odd columns, each solved
+ * exactly along j (S, C, N coefficients; the six off-column terms and b on
+ * the right). */
+static void sweep_zebra_y(int nx, int ny, const double *st, const uint8_t *dir, double *x,
+                          const double *b) {
+  size_t n = (size_t)nx * ny;
+  for (int parity = 0; parity < 2; ++parity) {
+#pragma omp parallel
+    {
+      double *a = (double *)malloc(4 * (size_t)ny * sizeof(double));
+      double *c = a + ny, *e = c + ny, *d = e + ny;
+#pragma omp for schedule(static)
+      for (int i = parity; i < nx; i += 2) {
+        for (int j = 0; j < ny; ++j) {
+          size_t q = ID(i, j, nx);
+          if (dir[q]) {
+            a[j] = 0.0;
+            c[j] = 1.0;
+            e[j] = 0.0;
+            d[j] = x[q];
+            continue;
+          }
+          a[j] = j > 0 ? PLANE(st, 1, n)[q] : 0.0;
+          c[j] = PLANE(st, 4, n)[q];
+          e[j] = j < ny - 1 ? PLANE(st, 7, n)[q] : 0.0;
+          double s = b[q];
+          for (int di = -1; di <= 1; di += 2) {
+            if (i + di < 0 || i + di >= nx) continue;
+            for (int dj = -1; dj <= 1; ++dj) {
+              if (j + dj < 0 || j + dj >= ny) continue;
+              s -= PLANE(st, (dj + 1) * 3 + (di + 1), n)[q] * x[ID(i + di, j + dj, nx)];
+            }
+          }
+          d[j] = s;
+        }
+        for (int j = 1; j < ny; ++j) {
+          double m = a[j] / c[j - 1];
+          c[j] -= m * e[j - 1];
+          d[j] -= m * d[j - 1];
+        }
+        x[ID(i, ny - 1, nx)] = d[ny - 1] / c[ny - 1];
+        for (int j = ny - 2; j >= 0; --j)
+          x[ID(i, j, nx)] = (d[j] - e[j] * x[ID(i, j + 1, nx)]) / c[j];
+      }
+      free(a);
+    }
+  }
+}
+
 void orc_smooth(int nx, int ny, const double *st, const uint8_t *dir, double *x,
                 const double *b, int kind, int sweeps, double omega) {
   for (int s = 0; s < sweeps; ++s) {
@@ -451,6 +500,10 @@ void orc_smooth(int nx, int ny, const double *st, const uint8_t *dir, double *x,
       sweep_lex(nx, ny, st, dir, x, b);
     else if (kind == ORC_ZEBRA_X)
       sweep_zebra_x(nx, ny, st, dir, x, b);
+    else if (kind == ORC_ZEBRA_XY) {
+      sweep_zebra_x(nx, ny, st, dir, x, b);
+      sweep_zebra_y(nx, ny, st, dir, x, b);
+    }
     else if (kind == ORC_JACOBI)
       sweep_jacobi(nx, ny, st, dir, x, b, omega);
     else

@@ -25,7 +25,7 @@
 extern "C" {
 #endif
 
-enum { ORC_GS4 = 0, ORC_GS_LEX = 1, ORC_JACOBI = 2, ORC_ZEBRA_X = 3 };
+enum { ORC_GS4 = 0, ORC_GS_LEX = 1, ORC_JACOBI = 2, ORC_ZEBRA_X = 3, ORC_ZEBRA_XY = 4 };
 /* Edges with a homogeneous Neumann condition (bit mask). */
 enum { ORC_NEU_W = 1, ORC_NEU_E = 2, ORC_NEU_S = 4, ORC_NEU_N = 8 };
 

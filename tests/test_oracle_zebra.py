@@ -83,3 +83,53 @@ def test_zebra_multigrid_beats_point_smoother_on_anisotropic_grid():
     assert rz["status"] == 0 and rp["status"] == 0
     assert rz["cycles"] <= rp["cycles"] // 2, (rz["cycles"], rp["cycles"])
     assert np.max(np.abs(rz["phi"] - rp["phi"])) <= 1e-8 * np.max(np.abs(rp["phi"]))
+
+
+@pytest.mark.parametrize("name", ["annulus_neumann", "circle", "sinusoidal17x9"])
+def test_zebra_y_half_sweep_is_column_block_gauss_seidel(name):
+    """An alternating sweep is an x-line sweep followed by a y-line sweep;
+    the y-line part equals column-block Gauss-Seidel (even columns, then
+    odd ones) with SciPy's banded solver per column."""
+    q = _problem(name)
+    s = oracle.setup(q)
+    st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], q.dx, q.dy, s["dir"])
+    rng = np.random.default_rng(8)
+    x0 = np.where(s["dir"] == 1, q.phi0, rng.normal(size=q.phi0.shape))
+    xh = oracle.smooth(st, s["dir"], x0, s["f"], kind=oracle.ZEBRA_X, sweeps=1)
+    got = oracle.smooth(st, s["dir"], x0, s["f"], kind=oracle.ZEBRA_XY, sweeps=1)
+    x = xh.copy()
+    ny, nx = x.shape
+    P = {(di, dj): st[(dj + 1) * 3 + (di + 1)] for dj in (-1, 0, 1) for di in (-1, 0, 1)}
+    for i in list(range(0, nx, 2)) + list(range(1, nx, 2)):
+        ab = np.zeros((3, ny))
+        rhs = np.zeros(ny)
+        for j in range(ny):
+            if s["dir"][j, i]:
+                ab[1, j] = 1.0
+                rhs[j] = x[j, i]
+                continue
+            ab[1, j] = P[(0, 0)][j, i]
+            if j > 0:
+                ab[2, j - 1] = P[(0, -1)][j, i]
+            if j < ny - 1:
+                ab[0, j + 1] = P[(0, 1)][j, i]
+            r = s["f"][j, i]
+            for di in (-1, 1):
+                for dj in (-1, 0, 1):
+                    if 0 <= j + dj < ny and 0 <= i + di < nx:
+                        r -= P[(di, dj)][j, i] * x[j + dj, i + di]
+            rhs[j] = r
+        x[:, i] = sla.solve_banded((1, 1), ab, rhs)
+    assert np.max(np.abs(got - x)) <= 1e-12 * max(1.0, np.max(np.abs(x)))
+
+
+def test_alternating_zebra_on_the_sinh_stretch():
+    """The sinh-stretched grid of Section 5.1 is anisotropic in both
+    directions (varying with position): x-lines alone do not help, the
+    alternating x/y sweep does."""
+    q = w.sinh_stretch(129)
+    rp = oracle.solve_problem(q, rel_tol=1e-10, max_cycles=200)
+    rx = oracle.solve_problem(q, rel_tol=1e-10, max_cycles=200, smoother=oracle.ZEBRA_X)
+    rxy = oracle.solve_problem(q, rel_tol=1e-10, max_cycles=200, smoother=oracle.ZEBRA_XY)
+    assert rxy["cycles"] <= rp["cycles"] // 2 and rx["cycles"] > rp["cycles"] // 2
+    assert np.max(np.abs(rxy["phi"] - rp["phi"])) <= 1e-8 * np.max(np.abs(rp["phi"]))
