@@ -59,7 +59,7 @@ typedef enum {
 } tomg_status;
 
 enum { TOMG_FP64 = 0, TOMG_FP32_IR = 1 };
-enum { TOMG_GS4 = 0, TOMG_JACOBI = 1, TOMG_ZEBRA_X = 2 };
+enum { TOMG_GS4 = 0, TOMG_JACOBI = 1, TOMG_ZEBRA_X = 2, TOMG_ZEBRA_XY = 3 };
 
 typedef struct {
   int32_t nx, ny;          /* nodes including the outer ring; (nx-1) and (ny-1)
@@ -75,8 +75,13 @@ typedef struct {
                               (zebra x-line Gauss-Seidel: even rows, then odd
                               rows, each solved exactly for its nodes with its
                               neighbours held -- for grids whose coupling along
-                              i dominates; nx <= 4225).  The latter two run the
-                              unfused cycle and cannot be batched */
+                              i dominates; nx <= 4225), or TOMG_ZEBRA_XY (an
+                              x-line sweep then a y-line sweep, for grids
+                              anisotropic in both directions; the y-lines run as
+                              x-lines of the transposed level, kept beside it;
+                              nx, ny <= 4225, FP64, level-0 stencil stored).  The
+                              latter three run the unfused cycle and cannot be
+                              batched */
   double jacobi_omega;     /* damping of TOMG_JACOBI (default 0.8) */
   int32_t ir_inner_cycles; /* FP32 V-cycles per refinement step (default 2) */
   int32_t neumann;         /* edges with a homogeneous Neumann condition

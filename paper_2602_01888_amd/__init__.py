@@ -18,7 +18,7 @@ import torch  # noqa: F401  (binds the HIP runtime before the library loads)
 from . import _lib
 from ._lib import (FIELD, STATUS_NAMES, TOMG_EGEOMETRY, TOMG_EINVAL, TOMG_ENOCONV,  # noqa: F401
                    TOMG_ENOMEM, TOMG_ENONFINITE, TOMG_ESTATE, TOMG_FP32_IR, TOMG_FP64,
-                   TOMG_GS4, TOMG_JACOBI, TOMG_ZEBRA_X, TOMG_NEU_E, TOMG_NEU_N, TOMG_NEU_S, TOMG_NEU_W,
+                   TOMG_GS4, TOMG_JACOBI, TOMG_ZEBRA_X, TOMG_ZEBRA_XY, TOMG_NEU_E, TOMG_NEU_N, TOMG_NEU_S, TOMG_NEU_W,
                    TOMG_OK, Config)
 
 
@@ -37,7 +37,8 @@ def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=
     cfg.xi0, cfg.eta0 = xi0, eta0
     cfg.precision = {"fp64": TOMG_FP64, "fp32_ir": TOMG_FP32_IR, "mixed": TOMG_FP32_IR}[precision]
     cfg.nu1, cfg.nu2 = nu1, nu2
-    cfg.smoother = {"gs4": TOMG_GS4, "jacobi": TOMG_JACOBI, "zebra_x": TOMG_ZEBRA_X}[smoother]
+    cfg.smoother = {"gs4": TOMG_GS4, "jacobi": TOMG_JACOBI, "zebra_x": TOMG_ZEBRA_X,
+                    "zebra_xy": TOMG_ZEBRA_XY}[smoother]
     cfg.jacobi_omega = jacobi_omega
     cfg.ir_inner_cycles = ir_inner_cycles
     cfg.neumann = int(neumann)

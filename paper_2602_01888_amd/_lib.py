@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "TOMG_OK", -1: "TOMG_EINVAL", -2: "TOMG_ENOMEM", -3: "TOMG_EG
                 -4: "TOMG_ENOCONV", -5: "TOMG_ENONFINITE", -6: "TOMG_EDEVICE",
                 -7: "TOMG_ESTATE"}
 TOMG_FP64, TOMG_FP32_IR = 0, 1
-TOMG_GS4, TOMG_JACOBI, TOMG_ZEBRA_X = 0, 1, 2
+TOMG_GS4, TOMG_JACOBI, TOMG_ZEBRA_X, TOMG_ZEBRA_XY = 0, 1, 2, 3
 TOMG_NEU_W, TOMG_NEU_E, TOMG_NEU_S, TOMG_NEU_N = 1, 2, 4, 8
 FIELD = {"exx": 0, "exy": 1, "eyy": 2, "det": 3, "rhs": 4, "dir": 5, "stencil": 6, "x": 7}
 

@@ -40,7 +40,10 @@ static bool config_ok(const tomg_config &c) {
   if (!(c.dx > 0.0) || !(c.dy > 0.0) || !std::isfinite(c.dx) || !std::isfinite(c.dy)) return false;
   if (c.precision != TOMG_FP64 && c.precision != TOMG_FP32_IR) return false;
   if (c.nu1 < 1 || c.nu2 < 1 || c.nu1 > 4 || c.nu2 > 4) return false;
-  if (c.smoother != TOMG_GS4 && c.smoother != TOMG_JACOBI && c.smoother != TOMG_ZEBRA_X)
+  if (c.smoother != TOMG_GS4 && c.smoother != TOMG_JACOBI && c.smoother != TOMG_ZEBRA_X &&
+      c.smoother != TOMG_ZEBRA_XY)
+    return false;
+  if (c.smoother == TOMG_ZEBRA_XY && (c.ny > 4225 || c.nx > 4225 || c.precision != TOMG_FP64))
     return false;
   if (c.smoother == TOMG_ZEBRA_X && c.nx > 4225) return false;  // the row in LDS
   if (c.smoother == TOMG_JACOBI && !(c.jacobi_omega > 0.0 && c.jacobi_omega <= 1.0)) return false;
@@ -89,6 +92,14 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
     o.b[l] = take(n * 8);
     o.dir[l] = take(n);
   }
+  if (cfg.smoother == TOMG_ZEBRA_XY)
+    for (int l = 0; l < o.L; ++l) {
+      const size_t n = (size_t)o.nx[l] * o.ny[l];
+      o.stT[l] = take(9 * n * 8);
+      o.xT[l] = take(n * 8);
+      o.bT[l] = take(n * 8);
+      o.dirT[l] = take(n);
+    }
   if (cfg.precision == TOMG_FP32_IR) {
     o.exx32 = take(n0 * 4);
     o.exy32 = take(n0 * 4);
@@ -215,6 +226,12 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
     v.n = (size_t)v.nx * v.ny;
     v.dir = (uint8_t *)(w + lay.dir[l]);
     if (l == 0 && stored_level0(*cfg)) v.st = D(lay.st[0]);
+    if (cfg->smoother == TOMG_ZEBRA_XY) {
+      v.stT = D(lay.stT[l]);
+      v.xT = D(lay.xT[l]);
+      v.bT = D(lay.bT[l]);
+      v.dirT = (uint8_t *)(w + lay.dirT[l]);
+    }
     if (l > 0) {
       v.st = D(lay.st[l]);
       v.x = D(lay.x[l]);

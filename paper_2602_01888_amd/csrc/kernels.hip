@@ -832,6 +832,31 @@ __global__ void k_gs_colour(Op op, T *x, const T *b, const uint8_t *dir, int nx,
   x[c] = (b[c] - off) / dg;
 }
 
+// dst = src transposed: dst[i * ny + j] = src[j * nx + i], through a 32 x 32
+// LDS tile so that both the reads and the writes are coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ src, T *__restrict__ dst,
+                                                   int nx, int ny) {
+  __shared__ T tile[32][33];
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + tx, j = j0 + r;
+    if (i < nx && j < ny) tile[r][tx] = src[(size_t)j * nx + i];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = j0 + tx, i = i0 + r;
+    if (i < nx && j < ny) dst[(size_t)i * ny + j] = tile[tx][r];
+  }
+}
+
+template <typename T>
+void transpose(tomg_problem *p, const T *src, T *dst, int nx, int ny) {
+  hipLaunchKernelGGL((k_transpose<T>), dim3((nx + 31) / 32, (ny + 31) / 32), 256, 0, p->stream,
+                     src, dst, nx, ny);
+}
+
 // Zebra x-line Gauss-Seidel, one parity of rows: block blk solves row
 // j = parity + 2 blk exactly for its own nodes, the rows above and below
 // held.  The row is a tridiagonal system: a free node keeps its W, C, E
@@ -1404,6 +1429,43 @@ void smooth_level(tomg_problem *p, const Op &op, T *x, const T *b, const uint8_t
     }
 }
 
+// Alternating zebra sweeps on stored stencils (FP64): an x-line sweep, then
+// the y-line sweep as an x-line sweep of the transposed level (stencil and
+// flags transposed at setup; iterate and right-hand side transposed in and
+// the iterate back out).
+void smooth_level_xy(tomg_problem *p, int l, const double *st, double *x, const double *b,
+                     int sweeps) {
+  const tomg::Level &v = p->lv[l];
+  const StOpB<double> op = st_op_b<double>(st, v.nx, v.ny);
+  const StOpB<double> opT = st_op_b<double>(v.stT, v.ny, v.nx);
+  for (int s = 0; s < sweeps; ++s) {
+    for (int parity = 0; parity < 2; ++parity)
+      hipLaunchKernelGGL((k_zebra_x<StOpB<double>, double>), (v.ny - parity + 1) / 2,
+                         kZebraThreads, zebra_shmem(v.nx, sizeof(double)), p->stream, op, x, b,
+                         (const uint8_t *)v.dir, v.nx, v.ny, parity);
+    transpose<double>(p, x, v.xT, v.nx, v.ny);
+    transpose<double>(p, b, v.bT, v.nx, v.ny);
+    for (int parity = 0; parity < 2; ++parity)
+      hipLaunchKernelGGL((k_zebra_x<StOpB<double>, double>), (v.nx - parity + 1) / 2,
+                         kZebraThreads, zebra_shmem(v.ny, sizeof(double)), p->stream, opT, v.xT,
+                         (const double *)v.bT, (const uint8_t *)v.dirT, v.ny, v.nx, parity);
+    transpose<double>(p, (const double *)v.xT, x, v.ny, v.nx);
+  }
+}
+
+// Smoothing on a stored-stencil level (the unfused cycle).
+template <typename T>
+void smooth_stored(tomg_problem *p, int l, const T *st, T *x, const T *b, int sweeps) {
+  const tomg::Level &v = p->lv[l];
+  if constexpr (std::is_same<T, double>::value) {
+    if (p->cfg.smoother == TOMG_ZEBRA_XY) {
+      smooth_level_xy(p, l, st, x, b, sweeps);
+      return;
+    }
+  }
+  smooth_level(p, st_op_b<T>(st, v.nx, v.ny), x, b, v.dir, v.nx, v.ny, sweeps);
+}
+
 template <class Op, typename T>
 void restrict_level(tomg_problem *p, const Op &op, const T *x, const T *b, const uint8_t *dir,
                     int nxf, T *bc, int nxc, int nyc, const uint8_t *dirc = nullptr) {
@@ -1445,7 +1507,7 @@ hipError_t run_vcycle_stored(tomg_problem *p, T *x0, const T *b0, const LevelVie
     const T *b = l == 0 ? b0 : views[l].b;
     if (l > 0 || zero0) hipLaunchKernelGGL((k_zero<T>), grid1(lv.n), 256, 0, p->stream, x, lv.n);
     const StOpB<T> op = st_op_b<T>(views[l].st, lv.nx, lv.ny);
-    smooth_level(p, op, x, b, lv.dir, lv.nx, lv.ny, p->cfg.nu1);
+    smooth_stored<T>(p, l, views[l].st, x, b, p->cfg.nu1);
     // residual once per fine node, then its full weighting
     T *r = reinterpret_cast<T *>(p->tmp);
     hipLaunchKernelGGL((k_residual<StOpB<T>, T>), grid2(lv.nx, lv.ny, blk), blk, 0, p->stream, op,
@@ -1465,8 +1527,7 @@ hipError_t run_vcycle_stored(tomg_problem *p, T *x0, const T *b0, const LevelVie
     const T *b = l == 0 ? b0 : views[l].b;
     hipLaunchKernelGGL((k_prolong<T>), grid2(lv.nx, lv.ny, blk), blk, 0, p->stream,
                        (const T *)views[l + 1].x, lc.nx, x, lv.dir, lv.nx, lv.ny);
-    smooth_level(p, st_op_b<T>(views[l].st, lv.nx, lv.ny), x, b, lv.dir, lv.nx, lv.ny,
-                 p->cfg.nu2);
+    smooth_stored<T>(p, l, views[l].st, x, b, p->cfg.nu2);
   }
   return hipGetLastError();
 }
@@ -1630,6 +1691,16 @@ hipError_t launch_hierarchy(tomg_problem *p) {
   const tomg::Level &lc = p->lv[p->L - 1];
   hipLaunchKernelGGL(k_coarse_inverse, 1, 256, 0, p->stream, lc.st, lc.dir, lc.nx, lc.ny,
                      p->cinv, p->cidx, p->scal);
+  if (p->cfg.smoother == TOMG_ZEBRA_XY)
+    // the transposed levels of the y-line sweeps: plane (di, dj) becomes (dj, di)
+    for (int l = 0; l < p->L; ++l) {
+      const tomg::Level &v = p->lv[l];
+      for (int k = 0; k < 9; ++k) {
+        const int di = k % 3 - 1, dj = k / 3 - 1, kt = (di + 1) * 3 + (dj + 1);
+        transpose<double>(p, v.st + (size_t)k * v.n, v.stT + (size_t)kt * v.n, v.nx, v.ny);
+      }
+      transpose<uint8_t>(p, v.dir, v.dirT, v.nx, v.ny);
+    }
   return hipGetLastError();
 }
 
@@ -1815,7 +1886,9 @@ void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kin
 }
 
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps) {
-  if (stored_level0(p->cfg))
+  if (p->cfg.smoother == TOMG_ZEBRA_XY)
+    smooth_level_xy(p, 0, p->lv[0].st, phi, (const double *)p->f, sweeps);
+  else if (stored_level0(p->cfg))
     smooth_level(p, st_op_b<double>(p->lv[0].st, p->cfg.nx, p->cfg.ny), phi,
                  (const double *)p->f, p->lv[0].dir, p->cfg.nx, p->cfg.ny, sweeps);
   else

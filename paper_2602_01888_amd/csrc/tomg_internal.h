@@ -39,6 +39,9 @@ struct Level {
   double *x2 = nullptr;  // second iterate buffer of the fused passes (levels >= 1)
   uint8_t *dir = nullptr;
   float *st32 = nullptr, *x32 = nullptr, *b32 = nullptr, *x2_32 = nullptr;  // FP32 (IR)
+  // alternating zebra: the level transposed (node (i, j) at i * ny + j)
+  double *stT = nullptr, *xT = nullptr, *bT = nullptr;
+  uint8_t *dirT = nullptr;
 };
 
 // ---- per-problem launch arguments (device copies live in the workspace) ----
@@ -149,6 +152,7 @@ struct Layout {
   size_t dir[kMaxLevels], st[kMaxLevels], x[kMaxLevels], b[kMaxLevels], x2[kMaxLevels];
   size_t exx32, exy32, eyy32, e32, e32b, r32;
   size_t st32[kMaxLevels], x32[kMaxLevels], b32[kMaxLevels], x2_32[kMaxLevels];
+  size_t stT[kMaxLevels], xT[kMaxLevels], bT[kMaxLevels], dirT[kMaxLevels];
   size_t args, bout;  // device copy of the launch arguments; batch results
   size_t total = 0;
 };
@@ -157,7 +161,9 @@ int level_shapes(int nx, int ny, int *nxs, int *nys, int neumann);
 
 // The level-0 operator is stored as a 9-point stencil (Neumann edges, or the
 // flux form) and every cycle runs the unfused kernels on stored stencils.
-inline bool stored_level0(const tomg_config &c) { return c.neumann != 0 || c.flux != 0; }
+inline bool stored_level0(const tomg_config &c) {
+  return c.neumann != 0 || c.flux != 0 || c.smoother == TOMG_ZEBRA_XY;
+}
 bool make_layout(const tomg_config &cfg, Layout *lay);
 
 }  // namespace tomg
