@@ -43,9 +43,10 @@ static bool config_ok(const tomg_config &c) {
   if (c.smoother != TOMG_GS4 && c.smoother != TOMG_JACOBI && c.smoother != TOMG_ZEBRA_X &&
       c.smoother != TOMG_ZEBRA_XY)
     return false;
-  if (c.smoother == TOMG_ZEBRA_XY && (c.ny > 4225 || c.nx > 4225 || c.precision != TOMG_FP64))
+  if (c.smoother == TOMG_ZEBRA_XY &&
+      (c.ny > kZebraMaxNx || c.nx > kZebraMaxNx || c.precision != TOMG_FP64))
     return false;
-  if (c.smoother == TOMG_ZEBRA_X && c.nx > 4225) return false;  // the row in LDS
+  if (c.smoother == TOMG_ZEBRA_X && c.nx > kZebraMaxNx) return false;  // the row in LDS
   if (c.smoother == TOMG_JACOBI && !(c.jacobi_omega > 0.0 && c.jacobi_omega <= 1.0)) return false;
   if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
   if (c.neumann < 0 || c.neumann > 15) return false;

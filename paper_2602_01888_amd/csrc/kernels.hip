@@ -876,9 +876,9 @@ void transpose(tomg_problem *p, const T *src, T *dst, int nx, int ny) {
 // the first barrier and all writes after the last, so the row is updated in
 // place.
 constexpr int kZebraThreads = 256, kZebraChunk = 17;
-constexpr int kZebraMaxNx = 4225;  // four padded FP64 rows of LDS fit in 160 KB
 __host__ __device__ constexpr int zebra_pad(int i) { return i + (i >> 4); }
 inline size_t zebra_shmem(int nx, size_t elem) { return 4 * (size_t)(zebra_pad(nx) + 1) * elem; }
+static_assert(4 * (zebra_pad(kZebraMaxNx) + 1) * 8 <= 160 * 1024, "zebra row exceeds LDS");
 
 template <class Op, typename T>
 __global__ __launch_bounds__(kZebraThreads) void k_zebra_x(Op op, T *x, const T *b,

@@ -161,6 +161,10 @@ int level_shapes(int nx, int ny, int *nxs, int *nys, int neumann);
 
 // The level-0 operator is stored as a 9-point stencil (Neumann edges, or the
 // flux form) and every cycle runs the unfused kernels on stored stencils.
+// Longest line of the zebra smoothers: four padded FP64 rows of LDS fit in
+// 160 KB.
+constexpr int kZebraMaxNx = 4225;
+
 inline bool stored_level0(const tomg_config &c) {
   return c.neumann != 0 || c.flux != 0 || c.smoother == TOMG_ZEBRA_XY;
 }
