@@ -93,7 +93,9 @@ typedef struct {
                               Dirichlet); eq. 18 is applied there with a mirror
                               ghost layer (phi and the tensor mirrored across
                               the edge, eps_xy with its sign changed) folded onto
-                              the mirror nodes.  Requires TOMG_FP64; the level-0
+                              the mirror nodes.  TOMG_FP64, or TOMG_FP32_IR with
+                              TOMG_GS4 (an FP32 copy of the stored stencil feeds
+                              the inner cycles); the level-0
                               stencil is stored (9 planes more workspace), the
                               level passes run on it and the hierarchy ends in
                               a coarsest grid of at most 5 x 5 nodes; such a
@@ -104,8 +106,9 @@ typedef struct {
                               means of eps_xx, eps_yy and cell means of eps_xy
                               times cell-centred differences; symmetric, equal
                               to eq. 18 for constant eps, second order.  Like
-                              Neumann edges it stores the level-0 stencil,
-                              requires TOMG_FP64 and is not batched */
+                              Neumann edges it stores the level-0 stencil, takes
+                              TOMG_FP64 or TOMG_FP32_IR with TOMG_GS4, and is
+                              not batched */
   int32_t reserved[1];     /* set to zero */
 } tomg_config;
 

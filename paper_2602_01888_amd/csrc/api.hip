@@ -50,9 +50,9 @@ static bool config_ok(const tomg_config &c) {
   if (c.smoother == TOMG_JACOBI && !(c.jacobi_omega > 0.0 && c.jacobi_omega <= 1.0)) return false;
   if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
   if (c.neumann < 0 || c.neumann > 15) return false;
-  if (c.neumann && c.precision != TOMG_FP64) return false;
   if (c.flux != 0 && c.flux != 1) return false;
-  if (c.flux && c.precision != TOMG_FP64) return false;
+  // a stored level-0 stencil with FP32 inner cycles: the fused passes only
+  if (stored_level0(c) && c.precision != TOMG_FP64 && c.smoother != TOMG_GS4) return false;
   int a[kMaxLevels], b[kMaxLevels];
   return level_shapes(c.nx, c.ny, a, b, c.neumann) > 0;
 }
@@ -108,6 +108,7 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
     o.e32 = take(n0 * 4);
     o.e32b = take(n0 * 4);
     o.r32 = take(n0 * 4);
+    if (stored_level0(cfg)) o.st32[0] = take(9 * n0 * 4);
     for (int l = 1; l < o.L; ++l) {
       const size_t n = (size_t)o.nx[l] * o.ny[l];
       o.st32[l] = take(9 * n * 4);
@@ -247,6 +248,7 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
     p->e32 = F(lay.e32);
     p->e32b = F(lay.e32b);
     p->r32 = F(lay.r32);
+    if (stored_level0(*cfg)) p->lv[0].st32 = F(lay.st32[0]);
     for (int l = 1; l < p->L; ++l) {
       p->lv[l].st32 = F(lay.st32[l]);
       p->lv[l].x32 = F(lay.x32[l]);

@@ -658,9 +658,8 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0,
   a.exx = exx;
   a.exy = exy;
   a.eyy = eyy;
-  const bool stored = stored_level0(p->cfg);  // level 0 stencil stored (FP64 only)
-  a.st = l == 0 ? (stored ? (const T *)(void *)v.st : nullptr)
-                : (const T *)(f32 ? (void *)v.st32 : (void *)v.st);
+  const bool stored = stored_level0(p->cfg);  // level 0 stencil stored
+  a.st = (l > 0 || stored) ? (const T *)(f32 ? (void *)v.st32 : (void *)v.st) : nullptr;
   const double dx = p->cfg.dx, dy = p->cfg.dy;
   a.cx = T(1.0 / (dx * dx));
   a.cy = T(1.0 / (dy * dy));

@@ -817,6 +817,13 @@ __global__ void k_zero(T *x, size_t n) {
     x[c] = T(0);
 }
 
+// y = fl32(x), n elements.
+__global__ void k_narrow(const double *__restrict__ x, float *__restrict__ y, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x)
+    y[c] = (float)x[c];
+}
+
 // One colour of four-colour Gauss-Seidel: nodes with i = i0 (mod 2),
 // j = j0 (mod 2) that are not Dirichlet (ring nodes only on Neumann edges).
 template <class Op, typename T>
@@ -1212,9 +1219,10 @@ __device__ __forceinline__ void ir_residual_body(const RedArgs &a, const double 
     for (int i = threadIdx.x; i < a.nx; i += blockDim.x) {
       double r = 0.0;
       if (!a.dir[row + i]) {
-        r = resid0<false>(a, phi, i, j);
+        // a stored stencil has free nodes on the ring (Neumann edges)
+        r = a.st0 ? resid_st<false>(a, phi, i, j) : resid0<false>(a, phi, i, j);
         if constexpr (B0) {
-          const double r0 = resid0<true>(a, phi, i, j);
+          const double r0 = a.st0 ? resid_st<true>(a, phi, i, j) : resid0<true>(a, phi, i, j);
           s0 += r0 * r0;
         }
       }
@@ -1639,9 +1647,13 @@ hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, con
                      p->scal + kSlotMinDet, 0, p->scal, 0, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
                      2, p->scal + kSlotBad, 0, p->scal, 0, nullptr);
-  if (stored_level0(p->cfg))
+  if (stored_level0(p->cfg)) {
     hipLaunchKernelGGL(k_fold_stencil, kRedBlocks, kRedThreads, 0, p->stream, op64(p), ny,
                        (const uint8_t *)p->lv[0].dir, p->lv[0].st, p->cfg.flux);
+    if (f32)  // the FP32 inner cycles relax with a rounded copy
+      hipLaunchKernelGGL(k_narrow, 4096, 256, 0, p->stream, (const double *)p->lv[0].st,
+                         p->lv[0].st32, 9 * p->lv[0].n);
+  }
   return hipGetLastError();
 }
 

@@ -83,6 +83,24 @@ def test_invalid_configs_size_to_zero(lib, kw):
     assert t.workspace_bytes(cfg(65, 65, **kw)) == 0
 
 
+def test_stored_stencil_mixed_precision_configs(lib):
+    """Neumann edges and the flux form keep the level-0 stencil stored; with
+    FP32 inner cycles an FP32 copy of it is added, and only the four-colour
+    smoother (fused passes) takes that combination."""
+    import paper_2602_01888_amd as t
+    n = 4097 * 4097
+    w64 = t.workspace_bytes(cfg(4097, 4097, neumann=t.TOMG_NEU_S))
+    w32 = t.workspace_bytes(cfg(4097, 4097, neumann=t.TOMG_NEU_S, precision="fp32_ir"))
+    w32d = t.workspace_bytes(cfg(4097, 4097, precision="fp32_ir"))
+    w64d = t.workspace_bytes(cfg(4097, 4097))
+    assert w64 - w64d >= 9 * 8 * n
+    assert w32 - w32d >= 9 * 8 * n + 9 * 4 * n
+    assert t.workspace_bytes(cfg(129, 129, flux=True, precision="fp32_ir")) > 0
+    for sm in ("jacobi", "zebra_x", "zebra_xy"):
+        assert t.workspace_bytes(cfg(129, 129, flux=True, precision="fp32_ir", smoother=sm)) == 0
+        assert t.workspace_bytes(cfg(129, 129, neumann=1, precision="fp32_ir", smoother=sm)) == 0
+
+
 def test_create_rejects_bad_arguments_before_touching_the_device(lib):
     """NULL workspace, misaligned workspace and undersized workspace are
     rejected by host checks alone."""

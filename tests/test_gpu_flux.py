@@ -105,3 +105,30 @@ def test_flux_fullsize_conductor(tomg):
     b0 = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], q.phi0, s["f"]))
     rel = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], np_(phi), s["f"])) / b0
     assert rel <= 1e-10 * (1 + 1e-3), rel
+
+
+@pytest.mark.parametrize("name", ["circle257", "circle129_SE"])
+def test_flux_mixed_precision(tomg, name):
+    """The flux form with FP32 inner cycles on its rounded stored stencil:
+    the oracle's FP64 flux-form residual of the result meets the tolerance
+    and the result is as close to the flux-form discrete solution as an FP64
+    solve stopped at that tolerance."""
+    q = CASES[name]()
+    print(f"[flux_mixed] {name}", flush=True)
+    p, d = tomg.setup_from_grid(q, flux=True, precision="mixed")
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=200)
+    assert res.ok
+    ro = oracle.solve_problem(q, rel_tol=1e-13, max_cycles=200, flux=True)
+    s, mg = ro["setup"], ro["mg"]
+    b0 = mg.initial_residual(q.phi0, s["f"])
+    rel = oracle.norm2_free(s["dir"], oracle.residual(mg.stencil(0), s["dir"], np_(phi),
+                                                      s["f"])) / b0
+    print(f"  refinement steps {res.cycles} rel {res.rel:.3e} oracle {rel:.3e}", flush=True)
+    assert rel <= 1e-10 * (1 + 1e-6), rel
+    e10 = rel_err(oracle.solve_problem(q, rel_tol=1e-10, max_cycles=200, flux=True)["phi"],
+                  ro["phi"])
+    e = rel_err(np_(phi), ro["phi"])
+    print(f"  error vs discrete solution {e:.2e} (FP64 at the same tolerance {e10:.2e})",
+          flush=True)
+    assert e <= max(10 * e10, 1e-12)

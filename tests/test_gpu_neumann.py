@@ -171,3 +171,67 @@ def test_fullsize_semi_annulus(tomg):
     err = np.max(np.abs(np_(phi) - q.phi_exact))
     print(f"  error vs closed form {err:.3e}", flush=True)
     assert err <= 2.5e-9
+
+
+@pytest.mark.parametrize("name", ["annulus65", "annulus129x65", "circle65_SE", "circle129_WES"])
+def test_mixed_precision_neumann(tomg, name):
+    """FP32 inner cycles on the rounded stored stencil inside FP64
+    refinement: the oracle's FP64 residual of the result meets the stopping
+    tolerance, and the result is as close to the discrete solution as an FP64
+    solve stopped at that tolerance."""
+    q = CASES[name]()
+    print(f"[neumann_mixed] {name}", flush=True)
+    p, d = tomg.setup_from_grid(q, precision="mixed", ir_inner_cycles=2)
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=400)
+    print(f"  refinement steps {res.cycles} rel {res.rel:.3e}", flush=True)
+    assert res.ok
+    ro = oracle.solve_problem(q, rel_tol=1e-13, max_cycles=400)
+    s, mg = ro["setup"], ro["mg"]
+    b0 = mg.initial_residual(q.phi0, s["f"])
+    rel = oracle.norm2_free(s["dir"], oracle.residual(mg.stencil(0), s["dir"], np_(phi),
+                                                      s["f"])) / b0
+    assert rel <= 1e-10 * (1 + 1e-6), rel
+    assert rel == pytest.approx(res.rel, rel=1e-6)
+    # as close to the discrete solution as an FP64 solve stopped at the same
+    # tolerance (the oracle's own iterate), within a factor 10
+    e10 = rel_err(oracle.solve_problem(q, rel_tol=1e-10, max_cycles=400)["phi"], ro["phi"])
+    e = rel_err(np_(phi), ro["phi"])
+    print(f"  error vs discrete solution {e:.2e} (FP64 at the same tolerance {e10:.2e})",
+          flush=True)
+    assert e <= max(10 * e10, 1e-12)
+    dmask = s["dir"].astype(bool)
+    assert np.array_equal(np_(phi)[dmask], q.phi0[dmask])
+
+
+def test_mixed_precision_limits(tomg):
+    """A stored level-0 stencil takes FP32 inner cycles only with the
+    four-colour smoother (the fused passes)."""
+    mk = tomg.make_config
+    assert tomg.workspace_bytes(mk(129, 129, 1.0, 1.0, neumann=S, precision="mixed")) > 0
+    assert tomg.workspace_bytes(mk(129, 129, 1.0, 1.0, neumann=S, precision="mixed",
+                                   smoother="jacobi")) == 0
+    assert tomg.workspace_bytes(mk(129, 129, 1.0, 1.0, neumann=S, precision="mixed",
+                                   smoother="zebra_x")) == 0
+
+
+def test_fullsize_semi_annulus_mixed(tomg):
+    """4097 x 4097 with the Neumann sides, FP32 inner cycles: the oracle's
+    residual of the result meets the tolerance and the error against the
+    closed form is that of the FP64 solve."""
+    n = 4097
+    q = w.polar_semi_annulus(n, neumann=True)
+    print(f"[neumann_fullsize_mixed] {n}", flush=True)
+    p, d = tomg.setup_from_grid(q, precision="mixed", ir_inner_cycles=4)
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=200)
+    print(f"  refinement steps {res.cycles} rel {res.rel:.3e}", flush=True)
+    assert res.ok
+    s = oracle.setup(q)
+    st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], q.dx, q.dy, s["dir"])
+    b0 = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], q.phi0, s["f"]))
+    rel = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], np_(phi), s["f"])) / b0
+    assert rel <= 1e-10 * (1 + 1e-3), rel
+    err = np.max(np.abs(np_(phi) - q.phi_exact))
+    print(f"  error vs closed form {err:.3e}", flush=True)
+    assert err <= 5e-7
