@@ -98,8 +98,8 @@ typedef struct {
                               the inner cycles); the level-0
                               stencil is stored (9 planes more workspace), the
                               level passes run on it and the hierarchy ends in
-                              a coarsest grid of at most 5 x 5 nodes; such a
-                              problem cannot be batched */
+                              a coarsest grid of at most 5 x 5 nodes; it is
+                              batched only with other stored-stencil problems */
   int32_t flux;            /* operator form: 0 (default) the paper's expanded
                               eq. 18; 1 the symmetric flux (energy) form --
                               minus the gradient of a discrete energy with face
@@ -108,7 +108,7 @@ typedef struct {
                               to eq. 18 for constant eps, second order.  Like
                               Neumann edges it stores the level-0 stencil, takes
                               TOMG_FP64 or TOMG_FP32_IR with TOMG_GS4, and is
-                              not batched */
+                              batched only with other stored-stencil problems */
   int32_t reserved[1];     /* set to zero */
 } tomg_config;
 
@@ -216,7 +216,9 @@ tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
  * reported relative residual may differ from solve()'s in the last bits.
  * 1 <= n <= 4096.  Batched launches need
  * one cycle configuration (precision, nu1, nu2, four-colour smoother,
- * ir_inner_cycles); other mixes are solved one after another.  Work the
+ * ir_inner_cycles, and one level-0 operator form: on-the-fly eq. 18 for all,
+ * or a stored stencil -- Neumann edges, flux form -- for all); other mixes
+ * are solved one after another.  Work the
  * caller queued for a problem on another stream must be ordered before the
  * call (the batch runs on the stream of probs[0]). */
 tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, int32_t n,

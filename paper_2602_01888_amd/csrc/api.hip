@@ -497,7 +497,9 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
 
 namespace {
 
-// Batched execution needs one configuration of the cycle for all problems.
+// Batched execution needs one configuration of the cycle for all problems:
+// one launch serves a stage of every problem, so the level-0 operator is
+// either on-the-fly eq. 18 for all of them or a stored stencil for all.
 bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
   const tomg_problem *lead = probs[0];
   if (!lead) return false;
@@ -505,7 +507,8 @@ bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
     const tomg_problem *p = probs[k];
     if (!p || !d_phis[k] || !p->ready) return false;
     if (p->cfg.precision != lead->cfg.precision || p->cfg.nu1 != lead->cfg.nu1 ||
-        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 || stored_level0(p->cfg) ||
+        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 ||
+        stored_level0(p->cfg) != stored_level0(lead->cfg) ||
         p->cfg.ir_inner_cycles != lead->cfg.ir_inner_cycles)
       return false;
   }

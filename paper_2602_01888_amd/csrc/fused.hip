@@ -822,11 +822,14 @@ static void batch_pass(tomg_problem *const *probs, const int *idx, int cnt, int 
       nb += h->nbx * h->nby;
     }
     if (!tab.count) continue;
-    const int nu = up ? probs[idx[k0]]->cfg.nu2 : probs[idx[k0]]->cfg.nu1;
+    const tomg_problem *p0 = probs[idx[k0]];
+    const int nu = up ? p0->cfg.nu2 : p0->cfg.nu1;
+    // a batch has one level-0 operator form (on-the-fly or stored) for all
+    const bool eps = l == 0 && !stored_level0(p0->cfg);
     if (up)
-      launch_up<T>(nu, l == 0, flag, *first, s, &tab, nb);
+      launch_up<T>(nu, eps, flag, *first, s, &tab, nb);
     else
-      launch_down<T>(nu, l == 0, flag, *first, s, &tab, nb);
+      launch_down<T>(nu, eps, flag, *first, s, &tab, nb);
   }
 }
 

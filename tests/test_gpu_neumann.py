@@ -140,11 +140,37 @@ def test_semi_annulus_second_order(tomg):
     assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2, errs
 
 
-def test_neumann_problem_is_not_batched(tomg):
-    q = CASES["circle65_SE"]()
-    p, d = tomg.setup_from_grid(q)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_stored_stencil_problems_batch(tomg, precision):
+    """Neumann-edge and flux-form problems (stored level-0 stencils) batch
+    together: the batched launches run (batch_step accepts the set), and
+    every result is bitwise the one solve() gives alone, with the same cycle
+    count."""
+    import torch
+    specs = [("annulus65", False), ("annulus129x65", False), ("circle65_SE", False),
+             ("circle129_WES", False), ("circle65_SE", True), ("circle33_all", True)]
+    print(f"[neumann_batch] {len(specs)} problems {precision}", flush=True)
+    ps, ds = zip(*[tomg.setup_from_grid(CASES[name](), precision=precision, flux=flux)
+                   for name, flux in specs])
+    probe = [d["phi0"].clone() for d in ds]
+    tomg.batch_step(list(ps), probe, [True] * len(ps))  # raises unless batchable
+    phis = [d["phi0"].clone() for d in ds]
+    res = tomg.solve_batch(list(ps), phis, rel_tol=1e-10, max_cycles=400)
+    assert all(r.ok for r in res), res
+    for p, d, phi, r in zip(ps, ds, phis, res):
+        alone = d["phi0"].clone()
+        ra = p.solve(alone, rel_tol=1e-10, max_cycles=400)
+        assert ra.cycles == r.cycles and abs(ra.rel - r.rel) <= 1e-12 * ra.rel
+        assert bool((alone == phi).all())
+    torch.cuda.synchronize()
+
+
+def test_stored_and_on_the_fly_problems_do_not_share_a_batch(tomg):
+    """One batched launch serves one level-0 operator form."""
+    pn, dn = tomg.setup_from_grid(CASES["circle65_SE"]())
+    pd, dd = tomg.setup_from_grid(w.perturbed_circle(65, seed=2))
     with pytest.raises(tomg.TomgError) as e:
-        tomg.batch_step([p], [d["phi0"].clone()], [True])
+        tomg.batch_step([pn, pd], [dn["phi0"].clone(), dd["phi0"].clone()], [True, True])
     assert e.value.status == tomg.TOMG_EINVAL
 
 
