@@ -161,3 +161,27 @@ def test_c4_full_batch(tomg):
         ra = ps[k].solve(alone, rel_tol=1e-10, max_cycles=100)
         assert ra.cycles == res[k].cycles
         assert bool((alone == phis[k]).all()), q.name
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_largest_grid_8193(tomg, precision):
+    """The same conductor workload at 8193 x 8193 (67 M unknowns, 11 levels,
+    four times the benchmark size): the oracle's residual of the GPU
+    solution meets the tolerance, in about the cycle count of the smaller
+    grid (the V-cycle's rate does not depend on the grid size)."""
+    import torch
+    n = 8193
+    prob = w.perturbed_circle(n, seed=1)
+    print(f"[fullsize] solve {n}x{n} {precision}", flush=True)
+    p, phi, r = gpu_solve(tomg, prob, precision, 1e-10)
+    assert r.ok, r
+    assert tomg.num_levels(p.cfg) == 11
+    del p
+    torch.cuda.empty_cache()
+    s = oracle.setup(prob)
+    st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], prob.dx, prob.dy, s["dir"])
+    rel = oracle_rel(st, s, prob, phi)
+    print(f"  gpu rel {r.rel:.3e}  oracle rel {rel:.3e}  cycles {r.cycles}", flush=True)
+    assert rel <= 1e-10 * (1 + 1e-6)
+    assert abs(rel - r.rel) <= 1e-6 * r.rel
+    assert r.cycles <= 14
