@@ -1446,13 +1446,13 @@ void smooth_level_xy(tomg_problem *p, int l, const double *st, double *x, const 
   const tomg::Level &v = p->lv[l];
   const StOpB<double> op = st_op_b<double>(st, v.nx, v.ny);
   const StOpB<double> opT = st_op_b<double>(v.stT, v.ny, v.nx);
+  transpose<double>(p, b, v.bT, v.nx, v.ny);  // the right-hand side is fixed while smoothing
   for (int s = 0; s < sweeps; ++s) {
     for (int parity = 0; parity < 2; ++parity)
       hipLaunchKernelGGL((k_zebra_x<StOpB<double>, double>), (v.ny - parity + 1) / 2,
                          kZebraThreads, zebra_shmem(v.nx, sizeof(double)), p->stream, op, x, b,
                          (const uint8_t *)v.dir, v.nx, v.ny, parity);
     transpose<double>(p, x, v.xT, v.nx, v.ny);
-    transpose<double>(p, b, v.bT, v.nx, v.ny);
     for (int parity = 0; parity < 2; ++parity)
       hipLaunchKernelGGL((k_zebra_x<StOpB<double>, double>), (v.nx - parity + 1) / 2,
                          kZebraThreads, zebra_shmem(v.ny, sizeof(double)), p->stream, opT, v.xT,
