@@ -240,18 +240,21 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
 tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,
                             const int32_t *fresh, double *rel_out);
 
-/* Numerical grid generation (Section 4.2, eq. 36-37): the node coordinates
- * x'(xi, eta), y'(xi, eta) of the physical grid solve Laplace's equation on
- * the problem's computational grid, with the boundary map as Dirichlet data.
- * On entry d_xp, d_yp (double[ny][nx], device) hold the boundary map on the
- * outer ring and an initial guess inside (zeros will do); on return the
- * interior solves the 5-point Laplace equation to the relative residual
- * rel_tol (as solve()), *cycles_out (nullable) the larger of the two cycle
- * counts.  The problem's operator is left as the identity tensor: call
- * setup_coeffs with the generated grid (d_xp, d_yp) before solving the
- * physical problem.  Errors as solve(); synchronises the problem's stream. */
-tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, double rel_tol,
-                              int32_t max_cycles, int32_t *cycles_out);
+/* Numerical grid generation (Section 4.2, eq. 36-37; Section 5.2 for an
+ * embedded body): the node coordinates x'(xi, eta), y'(xi, eta) of the
+ * physical grid solve Laplace's equation on the problem's computational
+ * grid, with the boundary map as Dirichlet data.  On entry d_xp, d_yp
+ * (double[ny][nx], device) hold the map on the outer ring and on the nodes
+ * d_mask marks (uint8[ny][nx], device, nullable: 1 = the map is prescribed
+ * there, such as the outline of an embedded square), and an initial guess
+ * elsewhere (zeros will do); on return the other nodes solve the 5-point
+ * Laplace equation to the relative residual rel_tol (as solve()),
+ * *cycles_out (nullable) the larger of the two cycle counts.  The
+ * problem's operator is left as the identity tensor: call setup_coeffs
+ * with the generated grid (d_xp, d_yp) before solving the physical
+ * problem.  Errors as solve(); synchronises the problem's stream. */
+tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, const uint8_t *d_mask,
+                              double rel_tol, int32_t max_cycles, int32_t *cycles_out);
 
 /* Field recovery (eq. 2): the physical electric field E' = (J^T)^-1 E with
  * E = -grad phi on the uniform grid, at every node of the problem's grid.

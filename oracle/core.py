@@ -366,20 +366,25 @@ class MG:
         return phi, st, cyc.value, rel.value, hist[:min(hist_len, cyc.value + 1)]
 
 
-def generate_grid(xb, yb, dx, dy, rel_tol=1e-13, max_cycles=200):
+def generate_grid(xb, yb, dx, dy, rel_tol=1e-13, max_cycles=200, mask=None):
     """Numerical grid generation (Section 4.2, eq. 36-37): x'(xi, eta) and
     y'(xi, eta) solve Laplace's equation on the computational grid with the
     boundary map as Dirichlet data.  The operator is this oracle's eq. 18 with
     the identity tensor (the 5-point Laplacian), solved by its multigrid.
-    xb, yb: node arrays carrying the boundary values.  Returns (xp, yp)."""
+    xb, yb: node arrays carrying the boundary values on the outer ring and,
+    where mask is 1, inside the grid (an embedded body's outline, Section
+    5.2).  Returns (xp, yp)."""
     xb, yb = _f64(xb), _f64(yb)
     ny, nx = xb.shape
     one, zero = np.ones((ny, nx)), np.zeros((ny, nx))
-    mg = MG(one, zero, one, dx, dy)
+    mg = MG(one, zero, one, dx, dy, mask=mask)
+    fixed = np.zeros((ny, nx), dtype=bool)
+    fixed[0, :] = fixed[-1, :] = fixed[:, 0] = fixed[:, -1] = True
+    if mask is not None:
+        fixed |= np.asarray(mask).astype(bool)
     out = []
     for b0 in (xb, yb):
-        start = b0.copy()
-        start[1:-1, 1:-1] = 0.0
+        start = np.where(fixed, b0, 0.0)
         phi, status, _, rel, _ = mg.solve(start, zero, rel_tol, max_cycles)
         if status == 2:
             raise FloatingPointError("grid generation diverged")

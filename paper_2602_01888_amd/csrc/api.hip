@@ -661,8 +661,8 @@ tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, i
   return TOMG_OK;
 }
 
-tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, double rel_tol,
-                              int32_t max_cycles, int32_t *cycles_out) {
+tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, const uint8_t *d_mask,
+                              double rel_tol, int32_t max_cycles, int32_t *cycles_out) {
   if (!p || !d_xp || !d_yp) return TOMG_EINVAL;
   if (!(rel_tol > 0.0) || max_cycles < 0)
     return fail(p, TOMG_EINVAL, "laplace_grid: bad tol/max_cycles");
@@ -671,7 +671,7 @@ tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, doubl
   p->ready = false;
   p->unchecked = false;
   HIP_TRY(p, hipMemsetAsync(p->scal + kSlotBadRhs, 0, sizeof(double), p->stream));
-  HIP_TRY(p, launch_setup_identity(p));
+  HIP_TRY(p, launch_setup_identity(p, d_mask));
   HIP_TRY(p, launch_hierarchy(p));
   double h[kNumSlots];
   tomg_status s = read_scalars(p, h);

@@ -433,9 +433,9 @@ __global__ void k_field(int nx, int ny, double dx, double dy, const double *__re
 __global__ void k_setup_identity(int nx, int ny, double *__restrict__ exx,
                                  double *__restrict__ exy, double *__restrict__ eyy,
                                  double *__restrict__ det, double *__restrict__ f,
-                                 uint8_t *__restrict__ dir, float *__restrict__ exx32,
-                                 float *__restrict__ exy32, float *__restrict__ eyy32,
-                                 double *__restrict__ partials) {
+                                 uint8_t *__restrict__ dir, const uint8_t *__restrict__ mask,
+                                 float *__restrict__ exx32, float *__restrict__ exy32,
+                                 float *__restrict__ eyy32, double *__restrict__ partials) {
   const size_t n = (size_t)nx * ny;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x) {
@@ -450,7 +450,8 @@ __global__ void k_setup_identity(int nx, int ny, double *__restrict__ exx,
       exy32[c] = 0.0f;
       eyy32[c] = 1.0f;
     }
-    dir[c] = (uint8_t)(i == 0 || j == 0 || i == (size_t)nx - 1 || j == (size_t)ny - 1);
+    dir[c] = (uint8_t)(i == 0 || j == 0 || i == (size_t)nx - 1 || j == (size_t)ny - 1 ||
+                       (mask && mask[c]));
   }
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = 1.0;
@@ -1664,10 +1665,10 @@ hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, co
   return hipGetLastError();
 }
 
-hipError_t launch_setup_identity(tomg_problem *p) {
+hipError_t launch_setup_identity(tomg_problem *p, const uint8_t *mask) {
   const bool f32 = p->cfg.precision == TOMG_FP32_IR;
   hipLaunchKernelGGL(k_setup_identity, kRedBlocks, kRedThreads, 0, p->stream, p->cfg.nx,
-                     p->cfg.ny, p->exx, p->exy, p->eyy, p->det, p->f, p->lv[0].dir,
+                     p->cfg.ny, p->exx, p->exy, p->eyy, p->det, p->f, p->lv[0].dir, mask,
                      f32 ? p->exx32 : nullptr, f32 ? p->exy32 : nullptr,
                      f32 ? p->eyy32 : nullptr, p->partials);
   hipLaunchKernelGGL((k_finalize<1>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 2,

@@ -22,6 +22,8 @@ from .gen import (  # noqa: F401
     square_to_disc,
     disc_boundary,
     disc_on_grid,
+    embedded_body_boundary,
+    embedded_flow,
     gaussian_sources,
     random_sinusoidal,
     batch_mixed,

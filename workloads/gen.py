@@ -257,6 +257,92 @@ def disc_on_grid(xp, yp, b: float, kind: str) -> GridProblem:
                        phi_exact=phi, meta={"b": b})
 
 
+def embedded_body_boundary(n: int = 257, kind: str = "cylinder", L: float = 10.0,
+                           half: float = 2.5, a: float = 10.0, n_osc: int = 3,
+                           amp: Optional[float] = None):
+    """Boundary data of the grids of Section 5.2: an embedded body in the
+    computational square [-L/2, L/2]^2, which the map leaves fixed on its
+    outer ring.  The body is the computational square [-half, half]^2; the
+    nodes of its outline carry the body's map:
+      kind = "cylinder": the square-to-disc map of eq. 44 (a circle of radius
+        half);
+      kind = "arbitrary": eq. 51, each side of the square displaced normally by
+        amp sin(pi n_osc s) (s in [0, 1] along the side), outward on the
+        sides x = half, y = half, inward on x = -half, y = -half; amp defaults
+        to a times the spacing of the paper's 257-node grid (a = 10: 0.39),
+        kept fixed in physical units at other resolutions.
+    Returns (xb, yb, outline): the map on the outer ring (the identity) and on
+    the outline (uint8 mask), zero elsewhere; the other nodes are found by
+    solving eq. 36-37 (grid generation with the outline held)."""
+    d = L / (n - 1)
+    k0 = half / d
+    if abs(k0 - round(k0)) > 1e-9:
+        raise ValueError("the body's square must fall on grid lines")
+    XI, ETA = _grid(n, n, -L / 2, -L / 2, d, d)
+    ring = _outer_ring(n, n)
+    lo, hi = (n - 1) // 2 - int(round(k0)), (n - 1) // 2 + int(round(k0))
+    outline = np.zeros((n, n), dtype=bool)
+    outline[lo:hi + 1, lo] = outline[lo:hi + 1, hi] = True
+    outline[lo, lo:hi + 1] = outline[hi, lo:hi + 1] = True
+    xb, yb = np.zeros((n, n)), np.zeros((n, n))
+    xb[ring], yb[ring] = XI[ring], ETA[ring]
+    xs, ys = XI[outline], ETA[outline]
+    if kind == "cylinder":
+        b = half
+        on_x = np.isclose(np.abs(xs), b)  # the sides xi = -+b (corners included)
+        xo = np.where(on_x, np.sign(xs) * b * np.sqrt(1.0 - ys ** 2 / (2 * b * b)),
+                      xs / math.sqrt(2.0))
+        yo = np.where(on_x, ys / math.sqrt(2.0),
+                      np.sign(ys) * b * np.sqrt(1.0 - xs ** 2 / (2 * b * b)))
+    elif kind == "arbitrary":
+        A = a * (L / 256.0) if amp is None else amp
+        sx = np.sin(np.pi * n_osc * (ys + half) / (2 * half))
+        sy = np.sin(np.pi * n_osc * (xs + half) / (2 * half))
+        xo = np.where(np.isclose(xs, -half), xs - A * sx,
+                      np.where(np.isclose(xs, half), xs + A * sx, xs))
+        yo = np.where(np.isclose(ys, -half), ys - A * sy,
+                      np.where(np.isclose(ys, half), ys + A * sy, ys))
+    else:
+        raise ValueError(kind)
+    xb[outline], yb[outline] = xo, yo
+    return xb, yb, outline.astype(np.uint8)
+
+
+def embedded_flow(xp, yp, L: float = 10.0, half: float = 2.5, psi0: float = -1.0,
+                  psi1: float = 1.0, data: str = "eq47") -> GridProblem:
+    """The potential-flow problem of Section 5.2 on a generated grid (xp, yp)
+    of the computational square [-L/2, L/2]^2: the stream function solves
+    Laplace's equation (rho' = 0) with psi = 0 on the body, the computational
+    square [-half, half]^2 (its nodes are Dirichlet nodes), and on the outer
+    ring
+      data = "eq47": the values of eq. 47 -- psi0 on the bottom edge, psi1 on
+        the top, varying linearly in y on the inflow and outflow edges;
+      data = "cylinder_exact": the unbounded flow past a circle of radius
+        half, psi = y' (1 - half^2 / r'^2), which vanishes on the circle the
+        cylinder grid maps the body's outline onto; phi_exact holds it at
+        every node (a closed form for the whole discrete problem).
+    Numeric Jacobian from the node coordinates."""
+    n = xp.shape[0]
+    d = L / (n - 1)
+    XI, ETA = _grid(n, n, -L / 2, -L / 2, d, d)
+    ring = _outer_ring(n, n)
+    body = (np.abs(XI) <= half + 1e-12) & (np.abs(ETA) <= half + 1e-12)
+    phi0 = np.zeros((n, n))
+    exact = None
+    if data == "eq47":
+        phi0[ring] = psi0 + (psi1 - psi0) * (ETA[ring] + L / 2) / L
+    elif data == "cylinder_exact":
+        r2 = xp ** 2 + yp ** 2
+        exact = np.where(body, 0.0, yp * (1.0 - half * half / np.maximum(r2, 1e-300)))
+        phi0[ring] = exact[ring]
+    else:
+        raise ValueError(data)
+    return GridProblem(f"embedded_flow_{data}_{n}", n, n, -L / 2, -L / 2, d, d,
+                       np.ascontiguousarray(xp), np.ascontiguousarray(yp), np.zeros((n, n)),
+                       phi0, jac=None, mask=body.astype(np.uint8), phi_exact=exact,
+                       meta={"L": L, "half": half, "psi": (psi0, psi1), "data": data})
+
+
 # ----------------------------------------------------------------------------
 # Benchmark workloads
 # ----------------------------------------------------------------------------
