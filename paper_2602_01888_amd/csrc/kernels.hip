@@ -305,9 +305,17 @@ __global__ void k_fold_stencil(EpsOp<double> op, int ny, const uint8_t *__restri
                                double *__restrict__ st, int flux) {
   const int nx = op.nx;
   const size_t n = (size_t)nx * ny;
+  const bool small = n < (size_t(1) << 32);
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x) {
-    const int j = (int)(c / (size_t)nx), i = (int)(c - (size_t)j * nx);
+    int i, j;
+    if (small) {  // 32-bit division where the index fits
+      j = (int)((unsigned)c / (unsigned)nx);
+      i = (int)((unsigned)c - (unsigned)j * (unsigned)nx);
+    } else {
+      j = (int)(c / (size_t)nx);
+      i = (int)(c - (size_t)j * nx);
+    }
     double a[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) a[k] = 0.0;
@@ -373,12 +381,18 @@ __global__ void k_fold_stencil(EpsOp<double> op, int ny, const uint8_t *__restri
         g[7] = ay + gy;
         g[8] = k6;
       }
+      // each ghost coefficient onto its mirror node; the target slot is
+      // selected arithmetically so that a[] stays in registers (adding 0.0
+      // leaves the other slots unchanged)
 #pragma unroll
       for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
         for (int di = -1; di <= 1; ++di) {
           const int ti = mirror_index(i + di, nx) - i, tj = mirror_index(j + dj, ny) - j;
-          a[(tj + 1) * 3 + ti + 1] += g[(dj + 1) * 3 + di + 1];
+          const int tk = (tj + 1) * 3 + ti + 1;
+          const double v = g[(dj + 1) * 3 + di + 1];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) a[k] += k == tk ? v : 0.0;
         }
     }
 #pragma unroll
