@@ -3,6 +3,7 @@
 import numpy as np
 import pytest
 
+import oracle
 import workloads as w
 
 pytestmark = pytest.mark.gpu
@@ -153,3 +154,43 @@ def test_nonfinite_update_rhs_marks_batch_nan_until_next_setup(tomg):
     (r,) = tomg.batch_step([p], [phi], [True])
     assert abs(r - 1) < 1e-12
     assert torch.isfinite(phi).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_zero_problem_converges_immediately(tomg, precision):
+    """Zero source and zero Dirichlet data: the zero-interior start is the
+    solution, |b| = 0, and the solve stops before any cycle with a relative
+    residual of 0 (alone and batched), leaving phi exactly zero."""
+    import torch
+    q = w.identity_map(65)
+    p, d = tomg.setup_from_grid(q, precision=precision)
+    phi = d["phi0"].clone()
+    r = p.solve(phi, rel_tol=1e-10)
+    assert r.ok and r.cycles == 0 and r.rel == 0.0
+    assert bool((phi == 0).all())
+    phis = [d["phi0"].clone(), d["phi0"].clone()]
+    p2, _ = tomg.setup_from_grid(q, precision=precision)
+    res = tomg.solve_batch([p, p2], phis, rel_tol=1e-10)
+    assert all(x.ok and x.cycles == 0 and x.rel == 0.0 for x in res)
+    assert all(bool((f == 0).all()) for f in phis)
+    torch.cuda.synchronize()
+
+
+def test_fully_masked_grid_has_nothing_to_solve(tomg):
+    """Every node Dirichlet (an interior mask covering the grid): no
+    unknowns, the solve returns at once and phi keeps its Dirichlet values;
+    the oracle agrees."""
+    import numpy as np
+    import torch
+    q = w.manufactured_sinusoidal(65)
+    q.mask = np.ones((q.ny, q.nx), dtype=np.uint8)
+    q.phi0 = q.phi_exact.copy()
+    p, d = tomg.setup_from_grid(q)
+    phi = d["phi0"].clone()
+    r = p.solve(phi, rel_tol=1e-10)
+    assert r.ok and r.cycles == 0 and r.rel == 0.0
+    assert bool((phi == d["phi0"]).all())
+    ro = oracle.solve_problem(q)
+    assert ro["status"] == 0 and ro["cycles"] == 0
+    assert np.array_equal(ro["phi"], q.phi0)
+    torch.cuda.synchronize()
