@@ -207,3 +207,43 @@ def test_mixed_precision_solution(tomg):
     st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], prob.dx, prob.dy, s["dir"])
     ref = direct.direct_solve(st, s["dir"], s["f"], prob.phi0)
     assert rel_err(np_(b), ref) <= 1e-9
+
+
+def _dielectric(prob, kind):
+    """A physical permittivity per node: a disc of relative permittivity 4 in
+    the physical domain (a dielectric body), or a smooth variation."""
+    if kind == "disc":
+        r = np.hypot(prob.xp - 0.6, prob.yp - 0.4)
+        return np.where(r < 0.15, 4.0, 1.0)
+    return 1.0 + 0.5 * np.sin(3.0 * prob.xp) * np.cos(2.0 * prob.yp) ** 2
+
+
+@pytest.mark.parametrize("name,kind", [("circle257", "disc"), ("sinusoidal129", "smooth"),
+                                       ("rect129x65", "disc")])
+def test_physical_permittivity_parity(tomg, name, kind):
+    """setup_coeffs with a physical permittivity eps' (eq. 10: the tensor is
+    det J J^-1 eps' J^-T): tensor fields and the solution against the
+    oracle."""
+    import torch
+    prob = CASES[name]()
+    ep = _dielectric(prob, kind)
+    print(f"[eps_phys] {name} {kind}", flush=True)
+    p = tomg.Problem.from_grid(prob)
+    d = tomg.upload(prob)
+    ept = torch.as_tensor(np.ascontiguousarray(ep)).cuda()
+    if d["jac"] is not None:
+        p.setup_coeffs(d["rho"], jac=d["jac"], eps_phys=ept, mask=d["mask"])
+    else:
+        p.setup_coeffs(d["rho"], xp=d["xp"], yp=d["yp"], eps_phys=ept, mask=d["mask"])
+    s = oracle.setup(prob, ep)
+    m = np.ones((prob.ny, prob.nx), bool)
+    m[0, 0] = m[0, -1] = m[-1, 0] = m[-1, -1] = False
+    scale = max(np.max(np.abs(s["exx"][m])), np.max(np.abs(s["eyy"][m])))
+    for key in ("exx", "exy", "eyy"):
+        assert np.max(np.abs(np_(p.export(key))[m] - s[key][m])) <= 1e-14 * scale, key
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-12, max_cycles=200)
+    assert res.ok
+    ro = oracle.solve_problem(prob, rel_tol=1e-13, max_cycles=200, eps_phys=ep)
+    print(f"  cycles gpu {res.cycles}", flush=True)
+    assert rel_err(np_(phi), ro["phi"]) <= 1e-10
