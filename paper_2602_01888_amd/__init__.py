@@ -230,6 +230,13 @@ class Problem:
         self._check(self.lib.tomg_smooth(self._h, _ptr(phi, torch.float64, (self.ny, self.nx),
                                                        "phi"), sweeps), "smooth")
 
+    def set_stream(self, stream: torch.cuda.Stream):
+        """tomg_set_stream: later calls run on `stream` (same device); work
+        queued for the problem on the old stream must be ordered before."""
+        self._check(self.lib.tomg_set_stream(self._h, C.c_void_p(stream.cuda_stream)),
+                    "set_stream")
+        self.stream = stream
+
     def profile(self, enable: bool = True):
         self._check(self.lib.tomg_profile(self._h, 1 if enable else 0), "profile")
 

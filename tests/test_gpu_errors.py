@@ -194,3 +194,53 @@ def test_fully_masked_grid_has_nothing_to_solve(tomg):
     assert ro["status"] == 0 and ro["cycles"] == 0
     assert np.array_equal(ro["phi"], q.phi0)
     torch.cuda.synchronize()
+
+
+def test_set_stream_gives_the_same_solution(tomg):
+    """A problem moved to another stream solves there, bitwise as before."""
+    import torch
+    q = w.perturbed_circle(257, seed=4)
+    p, d = tomg.setup_from_grid(q)
+    a = d["phi0"].clone()
+    ra = p.solve(a, rel_tol=1e-10)
+    s = torch.cuda.Stream()
+    b = d["phi0"].clone()
+    s.wait_stream(torch.cuda.current_stream())
+    p.set_stream(s)
+    with torch.cuda.stream(s):
+        rb = p.solve(b, rel_tol=1e-10)
+    torch.cuda.synchronize()
+    assert ra.ok and rb.ok and ra.cycles == rb.cycles and ra.rel == rb.rel
+    assert bool((a == b).all())
+
+
+def test_profile_counts_level0_passes(tomg):
+    """tomg_profile / tomg_profile_read: one level-0 down and one up pass per
+    cycle (cycles queued past convergence are counted too), positive times,
+    nothing recorded once profiling is off."""
+    import torch
+    q = w.perturbed_circle(513, seed=4)
+    p, d = tomg.setup_from_grid(q)
+    phi = d["phi0"].clone()
+    p.profile(True)
+    r = p.solve(phi, rel_tol=1e-10)
+    dm, dc, um, uc = p.profile_read()
+    p.profile(False)
+    assert r.ok and dc >= r.cycles and uc >= r.cycles and dc == uc
+    assert dm > 0.0 and um > 0.0
+    phi.copy_(d["phi0"])
+    p.solve(phi, rel_tol=1e-10)
+    assert p.profile_read() == (dm, dc, um, uc)
+    torch.cuda.synchronize()
+
+
+def test_copy_probe_copies_and_checks_alignment(tomg):
+    import torch
+    src = torch.randn(1 << 21, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    tomg.copy_probe(src, dst)
+    torch.cuda.synchronize()
+    assert bool((src == dst).all())
+    with pytest.raises(tomg.TomgError) as e:
+        tomg.copy_probe(src[1:], dst[1:])  # 8-byte offset: not 16-byte aligned
+    assert e.value.status == tomg.TOMG_EINVAL
