@@ -5,7 +5,10 @@ the set of problems being solved on the device and advances all of them
 together, one V-cycle (or refinement step) per ``tomg_batch_step``; between
 two steps it retires problems that reached the tolerance and admits queued
 requests, so a request that arrives while others are being solved joins the
-next step instead of waiting for the batch to drain.
+next step instead of waiting for the batch to drain.  One batched launch
+serves one level-0 operator form, so a step advances the problems with the
+on-the-fly eq. 18 operator and those with a stored stencil (Neumann edges,
+flux form) as two groups.
 
 Memory.  Every geometry the server holds (being solved, or idle and kept for
 a later warm re-solve) costs its library workspace plus its solution array;
@@ -68,6 +71,13 @@ class Request:
     arrival: float = 0.0
     xi0: float = 0.0
     eta0: float = 0.0
+    neumann: int = 0      # edges with a zero normal derivative (TOMG_NEU_* bits)
+    flux: bool = False    # the symmetric flux form of the operator
+
+    @property
+    def stored_form(self) -> bool:
+        """True when the problem's level-0 operator is a stored stencil."""
+        return bool(self.neumann) or bool(self.flux)
 
 
 @dataclass
@@ -127,7 +137,8 @@ class TomgBackend:
         self.device = torch.device("cuda") if device is None else torch.device(device)
 
     def footprint(self, req: Request) -> int:
-        cfg = self.tomg.make_config(req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0, **self.kw)
+        cfg = self.tomg.make_config(req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0,
+                                    neumann=req.neumann, flux=req.flux, **self.kw)
         return self.tomg.workspace_bytes(cfg) + 8 * req.nx * req.ny
 
     def transient(self, req: Request) -> int:
@@ -138,7 +149,8 @@ class TomgBackend:
         """New problem with its coefficient setup queued (checks deferred);
         returns (problem, phi)."""
         p = self.tomg.Problem(req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0,
-                              device=self.device, **self.kw)
+                              device=self.device, neumann=req.neumann, flux=req.flux,
+                              **self.kw)
         g = req.geometry()
         rho = req.source()
         if g.get("jac") is not None:
@@ -278,8 +290,16 @@ class Server:
         if not self.active:
             return done
         acts = self.active
-        rels = self.backend.step([a.res.problem for a in acts], [a.res.phi for a in acts],
-                                 [a.fresh for a in acts])
+        # one batched step per level-0 operator form (on the fly / stored)
+        rels = [math.nan] * len(acts)
+        for form in (False, True):
+            grp = [k for k, a in enumerate(acts) if a.req.stored_form == form]
+            if not grp:
+                continue
+            out = self.backend.step([acts[k].res.problem for k in grp],
+                                    [acts[k].res.phi for k in grp], [acts[k].fresh for k in grp])
+            for k, r in zip(grp, out):
+                rels[k] = r
         t = self.clock()
         self.stats["steps"] += 1
         keep = []

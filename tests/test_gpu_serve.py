@@ -103,3 +103,40 @@ def test_served_folded_map_fails_alone(env):
     assert f.status == tomg.TOMG_EGEOMETRY and "det J" in f.error and f.cycles == 0
     assert "folded" not in srv.resident
     assert all(done[r.rid].ok for r in reqs)
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir", "fp64"])
+def test_served_neumann_and_circle_mix_equal_alone(env, precision):
+    """A stream mixing perturbed circles with the semi-annulus of Section 4.1
+    (Neumann sides: a stored level-0 stencil, batched apart from the
+    circles), cold and warm: each result is bitwise the solve of the same
+    request alone."""
+    torch, tomg, serve, D = env
+    descs = w.serving_stream(16, rate=1000.0, seed=5, sides=(65, 129, 257),
+                             kinds=("circle", "annulus"))
+    reqs = [serve.Request(**D.request_fields(d, "cuda")) for d in descs]
+    kinds = [d["kind"] for d in descs]
+    print(f"[serve_mix] {len(reqs)} requests {precision}: {kinds.count('annulus')} annulus, "
+          f"{sum(d['warm'] for d in descs)} warm", flush=True)
+    assert "annulus" in kinds and "circle" in kinds
+    srv = serve.Server(serve.TomgBackend(precision=precision), budget_bytes=8 << 30,
+                       max_active=6, keep_results=True, max_cycles=200)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.drain()
+    assert len(done) == len(reqs) and all(c.ok for c in done), [c for c in done if not c.ok]
+    by = {r.rid: r for r in reqs}
+    for c in done:
+        r = by[c.rid]
+        g = r.geometry()
+        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, r.xi0, r.eta0, precision=precision,
+                         neumann=r.neumann)
+        rho = r.source()
+        if g["jac"] is not None:
+            p.setup_coeffs(rho, jac=g["jac"], mask=g["mask"])
+        else:
+            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g["mask"])
+        phi = c.phi_start.clone()
+        ra = p.solve(phi, rel_tol=1e-10, max_cycles=200)
+        assert ra.cycles == c.cycles, (c.rid, ra, c)
+        assert bool((phi == c.phi).all()), c.rid

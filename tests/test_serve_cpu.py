@@ -256,3 +256,34 @@ def test_deferred_setup_failure_is_diagnosed_and_dropped():
     assert by[0].ok and by[2].ok
     assert "g1" not in s.resident and "g0" in s.resident and "g2" in s.resident
     assert s.used == sum(r.nbytes for r in s.resident.values())
+
+
+def test_operator_forms_step_in_separate_batches():
+    """Requests with a stored level-0 stencil (Neumann edges, flux form) and
+    on-the-fly ones are advanced in one backend step per form; each request
+    keeps its own sequence of residuals."""
+    be = FakeBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    r0, r1, r2, r3 = req(0), req(1), req(2), req(3)
+    r1.neumann = 4 | 8
+    r3.flux = True
+    for r in (r0, r1, r2, r3):
+        s.submit(r)
+    done = s.drain()
+    assert sorted(c.rid for c in done) == [0, 1, 2, 3] and all(c.ok for c in done)
+    assert all(c.cycles == 3 for c in done)
+    # every server step made two backend steps: on the fly, then stored
+    assert be.steps[:2] == [[0, 2], [1, 3]]
+    assert all(set(a) in ({0, 2}, {1, 3}) for a in be.steps)
+
+
+def test_serving_stream_default_kinds_unchanged():
+    """The annulus kind is opt-in: the default stream draws circle and
+    sinusoidal geometries exactly as before (one integer draw of 2)."""
+    import workloads as w
+    a = w.serving_stream(50, rate=100.0, seed=3)
+    b = w.serving_stream(50, rate=100.0, seed=3, kinds=("circle", "sinusoidal"))
+    assert a == b
+    assert {d["kind"] for d in a} == {"circle", "sinusoidal"}
+    c = w.serving_stream(50, rate=100.0, seed=3, kinds=("circle", "annulus"))
+    assert [d["kind"] == "circle" for d in c] == [d["kind"] == "circle" for d in a]

@@ -28,4 +28,5 @@ from .gen import (  # noqa: F401
     random_sinusoidal,
     batch_mixed,
     serving_stream,
+    draw_annulus_sources,
 )

@@ -25,7 +25,8 @@ import math
 import numpy as np
 import torch
 
-from .gen import draw_box_sources, draw_circle, draw_circle_sources, draw_sinusoidal
+from .gen import (draw_annulus_sources, draw_box_sources, draw_circle, draw_circle_sources,
+                  draw_sinusoidal)
 
 SIGMA = 0.02
 
@@ -37,9 +38,15 @@ def _grid(n, device):
     return XI, ETA, d
 
 
+ANNULUS_SIGMA = 0.3
+
+
 def geometry_params(kind, geom_seed):
     """Host-side draws of a cold request: (map parameters, amps, centres)."""
     rng = np.random.default_rng(geom_seed)
+    if kind == "annulus":
+        amps, centres = draw_annulus_sources(rng, 4)
+        return {}, amps, np.asarray(centres)
     if kind == "circle":
         acoef = draw_circle(rng)
         amps, centres = draw_circle_sources(rng, acoef, 8)
@@ -51,6 +58,9 @@ def geometry_params(kind, geom_seed):
 def source_params(kind, map_params, source_seed):
     """Host-side draws of a warm request's sources."""
     rng = np.random.default_rng(source_seed)
+    if kind == "annulus":
+        amps, centres = draw_annulus_sources(rng, 4)
+        return amps, np.asarray(centres)
     if kind == "circle":
         amps, centres = draw_circle_sources(rng, map_params["acoef"], 8)
         return amps, np.asarray(centres)
@@ -103,7 +113,26 @@ def gaussian_rho(xp, yp, amps, centres, sigma=SIGMA):
     return rho.contiguous()
 
 
+def semi_annulus_geometry(n, device):
+    """The semi-annulus of Section 4.1 (see ``gen.polar_semi_annulus``):
+    x' = xi cos eta, y' = xi sin eta on [2, 5] x [0, pi], analytic partials,
+    phi = 1 on the arc r = 2 and 0 on r = 5; the straight sides eta = 0, pi
+    are Neumann edges (the request carries them)."""
+    dx, dy = 3.0 / (n - 1), math.pi / (n - 1)
+    xi = 2.0 + dx * torch.arange(n, dtype=torch.float64, device=device)
+    eta = dy * torch.arange(n, dtype=torch.float64, device=device)
+    ETA, XI = torch.meshgrid(eta, xi, indexing="ij")
+    c, s = torch.cos(ETA), torch.sin(ETA)
+    jac = torch.stack([c, -XI * s, s, XI * c]).contiguous()
+    phi0 = torch.zeros((n, n), dtype=torch.float64, device=device)
+    phi0[:, 0] = 1.0
+    return {"xp": (XI * c).contiguous(), "yp": (XI * s).contiguous(), "jac": jac,
+            "mask": None, "phi0": phi0}
+
+
 def geometry(kind, n, map_params, device):
+    if kind == "annulus":
+        return semi_annulus_geometry(n, device)
     if kind == "circle":
         return circle_geometry(n, map_params["acoef"], device)
     return sinusoidal_geometry(n, map_params["amp"], device)
@@ -125,10 +154,15 @@ def request_fields(desc, device):
         held["g"] = geometry(kind, n, mp, device)
         return held["g"]
 
+    sigma = ANNULUS_SIGMA if kind == "annulus" else SIGMA
+
     def source():
         # a cold request asks for the geometry first: reuse its coordinates
         g = held.pop("g", None) or geometry(kind, n, mp, device)
-        return gaussian_rho(g["xp"], g["yp"], amps, centres)
+        return gaussian_rho(g["xp"], g["yp"], amps, centres, sigma)
 
-    return {"rid": desc["id"], "geom": desc["geom"], "nx": n, "ny": n, "dx": d, "dy": d,
-            "geometry": geom, "source": source, "warm": desc["warm"], "arrival": desc["t"]}
+    out = {"rid": desc["id"], "geom": desc["geom"], "nx": n, "ny": n, "dx": d, "dy": d,
+           "geometry": geom, "source": source, "warm": desc["warm"], "arrival": desc["t"]}
+    if kind == "annulus":  # [2, 5] x [0, pi], Neumann sides eta = 0, pi
+        out.update(dx=3.0 / (n - 1), dy=math.pi / (n - 1), xi0=2.0, eta0=0.0, neumann=4 | 8)
+    return out

@@ -484,17 +484,31 @@ def batch_mixed(count: int = 256, base_seed: int = 1000,
     return out
 
 
+def draw_annulus_sources(rng, n_gauss=4):
+    """Gaussian sources inside the semi-annulus 2 <= r <= 5, 0 <= theta <= pi:
+    amplitudes N(0,1), centres at r ~ U(2.5, 4.5), theta ~ U(0.2, pi - 0.2)
+    (drawn in that order per source)."""
+    amps, centres = [], []
+    for _ in range(n_gauss):
+        amps.append(float(rng.normal()))
+        r, th = float(rng.uniform(2.5, 4.5)), float(rng.uniform(0.2, math.pi - 0.2))
+        centres.append((r * math.cos(th), r * math.sin(th)))
+    return np.asarray(amps), centres
+
+
 def serving_stream(count: int, rate: float, seed: int = 7,
-                   sides=(129, 257, 513, 1025, 2049), warm_frac: float = 0.3):
+                   sides=(129, 257, 513, 1025, 2049), warm_frac: float = 0.3,
+                   kinds=("circle", "sinusoidal")):
     """Request descriptors for the serving workload (no arrays are built here).
 
     rng = default_rng(seed).  Arrival gaps are exponential with mean 1/rate
     seconds.  For each request, in order: gap; u = rng.uniform() (< warm_frac
     selects a warm re-solve of an already-seen geometry, when one exists);
     for a cold request the side index rng.integers(len(sides)), the geometry
-    kind rng.integers(2) (0 = perturbed circle, 1 = sinusoidal) and a geometry
-    seed rng.integers(2**31); for a warm request the index of the earlier
-    geometry rng.integers(number seen so far) and a fresh source seed
+    kind kinds[rng.integers(len(kinds))] (by default perturbed circle or
+    sinusoidal map; "annulus" adds the semi-annulus with Neumann sides) and a
+    geometry seed rng.integers(2**31); for a warm request the index of the
+    earlier geometry rng.integers(number seen so far) and a fresh source seed
     rng.integers(2**31)."""
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -510,7 +524,7 @@ def serving_stream(count: int, rate: float, seed: int = 7,
                          "source_seed": int(rng.integers(2 ** 31))})
         else:
             side = sides[int(rng.integers(len(sides)))]
-            kind = "circle" if int(rng.integers(2)) == 0 else "sinusoidal"
+            kind = kinds[int(rng.integers(len(kinds)))]
             gs = int(rng.integers(2 ** 31))
             g = {"gid": len(geoms), "side": side, "kind": kind, "geom_seed": gs}
             geoms.append(g)
