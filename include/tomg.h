@@ -249,12 +249,18 @@ tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, i
  * there, such as the outline of an embedded square), and an initial guess
  * elsewhere (zeros will do); on return the other nodes solve the 5-point
  * Laplace equation to the relative residual rel_tol (as solve()),
- * *cycles_out (nullable) the larger of the two cycle counts.  The
+ * *cycles_out (nullable) the larger of the two cycle counts.  d_px, d_py
+ * (double[ny][nx], device, nullable) are source terms: the conclusion's
+ * adaptive grids solve Poisson's equation lap x' = P, lap y' = Q on the
+ * computational grid (the 5-point Laplacian, spacings dx, dy); along a grid
+ * line x'' = P, so nodes cluster where P changes from negative to positive;
+ * NULL means zero.  The
  * problem's operator is left as the identity tensor: call setup_coeffs
  * with the generated grid (d_xp, d_yp) before solving the physical
  * problem.  Errors as solve(); synchronises the problem's stream. */
 tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, const uint8_t *d_mask,
-                              double rel_tol, int32_t max_cycles, int32_t *cycles_out);
+                              const double *d_px, const double *d_py, double rel_tol,
+                              int32_t max_cycles, int32_t *cycles_out);
 
 /* Field recovery (eq. 2): the physical electric field E' = (J^T)^-1 E with
  * E = -grad phi on the uniform grid, at every node of the problem's grid.

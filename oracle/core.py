@@ -366,14 +366,16 @@ class MG:
         return phi, st, cyc.value, rel.value, hist[:min(hist_len, cyc.value + 1)]
 
 
-def generate_grid(xb, yb, dx, dy, rel_tol=1e-13, max_cycles=200, mask=None):
+def generate_grid(xb, yb, dx, dy, rel_tol=1e-13, max_cycles=200, mask=None, px=None, py=None):
     """Numerical grid generation (Section 4.2, eq. 36-37): x'(xi, eta) and
     y'(xi, eta) solve Laplace's equation on the computational grid with the
     boundary map as Dirichlet data.  The operator is this oracle's eq. 18 with
     the identity tensor (the 5-point Laplacian), solved by its multigrid.
     xb, yb: node arrays carrying the boundary values on the outer ring and,
     where mask is 1, inside the grid (an embedded body's outline, Section
-    5.2).  Returns (xp, yp)."""
+    5.2).  px, py: source terms (the adaptive grids of the conclusion: lap x' =
+    px, lap y' = py on the computational grid); None means zero.  Returns
+    (xp, yp)."""
     xb, yb = _f64(xb), _f64(yb)
     ny, nx = xb.shape
     one, zero = np.ones((ny, nx)), np.zeros((ny, nx))
@@ -383,9 +385,10 @@ def generate_grid(xb, yb, dx, dy, rel_tol=1e-13, max_cycles=200, mask=None):
     if mask is not None:
         fixed |= np.asarray(mask).astype(bool)
     out = []
-    for b0 in (xb, yb):
+    for b0, src in ((xb, px), (yb, py)):
+        rhs_g = zero if src is None else _f64(src)
         start = np.where(fixed, b0, 0.0)
-        phi, status, _, rel, _ = mg.solve(start, zero, rel_tol, max_cycles)
+        phi, status, _, rel, _ = mg.solve(start, rhs_g, rel_tol, max_cycles)
         if status == 2:
             raise FloatingPointError("grid generation diverged")
         out.append(phi)

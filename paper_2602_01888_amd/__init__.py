@@ -187,15 +187,18 @@ class Problem:
                     "residual_norm")
         return a.value, r.value
 
-    def laplace_grid(self, xp, yp, rel_tol=1e-12, max_cycles=200, mask=None) -> int:
+    def laplace_grid(self, xp, yp, rel_tol=1e-12, max_cycles=200, mask=None, px=None,
+                     py=None) -> int:
         """tomg_laplace_grid: fills xp, yp (map given on the ring and where
-        mask is 1) with the solution of Laplace's equation elsewhere; returns
-        the cycles."""
+        mask is 1) with the solution of Laplace's equation elsewhere, or of
+        Poisson's equation with the sources px, py; returns the cycles."""
         shp = (self.ny, self.nx)
         cyc = C.c_int32()
         self._check(self.lib.tomg_laplace_grid(self._h, _ptr(xp, torch.float64, shp, "xp"),
                                                _ptr(yp, torch.float64, shp, "yp"),
-                                               _ptr(mask, torch.uint8, shp, "mask"), rel_tol,
+                                               _ptr(mask, torch.uint8, shp, "mask"),
+                                               _ptr(px, torch.float64, shp, "px"),
+                                               _ptr(py, torch.float64, shp, "py"), rel_tol,
                                                max_cycles, C.byref(cyc)), "laplace_grid")
         return cyc.value
 

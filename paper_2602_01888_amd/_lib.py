@@ -71,7 +71,7 @@ def load(path: str = LIB_PATH):
         "tomg_batch_step": (C.c_int, [C.POINTER(P), C.POINTER(VP), I32, C.POINTER(I32),
                                       C.POINTER(D)]),
         "tomg_field": (C.c_int, [P, VP, VP, VP, VP, VP, VP]),
-        "tomg_laplace_grid": (C.c_int, [P, VP, VP, VP, D, I32, C.POINTER(I32)]),
+        "tomg_laplace_grid": (C.c_int, [P, VP, VP, VP, VP, VP, D, I32, C.POINTER(I32)]),
         "tomg_export": (C.c_int, [P, I32, I32, VP]),
         "tomg_level_shape": (C.c_int, [P, I32, C.POINTER(I32), C.POINTER(I32)]),
         "tomg_smooth": (C.c_int, [P, VP, I32]),

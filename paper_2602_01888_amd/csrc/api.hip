@@ -662,7 +662,8 @@ tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, i
 }
 
 tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, const uint8_t *d_mask,
-                              double rel_tol, int32_t max_cycles, int32_t *cycles_out) {
+                              const double *d_px, const double *d_py, double rel_tol,
+                              int32_t max_cycles, int32_t *cycles_out) {
   if (!p || !d_xp || !d_yp) return TOMG_EINVAL;
   if (!(rel_tol > 0.0) || max_cycles < 0)
     return fail(p, TOMG_EINVAL, "laplace_grid: bad tol/max_cycles");
@@ -680,8 +681,18 @@ tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, const
   p->ready = true;
   int32_t c1 = 0, c2 = 0;
   double r1 = 0.0, r2 = 0.0;
+  // the right-hand side of each coordinate's equation: its source, or zero
+  // (setup left f = 0)
+  const size_t fb = p->lv[0].n * sizeof(double);
+  if (d_px) HIP_TRY(p, hipMemcpyAsync(p->f, d_px, fb, hipMemcpyDeviceToDevice, p->stream));
   s = solve(p, d_xp, rel_tol, max_cycles, &c1, &r1);
-  if (s == TOMG_OK) s = solve(p, d_yp, rel_tol, max_cycles, &c2, &r2);
+  if (s == TOMG_OK) {
+    if (d_py)
+      HIP_TRY(p, hipMemcpyAsync(p->f, d_py, fb, hipMemcpyDeviceToDevice, p->stream));
+    else if (d_px)
+      HIP_TRY(p, launch_zero(p, p->f, p->lv[0].n));
+    s = solve(p, d_yp, rel_tol, max_cycles, &c2, &r2);
+  }
   if (cycles_out) *cycles_out = c1 > c2 ? c1 : c2;
   return s;
 }

@@ -1679,6 +1679,11 @@ hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, co
   return hipGetLastError();
 }
 
+hipError_t launch_zero(tomg_problem *p, double *x, size_t n) {
+  hipLaunchKernelGGL((k_zero<double>), grid1(n), 256, 0, p->stream, x, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_setup_identity(tomg_problem *p, const uint8_t *mask) {
   const bool f32 = p->cfg.precision == TOMG_FP32_IR;
   hipLaunchKernelGGL(k_setup_identity, kRedBlocks, kRedThreads, 0, p->stream, p->cfg.nx,

@@ -232,6 +232,7 @@ hipError_t launch_ir_correct(tomg_problem *p, double *phi);
 hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free);
 hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir);
 hipError_t launch_setup_identity(tomg_problem *p, const uint8_t *mask);
+hipError_t launch_zero(tomg_problem *p, double *x, size_t n);
 hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, const double *yp,
                         const double *jac, double *ex, double *ey);
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps);

@@ -72,3 +72,32 @@ def test_disc_with_source_on_generated_grid_is_second_order(env):
         l2.append(float(np.sqrt(np.sum(e * e)) / n))
     print(f"  L2 errors {l2}", flush=True)
     assert 3.5 <= l2[0] / l2[1] <= 4.5 and 3.5 <= l2[1] / l2[2] <= 4.5
+
+
+def test_grid_generation_with_sources_matches_oracle(env):
+    """tomg_laplace_grid with source terms (lap x' = P, lap y' = Q; the
+    conclusion's adaptive grids): the quadratic map with its constant
+    sources is reproduced, and a clustering source gives the oracle's grid."""
+    torch, tomg = env
+    n = 129
+    q = w.identity_map(n)
+    x, y = q.xp, q.yp
+    a, c = 0.4, -0.3
+    xt, yt = x + a * (x ** 2 + y ** 2) / 4.0, y + c * y ** 2
+    xb, yb = xt.copy(), yt.copy()
+    xb[1:-1, 1:-1] = yb[1:-1, 1:-1] = 0.0
+    p = tomg.Problem(n, n, q.dx, q.dy)
+    xp, yp = torch.as_tensor(xb).cuda(), torch.as_tensor(yb).cuda()
+    p.laplace_grid(xp, yp, rel_tol=1e-13, px=torch.full((n, n), a, dtype=torch.float64).cuda(),
+                   py=torch.full((n, n), 2.0 * c, dtype=torch.float64).cuda())
+    assert np.max(np.abs(xp.cpu().numpy() - xt)) <= 1e-11
+    assert np.max(np.abs(yp.cpu().numpy() - yt)) <= 1e-11
+    # a clustering source in x only (y' keeps Laplace's equation)
+    xb, yb = x.copy(), y.copy()
+    xb[1:-1, 1:-1] = yb[1:-1, 1:-1] = 0.0
+    px = 40.0 * (x - 0.5) * np.exp(-((x - 0.5) / 0.1) ** 2)
+    xg, yg = torch.as_tensor(xb).cuda(), torch.as_tensor(yb).cuda()
+    p.laplace_grid(xg, yg, rel_tol=1e-13, px=torch.as_tensor(px).cuda())
+    rx, ry = oracle.generate_grid(xb, yb, q.dx, q.dy, rel_tol=1e-13, px=px)
+    assert np.max(np.abs(xg.cpu().numpy() - rx)) <= 1e-11
+    assert np.max(np.abs(yg.cpu().numpy() - ry)) <= 1e-11

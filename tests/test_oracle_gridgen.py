@@ -71,3 +71,46 @@ def test_harmonic_on_unit_disc_generated_grid_is_second_order():
     # eq. 45 with n = 8, b = 1 (Section 4.2.2)
     e = [_solve_on_generated(n, 1.0, "harmonic8") for n in (33, 65, 129)]
     assert 3.5 <= e[0][0] / e[1][0] <= 4.5 and 3.5 <= e[1][0] / e[2][0] <= 4.5
+
+
+def test_sources_give_the_quadratic_map():
+    """Grid generation with source terms (the conclusion's adaptive grids):
+    x' = xi + a (xi^2 + eta^2) / 4 has lap x' = a, y' = eta + c eta^2 has
+    lap y' = 2c; the 5-point Laplacian is exact on quadratics, so with these
+    constant sources and the map's boundary values the generated grid is
+    the map itself (a wrong sign or a missing h^2 scaling of the source
+    breaks this)."""
+    n = 33
+    q = w.identity_map(n)
+    x, y = q.xp, q.yp
+    a, c = 0.4, -0.3
+    xt, yt = x + a * (x ** 2 + y ** 2) / 4.0, y + c * y ** 2
+    xb, yb = xt.copy(), yt.copy()
+    xb[1:-1, 1:-1] = yb[1:-1, 1:-1] = 0.0
+    px, py = np.full((n, n), a), np.full((n, n), 2.0 * c)
+    xp, yp = oracle.generate_grid(xb, yb, q.dx, q.dy, px=px, py=py)
+    assert np.max(np.abs(xp - xt)) <= 1e-12 and np.max(np.abs(yp - yt)) <= 1e-12
+    # without the sources the interior differs
+    x0, _ = oracle.generate_grid(xb, yb, q.dx, q.dy)
+    assert np.max(np.abs(x0 - xt)) > 1e-3
+
+
+def test_source_clusters_nodes():
+    """An adaptive grid of the conclusion: along a line x'' = P, so the
+    spacing of x' falls where P < 0 and grows where P > 0; a source that
+    changes sign from negative to positive across xi = 0.5 clusters the
+    nodes there (and the opposite sign spreads them)."""
+    n = 65
+    q = w.identity_map(n)
+    x, y = q.xp, q.yp
+    xb, yb = x.copy(), y.copy()
+    xb[1:-1, 1:-1] = yb[1:-1, 1:-1] = 0.0
+    band = (x - 0.5) * np.exp(-((x - 0.5) / 0.1) ** 2)
+    mid = n // 2
+    for k, closer in ((40.0, True), (-40.0, False)):
+        xp, yp = oracle.generate_grid(xb, yb, q.dx, q.dy, px=k * band)
+        dx_mid = xp[mid, mid + 1] - xp[mid, mid]
+        dx_far = xp[mid, 9] - xp[mid, 8]
+        assert (dx_mid < 0.9 * dx_far) if closer else (dx_mid > 1.1 * dx_far)
+        assert np.all(np.diff(xp[mid]) > 0)  # still a valid (monotone) grid line
+        assert np.max(np.abs(yp - y)) <= 1e-12
