@@ -43,6 +43,7 @@ CASES = {
     "sinusoidal129": lambda: w.manufactured_sinusoidal(129),
     "annulus_neumann65": lambda: w.polar_semi_annulus(65, neumann=True),
     "circle129_SE": lambda: _circle_se(129),
+    "rect129x65": lambda: w.manufactured_sinusoidal(129, ny=65),  # dx != dy
 }
 
 
