@@ -247,3 +247,25 @@ def test_physical_permittivity_parity(tomg, name, kind):
     ro = oracle.solve_problem(prob, rel_tol=1e-13, max_cycles=200, eps_phys=ep)
     print(f"  cycles gpu {res.cycles}", flush=True)
     assert rel_err(np_(phi), ro["phi"]) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_jacobi_solve(tomg, precision):
+    """Damped-Jacobi smoothing (omega = 0.8) through a whole solve: FP64 takes
+    the oracle's cycle count and reaches its solution; with FP32 inner cycles
+    the oracle's FP64 residual of the result meets the tolerance."""
+    prob = CASES["circle257"]()
+    p, d = tomg.setup_from_grid(prob, precision=precision, smoother="jacobi")
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=200)
+    assert res.ok
+    s = oracle.setup(prob)
+    st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], prob.dx, prob.dy, s["dir"])
+    b0 = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], prob.phi0, s["f"]))
+    rel = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], np_(phi), s["f"])) / b0
+    assert rel <= 1e-10 * (1 + 1e-6), rel
+    print(f"[jacobi] {precision}: cycles {res.cycles}", flush=True)
+    if precision == "fp64":
+        ro = oracle.solve_problem(prob, rel_tol=1e-10, max_cycles=200, smoother=oracle.JACOBI)
+        assert res.cycles == ro["cycles"]
+        assert rel_err(np_(phi), ro["phi"]) <= 1e-10
