@@ -79,6 +79,13 @@ class Request:
         """True when the problem's level-0 operator is a stored stencil."""
         return bool(self.neumann) or bool(self.flux)
 
+    @property
+    def shape(self):
+        """What a problem's workspace depends on: a problem created for one
+        request can be set up again for another of the same shape."""
+        return (self.nx, self.ny, self.dx, self.dy, self.xi0, self.eta0, self.neumann,
+                bool(self.flux))
+
 
 @dataclass
 class Completion:
@@ -110,6 +117,7 @@ class _Resident:
     phi: object
     nbytes: int
     busy: bool = False
+    shape: object = None  # Request.shape of the geometry it was set up for
 
 
 @dataclass
@@ -128,6 +136,8 @@ class TomgBackend:
     """The library as seen by the server: problem creation and setup, warm
     right-hand-side updates and the batched step."""
 
+    reuses = True  # create() can set up an evicted problem of the same shape again
+
     def __init__(self, precision="fp32_ir", nu1=2, nu2=2, ir_inner_cycles=2, device=None):
         import torch
 
@@ -145,12 +155,13 @@ class TomgBackend:
         # coordinates, analytic partials or mask, initial guess and source
         return 8 * req.nx * req.ny * 8
 
-    def create(self, req: Request):
-        """New problem with its coefficient setup queued (checks deferred);
-        returns (problem, phi)."""
-        p = self.tomg.Problem(req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0,
-                              device=self.device, neumann=req.neumann, flux=req.flux,
-                              **self.kw)
+    def create(self, req: Request, reuse=None):
+        """Problem with its coefficient setup queued (checks deferred): a new
+        one, or `reuse` (an evicted problem of the same shape, whose
+        workspace the new setup overwrites); returns (problem, phi)."""
+        p = reuse if reuse is not None else self.tomg.Problem(
+            req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0, device=self.device,
+            neumann=req.neumann, flux=req.flux, **self.kw)
         g = req.geometry()
         rho = req.source()
         if g.get("jac") is not None:
@@ -195,7 +206,7 @@ class Server:
         self.resident: "OrderedDict[Hashable, _Resident]" = OrderedDict()  # LRU order
         self.used = 0
         self.stats = {"admitted": 0, "warm": 0, "cold": 0, "evicted": 0, "steps": 0,
-                      "rejected": 0}
+                      "rejected": 0, "reused": 0}
 
     # -- queue ------------------------------------------------------------
     def submit(self, req: Request):
@@ -206,9 +217,10 @@ class Server:
         return not self.active and not self.queue
 
     # -- memory -----------------------------------------------------------
-    def _evict_for(self, need: int) -> bool:
+    def _evict_for(self, need: int, dropped: Optional[list] = None) -> bool:
         """Evicts idle geometries (least recently used first) until `need`
-        more bytes fit; False if they cannot be made to fit."""
+        more bytes fit; False if they cannot be made to fit.  The (shape,
+        problem) of each evicted geometry is appended to `dropped`."""
         if self.used + need <= self.budget:
             return True
         idle = [r for r in self.resident.values() if not r.busy]
@@ -218,6 +230,8 @@ class Server:
         for r in idle:
             if self.used + need <= self.budget:
                 break
+            if dropped is not None:
+                dropped.append((r.shape, r.problem))
             self._drop(r)
             self.stats["evicted"] += 1
         return True
@@ -256,15 +270,25 @@ class Server:
                         f"request needs {need} bytes, budget {self.budget}")))
                     self.stats["rejected"] += 1
                     continue
-                if not self._evict_for(need + self.backend.transient(req)):
+                dropped = []
+                if not self._evict_for(need + self.backend.transient(req), dropped):
                     self.queue.appendleft(req)  # first come, first served: wait
                     break
+                # a geometry evicted for this request that had the same shape
+                # gives its problem (and workspace) to it instead of a new one
+                reuse = None
+                if getattr(self.backend, "reuses", False):
+                    reuse = next((pb for sh, pb in dropped if sh == req.shape), None)
                 try:
-                    prob, phi = self.backend.create(req)
+                    if reuse is not None:
+                        prob, phi = self.backend.create(req, reuse=reuse)
+                        self.stats["reused"] += 1
+                    else:
+                        prob, phi = self.backend.create(req)
                 except Exception as e:
                     done.append(self._failed(req, now, e))
                     continue
-                res = _Resident(req.geom, prob, phi, need, busy=True)
+                res = _Resident(req.geom, prob, phi, need, busy=True, shape=req.shape)
                 self.resident[req.geom] = res
                 self.used += need
                 act = _Active(req, res, now, warm_start=False)

@@ -140,3 +140,33 @@ def test_served_neumann_and_circle_mix_equal_alone(env, precision):
         ra = p.solve(phi, rel_tol=1e-10, max_cycles=200)
         assert ra.cycles == c.cycles, (c.rid, ra, c)
         assert bool((phi == c.phi).all()), c.rid
+
+
+def test_served_with_problem_reuse_equal_alone(env):
+    """A budget small enough that most cold requests evict an idle geometry,
+    whose problem is set up again for the new request when the shapes match:
+    every result is still bitwise the solve of the same request alone."""
+    torch, tomg, serve, D = env
+    reqs, descs = stream(D, serve, 24, (65, 129))
+    srv = serve.Server(serve.TomgBackend(precision="fp32_ir"), budget_bytes=6 << 20,
+                       max_active=3, keep_results=True)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.drain()
+    print(f"[serve_reuse] {srv.stats}", flush=True)
+    assert len(done) == len(reqs) and all(c.ok for c in done), [c for c in done if not c.ok]
+    assert srv.stats["reused"] > 0
+    by = {r.rid: r for r in reqs}
+    for c in done:
+        r = by[c.rid]
+        g = r.geometry()
+        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, precision="fp32_ir")
+        rho = r.source()
+        if g["jac"] is not None:
+            p.setup_coeffs(rho, jac=g["jac"], mask=g["mask"])
+        else:
+            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g["mask"])
+        phi = c.phi_start.clone()
+        ra = p.solve(phi, rel_tol=1e-10, max_cycles=100)
+        assert ra.cycles == c.cycles, (c.rid, ra, c)
+        assert bool((phi == c.phi).all()), c.rid

@@ -287,3 +287,30 @@ def test_serving_stream_default_kinds_unchanged():
     assert {d["kind"] for d in a} == {"circle", "sinusoidal"}
     c = w.serving_stream(50, rate=100.0, seed=3, kinds=("circle", "annulus"))
     assert [d["kind"] == "circle" for d in c] == [d["kind"] == "circle" for d in a]
+
+
+def test_evicted_problem_of_the_same_shape_is_reused():
+    """Under memory pressure a geometry evicted for a cold request hands its
+    problem to the request when the shapes match (no new problem); the
+    accounting is unchanged."""
+    class Reusing(FakeBackend):
+        reuses = True
+
+        def create(self, req, reuse=None):
+            p, phi = super().create(req)
+            p.reused_from = None if reuse is None else reuse.req.rid
+            return p, phi
+
+    be = Reusing(rate=0.1, bytes_per_node=10)
+    s = S.Server(be, budget_bytes=10 * 100 * 2, rel_tol=2e-3, clock=Clock())
+    s.submit(req(0))             # shape 10 x 10: 1000 bytes
+    s.submit(req(1))
+    s.drain()                    # both idle and resident: budget full
+    s.submit(req(2))             # same shape: evicts geometry 0 and reuses its problem
+    s.submit(req(3, n=5))        # other shape: evicts geometry 1, new problem
+    s.drain()
+    assert s.stats["reused"] == 1 and s.stats["evicted"] == 2
+    res = {r.key: r for r in s.resident.values()}
+    assert res["g2"].problem.reused_from == 0
+    assert res["g3"].problem.reused_from is None
+    assert s.used == 1000 + 250
