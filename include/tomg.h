@@ -129,7 +129,10 @@ size_t tomg_workspace_bytes(const tomg_config *cfg);
 /* Creates a problem on the current HIP device.  d_ws: caller-owned device
  * workspace of at least tomg_workspace_bytes(cfg) bytes, 256-byte aligned,
  * kept alive until tomg_destroy.  stream: a hipStream_t (NULL = the null
- * stream).  Host state only is allocated.  *out is NULL on failure. */
+ * stream).  Host state only is allocated; the problem's launch arguments
+ * are stored into the workspace by work queued on the stream (no host wait),
+ * so a problem can be created while the stream is busy.  *out is NULL on
+ * failure. */
 tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, void *stream,
                         tomg_problem **out);
 
@@ -239,6 +242,20 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
  * TOMG_ESTATE); runs on the stream of probs[0] and synchronises it. */
 tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,
                             const int32_t *fresh, double *rel_out);
+
+/* tomg_batch_step without the host wait: the same step is queued on the
+ * stream of probs[0] and the call returns; d_rel_out (double[n], device,
+ * caller-owned) receives in stream order the relative residual of input k
+ * at position k.  A server can then prepare the next step's problems on
+ * the host (and queue their setup on the same stream) while this one runs,
+ * and read d_rel_out after synchronising the stream or an event recorded
+ * after this call.  The problems, their iterates and d_rel_out must stay
+ * alive, and must not be freed or given to another call that reads them
+ * from a different stream, until the step has run.  Arguments and errors
+ * as tomg_batch_step (a null d_rel_out is TOMG_EINVAL); device faults of
+ * the step surface at the next synchronising call. */
+tomg_status tomg_batch_launch(tomg_problem *const *probs, double *const *d_phis, int32_t n,
+                              const int32_t *fresh, double *d_rel_out);
 
 /* Numerical grid generation (Section 4.2, eq. 36-37; Section 5.2 for an
  * embedded body): the node coordinates x'(xi, eta), y'(xi, eta) of the

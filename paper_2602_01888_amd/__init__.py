@@ -307,6 +307,29 @@ def batch_step(problems: Sequence[Problem], phis: Sequence[torch.Tensor], fresh:
     return list(rel)
 
 
+def batch_launch(problems: Sequence[Problem], phis: Sequence[torch.Tensor],
+                 fresh: Sequence[bool], rel_out: torch.Tensor):
+    """tomg_batch_launch: queues the step of ``batch_step`` on the stream of
+    problems[0] and returns at once; rel_out (float64 device tensor of at
+    least len(problems) elements) receives the relative residuals in stream
+    order.  The caller keeps the problems, iterates and rel_out alive until
+    the step has run."""
+    lib = _lib.load()
+    n = len(problems)
+    if n == 0:
+        return
+    if not (rel_out.is_cuda and rel_out.dtype == torch.float64 and rel_out.is_contiguous()
+            and rel_out.numel() >= n):
+        raise TomgError(TOMG_EINVAL, "rel_out: contiguous float64 device tensor of >= n elements")
+    hs = (C.c_void_p * n)(*[p._h.value for p in problems])
+    ps = (C.c_void_p * n)(*[_ptr(t, torch.float64, (p.ny, p.nx), "phi").value
+                            for p, t in zip(problems, phis)])
+    fr = (C.c_int32 * n)(*[1 if f else 0 for f in fresh])
+    st = lib.tomg_batch_launch(hs, ps, n, fr, C.c_void_p(rel_out.data_ptr()))
+    if st != TOMG_OK:
+        raise TomgError(st, "tomg_batch_launch")
+
+
 def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None):
     """Device copy of src into dst with the library's STREAM-style kernel."""
     lib = _lib.load()

@@ -24,7 +24,7 @@ EXPORTS = ["tomg_config_default", "tomg_num_levels", "tomg_workspace_bytes", "to
            "tomg_destroy", "tomg_last_error", "tomg_set_stream", "setup_coeffs",
            "tomg_setup_coeffs_async", "tomg_setup_check",
            "tomg_update_rhs", "vcycle", "solve", "residual_norm", "tomg_solve_batch",
-           "tomg_batch_step", "tomg_field", "tomg_laplace_grid",
+           "tomg_batch_step", "tomg_batch_launch", "tomg_field", "tomg_laplace_grid",
            "tomg_export", "tomg_level_shape", "tomg_smooth", "tomg_residual", "tomg_profile",
            "tomg_profile_read", "tomg_copy_probe"]
 
@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
                                        C.POINTER(I32), C.POINTER(D), C.POINTER(C.c_int)]),
         "tomg_batch_step": (C.c_int, [C.POINTER(P), C.POINTER(VP), I32, C.POINTER(I32),
                                       C.POINTER(D)]),
+        "tomg_batch_launch": (C.c_int, [C.POINTER(P), C.POINTER(VP), I32, C.POINTER(I32), VP]),
         "tomg_field": (C.c_int, [P, VP, VP, VP, VP, VP, VP]),
         "tomg_laplace_grid": (C.c_int, [P, VP, VP, VP, VP, VP, D, I32, C.POINTER(I32)]),
         "tomg_export": (C.c_int, [P, I32, I32, VP]),

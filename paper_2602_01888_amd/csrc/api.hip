@@ -265,10 +265,10 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
   build_pass_args(p);
   build_tail_args(p);
   build_red_args(p);
+  // queued on the stream, no host wait: a problem can be created while the
+  // stream still runs other problems' work
   hipError_t e = hipMemsetAsync(p->scal, 0, kNumSlots * sizeof(double), p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->dargs, &p->hargs, sizeof(ArgsBlob), hipMemcpyHostToDevice, p->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e == hipSuccess) e = upload_args(p);
   if (e != hipSuccess) {
     delete p;
     return TOMG_EDEVICE;
@@ -516,20 +516,21 @@ bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
 }
 
 // Initial norms of the problems idx[0..cnt): |b| from the zero interior
-// start and the residual of the given iterate; relative residuals to out[q].
+// start and the residual of the given iterate; relative residuals to out[q]
+// (to out[idx[q]] with by_index).
 void batch_begin(tomg_problem *const *probs, const int *idx, int cnt, double *const *d_phis,
-                 bool ir, double *out, hipStream_t s) {
+                 bool ir, double *out, hipStream_t s, bool by_index = false) {
   batch_begin_norms(probs, idx, cnt, ir, d_phis, s);
-  batch_finalize(probs, idx, cnt, 2, kSlotB0, false, out, s);
-  batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s);
+  batch_finalize(probs, idx, cnt, 2, kSlotB0, false, out, s, by_index);
+  batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s, by_index);
 }
 
 // One V-cycle (FP64) or one refinement step (FP32 inner cycles) of the
-// problems idx[0..cnt), then their residuals; relative residuals to out[q].
-// Each stage is one launch over all problems that have that level above
-// their single-workgroup tail.
+// problems idx[0..cnt), then their residuals; relative residuals to out[q]
+// (to out[idx[q]] with by_index).  Each stage is one launch over all
+// problems that have that level above their single-workgroup tail.
 void batch_cycle(tomg_problem *const *probs, const int *idx, int cnt, double *const *d_phis,
-                 bool ir, int inner, double *out, hipStream_t s) {
+                 bool ir, int inner, double *out, hipStream_t s, bool by_index = false) {
   int maxlc = 0;
   for (int q = 0; q < cnt; ++q) maxlc = std::max(maxlc, probs[idx[q]]->lc);
   std::vector<int> lvl;
@@ -550,9 +551,9 @@ void batch_cycle(tomg_problem *const *probs, const int *idx, int cnt, double *co
   if (ir) {
     batch_ir_update(probs, idx, cnt, d_phis, s);
     batch_ir_residual(probs, idx, cnt, d_phis, s);
-    batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s);
+    batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s, by_index);
   } else {
-    batch_finalize(probs, idx, cnt, 1, kSlotRes, true, out, s);
+    batch_finalize(probs, idx, cnt, 1, kSlotRes, true, out, s, by_index);
   }
 }
 
@@ -636,10 +637,10 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
   return first;
 }
 
-tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,
-                            const int32_t *fresh, double *rel_out) {
-  if (!probs || !d_phis || !fresh || !rel_out || n < 0 || n > kMaxBatch) return TOMG_EINVAL;
-  if (n == 0) return TOMG_OK;
+// Queues one continuous-batching step; relative residuals to out[k] (device)
+// for input position k.
+static tomg_status batch_enqueue(tomg_problem *const *probs, double *const *d_phis, int32_t n,
+                                 const int32_t *fresh, double *out) {
   if (!batch_uniform(probs, d_phis, n)) {
     for (int k = 0; k < n; ++k)
       if (probs[k] && !probs[k]->ready) return fail(probs[k], TOMG_ESTATE, "batch_step before setup_coeffs");
@@ -650,15 +651,27 @@ tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, i
   const bool ir = lead->cfg.precision == TOMG_FP32_IR;
   std::vector<int> fr, cy;
   for (int k = 0; k < n; ++k) (fresh[k] ? fr : cy).push_back(k);
-  const int nf = (int)fr.size(), nc = (int)cy.size();
-  if (nf) batch_begin(probs, fr.data(), nf, d_phis, ir, lead->bout, s);
-  if (nc)
-    batch_cycle(probs, cy.data(), nc, d_phis, ir, lead->cfg.ir_inner_cycles, lead->bout + nf, s);
-  std::vector<double> h(n);
-  if (!read_back(h.data(), lead->bout, n, s)) return TOMG_EDEVICE;
-  for (int q = 0; q < nf; ++q) rel_out[fr[q]] = h[q];
-  for (int q = 0; q < nc; ++q) rel_out[cy[q]] = h[nf + q];
-  return TOMG_OK;
+  if (!fr.empty()) batch_begin(probs, fr.data(), (int)fr.size(), d_phis, ir, out, s, true);
+  if (!cy.empty())
+    batch_cycle(probs, cy.data(), (int)cy.size(), d_phis, ir, lead->cfg.ir_inner_cycles, out, s,
+                true);
+  return hipGetLastError() == hipSuccess ? TOMG_OK : TOMG_EDEVICE;
+}
+
+tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,
+                            const int32_t *fresh, double *rel_out) {
+  if (!probs || !d_phis || !fresh || !rel_out || n < 0 || n > kMaxBatch) return TOMG_EINVAL;
+  if (n == 0) return TOMG_OK;
+  tomg_status st = batch_enqueue(probs, d_phis, n, fresh, probs[0]->bout);
+  if (st != TOMG_OK) return st;
+  return read_back(rel_out, probs[0]->bout, n, probs[0]->stream) ? TOMG_OK : TOMG_EDEVICE;
+}
+
+tomg_status tomg_batch_launch(tomg_problem *const *probs, double *const *d_phis, int32_t n,
+                              const int32_t *fresh, double *d_rel_out) {
+  if (!probs || !d_phis || !fresh || !d_rel_out || n < 0 || n > kMaxBatch) return TOMG_EINVAL;
+  if (n == 0) return TOMG_OK;
+  return batch_enqueue(probs, d_phis, n, fresh, d_rel_out);
 }
 
 tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, const uint8_t *d_mask,

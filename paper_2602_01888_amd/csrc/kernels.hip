@@ -10,6 +10,7 @@
 // tree, so a residual norm is bitwise reproducible from run to run.
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "tomg_internal.h"
@@ -830,6 +831,19 @@ __global__ void k_zero(T *x, size_t n) {
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x)
     x[c] = T(0);
+}
+
+// Words of host data carried to the device in a kernel's own arguments: the
+// runtime copies the arguments when the launch is queued, so the upload
+// needs neither pinned host memory nor a wait for the stream.
+constexpr int kWordsPerStore = 240;  // 1920 bytes of argument per launch
+struct WordChunk {
+  uint64_t w[kWordsPerStore];
+};
+
+__global__ __launch_bounds__(256) void k_store_words(uint64_t *__restrict__ dst, WordChunk c,
+                                                     int n) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = c.w[threadIdx.x];
 }
 
 // y = fl32(x), n elements.
@@ -1679,6 +1693,20 @@ hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, co
   return hipGetLastError();
 }
 
+hipError_t upload_args(tomg_problem *p) {
+  static_assert(sizeof(ArgsBlob) % sizeof(uint64_t) == 0, "blob of whole words");
+  const int nw = (int)(sizeof(ArgsBlob) / sizeof(uint64_t));
+  const uint64_t *src = reinterpret_cast<const uint64_t *>(&p->hargs);
+  uint64_t *dst = reinterpret_cast<uint64_t *>(p->dargs);
+  WordChunk c;
+  for (int w0 = 0; w0 < nw; w0 += kWordsPerStore) {
+    const int n = std::min(kWordsPerStore, nw - w0);
+    std::memcpy(c.w, src + w0, n * sizeof(uint64_t));
+    hipLaunchKernelGGL(k_store_words, 1, 256, 0, p->stream, dst + w0, c, n);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(tomg_problem *p, double *x, size_t n) {
   hipLaunchKernelGGL((k_zero<double>), grid1(n), 256, 0, p->stream, x, n);
   return hipGetLastError();
@@ -1894,7 +1922,7 @@ void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double
 }
 
 void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kind, int slot,
-                    bool rel, double *out, hipStream_t s) {
+                    bool rel, double *out, hipStream_t s, bool by_index) {
   BatchTab tab;
   for (int k0 = 0; k0 < cnt; k0 += kBatchMax) {
     tab.count = 0;
@@ -1909,7 +1937,7 @@ void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kin
       e.nbx = e.nby = 1;
       e.start = tab.count;
       e.slot = slot;
-      e.out = k;
+      e.out = by_index ? idx[k] : k;
       ++tab.count;
     }
     if (tab.count)

@@ -233,6 +233,8 @@ hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zer
 hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir);
 hipError_t launch_setup_identity(tomg_problem *p, const uint8_t *mask);
 hipError_t launch_zero(tomg_problem *p, double *x, size_t n);
+// Queues the copy of p->hargs into p->dargs on p->stream (no host wait).
+hipError_t upload_args(tomg_problem *p);
 hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, const double *yp,
                         const double *jac, double *ex, double *ey);
 hipError_t launch_smooth0(tomg_problem *p, double *phi, int sweeps);
@@ -267,9 +269,11 @@ void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double
                      hipStream_t s);
 // kind 0: the reduction partials (fin_red), 1: the level-0 up-pass partials
 // (fin_norm), 2: the second half of a two-norm pass (fin_red0); slot: scalar slot written; rel: also write rel and done, and
-// copy the value into out[k] for entry k (out = the leading problem's bout)
+// copy the value into out[k] for entry k (out = the leading problem's bout),
+// or into out[idx[k]] with by_index
 void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kind, int slot,
-                    bool rel, double *out, hipStream_t s);
+                    bool rel, double *out, hipStream_t s,
+                    bool by_index = false);
 
 // Pass timing around level-0 passes (no-ops unless p->prof).
 void prof_begin(tomg_problem *p, int kind);

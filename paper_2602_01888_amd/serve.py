@@ -186,6 +186,27 @@ class TomgBackend:
     def step(self, problems, phis, fresh):
         return self.tomg.batch_step(problems, phis, fresh)
 
+    def launch(self, problems, phis, fresh):
+        """Queues one batched step (tomg_batch_launch) and returns a handle for
+        collect(): the residuals travel to pinned host memory behind the step,
+        and an event marks their arrival."""
+        torch = self.torch
+        stream = problems[0].stream
+        n = len(problems)
+        with torch.cuda.stream(stream):
+            dev = torch.empty(n, dtype=torch.float64, device=self.device)
+            self.tomg.batch_launch(problems, phis, fresh, dev)
+            host = torch.empty(n, dtype=torch.float64, pin_memory=True)
+            host.copy_(dev, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return ev, host, dev
+
+    def collect(self, handle):
+        ev, host, _ = handle
+        ev.synchronize()
+        return host.tolist()
+
     def copy(self, phi):
         return phi.clone()
 
@@ -193,8 +214,12 @@ class TomgBackend:
 class Server:
     def __init__(self, backend, budget_bytes: int = 64 << 30, rel_tol: float = 1e-10,
                  max_cycles: int = 100, max_active: int = 256, keep_results: bool = False,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, pipeline: bool = True):
         self.backend = backend
+        # with a backend that can queue a step without waiting for it, the
+        # next step's admissions are prepared on the host while the device
+        # runs the current one
+        self.pipeline = bool(pipeline) and hasattr(backend, "launch")
         self.budget = int(budget_bytes)
         self.rel_tol = rel_tol
         self.max_cycles = max_cycles
@@ -306,26 +331,45 @@ class Server:
                           error=str(exc))
 
     # -- one step ------------------------------------------------------------
-    def step(self) -> List[Completion]:
-        """Admits what fits, advances every active problem by one step and
-        returns the requests that completed."""
-        done: List[Completion] = []
-        self._admit(self.clock(), done)
-        if not self.active:
-            return done
-        acts = self.active
-        # one batched step per level-0 operator form (on the fly / stored)
-        rels = [math.nan] * len(acts)
+    def _groups(self, acts):
+        """One batched step per level-0 operator form (on the fly / stored):
+        the positions in `acts` of each non-empty group."""
+        out = []
         for form in (False, True):
             grp = [k for k, a in enumerate(acts) if a.req.stored_form == form]
-            if not grp:
-                continue
-            out = self.backend.step([acts[k].res.problem for k in grp],
-                                    [acts[k].res.phi for k in grp], [acts[k].fresh for k in grp])
+            if grp:
+                out.append(grp)
+        return out
+
+    def _args(self, acts, grp):
+        return ([acts[k].res.problem for k in grp], [acts[k].res.phi for k in grp],
+                [acts[k].fresh for k in grp])
+
+    def step(self) -> List[Completion]:
+        """Admits what fits, advances every active problem by one step and
+        returns the requests that completed.  Pipelined, the requests that
+        arrive meanwhile are admitted (their setups queued) while the step
+        runs on the device, and join the next step."""
+        done: List[Completion] = []
+        if not self.pipeline or not self.active:
+            self._admit(self.clock(), done)
+        if not self.active:
+            return done
+        acts = list(self.active)
+        rels = [math.nan] * len(acts)
+        groups = self._groups(acts)
+        if self.pipeline:
+            handles = [self.backend.launch(*self._args(acts, g)) for g in groups]
+            self._admit(self.clock(), done)
+            outs = [self.backend.collect(h) for h in handles]
+        else:
+            outs = [self.backend.step(*self._args(acts, g)) for g in groups]
+        for grp, out in zip(groups, outs):
             for k, r in zip(grp, out):
                 rels[k] = r
         t = self.clock()
         self.stats["steps"] += 1
+        joined = self.active[len(acts):]  # admitted while the step ran
         keep = []
         for a, r in zip(acts, rels):
             if a.fresh:
@@ -357,7 +401,7 @@ class Server:
             else:
                 self.resident.move_to_end(a.res.key)
             done.append(c)
-        self.active = keep
+        self.active = keep + joined
         return done
 
     # -- drivers ---------------------------------------------------------------

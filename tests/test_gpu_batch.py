@@ -77,3 +77,61 @@ def test_single_problem_batch_and_empty(tomg):
     (r,) = tomg.solve_batch([p], [phi])
     assert r.ok
     assert tomg.solve_batch([], []) == []
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_batch_launch_equals_batch_step(tomg, precision):
+    """tomg_batch_launch queues the step of tomg_batch_step: over a few steps
+    with problems joining late (fresh) the residuals land at the inputs'
+    positions and equal batch_step's, and the iterates are bitwise equal."""
+    import torch
+    probs = mixed_batch(6) + [w.perturbed_circle(129, seed=7)]
+    print(f"[batch_launch] {len(probs)} problems {precision}", flush=True)
+    a = [tomg.setup_from_grid(q, precision=precision) for q in probs]
+    b = [tomg.setup_from_grid(q, precision=precision) for q in probs]
+    pa, pb = [p for p, _ in a], [p for p, _ in b]
+    fa = [d["phi0"].clone() for _, d in a]
+    fb = [d["phi0"].clone() for _, d in b]
+    n = len(probs)
+    fresh = [True] * n
+    for step in range(4):
+        # problems 1 and 4 join at step 2: fresh while the others iterate
+        members = [k for k in range(n) if step >= 2 or k not in (1, 4)]
+        fr = [fresh[k] for k in members]
+        ra = tomg.batch_step([pa[k] for k in members], [fa[k] for k in members], fr)
+        out = torch.full((len(members) + 3,), -1.0, dtype=torch.float64, device="cuda")
+        tomg.batch_launch([pb[k] for k in members], [fb[k] for k in members], fr, out)
+        torch.cuda.synchronize()
+        rb = out.cpu().tolist()
+        assert rb[len(members):] == [-1.0] * 3  # nothing past the n entries
+        assert np.allclose(ra, rb[:len(members)], rtol=1e-12, atol=0), (step, ra, rb)
+        for k in members:
+            fresh[k] = False
+    for x, y in zip(fa, fb):
+        assert bool((x == y).all())
+
+
+def test_batch_launch_errors(tomg):
+    import ctypes as C
+    import torch
+    from paper_2602_01888_amd import _lib
+    p, d = tomg.setup_from_grid(w.perturbed_circle(65, seed=1))
+    phi = d["phi0"].clone()
+    lib = _lib.load()
+    hs = (C.c_void_p * 1)(p._h.value)
+    ps = (C.c_void_p * 1)(phi.data_ptr())
+    fr = (C.c_int32 * 1)(1)
+    assert lib.tomg_batch_launch(hs, ps, 1, fr, None) == tomg.TOMG_EINVAL
+    assert lib.tomg_batch_launch(hs, ps, -1, fr, None) == tomg.TOMG_EINVAL
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    assert lib.tomg_batch_launch(hs, ps, 0, fr, C.c_void_p(out.data_ptr())) == tomg.TOMG_OK
+    with pytest.raises(tomg.TomgError):
+        tomg.batch_launch([p], [phi], [True], torch.zeros(1, dtype=torch.float32, device="cuda"))
+    q = tomg.Problem(65, 65, 1 / 64, 1 / 64)  # no setup: state error, nothing queued
+    with pytest.raises(tomg.TomgError) as e:
+        tomg.batch_launch([q], [phi], [True], out)
+    assert e.value.status == tomg.TOMG_ESTATE
+    tomg.batch_launch([p], [phi], [True], out)
+    torch.cuda.synchronize()
+    (r,) = tomg.batch_step([p], [phi.clone()], [True])
+    assert abs(out.item() - r) <= 1e-12 * abs(r)

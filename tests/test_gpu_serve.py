@@ -170,3 +170,30 @@ def test_served_with_problem_reuse_equal_alone(env):
         ra = p.solve(phi, rel_tol=1e-10, max_cycles=100)
         assert ra.cycles == c.cycles, (c.rid, ra, c)
         assert bool((phi == c.phi).all()), c.rid
+
+
+def test_pipelined_and_serial_servers_agree(env):
+    """The pipelined server (admissions prepared while a step runs, problems
+    created on a busy stream) and the serial one give bitwise the same
+    iterates and cycle counts for every request.  The budget holds every
+    geometry, so each geometry sees the same sequence of requests in both
+    (with evictions, which geometry is resident depends on timing)."""
+    torch, tomg, serve, D = env
+    assert serve.Server(serve.TomgBackend()).pipeline
+    res = {}
+    for pipeline in (True, False):
+        reqs, _ = stream(D, serve, 18, (65, 129, 257))
+        srv = serve.Server(serve.TomgBackend(precision="fp32_ir"), budget_bytes=8 << 30,
+                           max_active=5, keep_results=True, pipeline=pipeline)
+        for r in reqs:
+            srv.submit(r)
+        done = srv.drain()
+        print(f"[serve_pipeline] pipeline={pipeline} {srv.stats}", flush=True)
+        assert len(done) == len(reqs) and all(c.ok for c in done), [c for c in done if not c.ok]
+        res[pipeline] = {c.rid: c for c in done}
+    assert sorted(res[True]) == sorted(res[False])
+    for rid, c in res[True].items():
+        s = res[False][rid]
+        assert c.cycles == s.cycles and c.warm_start == s.warm_start, (rid, c, s)
+        assert bool((c.phi_start == s.phi_start).all()), rid
+        assert bool((c.phi == s.phi).all()), rid

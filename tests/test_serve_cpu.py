@@ -314,3 +314,73 @@ def test_evicted_problem_of_the_same_shape_is_reused():
     assert res["g2"].problem.reused_from == 0
     assert res["g3"].problem.reused_from is None
     assert s.used == 1000 + 250
+
+
+class PipeBackend(FakeBackend):
+    """A backend that queues a step (launch) and waits for it later
+    (collect); the log records the order of the calls."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.log = []
+
+    def create(self, req):
+        self.log.append(("create", req.rid))
+        return super().create(req)
+
+    def launch(self, problems, phis, fresh):
+        self.log.append(("launch", [p.req.rid for p in problems]))
+        return self.step(problems, phis, fresh)
+
+    def collect(self, handle):
+        self.log.append(("collect",))
+        return handle
+
+
+def _mixed_stream(n):
+    out = []
+    for k in range(n):
+        warm = k % 3 == 2
+        out.append(req(k, n=10 + 2 * (k % 4), geom=f"g{k % 5}", warm=warm, arrival=0.1 * k))
+    return out
+
+
+def test_pipelined_admission_runs_while_the_step_is_in_flight():
+    be = PipeBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    assert s.pipeline
+    s.submit(req(0))
+    s.step()  # idle server: admit, then launch
+    s.submit(req(1))
+    s.step()
+    # request 1 was created between the launch and the collect of the step
+    # that advanced request 0, and joined the step after it
+    k = be.log.index(("create", 1))
+    assert be.log[k - 1] == ("launch", [0]) and be.log[k + 1] == ("collect",)
+    s.step()
+    assert be.steps[-1] == [0, 1]
+
+
+def test_pipelined_server_gives_the_serial_results():
+    def run(backend, pipeline):
+        s = S.Server(backend, budget_bytes=4000, rel_tol=2e-3, clock=Clock(), pipeline=pipeline,
+                     max_active=4)
+        done = []
+        for r in _mixed_stream(24):
+            s.submit(r)
+            done += s.step()
+        done += s.drain()
+        return {c.rid: (c.status, c.cycles, c.rel, c.warm_start) for c in done}, s.stats
+
+    serial, st_serial = run(FakeBackend(rate=0.2), False)
+    piped, st_piped = run(PipeBackend(rate=0.2), True)
+    assert sorted(serial) == sorted(piped) == list(range(24))
+    assert serial == piped
+    assert st_serial["evicted"] > 0 and st_piped["evicted"] > 0
+
+
+def test_serial_backend_is_not_pipelined():
+    s = S.Server(FakeBackend(), budget_bytes=10 ** 6, pipeline=True)
+    assert not s.pipeline
+    s = S.Server(PipeBackend(), budget_bytes=10 ** 6, pipeline=False)
+    assert not s.pipeline
