@@ -142,7 +142,10 @@ void tomg_destroy(tomg_problem *p);
 /* Human-readable description of the last error on p (never NULL). */
 const char *tomg_last_error(const tomg_problem *p);
 
-/* Re-targets the problem to another stream (same device). */
+/* Re-targets the problem to another stream (same device).  Waits on the
+ * host for the problem's current stream first, so that the work already
+ * queued there (the argument store of tomg_create, an asynchronous setup)
+ * is complete before later calls run on the new stream. */
 tomg_status tomg_set_stream(tomg_problem *p, void *stream);
 
 /* Coefficient setup (eq. 1, 10-15, 11; numeric Jacobian eq. 39-42), then the

@@ -234,8 +234,9 @@ class Problem:
                                                        "phi"), sweeps), "smooth")
 
     def set_stream(self, stream: torch.cuda.Stream):
-        """tomg_set_stream: later calls run on `stream` (same device); work
-        queued for the problem on the old stream must be ordered before."""
+        """tomg_set_stream: later calls run on `stream` (same device); the
+        call first waits for the problem's old stream, so the work queued
+        there is complete."""
         self._check(self.lib.tomg_set_stream(self._h, C.c_void_p(stream.cuda_stream)),
                     "set_stream")
         self.stream = stream

@@ -290,6 +290,10 @@ const char *tomg_last_error(const tomg_problem *p) {
 
 tomg_status tomg_set_stream(tomg_problem *p, void *stream) {
   if (!p) return TOMG_EINVAL;
+  // work already queued for the problem (the argument store of its create,
+  // an asynchronous setup) runs before anything on the new stream
+  if (hipStreamSynchronize(p->stream) != hipSuccess)
+    return fail(p, TOMG_EDEVICE, "set_stream: the previous stream failed");
   p->stream = (hipStream_t)stream;
   return TOMG_OK;
 }

@@ -214,6 +214,31 @@ def test_set_stream_gives_the_same_solution(tomg):
     assert bool((a == b).all())
 
 
+def test_set_stream_right_after_create(tomg):
+    """A problem created on a busy stream (its argument store still queued
+    behind other work) and moved at once to a second stream solves there
+    bitwise as a problem that never moved."""
+    import torch
+    q = w.perturbed_circle(257, seed=6)
+    ref, d = tomg.setup_from_grid(q)
+    a = d["phi0"].clone()
+    ra = ref.solve(a, rel_tol=1e-10)
+    big = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+    for _ in range(8):  # keep the creating stream busy for a while
+        big.mul_(1.0000001)
+    p = tomg.Problem(q.nx, q.ny, q.dx, q.dy, q.xi0, q.eta0)
+    s = torch.cuda.Stream()
+    p.set_stream(s)
+    with torch.cuda.stream(s):
+        e = tomg.upload(q, "cuda")
+        p.setup_coeffs(e["rho"], xp=e["xp"], yp=e["yp"], mask=e["mask"])
+        b = e["phi0"].clone()
+        rb = p.solve(b, rel_tol=1e-10)
+    torch.cuda.synchronize()
+    assert ra.ok and rb.ok and ra.cycles == rb.cycles, (ra, rb)
+    assert bool((a == b).all())
+
+
 def test_profile_counts_level0_passes(tomg):
     """tomg_profile / tomg_profile_read: one level-0 down and one up pass per
     cycle (cycles queued past convergence are counted too), positive times,
