@@ -733,15 +733,19 @@ __global__ __launch_bounds__(kGX *kGY) void k_coarsen_eps(EpsOp<double> op, cons
   }
 }
 
+constexpr int kInvThreads = 1024, kInvWaves = kInvThreads / 64;
+
 // Coarsest level: index map of the free nodes and the explicit inverse of
 // the coarsest matrix by Gauss-Jordan elimination with partial pivoting (one
 // block).  cidx[ncoarse] receives the unknown count.
-__global__ __launch_bounds__(256) void k_coarse_inverse(const double *st, const uint8_t *dir,
+__global__ __launch_bounds__(kInvThreads) void k_coarse_inverse(const double *st, const uint8_t *dir,
                                                         int nx, int ny, double *inv, int *cidx,
                                                         double *scal) {
   // Gauss-Jordan with partial pivoting on m <= kMaxCoarseUnknowns < 64
-  // unknowns: lane t & 63 owns a column, wave t >> 6 every fourth row; the
-  // pivot search is a shuffle reduction in wave 0
+  // unknowns: lane t & 63 owns a column, wave t >> 6 every kInvWaves-th row
+  // (sixteen waves: three or four rows each on 49 unknowns, so the
+  // elimination of a pivot step is short next to its barriers); the pivot
+  // search is a shuffle reduction in wave 0
   constexpr int M = kMaxCoarseUnknowns;
   __shared__ double A[M][M + 1], B[M][M + 1];
   __shared__ double fac[M], rowa[M], rowb[M];
@@ -758,12 +762,12 @@ __global__ __launch_bounds__(256) void k_coarse_inverse(const double *st, const 
   __syncthreads();
   const int m = sm;
   if (c < m)
-    for (int r = w; r < m; r += 4) {
+    for (int r = w; r < m; r += kInvWaves) {
       A[r][c] = 0.0;
       B[r][c] = (r == c) ? 1.0 : 0.0;
     }
   __syncthreads();
-  for (int q = t; q < n; q += 256) {
+  for (int q = t; q < n; q += kInvThreads) {
     const int row = cid[q];
     if (row < 0) continue;
     const int I = q % nx, J = q / nx;
@@ -806,7 +810,7 @@ __global__ __launch_bounds__(256) void k_coarse_inverse(const double *st, const 
     __syncthreads();
     if (c < m) {
       const double ra = rowa[c], rb = rowb[c];
-      for (int r = w; r < m; r += 4) {
+      for (int r = w; r < m; r += kInvWaves) {
         if (r == k) {
           A[k][c] = ra;
           B[k][c] = rb;
@@ -819,7 +823,7 @@ __global__ __launch_bounds__(256) void k_coarse_inverse(const double *st, const 
     __syncthreads();
   }
   if (c < m)
-    for (int r = w; r < m; r += 4) inv[r * m + c] = B[r][c];
+    for (int r = w; r < m; r += kInvWaves) inv[r * m + c] = B[r][c];
 }
 
 // ---------------------------------------------------------------------------
@@ -1749,7 +1753,7 @@ hipError_t launch_hierarchy(tomg_problem *p) {
                          lc.dir, lc.st, st32);
   }
   const tomg::Level &lc = p->lv[p->L - 1];
-  hipLaunchKernelGGL(k_coarse_inverse, 1, 256, 0, p->stream, lc.st, lc.dir, lc.nx, lc.ny,
+  hipLaunchKernelGGL(k_coarse_inverse, 1, kInvThreads, 0, p->stream, lc.st, lc.dir, lc.nx, lc.ny,
                      p->cinv, p->cidx, p->scal);
   if (p->cfg.smoother == TOMG_ZEBRA_XY)
     // the transposed levels of the y-line sweeps: plane (di, dj) becomes (dj, di)
