@@ -25,6 +25,15 @@ back with the request's first step, whose residual is then non-finite; the
 server asks the backend for the reason, reports it in the completion and
 drops the geometry.
 
+Pipelining.  With a backend that can queue a step without waiting for it
+(``launch``/``collect``; ``TomgBackend`` uses ``tomg_batch_launch``), a
+server step queues the batched step, then admits the requests that arrived
+meanwhile (problem creation, input evaluation and setups, all queued on the
+same stream behind the step), then waits for the step's residuals.  The
+newly admitted requests join the next step.  Only idle geometries are
+evicted or re-used during admission, so nothing the running step reads is
+touched.  ``pipeline=False`` gives the serial order (admit, step, wait).
+
 Warm re-solves.  A request marked warm whose geometry is resident and idle
 skips the coefficient setup and the hierarchy build: only the right-hand
 side is recomputed (``tomg_update_rhs``), and the iteration starts from the
