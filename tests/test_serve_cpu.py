@@ -235,10 +235,21 @@ def test_percentile():
     assert S.percentile([1.0, 2.0], 50) == 1.5
 
 
-def test_deferred_setup_failure_is_diagnosed_and_dropped():
+class _Queued:
+    """Mixin: launch/collect over the backend's step (a pipelined backend)."""
+
+    def launch(self, problems, phis, fresh):
+        return self.step(problems, phis, fresh)
+
+    def collect(self, handle):
+        return handle
+
+
+@pytest.mark.parametrize("pipelined", [False, True])
+def test_deferred_setup_failure_is_diagnosed_and_dropped(pipelined):
     """A setup whose checks fail on the device shows up as a non-finite first
     residual; the server reports the backend's diagnosis and does not keep
-    the geometry for warm re-use."""
+    the geometry for warm re-use (serial and pipelined server)."""
     class DeferredBackend(FakeBackend):
         def step(self, problems, phis, fresh):
             out = super().step(problems, phis, fresh)
@@ -247,8 +258,10 @@ def test_deferred_setup_failure_is_diagnosed_and_dropped():
         def diagnose(self, problem):
             return -3, f"det J <= 0 in request {problem.req.rid}"
 
-    be = DeferredBackend(rate=0.1)
+    cls = type("QueuedDeferred", (_Queued, DeferredBackend), {}) if pipelined else DeferredBackend
+    be = cls(rate=0.1)
     s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    assert s.pipeline == pipelined
     for k in range(3):
         s.submit(req(k))
     by = {c.rid: c for c in s.drain()}
