@@ -96,11 +96,21 @@ class Problem:
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._alloc_stream = torch.cuda.current_stream(self.device)
+        self._mark_stream()
         self._h = C.c_void_p()
         st = self.lib.tomg_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()), nbytes,
                                   C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
         if st != TOMG_OK:
             raise TomgError(st, "tomg_create failed")
+
+    def _mark_stream(self):
+        # the library's work on the problem's stream (from the argument store
+        # of create on) uses the workspace: when that is not the stream the
+        # workspace was allocated on, the allocator must not re-use the
+        # memory before that stream's work has run
+        if self.stream != self._alloc_stream:
+            self.workspace.record_stream(self.stream)
 
     @classmethod
     def from_grid(cls, prob, **kw):
@@ -240,6 +250,7 @@ class Problem:
         self._check(self.lib.tomg_set_stream(self._h, C.c_void_p(stream.cuda_stream)),
                     "set_stream")
         self.stream = stream
+        self._mark_stream()
 
     def profile(self, enable: bool = True):
         self._check(self.lib.tomg_profile(self._h, 1 if enable else 0), "profile")
