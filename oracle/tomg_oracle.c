@@ -857,6 +857,17 @@ double orc_mg_initial_residual(orc_mg *mg, const double *phi, const double *f) {
   return orc_norm2_free(nx, ny, mg->dir[0], mg->r[0]);
 }
 
+/* Relative residual of the stopping test: ||r|| / ||f - A phi0||, phi0 the
+ * Dirichlet data with zeros elsewhere.  When that norm is 0 (phi0 already
+ * solves the problem) the denominator is r0, the residual norm of the
+ * starting iterate, so a warm start is iterated until its own residual has
+ * dropped by the tolerance; a zero residual is 0, a non-finite one stays
+ * non-finite. */
+static double rel_residual(double rn, double b0, double r0) {
+  if (rn == 0.0) return 0.0;
+  return rn / (b0 > 0.0 ? b0 : r0);
+}
+
 int orc_mg_solve(orc_mg *mg, double *phi, const double *f, double rel_tol,
                  int max_cycles, int *cycles_out, double *rel_out, double *hist,
                  int hist_len) {
@@ -866,7 +877,8 @@ int orc_mg_solve(orc_mg *mg, double *phi, const double *f, double rel_tol,
   double rel;
   orc_residual(nx, ny, mg->st[0], mg->dir[0], phi, f, mg->r[0]);
   double rn = orc_norm2_free(nx, ny, mg->dir[0], mg->r[0]);
-  rel = b0 > 0.0 ? rn / b0 : 0.0;
+  const double r0 = rn;
+  rel = rel_residual(rn, b0, r0);
   if (hist && hist_len > 0) hist[0] = rel;
   int status = 1;
   while (1) {
@@ -883,7 +895,7 @@ int orc_mg_solve(orc_mg *mg, double *phi, const double *f, double rel_tol,
     ++cycles;
     orc_residual(nx, ny, mg->st[0], mg->dir[0], phi, f, mg->r[0]);
     rn = orc_norm2_free(nx, ny, mg->dir[0], mg->r[0]);
-    rel = rn / b0;
+    rel = rel_residual(rn, b0, r0);
     if (hist && cycles < hist_len) hist[cycles] = rel;
   }
   *cycles_out = cycles;

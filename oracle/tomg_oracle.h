@@ -116,8 +116,11 @@ const double *orc_mg_stencil(const orc_mg *mg, int l);
 const uint8_t *orc_mg_dir(const orc_mg *mg, int l);
 void orc_mg_vcycle(orc_mg *mg, double *phi, const double *f);
 double orc_mg_initial_residual(orc_mg *mg, const double *phi, const double *f);
-/* Returns 0 when converged, 1 when max_cycles was reached, 2 on a non-finite
- * residual. */
+/* V-cycles from phi (its Dirichlet values held) until the relative
+ * residual ||f - A phi||_2 / ||f - A phi0||_2 over free nodes is <= rel_tol
+ * (phi0: the Dirichlet values with zeros elsewhere; when that norm is 0 the
+ * denominator is the residual norm of the starting phi).  Returns 0 when
+ * converged, 1 when max_cycles was reached, 2 on a non-finite residual. */
 int orc_mg_solve(orc_mg *mg, double *phi, const double *f, double rel_tol,
                  int max_cycles, int *cycles_out, double *rel_out,
                  double *hist, int hist_len);

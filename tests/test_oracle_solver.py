@@ -156,3 +156,24 @@ def test_initial_residual_definition():
     b0 = mg.initial_residual(guess, s["f"])
     r = oracle.residual(st, s["dir"], p.phi0, s["f"])
     assert b0 == pytest.approx(np.sqrt(np.sum(r[s["dir"] == 0] ** 2)), rel=1e-14)
+
+
+def test_stopping_test_when_zero_start_solves_the_problem():
+    """Zero source and zero boundary data: the discrete solution is exactly
+    zero (closed form).  The zero-interior start is converged at once; a
+    non-zero warm start is measured against its own residual (the
+    denominator ||f - A phi0|| is 0), so the multigrid iterates it down to
+    the zero solution instead of returning it unchanged."""
+    prob = w.manufactured_sinusoidal(33)
+    prob.rho = np.zeros_like(prob.rho)
+    prob.phi0 = np.zeros_like(prob.phi0)
+    ro = oracle.solve_problem(prob, rel_tol=1e-10)
+    assert ro["status"] == 0 and ro["cycles"] == 0 and ro["rel"] == 0.0
+    xi, eta = np.meshgrid(np.linspace(0, 1, 33), np.linspace(0, 1, 33))
+    x0 = np.sin(np.pi * xi) * np.sin(np.pi * eta)
+    x0[0, :] = x0[-1, :] = x0[:, 0] = x0[:, -1] = 0.0  # the Dirichlet data stay 0
+    s, mg = ro["setup"], ro["mg"]
+    x, st, cyc, rel, hist = mg.solve(x0, s["f"], 1e-10, 100, hist_len=100)
+    assert st == 0 and cyc > 0 and rel <= 1e-10
+    assert hist[0] == 1.0
+    assert np.max(np.abs(x)) <= 1e-8
