@@ -14,6 +14,8 @@ import numpy as np
 from . import build as _build
 
 GS4, GS_LEX, JACOBI, ZEBRA_X, ZEBRA_XY = 0, 1, 2, 3, 4
+# coarse-grid operators: Galerkin product, or eq. 18 rediscretised per level
+GALERKIN, REDISCRETIZE = 0, 1
 # edges with a homogeneous Neumann condition (bit mask)
 NEU_W, NEU_E, NEU_S, NEU_N = 1, 2, 4, 8
 
@@ -54,6 +56,7 @@ def _load():
         "orc_mg_create": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, d]),
         "orc_mg_create_bc": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, i, d]),
         "orc_mg_create_op": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, i, i, d]),
+        "orc_mg_create_full": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, i, i, i, d]),
         "orc_mg_destroy": (None, [p]),
         "orc_mg_num_levels": (i, [p]),
         "orc_mg_level_shape": (None, [p, i, C.POINTER(i), C.POINTER(i)]),
@@ -284,23 +287,26 @@ def error_norms(a, b):
 # ------------------------------------------------------------ multigrid ----
 
 class MG:
-    """Oracle multigrid hierarchy (Galerkin coarse operators, V(nu1, nu2),
-    direct coarsest solve).  smoother: GS4 (the GPU's ordering, "mirror
-    mode"), GS_LEX (the paper's lexicographic ordering), JACOBI or ZEBRA_X
-    (x-line Gauss-Seidel, even rows then odd rows)."""
+    """Oracle multigrid hierarchy (V(nu1, nu2), direct coarsest solve).
+    smoother: GS4 (the GPU's ordering, "mirror mode"), GS_LEX (the paper's
+    lexicographic ordering), JACOBI or ZEBRA_X (x-line Gauss-Seidel, even
+    rows then odd rows).  coarse_op: GALERKIN (default) or REDISCRETIZE
+    (eq. 18 on each coarse grid with the tensor sampled there; Dirichlet
+    edges and the eq. 18 form only)."""
 
     def __init__(self, exx, exy, eyy, dx, dy, mask=None, nu1=2, nu2=2, smoother=GS4,
-                 omega=0.8, neumann=0, flux=False):
+                 omega=0.8, neumann=0, flux=False, coarse_op=GALERKIN):
         self._keep = [_f64(exx), _f64(exy), _f64(eyy)]
         ny, nx = self._keep[0].shape
         m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         self.nx, self.ny = nx, ny
-        self._h = _load().orc_mg_create_op(nx, ny, dx, dy, _d(self._keep[0]),
-                                           _d(self._keep[1]), _d(self._keep[2]), _u8(m),
-                                           int(neumann), 1 if flux else 0, nu1, nu2, smoother,
-                                           omega)
+        self._h = _load().orc_mg_create_full(nx, ny, dx, dy, _d(self._keep[0]),
+                                             _d(self._keep[1]), _d(self._keep[2]), _u8(m),
+                                             int(neumann), 1 if flux else 0, int(coarse_op),
+                                             nu1, nu2, smoother, omega)
         if not self._h:
-            raise ValueError(f"grid {nx}x{ny} does not coarsen to <= 9x9 nodes")
+            raise ValueError(f"grid {nx}x{ny}: does not coarsen to <= 9x9 nodes, or the "
+                             f"coarse operator does not apply to this problem")
 
     @classmethod
     def from_setup(cls, s, dx, dy, mask=None, **kw):
@@ -396,12 +402,12 @@ def generate_grid(xb, yb, dx, dy, rel_tol=1e-13, max_cycles=200, mask=None, px=N
 
 
 def solve_problem(prob, rel_tol=1e-10, max_cycles=200, smoother=GS4, nu1=2, nu2=2,
-                  eps_phys=None, hist_len=0, flux=False):
+                  eps_phys=None, hist_len=0, flux=False, coarse_op=GALERKIN):
     """Setup plus multigrid solve of a ``workloads.GridProblem`` from its
     ``phi0``.  Returns a dict with phi, cycles, rel, status and the setup."""
     s = setup(prob, eps_phys)
     mg = MG.from_setup(s, prob.dx, prob.dy, mask=prob.mask, nu1=nu1, nu2=nu2,
-                       smoother=smoother, flux=flux)
+                       smoother=smoother, flux=flux, coarse_op=coarse_op)
     phi, status, cycles, rel, hist = mg.solve(prob.phi0, s["f"], rel_tol, max_cycles, hist_len)
     return {"phi": phi, "status": status, "cycles": cycles, "rel": rel, "hist": hist,
             "setup": s, "mg": mg}

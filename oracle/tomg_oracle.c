@@ -736,6 +736,40 @@ orc_mg *orc_mg_create_bc(int nx, int ny, double dx, double dy, const double *exx
 orc_mg *orc_mg_create_op(int nx, int ny, double dx, double dy, const double *exx,
                          const double *exy, const double *eyy, const uint8_t *mask,
                          int neumann, int flux, int nu1, int nu2, int smoother, double omega) {
+  return orc_mg_create_full(nx, ny, dx, dy, exx, exy, eyy, mask, neumann, flux, 0, nu1, nu2,
+                            smoother, omega);
+}
+
+/* Rediscretised coarse level l (Section 3 gives eq. 23's coarse problem but
+ * not its operator; the tensor is computed once on the fine grid and
+ * sampled on the coarser ones): the coarse tensor is the fine tensor at the
+ * coarse node's position -- node (I, J) of level l takes level l-1's value at
+ * (2I, 2J) -- and so is the Dirichlet set (plus the outer ring); the
+ * operator is then eq. 18 itself with the coarse spacings (twice the fine
+ * ones). */
+static void rediscretise_level(int nxf, int nyf, const double *exf, const double *eyf,
+                               const double *ezf, const uint8_t *dirf, int nxc, int nyc,
+                               double dxc, double dyc, double *exc, double *eyc, double *ezc,
+                               uint8_t *dirc, double *stc) {
+  (void)nyf;
+  for (int J = 0; J < nyc; ++J)
+    for (int I = 0; I < nxc; ++I) {
+      size_t c = ID(I, J, nxc), f = ID(2 * I, 2 * J, nxf);
+      exc[c] = exf[f];
+      eyc[c] = eyf[f];
+      ezc[c] = ezf[f];
+      int ring = I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1;
+      dirc[c] = (uint8_t)(ring || dirf[f]);
+    }
+  orc_fine_stencil(nxc, nyc, dxc, dyc, exc, eyc, ezc, dirc, stc);
+}
+
+orc_mg *orc_mg_create_full(int nx, int ny, double dx, double dy, const double *exx,
+                           const double *exy, const double *eyy, const uint8_t *mask,
+                           int neumann, int flux, int coarse_op, int nu1, int nu2, int smoother,
+                           double omega) {
+  /* rediscretisation applies eq. 18 on every level: Dirichlet edges only */
+  if (coarse_op != 0 && (coarse_op != 1 || neumann != 0 || flux != 0)) return NULL;
   orc_mg *mg = (orc_mg *)calloc(1, sizeof(orc_mg));
   mg->L = orc_levels_lim(nx, ny, mg->nx, mg->ny, ORC_MAXL, neumann ? 5 : 9);
   if (mg->L == 0) {
@@ -759,9 +793,31 @@ orc_mg *orc_mg_create_op(int nx, int ny, double dx, double dy, const double *exx
     orc_flux_stencil(nx, ny, dx, dy, exx, exy, eyy, mg->dir[0], mg->st[0]);
   else
     orc_fine_stencil(nx, ny, dx, dy, exx, exy, eyy, mg->dir[0], mg->st[0]);
-  for (int l = 1; l < mg->L; ++l)
-    orc_galerkin(mg->nx[l - 1], mg->ny[l - 1], mg->st[l - 1], mg->dir[l - 1], mg->nx[l],
-                 mg->ny[l], mg->st[l], mg->dir[l]);
+  if (coarse_op == 1) {
+    /* the tensor of the level above, starting from the fine grid's */
+    size_t n0 = (size_t)nx * ny;
+    double *t[2][3];
+    for (int q = 0; q < 2; ++q)
+      for (int k = 0; k < 3; ++k) t[q][k] = (double *)malloc(n0 * sizeof(double));
+    memcpy(t[0][0], exx, n0 * sizeof(double));
+    memcpy(t[0][1], exy, n0 * sizeof(double));
+    memcpy(t[0][2], eyy, n0 * sizeof(double));
+    double hx = dx, hy = dy;
+    for (int l = 1; l < mg->L; ++l) {
+      int a = (l - 1) & 1, b = l & 1;
+      hx *= 2.0;
+      hy *= 2.0;
+      rediscretise_level(mg->nx[l - 1], mg->ny[l - 1], t[a][0], t[a][1], t[a][2], mg->dir[l - 1],
+                         mg->nx[l], mg->ny[l], hx, hy, t[b][0], t[b][1], t[b][2], mg->dir[l],
+                         mg->st[l]);
+    }
+    for (int q = 0; q < 2; ++q)
+      for (int k = 0; k < 3; ++k) free(t[q][k]);
+  } else {
+    for (int l = 1; l < mg->L; ++l)
+      orc_galerkin(mg->nx[l - 1], mg->ny[l - 1], mg->st[l - 1], mg->dir[l - 1], mg->nx[l],
+                   mg->ny[l], mg->st[l], mg->dir[l]);
+  }
   /* coarsest dense system over its free nodes */
   int l = mg->L - 1, cx = mg->nx[l], cy = mg->ny[l];
   size_t nc = (size_t)cx * cy;

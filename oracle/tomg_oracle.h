@@ -109,6 +109,15 @@ orc_mg *orc_mg_create_bc(int nx, int ny, double dx, double dy, const double *exx
 orc_mg *orc_mg_create_op(int nx, int ny, double dx, double dy, const double *exx,
                          const double *exy, const double *eyy, const uint8_t *mask,
                          int neumann, int flux, int nu1, int nu2, int smoother, double omega);
+/* As orc_mg_create_op, with the coarse operator chosen: coarse_op 0 the
+ * Galerkin product (1/4) P^T A P with the Dirichlet-aware prolongation, 1
+ * rediscretisation -- eq. 18 on each coarse grid with the tensor and the
+ * Dirichlet set sampled at the coarse nodes (Dirichlet edges and the eq. 18
+ * form only; NULL otherwise). */
+orc_mg *orc_mg_create_full(int nx, int ny, double dx, double dy, const double *exx,
+                           const double *exy, const double *eyy, const uint8_t *mask,
+                           int neumann, int flux, int coarse_op, int nu1, int nu2, int smoother,
+                           double omega);
 void orc_mg_destroy(orc_mg *mg);
 int orc_mg_num_levels(const orc_mg *mg);
 void orc_mg_level_shape(const orc_mg *mg, int l, int *nx, int *ny);
