@@ -51,7 +51,8 @@ typedef enum {
   TOMG_OK = 0,
   TOMG_EINVAL = -1,     /* bad argument: NULL, sizes not coarsenable, tol <= 0 ... */
   TOMG_ENOMEM = -2,     /* workspace smaller than tomg_workspace_bytes() */
-  TOMG_EGEOMETRY = -3,  /* det J <= 0 at a node other than the four corners */
+  TOMG_EGEOMETRY = -3,  /* det J <= 0 at a node other than the four corners, or a
+                           singular coarsest-level matrix (no Dirichlet node) */
   TOMG_ENOCONV = -4,    /* max_cycles reached; phi holds the last iterate */
   TOMG_ENONFINITE = -5, /* NaN/Inf in the coefficients, the source or the residual */
   TOMG_EDEVICE = -6,    /* a HIP runtime call failed */
@@ -93,9 +94,9 @@ typedef struct {
                               Dirichlet); eq. 18 is applied there with a mirror
                               ghost layer (phi and the tensor mirrored across
                               the edge, eps_xy with its sign changed) folded onto
-                              the mirror nodes.  TOMG_FP64, or TOMG_FP32_IR with
-                              TOMG_GS4 (an FP32 copy of the stored stencil feeds
-                              the inner cycles); the level-0
+                              the mirror nodes.  TOMG_FP64, or TOMG_FP32_IR (an
+                              FP32 copy of the stored stencil feeds the inner
+                              cycles; not with TOMG_ZEBRA_XY); the level-0
                               stencil is stored (9 planes more workspace), the
                               level passes run on it and the hierarchy ends in
                               a coarsest grid of at most 5 x 5 nodes; it is
@@ -107,8 +108,8 @@ typedef struct {
                               times cell-centred differences; symmetric, equal
                               to eq. 18 for constant eps, second order.  Like
                               Neumann edges it stores the level-0 stencil, takes
-                              TOMG_FP64 or TOMG_FP32_IR with TOMG_GS4, and is
-                              batched only with other stored-stencil problems */
+                              TOMG_FP64 or TOMG_FP32_IR, and is batched only
+                              with other stored-stencil problems */
   int32_t reserved[1];     /* set to zero */
 } tomg_config;
 
@@ -166,7 +167,8 @@ tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp
                          const double *d_jac, const double *d_eps_phys,
                          const double *d_rho_phys, const uint8_t *d_mask);
 
-/* setup_coeffs without its host synchronisation: the same kernels are queued
+/* setup_coeffs (eq. 1, 10-15, 11; eq. 39-42) without its host
+ * synchronisation: the same kernels are queued
  * on the problem's stream and the call returns at once, so that a caller
  * admitting new geometries while other solves run does not wait for the
  * device.  Argument errors are reported at once; the geometry checks
@@ -196,22 +198,33 @@ tomg_status tomg_update_rhs(tomg_problem *p, const double *d_rho_phys);
  * (FP64 residual, ir_inner_cycles FP32 V-cycles, FP64 update). */
 tomg_status vcycle(tomg_problem *p, double *d_phi);
 
-/* Repeats vcycle until ||f - A phi||_2 / ||f - A phi0||_2 <= rel_tol over
- * free nodes, where phi0 has the Dirichlet values of d_phi and zeros
- * elsewhere; d_phi is the initial guess on entry.  Host outputs (nullable):
- * *cycles_out cycles (refinement steps for TOMG_FP32_IR) taken, *rel_res_out
- * the final relative residual.  Returns TOMG_ENOCONV with phi holding the last
- * iterate if max_cycles is reached, TOMG_ENONFINITE if the residual becomes
- * NaN/Inf. */
+/* Multigrid solve (Section 3): the V-cycle of eq. 19-24 repeated from the
+ * initial guess in d_phi until the residual of eq. 20 has dropped by rel_tol.
+ * The paper stops when the change of the iterate falls below a tolerance
+ * (1e-10) in an unnamed norm; this library reads that test as the relative
+ * residual of the discrete system,
+ *     ||f - A phi||_2 / ||f - A phi0||_2 <= rel_tol   over free nodes,
+ * where phi0 has the Dirichlet values of d_phi and zeros elsewhere (so the
+ * measure does not depend on the initial guess).  When ||f - A phi0|| is 0
+ * (phi0 already solves the problem) the denominator is the residual norm of
+ * the initial guess instead.  Host outputs (nullable): *cycles_out cycles
+ * (refinement steps for TOMG_FP32_IR) taken, *rel_res_out the final relative
+ * residual.  Returns TOMG_ENOCONV with phi holding the last iterate if
+ * max_cycles is reached, TOMG_ENONFINITE if the residual becomes NaN/Inf.
+ * Synchronises the problem's stream. */
 tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cycles,
                   int32_t *cycles_out, double *rel_res_out);
 
-/* abs = ||f - A phi||_2 over free nodes; rel = abs / ||f - A phi0||_2 (0 when
- * the denominator is 0).  Host outputs, nullable. */
+/* Residual norms of eq. 20 (r = f - A phi at free nodes, A the operator of
+ * eq. 18): abs = ||r||_2; rel = abs / ||f - A phi0||_2 as in solve(), with
+ * phi taken as the initial guess when that denominator is 0 (so rel is 1, or
+ * 0 when abs is 0).  Host outputs, nullable; synchronises the problem's
+ * stream. */
 tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
                           double *rel_out);
 
-/* Solves n independent problems together: each V-cycle stage is launched
+/* Solves n independent problems together, each by the multigrid solve of
+ * Section 3 with solve()'s stopping test: each V-cycle stage is launched
  * once across all problems still iterating, on the first problem's stream,
  * and a problem leaves the batch as soon as it converges.  Per-problem host
  * outputs cycles_out[n], rel_out[n], status_out[n] (nullable).  Returns
@@ -246,7 +259,8 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
 tomg_status tomg_batch_step(tomg_problem *const *probs, double *const *d_phis, int32_t n,
                             const int32_t *fresh, double *rel_out);
 
-/* tomg_batch_step without the host wait: the same step is queued on the
+/* tomg_batch_step (one V-cycle of Section 3, eq. 19-24, per problem) without
+ * the host wait: the same step is queued on the
  * stream of probs[0] and the call returns; d_rel_out (double[n], device,
  * caller-owned) receives in stream order the relative residual of input k
  * at position k.  A server can then prepare the next step's problems on

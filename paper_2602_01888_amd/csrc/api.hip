@@ -51,8 +51,6 @@ static bool config_ok(const tomg_config &c) {
   if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
   if (c.neumann < 0 || c.neumann > 15) return false;
   if (c.flux != 0 && c.flux != 1) return false;
-  // a stored level-0 stencil with FP32 inner cycles: the fused passes only
-  if (stored_level0(c) && c.precision != TOMG_FP64 && c.smoother != TOMG_GS4) return false;
   int a[kMaxLevels], b[kMaxLevels];
   return level_shapes(c.nx, c.ny, a, b, c.neumann) > 0;
 }
@@ -267,7 +265,7 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
   build_red_args(p);
   // queued on the stream, no host wait: a problem can be created while the
   // stream still runs other problems' work
-  hipError_t e = hipMemsetAsync(p->scal, 0, kNumSlots * sizeof(double), p->stream);
+  hipError_t e = launch_set_slots(p, (1u << kNumSlots) - 1u, 0.0);
   if (e == hipSuccess) e = upload_args(p);
   if (e != hipSuccess) {
     delete p;
@@ -309,7 +307,9 @@ static tomg_status setup_status(tomg_problem *p, const double *h) {
     return fail(p, TOMG_ENONFINITE, "setup_coeffs: %g non-finite coefficients or sources",
                 h[kSlotBad]);
   if (h[kSlotPivot] != 0.0)
-    return fail(p, TOMG_EGEOMETRY, "setup_coeffs: singular coarsest-level matrix");
+    return fail(p, TOMG_EGEOMETRY,
+                "setup_coeffs: singular coarsest-level matrix (a problem without Dirichlet "
+                "nodes has no unique solution)");
   return TOMG_OK;
 }
 
@@ -335,7 +335,8 @@ static tomg_status setup_launch(tomg_problem *p, const double *d_xp, const doubl
   if (!d_jac && (!d_xp || !d_yp))
     return fail(p, TOMG_EINVAL, "setup_coeffs: need the Jacobian or both coordinate arrays");
   // the setup's own source check replaces that of any earlier update_rhs
-  HIP_TRY(p, hipMemsetAsync(p->scal + kSlotBadRhs, 0, sizeof(double), p->stream));
+  // (the coarsest inverse gives its own singularity verdict)
+  HIP_TRY(p, launch_set_slots(p, 1u << kSlotBadRhs, 0.0));
   HIP_TRY(p, launch_setup(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask));
   HIP_TRY(p, launch_hierarchy(p));
   return TOMG_OK;
@@ -525,8 +526,8 @@ bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
 void batch_begin(tomg_problem *const *probs, const int *idx, int cnt, double *const *d_phis,
                  bool ir, double *out, hipStream_t s, bool by_index = false) {
   batch_begin_norms(probs, idx, cnt, ir, d_phis, s);
-  batch_finalize(probs, idx, cnt, 2, kSlotB0, false, out, s, by_index);
-  batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s, by_index);
+  batch_finalize(probs, idx, cnt, 2, kSlotB0, kRelNone, out, s, by_index);
+  batch_finalize(probs, idx, cnt, 0, kSlotRes, kRelBegin, out, s, by_index);
 }
 
 // One V-cycle (FP64) or one refinement step (FP32 inner cycles) of the
@@ -555,9 +556,9 @@ void batch_cycle(tomg_problem *const *probs, const int *idx, int cnt, double *co
   if (ir) {
     batch_ir_update(probs, idx, cnt, d_phis, s);
     batch_ir_residual(probs, idx, cnt, d_phis, s);
-    batch_finalize(probs, idx, cnt, 0, kSlotRes, true, out, s, by_index);
+    batch_finalize(probs, idx, cnt, 0, kSlotRes, kRelCycle, out, s, by_index);
   } else {
-    batch_finalize(probs, idx, cnt, 1, kSlotRes, true, out, s, by_index);
+    batch_finalize(probs, idx, cnt, 1, kSlotRes, kRelCycle, out, s, by_index);
   }
 }
 
@@ -688,7 +689,7 @@ tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, const
     return fail(p, TOMG_EINVAL, "laplace_grid: needs Dirichlet edges and the eq. 18 form");
   p->ready = false;
   p->unchecked = false;
-  HIP_TRY(p, hipMemsetAsync(p->scal + kSlotBadRhs, 0, sizeof(double), p->stream));
+  HIP_TRY(p, launch_set_slots(p, 1u << kSlotBadRhs, 0.0));
   HIP_TRY(p, launch_setup_identity(p, d_mask));
   HIP_TRY(p, launch_hierarchy(p));
   double h[kNumSlots];

@@ -170,11 +170,24 @@ __device__ double block_reduce(double v) {
   return v;  // valid in thread 0
 }
 
+// Relative residual of the stopping test: v / ||f - A phi0|| (phi0: the
+// Dirichlet values and zero elsewhere).  When that norm is 0 -- the zero
+// interior start is already the solution -- the denominator is the residual
+// norm r0 of the solve's starting iterate, so a warm start still iterates
+// until its residual has dropped by the tolerance.  v = 0 gives 0; a
+// non-finite v stays non-finite.
+__device__ __forceinline__ double rel_residual(double v, double b0, double r0) {
+  if (v == 0.0) return 0.0;
+  return v / (b0 > 0.0 ? b0 : r0);
+}
+
 // One block: fixed-order reduction of n partials into out[0].
-// mode 0 sum, 1 min, 2 max, 3 sqrt(sum).  When rel_slot >= 0 the result is
-// also divided by scal[kSlotB0] into scal[kSlotRel] and compared against
-// scal[kSlotTol] into scal[kSlotDone]; rel == 2 also counts a cycle.  A
-// nonzero *skip makes the launch a no-op.
+// OP 0 sum, 1 min, 2 max; do_sqrt takes the square root of the result.
+// rel == kRelBegin (the initial norms of a solve): out[0] is also recorded as
+// the starting iterate's residual scal[kSlotR0]; rel != kRelNone: the
+// relative residual (rel_residual) into scal[kSlotRel] and its comparison
+// with scal[kSlotTol] into scal[kSlotDone]; kRelCycle also counts a cycle.
+// A nonzero *skip makes the launch a no-op.
 template <int OP>
 __global__ void k_finalize(const double *partials, int n, int stride, double *out, int do_sqrt,
                            double *scal, int rel, const double *skip) {
@@ -185,14 +198,21 @@ __global__ void k_finalize(const double *partials, int n, int stride, double *ou
   if (threadIdx.x == 0) {
     if (do_sqrt) v = sqrt(v);
     out[0] = v;
-    if (rel) {
-      const double b0 = scal[kSlotB0];
-      const double r = b0 > 0.0 ? v / b0 : 0.0;
+    if (rel != kRelNone) {
+      if (rel == kRelBegin) scal[kSlotR0] = v;
+      const double r = rel_residual(v, scal[kSlotB0], scal[kSlotR0]);
       scal[kSlotRel] = r;
       scal[kSlotDone] = (r <= scal[kSlotTol]) ? 1.0 : 0.0;
-      if (rel == 2) scal[kSlotCycles] += 1.0;
+      if (rel == kRelCycle) scal[kSlotCycles] += 1.0;
     }
   }
+}
+
+// scal[slot] = v for the slots named in a bit mask (a fill kernel rather
+// than a memset, so that a captured stream records no memset node).
+__global__ void k_set_slots(double *scal, unsigned mask, double v) {
+  const int k = threadIdx.x;
+  if (k < kNumSlots && ((mask >> k) & 1u)) scal[k] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -780,6 +800,22 @@ __global__ __launch_bounds__(kInvThreads) void k_coarse_inverse(const double *st
       }
   }
   __syncthreads();
+  // scale of the pivot test: the largest diagonal magnitude (wave 0, lanes
+  // over rows); a pivot below 1e-12 of it marks the matrix singular (a
+  // problem without Dirichlet nodes, for example: its operator annihilates
+  // constants on every level)
+  __shared__ double dscale;
+  if (w == 0) {
+    double d = c < m ? fabs(A[c][c]) : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off, 64));
+    if (c == 0) {
+      dscale = d;
+      scal[kSlotPivot] = 0.0;  // this setup's own verdict
+    }
+  }
+  __syncthreads();
+  const double tiny = 1e-12 * dscale;
   for (int k = 0; k < m; ++k) {
     if (w == 0) {
       // largest |A[r][k]| for r >= k, the first on ties
@@ -794,7 +830,7 @@ __global__ __launch_bounds__(kInvThreads) void k_coarse_inverse(const double *st
           p = op;
         }
       }
-      if (c == 0 && v == 0.0) scal[kSlotPivot] = 1.0;
+      if (c == 0 && !(v > tiny)) scal[kSlotPivot] = 1.0;
       if (p != k && c < m) {
         double u = A[k][c]; A[k][c] = A[p][c]; A[p][c] = u;
         u = B[k][c]; B[k][c] = B[p][c]; B[p][c] = u;
@@ -1347,8 +1383,9 @@ __global__ void k_red_b(BatchTab tab) {
 }
 
 // Batched finalize: one block per problem; sqrt of the fixed-order sum into
-// scal[slot]; with rel, the relative residual and the convergence flag too,
-// and a copy into out[e.out].
+// scal[slot]; with rel != kRelNone, the relative residual and the
+// convergence flag too, and a copy into out[e.out]; kRelBegin also records
+// the starting iterate's residual (as k_finalize).
 __global__ void k_finalize_b(BatchTab tab, int rel, double *out) {
   const BatchEntry &e = tab.e[blockIdx.x];
   const FinArgs a = *static_cast<const FinArgs *>(e.args);
@@ -1358,9 +1395,9 @@ __global__ void k_finalize_b(BatchTab tab, int rel, double *out) {
   if (threadIdx.x == 0) {
     v = sqrt(v);
     a.scal[e.slot] = v;
-    if (rel) {
-      const double b0 = a.scal[kSlotB0];
-      double r = b0 > 0.0 ? v / b0 : 0.0;
+    if (rel != kRelNone) {
+      if (rel == kRelBegin) a.scal[kSlotR0] = v;
+      double r = rel_residual(v, a.scal[kSlotB0], a.scal[kSlotR0]);
       // a setup that failed its checks (folded map, non-finite input,
       // singular coarsest matrix) or a non-finite new right-hand side
       // reports a non-finite residual
@@ -1711,6 +1748,11 @@ hipError_t upload_args(tomg_problem *p) {
   return hipGetLastError();
 }
 
+hipError_t launch_set_slots(tomg_problem *p, unsigned mask, double v) {
+  hipLaunchKernelGGL(k_set_slots, 1, 64, 0, p->stream, p->scal, mask, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(tomg_problem *p, double *x, size_t n) {
   hipLaunchKernelGGL((k_zero<double>), grid1(n), 256, 0, p->stream, x, n);
   return hipGetLastError();
@@ -1863,16 +1905,6 @@ hipError_t launch_ir_correct(tomg_problem *p, double *phi) {
   return hipGetLastError();
 }
 
-hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free) {
-  const RedArgs &r = p->hargs.red;
-  if (zero_free)
-    hipLaunchKernelGGL(k_resnorm<true>, r.nblk, kRedThreads, 0, p->stream, r, phi);
-  else
-    hipLaunchKernelGGL(k_resnorm<false>, r.nblk, kRedThreads, 0, p->stream, r, phi);
-  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
-                     p->scal + slot, 1, p->scal, slot == kSlotRes ? 1 : 0, nullptr);
-  return hipGetLastError();
-}
 
 // ---- batched reductions ----------------------------------------------------
 
@@ -1926,7 +1958,7 @@ void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double
 }
 
 void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kind, int slot,
-                    bool rel, double *out, hipStream_t s, bool by_index) {
+                    int rel, double *out, hipStream_t s, bool by_index) {
   BatchTab tab;
   for (int k0 = 0; k0 < cnt; k0 += kBatchMax) {
     tab.count = 0;
@@ -1945,7 +1977,7 @@ void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kin
       ++tab.count;
     }
     if (tab.count)
-      hipLaunchKernelGGL(k_finalize_b, tab.count, kRedThreads, 0, s, tab, rel ? 1 : 0, out);
+      hipLaunchKernelGGL(k_finalize_b, tab.count, kRedThreads, 0, s, tab, rel, out);
   }
 }
 

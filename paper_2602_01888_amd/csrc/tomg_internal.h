@@ -27,8 +27,14 @@ enum Slot {
   kSlotTol = 7,     // stopping tolerance used by the device-side check
   kSlotCycles = 8,  // cycles whose norm was finalized (counted on the device)
   kSlotBadRhs = 9,  // count of non-finite right-hand-side values (update_rhs)
+  kSlotR0 = 10,     // residual norm of the solve's starting iterate (the
+                    // denominator of the relative residual when kSlotB0 is 0)
   kNumSlots = 16
 };
+
+// Modes of the relative-residual bookkeeping of a finalize: none; the
+// initial norms of a solve (also records kSlotR0); after a cycle.
+enum { kRelNone = 0, kRelBegin = 1, kRelCycle = 2 };
 
 struct Level {
   int nx = 0, ny = 0;
@@ -229,10 +235,11 @@ void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *co
 int tail_max_nodes();
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi);
 hipError_t launch_ir_correct(tomg_problem *p, double *phi);
-hipError_t launch_resnorm(tomg_problem *p, const double *phi, int slot, bool zero_free);
 hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir);
 hipError_t launch_setup_identity(tomg_problem *p, const uint8_t *mask);
 hipError_t launch_zero(tomg_problem *p, double *x, size_t n);
+// scal[k] = v for every bit k of mask (a fill kernel on the problem's stream)
+hipError_t launch_set_slots(tomg_problem *p, unsigned mask, double v);
 // Queues the copy of p->hargs into p->dargs on p->stream (no host wait).
 hipError_t upload_args(tomg_problem *p);
 hipError_t launch_field(tomg_problem *p, const double *phi, const double *xp, const double *yp,
@@ -268,12 +275,12 @@ void batch_begin_norms(tomg_problem *const *probs, const int *idx, int cnt, bool
 void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
                      hipStream_t s);
 // kind 0: the reduction partials (fin_red), 1: the level-0 up-pass partials
-// (fin_norm), 2: the second half of a two-norm pass (fin_red0); slot: scalar slot written; rel: also write rel and done, and
-// copy the value into out[k] for entry k (out = the leading problem's bout),
-// or into out[idx[k]] with by_index
+// (fin_norm), 2: the second half of a two-norm pass (fin_red0); slot: scalar
+// slot written; rel (kRel*): also write rel and done, and copy the value into
+// out[k] for entry k (out = the leading problem's bout), or into out[idx[k]]
+// with by_index
 void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kind, int slot,
-                    bool rel, double *out, hipStream_t s,
-                    bool by_index = false);
+                    int rel, double *out, hipStream_t s, bool by_index = false);
 
 // Pass timing around level-0 passes (no-ops unless p->prof).
 void prof_begin(tomg_problem *p, int kind);

@@ -269,3 +269,129 @@ def test_copy_probe_copies_and_checks_alignment(tomg):
     with pytest.raises(tomg.TomgError) as e:
         tomg.copy_probe(src[1:], dst[1:])  # 8-byte offset: not 16-byte aligned
     assert e.value.status == tomg.TOMG_EINVAL
+
+
+# -- singular coarsest matrix; re-setup after a failed setup ----------------
+
+def _disc_mask(prob, r=0.2):
+    rr = np.hypot(prob.xp - 0.5, prob.yp - 0.5)
+    return (rr <= r).astype(np.uint8)
+
+
+def test_singular_coarsest_matrix_then_good_setup(tomg):
+    """All four edges Neumann and no Dirichlet node: the operator annihilates
+    constants on every level, so the coarsest matrix is singular and the
+    setup fails with EGEOMETRY.  The same problem set up again with Dirichlet
+    nodes (a disc held at 0.5) is usable: the verdict of the failed setup
+    does not stick, and the solve matches the oracle."""
+    import torch
+    prob = w.manufactured_sinusoidal(33)
+    prob.neumann = 15
+    p = tomg.Problem.from_grid(prob)
+    d = tomg.upload(prob)
+    print("[singular] 33x33 all-Neumann without Dirichlet nodes", flush=True)
+    with pytest.raises(tomg.TomgError) as e:
+        p.setup_coeffs(d["rho"], jac=d["jac"])
+    assert e.value.status == tomg.TOMG_EGEOMETRY and "singular" in str(e.value)
+    mask = _disc_mask(prob)
+    prob.mask = mask
+    prob.phi0 = np.where(mask == 1, 0.5, 0.0)
+    p.setup_coeffs(d["rho"], jac=d["jac"], mask=torch.tensor(mask, device="cuda"))
+    phi = torch.tensor(prob.phi0, device="cuda")
+    res = p.solve(phi, rel_tol=1e-12, max_cycles=200)
+    assert res.ok
+    ro = oracle.solve_problem(prob, rel_tol=1e-13, max_cycles=400)
+    assert ro["status"] == 0
+    err = np.max(np.abs(phi.cpu().numpy() - ro["phi"])) / np.max(np.abs(ro["phi"]))
+    print(f"  cycles {res.cycles}, error vs oracle {err:.2e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_failed_geometry_then_good_setup(tomg):
+    """A folded map fails its check; the same problem then takes a valid map
+    and solves like a fresh problem, bitwise."""
+    bad = w.manufactured_sinusoidal(33, amp=0.5)
+    good = w.manufactured_sinusoidal(33)
+    p = tomg.Problem.from_grid(good)
+    db, dg = tomg.upload(bad), tomg.upload(good)
+    with pytest.raises(tomg.TomgError) as e:
+        p.setup_coeffs(db["rho"], jac=db["jac"])
+    assert e.value.status == tomg.TOMG_EGEOMETRY
+    p.setup_coeffs(dg["rho"], jac=dg["jac"])
+    a = dg["phi0"].clone()
+    assert p.solve(a).ok
+    q, dq = tomg.setup_from_grid(good)
+    b = dq["phi0"].clone()
+    assert q.solve(b).ok
+    assert bool((a == b).all())
+
+
+# -- stopping test when the zero-interior start is the solution --------------
+
+def _zero_problem(n=65):
+    """Zero source and zero boundary data: ||f - A phi0|| = 0 and the
+    discrete solution is zero at every node."""
+    prob = w.manufactured_sinusoidal(n)
+    prob.rho = np.zeros_like(prob.rho)
+    prob.phi0 = np.zeros_like(prob.phi0)
+    return prob
+
+
+def _warm_start(prob):
+    xi, eta = np.meshgrid(np.linspace(0, 1, prob.nx), np.linspace(0, 1, prob.ny))
+    x0 = np.sin(np.pi * xi) * np.sin(2 * np.pi * eta) * (1 + 0.3 * xi)
+    x0[0, :] = x0[-1, :] = x0[:, 0] = x0[:, -1] = 0.0  # the Dirichlet data stay 0
+    return x0
+
+
+def test_warm_start_on_exact_zero_start(tomg):
+    """||f - A phi0|| = 0 with a non-zero warm start: the relative residual
+    is measured against the warm start's own residual, so the solve iterates
+    (as the oracle does, same cycle count) down to the discrete solution 0
+    instead of returning the warm start unchanged."""
+    import torch
+    prob = _zero_problem()
+    p, d = tomg.setup_from_grid(prob)
+    x0 = _warm_start(prob)
+    phi = torch.tensor(x0, device="cuda")
+    a0, rel0 = p.residual_norm(phi)
+    assert a0 > 0 and rel0 == 1.0
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=100)
+    ro = oracle.solve_problem(prob, rel_tol=1e-10)  # zero start: nothing to do
+    assert ro["cycles"] == 0 and ro["status"] == 0
+    s = ro["setup"]
+    mg = ro["mg"]
+    xo, st, cyc, rel, _ = mg.solve(x0, s["f"], 1e-10, 100)
+    print(f"[zero_start] cycles gpu {res.cycles} oracle {cyc} rel {res.rel:.2e}", flush=True)
+    assert res.ok and st == 0 and res.cycles == cyc and res.cycles > 0
+    assert res.rel == pytest.approx(rel, rel=1e-6)
+    g = phi.cpu().numpy()
+    assert np.max(np.abs(g - xo)) <= 1e-12 * np.max(np.abs(x0))
+    assert np.max(np.abs(g)) <= 1e-8 * np.max(np.abs(x0))
+    # a zero start is converged at once
+    z = torch.zeros_like(phi)
+    rz = p.solve(z, rel_tol=1e-10)
+    assert rz.ok and rz.cycles == 0 and rz.rel == 0.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_warm_start_on_exact_zero_start_batched(tomg, precision):
+    """The same in continuous batching: the fresh step reports relative
+    residual 1 (the warm start against itself), later steps follow solve()
+    bitwise."""
+    import torch
+    prob = _zero_problem()
+    p, d = tomg.setup_from_grid(prob, precision=precision)
+    x0 = torch.tensor(_warm_start(prob), device="cuda")
+    a = x0.clone()
+    rels = tomg.batch_step([p], [a], [True])
+    assert rels[0] == 1.0
+    steps = 0
+    while rels[0] > 1e-10 and steps < 50:
+        rels = tomg.batch_step([p], [a], [False])
+        steps += 1
+    b = x0.clone()
+    res = p.solve(b, rel_tol=1e-10, max_cycles=50)
+    print(f"[zero_start_batch] {precision}: steps {steps} solve cycles {res.cycles}", flush=True)
+    assert res.ok and res.cycles == steps
+    assert bool((a == b).all())

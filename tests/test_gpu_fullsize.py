@@ -185,3 +185,47 @@ def test_largest_grid_8193(tomg, precision):
     assert rel <= 1e-10 * (1 + 1e-6)
     assert abs(rel - r.rel) <= 1e-6 * r.rel
     assert r.cycles <= 14
+
+
+def _first_of_side(side, count=256, base_seed=1000, sides=(65, 129, 257, 513, 1025)):
+    """The first problem of the 256-problem batch with the given side (the
+    seeds of w.batch_mixed)."""
+    for p in range(count):
+        s = base_seed + p
+        if sides[int(np.random.default_rng(s).integers(len(sides)))] == side:
+            return p, w.random_sinusoidal(side, s + 10 ** 6)
+    raise AssertionError(side)
+
+
+def oracle_reference(q):
+    """The oracle's multigrid solution continued to relative residual 1e-13
+    or to its FP64 floor: these problems (sources of width 0.02 on a zero
+    boundary) stagnate at 1e-12 - 3e-12, which is accepted as converged."""
+    ro = oracle.solve_problem(q, rel_tol=1e-13, max_cycles=60)
+    assert ro["status"] == 0 or (ro["status"] == 1 and ro["rel"] <= 1e-11), ro["rel"]
+    return ro["phi"]
+
+
+def test_c4_large_problems_elementwise(tomg):
+    """The batch's 513 x 513 and 1025 x 1025 problems, solved together in
+    mixed precision by tomg_solve_batch, against the oracle's converged
+    multigrid solution node by node: <= 1e-10 at the 1e-10 stopping point
+    and at a tightened tolerance (1e-11; their residual floor is about
+    1e-12)."""
+    import torch
+    picks = [_first_of_side(513), _first_of_side(1025)]
+    qs = [q for _, q in picks]
+    print(f"[fullsize] batch problems {[p for p, _ in picks]} sides "
+          f"{[q.nx for q in qs]}", flush=True)
+    refs = [oracle_reference(q) for q in qs]
+    ps, ds = zip(*[tomg.setup_from_grid(q, precision="fp32_ir") for q in qs])
+    for tol in (1e-10, 1e-11):
+        phis = [d["phi0"].clone() for d in ds]
+        res = tomg.solve_batch(list(ps), phis, rel_tol=tol, max_cycles=100)
+        torch.cuda.synchronize()
+        assert all(r.ok for r in res), res
+        errs = [float(np.max(np.abs(f.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+                for f, ref in zip(phis, refs)]
+        print(f"  tol {tol:.0e}: steps {[r.cycles for r in res]} errors "
+              f"{['%.2e' % e for e in errs]}", flush=True)
+        assert max(errs) <= 1e-10

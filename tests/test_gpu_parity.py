@@ -192,21 +192,27 @@ def test_run_twice_bitwise(tomg):
 
 
 def test_mixed_precision_solution(tomg):
-    """FP32 inner V-cycles inside FP64 iterative refinement reach the same
-    1e-10 relative residual and the FP64 solution."""
+    """FP32 inner V-cycles inside FP64 iterative refinement against the
+    sparse direct solution: the error at the 1e-10 stopping point is
+    reported beside the FP64 path's, and at a tightened tolerance (1e-13,
+    the parity protocol's second step) both are asserted <= 1e-10."""
     prob = w.perturbed_circle(257)
     p64, d = tomg.setup_from_grid(prob)
     p32, _ = tomg.setup_from_grid(prob, precision="fp32_ir")
-    a = d["phi0"].clone()
-    b = d["phi0"].clone()
-    r64 = p64.solve(a, rel_tol=1e-10)
-    r32 = p32.solve(b, rel_tol=1e-10, max_cycles=60)
-    print(f"  fp64 cycles={r64.cycles} ir steps={r32.cycles} rel={r32.rel:.2e}", flush=True)
-    assert r64.ok and r32.ok
     s = oracle.setup(prob)
     st = oracle.fine_stencil(s["exx"], s["exy"], s["eyy"], prob.dx, prob.dy, s["dir"])
     ref = direct.direct_solve(st, s["dir"], s["f"], prob.phi0)
-    assert rel_err(np_(b), ref) <= 1e-9
+    errs = {}
+    for tol in (1e-10, 1e-13):
+        a = d["phi0"].clone()
+        b = d["phi0"].clone()
+        r64 = p64.solve(a, rel_tol=tol, max_cycles=100)
+        r32 = p32.solve(b, rel_tol=tol, max_cycles=100)
+        assert r64.ok and r32.ok
+        errs[tol] = (rel_err(np_(a), ref), rel_err(np_(b), ref))
+        print(f"  tol {tol:.0e}: fp64 cycles={r64.cycles} err={errs[tol][0]:.2e}; "
+              f"ir steps={r32.cycles} err={errs[tol][1]:.2e}", flush=True)
+    assert errs[1e-13][0] <= 1e-10 and errs[1e-13][1] <= 1e-10
 
 
 def _dielectric(prob, kind):

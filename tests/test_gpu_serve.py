@@ -197,3 +197,53 @@ def test_pipelined_and_serial_servers_agree(env):
         assert c.cycles == s.cycles and c.warm_start == s.warm_start, (rid, c, s)
         assert bool((c.phi_start == s.phi_start).all()), rid
         assert bool((c.phi == s.phi).all()), rid
+
+
+def test_served_large_sides(env):
+    """A stream with the serving workload's large sides (1025 and 2049
+    among 129): every result is bitwise the request solved alone, and with
+    the server's tolerance tightened to 1e-11 (these requests' FP64 residual
+    floor is 1e-12 - 7e-12) a 1025 x 1025 request matches the oracle's
+    converged solution node by node to 1e-10."""
+    torch, tomg, serve, D = env
+    descs = w.serving_stream(7, rate=1000.0, seed=2, sides=(129, 1025, 2049))
+    sides = [d["side"] for d in descs]
+    assert 1025 in sides and 2049 in sides, sides
+    reqs = [serve.Request(**D.request_fields(d, "cuda")) for d in descs]
+    print(f"[serve_large] sides {sides}", flush=True)
+    srv = serve.Server(serve.TomgBackend(), budget_bytes=16 << 30, max_active=4,
+                       keep_results=True, rel_tol=1e-11)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.drain()
+    assert len(done) == len(reqs) and all(c.ok for c in done), [c for c in done if not c.ok]
+    by = {r.rid: r for r in reqs}
+    checked = False
+    for c in done:
+        r = by[c.rid]
+        g = r.geometry()
+        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, precision="fp32_ir")
+        rho = r.source()
+        if g["jac"] is not None:
+            p.setup_coeffs(rho, jac=g["jac"], mask=g["mask"])
+        else:
+            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g["mask"])
+        phi = c.phi_start.clone()
+        ra = p.solve(phi, rel_tol=1e-11, max_cycles=100)
+        assert ra.cycles == c.cycles, (c.rid, ra, c)
+        assert bool((phi == c.phi).all()), c.rid
+        if r.nx == 1025 and not checked:
+            gh = {k: (None if v is None else v.cpu().numpy()) for k, v in g.items()}
+            q = w.GridProblem("served", r.nx, r.ny, 0.0, 0.0, r.dx, r.dy, gh["xp"], gh["yp"],
+                              rho.cpu().numpy(), c.phi_start.cpu().numpy(), jac=gh["jac"],
+                              mask=gh["mask"])
+            ro = oracle.solve_problem(q, rel_tol=1e-13, max_cycles=60)
+            # continued to 1e-13 or to the FP64 floor (about 1.5e-12 here)
+            assert ro["status"] == 0 or (ro["status"] == 1 and ro["rel"] <= 1e-11)
+            err = float(np.max(np.abs(c.phi.cpu().numpy() - ro["phi"])) /
+                        np.max(np.abs(ro["phi"])))
+            print(f"  request {c.rid} (1025, warm={c.rid in [d['id'] for d in descs if d['warm']]})"
+                  f": error vs oracle {err:.2e}", flush=True)
+            assert err <= 1e-10
+            checked = True
+    assert checked
