@@ -110,10 +110,21 @@ typedef struct {
                               Neumann edges it stores the level-0 stencil, takes
                               TOMG_FP64 or TOMG_FP32_IR, and is batched only
                               with other stored-stencil problems */
-  int32_t reserved[1];     /* set to zero */
+  int32_t coarse_op;       /* coarse-grid operator of eq. 23 (Section 3 does not
+                              name one): TOMG_GALERKIN (default), the product
+                              (1/4) P^T A P with the bilinear prolongation P
+                              restricted to unknowns; or TOMG_REDISCRETIZE,
+                              eq. 18 itself on each coarse grid (spacings 2^l
+                              dx, 2^l dy) with the tensor of level 0 sampled at
+                              the coarse nodes and the Dirichlet set sampled
+                              likewise (plus the outer ring) -- Dirichlet edges
+                              and the eq. 18 form only (neumann = 0, flux = 0,
+                              not TOMG_ZEBRA_XY).  The discrete solution does
+                              not depend on it; the convergence rate does */
 } tomg_config;
 
 enum { TOMG_NEU_W = 1, TOMG_NEU_E = 2, TOMG_NEU_S = 4, TOMG_NEU_N = 8 };
+enum { TOMG_GALERKIN = 0, TOMG_REDISCRETIZE = 1 };
 
 /* Fills *cfg with the defaults above for an nx x ny grid of spacing dx, dy. */
 void tomg_config_default(tomg_config *cfg, int32_t nx, int32_t ny, double dx, double dy);

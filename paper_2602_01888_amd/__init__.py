@@ -18,8 +18,8 @@ import torch  # noqa: F401  (binds the HIP runtime before the library loads)
 from . import _lib
 from ._lib import (FIELD, STATUS_NAMES, TOMG_EGEOMETRY, TOMG_EINVAL, TOMG_ENOCONV,  # noqa: F401
                    TOMG_ENOMEM, TOMG_ENONFINITE, TOMG_ESTATE, TOMG_FP32_IR, TOMG_FP64,
-                   TOMG_GS4, TOMG_JACOBI, TOMG_ZEBRA_X, TOMG_ZEBRA_XY, TOMG_NEU_E, TOMG_NEU_N, TOMG_NEU_S, TOMG_NEU_W,
-                   TOMG_OK, Config)
+                   TOMG_GS4, TOMG_JACOBI, TOMG_ZEBRA_X, TOMG_ZEBRA_XY, TOMG_NEU_E, TOMG_NEU_N,
+                   TOMG_NEU_S, TOMG_NEU_W, TOMG_GALERKIN, TOMG_REDISCRETIZE, TOMG_OK, Config)
 
 
 class TomgError(RuntimeError):
@@ -30,7 +30,7 @@ class TomgError(RuntimeError):
 
 def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
                 smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, neumann=0,
-                flux=False) -> Config:
+                flux=False, coarse_op="galerkin") -> Config:
     lib = _lib.load()
     cfg = Config()
     lib.tomg_config_default(C.byref(cfg), nx, ny, dx, dy)
@@ -43,6 +43,7 @@ def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=
     cfg.ir_inner_cycles = ir_inner_cycles
     cfg.neumann = int(neumann)
     cfg.flux = 1 if flux else 0
+    cfg.coarse_op = {"galerkin": TOMG_GALERKIN, "rediscretize": TOMG_REDISCRETIZE}[coarse_op]
     return cfg
 
 
@@ -85,10 +86,11 @@ class Problem:
 
     def __init__(self, nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
                  smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, device=None,
-                 stream: Optional[torch.cuda.Stream] = None, neumann=0, flux=False):
+                 stream: Optional[torch.cuda.Stream] = None, neumann=0, flux=False,
+                 coarse_op="galerkin"):
         self.lib = _lib.load()
         self.cfg = make_config(nx, ny, dx, dy, xi0, eta0, precision, nu1, nu2, smoother,
-                               jacobi_omega, ir_inner_cycles, neumann, flux)
+                               jacobi_omega, ir_inner_cycles, neumann, flux, coarse_op)
         self.nx, self.ny = nx, ny
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:

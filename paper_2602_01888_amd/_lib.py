@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "TOMG_OK", -1: "TOMG_EINVAL", -2: "TOMG_ENOMEM", -3: "TOMG_EG
 TOMG_FP64, TOMG_FP32_IR = 0, 1
 TOMG_GS4, TOMG_JACOBI, TOMG_ZEBRA_X, TOMG_ZEBRA_XY = 0, 1, 2, 3
 TOMG_NEU_W, TOMG_NEU_E, TOMG_NEU_S, TOMG_NEU_N = 1, 2, 4, 8
+TOMG_GALERKIN, TOMG_REDISCRETIZE = 0, 1
 FIELD = {"exx": 0, "exy": 1, "eyy": 2, "det": 3, "rhs": 4, "dir": 5, "stencil": 6, "x": 7}
 
 # Every symbol include/tomg.h declares.
@@ -34,7 +35,7 @@ class Config(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("precision", C.c_int32),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32),
                 ("jacobi_omega", C.c_double), ("ir_inner_cycles", C.c_int32),
-                ("neumann", C.c_int32), ("flux", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("neumann", C.c_int32), ("flux", C.c_int32), ("coarse_op", C.c_int32)]
 
 
 _lib = None

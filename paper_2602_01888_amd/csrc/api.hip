@@ -51,6 +51,9 @@ static bool config_ok(const tomg_config &c) {
   if (c.precision == TOMG_FP32_IR && (c.ir_inner_cycles < 1 || c.ir_inner_cycles > 16)) return false;
   if (c.neumann < 0 || c.neumann > 15) return false;
   if (c.flux != 0 && c.flux != 1) return false;
+  if (c.coarse_op != TOMG_GALERKIN && c.coarse_op != TOMG_REDISCRETIZE) return false;
+  // rediscretisation builds eq. 18 on every level: Dirichlet edges only
+  if (c.coarse_op == TOMG_REDISCRETIZE && stored_level0(c)) return false;
   int a[kMaxLevels], b[kMaxLevels];
   return level_shapes(c.nx, c.ny, a, b, c.neumann) > 0;
 }

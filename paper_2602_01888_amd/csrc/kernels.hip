@@ -753,6 +753,46 @@ __global__ __launch_bounds__(kGX *kGY) void k_coarsen_eps(EpsOp<double> op, cons
   }
 }
 
+// Coarse level rediscretised (TOMG_REDISCRETIZE): eq. 18 on the level's own
+// grid, whose spacings are s dx, s dy (s = 2^l; the coefficients cx..hxy
+// come with them), with the tensor of level 0 sampled at the coarse nodes --
+// node (I, J) takes level 0's tensor at (s I, s J) -- and the Dirichlet set
+// sampled the same way, plus the outer ring.  Dirichlet nodes get identity
+// rows.  One thread per coarse node, grid-stride.
+__global__ void k_rediscretize(const double *__restrict__ exx, const double *__restrict__ exy,
+                               const double *__restrict__ eyy, const uint8_t *__restrict__ dir0,
+                               int nx0, int s, int nxc, int nyc, double cx, double cy, double qx,
+                               double qy, double qxy, double hxy, uint8_t *__restrict__ dirc,
+                               double *__restrict__ stc, float *__restrict__ stc32) {
+  const size_t nc = (size_t)nxc * nyc, row = (size_t)s * nx0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int J = (int)(c / (size_t)nxc), I = (int)(c - (size_t)J * nxc);
+    const size_t f = (size_t)J * row + (size_t)s * I;
+    const bool ring = I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1;
+    const bool d = ring || dir0[f];
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (d) {
+      a[4] = 1.0;
+    } else {
+      const double ax = exx[f] * cx, ay = eyy[f] * cy;
+      const double gx = (exx[f + s] - exx[f - s]) * qx + (exy[f + row] - exy[f - row]) * qxy;
+      const double gy = (eyy[f + row] - eyy[f - row]) * qy + (exy[f + s] - exy[f - s]) * qxy;
+      const double k6 = exy[f] * hxy;
+      a[0] = k6;      a[1] = ay - gy; a[2] = -k6;
+      a[3] = ax - gx; a[4] = -2.0 * (ax + ay); a[5] = ax + gx;
+      a[6] = -k6;     a[7] = ay + gy; a[8] = k6;
+    }
+    dirc[c] = d ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) stc[k * nc + c] = a[k];
+    if (stc32) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) stc32[k * nc + c] = (float)a[k];
+    }
+  }
+}
+
 constexpr int kInvThreads = 1024, kInvWaves = kInvThreads / 64;
 
 // Coarsest level: index map of the free nodes and the explicit inverse of
@@ -1786,7 +1826,14 @@ hipError_t launch_hierarchy(tomg_problem *p) {
     const tomg::Level &lf = p->lv[l - 1], &lc = p->lv[l];
     const dim3 grid((lc.nx + kGX - 1) / kGX, (lc.ny + kGY - 1) / kGY);
     float *st32 = f32 ? lc.st32 : nullptr;
-    if (l == 1 && !stored_level0(p->cfg))
+    if (p->cfg.coarse_op == TOMG_REDISCRETIZE) {
+      const double H = p->cfg.dx * (double)(1 << l), K = p->cfg.dy * (double)(1 << l);
+      hipLaunchKernelGGL(k_rediscretize, grid1(lc.n), 256, 0, p->stream, (const double *)p->exx,
+                         (const double *)p->exy, (const double *)p->eyy,
+                         (const uint8_t *)p->lv[0].dir, p->cfg.nx, 1 << l, lc.nx, lc.ny,
+                         1.0 / (H * H), 1.0 / (K * K), 0.25 / (H * H), 0.25 / (K * K),
+                         0.25 / (H * K), 0.5 / (H * K), lc.dir, lc.st, st32);
+    } else if (l == 1 && !stored_level0(p->cfg))
       hipLaunchKernelGGL(k_coarsen_eps, grid, kGX * kGY, 0, p->stream, op64(p), lf.dir, lf.nx,
                          lf.ny, lc.nx, lc.ny, lc.dir, lc.st, st32);
     else

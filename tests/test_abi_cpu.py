@@ -160,3 +160,19 @@ def test_every_declaration_is_documented():
 def test_paper_calls_cite_their_passage(name):
     doc = declaration_comments()[name]
     assert re.search(r"\b(Section \d|eq\. \d)", doc), f"{name} cites no passage"
+
+
+def test_coarse_operator_options(lib):
+    """coarse_op: the Galerkin product (default) or rediscretisation, which
+    applies eq. 18 on every level and so needs Dirichlet edges and the eq. 18
+    form; the workspace is the same either way."""
+    import paper_2602_01888_amd as t
+    g = t.workspace_bytes(cfg(129, 129))
+    assert t.workspace_bytes(cfg(129, 129, coarse_op="rediscretize")) == g
+    assert t.workspace_bytes(cfg(129, 129, coarse_op="rediscretize", precision="fp32_ir")) > g
+    assert t.workspace_bytes(cfg(129, 129, coarse_op="rediscretize", neumann=1)) == 0
+    assert t.workspace_bytes(cfg(129, 129, coarse_op="rediscretize", flux=True)) == 0
+    assert t.workspace_bytes(cfg(129, 129, coarse_op="rediscretize", smoother="zebra_xy")) == 0
+    c = cfg(129, 129)
+    c.coarse_op = 2
+    assert t.workspace_bytes(c) == 0
