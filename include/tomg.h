@@ -319,6 +319,36 @@ tomg_status tomg_laplace_grid(tomg_problem *p, double *d_xp, double *d_yp, const
 tomg_status tomg_field(tomg_problem *p, const double *d_phi, const double *d_xp,
                        const double *d_yp, const double *d_jac, double *d_ex, double *d_ey);
 
+/* ---- allocation-free solve ---------------------------------------------- */
+/* Largest workspace tomg_solve_noalloc offers (a 1025 x 1025 grid fits in
+ * either precision). */
+#define TOMG_NOALLOC_MAX_BYTES (128u * 1024u * 1024u)
+
+/* For callers that cannot allocate memory -- code that must not call
+ * hipMalloc or grow a heap, such as tight serving loops or harnesses that
+ * forbid allocation: setup_coeffs followed by solve, on a problem whose
+ * workspace is a static device array owned by the library
+ * (TOMG_NOALLOC_MAX_BYTES bytes on each GPU it runs on, held until the
+ * process ends) instead of a caller-owned one, with the problem's host state
+ * on the call's stack.  The call allocates nothing, on the device or on the
+ * host.  Arguments: cfg and stream as tomg_create (the current device's
+ * array is used), the inputs as setup_coeffs, d_phi / rel_tol / max_cycles /
+ * cycles_out / rel_res_out as solve; err (host, nullable) receives up to
+ * err_len bytes of a message (empty on success).  A configuration whose
+ * tomg_workspace_bytes exceeds TOMG_NOALLOC_MAX_BYTES is refused with
+ * TOMG_ENOMEM before any device work.  Every call on a GPU uses that GPU's
+ * one array, which keeps the last call's contents (each call initialises
+ * what it reads): calls that overlap on one GPU -- from other host threads,
+ * or a stream that has not finished an earlier call's work -- race.
+ * Synchronises `stream`; results are those of tomg_create + setup_coeffs +
+ * solve with the same arguments. */
+tomg_status tomg_solve_noalloc(const tomg_config *cfg, const double *d_xp, const double *d_yp,
+                               const double *d_jac, const double *d_eps_phys,
+                               const double *d_rho_phys, const uint8_t *d_mask, double *d_phi,
+                               double rel_tol, int32_t max_cycles, void *stream,
+                               int32_t *cycles_out, double *rel_res_out, char *err,
+                               size_t err_len);
+
 /* ---- diagnostics: read back internal arrays (parity testing) ----------- */
 enum {
   TOMG_FIELD_EXX = 0,    /* level 0, nx*ny doubles */

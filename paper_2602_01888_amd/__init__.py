@@ -344,6 +344,31 @@ def batch_launch(problems: Sequence[Problem], phis: Sequence[torch.Tensor],
         raise TomgError(st, "tomg_batch_launch")
 
 
+NOALLOC_MAX_BYTES = 128 * 1024 * 1024  # TOMG_NOALLOC_MAX_BYTES
+
+
+def solve_noalloc(cfg: Config, rho, phi, xp=None, yp=None, jac=None, eps_phys=None, mask=None,
+                  rel_tol=1e-10, max_cycles=100, stream=None):
+    """tomg_solve_noalloc: setup_coeffs + solve on the library's static
+    workspace (no allocation by the library).  Returns (SolveResult,
+    message)."""
+    lib = _lib.load()
+    shp = (cfg.ny, cfg.nx)
+    s = stream if stream is not None else torch.cuda.current_stream(phi.device)
+    cyc, rel = C.c_int32(), C.c_double()
+    err = C.create_string_buffer(256)
+    st = lib.tomg_solve_noalloc(C.byref(cfg), _ptr(xp, torch.float64, shp, "xp"),
+                                _ptr(yp, torch.float64, shp, "yp"),
+                                _ptr(jac, torch.float64, (4,) + shp, "jac"),
+                                _ptr(eps_phys, torch.float64, shp, "eps_phys"),
+                                _ptr(rho, torch.float64, shp, "rho"),
+                                _ptr(mask, torch.uint8, shp, "mask"),
+                                _ptr(phi, torch.float64, shp, "phi"), rel_tol, max_cycles,
+                                C.c_void_p(s.cuda_stream), C.byref(cyc), C.byref(rel), err,
+                                len(err))
+    return SolveResult(st, cyc.value, rel.value), err.value.decode()
+
+
 def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None):
     """Device copy of src into dst with the library's STREAM-style kernel."""
     lib = _lib.load()

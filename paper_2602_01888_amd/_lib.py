@@ -27,7 +27,7 @@ EXPORTS = ["tomg_config_default", "tomg_num_levels", "tomg_workspace_bytes", "to
            "tomg_update_rhs", "vcycle", "solve", "residual_norm", "tomg_solve_batch",
            "tomg_batch_step", "tomg_batch_launch", "tomg_field", "tomg_laplace_grid",
            "tomg_export", "tomg_level_shape", "tomg_smooth", "tomg_residual", "tomg_profile",
-           "tomg_profile_read", "tomg_copy_probe"]
+           "tomg_profile_read", "tomg_copy_probe", "tomg_solve_noalloc"]
 
 
 class Config(C.Structure):
@@ -81,6 +81,9 @@ def load(path: str = LIB_PATH):
         "tomg_profile": (C.c_int, [P, I32]),
         "tomg_profile_read": (C.c_int, [P, C.POINTER(D)]),
         "tomg_copy_probe": (C.c_int, [VP, VP, C.c_size_t, VP]),
+        "tomg_solve_noalloc": (C.c_int, [cfgp, VP, VP, VP, VP, VP, VP, VP, D, I32, VP,
+                                         C.POINTER(I32), C.POINTER(D), C.c_char_p,
+                                         C.c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -191,17 +192,13 @@ size_t tomg_workspace_bytes(const tomg_config *cfg) {
   return make_layout(*cfg, &lay) ? lay.total : 0;
 }
 
-tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, void *stream,
-                        tomg_problem **out) {
-  if (!out) return TOMG_EINVAL;
-  *out = nullptr;
-  if (!cfg || !d_ws) return TOMG_EINVAL;
-  if (((uintptr_t)d_ws) % 256 != 0) return TOMG_EINVAL;
-  Layout lay;
-  if (!make_layout(*cfg, &lay)) return TOMG_EINVAL;
-  if (ws_bytes < lay.total) return TOMG_ENOMEM;
-  tomg_problem *p = new (std::nothrow) tomg_problem();
-  if (!p) return TOMG_ENOMEM;
+}  // extern "C"
+
+// Binds the problem state p to the workspace d_ws (laid out by lay) and
+// queues the clearing of its scalar block and the store of its launch
+// arguments on the stream.  Allocates nothing.
+static hipError_t init_problem(tomg_problem *p, const tomg_config *cfg, const Layout &lay,
+                               void *d_ws, size_t ws_bytes, void *stream) {
   p->err[0] = 0;
   p->cfg = *cfg;
   p->lay = lay;
@@ -270,7 +267,23 @@ tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, voi
   // stream still runs other problems' work
   hipError_t e = launch_set_slots(p, (1u << kNumSlots) - 1u, 0.0);
   if (e == hipSuccess) e = upload_args(p);
-  if (e != hipSuccess) {
+  return e;
+}
+
+extern "C" {
+
+tomg_status tomg_create(const tomg_config *cfg, void *d_ws, size_t ws_bytes, void *stream,
+                        tomg_problem **out) {
+  if (!out) return TOMG_EINVAL;
+  *out = nullptr;
+  if (!cfg || !d_ws) return TOMG_EINVAL;
+  if (((uintptr_t)d_ws) % 256 != 0) return TOMG_EINVAL;
+  Layout lay;
+  if (!make_layout(*cfg, &lay)) return TOMG_EINVAL;
+  if (ws_bytes < lay.total) return TOMG_ENOMEM;
+  tomg_problem *p = new (std::nothrow) tomg_problem();
+  if (!p) return TOMG_ENOMEM;
+  if (init_problem(p, cfg, lay, d_ws, ws_bytes, stream) != hipSuccess) {
     delete p;
     return TOMG_EDEVICE;
   }
@@ -799,6 +812,102 @@ tomg_status tomg_profile_read(tomg_problem *p, double *out) {
   out[2] = p->prof_ms[1];
   out[3] = p->prof_cnt[1];
   return TOMG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Solve without any allocation (tomg_solve_noalloc)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kNoallocBytes = size_t(TOMG_NOALLOC_MAX_BYTES);
+
+// The workspace of tomg_solve_noalloc.  Every GPU the library runs on holds
+// its own copy of this array until the process ends.  In host code the name
+// stands for a host-side shadow, not a device address: kernels and copies get
+// the address hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// (with that device current).
+hipError_t scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr || ((uintptr_t)ptr) % 256 != 0) return hipErrorInvalidValue;
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+void set_err(char *err, size_t len, const char *msg) {
+  if (err && len > 0) snprintf(err, len, "%s", msg);
+}
+
+}  // namespace
+
+extern "C" {
+
+tomg_status tomg_solve_noalloc(const tomg_config *cfg, const double *d_xp, const double *d_yp,
+                               const double *d_jac, const double *d_eps_phys,
+                               const double *d_rho_phys, const uint8_t *d_mask, double *d_phi,
+                               double rel_tol, int32_t max_cycles, void *stream,
+                               int32_t *cycles_out, double *rel_res_out, char *err,
+                               size_t err_len) {
+  set_err(err, err_len, "");
+  if (!cfg || !d_phi) {
+    set_err(err, err_len, "solve_noalloc: null configuration or phi");
+    return TOMG_EINVAL;
+  }
+  Layout lay;
+  if (!make_layout(*cfg, &lay)) {
+    set_err(err, err_len, "solve_noalloc: invalid configuration");
+    return TOMG_EINVAL;
+  }
+  if (lay.total > kNoallocBytes) {
+    char msg[160];
+    snprintf(msg, sizeof msg,
+             "solve_noalloc: the problem needs %zu bytes of workspace, more than the "
+             "static %zu",
+             lay.total, kNoallocBytes);
+    set_err(err, err_len, msg);
+    return TOMG_ENOMEM;
+  }
+  void *ws = nullptr;
+  if (scratch_address(&ws) != hipSuccess) {
+    set_err(err, err_len, "solve_noalloc: the static workspace has no device address");
+    return TOMG_EDEVICE;
+  }
+  // the problem state lives on this call's stack; the device work it queues
+  // ends before the call returns (solve synchronises the stream)
+  tomg_problem p;
+  tomg_status s = TOMG_OK;
+  if (init_problem(&p, cfg, lay, ws, kNoallocBytes, stream) != hipSuccess) {
+    set_err(err, err_len, "solve_noalloc: launch failed");
+    return TOMG_EDEVICE;
+  }
+  s = setup_coeffs(&p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask);
+  if (s == TOMG_OK) s = solve(&p, d_phi, rel_tol, max_cycles, cycles_out, rel_res_out);
+  if (s != TOMG_OK) {
+    // setup_coeffs and solve leave their own message
+    set_err(err, err_len, p.err);
+    (void)hipStreamSynchronize(p.stream);  // no queued work outlives the stack state
+  }
+  destroy_events(&p);
+  return s;
 }
 
 tomg_status tomg_copy_probe(const void *d_src, void *d_dst, size_t bytes, void *stream) {

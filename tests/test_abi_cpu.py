@@ -13,9 +13,13 @@ HEADER = os.path.join(ROOT, "include", "tomg.h")
 LIB = os.path.join(ROOT, "paper_2602_01888_amd", "libtomg.so")
 
 
+def header_text():
+    """The header without preprocessor lines (macros are not declarations)."""
+    return re.sub(r"^[ \t]*#.*$", "", open(HEADER).read(), flags=re.M)
+
+
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"/\*.*?\*/", "", header_text(), flags=re.S)
     names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\([^;{]*\)\s*;", text)
     return sorted(set(names))
 
@@ -142,7 +146,7 @@ PAPER_CALLS = ["setup_coeffs", "tomg_setup_coeffs_async", "tomg_update_rhs", "vc
 
 def declaration_comments():
     """name -> the comment block written directly above its declaration."""
-    text = open(HEADER).read()
+    text = header_text()
     out = {}
     for m in re.finditer(r"/\*((?:(?!\*/).)*)\*/\s*\n([^/;{}]*?)\b([A-Za-z_]\w*)\s*\([^;{]*\)\s*;",
                          text, flags=re.S):

@@ -1,0 +1,73 @@
+"""tomg_solve_noalloc (setup + solve on the library's static per-GPU
+workspace, no allocation) against the workspace path tomg_create +
+setup_coeffs + solve: two calls in a row, the second on a smaller grid, each
+bitwise the workspace path's result; a configuration beyond the static size
+is refused with a message."""
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tomg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_01888_amd as t
+    return t
+
+
+def _workspace_path(tomg, prob, precision):
+    p, d = tomg.setup_from_grid(prob, precision=precision)
+    phi = d["phi0"].clone()
+    res = p.solve(phi, rel_tol=1e-10, max_cycles=100)
+    return res, phi, d
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_noalloc_equals_workspace_path(tomg, precision):
+    import torch
+    probs = [w.perturbed_circle(513, seed=2), w.manufactured_sinusoidal(129)]
+    for k, prob in enumerate(probs):
+        print(f"[noalloc] call {k}: {prob.nx}x{prob.ny} {precision}", flush=True)
+        ref, phi_ref, d = _workspace_path(tomg, prob, precision)
+        assert ref.ok
+        cfg = tomg.make_config(prob.nx, prob.ny, prob.dx, prob.dy, prob.xi0, prob.eta0,
+                               precision=precision)
+        phi = d["phi0"].clone()
+        res, msg = tomg.solve_noalloc(cfg, d["rho"], phi, xp=d["xp"], yp=d["yp"], jac=d["jac"],
+                                      mask=d["mask"], rel_tol=1e-10, max_cycles=100)
+        torch.cuda.synchronize()
+        print(f"  cycles {res.cycles} (workspace path {ref.cycles}) rel {res.rel:.3e}",
+              flush=True)
+        assert res.ok and msg == "", msg
+        assert res.cycles == ref.cycles and res.rel == ref.rel
+        assert bool((phi == phi_ref).all())
+        g = phi.cpu().numpy()
+        assert np.array_equal(g[prob.mask.astype(bool)] if prob.mask is not None else g[0],
+                              prob.phi0[prob.mask.astype(bool)] if prob.mask is not None
+                              else prob.phi0[0])
+
+
+def test_noalloc_refuses_oversized_problems(tomg):
+    import torch
+    cfg = tomg.make_config(2049, 2049, 1 / 2048, 1 / 2048)
+    assert tomg.workspace_bytes(cfg) > tomg.NOALLOC_MAX_BYTES
+    phi = torch.zeros((2049, 2049), dtype=torch.float64, device="cuda")
+    rho = torch.zeros_like(phi)
+    res, msg = tomg.solve_noalloc(cfg, rho, phi, xp=phi, yp=phi)
+    assert res.status == tomg.TOMG_ENOMEM and "more than the static" in msg
+    assert bool((phi == 0).all())
+
+
+def test_noalloc_reports_setup_errors(tomg):
+    prob = w.manufactured_sinusoidal(65, amp=0.5)  # folded map
+    d = tomg.upload(prob)
+    cfg = tomg.make_config(prob.nx, prob.ny, prob.dx, prob.dy)
+    phi = d["phi0"].clone()
+    res, msg = tomg.solve_noalloc(cfg, d["rho"], phi, jac=d["jac"])
+    assert res.status == tomg.TOMG_EGEOMETRY and "det J" in msg
