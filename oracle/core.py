@@ -33,6 +33,7 @@ def _load():
     sz, i, d, p = C.c_size_t, C.c_int, C.c_double, C.c_void_p
     sig = {
         "orc_num_threads": (i, []),
+        "orc_set_threads": (None, [i]),
         "orc_jacobian_numeric": (i, [i, i, d, d, _D, _D, _D, _D, _D, _D]),
         "orc_field": (None, [i, i, d, d, _D, _D, _D, _D, _D, _D, _D]),
         "orc_permittivity": (None, [sz, _D, _D, _D, _D, _D, _D, _D, _D, _D]),
@@ -97,6 +98,11 @@ def _f64(a):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the calling host thread's later oracle calls."""
+    _load().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- setup ----

@@ -36,6 +36,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the calling host thread's later parallel loops (the results do
+ * not depend on it: the loops run over independent nodes). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Section 2: Jacobian, permittivity, charge                                 */
 /* ------------------------------------------------------------------------ */

@@ -30,6 +30,7 @@ enum { ORC_GS4 = 0, ORC_GS_LEX = 1, ORC_JACOBI = 2, ORC_ZEBRA_X = 3, ORC_ZEBRA_X
 enum { ORC_NEU_W = 1, ORC_NEU_E = 2, ORC_NEU_S = 4, ORC_NEU_N = 8 };
 
 int orc_num_threads(void);
+void orc_set_threads(int n);
 
 /* Jacobian by central differences (eq. 39-42) in the interior and
  * second-order one-sided differences on the grid edges.  Needs nx, ny >= 3. */

@@ -517,11 +517,6 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
 // Host side
 // ---------------------------------------------------------------------------
 
-static int env_int(const char *name, int dflt) {
-  const char *s = getenv(name);
-  return (s && *s) ? atoi(s) : dflt;
-}
-
 // Rows per block.  A pass is a set of blocks that each march up their band
 // two rows per step, so its time is about (steps per block) x (rounds of
 // blocks the device needs); halo rows are recomputed by both neighbours.
@@ -529,7 +524,6 @@ static int env_int(const char *name, int dflt) {
 // pass be resident at once (slots = resident blocks per CU x CUs), and on
 // levels above 2M nodes, where the pass is bound by memory traffic, at least
 // three halo depths tall so that halo rows add at most two thirds to it.
-// TOMG_CH_L<level> forces the band of one level (tuning only).
 //
 // In a batch the other problems fill the device, so a problem's passes use
 // taller bands (less halo work): the tallest band up to 128 rows that still
@@ -542,11 +536,7 @@ static int pick_band_batch(int nx, int ny, int W) {
   return CH;
 }
 
-static int pick_band(int nx, int ny, int W, int level, long slots, int hv) {
-  char name[32];
-  snprintf(name, sizeof name, "TOMG_CH_L%d", level);
-  const int forced = env_int(name, 0);
-  if (forced > 0) return forced < kMinBand ? kMinBand : forced;
+static int pick_band(int nx, int ny, int W, long slots, int hv) {
   const long bx = (nx + W - 1) / W;
   int CH = (long)nx * ny > (2L << 20) ? 3 * hv + (3 * hv & 1) : kMinBand;
   while (CH < ny && bx * ((ny + CH - 1) / CH) > slots) CH += 2;
@@ -677,11 +667,10 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0,
   const int nu = up ? p->cfg.nu2 : p->cfg.nu1;
   a.W = kBW - 2 * (4 * nu + 2);
   a.CH = batch ? pick_band_batch(a.nx, a.ny, a.W)
-              : pick_band(a.nx, a.ny, a.W, l, pass_slots<T>(l, up, nu, !stored), 2 * nu + 3);
+              : pick_band(a.nx, a.ny, a.W, pass_slots<T>(l, up, nu, !stored), 2 * nu + 3);
   a.nbx = (a.nx + a.W - 1) / a.W;
   a.nby = (a.ny + a.CH - 1) / a.CH;
-  // TOMG_XCD_ORDER=0 keeps the two-dimensional launch order (tuning only)
-  a.xcd_order = (!batch && a.nbx > 1 && env_int("TOMG_XCD_ORDER", 1) != 0) ? 1 : 0;
+  a.xcd_order = (!batch && a.nbx > 1) ? 1 : 0;
   return a;
 }
 
