@@ -188,11 +188,68 @@ tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp
  * setup_coeffs would have returned), by tomg_setup_check, and by
  * tomg_solve_batch / tomg_batch_step, which write a NaN relative residual for
  * a problem whose setup failed (tomg_solve_batch: status TOMG_ENONFINITE for
- * it; tomg_setup_check then names the cause).
+ * it; tomg_setup_check then names the cause).  The coarsest inverse is
+ * launched with the problem's next cycle: a batched step launches those of
+ * all the problems set up this way in one launch (one workgroup each).
  * Inputs must stay valid until the queued work has run (stream order). */
 tomg_status tomg_setup_coeffs_async(tomg_problem *p, const double *d_xp, const double *d_yp,
                                     const double *d_jac, const double *d_eps_phys,
                                     const double *d_rho_phys, const uint8_t *d_mask);
+
+/* ---- analytic maps and Gaussian sources evaluated on the device ---------- */
+/* A request described by a few numbers instead of node arrays: the map from
+ * the computational grid (xi_i = xi0 + i dx, eta_j = eta0 + j dy) to the
+ * physical nodes, and a sum of Gaussian charge densities, evaluated by the
+ * setup kernel itself (no input arrays, no host-to-device copy). */
+enum {
+  TOMG_MAP_SINUSOIDAL = 1,       /* x' = xi + amp s, y' = eta + amp s, s = sin(pi xi) sin(pi eta);
+                                    analytic Jacobian; Dirichlet data 0 on the outer ring */
+  TOMG_MAP_PERTURBED_CIRCLE = 2, /* radial stretch about (cx, cy): with r = |xi - c| and theta
+                                    its polar angle, R(theta) = r_c + pert * sum_{k=2..5}
+                                    coef[k-2] cos(k (theta - phase)); r' = r_in + (r - r_in)
+                                    (R - r_in) / (r_c - r_in) on [r_in, r_c], r' = R + (r - r_c)
+                                    (r_out - R) / (r_out - r_c) on (r_c, r_out], r' = r
+                                    elsewhere, x' = c + r' (cos theta, sin theta); numeric
+                                    Jacobian (eq. 39-42); nodes with r <= r_c are Dirichlet
+                                    nodes of value value_in, the outer ring 0 */
+  TOMG_MAP_POLAR = 3             /* x' = xi cos eta, y' = xi sin eta (eq. 29); analytic
+                                    Jacobian; Dirichlet data value_in on the arc i = 0 and 0
+                                    elsewhere on the ring */
+};
+#define TOMG_MAX_GAUSSIANS 16
+typedef struct {
+  int32_t kind;      /* TOMG_MAP_* */
+  int32_t reserved;  /* set to zero */
+  double amp;        /* TOMG_MAP_SINUSOIDAL */
+  double cx, cy, r_in, r_c, r_out, pert, coef[4], phase;  /* TOMG_MAP_PERTURBED_CIRCLE */
+  double value_in;   /* conductor (TOMG_MAP_PERTURBED_CIRCLE) or inner-arc (TOMG_MAP_POLAR) value */
+} tomg_map_desc;
+typedef struct {
+  int32_t count;     /* Gaussians, 0 .. TOMG_MAX_GAUSSIANS */
+  int32_t reserved;  /* set to zero */
+  double sigma;      /* rho'(x') = sum_m amp[m] exp(-|x' - (cx[m], cy[m])|^2 / (2 sigma^2)) */
+  double amp[TOMG_MAX_GAUSSIANS], cx[TOMG_MAX_GAUSSIANS], cy[TOMG_MAX_GAUSSIANS];
+} tomg_source_desc;
+enum { TOMG_SETUP_ASYNC = 1 };
+
+/* setup_coeffs (eq. 1, 10-15, 11; eq. 39-42 for a numeric Jacobian) for a
+ * map and source given by descriptors, evaluated node by node on the device
+ * (physical permittivity 1).  d_phi_init (device, double[ny][nx], nullable)
+ * receives the map's Dirichlet data and zeros elsewhere -- the initial guess
+ * solve() takes.  flags: TOMG_SETUP_ASYNC queues the work without the host
+ * check, as tomg_setup_coeffs_async; else as setup_coeffs.  The descriptors
+ * are copied; tomg_update_rhs_desc re-uses the map.  TOMG_EINVAL for an
+ * unknown map kind or flag, a perturbed circle without r_in < r_c < r_out,
+ * count outside 0..TOMG_MAX_GAUSSIANS, or count > 0 with sigma <= 0. */
+tomg_status tomg_setup_coeffs_desc(tomg_problem *p, const tomg_map_desc *map,
+                                   const tomg_source_desc *src, double *d_phi_init,
+                                   uint32_t flags);
+
+/* tomg_update_rhs (eq. 11: f = -rho' det J) with the source given by a
+ * descriptor, evaluated at the nodes of the map of the last
+ * tomg_setup_coeffs_desc (TOMG_ESTATE if the problem was set up otherwise).
+ * Asynchronous. */
+tomg_status tomg_update_rhs_desc(tomg_problem *p, const tomg_source_desc *src);
 
 /* Synchronises the problem's stream and returns the status of the checks of
  * the last setup (TOMG_OK, TOMG_EGEOMETRY or TOMG_ENONFINITE, as

@@ -19,7 +19,9 @@ from . import _lib
 from ._lib import (FIELD, STATUS_NAMES, TOMG_EGEOMETRY, TOMG_EINVAL, TOMG_ENOCONV,  # noqa: F401
                    TOMG_ENOMEM, TOMG_ENONFINITE, TOMG_ESTATE, TOMG_FP32_IR, TOMG_FP64,
                    TOMG_GS4, TOMG_JACOBI, TOMG_ZEBRA_X, TOMG_ZEBRA_XY, TOMG_NEU_E, TOMG_NEU_N,
-                   TOMG_NEU_S, TOMG_NEU_W, TOMG_GALERKIN, TOMG_REDISCRETIZE, TOMG_OK, Config)
+                   TOMG_NEU_S, TOMG_NEU_W, TOMG_GALERKIN, TOMG_REDISCRETIZE, TOMG_OK, Config,
+                   TOMG_MAP_PERTURBED_CIRCLE, TOMG_MAP_POLAR, TOMG_MAP_SINUSOIDAL,
+                   TOMG_MAX_GAUSSIANS, MapDesc, SourceDesc)
 
 
 class TomgError(RuntimeError):
@@ -101,6 +103,7 @@ class Problem:
         self._alloc_stream = torch.cuda.current_stream(self.device)
         self._mark_stream()
         self._h = C.c_void_p()
+        self.from_map = False  # the last setup was setup_desc
         st = self.lib.tomg_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()), nbytes,
                                   C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
         if st != TOMG_OK:
@@ -169,7 +172,25 @@ class Problem:
                 _ptr(eps_phys, torch.float64, shp, "eps_phys"),
                 _ptr(rho, torch.float64, shp, "rho"), _ptr(mask, torch.uint8, shp, "mask"))
         fn = self.lib.setup_coeffs if check else self.lib.tomg_setup_coeffs_async
+        self.from_map = False
         self._check(fn(self._h, *args), "setup_coeffs")
+
+    def setup_desc(self, map_desc: MapDesc, source: SourceDesc, phi_init=None, check=True):
+        """tomg_setup_coeffs_desc: setup from a map and a source descriptor
+        (``map_desc()``, ``source_desc()``) evaluated on the device; phi_init
+        (optional, float64 (ny, nx)) receives the Dirichlet data and zeros.
+        check=False queues the work as ``setup_coeffs(check=False)``."""
+        self.from_map = False
+        st = self.lib.tomg_setup_coeffs_desc(
+            self._h, C.byref(map_desc), C.byref(source),
+            _ptr(phi_init, torch.float64, (self.ny, self.nx), "phi_init"),
+            0 if check else _lib.TOMG_SETUP_ASYNC)
+        self._check(st, "setup_coeffs_desc")
+        self.from_map = True
+
+    def update_rhs_desc(self, source: SourceDesc):
+        """tomg_update_rhs_desc: a new source on the map of the last setup_desc."""
+        self._check(self.lib.tomg_update_rhs_desc(self._h, C.byref(source)), "update_rhs_desc")
 
     def setup_check(self):
         """Raises TomgError if the last (asynchronous) setup failed its checks."""
@@ -269,6 +290,34 @@ class Problem:
                                                          "phi"), C.c_void_p(r.data_ptr())),
                     "residual")
         return r
+
+
+def map_desc(kind: str, amp=0.0, centre=(0.5, 0.5), r_in=0.0, r_c=0.0, r_out=0.0, pert=0.0,
+             coef=(0.0, 0.0, 0.0, 0.0), phase=0.0, value_in=0.0) -> MapDesc:
+    """A tomg_map_desc: kind "sinusoidal" (amp), "circle" (perturbed circle:
+    centre, r_in < r_c < r_out, pert, coef of cos 2..5 theta, phase,
+    value_in on the conductor) or "polar" (value_in on the arc i = 0)."""
+    m = MapDesc()
+    m.kind = {"sinusoidal": TOMG_MAP_SINUSOIDAL, "circle": TOMG_MAP_PERTURBED_CIRCLE,
+              "polar": TOMG_MAP_POLAR}[kind]
+    m.amp = float(amp)
+    m.cx, m.cy = float(centre[0]), float(centre[1])
+    m.r_in, m.r_c, m.r_out, m.pert = float(r_in), float(r_c), float(r_out), float(pert)
+    for k in range(4):
+        m.coef[k] = float(coef[k])
+    m.phase, m.value_in = float(phase), float(value_in)
+    return m
+
+
+def source_desc(amps, centres, sigma) -> SourceDesc:
+    """A tomg_source_desc: rho' = sum_m amps[m] exp(-|x' - centres[m]|^2 / (2 sigma^2))."""
+    if len(amps) > TOMG_MAX_GAUSSIANS or len(amps) != len(centres):
+        raise TomgError(TOMG_EINVAL, f"{len(amps)} sources (at most {TOMG_MAX_GAUSSIANS})")
+    s = SourceDesc()
+    s.count, s.sigma = len(amps), float(sigma)
+    for k, (a, c) in enumerate(zip(amps, centres)):
+        s.amp[k], s.cx[k], s.cy[k] = float(a), float(c[0]), float(c[1])
+    return s
 
 
 # Module-level spellings of the C-ABI calls.

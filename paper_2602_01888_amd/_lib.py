@@ -27,7 +27,26 @@ EXPORTS = ["tomg_config_default", "tomg_num_levels", "tomg_workspace_bytes", "to
            "tomg_update_rhs", "vcycle", "solve", "residual_norm", "tomg_solve_batch",
            "tomg_batch_step", "tomg_batch_launch", "tomg_field", "tomg_laplace_grid",
            "tomg_export", "tomg_level_shape", "tomg_smooth", "tomg_residual", "tomg_profile",
-           "tomg_profile_read", "tomg_copy_probe", "tomg_solve_noalloc"]
+           "tomg_profile_read", "tomg_copy_probe", "tomg_solve_noalloc",
+           "tomg_setup_coeffs_desc", "tomg_update_rhs_desc"]
+
+TOMG_MAP_SINUSOIDAL, TOMG_MAP_PERTURBED_CIRCLE, TOMG_MAP_POLAR = 1, 2, 3
+TOMG_MAX_GAUSSIANS = 16
+TOMG_SETUP_ASYNC = 1
+
+
+class MapDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("amp", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("r_in", C.c_double),
+                ("r_c", C.c_double), ("r_out", C.c_double), ("pert", C.c_double),
+                ("coef", C.c_double * 4), ("phase", C.c_double), ("value_in", C.c_double)]
+
+
+class SourceDesc(C.Structure):
+    _fields_ = [("count", C.c_int32), ("reserved", C.c_int32), ("sigma", C.c_double),
+                ("amp", C.c_double * TOMG_MAX_GAUSSIANS),
+                ("cx", C.c_double * TOMG_MAX_GAUSSIANS),
+                ("cy", C.c_double * TOMG_MAX_GAUSSIANS)]
 
 
 class Config(C.Structure):
@@ -81,6 +100,9 @@ def load(path: str = LIB_PATH):
         "tomg_profile": (C.c_int, [P, I32]),
         "tomg_profile_read": (C.c_int, [P, C.POINTER(D)]),
         "tomg_copy_probe": (C.c_int, [VP, VP, C.c_size_t, VP]),
+        "tomg_setup_coeffs_desc": (C.c_int, [P, C.POINTER(MapDesc), C.POINTER(SourceDesc), VP,
+                                             C.c_uint32]),
+        "tomg_update_rhs_desc": (C.c_int, [P, C.POINTER(SourceDesc)]),
         "tomg_solve_noalloc": (C.c_int, [cfgp, VP, VP, VP, VP, VP, VP, VP, D, I32, VP,
                                          C.POINTER(I32), C.POINTER(D), C.c_char_p,
                                          C.c_size_t]),

@@ -342,9 +342,12 @@ static tomg_status pending_setup_status(tomg_problem *p, const double *h) {
   return TOMG_OK;
 }
 
+// Queues the setup kernels.  defer_inverse: the coarsest inverse waits for
+// the problem's next cycle (batched with other problems' in a batch step).
 static tomg_status setup_launch(tomg_problem *p, const double *d_xp, const double *d_yp,
                                 const double *d_jac, const double *d_eps_phys,
-                                const double *d_rho_phys, const uint8_t *d_mask) {
+                                const double *d_rho_phys, const uint8_t *d_mask,
+                                bool defer_inverse) {
   p->ready = false;
   p->unchecked = false;
   if (!d_rho_phys) return fail(p, TOMG_EINVAL, "setup_coeffs: rho is NULL");
@@ -353,8 +356,44 @@ static tomg_status setup_launch(tomg_problem *p, const double *d_xp, const doubl
   // the setup's own source check replaces that of any earlier update_rhs
   // (the coarsest inverse gives its own singularity verdict)
   HIP_TRY(p, launch_set_slots(p, 1u << kSlotBadRhs, 0.0));
+  p->has_map = false;
   HIP_TRY(p, launch_setup(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask));
-  HIP_TRY(p, launch_hierarchy(p));
+  HIP_TRY(p, launch_hierarchy(p, defer_inverse));
+  return TOMG_OK;
+}
+
+static const char *source_desc_error(const tomg_source_desc *src) {
+  if (!src) return "source descriptor is NULL";
+  if (src->count < 0 || src->count > TOMG_MAX_GAUSSIANS)
+    return "source count outside 0..TOMG_MAX_GAUSSIANS";
+  if (src->count > 0 && !(src->sigma > 0.0)) return "source sigma <= 0";
+  return nullptr;
+}
+
+static const char *map_desc_error(const tomg_map_desc *m) {
+  if (!m) return "map descriptor is NULL";
+  if (m->kind == TOMG_MAP_SINUSOIDAL || m->kind == TOMG_MAP_POLAR) return nullptr;
+  if (m->kind != TOMG_MAP_PERTURBED_CIRCLE) return "unknown map kind";
+  if (!(m->r_in < m->r_c && m->r_c < m->r_out))
+    return "perturbed circle needs r_in < r_c < r_out";
+  return nullptr;
+}
+
+// setup_launch for a map and a source given by descriptors.
+static tomg_status setup_desc_launch(tomg_problem *p, const tomg_map_desc *map,
+                                     const tomg_source_desc *src, double *d_phi_init,
+                                     bool defer_inverse) {
+  p->ready = false;
+  p->unchecked = false;
+  p->has_map = false;
+  if (const char *e = map_desc_error(map)) return fail(p, TOMG_EINVAL, "setup_coeffs_desc: %s", e);
+  if (const char *e = source_desc_error(src))
+    return fail(p, TOMG_EINVAL, "setup_coeffs_desc: %s", e);
+  HIP_TRY(p, launch_set_slots(p, 1u << kSlotBadRhs, 0.0));
+  HIP_TRY(p, launch_setup_desc(p, *map, *src, d_phi_init));
+  HIP_TRY(p, launch_hierarchy(p, defer_inverse));
+  p->map = *map;
+  p->has_map = true;
   return TOMG_OK;
 }
 
@@ -364,7 +403,7 @@ tomg_status setup_coeffs(tomg_problem *p, const double *d_xp, const double *d_yp
                          const double *d_jac, const double *d_eps_phys,
                          const double *d_rho_phys, const uint8_t *d_mask) {
   if (!p) return TOMG_EINVAL;
-  tomg_status s = setup_launch(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask);
+  tomg_status s = setup_launch(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask, false);
   if (s != TOMG_OK) return s;
   double h[kNumSlots];
   s = read_scalars(p, h);
@@ -379,10 +418,44 @@ tomg_status tomg_setup_coeffs_async(tomg_problem *p, const double *d_xp, const d
                                     const double *d_jac, const double *d_eps_phys,
                                     const double *d_rho_phys, const uint8_t *d_mask) {
   if (!p) return TOMG_EINVAL;
-  tomg_status s = setup_launch(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask);
+  tomg_status s = setup_launch(p, d_xp, d_yp, d_jac, d_eps_phys, d_rho_phys, d_mask, true);
   if (s != TOMG_OK) return s;
   p->ready = true;
   p->unchecked = true;
+  return TOMG_OK;
+}
+
+tomg_status tomg_setup_coeffs_desc(tomg_problem *p, const tomg_map_desc *map,
+                                   const tomg_source_desc *src, double *d_phi_init,
+                                   uint32_t flags) {
+  if (!p) return TOMG_EINVAL;
+  if (flags & ~(uint32_t)TOMG_SETUP_ASYNC)
+    return fail(p, TOMG_EINVAL, "setup_coeffs_desc: unknown flags %#x", flags);
+  const bool async = flags & TOMG_SETUP_ASYNC;
+  tomg_status s = setup_desc_launch(p, map, src, d_phi_init, async);
+  if (s != TOMG_OK) return s;
+  if (async) {
+    p->ready = true;
+    p->unchecked = true;
+    return TOMG_OK;
+  }
+  double h[kNumSlots];
+  s = read_scalars(p, h);
+  if (s != TOMG_OK) return s;
+  s = setup_status(p, h);
+  if (s != TOMG_OK) return s;
+  p->ready = true;
+  return TOMG_OK;
+}
+
+tomg_status tomg_update_rhs_desc(tomg_problem *p, const tomg_source_desc *src) {
+  if (!p) return TOMG_EINVAL;
+  if (!p->ready) return fail(p, TOMG_ESTATE, "update_rhs_desc before setup_coeffs");
+  if (!p->has_map)
+    return fail(p, TOMG_ESTATE, "update_rhs_desc: the problem was not set up from a map");
+  if (const char *e = source_desc_error(src))
+    return fail(p, TOMG_EINVAL, "update_rhs_desc: %s", e);
+  HIP_TRY(p, launch_update_rhs_desc(p, p->map, *src));
   return TOMG_OK;
 }
 
@@ -390,6 +463,7 @@ tomg_status tomg_setup_check(tomg_problem *p) {
   if (!p) return TOMG_EINVAL;
   if (!p->ready) return fail(p, TOMG_ESTATE, "setup_check before setup_coeffs");
   if (!p->unchecked) return TOMG_OK;
+  HIP_TRY(p, launch_coarse_inverse(p));
   double h[kNumSlots];
   tomg_status s = read_scalars(p, h);
   if (s != TOMG_OK) return s;
@@ -406,6 +480,7 @@ tomg_status tomg_update_rhs(tomg_problem *p, const double *d_rho_phys) {
 tomg_status vcycle(tomg_problem *p, double *d_phi) {
   if (!p || !d_phi) return TOMG_EINVAL;
   if (!p->ready) return fail(p, TOMG_ESTATE, "vcycle before setup_coeffs");
+  HIP_TRY(p, launch_coarse_inverse(p));
   if (p->cfg.precision == TOMG_FP32_IR) {
     HIP_TRY(p, launch_ir_residual(p, d_phi));
     HIP_TRY(p, launch_ir_correct(p, d_phi));
@@ -419,6 +494,7 @@ tomg_status residual_norm(tomg_problem *p, const double *d_phi, double *abs_out,
                           double *rel_out) {
   if (!p || !d_phi) return TOMG_EINVAL;
   if (!p->ready) return fail(p, TOMG_ESTATE, "residual_norm before setup_coeffs");
+  HIP_TRY(p, launch_coarse_inverse(p));  // its singularity verdict is reported here too
   HIP_TRY(p, launch_begin(p, d_phi, false));
   double h[kNumSlots];
   tomg_status s = read_scalars(p, h);
@@ -435,6 +511,7 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
   if (!p || !d_phi) return TOMG_EINVAL;
   if (!(rel_tol > 0.0) || max_cycles < 0) return fail(p, TOMG_EINVAL, "solve: bad tol/max_cycles");
   if (!p->ready) return fail(p, TOMG_ESTATE, "solve before setup_coeffs");
+  HIP_TRY(p, launch_coarse_inverse(p));
   const bool ir = p->cfg.precision == TOMG_FP32_IR;
   // the device-side stopping test compares with this tolerance; the cycle
   // counter starts at zero
@@ -621,6 +698,7 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
   for (int k = 0; k < n; ++k) act[k] = k;
   std::vector<double> hrel(n);
   int na = n;
+  batch_coarse_inverse(probs, act.data(), na, s);
   batch_begin(probs, act.data(), na, d_phis, ir, lead->bout, s);
   if (!read_back(hrel.data(), lead->bout, na, s)) return TOMG_EDEVICE;
   while (true) {
@@ -670,8 +748,11 @@ static tomg_status batch_enqueue(tomg_problem *const *probs, double *const *d_ph
   tomg_problem *lead = probs[0];
   hipStream_t s = lead->stream;
   const bool ir = lead->cfg.precision == TOMG_FP32_IR;
-  std::vector<int> fr, cy;
+  std::vector<int> fr, cy, all(n);
   for (int k = 0; k < n; ++k) (fresh[k] ? fr : cy).push_back(k);
+  // coarsest inverses of setups queued without one: one launch for all
+  for (int k = 0; k < n; ++k) all[k] = k;
+  batch_coarse_inverse(probs, all.data(), n, s);
   if (!fr.empty()) batch_begin(probs, fr.data(), (int)fr.size(), d_phis, ir, out, s, true);
   if (!cy.empty())
     batch_cycle(probs, cy.data(), (int)cy.size(), d_phis, ir, lead->cfg.ir_inner_cycles, out, s,

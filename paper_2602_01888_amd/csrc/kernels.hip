@@ -494,6 +494,188 @@ __global__ void k_setup_identity(int nx, int ny, double *__restrict__ exx,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Setup from descriptors: the map and the sources evaluated at each node
+// ---------------------------------------------------------------------------
+
+// Physical coordinates of computational point (xi, eta) under map m;
+// (cph, sph) = (cos, sin) of the perturbation phase.
+template <int KIND>
+__device__ __forceinline__ void map_point(const tomg_map_desc &m, double cph, double sph,
+                                          double xi, double eta, double &x, double &y) {
+  if constexpr (KIND == TOMG_MAP_SINUSOIDAL) {
+    const double s = sin(M_PI * xi) * sin(M_PI * eta);
+    x = xi + m.amp * s;
+    y = eta + m.amp * s;
+  } else if constexpr (KIND == TOMG_MAP_POLAR) {
+    x = xi * cos(eta);
+    y = xi * sin(eta);
+  } else {
+    const double ux = xi - m.cx, uy = eta - m.cy;
+    const double r = hypot(ux, uy);
+    if (r >= m.r_in && r <= m.r_out) {
+      const double ct = ux / r, st = uy / r;
+      // cos(k (theta - phase)) for k = 2..5 from cos(theta - phase) by the
+      // recurrence cos((k+1) p) = 2 cos p cos(k p) - cos((k-1) p)
+      const double c1 = ct * cph + st * sph;
+      double ckm1 = c1, ck = 2.0 * c1 * c1 - 1.0;
+      double R = m.coef[0] * ck;
+#pragma unroll
+      for (int k = 3; k <= 5; ++k) {
+        const double cn = 2.0 * c1 * ck - ckm1;
+        ckm1 = ck;
+        ck = cn;
+        R += m.coef[k - 2] * ck;
+      }
+      R = m.r_c + m.pert * R;
+      const double rp = r <= m.r_c ? m.r_in + (r - m.r_in) * (R - m.r_in) / (m.r_c - m.r_in)
+                                   : R + (r - m.r_c) * (m.r_out - R) / (m.r_out - m.r_c);
+      x = m.cx + rp * ct;
+      y = m.cy + rp * st;
+    } else {  // outside the stretched annulus the map is the identity
+      x = xi;
+      y = eta;
+    }
+  }
+}
+
+__device__ __forceinline__ double gaussians(const tomg_source_desc &g, double x, double y) {
+  const double inv = 1.0 / (2.0 * g.sigma * g.sigma);
+  double v = 0.0;
+  for (int k = 0; k < g.count; ++k) {
+    const double ax = x - g.cx[k], ay = y - g.cy[k];
+    v += g.amp[k] * exp(-(ax * ax + ay * ay) * inv);
+  }
+  return v;
+}
+
+// Second-order differences of both map coordinates along one axis at index
+// q of n points (central inside, one-sided on the edges, as for node
+// coordinates given as arrays); at(k, x, y) gives the point of index k.
+template <class F>
+__device__ __forceinline__ void diff_axis(F at, int q, int n, double inv2h, double x0,
+                                          double y0, double &gx, double &gy) {
+  double xa, ya, xb, yb;
+  if (q == 0 || q == n - 1) {
+    const int s = q == 0 ? 1 : -1;
+    at(q + s, xa, ya);
+    at(q + 2 * s, xb, yb);
+    gx = s * (-3.0 * x0 + 4.0 * xa - xb) * inv2h;
+    gy = s * (-3.0 * y0 + 4.0 * ya - yb) * inv2h;
+  } else {
+    at(q + 1, xa, ya);
+    at(q - 1, xb, yb);
+    gx = (xa - xb) * inv2h;
+    gy = (ya - yb) * inv2h;
+  }
+}
+
+// k_setup with the map, the sources and the Dirichlet set evaluated from
+// descriptors (physical permittivity 1); phi_init (nullable) receives the
+// map's Dirichlet data and zeros elsewhere.
+template <int KIND>
+__global__ void k_setup_desc(int nx, int ny, double xi0, double eta0, double dx, double dy,
+                             tomg_map_desc m, tomg_source_desc src, double *__restrict__ exx,
+                             double *__restrict__ exy, double *__restrict__ eyy,
+                             double *__restrict__ det, double *__restrict__ f,
+                             uint8_t *__restrict__ dir, float *__restrict__ exx32,
+                             float *__restrict__ exy32, float *__restrict__ eyy32,
+                             double *__restrict__ phi_init, double *__restrict__ partials,
+                             int neumann) {
+  const size_t n = (size_t)nx * ny;
+  const double i2dx = 0.5 / dx, i2dy = 0.5 / dy;
+  const double cph = cos(m.phase), sph = sin(m.phase);
+  double mind = INFINITY, bad = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(c / (size_t)nx), i = (int)(c - (size_t)j * nx);
+    const double xi = xi0 + i * dx, eta = eta0 + j * dy;
+    double x, y, jxx, jxy, jyx, jyy;
+    map_point<KIND>(m, cph, sph, xi, eta, x, y);
+    if constexpr (KIND == TOMG_MAP_SINUSOIDAL) {
+      const double a = m.amp * M_PI * cos(M_PI * xi) * sin(M_PI * eta);
+      const double b = m.amp * M_PI * sin(M_PI * xi) * cos(M_PI * eta);
+      jxx = 1.0 + a;
+      jxy = b;
+      jyx = a;
+      jyy = 1.0 + b;
+    } else if constexpr (KIND == TOMG_MAP_POLAR) {
+      jxx = cos(eta);
+      jxy = -xi * sin(eta);
+      jyx = sin(eta);
+      jyy = xi * cos(eta);
+    } else {  // numeric Jacobian from the map at the neighbouring nodes
+      diff_axis([&](int k, double &px, double &py) {
+        map_point<KIND>(m, cph, sph, xi0 + k * dx, eta, px, py);
+      }, i, nx, i2dx, x, y, jxx, jyx);
+      diff_axis([&](int k, double &px, double &py) {
+        map_point<KIND>(m, cph, sph, xi, eta0 + k * dy, px, py);
+      }, j, ny, i2dy, x, y, jxy, jyy);
+    }
+    const double D = jxx * jyy - jxy * jyx;
+    const double vxx = (jyy * jyy + jxy * jxy) / D;
+    const double vxy = (-jyy * jyx - jxy * jxx) / D;
+    const double vyy = (jyx * jyx + jxx * jxx) / D;
+    const double fv = -gaussians(src, x, y) * D;
+    __builtin_nontemporal_store(vxx, exx + c);
+    __builtin_nontemporal_store(vxy, exy + c);
+    __builtin_nontemporal_store(vyy, eyy + c);
+    __builtin_nontemporal_store(D, det + c);
+    __builtin_nontemporal_store(fv, f + c);
+    if (exx32) {
+      exx32[c] = (float)vxx;
+      exy32[c] = (float)vxy;
+      eyy32[c] = (float)vyy;
+    }
+    const bool ring = (i == 0 && !(neumann & TOMG_NEU_W)) ||
+                      (i == nx - 1 && !(neumann & TOMG_NEU_E)) ||
+                      (j == 0 && !(neumann & TOMG_NEU_S)) ||
+                      (j == ny - 1 && !(neumann & TOMG_NEU_N));
+    bool held = false;  // interior Dirichlet node of the map (the conductor)
+    double g = 0.0;     // Dirichlet value
+    if constexpr (KIND == TOMG_MAP_PERTURBED_CIRCLE) {
+      held = hypot(xi - m.cx, eta - m.cy) <= m.r_c;
+      if (held) g = m.value_in;
+    } else if constexpr (KIND == TOMG_MAP_POLAR) {
+      if (i == 0 && ring) g = m.value_in;
+    }
+    dir[c] = (uint8_t)(ring || held);
+    if (phi_init) phi_init[c] = (ring || held) ? g : 0.0;
+    const bool corner = ring && (i == 0 || i == nx - 1) && (j == 0 || j == ny - 1);
+    if (!corner) {
+      mind = fmin(mind, D);
+      if (!isfinite(vxx) || !isfinite(vxy) || !isfinite(vyy) || !isfinite(fv)) bad += 1.0;
+    }
+  }
+  const double mn = block_reduce<1>(mind);
+  const double b = block_reduce<0>(bad);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = mn;
+    partials[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// f = -rho' det J with rho' from a source descriptor at the nodes of map m.
+template <int KIND>
+__global__ void k_update_rhs_desc(int nx, int ny, double xi0, double eta0, double dx, double dy,
+                                  tomg_map_desc m, tomg_source_desc src, const double *det,
+                                  double *f, double *partials) {
+  const size_t n = (size_t)nx * ny;
+  const double cph = cos(m.phase), sph = sin(m.phase);
+  double bad = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(c / (size_t)nx), i = (int)(c - (size_t)j * nx);
+    double x, y;
+    map_point<KIND>(m, cph, sph, xi0 + i * dx, eta0 + j * dy, x, y);
+    const double rho = gaussians(src, x, y);
+    f[c] = -rho * det[c];
+    if (!isfinite(rho)) bad += 1.0;
+  }
+  const double b = block_reduce<0>(bad);
+  if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
 __global__ void k_update_rhs(const double *rho, const double *det, double *f, size_t n,
                              double *partials) {
   double bad = 0.0;
@@ -798,9 +980,9 @@ constexpr int kInvThreads = 1024, kInvWaves = kInvThreads / 64;
 // Coarsest level: index map of the free nodes and the explicit inverse of
 // the coarsest matrix by Gauss-Jordan elimination with partial pivoting (one
 // block).  cidx[ncoarse] receives the unknown count.
-__global__ __launch_bounds__(kInvThreads) void k_coarse_inverse(const double *st, const uint8_t *dir,
-                                                        int nx, int ny, double *inv, int *cidx,
-                                                        double *scal) {
+__device__ __forceinline__ void coarse_inverse_body(const double *st, const uint8_t *dir, int nx,
+                                                    int ny, double *inv, int *cidx,
+                                                    double *scal) {
   // Gauss-Jordan with partial pivoting on m <= kMaxCoarseUnknowns < 64
   // unknowns: lane t & 63 owns a column, wave t >> 6 every kInvWaves-th row
   // (sixteen waves: three or four rows each on 49 unknowns, so the
@@ -900,6 +1082,16 @@ __global__ __launch_bounds__(kInvThreads) void k_coarse_inverse(const double *st
   }
   if (c < m)
     for (int r = w; r < m; r += kInvWaves) inv[r * m + c] = B[r][c];
+}
+
+__global__ __launch_bounds__(kInvThreads) void k_coarse_inverse(InvArgs a) {
+  coarse_inverse_body(a.st, a.dir, a.nx, a.ny, a.inv, a.cidx, a.scal);
+}
+
+// Batched form: one workgroup per problem.
+__global__ __launch_bounds__(kInvThreads) void k_coarse_inverse_b(BatchTab tab) {
+  const InvArgs a = *static_cast<const InvArgs *>(tab.e[blockIdx.x].args);
+  coarse_inverse_body(a.st, a.dir, a.nx, a.ny, a.inv, a.cidx, a.scal);
 }
 
 // ---------------------------------------------------------------------------
@@ -1753,6 +1945,14 @@ hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, con
                      p->cfg.dy, xp, yp, jac, epsp, rho, mask, p->exx, p->exy, p->eyy, p->det,
                      p->f, p->lv[0].dir, f32 ? p->exx32 : nullptr, f32 ? p->exy32 : nullptr,
                      f32 ? p->eyy32 : nullptr, p->partials, p->cfg.neumann);
+  return finish_setup(p);
+}
+
+// After a level-0 setup kernel: its min-det and non-finite checks into the
+// scalar block, and the stored level-0 stencil where the problem has one.
+hipError_t finish_setup(tomg_problem *p) {
+  const int ny = p->cfg.ny;
+  const bool f32 = p->cfg.precision == TOMG_FP32_IR;
   hipLaunchKernelGGL((k_finalize<1>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 2,
                      p->scal + kSlotMinDet, 0, p->scal, 0, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + 1, kRedBlocks,
@@ -1764,6 +1964,38 @@ hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, con
       hipLaunchKernelGGL(k_narrow, 4096, 256, 0, p->stream, (const double *)p->lv[0].st,
                          p->lv[0].st32, 9 * p->lv[0].n);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_desc(tomg_problem *p, const tomg_map_desc &m, const tomg_source_desc &src,
+                             double *phi_init) {
+  const tomg_config &c = p->cfg;
+  const bool f32 = c.precision == TOMG_FP32_IR;
+#define TOMG_DESC(KIND)                                                                        \
+  hipLaunchKernelGGL(k_setup_desc<KIND>, kRedBlocks, kRedThreads, 0, p->stream, c.nx, c.ny,     \
+                     c.xi0, c.eta0, c.dx, c.dy, m, src, p->exx, p->exy, p->eyy, p->det, p->f,  \
+                     p->lv[0].dir, f32 ? p->exx32 : nullptr, f32 ? p->exy32 : nullptr,         \
+                     f32 ? p->eyy32 : nullptr, phi_init, p->partials, c.neumann)
+  if (m.kind == TOMG_MAP_SINUSOIDAL) TOMG_DESC(TOMG_MAP_SINUSOIDAL);
+  else if (m.kind == TOMG_MAP_POLAR) TOMG_DESC(TOMG_MAP_POLAR);
+  else TOMG_DESC(TOMG_MAP_PERTURBED_CIRCLE);
+#undef TOMG_DESC
+  return finish_setup(p);
+}
+
+hipError_t launch_update_rhs_desc(tomg_problem *p, const tomg_map_desc &m,
+                                  const tomg_source_desc &src) {
+  const tomg_config &c = p->cfg;
+#define TOMG_DESC(KIND)                                                                        \
+  hipLaunchKernelGGL(k_update_rhs_desc<KIND>, kRedBlocks, kRedThreads, 0, p->stream, c.nx,      \
+                     c.ny, c.xi0, c.eta0, c.dx, c.dy, m, src, (const double *)p->det, p->f,     \
+                     p->partials)
+  if (m.kind == TOMG_MAP_SINUSOIDAL) TOMG_DESC(TOMG_MAP_SINUSOIDAL);
+  else if (m.kind == TOMG_MAP_POLAR) TOMG_DESC(TOMG_MAP_POLAR);
+  else TOMG_DESC(TOMG_MAP_PERTURBED_CIRCLE);
+#undef TOMG_DESC
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, kRedBlocks, 1,
+                     p->scal + kSlotBadRhs, 0, p->scal, 0, nullptr);
   return hipGetLastError();
 }
 
@@ -1820,7 +2052,7 @@ hipError_t launch_update_rhs(tomg_problem *p, const double *rho) {
   return hipGetLastError();
 }
 
-hipError_t launch_hierarchy(tomg_problem *p) {
+hipError_t launch_hierarchy(tomg_problem *p, bool defer_inverse) {
   const bool f32 = p->cfg.precision == TOMG_FP32_IR;
   for (int l = 1; l < p->L; ++l) {
     const tomg::Level &lf = p->lv[l - 1], &lc = p->lv[l];
@@ -1841,9 +2073,11 @@ hipError_t launch_hierarchy(tomg_problem *p) {
                          st_op<double>(lf.st, lf.nx, lf.ny), lf.dir, lf.nx, lf.ny, lc.nx, lc.ny,
                          lc.dir, lc.st, st32);
   }
-  const tomg::Level &lc = p->lv[p->L - 1];
-  hipLaunchKernelGGL(k_coarse_inverse, 1, kInvThreads, 0, p->stream, lc.st, lc.dir, lc.nx, lc.ny,
-                     p->cinv, p->cidx, p->scal);
+  p->inv_pending = true;
+  if (!defer_inverse) {
+    const hipError_t e = launch_coarse_inverse(p);
+    if (e != hipSuccess) return e;
+  }
   if (p->cfg.smoother == TOMG_ZEBRA_XY)
     // the transposed levels of the y-line sweeps: plane (di, dj) becomes (dj, di)
     for (int l = 0; l < p->L; ++l) {
@@ -1855,6 +2089,37 @@ hipError_t launch_hierarchy(tomg_problem *p) {
       transpose<uint8_t>(p, v.dir, v.dirT, v.nx, v.ny);
     }
   return hipGetLastError();
+}
+
+hipError_t launch_coarse_inverse(tomg_problem *p) {
+  if (!p->inv_pending) return hipSuccess;
+  hipLaunchKernelGGL(k_coarse_inverse, 1, kInvThreads, 0, p->stream, p->hargs.inv);
+  p->inv_pending = false;
+  return hipGetLastError();
+}
+
+void batch_coarse_inverse(tomg_problem *const *probs, const int *idx, int cnt, hipStream_t s) {
+  BatchTab tab;
+  tab.count = 0;
+  auto flush = [&] {
+    if (tab.count) hipLaunchKernelGGL(k_coarse_inverse_b, tab.count, kInvThreads, 0, s, tab);
+    tab.count = 0;
+  };
+  for (int k = 0; k < cnt; ++k) {
+    tomg_problem *p = probs[idx[k]];
+    if (!p->inv_pending) continue;
+    BatchEntry &e = tab.e[tab.count];
+    e.args = &p->dargs->inv;
+    e.phi = nullptr;
+    e.role = 0;
+    e.nbx = e.nby = 1;
+    e.start = tab.count;
+    e.slot = e.out = 0;
+    ++tab.count;
+    p->inv_pending = false;
+    if (tab.count == kBatchMax) flush();
+  }
+  flush();
 }
 
 hipError_t launch_vcycle64(tomg_problem *p, double *phi, bool with_norm) {
@@ -1910,6 +2175,8 @@ void build_red_args(tomg_problem *p) {
   const PassArgs<double> &u = p->hargs.up64[0], &ub = p->hargs.up64b[0];
   p->hargs.fin_norm = {p->partials, p->scal, u.nbx * u.nby};
   p->hargs.fin_normb = {p->partials, p->scal, ub.nbx * ub.nby};
+  const Level &lc = p->lv[p->L - 1];
+  p->hargs.inv = {lc.st, lc.dir, lc.nx, lc.ny, p->cinv, p->cidx, p->scal};
 }
 
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {

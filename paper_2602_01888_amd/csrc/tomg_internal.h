@@ -113,6 +113,16 @@ struct RedArgs {
   int nblk;  // blocks of the reduction (a function of the grid size only)
 };
 
+// Coarsest inverse of one problem (its launch may be deferred and batched).
+struct InvArgs {
+  const double *st;
+  const uint8_t *dir;
+  int nx, ny;
+  double *inv;
+  int *cidx;
+  double *scal;
+};
+
 // Fixed-order reduction of partials into the scalar block.
 struct FinArgs {
   const double *partials;
@@ -133,6 +143,7 @@ struct ArgsBlob {
   FinArgs fin_red, fin_norm, fin_red0;  // partials of the reductions, the up pass,
                                         // and the second half of a two-norm pass
   FinArgs fin_normb;                    // the up pass as launched in a batch
+  InvArgs inv;                          // the coarsest inverse
 };
 
 // One problem's share of a batched launch: blocks [start, start + nbx*nby).
@@ -199,6 +210,9 @@ struct tomg_problem {
   const double *skip = nullptr;     // device convergence flag while solve() queues cycles
   double up[2] = {0.0, 0.0};        // source of the tolerance/cycle-count upload
   bool unchecked = false;           // setup issued without its host-side check
+  bool inv_pending = false;         // coarsest inverse of the last setup not launched yet
+  bool has_map = false;             // the last setup came from a map descriptor
+  tomg_map_desc map{};              // ... this one (for tomg_update_rhs_desc)
   bool ready = false;
   // level-0 pass timing (tomg_profile): event pairs recorded since the last
   // harvest, per kind (0 down, 1 up)
@@ -217,7 +231,20 @@ namespace tomg {
 hipError_t launch_setup(tomg_problem *p, const double *xp, const double *yp, const double *jac,
                         const double *epsp, const double *rho, const uint8_t *mask);
 hipError_t launch_update_rhs(tomg_problem *p, const double *rho);
-hipError_t launch_hierarchy(tomg_problem *p);
+hipError_t finish_setup(tomg_problem *p);
+hipError_t launch_setup_desc(tomg_problem *p, const tomg_map_desc &m, const tomg_source_desc &src,
+                             double *phi_init);
+hipError_t launch_update_rhs_desc(tomg_problem *p, const tomg_map_desc &m,
+                                  const tomg_source_desc &src);
+// Galerkin (or rediscretised) levels; the coarsest inverse too unless
+// defer_inverse (then it is launched by launch_coarse_inverse or, batched,
+// by batch_coarse_inverse before the problem's next cycle).
+hipError_t launch_hierarchy(tomg_problem *p, bool defer_inverse = false);
+// The problem's pending coarsest inverse, if any, on its stream.
+hipError_t launch_coarse_inverse(tomg_problem *p);
+// The pending coarsest inverses of probs[idx[0..cnt)] in one launch per up to
+// kBatchMax problems (one workgroup each) on stream s.
+void batch_coarse_inverse(tomg_problem *const *probs, const int *idx, int cnt, hipStream_t s);
 hipError_t launch_vcycle64(tomg_problem *p, double *phi, bool with_norm);
 
 // fused level passes (fused.hip)

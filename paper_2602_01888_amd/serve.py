@@ -40,6 +40,13 @@ side is recomputed (``tomg_update_rhs``), and the iteration starts from the
 geometry's last solution.  If the geometry has been evicted the request is
 served cold.
 
+Inputs.  A request that carries map and source descriptors is set up by
+``tomg_setup_coeffs_desc`` (and re-sourced by ``tomg_update_rhs_desc``): the
+setup kernel evaluates the map, its Jacobian and the charge density at each
+node, so admission launches a handful of library kernels and moves no input
+arrays.  Other requests hand the library device arrays from ``geometry()``
+and ``source()``.
+
 The arithmetic of each problem does not depend on the others in the batch or
 on when it joined: a request's result is bitwise the result of solving it
 alone from the same initial guess.
@@ -82,6 +89,11 @@ class Request:
     eta0: float = 0.0
     neumann: int = 0      # edges with a zero normal derivative (TOMG_NEU_* bits)
     flux: bool = False    # the symmetric flux form of the operator
+    # the same request as descriptors (keyword arguments of the library's
+    # map_desc and source_desc): a backend that takes them evaluates the map
+    # and the source in its setup kernel, with no input arrays
+    map_desc: Optional[dict] = None
+    source_desc: Optional[dict] = None
 
     @property
     def stored_form(self) -> bool:
@@ -147,11 +159,13 @@ class TomgBackend:
 
     reuses = True  # create() can set up an evicted problem of the same shape again
 
-    def __init__(self, precision="fp32_ir", nu1=2, nu2=2, ir_inner_cycles=2, device=None):
+    def __init__(self, precision="fp32_ir", nu1=2, nu2=2, ir_inner_cycles=2, device=None,
+                 descriptors=True):
         import torch
 
         import paper_2602_01888_amd as tomg
         self.tomg, self.torch = tomg, torch
+        self.descriptors = descriptors  # set requests that carry them up from descriptors
         self.kw = dict(precision=precision, nu1=nu1, nu2=nu2, ir_inner_cycles=ir_inner_cycles)
         self.device = torch.device("cuda") if device is None else torch.device(device)
 
@@ -161,8 +175,13 @@ class TomgBackend:
         return self.tomg.workspace_bytes(cfg) + 8 * req.nx * req.ny
 
     def transient(self, req: Request) -> int:
+        if self._by_desc(req):  # evaluated in the setup kernel: no input arrays
+            return 0
         # coordinates, analytic partials or mask, initial guess and source
         return 8 * req.nx * req.ny * 8
+
+    def _by_desc(self, req: Request) -> bool:
+        return self.descriptors and req.map_desc is not None and req.source_desc is not None
 
     def create(self, req: Request, reuse=None):
         """Problem with its coefficient setup queued (checks deferred): a new
@@ -171,6 +190,13 @@ class TomgBackend:
         p = reuse if reuse is not None else self.tomg.Problem(
             req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0, device=self.device,
             neumann=req.neumann, flux=req.flux, **self.kw)
+        if self._by_desc(req):
+            with self.torch.cuda.stream(p.stream):
+                phi = self.torch.empty((req.ny, req.nx), dtype=self.torch.float64,
+                                       device=self.device)
+            p.setup_desc(self.tomg.map_desc(**req.map_desc),
+                         self.tomg.source_desc(**req.source_desc), phi_init=phi, check=False)
+            return p, phi
         g = req.geometry()
         rho = req.source()
         if g.get("jac") is not None:
@@ -190,7 +216,10 @@ class TomgBackend:
         return TOMG_ENONFINITE, "non-finite residual"
 
     def new_source(self, problem, req: Request):
-        problem.update_rhs(req.source())
+        if problem.from_map and self._by_desc(req):
+            problem.update_rhs_desc(self.tomg.source_desc(**req.source_desc))
+        else:
+            problem.update_rhs(req.source())
 
     def step(self, problems, phis, fresh):
         return self.tomg.batch_step(problems, phis, fresh)

@@ -141,7 +141,8 @@ def test_null_problem_calls(lib):
 # the passage (section or equation) that defines it.
 PAPER_CALLS = ["setup_coeffs", "tomg_setup_coeffs_async", "tomg_update_rhs", "vcycle", "solve",
                "residual_norm", "tomg_solve_batch", "tomg_batch_step", "tomg_batch_launch",
-               "tomg_laplace_grid", "tomg_field"]
+               "tomg_laplace_grid", "tomg_field", "tomg_setup_coeffs_desc",
+               "tomg_update_rhs_desc"]
 
 
 def declaration_comments():
@@ -180,3 +181,44 @@ def test_coarse_operator_options(lib):
     c = cfg(129, 129)
     c.coarse_op = 2
     assert t.workspace_bytes(c) == 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of tomg_config, tomg_map_desc and tomg_source_desc
+    have the C compiler's size and field offsets for include/tomg.h."""
+    import shutil
+    import subprocess
+    from paper_2602_01888_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"tomg_config": _lib.Config, "tomg_map_desc": _lib.MapDesc,
+               "tomg_source_desc": _lib.SourceDesc}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "tomg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True,
+                                                      capture_output=True,
+                                                      text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[f"{cname} size"]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname} {f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_descriptor_calls_reject_bad_descriptors_on_the_host(lib):
+    """NULL problem handles are rejected before any descriptor is read."""
+    import paper_2602_01888_amd as t
+    m = t.map_desc("circle", r_in=0.15, r_c=0.2, r_out=0.35)
+    s = t.source_desc([1.0], [(0.5, 0.5)], 0.02)
+    assert lib.tomg_setup_coeffs_desc(None, C.byref(m), C.byref(s), None, 0) == t.TOMG_EINVAL
+    assert lib.tomg_update_rhs_desc(None, C.byref(s)) == t.TOMG_EINVAL
+    with pytest.raises(t.TomgError):
+        t.source_desc([1.0] * 17, [(0.5, 0.5)] * 17, 0.02)

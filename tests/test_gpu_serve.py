@@ -23,6 +23,18 @@ def env():
     return torch, tomg, serve, D
 
 
+def alone(torch, tomg, r, precision="fp32_ir"):
+    """A problem set up for request r by itself, as the server's backend sets
+    it up: from the request's descriptors (a warm request's source on its
+    geometry's map gives the same coefficients and right-hand side as the
+    served update of the source)."""
+    p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, r.xi0, r.eta0, precision=precision,
+                     neumann=r.neumann)
+    ph = torch.empty((r.ny, r.nx), dtype=torch.float64, device="cuda")
+    p.setup_desc(tomg.map_desc(**r.map_desc), tomg.source_desc(**r.source_desc), phi_init=ph)
+    return p
+
+
 def stream(D, serve, count, sides):
     descs = w.serving_stream(count, rate=1000.0, seed=11, sides=sides)
     return [serve.Request(**D.request_fields(d, "cuda")) for d in descs], descs
@@ -44,8 +56,31 @@ def test_served_results_equal_alone(env, precision):
     by = {r.rid: r for r in reqs}
     for c in done:
         r = by[c.rid]
+        p = alone(torch, tomg, r, precision)
+        phi = c.phi_start.clone()
+        ra = p.solve(phi, rel_tol=1e-10, max_cycles=100)
+        assert ra.cycles == c.cycles, (c.rid, ra, c)
+        assert bool((phi == c.phi).all()), c.rid
+
+
+def test_array_inputs_backend_equal_alone(env):
+    """The backend without descriptors hands the library the request's
+    device arrays (setup_coeffs, update_rhs): each result is bitwise the
+    array setup of the same request alone."""
+    torch, tomg, serve, D = env
+    reqs, descs = stream(D, serve, 12, (65, 129, 257))
+    srv = serve.Server(serve.TomgBackend(descriptors=False), budget_bytes=8 << 30,
+                       max_active=5, keep_results=True)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.drain()
+    assert len(done) == len(reqs) and all(c.ok for c in done), [c for c in done if not c.ok]
+    assert srv.stats["warm"] > 0
+    by = {r.rid: r for r in reqs}
+    for c in done:
+        r = by[c.rid]
         g = r.geometry()
-        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, precision=precision)
+        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, precision="fp32_ir")
         rho = r.source()
         if g["jac"] is not None:
             p.setup_coeffs(rho, jac=g["jac"], mask=g["mask"])
@@ -77,7 +112,9 @@ def test_served_results_meet_tolerance_by_oracle(env):
         b0 = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], q.phi0, s["f"]))
         rel = oracle.norm2_free(s["dir"], oracle.residual(st, s["dir"], c.phi.cpu().numpy(),
                                                           s["f"])) / b0
-        assert rel <= 1e-10 * (1 + 1e-3), (c.rid, rel, c.rel)
+        # (the served coefficients come from descriptors: the map evaluated
+        # on the device, equal to the host arrays' to rounding)
+        assert rel <= 1e-10 * (1 + 1e-2), (c.rid, rel, c.rel)
 
 
 def test_served_folded_map_fails_alone(env):
@@ -128,14 +165,7 @@ def test_served_neumann_and_circle_mix_equal_alone(env, precision):
     by = {r.rid: r for r in reqs}
     for c in done:
         r = by[c.rid]
-        g = r.geometry()
-        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, r.xi0, r.eta0, precision=precision,
-                         neumann=r.neumann)
-        rho = r.source()
-        if g["jac"] is not None:
-            p.setup_coeffs(rho, jac=g["jac"], mask=g["mask"])
-        else:
-            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g["mask"])
+        p = alone(torch, tomg, r, precision)
         phi = c.phi_start.clone()
         ra = p.solve(phi, rel_tol=1e-10, max_cycles=200)
         assert ra.cycles == c.cycles, (c.rid, ra, c)
@@ -159,13 +189,7 @@ def test_served_with_problem_reuse_equal_alone(env):
     by = {r.rid: r for r in reqs}
     for c in done:
         r = by[c.rid]
-        g = r.geometry()
-        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, precision="fp32_ir")
-        rho = r.source()
-        if g["jac"] is not None:
-            p.setup_coeffs(rho, jac=g["jac"], mask=g["mask"])
-        else:
-            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g["mask"])
+        p = alone(torch, tomg, r, "fp32_ir")
         phi = c.phi_start.clone()
         ra = p.solve(phi, rel_tol=1e-10, max_cycles=100)
         assert ra.cycles == c.cycles, (c.rid, ra, c)
@@ -221,22 +245,16 @@ def test_served_large_sides(env):
     checked = False
     for c in done:
         r = by[c.rid]
-        g = r.geometry()
-        p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, precision="fp32_ir")
-        rho = r.source()
-        if g["jac"] is not None:
-            p.setup_coeffs(rho, jac=g["jac"], mask=g["mask"])
-        else:
-            p.setup_coeffs(rho, xp=g["xp"], yp=g["yp"], mask=g["mask"])
+        p = alone(torch, tomg, r, "fp32_ir")
         phi = c.phi_start.clone()
         ra = p.solve(phi, rel_tol=1e-11, max_cycles=100)
         assert ra.cycles == c.cycles, (c.rid, ra, c)
         assert bool((phi == c.phi).all()), c.rid
         if r.nx == 1025 and not checked:
-            gh = {k: (None if v is None else v.cpu().numpy()) for k, v in g.items()}
+            gh = {k: (None if v is None else v.cpu().numpy()) for k, v in r.geometry().items()}
             q = w.GridProblem("served", r.nx, r.ny, 0.0, 0.0, r.dx, r.dy, gh["xp"], gh["yp"],
-                              rho.cpu().numpy(), c.phi_start.cpu().numpy(), jac=gh["jac"],
-                              mask=gh["mask"])
+                              r.source().cpu().numpy(), c.phi_start.cpu().numpy(),
+                              jac=gh["jac"], mask=gh["mask"])
             ro = oracle.solve_problem(q, rel_tol=1e-13, max_cycles=60)
             # continued to 1e-13 or to the FP64 floor (about 1.5e-12 here)
             assert ro["status"] == 0 or (ro["status"] == 1 and ro["rel"] <= 1e-11)

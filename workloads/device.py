@@ -143,6 +143,28 @@ def semi_annulus_geometry(n, device):
             "mask": None, "phi0": phi0}
 
 
+def map_descriptor(kind, map_params, phase=0.0):
+    """Parameters of the same maps for a map descriptor of the library
+    (keyword arguments of its ``map_desc``): the perturbed circle about
+    (1/2, 1/2) with radii 0.15 < 0.2 < 0.35, perturbation 0.03 sum a_k
+    cos(k (theta - phase)) and conductor value 1; the sinusoidal map of
+    amplitude amp; the polar semi-annulus with value 1 on its inner arc."""
+    if kind == "annulus":
+        return {"kind": "polar", "value_in": 1.0}
+    if kind == "circle":
+        return {"kind": "circle", "centre": (0.5, 0.5), "r_in": 0.15, "r_c": 0.2, "r_out": 0.35,
+                "pert": 0.03, "coef": [float(a) for a in map_params["acoef"]],
+                "phase": float(phase), "value_in": 1.0}
+    return {"kind": "sinusoidal", "amp": float(map_params["amp"])}
+
+
+def source_descriptor(kind, amps, centres):
+    """Keyword arguments of the library's ``source_desc`` for drawn sources."""
+    return {"amps": [float(a) for a in amps], "centres": [(float(c[0]), float(c[1]))
+                                                          for c in centres],
+            "sigma": ANNULUS_SIGMA if kind == "annulus" else SIGMA}
+
+
 def geometry(kind, n, map_params, device):
     if kind == "annulus":
         return semi_annulus_geometry(n, device)
@@ -154,7 +176,8 @@ def geometry(kind, n, map_params, device):
 def request_fields(desc, device):
     """Fields of a serving request built from a ``gen.serving_stream``
     descriptor: geometry() and source() evaluate the arrays on `device` when
-    the server asks for them."""
+    the server asks for them; map_desc and source_desc give the same request
+    as map and source descriptors."""
     kind, n = desc["kind"], desc["side"]
     mp, amps, centres = geometry_params(kind, desc["geom_seed"])
     if desc["warm"]:
@@ -175,7 +198,9 @@ def request_fields(desc, device):
         return gaussian_rho(g["xp"], g["yp"], amps, centres, sigma)
 
     out = {"rid": desc["id"], "geom": desc["geom"], "nx": n, "ny": n, "dx": d, "dy": d,
-           "geometry": geom, "source": source, "warm": desc["warm"], "arrival": desc["t"]}
+           "geometry": geom, "source": source, "warm": desc["warm"], "arrival": desc["t"],
+           "map_desc": map_descriptor(kind, mp),
+           "source_desc": source_descriptor(kind, amps, centres)}
     if kind == "annulus":  # [2, 5] x [0, pi], Neumann sides eta = 0, pi
         out.update(dx=3.0 / (n - 1), dy=math.pi / (n - 1), xi0=2.0, eta0=0.0, neumann=4 | 8)
     return out
