@@ -72,7 +72,8 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
   };
   const size_t n0 = (size_t)cfg.nx * cfg.ny;
   o.scal = take(kNumSlots * sizeof(double));
-  const size_t nparts = std::max((size_t)2 * kRedBlocks, fused_max_blocks(cfg.nx, cfg.ny));
+  const size_t nparts = std::max({(size_t)2 * kRedBlocks, fused_max_blocks(cfg.nx, cfg.ny),
+                                  (size_t)2 * red_tiles(cfg.nx, cfg.ny)});
   o.partials = take(nparts * sizeof(double));
   o.cinv = take(kMaxCoarseUnknowns * kMaxCoarseUnknowns * sizeof(double));
   o.cidx = take(82 * sizeof(int));
@@ -110,6 +111,7 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
     o.e32 = take(n0 * 4);
     o.e32b = take(n0 * 4);
     o.r32 = take(n0 * 4);
+    o.phi2 = take(n0 * 8);
     if (stored_level0(cfg)) o.st32[0] = take(9 * n0 * 4);
     for (int l = 1; l < o.L; ++l) {
       const size_t n = (size_t)o.nx[l] * o.ny[l];
@@ -245,6 +247,7 @@ static hipError_t init_problem(tomg_problem *p, const tomg_config *cfg, const La
     p->eyy32 = F(lay.eyy32);
     p->e32 = F(lay.e32);
     p->e32b = F(lay.e32b);
+    p->phi2 = D(lay.phi2);
     p->r32 = F(lay.r32);
     if (stored_level0(*cfg)) p->lv[0].st32 = F(lay.st32[0]);
     for (int l = 1; l < p->L; ++l) {
@@ -564,8 +567,12 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
     hipError_t e = hipSuccess;
     for (int q = 0; q < k && e == hipSuccess; ++q) {
       if (ir) {
-        e = launch_ir_correct(p, d_phi);
-        if (e == hipSuccess) e = launch_ir_residual(p, d_phi);
+        // the update and the next residual in one pass; the iterate of an
+        // odd-numbered step lives in the problem's second array (steps
+        // skipped past convergence are a suffix, so the executed count
+        // tells where the last iterate is)
+        e = launch_ir_inner(p);
+        if (e == hipSuccess) e = launch_ir_step(p, d_phi, (cycles + q) & 1);
       } else {
         e = launch_vcycle64(p, d_phi, true);
       }
@@ -579,6 +586,11 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
     queued = (int)h[kSlotCycles] - cycles;
     cycles = (int)h[kSlotCycles];
     rel = h[kSlotRel];
+  }
+  if (ir && (cycles & 1)) {  // the last iterate is in the second array
+    HIP_TRY(p, hipMemcpyAsync(d_phi, p->phi2, p->lv[0].n * sizeof(double),
+                              hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
   }
   if (cycles_out) *cycles_out = cycles;
   if (rel_res_out) *rel_res_out = rel;
@@ -627,8 +639,12 @@ void batch_begin(tomg_problem *const *probs, const int *idx, int cnt, double *co
 // problems idx[0..cnt), then their residuals; relative residuals to out[q]
 // (to out[idx[q]] with by_index).  Each stage is one launch over all
 // problems that have that level above their single-workgroup tail.
+// With roles (indexed like probs), the refinement update and residual run as
+// one pass that moves problem k's iterate to its second array (roles[k] = 0)
+// or back (1); without, the update is applied in place.
 void batch_cycle(tomg_problem *const *probs, const int *idx, int cnt, double *const *d_phis,
-                 bool ir, int inner, double *out, hipStream_t s, bool by_index = false) {
+                 bool ir, int inner, double *out, hipStream_t s, bool by_index = false,
+                 const int *roles = nullptr) {
   int maxlc = 0;
   for (int q = 0; q < cnt; ++q) maxlc = std::max(maxlc, probs[idx[q]]->lc);
   std::vector<int> lvl;
@@ -647,8 +663,12 @@ void batch_cycle(tomg_problem *const *probs, const int *idx, int cnt, double *co
       if (participants(l)) batch_up(probs, lvl.data(), (int)lvl.size(), l, ir, !ir, d_phis, s);
   }
   if (ir) {
-    batch_ir_update(probs, idx, cnt, d_phis, s);
-    batch_ir_residual(probs, idx, cnt, d_phis, s);
+    if (roles) {
+      batch_ir_step(probs, idx, cnt, d_phis, roles, s);
+    } else {
+      batch_ir_update(probs, idx, cnt, d_phis, s);
+      batch_ir_residual(probs, idx, cnt, d_phis, s);
+    }
     batch_finalize(probs, idx, cnt, 0, kSlotRes, kRelCycle, out, s, by_index);
   } else {
     batch_finalize(probs, idx, cnt, 1, kSlotRes, kRelCycle, out, s, by_index);
@@ -697,6 +717,7 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
   std::vector<int> act(n);
   for (int k = 0; k < n; ++k) act[k] = k;
   std::vector<double> hrel(n);
+  std::vector<int> role(n, 0);
   int na = n;
   batch_coarse_inverse(probs, act.data(), na, s);
   batch_begin(probs, act.data(), na, d_phis, ir, lead->bout, s);
@@ -720,9 +741,21 @@ tomg_status tomg_solve_batch(tomg_problem *const *probs, double *const *d_phis, 
     }
     na = w;
     if (na == 0) break;
-    batch_cycle(probs, act.data(), na, d_phis, ir, lead->cfg.ir_inner_cycles, lead->bout, s);
+    for (int q = 0; q < na; ++q) role[act[q]] = cyc[act[q]] & 1;
+    batch_cycle(probs, act.data(), na, d_phis, ir, lead->cfg.ir_inner_cycles, lead->bout, s,
+                false, ir ? role.data() : nullptr);
     for (int q = 0; q < na; ++q) ++cyc[act[q]];
     if (!read_back(hrel.data(), lead->bout, na, s)) return TOMG_EDEVICE;
+  }
+  if (ir) {  // iterates left in the second arrays after an odd step count
+    std::vector<int> odd;
+    for (int k = 0; k < n; ++k)
+      if (cyc[k] & 1) odd.push_back(k);
+    if (!odd.empty()) {
+      batch_copy_back(probs, odd.data(), (int)odd.size(), d_phis, s);
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return TOMG_EDEVICE;
+    }
   }
   tomg_status first = TOMG_OK;
   for (int k = 0; k < n; ++k) {

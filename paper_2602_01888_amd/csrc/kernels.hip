@@ -1451,140 +1451,238 @@ __global__ void k_prolong(const T *ec, int nxc, T *x, const uint8_t *dir, int nx
 // in the same order alone and in a batch.
 // ---------------------------------------------------------------------------
 
-// Residual at free node (i, j) of level 0 from the stored tensor; with ZF the
-// values at free nodes are taken as zero (the phi0 of the stopping test).
-template <bool ZF>
-__device__ __forceinline__ double resid0(const RedArgs &a, const double *x, int i, int j) {
-  const size_t s = (size_t)a.nx, c = (size_t)j * a.nx + i;
-  auto v = [&](size_t q) -> double { return (ZF && !a.dir[q]) ? 0.0 : x[q]; };
-  const double ax = a.exx[c] * a.cx, ay = a.eyy[c] * a.cy;
-  const double gx = (a.exx[c + 1] - a.exx[c - 1]) * a.qx + (a.exy[c + s] - a.exy[c - s]) * a.qxy;
-  const double gy = (a.eyy[c + s] - a.eyy[c - s]) * a.qy + (a.exy[c + 1] - a.exy[c - 1]) * a.qxy;
-  const double k1 = ax + gx, k3 = ax - gx, k4 = ay + gy, k5 = ay - gy;
-  const double k6 = a.exy[c] * a.hxy, k2 = 2.0 * (ax + ay);
-  const double off = k1 * v(c + 1) + k3 * v(c - 1) + k4 * v(c + s) + k5 * v(c - s) +
-                     k6 * ((v(c + s + 1) - v(c + s - 1)) - (v(c - s + 1) - v(c - s - 1)));
-  return a.f[c] - off + k2 * v(c);
-}
+// Level-0 reductions run over tiles of one wave by kRedTileH rows.  Lane k
+// of a tile holds column i0 - 1 + k (clamped to the grid): lanes 1 .. 62
+// compute, lanes 0 and 63 only carry the neighbouring columns, whose values
+// reach the computing lanes by cross-lane shuffles, so each row costs one
+// load per array.  A lane walks its column down the tile with the rows
+// below, at and above the current one in registers and the next rows'
+// loads in flight (the loop is unrolled whole, so every row stays in place
+// in its registers).  Each lane sums its r^2 in row order and the tile's
+// partial is the wave's sum over the lanes in lane order: the tiles depend
+// only on the grid, so a problem reduces in the same order alone and in a
+// batch.
+//
+// Modes: kRmNorm sum of r^2 of x; kRmNormZF the same with the values at free
+// nodes taken as zero (the zero-interior start of the stopping test);
+// kRmBegin both; kRmIrRes r32 = fl32(r) (zero at Dirichlet nodes) and its
+// sum; kRmIrResB0 also the zero-interior sum; kRmIrStep the refinement
+// update and residual together: v = x + e32 at free nodes (x at Dirichlet
+// nodes) is written to xo and r = f - A v gives r32 and its sum.
+enum { kRmNorm = 0, kRmNormZF, kRmBegin, kRmIrRes, kRmIrResB0, kRmIrStep };
+constexpr int kRedCols = kRedTileW - 2;  // computed columns of a tile
 
-// The same from the stored level-0 stencil (Neumann edges: free nodes on the
-// ring; neighbours outside the grid carry zero coefficients and are read at
-// in-range nodes instead).
-template <bool ZF>
-__device__ __forceinline__ double resid_st(const RedArgs &a, const double *x, int i, int j) {
-  const size_t s = (size_t)a.nx, c = (size_t)j * a.nx + i, n = s * a.ny;
-  auto v = [&](size_t q) -> double { return (ZF && !a.dir[q]) ? 0.0 : x[q]; };
-  const size_t w = i > 0 ? c - 1 : c, e = i < a.nx - 1 ? c + 1 : c;
-  const size_t ds = j > 0 ? s : 0, us = j < a.ny - 1 ? s : 0;
-  const double *st = a.st0;
-  const double off = st[c] * v(w - ds) + st[n + c] * v(c - ds) + st[2 * n + c] * v(e - ds) +
-                     st[3 * n + c] * v(w) + st[5 * n + c] * v(e) + st[6 * n + c] * v(w + us) +
-                     st[7 * n + c] * v(c + us) + st[8 * n + c] * v(e + us);
-  return a.f[c] - off - st[4 * n + c] * v(c);
-}
+template <int M> constexpr bool rm_zf() { return M == kRmNormZF || M == kRmBegin || M == kRmIrResB0; }
+template <int M> constexpr bool rm_x() { return M != kRmNormZF; }
 
-// Level-0 reductions.  Block blk of nblk takes rows blk, blk + nblk, ...
-// (threads along the row), so every partial sum has a fixed order.
+// One row as loaded at the lane's column.
+template <bool ST>
+struct RedRaw {
+  double x, exx, exy, eyy, f;
+  double st[ST ? 9 : 1];
+  float e;
+  uint8_t d;
+};
 
-// Partial sums of r^2 over free nodes.
-template <bool ZF>
-__device__ __forceinline__ void resnorm_body(const RedArgs &a, const double *x, int blk) {
-  double s = 0.0;
-  if (a.st0) {  // Neumann edges: every free node, ring included
-    for (int j = blk; j < a.ny; j += a.nblk)
-      for (int i = threadIdx.x; i < a.nx; i += blockDim.x) {
-        if (a.dir[(size_t)j * a.nx + i]) continue;
-        const double r = resid_st<ZF>(a, x, i, j);
-        s += r * r;
-      }
+// One row of the window: the values at columns i-1, i, i+1, the Dirichlet
+// flags of the three (bits 0, 1, 2) and the row's own coefficients.
+template <bool ST>
+struct RedWin {
+  double vl, vc, vr, exx, exy, eyy, f;
+  double st[ST ? 9 : 1];
+  uint32_t d;
+};
+
+template <int M, bool ST>
+__device__ __forceinline__ void red_load(RedRaw<ST> &w, const RedArgs &a,
+                                         const double *__restrict__ x, int i, int r) {
+  const size_t c = (size_t)r * a.nx + i;
+  w.x = x[c];
+  w.d = a.dir[c];
+  if constexpr (M == kRmIrStep) w.e = a.e32[c];
+  w.f = a.f[c];
+  if constexpr (ST) {
+    const size_t n = (size_t)a.nx * a.ny;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w.st[k] = a.st0[k * n + c];
+  } else {
+    w.exx = a.exx[c];
+    w.exy = a.exy[c];
+    w.eyy = a.eyy[c];
   }
-  for (int j = 1 + blk; !a.st0 && j < a.ny - 1; j += a.nblk)
-    for (int i = 1 + threadIdx.x; i < a.nx - 1; i += blockDim.x) {
-      if (a.dir[(size_t)j * a.nx + i]) continue;
-      const double r = resid0<ZF>(a, x, i, j);
-      s += r * r;
-    }
-  s = block_reduce<0>(s);
-  if (threadIdx.x == 0) a.partials[blk] = s;
 }
 
-// Refinement, outer step: r = f - A64 phi at free nodes (FP64), r32 =
-// fl32(r) (zero at Dirichlet nodes), partial sums of r^2.  With B0 also the
-// partial sums of the zero-interior residual |f - A phi0|^2 into
-// partials[nblk + blk].
-template <bool B0>
-__device__ __forceinline__ void ir_residual_body(const RedArgs &a, const double *phi, int blk) {
+template <int M, bool ST>
+__device__ __forceinline__ void red_enter(RedWin<ST> &w, const RedRaw<ST> &q) {
+  double v = q.x;
+  if constexpr (M == kRmIrStep) v = q.d ? q.x : q.x + (double)q.e;
+  w.vc = v;
+  w.vl = __shfl_up(v, 1, 64);
+  w.vr = __shfl_down(v, 1, 64);
+  const uint32_t dc = q.d ? 2u : 0u;
+  w.d = dc | (__shfl_up(dc, 1, 64) >> 1) | (__shfl_down(dc, 1, 64) << 1);
+  w.f = q.f;
+  if constexpr (ST) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w.st[k] = q.st[k];
+  } else {
+    w.exx = q.exx;
+    w.exy = q.exy;
+    w.eyy = q.eyy;
+  }
+}
+
+// r = f - A v at the middle row from the rows below (S), at (C) and above
+// (N): the operator of eq. 18 or the stored stencil; with Z the values at
+// free nodes are taken as zero.
+template <bool ST, bool Z>
+__device__ __forceinline__ double red_resid(const RedArgs &a, const RedWin<ST> &S,
+                                            const RedWin<ST> &C, const RedWin<ST> &N,
+                                            double exxl, double exxr, double exyl, double exyr) {
+  auto z = [](const RedWin<ST> &w, int k) {
+    const double v = k == 0 ? w.vl : (k == 1 ? w.vc : w.vr);
+    return (!Z || ((w.d >> k) & 1u)) ? v : 0.0;
+  };
+  if constexpr (ST) {
+    const double *st = C.st;
+    const double off = st[0] * z(S, 0) + st[1] * z(S, 1) + st[2] * z(S, 2) + st[3] * z(C, 0) +
+                       st[5] * z(C, 2) + st[6] * z(N, 0) + st[7] * z(N, 1) + st[8] * z(N, 2);
+    return C.f - off - st[4] * z(C, 1);
+  } else {
+    const double ax = C.exx * a.cx, ay = C.eyy * a.cy;
+    const double gx = (exxr - exxl) * a.qx + (N.exy - S.exy) * a.qxy;
+    const double gy = (N.eyy - S.eyy) * a.qy + (exyr - exyl) * a.qxy;
+    const double k1 = ax + gx, k3 = ax - gx, k4 = ay + gy, k5 = ay - gy;
+    const double k6 = C.exy * a.hxy, k2 = 2.0 * (ax + ay);
+    const double off = k1 * z(C, 2) + k3 * z(C, 0) + k4 * z(N, 1) + k5 * z(S, 1) +
+                       k6 * ((z(N, 2) - z(N, 0)) - (z(S, 2) - z(S, 0)));
+    return C.f - off + k2 * z(C, 1);
+  }
+}
+
+template <int M, bool ST>
+__device__ __forceinline__ void red_tile(const RedArgs &a, const double *__restrict__ x,
+                                         double *__restrict__ xo, int t) {
+  constexpr int D = ST ? 1 : 3;  // rows loaded ahead of the window
+  const int tx = (a.nx + kRedCols - 1) / kRedCols;
+  const int lane = (int)threadIdx.x;
+  const int i = (t % tx) * kRedCols - 1 + lane;  // this lane's column
+  const int ic = i < 0 ? 0 : (i >= a.nx ? a.nx - 1 : i);
+  const bool computes = lane >= 1 && lane <= kRedCols && i < a.nx;
+  const int j0 = (t / tx) * kRedTileH, j1 = min(j0 + kRedTileH, a.ny);
+  auto row = [&](int r) { return r < 0 ? 0 : (r >= a.ny ? a.ny - 1 : r); };
+  float *__restrict__ r32 = a.r32;
   double s = 0.0, s0 = 0.0;
-  for (int j = blk; j < a.ny; j += a.nblk) {
-    const size_t row = (size_t)j * a.nx;
-    for (int i = threadIdx.x; i < a.nx; i += blockDim.x) {
+  RedWin<ST> w[3];
+  RedRaw<ST> q[D];
+  {
+    RedRaw<ST> t0;
+    red_load<M, ST>(t0, a, x, ic, row(j0 - 1));
+    red_enter<M, ST>(w[0], t0);
+    red_load<M, ST>(t0, a, x, ic, row(j0));
+    red_enter<M, ST>(w[1], t0);
+    red_load<M, ST>(t0, a, x, ic, row(j0 + 1));
+    red_enter<M, ST>(w[2], t0);
+  }
+  // The walk has a fixed length (rows past the grid are clamped to its last
+  // row), so the rows move through the window and the load slots without
+  // control flow around them and stay in the registers they were loaded
+  // into; only the arithmetic of rows outside the tile is skipped.
+#pragma unroll
+  for (int k = 0; k < D; ++k) red_load<M, ST>(q[k], a, x, ic, row(j0 + 2 + k));
+#pragma unroll
+  for (int u = 0; u < kRedTileH; ++u) {
+    const int j = j0 + u;
+    const RedWin<ST> &S = w[u % 3], &C = w[(u + 1) % 3], &N = w[(u + 2) % 3];
+    double exxl = 0.0, exxr = 0.0, exyl = 0.0, exyr = 0.0;
+    if constexpr (!ST) {
+      exxl = __shfl_up(C.exx, 1, 64);
+      exxr = __shfl_down(C.exx, 1, 64);
+      exyl = __shfl_up(C.exy, 1, 64);
+      exyr = __shfl_down(C.exy, 1, 64);
+    }
+    if (computes && j < j1) {
+      const size_t c = (size_t)j * a.nx + i;
       double r = 0.0;
-      if (!a.dir[row + i]) {
-        // a stored stencil has free nodes on the ring (Neumann edges)
-        r = a.st0 ? resid_st<false>(a, phi, i, j) : resid0<false>(a, phi, i, j);
-        if constexpr (B0) {
-          const double r0 = a.st0 ? resid_st<true>(a, phi, i, j) : resid0<true>(a, phi, i, j);
-          s0 += r0 * r0;
+      if (!(C.d & 2u)) {
+        // a free node on the ring exists only with a stored stencil
+        // (Neumann edges), whose clamped neighbours carry zero coefficients
+        if constexpr (rm_x<M>()) r = red_resid<ST, false>(a, S, C, N, exxl, exxr, exyl, exyr);
+        if constexpr (rm_zf<M>()) {
+          const double r0 = red_resid<ST, true>(a, S, C, N, exxl, exxr, exyl, exyr);
+          if constexpr (M == kRmNormZF) r = r0;
+          else s0 += r0 * r0;
         }
       }
-      a.r32[row + i] = (float)r;
+      if constexpr (M == kRmIrRes || M == kRmIrResB0 || M == kRmIrStep) r32[c] = (float)r;
+      if constexpr (M == kRmIrStep) xo[c] = C.vc;
       s += r * r;
     }
+    // row j + 2 enters the window in place of the row below, and row
+    // j + 2 + D is loaded into the freed slot (both only while the tile
+    // still needs them: the conditions are fixed at compile time)
+    if (u + 2 <= kRedTileH) red_enter<M, ST>(w[u % 3], q[u % D]);
+    if (u + 2 + D <= kRedTileH) red_load<M, ST>(q[u % D], a, x, ic, row(j + 2 + D));
   }
   s = block_reduce<0>(s);
-  if (threadIdx.x == 0) a.partials[blk] = s;
-  if constexpr (B0) {
+  if (threadIdx.x == 0) a.partials[t] = s;
+  if constexpr (M == kRmBegin || M == kRmIrResB0) {
     s0 = block_reduce<0>(s0);
-    if (threadIdx.x == 0) a.partials[a.nblk + blk] = s0;
+    if (threadIdx.x == 0) a.partials[a.nblk + t] = s0;
   }
 }
 
-// Both initial norms in one pass: partials[blk] = sum of r^2 of the given
-// iterate, partials[nblk + blk] = sum of r^2 of the zero-interior start.
-__device__ __forceinline__ void begin_body(const RedArgs &a, const double *x, int blk) {
-  double s = 0.0, s0 = 0.0;
-  if (a.st0) {  // Neumann edges: every free node, ring included
-    for (int j = blk; j < a.ny; j += a.nblk)
-      for (int i = threadIdx.x; i < a.nx; i += blockDim.x) {
-        if (a.dir[(size_t)j * a.nx + i]) continue;
-        const double r = resid_st<false>(a, x, i, j);
-        const double r0 = resid_st<true>(a, x, i, j);
-        s += r * r;
-        s0 += r0 * r0;
-      }
-  }
-  for (int j = 1 + blk; !a.st0 && j < a.ny - 1; j += a.nblk)
-    for (int i = 1 + threadIdx.x; i < a.nx - 1; i += blockDim.x) {
-      if (a.dir[(size_t)j * a.nx + i]) continue;
-      const double r = resid0<false>(a, x, i, j);
-      const double r0 = resid0<true>(a, x, i, j);
-      s += r * r;
-      s0 += r0 * r0;
+// Refinement update alone: phi += e32 at free nodes (the tiles of the
+// reductions, no partials).
+__device__ __forceinline__ void ir_update_body(const RedArgs &a, double *phi, int t) {
+  const int tx = (a.nx + kRedCols - 1) / kRedCols;
+  const int lane = (int)threadIdx.x;
+  const int i = (t % tx) * kRedCols - 1 + lane;
+  const int j0 = (t / tx) * kRedTileH, j1 = min(j0 + kRedTileH, a.ny);
+  if (lane < 1 || lane > kRedCols || i >= a.nx) return;
+  // eight rows at a time: every load of the group is issued before the
+  // first store
+  constexpr int G = 8;
+  for (int jg = j0; jg < j1; jg += G) {
+    double v[G];
+    float e[G];
+    uint8_t d[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const size_t c = (size_t)min(jg + k, j1 - 1) * a.nx + i;
+      v[k] = phi[c];
+      e[k] = a.e32[c];
+      d[k] = a.dir[c];
     }
-  s = block_reduce<0>(s);
-  if (threadIdx.x == 0) a.partials[blk] = s;
-  s0 = block_reduce<0>(s0);
-  if (threadIdx.x == 0) a.partials[a.nblk + blk] = s0;
-}
-
-// Refinement, update: phi += e32 at free nodes.
-__device__ __forceinline__ void ir_update_body(const RedArgs &a, double *phi, int blk) {
-  for (int j = blk; j < a.ny; j += a.nblk) {
-    const size_t row = (size_t)j * a.nx;
-    for (int i = threadIdx.x; i < a.nx; i += blockDim.x)
-      if (!a.dir[row + i]) phi[row + i] += (double)a.e32[row + i];
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+      if (jg + k < j1 && !d[k]) phi[(size_t)(jg + k) * a.nx + i] = v[k] + (double)e[k];
   }
 }
 
-template <bool ZF>
-__global__ void k_resnorm(RedArgs a, const double *x) { resnorm_body<ZF>(a, x, blockIdx.x); }
-template <bool B0>
-__global__ void k_ir_residual(RedArgs a, const double *phi, const double *skip) {
-  if (skip && *skip != 0.0) return;
-  ir_residual_body<B0>(a, phi, blockIdx.x);
+// ST: the problem has a stored level-0 stencil (a.st0).
+// phi = a.phi2 over the tile (the whole grid).
+__device__ __forceinline__ void copy_back_body(const RedArgs &a, double *phi, int t) {
+  const int tx = (a.nx + kRedCols - 1) / kRedCols;
+  const int lane = (int)threadIdx.x;
+  const int i = (t % tx) * kRedCols - 1 + lane;
+  const int j0 = (t / tx) * kRedTileH, j1 = min(j0 + kRedTileH, a.ny);
+  if (lane < 1 || lane > kRedCols || i >= a.nx) return;
+#pragma unroll 8
+  for (int j = j0; j < j1; ++j) {
+    const size_t c = (size_t)j * a.nx + i;
+    phi[c] = a.phi2[c];
+  }
 }
-__global__ void k_begin(RedArgs a, const double *x) { begin_body(a, x, blockIdx.x); }
-__global__ void k_ir_update(RedArgs a, double *phi, const double *skip) {
+
+template <int M, bool ST>
+__global__ void __launch_bounds__(kRedTileW) k_red(RedArgs a, const double *x, double *xo,
+                                                   const double *skip) {
+  if (skip && *skip != 0.0) return;
+  red_tile<M, ST>(a, x, xo, blockIdx.x);
+}
+__global__ void __launch_bounds__(kRedTileW) k_ir_update(RedArgs a, double *phi,
+                                                         const double *skip) {
   if (skip && *skip != 0.0) return;
   ir_update_body(a, phi, blockIdx.x);
 }
@@ -1598,20 +1696,28 @@ __device__ __forceinline__ const BatchEntry &locate(const BatchTab &tab, int b) 
   return tab.e[lo];
 }
 
-// kind 0: resnorm (ZF), 1: resnorm, 2: refinement residual, 3: refinement
-// update, 4: both initial norms, 5: refinement residual and zero-interior norm
-template <int KIND>
-__global__ void k_red_b(BatchTab tab) {
+// KIND: a reduction mode (kRm*), -1 for the refinement update alone, or -2
+// for the copy of the iterate from the problem's second array back into the
+// caller's.  With kRmIrStep the iterate moves between the caller's array and
+// the second one (a.phi2): role 0 reads the caller's and writes the second,
+// role 1 the other way round.
+// ST: every problem of the launch has a stored level-0 stencil.
+template <int KIND, bool ST>
+__global__ void __launch_bounds__(kRedTileW) k_red_b(BatchTab tab) {
   const BatchEntry &e = locate(tab, blockIdx.x);
   const RedArgs &a = *static_cast<const RedArgs *>(e.args);
-  const int blk = blockIdx.x - e.start;
+  const int t = blockIdx.x - e.start;
   double *phi = static_cast<double *>(e.phi);
-  if constexpr (KIND == 0) resnorm_body<true>(a, phi, blk);
-  if constexpr (KIND == 1) resnorm_body<false>(a, phi, blk);
-  if constexpr (KIND == 2) ir_residual_body<false>(a, phi, blk);
-  if constexpr (KIND == 3) ir_update_body(a, phi, blk);
-  if constexpr (KIND == 4) begin_body(a, phi, blk);
-  if constexpr (KIND == 5) ir_residual_body<true>(a, phi, blk);
+  if constexpr (KIND == -2) {
+    copy_back_body(a, phi, t);
+  } else if constexpr (KIND == -1) {
+    ir_update_body(a, phi, t);
+  } else if constexpr (KIND == kRmIrStep) {
+    if (e.role) red_tile<KIND, ST>(a, a.phi2, phi, t);
+    else red_tile<KIND, ST>(a, phi, a.phi2, t);
+  } else {
+    red_tile<KIND, ST>(a, phi, nullptr, t);
+  }
 }
 
 // Batched finalize: one block per problem; sqrt of the fixed-order sum into
@@ -2137,15 +2243,19 @@ hipError_t launch_vcycle64(tomg_problem *p, double *phi, bool with_norm) {
   }
   // no level-0 pass left norm partials (the Jacobi path): a separate norm
   const RedArgs &r = p->hargs.red;
-  hipLaunchKernelGGL(k_resnorm<false>, r.nblk, kRedThreads, 0, p->stream, r, phi);
+  if (r.st0)
+    hipLaunchKernelGGL((k_red<kRmNorm, true>), r.nblk, kRedTileW, 0, p->stream, r, phi, nullptr,
+                       nullptr);
+  else
+    hipLaunchKernelGGL((k_red<kRmNorm, false>), r.nblk, kRedTileW, 0, p->stream, r, phi,
+                       nullptr, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
                      p->scal + kSlotRes, 1, p->scal, 2, nullptr);
   return hipGetLastError();
 }
 
-int red_blocks(size_t n) {
-  const size_t b = (n + 4095) / 4096;
-  return (int)(b < 1 ? 1 : (b > (size_t)kRedBlocks ? kRedBlocks : b));
+int red_tiles(int nx, int ny) {
+  return ((nx + kRedTileW - 3) / (kRedTileW - 2)) * ((ny + kRedTileH - 1) / kRedTileH);
 }
 
 void build_red_args(tomg_problem *p) {
@@ -2169,7 +2279,8 @@ void build_red_args(tomg_problem *p) {
   r.e32 = p->e32;
   r.tmp = p->tmp;
   r.st0 = stored_level0(p->cfg) ? p->lv[0].st : nullptr;
-  r.nblk = red_blocks(p->lv[0].n);
+  r.phi2 = p->phi2;
+  r.nblk = red_tiles(p->cfg.nx, p->cfg.ny);
   p->hargs.fin_red = {p->partials, p->scal, r.nblk};
   p->hargs.fin_red0 = {p->partials + r.nblk, p->scal, r.nblk};
   const PassArgs<double> &u = p->hargs.up64[0], &ub = p->hargs.up64b[0];
@@ -2179,9 +2290,18 @@ void build_red_args(tomg_problem *p) {
   p->hargs.inv = {lc.st, lc.dir, lc.nx, lc.ny, p->cinv, p->cidx, p->scal};
 }
 
+template <int M>
+static void launch_red(tomg_problem *p, const double *x, double *xo, const double *skip) {
+  const RedArgs &r = p->hargs.red;
+  if (r.st0)
+    hipLaunchKernelGGL((k_red<M, true>), r.nblk, kRedTileW, 0, p->stream, r, x, xo, skip);
+  else
+    hipLaunchKernelGGL((k_red<M, false>), r.nblk, kRedTileW, 0, p->stream, r, x, xo, skip);
+}
+
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
   const RedArgs &r = p->hargs.red;
-  hipLaunchKernelGGL(k_ir_residual<false>, r.nblk, kRedThreads, 0, p->stream, r, phi, p->skip);
+  launch_red<kRmIrRes>(p, phi, nullptr, p->skip);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
                      p->scal + kSlotRes, 1, p->scal, 2, p->skip);
   return hipGetLastError();
@@ -2193,9 +2313,9 @@ hipError_t launch_ir_residual(tomg_problem *p, const double *phi) {
 hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir) {
   const RedArgs &r = p->hargs.red;
   if (ir)
-    hipLaunchKernelGGL(k_ir_residual<true>, r.nblk, kRedThreads, 0, p->stream, r, phi, nullptr);
+    launch_red<kRmIrResB0>(p, phi, nullptr, nullptr);
   else
-    hipLaunchKernelGGL(k_begin, r.nblk, kRedThreads, 0, p->stream, r, phi);
+    launch_red<kRmBegin>(p, phi, nullptr, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials + r.nblk,
                      r.nblk, 1, p->scal + kSlotB0, 1, p->scal, 0, nullptr);
   hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
@@ -2203,7 +2323,30 @@ hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir) {
   return hipGetLastError();
 }
 
+// One refinement step after the inner cycles: phi += e32 and the new
+// residual in one pass; the iterate moves from the caller's array to phi2
+// (second = false) or back (second = true).
+hipError_t launch_ir_step(tomg_problem *p, double *phi, bool second) {
+  const RedArgs &r = p->hargs.red;
+  if (second)
+    launch_red<kRmIrStep>(p, p->phi2, phi, p->skip);
+  else
+    launch_red<kRmIrStep>(p, phi, p->phi2, p->skip);
+  hipLaunchKernelGGL((k_finalize<0>), 1, kRedThreads, 0, p->stream, p->partials, r.nblk, 1,
+                     p->scal + kSlotRes, 1, p->scal, 2, p->skip);
+  return hipGetLastError();
+}
+
 hipError_t launch_ir_correct(tomg_problem *p, double *phi) {
+  hipError_t e = launch_ir_inner(p);
+  if (e != hipSuccess) return e;
+  const RedArgs &r = p->hargs.red;
+  hipLaunchKernelGGL(k_ir_update, r.nblk, kRedTileW, 0, p->stream, r, phi, p->skip);
+  return hipGetLastError();
+}
+
+// The inner FP32 cycles of a refinement step: e32 from r32.
+hipError_t launch_ir_inner(tomg_problem *p) {
   const int nx = p->cfg.nx;
   LevelView<float> v[kMaxLevels];
   for (int l = 0; l < p->L; ++l)
@@ -2214,17 +2357,16 @@ hipError_t launch_ir_correct(tomg_problem *p, double *phi) {
     hipError_t e = run_vcycle<float>(p, p->e32, p->r32, o32, v, k == 0, nullptr, nullptr);
     if (e != hipSuccess) return e;
   }
-  const RedArgs &r = p->hargs.red;
-  hipLaunchKernelGGL(k_ir_update, r.nblk, kRedThreads, 0, p->stream, r, phi, p->skip);
   return hipGetLastError();
 }
 
 
 // ---- batched reductions ----------------------------------------------------
 
+// roles (nullable, indexed like probs): the BatchEntry role of each problem.
 template <int KIND>
 static void batch_red(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
-                      hipStream_t s) {
+                      hipStream_t s, const int *roles = nullptr) {
   BatchTab tab;
   for (int k0 = 0; k0 < cnt; k0 += kBatchMax) {
     tab.count = 0;
@@ -2234,41 +2376,55 @@ static void batch_red(tomg_problem *const *probs, const int *idx, int cnt, doubl
       BatchEntry &e = tab.e[tab.count++];
       e.args = &p->dargs->red;
       e.phi = phis[idx[k]];
-      e.role = 0;
+      e.role = roles ? roles[idx[k]] : 0;
       e.nbx = p->hargs.red.nblk;
       e.nby = 1;
       e.start = nb;
       e.slot = e.out = 0;
       nb += e.nbx;
     }
-    if (tab.count) hipLaunchKernelGGL(k_red_b<KIND>, nb, kRedThreads, 0, s, tab);
+    if (!tab.count) continue;
+    if (probs[idx[k0]]->hargs.red.st0)
+      hipLaunchKernelGGL((k_red_b<KIND, true>), nb, kRedTileW, 0, s, tab);
+    else
+      hipLaunchKernelGGL((k_red_b<KIND, false>), nb, kRedTileW, 0, s, tab);
   }
 }
 
 void batch_resnorm(tomg_problem *const *probs, const int *idx, int cnt, bool zero_free,
                    double *const *phis, hipStream_t s) {
   if (zero_free)
-    batch_red<0>(probs, idx, cnt, phis, s);
+    batch_red<kRmNormZF>(probs, idx, cnt, phis, s);
   else
-    batch_red<1>(probs, idx, cnt, phis, s);
+    batch_red<kRmNorm>(probs, idx, cnt, phis, s);
 }
 
 void batch_ir_residual(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
                        hipStream_t s) {
-  batch_red<2>(probs, idx, cnt, phis, s);
+  batch_red<kRmIrRes>(probs, idx, cnt, phis, s);
 }
 
 void batch_begin_norms(tomg_problem *const *probs, const int *idx, int cnt, bool ir,
                        double *const *phis, hipStream_t s) {
   if (ir)
-    batch_red<5>(probs, idx, cnt, phis, s);
+    batch_red<kRmIrResB0>(probs, idx, cnt, phis, s);
   else
-    batch_red<4>(probs, idx, cnt, phis, s);
+    batch_red<kRmBegin>(probs, idx, cnt, phis, s);
 }
 
 void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
                      hipStream_t s) {
-  batch_red<3>(probs, idx, cnt, phis, s);
+  batch_red<-1>(probs, idx, cnt, phis, s);
+}
+
+void batch_ir_step(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                   const int *roles, hipStream_t s) {
+  batch_red<kRmIrStep>(probs, idx, cnt, phis, s, roles);
+}
+
+void batch_copy_back(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                     hipStream_t s) {
+  batch_red<-2>(probs, idx, cnt, phis, s);
 }
 
 void batch_finalize(tomg_problem *const *probs, const int *idx, int cnt, int kind, int slot,

@@ -14,6 +14,7 @@ constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarseUnknowns = 49;  // coarsest grid <= 9 x 9 nodes
 constexpr int kRedBlocks = 1024;        // fixed grid of every reduction kernel
 constexpr int kRedThreads = 256;
+constexpr int kRedTileW = 64, kRedTileH = 32;  // level-0 reduction tiles (columns x rows)
 
 // Slots of the device scalar block.
 enum Slot {
@@ -110,7 +111,8 @@ struct RedArgs {
   float *r32, *e32;
   double *tmp;
   const double *st0;  // level-0 stencil (Neumann edges only, else null)
-  int nblk;  // blocks of the reduction (a function of the grid size only)
+  double *phi2;       // second array of the iterate (refinement), else null
+  int nblk;  // tiles of the reduction (a function of the grid size only)
 };
 
 // Coarsest inverse of one problem (its launch may be deferred and batched).
@@ -167,7 +169,7 @@ struct Layout {
   int nx[kMaxLevels], ny[kMaxLevels];
   size_t exx, exy, eyy, det, f, tmp, partials, scal, cinv, cidx;
   size_t dir[kMaxLevels], st[kMaxLevels], x[kMaxLevels], b[kMaxLevels], x2[kMaxLevels];
-  size_t exx32, exy32, eyy32, e32, e32b, r32;
+  size_t exx32, exy32, eyy32, e32, e32b, r32, phi2;
   size_t st32[kMaxLevels], x32[kMaxLevels], b32[kMaxLevels], x2_32[kMaxLevels];
   size_t stT[kMaxLevels], xT[kMaxLevels], bT[kMaxLevels], dirT[kMaxLevels];
   size_t args, bout;  // device copy of the launch arguments; batch results
@@ -199,6 +201,7 @@ struct tomg_problem {
   tomg::Level lv[tomg::kMaxLevels];
   double *exx = nullptr, *exy = nullptr, *eyy = nullptr, *det = nullptr, *f = nullptr;
   double *tmp = nullptr, *partials = nullptr, *scal = nullptr, *cinv = nullptr;
+  double *phi2 = nullptr;  // refinement: second array of the iterate
   int *cidx = nullptr;
   float *exx32 = nullptr, *exy32 = nullptr, *eyy32 = nullptr, *e32 = nullptr, *r32 = nullptr;
   float *e32b = nullptr;
@@ -262,6 +265,8 @@ void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *co
 int tail_max_nodes();
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi);
 hipError_t launch_ir_correct(tomg_problem *p, double *phi);
+hipError_t launch_ir_inner(tomg_problem *p);
+hipError_t launch_ir_step(tomg_problem *p, double *phi, bool second);
 hipError_t launch_begin(tomg_problem *p, const double *phi, bool ir);
 hipError_t launch_setup_identity(tomg_problem *p, const uint8_t *mask);
 hipError_t launch_zero(tomg_problem *p, double *x, size_t n);
@@ -280,7 +285,7 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 void build_pass_args(tomg_problem *p);
 void build_tail_args(tomg_problem *p);
 void build_red_args(tomg_problem *p);
-int red_blocks(size_t n);
+int red_tiles(int nx, int ny);
 int tail_level(const tomg_problem *p);
 
 // batched stages over problems probs[idx[0..cnt-1]] (one launch per up to
@@ -300,6 +305,13 @@ void batch_ir_residual(tomg_problem *const *probs, const int *idx, int cnt, doub
 void batch_begin_norms(tomg_problem *const *probs, const int *idx, int cnt, bool ir,
                        double *const *phis, hipStream_t s);
 void batch_ir_update(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                     hipStream_t s);
+// update and residual in one pass (launch_ir_step); roles[k] (indexed like
+// probs): 0 the iterate moves from phis[k] to the problem's phi2, 1 back
+void batch_ir_step(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
+                   const int *roles, hipStream_t s);
+// phis[k] = the problem's phi2
+void batch_copy_back(tomg_problem *const *probs, const int *idx, int cnt, double *const *phis,
                      hipStream_t s);
 // kind 0: the reduction partials (fin_red), 1: the level-0 up-pass partials
 // (fin_norm), 2: the second half of a two-norm pass (fin_red0); slot: scalar
