@@ -275,7 +275,9 @@ def dense_solve(A, b):
 
 
 def levels(nx, ny, maxl=16, neumann=0):
-    """Level shapes; with Neumann edges the coarsest is at most 5 x 5."""
+    """Level shapes; with Neumann edges the coarsest is at most 5 x 5 where
+    halving reaches it, else at most 1024 nodes (the 201 x 201 family stops
+    at 26 x 26)."""
     a = (C.c_int * maxl)()
     b = (C.c_int * maxl)()
     L = _load().orc_levels_lim(nx, ny, a, b, maxl, 5 if neumann else 9)

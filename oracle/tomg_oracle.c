@@ -687,9 +687,11 @@ int orc_dense_solve(int m, double *A, double *b) {
 
 /* Grid hierarchy: halve while both node counts minus one are even and each
  * side keeps at least 3 nodes; always coarsen at least once, then keep
- * coarsening while either side exceeds 9 nodes.  Returns the number of
- * levels, or 0 when the grid cannot reach a coarsest level of at most 9x9
- * nodes. */
+ * coarsening while either side exceeds 9 nodes.  A grid whose halving stops
+ * above that (an odd number of intervals, as the 201 x 201 grid of Section
+ * 4.1 reaches at 26 x 26) keeps that coarsest level when it has at most
+ * ORC_MAX_COARSE_NODES nodes; its direct solve is then larger.  Returns the
+ * number of levels, or 0 when neither holds. */
 int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl) {
   return orc_levels_lim(nx, ny, nxs, nys, maxl, 9);
 }
@@ -713,7 +715,10 @@ int orc_levels_lim(int nx, int ny, int *nxs, int *nys, int maxl, int lim) {
     nys[L] = (cy - 1) / 2 + 1;
     ++L;
   }
-  if (L < 2 || nxs[L - 1] > lim || nys[L - 1] > lim) return 0;
+  if (L < 2) return 0;
+  if ((nxs[L - 1] > lim || nys[L - 1] > lim) &&
+      (long)nxs[L - 1] * nys[L - 1] > ORC_MAX_COARSE_NODES)
+    return 0;
   return L;
 }
 

@@ -99,6 +99,9 @@ int orc_dense_solve(int m, double *A, double *b);
 
 /* Multigrid hierarchy. */
 typedef struct orc_mg orc_mg;
+/* Largest coarsest level (nodes) kept when halving stops above the usual
+ * 9 x 9 (5 x 5 with Neumann edges) bound. */
+#define ORC_MAX_COARSE_NODES 1024
 int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl);
 int orc_levels_lim(int nx, int ny, int *nxs, int *nys, int maxl, int lim);
 orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
