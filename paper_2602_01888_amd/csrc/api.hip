@@ -32,7 +32,12 @@ int level_shapes(int nx, int ny, int *nxs, int *nys, int neumann) {
     nys[L] = (cy - 1) / 2 + 1;
     ++L;
   }
-  if (L < 2 || nxs[L - 1] > lim || nys[L - 1] > lim) return 0;
+  if (L < 2) return 0;
+  // halving stopped above the bound: the coarsest level is kept when its
+  // direct solve stays within kMaxCoarseNodes nodes
+  if ((nxs[L - 1] > lim || nys[L - 1] > lim) &&
+      (long)nxs[L - 1] * nys[L - 1] > kMaxCoarseNodes)
+    return 0;
   return L;
 }
 
@@ -75,8 +80,15 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
   const size_t nparts = std::max({(size_t)2 * kRedBlocks, fused_max_blocks(cfg.nx, cfg.ny),
                                   (size_t)2 * red_tiles(cfg.nx, cfg.ny)});
   o.partials = take(nparts * sizeof(double));
-  o.cinv = take(kMaxCoarseUnknowns * kMaxCoarseUnknowns * sizeof(double));
-  o.cidx = take(82 * sizeof(int));
+  // explicit inverse of the coarsest matrix, its node-to-unknown map and,
+  // for a coarsest level above kSmallCoarseNodes, the band LU (half-width
+  // nx + 1 in the row-major numbering of the unknowns)
+  const size_t mc = (size_t)o.nx[o.L - 1] * o.ny[o.L - 1];
+  const size_t mi = mc > (size_t)kSmallCoarseNodes ? mc : (size_t)kMaxCoarseUnknowns;
+  o.cinv = take(mi * mi * sizeof(double));
+  o.cidx = take((std::max(mc, (size_t)81) + 1) * sizeof(int));
+  if (mc > (size_t)kSmallCoarseNodes)
+    o.cband = take(mc * (2 * (size_t)(o.nx[o.L - 1] + 1) + 1) * sizeof(double));
   o.args = take(sizeof(ArgsBlob));
   o.bout = take(kMaxBatch * sizeof(double));
   o.exx = take(n0 * 8);
@@ -215,6 +227,7 @@ static hipError_t init_problem(tomg_problem *p, const tomg_config *cfg, const La
   p->partials = D(lay.partials);
   p->cinv = D(lay.cinv);
   p->cidx = (int *)(w + lay.cidx);
+  p->cband = lay.cband ? D(lay.cband) : nullptr;
   p->exx = D(lay.exx);
   p->exy = D(lay.exy);
   p->eyy = D(lay.eyy);

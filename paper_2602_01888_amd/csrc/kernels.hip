@@ -1080,8 +1080,98 @@ __device__ __forceinline__ void coarse_inverse_body(const double *st, const uint
     }
     __syncthreads();
   }
+  // column-major: entry (r, c) of the inverse at c * m + r, so that the
+  // coarsest solve's threads (one per row) read a column together
   if (c < m)
-    for (int r = w; r < m; r += kInvWaves) inv[r * m + c] = B[r][c];
+    for (int r = w; r < m; r += kInvWaves) inv[c * m + r] = B[r][c];
+}
+
+// A coarsest level of up to kMaxCoarseNodes nodes (a grid whose halving
+// stops above 9 x 9): the matrix over its free nodes, numbered row-major, is
+// banded with half-width bw = nx + 1.  One block factors it as A = L U in
+// band storage (band[r * (2 bw + 1) + bw + c - r]) without row exchanges --
+// the pivot test below flags a pivot that falls under 1e-12 of the largest
+// diagonal magnitude, as the small kernel's does -- and then thread q forms
+// row q of A^-1 by solving A^T z = e_q (U^T then L^T), every lane walking
+// the same band rows; z goes to inv[c * m + q] (the same column-major layout
+// as the small kernel's).
+__device__ void coarse_inverse_band_body(const InvArgs &a) {
+  __shared__ int cid[kMaxCoarseNodes];
+  __shared__ int sm;
+  __shared__ double dscale;
+  const int nx = a.nx, n = nx * a.ny, t = threadIdx.x;
+  const int bw = nx + 1, wd = 2 * bw + 1;
+  if (t == 0) {
+    int m = 0;
+    for (int q = 0; q < n; ++q) cid[q] = a.dir[q] ? -1 : m++;
+    sm = m;
+    for (int q = 0; q < n; ++q) a.cidx[q] = cid[q];
+    a.cidx[n] = m;
+  }
+  __syncthreads();
+  const int m = sm;
+  double *band = a.band;
+  auto at = [&](int r, int c) -> double & { return band[(size_t)r * wd + bw + c - r]; };
+  for (size_t q = t; q < (size_t)m * wd; q += blockDim.x) band[q] = 0.0;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int q = t; q < n; q += blockDim.x) {
+    const int row = cid[q];
+    if (row < 0) continue;
+    const int I = q % nx, J = q / nx;
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = I + di, jj = J + dj;
+        if (ii < 0 || jj < 0 || ii >= nx || jj >= a.ny) continue;
+        const int col = cid[jj * nx + ii];
+        if (col >= 0) at(row, col) = a.st[(size_t)((dj + 1) * 3 + di + 1) * n + q];
+      }
+    dmax = fmax(dmax, fabs(a.st[(size_t)4 * n + q]));
+  }
+  {  // largest diagonal magnitude over the block (waves, then wave maxima)
+    __shared__ double wmax[kInvWaves];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+    if ((t & 63) == 0) wmax[t >> 6] = dmax;
+    __syncthreads();
+    if (t == 0) {
+      double d = 0.0;
+      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) d = fmax(d, wmax[q]);
+      dscale = d;
+      a.scal[kSlotPivot] = 0.0;  // this setup's own verdict
+    }
+    __syncthreads();
+  }
+  const double tiny = 1e-12 * dscale;
+  // band LU: at step k the rows k+1 .. k+bw take their multiplier, then the
+  // trailing bw x bw block its update
+  for (int k = 0; k < m; ++k) {
+    const int hi = min(k + bw, m - 1), cnt = hi - k;
+    const double pv = at(k, k);
+    if (t == 0 && !(fabs(pv) > tiny)) a.scal[kSlotPivot] = 1.0;
+    for (int r = k + 1 + t; r <= hi; r += blockDim.x) at(r, k) /= pv;
+    __syncthreads();
+    for (int q = t; q < cnt * cnt; q += blockDim.x) {
+      const int r = k + 1 + q / cnt, c = k + 1 + q % cnt;
+      at(r, c) -= at(r, k) * at(k, c);
+    }
+    __syncthreads();
+  }
+  // row q of the inverse: U^T w = e_q, then L^T z = w (unit diagonal)
+  for (int q = t; q < m; q += blockDim.x) {
+    double *z = a.inv;  // z[c] of this row at inv[c * m + q]
+    for (int r = 0; r < m; ++r) {
+      double v = r == q ? 1.0 : 0.0;
+      if (r >= q)
+        for (int k = max(q, r - bw); k < r; ++k) v -= at(k, r) * z[(size_t)k * m + q];
+      z[(size_t)r * m + q] = r < q ? 0.0 : v / at(r, r);
+    }
+    for (int r = m - 1; r >= 0; --r) {
+      double v = z[(size_t)r * m + q];
+      for (int c = r + 1; c <= min(r + bw, m - 1); ++c) v -= at(c, r) * z[(size_t)c * m + q];
+      z[(size_t)r * m + q] = v;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kInvThreads) void k_coarse_inverse(InvArgs a) {
@@ -1092,6 +1182,10 @@ __global__ __launch_bounds__(kInvThreads) void k_coarse_inverse(InvArgs a) {
 __global__ __launch_bounds__(kInvThreads) void k_coarse_inverse_b(BatchTab tab) {
   const InvArgs a = *static_cast<const InvArgs *>(tab.e[blockIdx.x].args);
   coarse_inverse_body(a.st, a.dir, a.nx, a.ny, a.inv, a.cidx, a.scal);
+}
+
+__global__ __launch_bounds__(kInvThreads) void k_coarse_inverse_band(InvArgs a) {
+  coarse_inverse_band_body(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1752,7 +1846,7 @@ __global__ void k_finalize_b(BatchTab tab, int rel, double *out) {
 // Coarsest solve x = A^-1 b with the explicit inverse (one block).
 template <typename T>
 __global__ void k_coarse_solve(const double *inv, const int *cidx, const T *b, T *x, int n) {
-  __shared__ double bb[kMaxCoarseUnknowns];
+  __shared__ double bb[kMaxCoarseNodes];
   const int m = cidx[n];
   for (int c = threadIdx.x; c < n; c += blockDim.x)
     if (cidx[c] >= 0) bb[cidx[c]] = (double)b[c];
@@ -1761,7 +1855,7 @@ __global__ void k_coarse_solve(const double *inv, const int *cidx, const T *b, T
     const int k = cidx[c];
     double v = 0.0;
     if (k >= 0)
-      for (int q = 0; q < m; ++q) v += inv[k * m + q] * bb[q];
+      for (int q = 0; q < m; ++q) v += inv[(size_t)q * m + k] * bb[q];
     x[c] = (T)v;
   }
 }
@@ -1899,7 +1993,17 @@ void restrict_level(tomg_problem *p, const Op &op, const T *x, const T *b, const
 // First level handed to the single-workgroup tail: the first coarse level
 // with at most tail_max_nodes() nodes and at most 4 levels below it.
 }  // namespace
+// Threads of the coarsest solve: a wave for the small levels, up to 1024 for
+// the large ones (one row of the inverse each).
+static int coarse_solve_threads(const tomg_problem *p) {
+  const long n = (long)p->lv[p->L - 1].nx * p->lv[p->L - 1].ny;
+  return n <= 64 ? 64 : (n <= 256 ? 256 : 1024);
+}
+
 int tail_level(const tomg_problem *p) {
+  // the tail gives each thread one node of its two coarsest levels: a large
+  // coarsest level is solved on its own below the fused passes
+  if ((long)p->lv[p->L - 1].nx * p->lv[p->L - 1].ny > kSmallCoarseNodes) return p->L - 1;
   for (int l = 1; l < p->L; ++l)
     if ((long)p->lv[l].nx * p->lv[l].ny <= tail_max_nodes() && p->L - l <= 4) return l;
   return p->L - 1;
@@ -1934,7 +2038,7 @@ hipError_t run_vcycle_stored(tomg_problem *p, T *x0, const T *b0, const LevelVie
   }
   {
     const tomg::Level &lc = p->lv[L - 1];
-    hipLaunchKernelGGL((k_coarse_solve<T>), 1, 64, 0, p->stream, p->cinv, p->cidx,
+    hipLaunchKernelGGL((k_coarse_solve<T>), 1, coarse_solve_threads(p), 0, p->stream, p->cinv, p->cidx,
                        (const T *)views[L - 1].b, views[L - 1].x, (int)lc.n);
   }
   for (int l = L - 2; l >= 0; --l) {
@@ -1982,7 +2086,7 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
       sts[l] = views[l].st;
     }
     if (lc == L - 1)  // no tail (stored level-0 stencil): the coarsest solve alone
-      hipLaunchKernelGGL((k_coarse_solve<T>), 1, 64, 0, p->stream, p->cinv, p->cidx,
+      hipLaunchKernelGGL((k_coarse_solve<T>), 1, coarse_solve_threads(p), 0, p->stream, p->cinv, p->cidx,
                          (const T *)views[L - 1].b, views[L - 1].x, (int)p->lv[L - 1].n);
     else
       tail_cycle<T>(p, lc, xs, bs, sts);
@@ -2014,7 +2118,7 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
   }
   {
     const tomg::Level &lc = p->lv[L - 1];
-    hipLaunchKernelGGL((k_coarse_solve<T>), 1, 64, 0, p->stream, p->cinv, p->cidx,
+    hipLaunchKernelGGL((k_coarse_solve<T>), 1, coarse_solve_threads(p), 0, p->stream, p->cinv, p->cidx,
                        (const T *)views[L - 1].b, views[L - 1].x, (int)lc.n);
   }
   for (int l = L - 2; l >= 0; --l) {
@@ -2199,7 +2303,10 @@ hipError_t launch_hierarchy(tomg_problem *p, bool defer_inverse) {
 
 hipError_t launch_coarse_inverse(tomg_problem *p) {
   if (!p->inv_pending) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_inverse, 1, kInvThreads, 0, p->stream, p->hargs.inv);
+  if (p->cband)
+    hipLaunchKernelGGL(k_coarse_inverse_band, 1, kInvThreads, 0, p->stream, p->hargs.inv);
+  else
+    hipLaunchKernelGGL(k_coarse_inverse, 1, kInvThreads, 0, p->stream, p->hargs.inv);
   p->inv_pending = false;
   return hipGetLastError();
 }
@@ -2214,6 +2321,10 @@ void batch_coarse_inverse(tomg_problem *const *probs, const int *idx, int cnt, h
   for (int k = 0; k < cnt; ++k) {
     tomg_problem *p = probs[idx[k]];
     if (!p->inv_pending) continue;
+    if (p->cband) {  // a large coarsest level: its own launch
+      (void)launch_coarse_inverse(p);
+      continue;
+    }
     BatchEntry &e = tab.e[tab.count];
     e.args = &p->dargs->inv;
     e.phi = nullptr;
@@ -2287,7 +2398,7 @@ void build_red_args(tomg_problem *p) {
   p->hargs.fin_norm = {p->partials, p->scal, u.nbx * u.nby};
   p->hargs.fin_normb = {p->partials, p->scal, ub.nbx * ub.nby};
   const Level &lc = p->lv[p->L - 1];
-  p->hargs.inv = {lc.st, lc.dir, lc.nx, lc.ny, p->cinv, p->cidx, p->scal};
+  p->hargs.inv = {lc.st, lc.dir, p->cband, lc.nx, lc.ny, p->cinv, p->cidx, p->scal};
 }
 
 template <int M>

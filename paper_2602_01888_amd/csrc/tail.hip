@@ -28,7 +28,8 @@ namespace {
 
 constexpr int kTailThreads = 1024;
 constexpr int kTailMaxNodes = 65 * 65;  // per level: at most five nodes per thread
-constexpr int kTailLdsMax = 160 * 1024 - 1024;  // LDS per workgroup, less the static arrays
+// LDS per workgroup, less the static arrays (the coarsest right-hand side)
+constexpr int kTailLdsMax = 160 * 1024 - 9 * 1024;
 
 template <typename T>
 struct Own {
@@ -51,7 +52,7 @@ template <typename T>
 __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
   extern __shared__ unsigned char smem_raw[];
   T *X = reinterpret_cast<T *>(smem_raw);
-  __shared__ double bb[kMaxCoarseUnknowns];
+  __shared__ double bb[kMaxCoarseNodes];
   const int t = threadIdx.x;
   const int nl = a.nl;
   int total = 0, rmax = 0;
@@ -207,7 +208,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T> &a) {
       const int k = a.cidx[t];
       double s = 0.0;
       if (k >= 0)
-        for (int q = 0; q < m; ++q) s += a.cinv[k * m + q] * bb[q];
+        for (int q = 0; q < m; ++q) s += a.cinv[(size_t)q * m + k] * bb[q];
       X[v.off + t] = (T)s;
     }
     __syncthreads();

@@ -12,6 +12,11 @@ namespace tomg {
 
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarseUnknowns = 49;  // coarsest grid <= 9 x 9 nodes
+// A grid whose halving stops above 9 x 9 (5 x 5 with Neumann edges) keeps a
+// coarsest level of at most this many nodes (the 201 x 201 family: 26 x 26),
+// inverted through a band LU factorisation.
+constexpr int kMaxCoarseNodes = 1024;
+constexpr int kSmallCoarseNodes = 81;
 constexpr int kRedBlocks = 1024;        // fixed grid of every reduction kernel
 constexpr int kRedThreads = 256;
 constexpr int kRedTileW = 64, kRedTileH = 32;  // level-0 reduction tiles (columns x rows)
@@ -119,6 +124,7 @@ struct RedArgs {
 struct InvArgs {
   const double *st;
   const uint8_t *dir;
+  double *band;  // band LU workspace of a coarsest level above kSmallCoarseNodes
   int nx, ny;
   double *inv;
   int *cidx;
@@ -167,7 +173,7 @@ constexpr int kMaxBatch = 4096;  // problems per tomg_solve_batch call
 struct Layout {
   int L = 0;
   int nx[kMaxLevels], ny[kMaxLevels];
-  size_t exx, exy, eyy, det, f, tmp, partials, scal, cinv, cidx;
+  size_t exx, exy, eyy, det, f, tmp, partials, scal, cinv, cidx, cband;
   size_t dir[kMaxLevels], st[kMaxLevels], x[kMaxLevels], b[kMaxLevels], x2[kMaxLevels];
   size_t exx32, exy32, eyy32, e32, e32b, r32, phi2;
   size_t st32[kMaxLevels], x32[kMaxLevels], b32[kMaxLevels], x2_32[kMaxLevels];
@@ -202,6 +208,7 @@ struct tomg_problem {
   double *exx = nullptr, *exy = nullptr, *eyy = nullptr, *det = nullptr, *f = nullptr;
   double *tmp = nullptr, *partials = nullptr, *scal = nullptr, *cinv = nullptr;
   double *phi2 = nullptr;  // refinement: second array of the iterate
+  double *cband = nullptr; // band LU of a large coarsest level
   int *cidx = nullptr;
   float *exx32 = nullptr, *exy32 = nullptr, *eyy32 = nullptr, *e32 = nullptr, *r32 = nullptr;
   float *e32b = nullptr;

@@ -68,8 +68,12 @@ def test_levels_and_workspace(lib):
     assert t.num_levels(cfg(129, 129)) == 5
     assert t.num_levels(cfg(4097, 4097)) == 10
     assert t.num_levels(cfg(129, 65)) == 5
-    assert t.num_levels(cfg(201, 201)) == 0
-    assert t.workspace_bytes(cfg(201, 201)) == 0
+    # the 201 x 201 grid of Section 4.1 stops halving at 26 x 26 (a large
+    # coarsest level, inverted through a band LU); 1001 would stop at 126 x 126
+    assert t.num_levels(cfg(201, 201)) == 4
+    assert t.workspace_bytes(cfg(201, 201)) > 0
+    assert t.num_levels(cfg(1001, 1001)) == 0
+    assert t.workspace_bytes(cfg(1001, 1001)) == 0
     w64 = t.workspace_bytes(cfg(4097, 4097))
     w32 = t.workspace_bytes(cfg(4097, 4097, precision="fp32_ir"))
     n = 4097 * 4097
