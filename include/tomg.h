@@ -251,6 +251,15 @@ tomg_status tomg_setup_coeffs_desc(tomg_problem *p, const tomg_map_desc *map,
  * Asynchronous. */
 tomg_status tomg_update_rhs_desc(tomg_problem *p, const tomg_source_desc *src);
 
+/* The relative residual (the eq. 20 norm over the stopping test's
+ * denominator, Section 3) of the problem's last solve, alone or batched:
+ * out[0] at its start and out[c] after its cycle c.  *count (nullable)
+ * receives the number of entries recorded (cycles + 1, at most 256); at
+ * most cap are written to out (host memory, nullable when cap is 0).
+ * Synchronises the problem's stream.  TOMG_EINVAL for a null problem or
+ * cap < 0. */
+tomg_status tomg_residual_history(tomg_problem *p, double *out, int32_t cap, int32_t *count);
+
 /* Synchronises the problem's stream and returns the status of the checks of
  * the last setup (TOMG_OK, TOMG_EGEOMETRY or TOMG_ENONFINITE, as
  * setup_coeffs); a failed check makes the problem unusable until the next

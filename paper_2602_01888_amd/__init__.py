@@ -192,6 +192,15 @@ class Problem:
         """tomg_update_rhs_desc: a new source on the map of the last setup_desc."""
         self._check(self.lib.tomg_update_rhs_desc(self._h, C.byref(source)), "update_rhs_desc")
 
+    def residual_history(self):
+        """tomg_residual_history: relative residuals of the last solve, at its
+        start and after each cycle (up to 256 entries)."""
+        buf = (C.c_double * 256)()
+        cnt = C.c_int32()
+        self._check(self.lib.tomg_residual_history(self._h, buf, 256, C.byref(cnt)),
+                    "residual_history")
+        return list(buf[:cnt.value])
+
     def setup_check(self):
         """Raises TomgError if the last (asynchronous) setup failed its checks."""
         self._check(self.lib.tomg_setup_check(self._h), "setup_check")

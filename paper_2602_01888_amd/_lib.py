@@ -28,7 +28,7 @@ EXPORTS = ["tomg_config_default", "tomg_num_levels", "tomg_workspace_bytes", "to
            "tomg_batch_step", "tomg_batch_launch", "tomg_field", "tomg_laplace_grid",
            "tomg_export", "tomg_level_shape", "tomg_smooth", "tomg_residual", "tomg_profile",
            "tomg_profile_read", "tomg_copy_probe", "tomg_solve_noalloc",
-           "tomg_setup_coeffs_desc", "tomg_update_rhs_desc"]
+           "tomg_setup_coeffs_desc", "tomg_update_rhs_desc", "tomg_residual_history"]
 
 TOMG_MAP_SINUSOIDAL, TOMG_MAP_PERTURBED_CIRCLE, TOMG_MAP_POLAR = 1, 2, 3
 TOMG_MAX_GAUSSIANS = 16
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
         "tomg_setup_coeffs_desc": (C.c_int, [P, C.POINTER(MapDesc), C.POINTER(SourceDesc), VP,
                                              C.c_uint32]),
         "tomg_update_rhs_desc": (C.c_int, [P, C.POINTER(SourceDesc)]),
+        "tomg_residual_history": (C.c_int, [P, C.POINTER(D), I32, C.POINTER(I32)]),
         "tomg_solve_noalloc": (C.c_int, [cfgp, VP, VP, VP, VP, VP, VP, VP, D, I32, VP,
                                          C.POINTER(I32), C.POINTER(D), C.c_char_p,
                                          C.c_size_t]),

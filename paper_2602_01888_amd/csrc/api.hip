@@ -76,7 +76,7 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
     return at;
   };
   const size_t n0 = (size_t)cfg.nx * cfg.ny;
-  o.scal = take(kNumSlots * sizeof(double));
+  o.scal = take((kNumSlots + kHistMax) * sizeof(double));
   const size_t nparts = std::max({(size_t)2 * kRedBlocks, fused_max_blocks(cfg.nx, cfg.ny),
                                   (size_t)2 * red_tiles(cfg.nx, cfg.ny)});
   o.partials = take(nparts * sizeof(double));
@@ -472,6 +472,18 @@ tomg_status tomg_update_rhs_desc(tomg_problem *p, const tomg_source_desc *src) {
   if (const char *e = source_desc_error(src))
     return fail(p, TOMG_EINVAL, "update_rhs_desc: %s", e);
   HIP_TRY(p, launch_update_rhs_desc(p, p->map, *src));
+  return TOMG_OK;
+}
+
+tomg_status tomg_residual_history(tomg_problem *p, double *out, int32_t cap, int32_t *count) {
+  if (!p || (cap > 0 && !out) || cap < 0) return TOMG_EINVAL;
+  double h[kNumSlots + kHistMax];
+  HIP_TRY(p, hipMemcpyAsync(h, p->scal, sizeof h, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  const double c = h[kSlotCycles];
+  const int n = std::isfinite(c) && c >= 0.0 ? (int)std::min(c + 1.0, (double)kHistMax) : 0;
+  for (int k = 0; k < n && k < cap; ++k) out[k] = h[kNumSlots + k];
+  if (count) *count = n;
   return TOMG_OK;
 }
 

@@ -181,6 +181,14 @@ __device__ __forceinline__ double rel_residual(double v, double b0, double r0) {
   return v / (b0 > 0.0 ? b0 : r0);
 }
 
+// The residual history after the scalar slots: entry 0 at the start of a
+// solve, entry c after its cycle c (cycles counted in kSlotCycles, which
+// the start of a batched solve resets; a single solve resets it itself).
+__device__ __forceinline__ void record_history(double *scal, int rel, double r) {
+  const int c = rel == kRelBegin ? 0 : (int)scal[kSlotCycles];
+  if (c >= 0 && c < kHistMax) scal[kNumSlots + c] = r;
+}
+
 // One block: fixed-order reduction of n partials into out[0].
 // OP 0 sum, 1 min, 2 max; do_sqrt takes the square root of the result.
 // rel == kRelBegin (the initial norms of a solve): out[0] is also recorded as
@@ -204,6 +212,7 @@ __global__ void k_finalize(const double *partials, int n, int stride, double *ou
       scal[kSlotRel] = r;
       scal[kSlotDone] = (r <= scal[kSlotTol]) ? 1.0 : 0.0;
       if (rel == kRelCycle) scal[kSlotCycles] += 1.0;
+      record_history(scal, rel, r);
     }
   }
 }
@@ -1838,6 +1847,9 @@ __global__ void k_finalize_b(BatchTab tab, int rel, double *out) {
         r = NAN;
       a.scal[kSlotRel] = r;
       a.scal[kSlotDone] = (r <= a.scal[kSlotTol]) ? 1.0 : 0.0;
+      if (rel == kRelBegin) a.scal[kSlotCycles] = 0.0;
+      if (rel == kRelCycle) a.scal[kSlotCycles] += 1.0;
+      record_history(a.scal, rel, r);
       out[e.out] = r;
     }
   }

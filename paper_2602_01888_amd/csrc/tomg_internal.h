@@ -37,6 +37,11 @@ enum Slot {
                     // denominator of the relative residual when kSlotB0 is 0)
   kNumSlots = 16
 };
+// After the slots: the relative residual at the start of the last solve and
+// after each of its cycles (the first kHistMax), for tomg_residual_history.
+enum {
+  kHistMax = 256
+};
 
 // Modes of the relative-residual bookkeeping of a finalize: none; the
 // initial norms of a solve (also records kSlotR0); after a cycle.

@@ -118,6 +118,9 @@ class Completion:
     admitted: float
     done: float
     warm_start: bool          # started from a resident geometry's last solution
+    queue_depth: int = 0      # requests still queued when this one was admitted
+    hbm_used: int = 0         # bytes the server held once this request was admitted
+    #                           (its geometries, this request's included)
     phi: object = None        # copy of the solution (keep_results=True)
     phi_start: object = None  # copy of the initial guess (keep_results=True)
     error: str = ""           # why a request failed before its first step
@@ -151,6 +154,8 @@ class _Active:
     cycles: int = 0
     rel: float = math.inf
     phi_start: object = None
+    queue_depth: int = 0
+    hbm_used: int = 0
 
 
 class TomgBackend:
@@ -356,6 +361,8 @@ class Server:
                 self.used += need
                 act = _Active(req, res, now, warm_start=False)
                 self.stats["cold"] += 1
+            act.queue_depth = len(self.queue) + len(passed)
+            act.hbm_used = self.used
             if self.keep:
                 act.phi_start = self.backend.copy(res.phi)
             self.active.append(act)
@@ -429,7 +436,7 @@ class Server:
                 keep.append(a)
                 continue
             c = Completion(a.req.rid, st, a.cycles, r, a.req.arrival, a.admitted, t,
-                           a.warm_start, error=err)
+                           a.warm_start, a.queue_depth, a.hbm_used, error=err)
             if self.keep:
                 c.phi = self.backend.copy(a.res.phi)
                 c.phi_start = a.phi_start

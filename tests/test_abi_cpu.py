@@ -146,7 +146,7 @@ def test_null_problem_calls(lib):
 PAPER_CALLS = ["setup_coeffs", "tomg_setup_coeffs_async", "tomg_update_rhs", "vcycle", "solve",
                "residual_norm", "tomg_solve_batch", "tomg_batch_step", "tomg_batch_launch",
                "tomg_laplace_grid", "tomg_field", "tomg_setup_coeffs_desc",
-               "tomg_update_rhs_desc"]
+               "tomg_update_rhs_desc", "tomg_residual_history"]
 
 
 def declaration_comments():

@@ -397,3 +397,19 @@ def test_serial_backend_is_not_pipelined():
     assert not s.pipeline
     s = S.Server(PipeBackend(), budget_bytes=10 ** 6, pipeline=False)
     assert not s.pipeline
+
+
+def test_completion_records_queue_depth_and_hbm_in_use():
+    """Each completion carries the queue depth and the bytes the server held
+    when its request was admitted (the per-request serving record)."""
+    be = FakeBackend(rate=0.1, bytes_per_node=10)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, max_active=2, clock=Clock())
+    for k in range(5):
+        s.submit(req(k))
+    done = {c.rid: c for c in s.drain()}
+    assert done[0].queue_depth == 4 and done[0].hbm_used == 1000
+    assert done[1].queue_depth == 3 and done[1].hbm_used == 2000
+    # later requests are admitted once the first two retire (their
+    # geometries stay resident: the server holds their bytes too)
+    assert done[2].queue_depth <= 2 and done[2].hbm_used >= 3000
+    assert all(c.admitted >= c.arrival for c in done.values())
