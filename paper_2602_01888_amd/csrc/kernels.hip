@@ -1763,7 +1763,6 @@ __device__ __forceinline__ void ir_update_body(const RedArgs &a, double *phi, in
   }
 }
 
-// ST: the problem has a stored level-0 stencil (a.st0).
 // phi = a.phi2 over the tile (the whole grid).
 __device__ __forceinline__ void copy_back_body(const RedArgs &a, double *phi, int t) {
   const int tx = (a.nx + kRedCols - 1) / kRedCols;
@@ -1778,16 +1777,35 @@ __device__ __forceinline__ void copy_back_body(const RedArgs &a, double *phi, in
   }
 }
 
+// The tile of block b among the n blocks [start, start + n) of a problem:
+// the device hands blocks to its eight XCDs round-robin (block b to XCD
+// b mod 8), so numbering each XCD's blocks consecutively gives each XCD a
+// contiguous run of tiles, whose shared halo lines then come from that
+// XCD's L2 once.  A bijection onto [0, n): each tile's partial sum, and so
+// the reduction, is the same whatever block computes it.
+__device__ __forceinline__ int xcd_tile_of(int b, int start, int n) {
+  auto first = [&](int y) { return start + (((y - start) % 8) + 8) % 8; };
+  auto count = [&](int y) {
+    const int f = first(y);
+    return f < start + n ? (start + n - 1 - f) / 8 + 1 : 0;
+  };
+  const int x = b & 7;
+  int off = 0;
+  for (int y = 0; y < x; ++y) off += count(y);
+  return off + (b - first(x)) / 8;
+}
+
+// ST: the problem has a stored level-0 stencil (a.st0).
 template <int M, bool ST>
 __global__ void __launch_bounds__(kRedTileW) k_red(RedArgs a, const double *x, double *xo,
                                                    const double *skip) {
   if (skip && *skip != 0.0) return;
-  red_tile<M, ST>(a, x, xo, blockIdx.x);
+  red_tile<M, ST>(a, x, xo, xcd_tile_of(blockIdx.x, 0, gridDim.x));
 }
 __global__ void __launch_bounds__(kRedTileW) k_ir_update(RedArgs a, double *phi,
                                                          const double *skip) {
   if (skip && *skip != 0.0) return;
-  ir_update_body(a, phi, blockIdx.x);
+  ir_update_body(a, phi, xcd_tile_of(blockIdx.x, 0, gridDim.x));
 }
 
 __device__ __forceinline__ const BatchEntry &locate(const BatchTab &tab, int b) {
@@ -1809,7 +1827,7 @@ template <int KIND, bool ST>
 __global__ void __launch_bounds__(kRedTileW) k_red_b(BatchTab tab) {
   const BatchEntry &e = locate(tab, blockIdx.x);
   const RedArgs &a = *static_cast<const RedArgs *>(e.args);
-  const int t = blockIdx.x - e.start;
+  const int t = xcd_tile_of(blockIdx.x, e.start, e.nbx);
   double *phi = static_cast<double *>(e.phi);
   if constexpr (KIND == -2) {
     copy_back_body(a, phi, t);
