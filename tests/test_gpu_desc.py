@@ -224,3 +224,22 @@ def test_async_desc_batch(env, precision):
         assert r.ok, r
         err = (phi - ref).abs().max().item() / max(ref.abs().max().item(), 1.0)
         assert err < 1e-9, err
+
+
+def test_async_desc_setup_reports_a_folded_map_later(env):
+    """A descriptor setup queued without the host check (TOMG_SETUP_ASYNC):
+    a folded map is reported by setup_check, and the problem works again
+    after a good setup."""
+    torch, tomg, D = env
+    n = 129
+    d = 1.0 / (n - 1)
+    p = tomg.Problem(n, n, d, d)
+    s = tomg.source_desc([1.0], [(0.4, 0.6)], 0.05)
+    phi = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    p.setup_desc(tomg.map_desc("sinusoidal", amp=0.5), s, phi_init=phi, check=False)
+    with pytest.raises(tomg.TomgError) as e:
+        p.setup_check()
+    assert e.value.status == tomg.TOMG_EGEOMETRY
+    p.setup_desc(tomg.map_desc("sinusoidal", amp=0.1), s, phi_init=phi, check=False)
+    p.setup_check()
+    assert p.solve(phi, rel_tol=1e-10).ok

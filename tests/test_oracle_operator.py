@@ -270,5 +270,7 @@ def test_level_hierarchy():
     assert len(oracle.levels(4097, 4097)) == 10
     assert oracle.levels(129, 65)[-1] == (9, 5)
     assert oracle.levels(9, 9) == [(9, 9), (5, 5)]
-    assert oracle.levels(201, 201) == []  # 200 = 8 * 25 never reaches 9 nodes
+    # 200 = 8 * 25 stops halving at 26 nodes: kept as a large coarsest level
+    assert oracle.levels(201, 201)[-1] == (26, 26)
+    assert oracle.levels(1001, 1001) == []  # would stop at 126 x 126: refused
     assert oracle.levels(3, 3) == []
