@@ -441,6 +441,8 @@ __global__ void k_field(int nx, int ny, double dx, double dy, const double *__re
   const size_t n = (size_t)nx * ny;
   const double i2dx = 0.5 / dx, i2dy = 0.5 / dy;
   const bool small = n < (size_t(1) << 32);
+  // four nodes per trip, so that their loads are in flight together
+#pragma unroll 4
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x) {
     int i, j;
