@@ -51,6 +51,13 @@ def _load():
         "orc_restrict_fw_bc": (None, [i, i, _D, i, i, _U8, _D]),
         "orc_prolong_add": (None, [i, i, _D, i, i, _U8, _D]),
         "orc_galerkin": (None, [i, i, _D, _U8, i, i, _D, _U8]),
+        "orc_restrict_s": (None, [i, i, _D, i, i, i, i, _U8, _D]),
+        "orc_prolong_add_s": (None, [i, i, _D, i, i, i, i, _U8, _D]),
+        "orc_galerkin_s": (None, [i, i, _D, _U8, i, i, i, i, _D, _U8]),
+        "orc_levels_semi": (i, [i, i, i, i, C.POINTER(i), C.POINTER(i), C.POINTER(i),
+                                C.POINTER(i), i, i]),
+        "orc_mg_create_semi": (p, [i, i, d, d, _D, _D, _D, _U8, i, i, i, i, i, i, i, i, d]),
+        "orc_mg_level_strides": (None, [p, i, C.POINTER(i), C.POINTER(i)]),
         "orc_dense_solve": (i, [i, _D, _D]),
         "orc_levels": (i, [i, i, C.POINTER(i), C.POINTER(i), i]),
         "orc_levels_lim": (i, [i, i, C.POINTER(i), C.POINTER(i), i, i]),
@@ -265,6 +272,44 @@ def galerkin(stf, dirf, nxc, nyc):
     return stc, dirc
 
 
+def coarse_shape(nxf, nyf, sx, sy):
+    """Coarse grid of a transfer with strides (sx, sy): a halved axis (stride
+    2) keeps every other node, a kept axis (stride 1) every node."""
+    return ((nxf - 1) // 2 + 1 if sx == 2 else nxf, (nyf - 1) // 2 + 1 if sy == 2 else nyf)
+
+
+def restrict_s(rf, sx, sy, dirc=None):
+    """Restriction P^T / (sx sy) with per-axis strides (semi-coarsening when
+    one of them is 1); dirc None gives zero on the whole coarse ring."""
+    rf = _f64(rf)
+    nyf, nxf = rf.shape
+    nxc, nyc = coarse_shape(nxf, nyf, sx, sy)
+    fc = np.empty((nyc, nxc))
+    dc = None if dirc is None else np.ascontiguousarray(dirc, dtype=np.uint8)
+    _load().orc_restrict_s(nxf, nyf, _d(rf), nxc, nyc, sx, sy, _u8(dc), _d(fc))
+    return fc
+
+
+def prolong_add_s(ec, xf, dirf, sx, sy):
+    ec = _f64(ec)
+    xf = _f64(xf).copy()
+    nyc, nxc = ec.shape
+    nyf, nxf = xf.shape
+    _load().orc_prolong_add_s(nxc, nyc, _d(ec), nxf, nyf, sx, sy, _u8(dirf), _d(xf))
+    return xf
+
+
+def galerkin_s(stf, dirf, sx, sy):
+    """(1 / (sx sy)) P^T A P with per-axis strides; returns (stencil, flags)."""
+    stf = _f64(stf)
+    _, nyf, nxf = stf.shape
+    nxc, nyc = coarse_shape(nxf, nyf, sx, sy)
+    stc = np.empty((9, nyc, nxc))
+    dirc = np.empty((nyc, nxc), dtype=np.uint8)
+    _load().orc_galerkin_s(nxf, nyf, _d(stf), _u8(dirf), nxc, nyc, sx, sy, _d(stc), _u8(dirc))
+    return stc, dirc
+
+
 def dense_solve(A, b):
     A = _f64(A).copy()
     b = _f64(b).copy()
@@ -274,13 +319,17 @@ def dense_solve(A, b):
     return b
 
 
-def levels(nx, ny, maxl=16, neumann=0):
+def levels(nx, ny, maxl=16, neumann=0, semi=0, semi_axis=0):
     """Level shapes; with Neumann edges the coarsest is at most 5 x 5 where
     halving reaches it, else at most 1024 nodes (the 201 x 201 family stops
-    at 26 x 26)."""
+    at 26 x 26).  semi: the first coarsenings halve axis semi_axis only."""
     a = (C.c_int * maxl)()
     b = (C.c_int * maxl)()
-    L = _load().orc_levels_lim(nx, ny, a, b, maxl, 5 if neumann else 9)
+    if semi:
+        L = _load().orc_levels_semi(nx, ny, semi, semi_axis, a, b, None, None, maxl,
+                                    5 if neumann else 9)
+    else:
+        L = _load().orc_levels_lim(nx, ny, a, b, maxl, 5 if neumann else 9)
     return [(a[k], b[k]) for k in range(L)]
 
 
@@ -303,15 +352,16 @@ class MG:
     edges and the eq. 18 form only)."""
 
     def __init__(self, exx, exy, eyy, dx, dy, mask=None, nu1=2, nu2=2, smoother=GS4,
-                 omega=0.8, neumann=0, flux=False, coarse_op=GALERKIN):
+                 omega=0.8, neumann=0, flux=False, coarse_op=GALERKIN, semi=0, semi_axis=0):
         self._keep = [_f64(exx), _f64(exy), _f64(eyy)]
         ny, nx = self._keep[0].shape
         m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         self.nx, self.ny = nx, ny
-        self._h = _load().orc_mg_create_full(nx, ny, dx, dy, _d(self._keep[0]),
+        self._h = _load().orc_mg_create_semi(nx, ny, dx, dy, _d(self._keep[0]),
                                              _d(self._keep[1]), _d(self._keep[2]), _u8(m),
                                              int(neumann), 1 if flux else 0, int(coarse_op),
-                                             nu1, nu2, smoother, omega)
+                                             int(semi), int(semi_axis), nu1, nu2, smoother,
+                                             omega)
         if not self._h:
             raise ValueError(f"grid {nx}x{ny}: does not coarsen to <= 9x9 nodes, or the "
                              f"coarse operator does not apply to this problem")
@@ -334,6 +384,12 @@ class MG:
     def shape(self, l):
         a, b = C.c_int(), C.c_int()
         _load().orc_mg_level_shape(self._h, l, C.byref(a), C.byref(b))
+        return a.value, b.value
+
+    def strides(self, l):
+        """Strides (sx, sy) of the transfer from level l to level l + 1."""
+        a, b = C.c_int(), C.c_int()
+        _load().orc_mg_level_strides(self._h, l, C.byref(a), C.byref(b))
         return a.value, b.value
 
     def _view(self, ptr, shape, dtype):
@@ -410,12 +466,14 @@ def generate_grid(xb, yb, dx, dy, rel_tol=1e-13, max_cycles=200, mask=None, px=N
 
 
 def solve_problem(prob, rel_tol=1e-10, max_cycles=200, smoother=GS4, nu1=2, nu2=2,
-                  eps_phys=None, hist_len=0, flux=False, coarse_op=GALERKIN):
+                  eps_phys=None, hist_len=0, flux=False, coarse_op=GALERKIN, semi=0,
+                  semi_axis=0):
     """Setup plus multigrid solve of a ``workloads.GridProblem`` from its
     ``phi0``.  Returns a dict with phi, cycles, rel, status and the setup."""
     s = setup(prob, eps_phys)
     mg = MG.from_setup(s, prob.dx, prob.dy, mask=prob.mask, nu1=nu1, nu2=nu2,
-                       smoother=smoother, flux=flux, coarse_op=coarse_op)
+                       smoother=smoother, flux=flux, coarse_op=coarse_op, semi=semi,
+                       semi_axis=semi_axis)
     phi, status, cycles, rel, hist = mg.solve(prob.phi0, s["f"], rel_tol, max_cycles, hist_len)
     return {"phi": phi, "status": status, "cycles": cycles, "rel": rel, "hist": hist,
             "setup": s, "mg": mg}

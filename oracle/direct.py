@@ -84,6 +84,29 @@ def bilinear_P(nxc, nyc, nxf, nyf):
     return sp.csr_matrix((vals, (rows, cols)), shape=(nxf * nyf, nxc * nyc))
 
 
+def linear_P_1d(nf, halved):
+    """One axis of a prolongation: linear interpolation from the (nf-1)/2+1
+    coarse nodes of a halved axis (coarse node K at fine node 2K), or the
+    identity for an axis that keeps every node."""
+    if not halved:
+        return sp.identity(nf, format="csr")
+    nc = (nf - 1) // 2 + 1
+    M = sp.lil_matrix((nf, nc))
+    for K in range(nc):
+        M[2 * K, K] = 1.0
+        if 2 * K - 1 >= 0:
+            M[2 * K - 1, K] = 0.5
+        if 2 * K + 1 < nf:
+            M[2 * K + 1, K] = 0.5
+    return M.tocsr()
+
+
+def tensor_P(nxf, nyf, sx, sy):
+    """Prolongation with per-axis strides (2 halved, 1 kept) as the
+    Kronecker product of the axis matrices (x fastest in the node order)."""
+    return sp.kron(linear_P_1d(nyf, sy == 2), linear_P_1d(nxf, sx == 2), format="csr")
+
+
 def five_point_laplacian(n, h):
     """Textbook 5-point Laplacian on the (n-2)^2 interior nodes of an n x n
     grid (x fastest), built as kron(I, T) + kron(T, I) with

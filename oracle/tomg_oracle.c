@@ -529,80 +529,108 @@ void orc_smooth(int nx, int ny, const double *st, const uint8_t *dir, double *x,
  * d = fine index - 2 * coarse index along one axis. */
 static double pw(int d) { return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0; }
 
-/* Full-weighting restriction I_h^H (the paper does not name one):
- * r_H(I,J) = (1/16) [4 r(2I,2J) + 2 (edge neighbours) + (corner neighbours)],
- * at coarse interior nodes; zero on the coarse outer ring.  This is the
- * transpose of bilinear prolongation divided by 4. */
-void orc_restrict_fw(int nxf, int nyf, const double *rf, int nxc, int nyc, double *fc) {
-  (void)nyf;
-  for (int J = 0; J < nyc; ++J)
-    for (int I = 0; I < nxc; ++I) {
-      double s = 0.0;
-      if (I > 0 && J > 0 && I < nxc - 1 && J < nyc - 1)
-        for (int dj = -1; dj <= 1; ++dj)
-          for (int di = -1; di <= 1; ++di)
-            s += pw(di) * pw(dj) / 4.0 * rf[ID(2 * I + di, 2 * J + dj, nxf)];
-      fc[ID(I, J, nxc)] = s;
-    }
-}
+/* Semi-coarsening (not in the paper, which halves both axes): a coarse grid
+ * may also be halved along one axis only, the other axis keeping every fine
+ * line.  Each transfer below takes a stride per axis -- 2 for an axis that is
+ * halved, 1 for one that is kept -- and the interpolation weight along an
+ * axis is the linear weight pw for stride 2 and the identity for stride 1.
+ * P is the tensor product of the two axis weights; the restriction is
+ * P^T / (sx sy) (full weighting along the halved axes) and the coarse
+ * operator (1 / (sx sy)) P^T A_h P, so that with both strides 2 every
+ * formula below is the one of the full coarsening. */
+static double tw(int s, int d) { return s == 2 ? pw(d) : (d == 0 ? 1.0 : 0.0); }
+/* Coarse indices K of an axis of stride s with a non-zero weight at fine
+ * index g: K = g/2 .. (g+1)/2 for stride 2, K = g for stride 1. */
+static int klo(int s, int g) { return s == 2 ? g / 2 : g; }
+static int khi(int s, int g) { return s == 2 ? (g + 1) / 2 : g; }
 
-/* The same restriction where the coarse outer ring may hold free nodes (a
- * Neumann edge): at a free ring node the sum runs over the fine nodes of its
- * support that lie inside the grid (the transpose of the prolongation, which
- * has no fine nodes outside); Dirichlet ring nodes get zero. */
-void orc_restrict_fw_bc(int nxf, int nyf, const double *rf, int nxc, int nyc,
-                        const uint8_t *dirc, double *fc) {
+/* Restriction I_h^H = P^T / (sx sy) (the paper does not name one).  With
+ * both strides 2 it is full weighting,
+ * r_H(I,J) = (1/16) [4 r(2I,2J) + 2 (edge neighbours) + (corner neighbours)];
+ * with one stride 1 it is full weighting along the halved axis alone,
+ * (1/4) [r(2I-1) + 2 r(2I) + r(2I+1)] on the coarse node's fine line.
+ * Interior coarse nodes take the sum; on the coarse outer ring a free node
+ * (a Neumann edge, when dirc is given) sums over the fine nodes of its
+ * support that lie inside the grid (the transpose of the prolongation,
+ * which has no fine nodes outside), and every other ring node gets zero. */
+void orc_restrict_s(int nxf, int nyf, const double *rf, int nxc, int nyc, int sx, int sy,
+                    const uint8_t *dirc, double *fc) {
+  const double scale = (double)(sx * sy);
   for (int J = 0; J < nyc; ++J)
     for (int I = 0; I < nxc; ++I) {
       double s = 0.0;
       int ring = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1);
-      if (!ring || !dirc[ID(I, J, nxc)])
+      if (!ring || (dirc && !dirc[ID(I, J, nxc)]))
         for (int dj = -1; dj <= 1; ++dj)
           for (int di = -1; di <= 1; ++di) {
-            int fi = 2 * I + di, fj = 2 * J + dj;
+            double w = tw(sx, di) * tw(sy, dj);
+            if (w == 0.0) continue;
+            int fi = sx * I + di, fj = sy * J + dj;
             if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
-            s += pw(di) * pw(dj) / 4.0 * rf[ID(fi, fj, nxf)];
+            s += w / scale * rf[ID(fi, fj, nxf)];
           }
       fc[ID(I, J, nxc)] = s;
     }
 }
 
-/* Bilinear prolongation I_H^h and the correction of eq. 24, applied at free
- * fine nodes only (Dirichlet values are never changed). */
-void orc_prolong_add(int nxc, int nyc, const double *ec, int nxf, int nyf,
-                     const uint8_t *dirf, double *xf) {
+/* Full weighting at coarse interior nodes, zero on the coarse outer ring. */
+void orc_restrict_fw(int nxf, int nyf, const double *rf, int nxc, int nyc, double *fc) {
+  orc_restrict_s(nxf, nyf, rf, nxc, nyc, 2, 2, NULL, fc);
+}
+
+/* Full weighting where the coarse outer ring may hold free nodes (a
+ * Neumann edge). */
+void orc_restrict_fw_bc(int nxf, int nyf, const double *rf, int nxc, int nyc,
+                        const uint8_t *dirc, double *fc) {
+  orc_restrict_s(nxf, nyf, rf, nxc, nyc, 2, 2, dirc, fc);
+}
+
+/* Prolongation I_H^h (bilinear for strides 2, 2; linear along the halved
+ * axis for a semi-coarsened level) and the correction of eq. 24, applied at
+ * free fine nodes only (Dirichlet values are never changed). */
+void orc_prolong_add_s(int nxc, int nyc, const double *ec, int nxf, int nyf, int sx, int sy,
+                       const uint8_t *dirf, double *xf) {
   (void)nyc;
   for (int j = 0; j < nyf; ++j)
     for (int i = 0; i < nxf; ++i) {
       if (dirf[ID(i, j, nxf)]) continue;
       double s = 0.0;
-      for (int J = j / 2; J <= (j + 1) / 2; ++J)
-        for (int I = i / 2; I <= (i + 1) / 2; ++I)
-          s += pw(i - 2 * I) * pw(j - 2 * J) * ec[ID(I, J, nxc)];
+      for (int J = klo(sy, j); J <= khi(sy, j); ++J)
+        for (int I = klo(sx, i); I <= khi(sx, i); ++I)
+          s += tw(sx, i - sx * I) * tw(sy, j - sy * J) * ec[ID(I, J, nxc)];
       xf[ID(i, j, nxf)] += s;
     }
 }
 
+void orc_prolong_add(int nxc, int nyc, const double *ec, int nxf, int nyf,
+                     const uint8_t *dirf, double *xf) {
+  orc_prolong_add_s(nxc, nyc, ec, nxf, nyf, 2, 2, dirf, xf);
+}
+
 /* Coarse operator of eq. 23.  The paper does not say how A_H is formed; the
- * reading taken is the Galerkin product A_H = (1/4) P^T A_h P with P the
- * bilinear prolongation restricted to the unknowns: rows of P at fine
- * Dirichlet nodes are zero, and only coarse nodes that are not Dirichlet
- * carry a column.  A coarse node is Dirichlet when it lies on the coarse
- * outer ring or when every fine node it interpolates to is Dirichlet (its
- * column of P would be empty); such nodes get an identity row. */
-void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
-                  int nxc, int nyc, double *stc, uint8_t *dirc) {
+ * reading taken is the Galerkin product A_H = (1/(sx sy)) P^T A_h P with P
+ * the prolongation of the level (bilinear for the full coarsening, so the
+ * factor is 1/4) restricted to the unknowns: rows of P at fine Dirichlet
+ * nodes are zero, and only coarse nodes that are not Dirichlet carry a
+ * column.  A coarse node is Dirichlet when it lies on the coarse outer ring
+ * or when every fine node it interpolates to is Dirichlet (its column of P
+ * would be empty); such nodes get an identity row. */
+void orc_galerkin_s(int nxf, int nyf, const double *stf, const uint8_t *dirf, int nxc,
+                    int nyc, int sx, int sy, double *stc, uint8_t *dirc) {
   size_t nf = (size_t)nxf * nyf, nc = (size_t)nxc * nyc;
+  const double scale = (double)(sx * sy);
   for (int J = 0; J < nyc; ++J)
     for (int I = 0; I < nxc; ++I) {
       /* on the ring the coarse node keeps the kind of the fine node it sits
        * on (Dirichlet, or free on a Neumann edge) */
-      int d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1) && dirf[ID(2 * I, 2 * J, nxf)];
+      int d = (I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1) &&
+              dirf[ID(sx * I, sy * J, nxf)];
       if (!d) {
         int any_free = 0;
         for (int dj = -1; dj <= 1; ++dj)
           for (int di = -1; di <= 1; ++di) {
-            int fi = 2 * I + di, fj = 2 * J + dj;
+            if (tw(sx, di) * tw(sy, dj) == 0.0) continue;
+            int fi = sx * I + di, fj = sy * J + dj;
             if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
             if (!dirf[ID(fi, fj, nxf)]) any_free = 1;
           }
@@ -620,14 +648,16 @@ void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
         continue;
       }
       double acc[9] = {0};
-      /* row I of P^T: fine nodes f = (2I+a, 2J+b) with weight pw(a) pw(b) */
+      /* row C of P^T: fine nodes f = (sx I + a, sy J + b) with weight
+       * tw(sx, a) tw(sy, b) */
       for (int b = -1; b <= 1; ++b)
         for (int a = -1; a <= 1; ++a) {
-          int fi = 2 * I + a, fj = 2 * J + b;
+          double wf = tw(sx, a) * tw(sy, b);
+          if (wf == 0.0) continue;
+          int fi = sx * I + a, fj = sy * J + b;
           if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
           size_t f = ID(fi, fj, nxf);
           if (dirf[f]) continue;
-          double wf = pw(a) * pw(b);
           /* row f of A_h: neighbours g = f + (p, q) */
           for (int q = -1; q <= 1; ++q)
             for (int p = -1; p <= 1; ++p) {
@@ -636,19 +666,24 @@ void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
               size_t g = ID(gi, gj, nxf);
               if (dirf[g]) continue;
               double a_fg = PLANE(stf, (q + 1) * 3 + (p + 1), nf)[f];
-              /* column K of P: coarse nodes K with |g - 2K| <= 1 */
-              for (int KJ = gj / 2; KJ <= (gj + 1) / 2; ++KJ)
-                for (int KI = gi / 2; KI <= (gi + 1) / 2; ++KI) {
+              /* column K of P: coarse nodes K with a weight at g */
+              for (int KJ = klo(sy, gj); KJ <= khi(sy, gj); ++KJ)
+                for (int KI = klo(sx, gi); KI <= khi(sx, gi); ++KI) {
                   int oi = KI - I, oj = KJ - J;
                   if (oi < -1 || oi > 1 || oj < -1 || oj > 1) continue;
                   if (dirc[ID(KI, KJ, nxc)]) continue;
-                  double wg = pw(gi - 2 * KI) * pw(gj - 2 * KJ);
+                  double wg = tw(sx, gi - sx * KI) * tw(sy, gj - sy * KJ);
                   acc[(oj + 1) * 3 + (oi + 1)] += wf * a_fg * wg;
                 }
             }
         }
-      for (int k = 0; k < 9; ++k) PLANE(stc, k, nc)[C] = acc[k] / 4.0;
+      for (int k = 0; k < 9; ++k) PLANE(stc, k, nc)[C] = acc[k] / scale;
     }
+}
+
+void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
+                  int nxc, int nyc, double *stc, uint8_t *dirc) {
+  orc_galerkin_s(nxf, nyf, stf, dirf, nxc, nyc, 2, 2, stc, dirc);
 }
 
 int orc_dense_solve(int m, double *A, double *b) {
@@ -702,20 +737,41 @@ int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl) {
  * system as small as the all-Dirichlet 9 x 9 one (at most 49 unknowns
  * there, at most 25 here). */
 int orc_levels_lim(int nx, int ny, int *nxs, int *nys, int maxl, int lim) {
+  return orc_levels_semi(nx, ny, 0, 0, nxs, nys, NULL, NULL, maxl, lim);
+}
+
+/* The same with the first `semi` coarsenings halving one axis only (axis 0:
+ * x, the node count nx; axis 1: y), each of them required (the grid is
+ * refused when that axis cannot be halved); the rule above then goes on
+ * from the last semi-coarsened grid.  sxs[l], sys[l] (nullable) receive
+ * the strides of the transfer from level l to level l + 1. */
+int orc_levels_semi(int nx, int ny, int semi, int axis, int *nxs, int *nys, int *sxs, int *sys,
+                    int maxl, int lim) {
   int L = 1;
   nxs[0] = nx;
   nys[0] = ny;
-  if (nx < 5 || ny < 5) return 0;
+  if (nx < 5 || ny < 5 || semi < 0 || axis < 0 || axis > 1) return 0;
   while (L < maxl) {
     int cx = nxs[L - 1], cy = nys[L - 1];
-    int can = ((cx - 1) % 2 == 0) && ((cy - 1) % 2 == 0) && cx >= 5 && cy >= 5;
-    int want = (L == 1) || cx > lim || cy > lim;
-    if (!(can && want)) break;
-    nxs[L] = (cx - 1) / 2 + 1;
-    nys[L] = (cy - 1) / 2 + 1;
+    int sx, sy;
+    if (L - 1 < semi) {
+      int c = axis == 0 ? cx : cy;
+      if ((c - 1) % 2 != 0 || c < 5) return 0;
+      sx = axis == 0 ? 2 : 1;
+      sy = axis == 0 ? 1 : 2;
+    } else {
+      int can = ((cx - 1) % 2 == 0) && ((cy - 1) % 2 == 0) && cx >= 5 && cy >= 5;
+      int want = (L == 1) || cx > lim || cy > lim;
+      if (!(can && want)) break;
+      sx = sy = 2;
+    }
+    nxs[L] = sx == 2 ? (cx - 1) / 2 + 1 : cx;
+    nys[L] = sy == 2 ? (cy - 1) / 2 + 1 : cy;
+    if (sxs) sxs[L - 1] = sx;
+    if (sys) sys[L - 1] = sy;
     ++L;
   }
-  if (L < 2) return 0;
+  if (L < 2 || L - 1 < semi) return 0;
   if ((nxs[L - 1] > lim || nys[L - 1] > lim) &&
       (long)nxs[L - 1] * nys[L - 1] > ORC_MAX_COARSE_NODES)
     return 0;
@@ -726,6 +782,7 @@ struct orc_mg {
   int L, nu1, nu2, smoother;
   double omega;
   int nx[ORC_MAXL], ny[ORC_MAXL];
+  int sx[ORC_MAXL], sy[ORC_MAXL]; /* strides of the transfer from level l to l + 1 */
   double *st[ORC_MAXL];
   uint8_t *dir[ORC_MAXL];
   double *x[ORC_MAXL], *b[ORC_MAXL], *r[ORC_MAXL];
@@ -783,10 +840,20 @@ orc_mg *orc_mg_create_full(int nx, int ny, double dx, double dy, const double *e
                            const double *exy, const double *eyy, const uint8_t *mask,
                            int neumann, int flux, int coarse_op, int nu1, int nu2, int smoother,
                            double omega) {
-  /* rediscretisation applies eq. 18 on every level: Dirichlet edges only */
-  if (coarse_op != 0 && (coarse_op != 1 || neumann != 0 || flux != 0)) return NULL;
+  return orc_mg_create_semi(nx, ny, dx, dy, exx, exy, eyy, mask, neumann, flux, coarse_op, 0, 0,
+                            nu1, nu2, smoother, omega);
+}
+
+orc_mg *orc_mg_create_semi(int nx, int ny, double dx, double dy, const double *exx,
+                           const double *exy, const double *eyy, const uint8_t *mask,
+                           int neumann, int flux, int coarse_op, int semi, int semi_axis,
+                           int nu1, int nu2, int smoother, double omega) {
+  /* rediscretisation applies eq. 18 on every level: Dirichlet edges and the
+   * full coarsening only */
+  if (coarse_op != 0 && (coarse_op != 1 || neumann != 0 || flux != 0 || semi != 0)) return NULL;
   orc_mg *mg = (orc_mg *)calloc(1, sizeof(orc_mg));
-  mg->L = orc_levels_lim(nx, ny, mg->nx, mg->ny, ORC_MAXL, neumann ? 5 : 9);
+  mg->L = orc_levels_semi(nx, ny, semi, semi_axis, mg->nx, mg->ny, mg->sx, mg->sy, ORC_MAXL,
+                          neumann ? 5 : 9);
   if (mg->L == 0) {
     free(mg);
     return NULL;
@@ -830,8 +897,8 @@ orc_mg *orc_mg_create_full(int nx, int ny, double dx, double dy, const double *e
       for (int k = 0; k < 3; ++k) free(t[q][k]);
   } else {
     for (int l = 1; l < mg->L; ++l)
-      orc_galerkin(mg->nx[l - 1], mg->ny[l - 1], mg->st[l - 1], mg->dir[l - 1], mg->nx[l],
-                   mg->ny[l], mg->st[l], mg->dir[l]);
+      orc_galerkin_s(mg->nx[l - 1], mg->ny[l - 1], mg->st[l - 1], mg->dir[l - 1], mg->nx[l],
+                     mg->ny[l], mg->sx[l - 1], mg->sy[l - 1], mg->st[l], mg->dir[l]);
   }
   /* coarsest dense system over its free nodes */
   int l = mg->L - 1, cx = mg->nx[l], cy = mg->ny[l];
@@ -877,6 +944,10 @@ void orc_mg_level_shape(const orc_mg *mg, int l, int *nx, int *ny) {
   *nx = mg->nx[l];
   *ny = mg->ny[l];
 }
+void orc_mg_level_strides(const orc_mg *mg, int l, int *sx, int *sy) {
+  *sx = mg->sx[l];
+  *sy = mg->sy[l];
+}
 const double *orc_mg_stencil(const orc_mg *mg, int l) { return mg->st[l]; }
 const uint8_t *orc_mg_dir(const orc_mg *mg, int l) { return mg->dir[l]; }
 const double *orc_mg_level_rhs(const orc_mg *mg, int l) { return mg->b[l]; }
@@ -907,11 +978,12 @@ static void vcycle_level(orc_mg *mg, int l, double *x, const double *b) {
   }
   orc_smooth(nx, ny, mg->st[l], mg->dir[l], x, b, mg->smoother, mg->nu1, mg->omega);
   orc_residual(nx, ny, mg->st[l], mg->dir[l], x, b, mg->r[l]);
-  orc_restrict_fw_bc(nx, ny, mg->r[l], mg->nx[l + 1], mg->ny[l + 1], mg->dir[l + 1],
-                     mg->b[l + 1]);
+  orc_restrict_s(nx, ny, mg->r[l], mg->nx[l + 1], mg->ny[l + 1], mg->sx[l], mg->sy[l],
+                 mg->dir[l + 1], mg->b[l + 1]);
   memset(mg->x[l + 1], 0, (size_t)mg->nx[l + 1] * mg->ny[l + 1] * sizeof(double));
   vcycle_level(mg, l + 1, mg->x[l + 1], mg->b[l + 1]);
-  orc_prolong_add(mg->nx[l + 1], mg->ny[l + 1], mg->x[l + 1], nx, ny, mg->dir[l], x);
+  orc_prolong_add_s(mg->nx[l + 1], mg->ny[l + 1], mg->x[l + 1], nx, ny, mg->sx[l], mg->sy[l],
+                    mg->dir[l], x);
   orc_smooth(nx, ny, mg->st[l], mg->dir[l], x, b, mg->smoother, mg->nu2, mg->omega);
 }
 

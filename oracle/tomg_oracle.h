@@ -91,6 +91,19 @@ void orc_prolong_add(int nxc, int nyc, const double *ec, int nxf, int nyf,
                      const uint8_t *dirf, double *xf);
 void orc_galerkin(int nxf, int nyf, const double *stf, const uint8_t *dirf,
                   int nxc, int nyc, double *stc, uint8_t *dirc);
+/* Semi-coarsening (an extension: the paper halves both axes): the same
+ * transfers and Galerkin product with a stride per axis, 2 for an axis that
+ * is halved and 1 for one that keeps every fine line; P is linear along a
+ * halved axis and the identity along a kept one, the restriction is
+ * P^T / (sx sy) and the coarse operator (1 / (sx sy)) P^T A P.  Strides
+ * (2, 2) give exactly the functions above.  dirc of orc_restrict_s is
+ * nullable (then every coarse ring node gets zero). */
+void orc_restrict_s(int nxf, int nyf, const double *rf, int nxc, int nyc, int sx, int sy,
+                    const uint8_t *dirc, double *fc);
+void orc_prolong_add_s(int nxc, int nyc, const double *ec, int nxf, int nyf, int sx, int sy,
+                       const uint8_t *dirf, double *xf);
+void orc_galerkin_s(int nxf, int nyf, const double *stf, const uint8_t *dirf, int nxc,
+                    int nyc, int sx, int sy, double *stc, uint8_t *dirc);
 
 /* Dense Gaussian elimination with partial pivoting; A (m*m, row-major) and
  * b are overwritten; the solution is left in b.  Returns 0, or -1 when a
@@ -104,6 +117,10 @@ typedef struct orc_mg orc_mg;
 #define ORC_MAX_COARSE_NODES 1024
 int orc_levels(int nx, int ny, int *nxs, int *nys, int maxl);
 int orc_levels_lim(int nx, int ny, int *nxs, int *nys, int maxl, int lim);
+/* The first `semi` coarsenings halve axis `semi_axis` only (0: x, 1: y);
+ * sxs/sys (nullable) receive the strides of each level's transfer. */
+int orc_levels_semi(int nx, int ny, int semi, int axis, int *nxs, int *nys, int *sxs, int *sys,
+                    int maxl, int lim);
 orc_mg *orc_mg_create(int nx, int ny, double dx, double dy, const double *exx,
                       const double *exy, const double *eyy, const uint8_t *mask,
                       int nu1, int nu2, int smoother, double omega);
@@ -122,9 +139,17 @@ orc_mg *orc_mg_create_full(int nx, int ny, double dx, double dy, const double *e
                            const double *exy, const double *eyy, const uint8_t *mask,
                            int neumann, int flux, int coarse_op, int nu1, int nu2, int smoother,
                            double omega);
+/* As orc_mg_create_full with the first `semi` coarsenings along axis
+ * `semi_axis` only (Galerkin coarse operators; NULL with rediscretisation). */
+orc_mg *orc_mg_create_semi(int nx, int ny, double dx, double dy, const double *exx,
+                           const double *exy, const double *eyy, const uint8_t *mask,
+                           int neumann, int flux, int coarse_op, int semi, int semi_axis,
+                           int nu1, int nu2, int smoother, double omega);
 void orc_mg_destroy(orc_mg *mg);
 int orc_mg_num_levels(const orc_mg *mg);
 void orc_mg_level_shape(const orc_mg *mg, int l, int *nx, int *ny);
+/* Strides of the transfer from level l to level l + 1. */
+void orc_mg_level_strides(const orc_mg *mg, int l, int *sx, int *sy);
 const double *orc_mg_stencil(const orc_mg *mg, int l);
 const uint8_t *orc_mg_dir(const orc_mg *mg, int l);
 void orc_mg_vcycle(orc_mg *mg, double *phi, const double *f);
