@@ -121,6 +121,25 @@ typedef struct {
                               and the eq. 18 form only (neumann = 0, flux = 0,
                               not TOMG_ZEBRA_XY).  The discrete solution does
                               not depend on it; the convergence rate does */
+  int32_t semi_levels;     /* semi-coarsening (an extension: Section 3 halves
+                              both axes): the first semi_levels coarsenings of
+                              the hierarchy halve axis semi_axis only and keep
+                              every line of the other, the rest halve both.
+                              The transfers are linear along the halved axis
+                              and the identity along the kept one, with
+                              restriction P^T / 2 and Galerkin coarse operators
+                              (1/2) P^T A P.  For grids whose coupling along one
+                              axis dominates (the semi-annulus of Section 4.1):
+                              halving that axis alone keeps the four-colour
+                              smoother's convergence independent of the
+                              anisotropy.  Default 0; > 0 needs TOMG_GS4 and
+                              TOMG_GALERKIN and runs the fused level passes down
+                              to the coarsest solve; such problems share no
+                              batched launch (tomg_solve_batch solves them one
+                              after another, tomg_batch_step and
+                              tomg_batch_launch refuse them with TOMG_EINVAL) */
+  int32_t semi_axis;       /* axis halved by the semi-coarsened levels: 0 the
+                              x axis (i, nx), 1 the y axis (j, ny) */
 } tomg_config;
 
 enum { TOMG_NEU_W = 1, TOMG_NEU_E = 2, TOMG_NEU_S = 4, TOMG_NEU_N = 8 };

@@ -32,7 +32,7 @@ class TomgError(RuntimeError):
 
 def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
                 smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, neumann=0,
-                flux=False, coarse_op="galerkin") -> Config:
+                flux=False, coarse_op="galerkin", semi_levels=0, semi_axis="x") -> Config:
     lib = _lib.load()
     cfg = Config()
     lib.tomg_config_default(C.byref(cfg), nx, ny, dx, dy)
@@ -46,6 +46,8 @@ def make_config(nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=
     cfg.neumann = int(neumann)
     cfg.flux = 1 if flux else 0
     cfg.coarse_op = {"galerkin": TOMG_GALERKIN, "rediscretize": TOMG_REDISCRETIZE}[coarse_op]
+    cfg.semi_levels = int(semi_levels)
+    cfg.semi_axis = {"x": 0, "y": 1, 0: 0, 1: 1}[semi_axis]
     return cfg
 
 
@@ -89,10 +91,11 @@ class Problem:
     def __init__(self, nx, ny, dx, dy, xi0=0.0, eta0=0.0, precision="fp64", nu1=2, nu2=2,
                  smoother="gs4", jacobi_omega=0.8, ir_inner_cycles=2, device=None,
                  stream: Optional[torch.cuda.Stream] = None, neumann=0, flux=False,
-                 coarse_op="galerkin"):
+                 coarse_op="galerkin", semi_levels=0, semi_axis="x"):
         self.lib = _lib.load()
         self.cfg = make_config(nx, ny, dx, dy, xi0, eta0, precision, nu1, nu2, smoother,
-                               jacobi_omega, ir_inner_cycles, neumann, flux, coarse_op)
+                               jacobi_omega, ir_inner_cycles, neumann, flux, coarse_op,
+                               semi_levels, semi_axis)
         self.nx, self.ny = nx, ny
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:

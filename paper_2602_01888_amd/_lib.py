@@ -54,7 +54,8 @@ class Config(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("precision", C.c_int32),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32),
                 ("jacobi_omega", C.c_double), ("ir_inner_cycles", C.c_int32),
-                ("neumann", C.c_int32), ("flux", C.c_int32), ("coarse_op", C.c_int32)]
+                ("neumann", C.c_int32), ("flux", C.c_int32), ("coarse_op", C.c_int32),
+                ("semi_levels", C.c_int32), ("semi_axis", C.c_int32)]
 
 
 _lib = None

@@ -16,23 +16,34 @@ namespace tomg {
 // Halve while both node counts minus one are even and each side keeps at
 // least 3 nodes; coarsen at least once, then while a side exceeds 9 nodes
 // (5 with Neumann edges, whose ring nodes are unknowns on the coarsest
-// level too: at most 25 coarsest unknowns instead of 49).
-int level_shapes(int nx, int ny, int *nxs, int *nys, int neumann) {
-  const int lim = neumann ? 5 : 9;
-  if (nx < 5 || ny < 5) return 0;
+// level too: at most 25 coarsest unknowns instead of 49).  With
+// semi-coarsening the first c.semi_levels coarsenings halve one axis only,
+// each of them required.
+int level_shapes(const tomg_config &c, int *nxs, int *nys, int *ck) {
+  const int lim = c.neumann ? 5 : 9;
+  if (c.nx < 5 || c.ny < 5) return 0;
   int L = 1;
-  nxs[0] = nx;
-  nys[0] = ny;
+  nxs[0] = c.nx;
+  nys[0] = c.ny;
   while (L < kMaxLevels) {
     const int cx = nxs[L - 1], cy = nys[L - 1];
-    const bool halvable = ((cx - 1) % 2 == 0) && ((cy - 1) % 2 == 0) && cx >= 5 && cy >= 5;
-    const bool wanted = (L == 1) || cx > lim || cy > lim;
-    if (!halvable || !wanted) break;
-    nxs[L] = (cx - 1) / 2 + 1;
-    nys[L] = (cy - 1) / 2 + 1;
+    int kind = 0;
+    if (L - 1 < c.semi_levels) {
+      const int side = c.semi_axis == 0 ? cx : cy;
+      if ((side - 1) % 2 != 0 || side < 5) return 0;
+      kind = c.semi_axis == 0 ? 1 : 2;
+    } else {
+      const bool halvable = ((cx - 1) % 2 == 0) && ((cy - 1) % 2 == 0) && cx >= 5 && cy >= 5;
+      const bool wanted = (L == 1) || cx > lim || cy > lim;
+      if (!halvable || !wanted) break;
+    }
+    nxs[L] = kind == 2 ? cx : (cx - 1) / 2 + 1;
+    nys[L] = kind == 1 ? cy : (cy - 1) / 2 + 1;
+    if (ck) ck[L - 1] = kind;
     ++L;
   }
-  if (L < 2) return 0;
+  if (L < 2 || L - 1 < c.semi_levels) return 0;
+  if (ck) ck[L - 1] = 0;
   // halving stopped above the bound: the coarsest level is kept when its
   // direct solve stays within kMaxCoarseNodes nodes
   if ((nxs[L - 1] > lim || nys[L - 1] > lim) &&
@@ -60,15 +71,19 @@ static bool config_ok(const tomg_config &c) {
   if (c.coarse_op != TOMG_GALERKIN && c.coarse_op != TOMG_REDISCRETIZE) return false;
   // rediscretisation builds eq. 18 on every level: Dirichlet edges only
   if (c.coarse_op == TOMG_REDISCRETIZE && stored_level0(c)) return false;
+  // semi-coarsened levels: fused four-colour passes and Galerkin operators
+  if (c.semi_levels < 0 || c.semi_levels >= kMaxLevels || c.semi_axis < 0 || c.semi_axis > 1)
+    return false;
+  if (c.semi_levels > 0 && (c.smoother != TOMG_GS4 || c.coarse_op != TOMG_GALERKIN)) return false;
   int a[kMaxLevels], b[kMaxLevels];
-  return level_shapes(c.nx, c.ny, a, b, c.neumann) > 0;
+  return level_shapes(c, a, b, nullptr) > 0;
 }
 
 bool make_layout(const tomg_config &cfg, Layout *lay) {
   if (!config_ok(cfg)) return false;
   Layout &o = *lay;
   o = Layout();
-  o.L = level_shapes(cfg.nx, cfg.ny, o.nx, o.ny, cfg.neumann);
+  o.L = level_shapes(cfg, o.nx, o.ny, o.ck);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -81,14 +96,21 @@ bool make_layout(const tomg_config &cfg, Layout *lay) {
                                   (size_t)2 * red_tiles(cfg.nx, cfg.ny)});
   o.partials = take(nparts * sizeof(double));
   // explicit inverse of the coarsest matrix, its node-to-unknown map and,
-  // for a coarsest level above kSmallCoarseNodes, the band LU (half-width
+  // for a coarsest level that may hold more unknowns than the one-block
+  // Gauss-Jordan takes (kMaxCoarseUnknowns: above kSmallCoarseNodes nodes,
+  // or free ring nodes of Neumann edges on a semi-coarsened hierarchy, such
+  // as 3 x 17 nodes without a Dirichlet edge), the band LU (half-width
   // nx + 1 in the row-major numbering of the unknowns)
-  const size_t mc = (size_t)o.nx[o.L - 1] * o.ny[o.L - 1];
-  const size_t mi = mc > (size_t)kSmallCoarseNodes ? mc : (size_t)kMaxCoarseUnknowns;
+  const int cxn = o.nx[o.L - 1], cyn = o.ny[o.L - 1];
+  const size_t mc = (size_t)cxn * cyn;
+  const int ring_x = !(cfg.neumann & TOMG_NEU_W) + !(cfg.neumann & TOMG_NEU_E);
+  const int ring_y = !(cfg.neumann & TOMG_NEU_S) + !(cfg.neumann & TOMG_NEU_N);
+  const long max_unknowns = (long)(cxn - ring_x) * (cyn - ring_y);
+  const bool band = mc > (size_t)kSmallCoarseNodes || max_unknowns > kMaxCoarseUnknowns;
+  const size_t mi = band ? mc : (size_t)kMaxCoarseUnknowns;
   o.cinv = take(mi * mi * sizeof(double));
   o.cidx = take((std::max(mc, (size_t)81) + 1) * sizeof(int));
-  if (mc > (size_t)kSmallCoarseNodes)
-    o.cband = take(mc * (2 * (size_t)(o.nx[o.L - 1] + 1) + 1) * sizeof(double));
+  if (band) o.cband = take(mc * (2 * (size_t)(cxn + 1) + 1) * sizeof(double));
   o.args = take(sizeof(ArgsBlob));
   o.bout = take(kMaxBatch * sizeof(double));
   o.exx = take(n0 * 8);
@@ -197,7 +219,7 @@ void tomg_config_default(tomg_config *cfg, int32_t nx, int32_t ny, double dx, do
 int32_t tomg_num_levels(const tomg_config *cfg) {
   if (!cfg || !config_ok(*cfg)) return 0;
   int a[kMaxLevels], b[kMaxLevels];
-  return level_shapes(cfg->nx, cfg->ny, a, b, cfg->neumann);
+  return level_shapes(*cfg, a, b, nullptr);
 }
 
 size_t tomg_workspace_bytes(const tomg_config *cfg) {
@@ -238,6 +260,7 @@ static hipError_t init_problem(tomg_problem *p, const tomg_config *cfg, const La
     Level &v = p->lv[l];
     v.nx = lay.nx[l];
     v.ny = lay.ny[l];
+    v.ck = lay.ck[l];
     v.n = (size_t)v.nx * v.ny;
     v.dir = (uint8_t *)(w + lay.dir[l]);
     if (l == 0 && stored_level0(*cfg)) v.st = D(lay.st[0]);
@@ -272,10 +295,10 @@ static hipError_t init_problem(tomg_problem *p, const tomg_config *cfg, const La
   }
   p->dargs = (ArgsBlob *)(w + lay.args);
   p->bout = D(lay.bout);
-  // the single-workgroup tail assumes Dirichlet rings; problems with a
-  // stored level-0 stencil (Neumann edges, flux form) run the level passes
-  // down to the coarsest solve
-  p->lc = stored_level0(*cfg) ? p->L - 1 : tail_level(p);
+  // the single-workgroup tail assumes Dirichlet rings and halves both axes;
+  // problems with a stored level-0 stencil (Neumann edges, flux form) or
+  // semi-coarsened levels run the level passes down to the coarsest solve
+  p->lc = (stored_level0(*cfg) || cfg->semi_levels > 0) ? p->L - 1 : tail_level(p);
   build_pass_args(p);
   build_tail_args(p);
   build_red_args(p);
@@ -642,7 +665,7 @@ bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
     const tomg_problem *p = probs[k];
     if (!p || !d_phis[k] || !p->ready) return false;
     if (p->cfg.precision != lead->cfg.precision || p->cfg.nu1 != lead->cfg.nu1 ||
-        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 ||
+        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 || p->cfg.semi_levels != 0 ||
         stored_level0(p->cfg) != stored_level0(lead->cfg) ||
         p->cfg.ir_inner_cycles != lead->cfg.ir_inner_cycles)
       return false;

@@ -144,8 +144,12 @@ constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 // odd rows (colours 2 then 3).  Four barriers per sweep and step, whatever
 // P.  The level-0 pass loads the next step's rows while it works on the
 // current ones; coarse levels issue a step's loads together at its start.
+// CK is the grid transfer to the coarse level: 0 both axes halved (bilinear
+// prolongation, full weighting), 1 x halved only, 2 y halved only
+// (semi-coarsening: linear along the halved axis, the identity along the
+// kept one, restriction (1/4) [1 2 1] along the halved axis).
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM,
-          bool MIR>
+          bool MIR, int CK>
 __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, const int by) {
   constexpr bool PF = EPS;  // level 0: the next step's rows are loaded during this step
   constexpr int H = 4 * NU + 2;
@@ -181,7 +185,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   const int m0 = (ys >> 1) + P - 1;  // newest pair of the first step
   const size_t n = (size_t)nx * ny;
   const int Ic = gc >> 1;
-  const int Ic1 = PROLONG ? min(Ic + 1, a.nxc - 1) : 0;
+  const int Ic1 = (PROLONG && CK != 2) ? min(Ic + 1, a.nxc - 1) : 0;
 
   for (int r = 0; r < NR; ++r) {
     L[r][t + 1] = T(0);
@@ -218,7 +222,17 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
 #pragma unroll
       for (int z = 0; z < 9; ++z) w.a[z] = ld_in(a.st + z * n + c);
     }
-    if constexpr (PROLONG) {
+    if constexpr (PROLONG && CK == 1) {  // x halved: coarse row rc, columns Ic, Ic + 1
+      const T *r0 = a.xc + (size_t)rc * a.nxc;
+      w.c00 = r0[Ic];
+      w.c01 = r0[Ic1];
+      w.c10 = w.c11 = T(0);
+    } else if constexpr (PROLONG && CK == 2) {  // y halved: rows J, J + 1, column gc
+      const int J = rc >> 1, J1 = min(J + 1, a.nyc - 1);
+      w.c00 = a.xc[(size_t)J * a.nxc + gc];
+      w.c10 = a.xc[(size_t)J1 * a.nxc + gc];
+      w.c01 = w.c11 = T(0);
+    } else if constexpr (PROLONG) {
       const int J = rc >> 1, J1 = min(J + 1, a.nyc - 1);
       const T *r0 = a.xc + (size_t)J * a.nxc;
       const T *r1 = a.xc + (size_t)J1 * a.nxc;
@@ -234,10 +248,16 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
     T v = ld ? w.x : T(0);
     if constexpr (PROLONG) {
       if (ld && !w.d && updc) {
-        T e = odd ? T(0.5) * (w.c00 + w.c01) : w.c00;
-        if (r & 1) {
-          const T e1 = odd ? T(0.5) * (w.c10 + w.c11) : w.c10;
-          e = T(0.5) * (e + e1);
+        T e;
+        if constexpr (CK == 2) {
+          e = w.c00;
+          if (r & 1) e = T(0.5) * (e + w.c10);
+        } else {
+          e = odd ? T(0.5) * (w.c00 + w.c01) : w.c00;
+          if (CK == 0 && (r & 1)) {
+            const T e1 = odd ? T(0.5) * (w.c10 + w.c11) : w.c10;
+            e = T(0.5) * (e + e1);
+          }
         }
         v += e;
       }
@@ -395,7 +415,43 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
             if constexpr (NORM) acc += res[q] * res[q];
           }
         }
-        if constexpr (RESTRICT) {
+        if constexpr (RESTRICT && CK == 1) {
+          // x halved: each residual row is a coarse row; (1/4) [1 2 1] along it
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) xch[q][t + 1] = res[q];
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) {
+            const int r = R0 + q;
+            if (r >= y0 && r < y1 && outc && !odd) {
+              const int I = gi >> 1, Jg = grow(r);
+              const bool ring = I == 0 || Jg == 0 || I == a.nxc - 1 || Jg == a.nyc - 1;
+              const bool fixed = ring && (!a.dirc || a.dirc[(size_t)Jg * a.nxc + I]);
+              const T v = fixed ? T(0)
+                               : (xch[q][t] + T(2) * xch[q][t + 1] + xch[q][t + 2]) * T(0.25);
+              st_out(a.bc + (size_t)Jg * a.nxc + I, v);
+            }
+          }
+        } else if constexpr (RESTRICT && CK == 2) {
+          // y halved: (1/4) [1 2 1] across rows 2J-1, 2J, 2J+1 at every column
+          T below[2 * P + 1];
+          below[0] = rprev;
+#pragma unroll
+          for (int q = 0; q < 2 * P; ++q) below[q + 1] = res[q];
+          rprev = res[2 * P - 1];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const int J = (R0 >> 1) + p;
+            if (2 * J >= y0 && 2 * J < y1 && J < a.nyc && outc) {
+              const int I = gi, Jg = MIR ? a.nyc - 1 - J : J;
+              const bool ring = I == 0 || Jg == 0 || I == a.nxc - 1 || Jg == a.nyc - 1;
+              const bool fixed = ring && (!a.dirc || a.dirc[(size_t)Jg * a.nxc + I]);
+              const T sum = MIR ? res[2 * p + 1] + T(2) * res[2 * p] + below[2 * p]
+                                : below[2 * p] + T(2) * res[2 * p] + res[2 * p + 1];
+              st_out(a.bc + (size_t)Jg * a.nxc + I, fixed ? T(0) : sum * T(0.25));
+            }
+          }
+        } else if constexpr (RESTRICT) {
           T below[2 * P + 1];
           below[0] = rprev;
 #pragma unroll
@@ -476,15 +532,16 @@ __device__ __forceinline__ void xcd_tile(int id, int nbx, int nby, int &bx, int 
   by = tile / nbx;
 }
 
-template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM,
+          int CK = 0>
 __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
   if (a.skip && *a.skip != 0.0) return;
   int bx = blockIdx.x, by = blockIdx.y;
   if (a.xcd_order) xcd_tile(blockIdx.x, a.nbx, a.nby, bx, by);
   if (mirrored<T>(by, a.ny))
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, CK>(a, bx, by);
   else
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, CK>(a, bx, by);
 }
 
 // Entry of a batched launch holding block b (entries sorted by start).
@@ -506,9 +563,9 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
   if (e.role == 2) a.xout = static_cast<T *>(e.phi);
   const int local = blockIdx.x - e.start, bx = local % e.nbx, by = local / e.nbx;
   if (mirrored<T>(by, a.ny))
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, 0>(a, bx, by);
   else
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, 0>(a, bx, by);
 }
 
 }  // namespace
@@ -561,20 +618,27 @@ size_t fused_max_blocks(int nx, int ny) {
 #define TOMG_PAIRS_ST 1
 #endif
 
-// Sweep count and pair count are compile-time; dispatch on the runtime nu.
+// Sweep count, pair count and transfer kind are compile-time; dispatch on
+// the runtime nu and a.ck (batched launches: both axes halved).
 template <typename T, bool EPS, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
 static void launch_pass(int nu, const PassArgs<T> &a, hipStream_t s, const BatchTab *tab,
                         int nblocks) {
   constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
+  const dim3 grid = a.xcd_order ? dim3(a.nbx * a.nby) : dim3(a.nbx, a.nby);
 #define TOMG_LAUNCH(NU)                                                                          \
   do {                                                                                           \
     if (tab)                                                                                     \
       hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>),              \
                          dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
+    else if (a.ck == 1)                                                                          \
+      hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 1>), grid,       \
+                         dim3(kBW), 0, s, a);                                                    \
+    else if (a.ck == 2)                                                                          \
+      hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 2>), grid,       \
+                         dim3(kBW), 0, s, a);                                                    \
     else                                                                                         \
-      hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>),                \
-                         a.xcd_order ? dim3(a.nbx * a.nby) : dim3(a.nbx, a.nby), dim3(kBW), 0,   \
-                         s, a);                                                                  \
+      hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>), grid,          \
+                         dim3(kBW), 0, s, a);                                                    \
   } while (0)
   switch (nu) {
     case 1: TOMG_LAUNCH(1); break;
@@ -675,6 +739,7 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0,
   a.nbx = (a.nx + a.W - 1) / a.W;
   a.nby = (a.ny + a.CH - 1) / a.CH;
   a.xcd_order = (!batch && a.nbx > 1) ? 1 : 0;
+  a.ck = v.ck;
   return a;
 }
 

@@ -946,6 +946,106 @@ __global__ __launch_bounds__(kGX *kGY) void k_coarsen_eps(EpsOp<double> op, cons
   }
 }
 
+// Transfer weight along one axis of a semi-coarsened level: the linear
+// weight pw along an axis that is halved, the identity along one that keeps
+// every fine line.
+__device__ __forceinline__ double tw(bool halved, int d) {
+  return halved ? pw(d) : (d == 0 ? 1.0 : 0.0);
+}
+
+// Kind of coarse node (I, J) of a level with strides (sx, sy): Dirichlet
+// outside the grid; on the ring the kind of the fine node under it;
+// elsewhere Dirichlet when every fine node of its support is (its column of
+// P would be empty).
+__device__ bool coarse_fixed_semi(const uint8_t *dirf, int nxf, int nyf, int nxc, int nyc,
+                                  int sx, int sy, int I, int J) {
+  if (I < 0 || J < 0 || I >= nxc || J >= nyc) return true;
+  const bool ring = I == 0 || J == 0 || I == nxc - 1 || J == nyc - 1;
+  if (ring && dirf[(size_t)(sy * J) * nxf + sx * I]) return true;
+  for (int b = -1; b <= 1; ++b)
+    for (int a = -1; a <= 1; ++a) {
+      if ((sx == 1 && a != 0) || (sy == 1 && b != 0)) continue;
+      const int fi = sx * I + a, fj = sy * J + b;
+      if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
+      if (!dirf[(size_t)fj * nxf + fi]) return false;
+    }
+  return true;
+}
+
+// Galerkin coarsening of a semi-coarsened level (an extension of eq. 23:
+// one axis halved, strides sx, sy = 2 halved, 1 kept): A_H = (1/2) P^T A_h P
+// with P linear along the halved axis and the identity along the other,
+// restricted to the unknowns as in k_coarsen (zero rows at fine Dirichlet
+// nodes, no columns at coarse Dirichlet nodes, identity rows there).  One
+// thread per coarse node: the fine stencils of its support (at most three
+// nodes) come from the operator -- eq. 18 from the tensor on level 0, the
+// stored stencil below -- and the products are summed in the order of the
+// triple sum (fine node, its neighbour, coarse column).  Setup only.
+template <class Op>
+__global__ void k_coarsen_semi(Op opf, const uint8_t *__restrict__ dirf, int nxf, int nyf,
+                               int nxc, int nyc, int sx, int sy, uint8_t *__restrict__ dirc,
+                               double *__restrict__ stc, float *__restrict__ stc32) {
+  const size_t nc = (size_t)nxc * nyc;
+  const bool hx = sx == 2, hy = sy == 2;
+  for (size_t C = (size_t)blockIdx.x * blockDim.x + threadIdx.x; C < nc;
+       C += (size_t)gridDim.x * blockDim.x) {
+    const int J = (int)(C / (size_t)nxc), I = (int)(C - (size_t)J * nxc);
+    bool fixed[9];
+#pragma unroll
+    for (int oj = -1; oj <= 1; ++oj)
+#pragma unroll
+      for (int oi = -1; oi <= 1; ++oi)
+        fixed[(oj + 1) * 3 + oi + 1] =
+            coarse_fixed_semi(dirf, nxf, nyf, nxc, nyc, sx, sy, I + oi, J + oj);
+    dirc[C] = fixed[4] ? 1 : 0;
+    double acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+    if (fixed[4]) {
+      acc[4] = 1.0;
+    } else {
+#pragma unroll
+      for (int b = -1; b <= 1; ++b)
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+          const double wf = tw(hx, a) * tw(hy, b);
+          if (wf == 0.0) continue;
+          const int fi = sx * I + a, fj = sy * J + b;
+          if (fi < 0 || fj < 0 || fi >= nxf || fj >= nyf) continue;
+          const size_t f = (size_t)fj * nxf + fi;
+          if (dirf[f]) continue;
+          double sf[9];
+          opf.full(f, sf);
+#pragma unroll
+          for (int q = -1; q <= 1; ++q)
+#pragma unroll
+            for (int pp = -1; pp <= 1; ++pp) {
+              const int gi = fi + pp, gj = fj + q;
+              if (gi < 0 || gj < 0 || gi >= nxf || gj >= nyf) continue;
+              if (dirf[(size_t)gj * nxf + gi]) continue;
+              const double afg = sf[(q + 1) * 3 + pp + 1];
+#pragma unroll
+              for (int oj = -1; oj <= 1; ++oj)
+#pragma unroll
+                for (int oi = -1; oi <= 1; ++oi) {
+                  const double wg = tw(hx, gi - sx * (I + oi)) * tw(hy, gj - sy * (J + oj));
+                  if (wg != 0.0 && !fixed[(oj + 1) * 3 + oi + 1])
+                    acc[(oj + 1) * 3 + oi + 1] += wf * afg * wg;
+                }
+            }
+        }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[k] *= 0.5;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) stc[k * nc + C] = acc[k];
+    if (stc32) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) stc32[k * nc + C] = (float)acc[k];
+    }
+  }
+}
+
 // Coarse level rediscretised (TOMG_REDISCRETIZE): eq. 18 on the level's own
 // grid, whose spacings are s dx, s dy (s = 2^l; the coefficients cx..hxy
 // come with them), with the tensor of level 0 sampled at the coarse nodes --
@@ -2035,7 +2135,8 @@ static int coarse_solve_threads(const tomg_problem *p) {
 int tail_level(const tomg_problem *p) {
   // the tail gives each thread one node of its two coarsest levels: a large
   // coarsest level is solved on its own below the fused passes
-  if ((long)p->lv[p->L - 1].nx * p->lv[p->L - 1].ny > kSmallCoarseNodes) return p->L - 1;
+  if (p->cband || (long)p->lv[p->L - 1].nx * p->lv[p->L - 1].ny > kSmallCoarseNodes)
+    return p->L - 1;
   for (int l = 1; l < p->L; ++l)
     if ((long)p->lv[l].nx * p->lv[l].ny <= tail_max_nodes() && p->L - l <= 4) return l;
   return p->L - 1;
@@ -2307,6 +2408,16 @@ hipError_t launch_hierarchy(tomg_problem *p, bool defer_inverse) {
                          (const uint8_t *)p->lv[0].dir, p->cfg.nx, 1 << l, lc.nx, lc.ny,
                          1.0 / (H * H), 1.0 / (K * K), 0.25 / (H * H), 0.25 / (K * K),
                          0.25 / (H * K), 0.5 / (H * K), lc.dir, lc.st, st32);
+    } else if (lf.ck != 0) {  // one axis halved
+      const int sx = lf.ck == 1 ? 2 : 1, sy = lf.ck == 2 ? 2 : 1;
+      if (l == 1 && !stored_level0(p->cfg))
+        hipLaunchKernelGGL((k_coarsen_semi<EpsOp<double>>), grid1(lc.n), 256, 0, p->stream,
+                           op64(p), (const uint8_t *)lf.dir, lf.nx, lf.ny, lc.nx, lc.ny, sx, sy,
+                           lc.dir, lc.st, st32);
+      else
+        hipLaunchKernelGGL((k_coarsen_semi<StOp<double>>), grid1(lc.n), 256, 0, p->stream,
+                           st_op<double>(lf.st, lf.nx, lf.ny), (const uint8_t *)lf.dir, lf.nx,
+                           lf.ny, lc.nx, lc.ny, sx, sy, lc.dir, lc.st, st32);
     } else if (l == 1 && !stored_level0(p->cfg))
       hipLaunchKernelGGL(k_coarsen_eps, grid, kGX * kGY, 0, p->stream, op64(p), lf.dir, lf.nx,
                          lf.ny, lc.nx, lc.ny, lc.dir, lc.st, st32);

@@ -49,6 +49,7 @@ enum { kRelNone = 0, kRelBegin = 1, kRelCycle = 2 };
 
 struct Level {
   int nx = 0, ny = 0;
+  int ck = 0;  // transfer to the next level: 0 both axes halved, 1 x only, 2 y only
   size_t n = 0;
   double *st = nullptr;  // 9 planes (levels >= 1)
   double *x = nullptr;   // correction (levels >= 1)
@@ -83,6 +84,7 @@ struct PassArgs {
   int CH, W;                 // band height, owned columns per block
   int nbx, nby;              // block grid
   int xcd_order;             // tiles in XCD-contiguous order (one-dimensional grid)
+  int ck;                    // transfer to the coarse level: 0 both axes halved, 1 x, 2 y
   const double *skip;        // nonzero *skip: the launch does nothing (solve()
                              // queues cycles past convergence as no-ops)
 };
@@ -178,6 +180,7 @@ constexpr int kMaxBatch = 4096;  // problems per tomg_solve_batch call
 struct Layout {
   int L = 0;
   int nx[kMaxLevels], ny[kMaxLevels];
+  int ck[kMaxLevels];  // transfer kind to the next level (0 full, 1 x halved, 2 y halved)
   size_t exx, exy, eyy, det, f, tmp, partials, scal, cinv, cidx, cband;
   size_t dir[kMaxLevels], st[kMaxLevels], x[kMaxLevels], b[kMaxLevels], x2[kMaxLevels];
   size_t exx32, exy32, eyy32, e32, e32b, r32, phi2;
@@ -187,7 +190,9 @@ struct Layout {
   size_t total = 0;
 };
 
-int level_shapes(int nx, int ny, int *nxs, int *nys, int neumann);
+// Level shapes of a configuration; ck[l] (nullable) receives the kind of
+// the transfer from level l to l + 1: 0 both axes halved, 1 x only, 2 y only.
+int level_shapes(const tomg_config &c, int *nxs, int *nys, int *ck);
 
 // The level-0 operator is stored as a 9-point stencil (Neumann edges, or the
 // flux form) and every cycle runs the unfused kernels on stored stencils.

@@ -226,3 +226,28 @@ def test_descriptor_calls_reject_bad_descriptors_on_the_host(lib):
     assert lib.tomg_update_rhs_desc(None, C.byref(s)) == t.TOMG_EINVAL
     with pytest.raises(t.TomgError):
         t.source_desc([1.0] * 17, [(0.5, 0.5)] * 17, 0.02)
+
+
+def test_semi_coarsening_options(lib):
+    """semi_levels / semi_axis: the level shapes are the oracle's (the first
+    coarsenings halve one axis only); semi-coarsening needs the four-colour
+    smoother and Galerkin operators, and a requested semi-coarsening that
+    cannot be made refuses the grid."""
+    import oracle
+    import paper_2602_01888_amd as t
+    for n, neu, semi, axis in ((4097, 12, 2, "x"), (257, 0, 1, "y"), (129, 0, 3, "x"),
+                               (65, 3, 2, "y")):
+        c = cfg(n, n, neumann=neu, semi_levels=semi, semi_axis=axis)
+        want = oracle.levels(n, n, neumann=neu, semi=semi, semi_axis=0 if axis == "x" else 1)
+        assert t.num_levels(c) == len(want) > 0
+        assert t.workspace_bytes(c) > t.workspace_bytes(cfg(n, n, neumann=neu)) or n == 129
+    assert t.workspace_bytes(cfg(129, 129, semi_levels=1, smoother="zebra_x")) == 0
+    assert t.workspace_bytes(cfg(129, 129, semi_levels=1, smoother="jacobi")) == 0
+    assert t.workspace_bytes(cfg(129, 129, semi_levels=1, coarse_op="rediscretize")) == 0
+    assert t.workspace_bytes(cfg(9, 9, semi_levels=3)) == 0
+    c = cfg(129, 129, semi_levels=1)
+    c.semi_axis = 2
+    assert t.workspace_bytes(c) == 0
+    c = cfg(129, 129)
+    c.semi_levels = -1
+    assert t.workspace_bytes(c) == 0
