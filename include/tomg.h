@@ -459,8 +459,10 @@ tomg_status tomg_residual(tomg_problem *p, const double *d_phi, double *d_r);
 /* enable != 0: bracket every level-0 down pass and up pass with HIP events
  * on the problem's stream; 0: stop.  Enabling resets the accumulators. */
 tomg_status tomg_profile(tomg_problem *p, int32_t enable);
-/* Synchronises the stream and returns out[4] = {total ms of level-0 down
- * passes, their count, total ms of level-0 up passes, their count} since
+/* Synchronises the stream and returns out[6] = {total ms of level-0 down
+ * passes, their count, total ms of level-0 up passes, their count, total ms
+ * of the chained level-0 passes of FP32 inner cycles (the up pass of one
+ * cycle and the down pass of the next in one launch), their count} since
  * tomg_profile(p, 1). */
 tomg_status tomg_profile_read(tomg_problem *p, double *out);
 /* STREAM-style device copy of `bytes` bytes (multiple of 16, 16-byte aligned

@@ -291,8 +291,10 @@ class Problem:
         self._check(self.lib.tomg_profile(self._h, 1 if enable else 0), "profile")
 
     def profile_read(self):
-        """(down_ms_total, down_count, up_ms_total, up_count) of level-0 passes."""
-        out = (C.c_double * 4)()
+        """(down_ms_total, down_count, up_ms_total, up_count, chained_ms_total,
+        chained_count) of level-0 passes (chained: the up pass of an FP32 inner
+        cycle and the down pass of the next in one launch)."""
+        out = (C.c_double * 6)()
         self._check(self.lib.tomg_profile_read(self._h, out), "profile_read")
         return tuple(out)
 

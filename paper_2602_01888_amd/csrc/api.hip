@@ -190,7 +190,7 @@ static tomg_status read_scalars(tomg_problem *p, double *h) {
 }
 
 static void destroy_events(tomg_problem *p) {
-  for (int kind = 0; kind < 2; ++kind)
+  for (int kind = 0; kind < tomg_problem::kProfKinds; ++kind)
     for (int e = 0; e < tomg_problem::kMaxEv; ++e)
       for (int q = 0; q < 2; ++q)
         if (p->ev[kind][e][q]) {
@@ -949,13 +949,14 @@ tomg_status tomg_residual(tomg_problem *p, const double *d_phi, double *d_r) {
 tomg_status tomg_profile(tomg_problem *p, int32_t enable) {
   if (!p) return TOMG_EINVAL;
   if (enable) {
-    for (int kind = 0; kind < 2; ++kind)
+    for (int kind = 0; kind < tomg_problem::kProfKinds; ++kind) {
       for (int e = 0; e < tomg_problem::kMaxEv; ++e)
         for (int q = 0; q < 2; ++q)
           if (!p->ev[kind][e][q]) HIP_TRY(p, hipEventCreate(&p->ev[kind][e][q]));
-    p->nev[0] = p->nev[1] = 0;
-    p->prof_ms[0] = p->prof_ms[1] = 0.0;
-    p->prof_cnt[0] = p->prof_cnt[1] = 0.0;
+      p->nev[kind] = 0;
+      p->prof_ms[kind] = 0.0;
+      p->prof_cnt[kind] = 0.0;
+    }
     p->prof = true;
   } else {
     HIP_TRY(p, hipStreamSynchronize(p->stream));
@@ -973,6 +974,8 @@ tomg_status tomg_profile_read(tomg_problem *p, double *out) {
   out[1] = p->prof_cnt[0];
   out[2] = p->prof_ms[1];
   out[3] = p->prof_cnt[1];
+  out[4] = p->prof_ms[2];
+  out[5] = p->prof_cnt[2];
   return TOMG_OK;
 }
 

@@ -697,6 +697,52 @@ static long pass_slots(int l, bool up, int nu, bool eps0) {
   return (long)nb * cus;
 }
 
+// The chained level-0 pass of the FP32 inner cycles (the up pass of a cycle
+// and the down pass of the next): nu2 + nu1 in 2 .. 4 sweeps, prolongation
+// on load and restriction of the final residual in the same launch.
+template <typename T, bool EPS>
+static int updown_blocks_per_cu(int nu) {
+  constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
+  const void *f;
+  switch (nu) {
+    case 2: f = reinterpret_cast<const void *>(k_pass<T, EPS, 2, P, false, true, true, false>); break;
+    case 3: f = reinterpret_cast<const void *>(k_pass<T, EPS, 3, P, false, true, true, false>); break;
+    default: f = reinterpret_cast<const void *>(k_pass<T, EPS, 4, P, false, true, true, false>); break;
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBW, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+template <typename T, bool EPS>
+static void launch_updown(int nu, const PassArgs<T> &a, hipStream_t s) {
+  constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
+  const dim3 grid = a.xcd_order ? dim3(a.nbx * a.nby) : dim3(a.nbx, a.nby);
+  switch (nu) {
+    case 2:
+      hipLaunchKernelGGL((k_pass<T, EPS, 2, P, false, true, true, false>), grid, dim3(kBW), 0, s, a);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_pass<T, EPS, 3, P, false, true, true, false>), grid, dim3(kBW), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_pass<T, EPS, 4, P, false, true, true, false>), grid, dim3(kBW), 0, s, a);
+      break;
+  }
+}
+
+// Chained only with a stored level-0 stencil (Neumann edges, the flux form):
+// there the pass moves 49 B per node for its own 4-byte iterate and a
+// chained pass saves half of them (Neumann semi-annulus at 4097^2, four
+// inner cycles per step: 18.7 -> 17.2 ms).  With the coefficients formed
+// from the tensor the level-0 pass is bound by its steps' phase chain, not
+// by its bytes, and the chained pass's sixteen colour phases per step made
+// it slower than the two passes it replaces (295 against 135 + 134 us).
+bool chain_inner(const tomg_problem *p) {
+  return p->cfg.precision == TOMG_FP32_IR && p->cfg.smoother == TOMG_GS4 && p->L >= 2 &&
+         p->cfg.nu1 + p->cfg.nu2 <= 4 && p->lv[0].ck == 0 && stored_level0(p->cfg);
+}
+
 // Arguments of the down (up) pass of level l in precision T: the level
 // iterate x_l is read (written) and its second buffer written (read).
 template <typename T>
@@ -763,6 +809,24 @@ void build_pass_args(tomg_problem *p) {
                                   p->exy32, p->eyy32);
       }
     }
+  if (chain_inner(p)) {
+    // the up pass's arguments (prolongation from level 1), with the
+    // restriction into level 1's right-hand side and the blocking of
+    // nu2 + nu1 sweeps
+    PassArgs<float> a = make_args<float>(p, 0, true, false, p->e32, p->e32b, p->r32, p->exx32,
+                                         p->exy32, p->eyy32);
+    const int nu = p->cfg.nu1 + p->cfg.nu2;
+    a.bc = p->lv[1].b32;
+    a.partials = nullptr;
+    a.W = kBW - 2 * (4 * nu + 2);
+    static const int cus = device_cus();
+    const long slots = (long)updown_blocks_per_cu<float, false>(nu) * cus;
+    a.CH = pick_band(a.nx, a.ny, a.W, slots, 2 * nu + 3);
+    a.nbx = (a.nx + a.W - 1) / a.W;
+    a.nby = (a.ny + a.CH - 1) / a.CH;
+    a.xcd_order = a.nbx > 1 ? 1 : 0;
+    g.updown32 = a;
+  }
 }
 
 template <typename T>
@@ -831,6 +895,28 @@ int fused_up(tomg_problem *p, int l, const T *pong, T *x, const T *b, const T *e
                nullptr, 0);
   return a.nbx * a.nby;
 }
+
+template <typename T>
+void fused_updown(tomg_problem *p, const T *pong, T *out, const T *b, const T *exx,
+                  const T *exy, const T *eyy, const T *st, const T *xc, T *bc) {
+  static_assert(std::is_same<T, float>::value, "chained passes run the FP32 inner cycles");
+  PassArgs<T> a = p->hargs.updown32;
+  a.xin = pong;
+  a.xout = out;
+  a.b = b;
+  a.exx = exx;
+  a.exy = exy;
+  a.eyy = eyy;
+  a.st = st;
+  a.xc = xc;
+  a.bc = bc;
+  a.partials = nullptr;
+  a.skip = p->skip;
+  launch_updown<T, false>(p->cfg.nu1 + p->cfg.nu2, a, p->stream);  // stored level 0 only
+}
+template void fused_updown<float>(tomg_problem *, const float *, float *, const float *,
+                                  const float *, const float *, const float *, const float *,
+                                  const float *, float *);
 
 template void fused_down<double>(tomg_problem *, int, const double *, double *, const double *,
                                  const double *, const double *, const double *, const double *,

@@ -2116,14 +2116,6 @@ void restrict_level(tomg_problem *p, const Op &op, const T *x, const T *b, const
                      nxf, bc, nxc, nyc, dirc);
 }
 
-// One V(nu1, nu2) cycle in precision T.  x0/b0: level-0 iterate and rhs;
-// op0: level-0 operator; coarse data from views[l].{x,b,st}.  zero0: the
-// level-0 iterate starts at zero (not read).  With the four-colour smoother
-// each level is one fused down pass and one fused up pass; when partials is
-// given, the level-0 up pass also leaves per-block sums of the squared final
-// residual there (block count in *nblocks).
-// First level handed to the single-workgroup tail: the first coarse level
-// with at most tail_max_nodes() nodes and at most 4 levels below it.
 }  // namespace
 // Threads of the coarsest solve: a wave for the small levels, up to 1024 for
 // the large ones (one row of the inverse each).
@@ -2132,6 +2124,8 @@ static int coarse_solve_threads(const tomg_problem *p) {
   return n <= 64 ? 64 : (n <= 256 ? 256 : 1024);
 }
 
+// First level handed to the single-workgroup tail: the first coarse level
+// with at most tail_max_nodes() nodes and at most 4 levels below it.
 int tail_level(const tomg_problem *p) {
   // the tail gives each thread one node of its two coarsest levels: a large
   // coarsest level is solved on its own below the fused passes
@@ -2185,6 +2179,66 @@ hipError_t run_vcycle_stored(tomg_problem *p, T *x0, const T *b0, const LevelVie
   return hipGetLastError();
 }
 
+// Levels 1 .. L-1 of a four-colour cycle, between the level-0 passes: the
+// fused down passes of levels 1 .. lc-1, the single-workgroup tail from
+// level lc (or the coarsest solve alone), the fused up passes of levels
+// lc-1 .. 1.
+template <typename T>
+static void coarse_levels(tomg_problem *p, const EpsOp<T> &op0, const LevelView<T> *views) {
+  const int L = p->L;
+  const int lc = p->lc;  // first level of the tail (the coarsest alone: no tail)
+  for (int l = 1; l < lc; ++l)
+    fused_down<T>(p, l, views[l].x, views[l].pong, views[l].b, op0.exx, op0.exy, op0.eyy,
+                  views[l].st, views[l + 1].b, true);
+  T *xs[kMaxLevels];
+  T *bs[kMaxLevels];
+  const T *sts[kMaxLevels];
+  for (int l = 0; l < L; ++l) {
+    xs[l] = views[l].x;
+    bs[l] = views[l].b;
+    sts[l] = views[l].st;
+  }
+  if (lc == L - 1)  // no tail: the coarsest solve alone
+    hipLaunchKernelGGL((k_coarse_solve<T>), 1, coarse_solve_threads(p), 0, p->stream, p->cinv,
+                       p->cidx, (const T *)views[L - 1].b, views[L - 1].x, (int)p->lv[L - 1].n);
+  else
+    tail_cycle<T>(p, lc, xs, bs, sts);
+  for (int l = lc - 1; l >= 1; --l)
+    fused_up<T>(p, l, views[l].pong, views[l].x, views[l].b, op0.exx, op0.exy, op0.eyy,
+                views[l].st, views[l + 1].x, nullptr);
+}
+
+// k FP32 V-cycles of a refinement step from a zero start, the level-0 up
+// pass of each cycle and the down pass of the next in one launch
+// (fused_updown): the same relaxations in the same order as the cycles run
+// one after another, so the same result bit for bit, with the level-0
+// arrays moved once per cycle instead of twice.  The pre-smoothed level-0
+// iterates alternate between e and e2 so that the last up pass leaves the
+// correction in e.
+static hipError_t run_inner_chain(tomg_problem *p, int k, float *e, float *e2, const float *b0,
+                                  const EpsOp<float> &op0, const LevelView<float> *views) {
+  auto pong = [&](int c) -> float * { return ((k - c) & 1) ? e : e2; };
+  prof_begin(p, 0);
+  fused_down<float>(p, 0, e, pong(1), b0, op0.exx, op0.exy, op0.eyy, views[0].st, views[1].b,
+                    true);
+  prof_end(p, 0);
+  for (int c = 1; c <= k; ++c) {
+    coarse_levels<float>(p, op0, views);
+    if (c < k) {
+      prof_begin(p, 2);
+      fused_updown<float>(p, pong(c), pong(c + 1), b0, op0.exx, op0.exy, op0.eyy, views[0].st,
+                          views[1].x, views[1].b);
+      prof_end(p, 2);
+    } else {
+      prof_begin(p, 1);
+      fused_up<float>(p, 0, pong(c), e, b0, op0.exx, op0.exy, op0.eyy, views[0].st, views[1].x,
+                      nullptr);
+      prof_end(p, 1);
+    }
+  }
+  return hipGetLastError();
+}
+
 // One V(nu1, nu2) cycle in precision T.  x0/b0: level-0 iterate and rhs;
 // op0: level-0 operator; coarse data from views[l].{x,b,st}.  zero0: the
 // level-0 iterate starts at zero (not read).  With the four-colour smoother,
@@ -2201,37 +2255,16 @@ hipError_t run_vcycle(tomg_problem *p, T *x0, const T *b0, const EpsOp<T> &op0,
   if (stored_level0(p->cfg) && p->cfg.smoother != TOMG_GS4)
     return run_vcycle_stored(p, x0, b0, views, zero0);
   if (p->cfg.smoother == TOMG_GS4) {
-    const int lc = p->lc;  // first level of the tail (the coarsest alone: no tail)
-    for (int l = 0; l < lc; ++l) {
-      T *x = l == 0 ? x0 : views[l].x;
-      const T *b = l == 0 ? b0 : views[l].b;
-      if (l == 0) prof_begin(p, 0);
-      fused_down<T>(p, l, x, views[l].pong, b, op0.exx, op0.exy, op0.eyy, views[l].st,
-                    views[l + 1].b, l > 0 || zero0);
-      if (l == 0) prof_end(p, 0);
-    }
-    T *xs[kMaxLevels];
-    T *bs[kMaxLevels];
-    const T *sts[kMaxLevels];
-    for (int l = 0; l < L; ++l) {
-      xs[l] = views[l].x;
-      bs[l] = views[l].b;
-      sts[l] = views[l].st;
-    }
-    if (lc == L - 1)  // no tail (stored level-0 stencil): the coarsest solve alone
-      hipLaunchKernelGGL((k_coarse_solve<T>), 1, coarse_solve_threads(p), 0, p->stream, p->cinv, p->cidx,
-                         (const T *)views[L - 1].b, views[L - 1].x, (int)p->lv[L - 1].n);
-    else
-      tail_cycle<T>(p, lc, xs, bs, sts);
-    for (int l = lc - 1; l >= 0; --l) {
-      T *x = l == 0 ? x0 : views[l].x;
-      const T *b = l == 0 ? b0 : views[l].b;
-      if (l == 0) prof_begin(p, 1);
-      const int nb = fused_up<T>(p, l, views[l].pong, x, b, op0.exx, op0.exy, op0.eyy,
-                                 views[l].st, views[l + 1].x, l == 0 ? partials : nullptr);
-      if (l == 0) prof_end(p, 1);
-      if (l == 0 && nblocks) *nblocks = partials ? nb : 0;
-    }
+    prof_begin(p, 0);
+    fused_down<T>(p, 0, x0, views[0].pong, b0, op0.exx, op0.exy, op0.eyy, views[0].st,
+                  views[1].b, zero0);
+    prof_end(p, 0);
+    coarse_levels<T>(p, op0, views);
+    prof_begin(p, 1);
+    const int nb = fused_up<T>(p, 0, views[0].pong, x0, b0, op0.exx, op0.exy, op0.eyy,
+                               views[0].st, views[1].x, partials);
+    prof_end(p, 1);
+    if (nblocks) *nblocks = partials ? nb : 0;
     return hipGetLastError();
   }
   // damped Jacobi: one launch per step
@@ -2607,6 +2640,8 @@ hipError_t launch_ir_inner(tomg_problem *p) {
     v[l] = {p->lv[l].x32, p->lv[l].b32, p->lv[l].st32, p->lv[l].x2_32};
   v[0].pong = p->e32b;
   const EpsOp<float> o32 = eps_op<float>(p->exx32, p->exy32, p->eyy32, nx, p->cfg.dx, p->cfg.dy);
+  if (chain_inner(p))
+    return run_inner_chain(p, p->cfg.ir_inner_cycles, p->e32, p->e32b, p->r32, o32, v);
   for (int k = 0; k < p->cfg.ir_inner_cycles; ++k) {
     hipError_t e = run_vcycle<float>(p, p->e32, p->r32, o32, v, k == 0, nullptr, nullptr);
     if (e != hipSuccess) return e;
@@ -2737,7 +2772,7 @@ void prof_end(tomg_problem *p, int kind) {
 // Called after the stream has been synchronised.
 void prof_harvest(tomg_problem *p) {
   if (!p->prof) return;
-  for (int kind = 0; kind < 2; ++kind) {
+  for (int kind = 0; kind < tomg_problem::kProfKinds; ++kind) {
     for (int e = 0; e < p->nev[kind]; ++e) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, p->ev[kind][e][0], p->ev[kind][e][1]) == hipSuccess) {

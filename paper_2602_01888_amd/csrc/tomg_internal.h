@@ -152,6 +152,9 @@ struct ArgsBlob {
   // problems of the batch fill the device
   PassArgs<double> down64b[kMaxLevels], up64b[kMaxLevels];
   PassArgs<float> down32b[kMaxLevels], up32b[kMaxLevels];
+  // level 0 of the FP32 inner cycles: the up pass of a cycle and the down
+  // pass of the next in one launch (nu2 + nu1 sweeps)
+  PassArgs<float> updown32;
   TailArgs<double> tail64;
   TailArgs<float> tail32;
   RedArgs red;
@@ -237,11 +240,12 @@ struct tomg_problem {
   // level-0 pass timing (tomg_profile): event pairs recorded since the last
   // harvest, per kind (0 down, 1 up)
   static constexpr int kMaxEv = 64;
+  static constexpr int kProfKinds = 3;  // level-0 down, up, and chained up-down passes
   bool prof = false;
-  hipEvent_t ev[2][kMaxEv][2] = {};
-  int nev[2] = {0, 0};
-  double prof_ms[2] = {0, 0};
-  double prof_cnt[2] = {0, 0};
+  hipEvent_t ev[kProfKinds][kMaxEv][2] = {};
+  int nev[kProfKinds] = {0, 0, 0};
+  double prof_ms[kProfKinds] = {0, 0, 0};
+  double prof_cnt[kProfKinds] = {0, 0, 0};
   char err[512];
 };
 
@@ -275,6 +279,16 @@ template <typename T>
 int fused_up(tomg_problem *p, int l, const T *pong, T *x, const T *b, const T *exx,
              const T *exy, const T *eyy, const T *st, const T *xc, double *partials);
 size_t fused_max_blocks(int nx, int ny);
+// Whether the FP32 inner cycles run chained (fused_updown): four-colour
+// smoother, nu1 + nu2 <= 4, both axes halved below level 0, the level-0
+// stencil stored.
+bool chain_inner(const tomg_problem *p);
+// Level-0 up pass of an FP32 inner cycle and down pass of the next in one
+// launch: pong (plus the prolongation of xc) in, nu2 + nu1 sweeps, the
+// result to out, the residual restricted into bc.
+template <typename T>
+void fused_updown(tomg_problem *p, const T *pong, T *out, const T *b, const T *exx,
+                  const T *exy, const T *eyy, const T *st, const T *xc, T *bc);
 
 // levels lc..L-1 of the cycle in one workgroup (tail.hip)
 template <typename T>

@@ -249,13 +249,13 @@ def test_profile_counts_level0_passes(tomg):
     phi = d["phi0"].clone()
     p.profile(True)
     r = p.solve(phi, rel_tol=1e-10)
-    dm, dc, um, uc = p.profile_read()
+    dm, dc, um, uc, cm, cc = p.profile_read()
     p.profile(False)
     assert r.ok and dc >= r.cycles and uc >= r.cycles and dc == uc
-    assert dm > 0.0 and um > 0.0
+    assert dm > 0.0 and um > 0.0 and cm == 0.0 and cc == 0  # no chained passes in FP64
     phi.copy_(d["phi0"])
     p.solve(phi, rel_tol=1e-10)
-    assert p.profile_read() == (dm, dc, um, uc)
+    assert p.profile_read() == (dm, dc, um, uc, cm, cc)
     torch.cuda.synchronize()
 
 
