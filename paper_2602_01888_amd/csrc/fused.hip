@@ -714,21 +714,34 @@ static int updown_blocks_per_cu(int nu) {
   return nb;
 }
 
-template <typename T, bool EPS>
-static void launch_updown(int nu, const PassArgs<T> &a, hipStream_t s) {
+template <typename T, bool EPS, int CK>
+static void launch_updown_ck(int nu, const PassArgs<T> &a, hipStream_t s) {
   constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
   const dim3 grid = a.xcd_order ? dim3(a.nbx * a.nby) : dim3(a.nbx, a.nby);
   switch (nu) {
     case 2:
-      hipLaunchKernelGGL((k_pass<T, EPS, 2, P, false, true, true, false>), grid, dim3(kBW), 0, s, a);
+      hipLaunchKernelGGL((k_pass<T, EPS, 2, P, false, true, true, false, CK>), grid, dim3(kBW), 0,
+                         s, a);
       break;
     case 3:
-      hipLaunchKernelGGL((k_pass<T, EPS, 3, P, false, true, true, false>), grid, dim3(kBW), 0, s, a);
+      hipLaunchKernelGGL((k_pass<T, EPS, 3, P, false, true, true, false, CK>), grid, dim3(kBW), 0,
+                         s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_pass<T, EPS, 4, P, false, true, true, false>), grid, dim3(kBW), 0, s, a);
+      hipLaunchKernelGGL((k_pass<T, EPS, 4, P, false, true, true, false, CK>), grid, dim3(kBW), 0,
+                         s, a);
       break;
   }
+}
+
+template <typename T, bool EPS>
+static void launch_updown(int nu, const PassArgs<T> &a, hipStream_t s) {
+  if (a.ck == 1)
+    launch_updown_ck<T, EPS, 1>(nu, a, s);
+  else if (a.ck == 2)
+    launch_updown_ck<T, EPS, 2>(nu, a, s);
+  else
+    launch_updown_ck<T, EPS, 0>(nu, a, s);
 }
 
 // Chained only with a stored level-0 stencil (Neumann edges, the flux form):
@@ -740,7 +753,7 @@ static void launch_updown(int nu, const PassArgs<T> &a, hipStream_t s) {
 // it slower than the two passes it replaces (295 against 135 + 134 us).
 bool chain_inner(const tomg_problem *p) {
   return p->cfg.precision == TOMG_FP32_IR && p->cfg.smoother == TOMG_GS4 && p->L >= 2 &&
-         p->cfg.nu1 + p->cfg.nu2 <= 4 && p->lv[0].ck == 0 && stored_level0(p->cfg);
+         p->cfg.nu1 + p->cfg.nu2 <= 4 && stored_level0(p->cfg);
 }
 
 // Arguments of the down (up) pass of level l in precision T: the level

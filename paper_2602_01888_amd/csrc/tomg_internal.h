@@ -280,8 +280,7 @@ int fused_up(tomg_problem *p, int l, const T *pong, T *x, const T *b, const T *e
              const T *exy, const T *eyy, const T *st, const T *xc, double *partials);
 size_t fused_max_blocks(int nx, int ny);
 // Whether the FP32 inner cycles run chained (fused_updown): four-colour
-// smoother, nu1 + nu2 <= 4, both axes halved below level 0, the level-0
-// stencil stored.
+// smoother, nu1 + nu2 <= 4, the level-0 stencil stored.
 bool chain_inner(const tomg_problem *p);
 // Level-0 up pass of an FP32 inner cycle and down pass of the next in one
 // launch: pong (plus the prolongation of xc) in, nu2 + nu1 sweeps, the
