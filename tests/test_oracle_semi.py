@@ -166,6 +166,22 @@ def test_semi_multigrid_rate_on_semi_annulus(n):
     assert st2 == 0 and cyc2 >= cyc + 5
 
 
+@pytest.mark.parametrize("n,ny,neumann", [(65, 33, False), (129, 65, True)])
+def test_semi_coarsening_fixes_the_aspect_two_annulus(n, ny, neumann):
+    """The semi-annulus on half as many angular nodes (cells twice as long
+    along the angle, radial coupling 18-110 times the angular one): point
+    smoothing with full coarsening needs 70-140 cycles, with the radial axis
+    halved alone for two levels at most 10."""
+    p = w.polar_semi_annulus(n, ny=ny, neumann=neumann)
+    s = oracle.setup(p)
+    full = _mg(p, s)
+    _, st0, c0, _, _ = full.solve(p.phi0, s["f"], 1e-10, 400)
+    semi = _mg(p, s, semi=2, semi_axis=0)
+    _, st2, c2, _, _ = semi.solve(p.phi0, s["f"], 1e-10, 400)
+    assert st0 == 0 and st2 == 0
+    assert c0 >= 60 and c2 <= 10, (c0, c2)
+
+
 def test_semi_multigrid_converges_to_direct_solution():
     """The discrete solution does not depend on the hierarchy: at a 1e-13
     residual the semi-coarsened multigrid matches SciPy's sparse LU solve."""
