@@ -972,32 +972,46 @@ __device__ bool coarse_fixed_semi(const uint8_t *dirf, int nxf, int nyf, int nxc
   return true;
 }
 
+// Coarse Dirichlet flags of a semi-coarsened level, one thread per coarse
+// node (the first of the level's two setup launches).
+__global__ void k_coarse_flags_semi(const uint8_t *__restrict__ dirf, int nxf, int nyf, int nxc,
+                                    int nyc, int sx, int sy, uint8_t *__restrict__ dirc) {
+  const size_t nc = (size_t)nxc * nyc;
+  for (size_t C = (size_t)blockIdx.x * blockDim.x + threadIdx.x; C < nc;
+       C += (size_t)gridDim.x * blockDim.x) {
+    const int J = (int)(C / (size_t)nxc), I = (int)(C - (size_t)J * nxc);
+    dirc[C] = coarse_fixed_semi(dirf, nxf, nyf, nxc, nyc, sx, sy, I, J) ? 1 : 0;
+  }
+}
+
 // Galerkin coarsening of a semi-coarsened level (an extension of eq. 23:
 // one axis halved, strides sx, sy = 2 halved, 1 kept): A_H = (1/2) P^T A_h P
 // with P linear along the halved axis and the identity along the other,
 // restricted to the unknowns as in k_coarsen (zero rows at fine Dirichlet
-// nodes, no columns at coarse Dirichlet nodes, identity rows there).  One
-// thread per coarse node: the fine stencils of its support (at most three
-// nodes) come from the operator -- eq. 18 from the tensor on level 0, the
-// stored stencil below -- and the products are summed in the order of the
-// triple sum (fine node, its neighbour, coarse column).  Setup only.
-template <class Op>
+// nodes, no columns at coarse Dirichlet nodes, identity rows there), with
+// the coarse flags written by k_coarse_flags_semi.  One thread per coarse
+// node: the fine stencils of its support (at most three nodes) come from
+// the operator -- eq. 18 from the tensor on level 0, the stored stencil
+// below -- and the products are summed in the order of the triple sum (fine
+// node, its neighbour, coarse column).  Setup only.
+template <class Op, int sx, int sy>
 __global__ void k_coarsen_semi(Op opf, const uint8_t *__restrict__ dirf, int nxf, int nyf,
-                               int nxc, int nyc, int sx, int sy, uint8_t *__restrict__ dirc,
+                               int nxc, int nyc, const uint8_t *__restrict__ dirc,
                                double *__restrict__ stc, float *__restrict__ stc32) {
   const size_t nc = (size_t)nxc * nyc;
-  const bool hx = sx == 2, hy = sy == 2;
+  constexpr bool hx = sx == 2, hy = sy == 2;
   for (size_t C = (size_t)blockIdx.x * blockDim.x + threadIdx.x; C < nc;
        C += (size_t)gridDim.x * blockDim.x) {
     const int J = (int)(C / (size_t)nxc), I = (int)(C - (size_t)J * nxc);
-    bool fixed[9];
+    bool fixed[9];  // coarse neighbours outside the grid count as Dirichlet
 #pragma unroll
     for (int oj = -1; oj <= 1; ++oj)
 #pragma unroll
-      for (int oi = -1; oi <= 1; ++oi)
-        fixed[(oj + 1) * 3 + oi + 1] =
-            coarse_fixed_semi(dirf, nxf, nyf, nxc, nyc, sx, sy, I + oi, J + oj);
-    dirc[C] = fixed[4] ? 1 : 0;
+      for (int oi = -1; oi <= 1; ++oi) {
+        const int KI = I + oi, KJ = J + oj;
+        fixed[(oj + 1) * 3 + oi + 1] = KI < 0 || KJ < 0 || KI >= nxc || KJ >= nyc ||
+                                       dirc[(size_t)KJ * nxc + KI] != 0;
+      }
     double acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = 0.0;
@@ -2443,14 +2457,25 @@ hipError_t launch_hierarchy(tomg_problem *p, bool defer_inverse) {
                          0.25 / (H * K), 0.5 / (H * K), lc.dir, lc.st, st32);
     } else if (lf.ck != 0) {  // one axis halved
       const int sx = lf.ck == 1 ? 2 : 1, sy = lf.ck == 2 ? 2 : 1;
-      if (l == 1 && !stored_level0(p->cfg))
-        hipLaunchKernelGGL((k_coarsen_semi<EpsOp<double>>), grid1(lc.n), 256, 0, p->stream,
-                           op64(p), (const uint8_t *)lf.dir, lf.nx, lf.ny, lc.nx, lc.ny, sx, sy,
-                           lc.dir, lc.st, st32);
-      else
-        hipLaunchKernelGGL((k_coarsen_semi<StOp<double>>), grid1(lc.n), 256, 0, p->stream,
-                           st_op<double>(lf.st, lf.nx, lf.ny), (const uint8_t *)lf.dir, lf.nx,
-                           lf.ny, lc.nx, lc.ny, sx, sy, lc.dir, lc.st, st32);
+      hipLaunchKernelGGL(k_coarse_flags_semi, grid1(lc.n), 256, 0, p->stream,
+                         (const uint8_t *)lf.dir, lf.nx, lf.ny, lc.nx, lc.ny, sx, sy, lc.dir);
+      const uint8_t *df = lf.dir, *dc = lc.dir;
+      if (l == 1 && !stored_level0(p->cfg)) {
+        if (sx == 2)
+          hipLaunchKernelGGL((k_coarsen_semi<EpsOp<double>, 2, 1>), grid1(lc.n), 256, 0,
+                             p->stream, op64(p), df, lf.nx, lf.ny, lc.nx, lc.ny, dc, lc.st, st32);
+        else
+          hipLaunchKernelGGL((k_coarsen_semi<EpsOp<double>, 1, 2>), grid1(lc.n), 256, 0,
+                             p->stream, op64(p), df, lf.nx, lf.ny, lc.nx, lc.ny, dc, lc.st, st32);
+      } else {
+        const StOp<double> op = st_op<double>(lf.st, lf.nx, lf.ny);
+        if (sx == 2)
+          hipLaunchKernelGGL((k_coarsen_semi<StOp<double>, 2, 1>), grid1(lc.n), 256, 0,
+                             p->stream, op, df, lf.nx, lf.ny, lc.nx, lc.ny, dc, lc.st, st32);
+        else
+          hipLaunchKernelGGL((k_coarsen_semi<StOp<double>, 1, 2>), grid1(lc.n), 256, 0,
+                             p->stream, op, df, lf.nx, lf.ny, lc.nx, lc.ny, dc, lc.st, st32);
+      }
     } else if (l == 1 && !stored_level0(p->cfg))
       hipLaunchKernelGGL(k_coarsen_eps, grid, kGX * kGY, 0, p->stream, op64(p), lf.dir, lf.nx,
                          lf.ny, lc.nx, lc.ny, lc.dir, lc.st, st32);

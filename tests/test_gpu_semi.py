@@ -53,6 +53,9 @@ CASES = {
     "annulus257x129_neumann_x1": (lambda: w.polar_semi_annulus(257, ny=129, neumann=True), 1,
                                   "x"),
     "circle65_all_x3": (lambda: _circle(65, W | E | S | N, seed=1), 3, "x"),
+    # the smallest grids: one pass level above a 5 x 9 or 9 x 3 coarsest grid
+    "sinus9_x2": (lambda: w.manufactured_sinusoidal(9), 2, "x"),
+    "sinus17x9_y1": (lambda: w.manufactured_sinusoidal(17, ny=9), 1, "y"),
     # cells twice as long along the angle: 74 cycles with full coarsening
     "annulus129x65_neumann_x2": (lambda: w.polar_semi_annulus(129, ny=65, neumann=True), 2,
                                  "x"),
