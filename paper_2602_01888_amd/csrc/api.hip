@@ -180,10 +180,11 @@ static tomg_status fail(tomg_problem *p, tomg_status s, const char *fmt, ...) {
       return fail(p, TOMG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
   } while (0)
 
-// Copies the device scalar block to the host and waits for the stream.
-static tomg_status read_scalars(tomg_problem *p, double *h) {
-  HIP_TRY(p, hipMemcpyAsync(h, p->scal, kNumSlots * sizeof(double), hipMemcpyDeviceToHost,
-                            p->stream));
+// Copies the device scalar block (and, with n > kNumSlots, the first n -
+// kNumSlots entries of the residual history after it) to the host and waits
+// for the stream.
+static tomg_status read_scalars(tomg_problem *p, double *h, int n = kNumSlots) {
+  HIP_TRY(p, hipMemcpyAsync(h, p->scal, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(p, hipStreamSynchronize(p->stream));
   prof_harvest(p);
   return TOMG_OK;
@@ -571,14 +572,58 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
   HIP_TRY(p, hipMemcpyAsync(p->scal + kSlotTol, p->up, 2 * sizeof(double),
                             hipMemcpyHostToDevice, p->stream));
   HIP_TRY(p, launch_begin(p, d_phi, ir));
-  double h[kNumSlots];
-  tomg_status s = read_scalars(p, h);
-  if (s != TOMG_OK) return s;
-  s = pending_setup_status(p, h);
-  if (s != TOMG_OK) return s;
-  int cycles = 0;
-  double rel = h[kSlotRel], prev = NAN;
-  int queued = 0;
+  const bool queue = p->cfg.smoother == TOMG_GS4;
+  // k cycles (refinement steps) queued behind the device convergence flag,
+  // the first of them cycle number `first`
+  auto launch_cycles = [&](int first, int k) {
+    p->skip = queue ? p->scal + kSlotDone : nullptr;
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < k && e == hipSuccess; ++q) {
+      if (ir) {
+        // the update and the next residual in one pass; the iterate of an
+        // odd-numbered step lives in the problem's second array (steps
+        // skipped past convergence are a suffix, so the executed count
+        // tells where the last iterate is)
+        e = launch_ir_inner(p);
+        if (e == hipSuccess) e = launch_ir_step(p, d_phi, (first + q) & 1);
+      } else {
+        e = launch_vcycle64(p, d_phi, true);
+      }
+    }
+    p->skip = nullptr;
+    return e;
+  };
+  double h[kNumSlots + 1];
+  int cycles = 0, queued = 0;
+  double rel, rel0, prev = NAN;
+  // A problem whose setup has been checked and that has converged before
+  // queues its first cycles right behind the initial norms, with no host
+  // check between: the initial norms set the device convergence flag (also
+  // for a non-finite start), so cycles queued past it do nothing.  Their
+  // number is what the last solve's contraction predicts from a relative
+  // residual of 1.  The initial relative residual is then read from the
+  // first entry of the residual history.
+  int k0 = 0;
+  if (queue && !p->unchecked && max_cycles > 0 && p->last_rate > 0.0 && p->last_rate < 1.0)
+    k0 = std::max(1, std::min({(int)std::ceil(std::log(rel_tol) / std::log(p->last_rate)), 16,
+                               max_cycles}));
+  if (k0 > 0) {
+    const hipError_t e = launch_cycles(0, k0);
+    if (e != hipSuccess) return fail(p, TOMG_EDEVICE, "solve: cycle launch failed: %s",
+                                     hipGetErrorString(e));
+    tomg_status s = read_scalars(p, h, kNumSlots + 1);
+    if (s != TOMG_OK) return s;
+    rel0 = prev = h[kNumSlots];
+    cycles = queued = (int)h[kSlotCycles];
+    rel = h[kSlotRel];
+  } else {
+    tomg_status s = read_scalars(p, h);
+    if (s != TOMG_OK) return s;
+    s = pending_setup_status(p, h);
+    if (s != TOMG_OK) return s;
+    rel0 = rel = h[kSlotRel];
+  }
+  tomg_status s;
   tomg_status st = TOMG_ENOCONV;
   // Cycles are queued several at a time between host checks.  Each cycle's
   // norm sets the device convergence flag; the launches of cycles queued
@@ -599,9 +644,8 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
       break;
     }
     int k = 1;
-    // the unfused cycles (Jacobi, Neumann edges) have no convergence check of
-    // their own and are checked after every cycle
-    const bool queue = p->cfg.smoother == TOMG_GS4;
+    // the unfused cycles (Jacobi, zebra) have no convergence check of their
+    // own and are checked after every cycle
     if (queue) {
       const double rate = queued > 0 ? std::pow(rel / prev, 1.0 / queued) : NAN;
       if (std::isfinite(rate) && rate > 0.0 && rate < 1.0)
@@ -611,21 +655,7 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
       k = std::max(1, std::min(k, 16));
     }
     k = std::min(k, max_cycles - cycles);
-    p->skip = queue ? p->scal + kSlotDone : nullptr;
-    hipError_t e = hipSuccess;
-    for (int q = 0; q < k && e == hipSuccess; ++q) {
-      if (ir) {
-        // the update and the next residual in one pass; the iterate of an
-        // odd-numbered step lives in the problem's second array (steps
-        // skipped past convergence are a suffix, so the executed count
-        // tells where the last iterate is)
-        e = launch_ir_inner(p);
-        if (e == hipSuccess) e = launch_ir_step(p, d_phi, (cycles + q) & 1);
-      } else {
-        e = launch_vcycle64(p, d_phi, true);
-      }
-    }
-    p->skip = nullptr;
+    const hipError_t e = launch_cycles(cycles, k);
     if (e != hipSuccess) return fail(p, TOMG_EDEVICE, "solve: cycle launch failed: %s",
                                      hipGetErrorString(e));
     s = read_scalars(p, h);
@@ -640,6 +670,8 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
                               hipMemcpyDeviceToDevice, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
   }
+  if (st == TOMG_OK && cycles > 0 && rel0 > 0.0 && rel > 0.0)
+    p->last_rate = std::pow(rel / rel0, 1.0 / cycles);
   if (cycles_out) *cycles_out = cycles;
   if (rel_res_out) *rel_res_out = rel;
   return st;

@@ -210,7 +210,8 @@ __global__ void k_finalize(const double *partials, int n, int stride, double *ou
       if (rel == kRelBegin) scal[kSlotR0] = v;
       const double r = rel_residual(v, scal[kSlotB0], scal[kSlotR0]);
       scal[kSlotRel] = r;
-      scal[kSlotDone] = (r <= scal[kSlotTol]) ? 1.0 : 0.0;
+      // a non-finite start also stops cycles queued behind it
+      scal[kSlotDone] = (r <= scal[kSlotTol] || (rel == kRelBegin && !isfinite(r))) ? 1.0 : 0.0;
       if (rel == kRelCycle) scal[kSlotCycles] += 1.0;
       record_history(scal, rel, r);
     }

@@ -233,6 +233,8 @@ struct tomg_problem {
   const double *skip = nullptr;     // device convergence flag while solve() queues cycles
   double up[2] = {0.0, 0.0};        // source of the tolerance/cycle-count upload
   bool unchecked = false;           // setup issued without its host-side check
+  double last_rate = 0.0;           // mean contraction per cycle of the last converged
+                                    // solve (0: none yet)
   bool inv_pending = false;         // coarsest inverse of the last setup not launched yet
   bool has_map = false;             // the last setup came from a map descriptor
   tomg_map_desc map{};              // ... this one (for tomg_update_rhs_desc)
