@@ -306,8 +306,12 @@ tomg_status vcycle(tomg_problem *p, double *d_phi);
  * the initial guess instead.  Host outputs (nullable): *cycles_out cycles
  * (refinement steps for TOMG_FP32_IR) taken, *rel_res_out the final relative
  * residual.  Returns TOMG_ENOCONV with phi holding the last iterate if
- * max_cycles is reached, TOMG_ENONFINITE if the residual becomes NaN/Inf.
- * Synchronises the problem's stream. */
+ * max_cycles is reached, TOMG_ENONFINITE if the residual becomes NaN/Inf (a
+ * non-finite initial residual leaves d_phi unchanged).  Cycles are queued in
+ * groups behind a device-side convergence flag and the host reads the
+ * residual between groups; cycles queued past convergence do nothing, so the
+ * result, the cycle count and the residual history are those of a check
+ * after every cycle.  Synchronises the problem's stream. */
 tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cycles,
                   int32_t *cycles_out, double *rel_res_out);
 
