@@ -243,8 +243,9 @@ __device__ __forceinline__ double d_j(const double *a, int nx, int ny, int j, si
 }
 
 // Grid-stride over the nodes in memory order, so that the whole grid of
-// threads sweeps one contiguous window of the arrays.  When exx32 is given the FP32 copies of the tensor used by the inner solver
-// of iterative refinement are written beside the FP64 fields.
+// threads sweeps one contiguous window of the arrays.  When exx32 is given
+// the FP32 copies of the tensor used by the inner solver of iterative
+// refinement are written beside the FP64 fields.
 __global__ void k_setup(int nx, int ny, double dx, double dy, const double *__restrict__ xp,
                         const double *__restrict__ yp, const double *__restrict__ jac,
                         const double *__restrict__ epsp, const double *__restrict__ rho,
