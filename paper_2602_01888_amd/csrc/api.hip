@@ -600,13 +600,16 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
   // queues its first cycles right behind the initial norms, with no host
   // check between: the initial norms set the device convergence flag (also
   // for a non-finite start), so cycles queued past it do nothing.  Their
-  // number is what the last solve's contraction predicts from a relative
-  // residual of 1.  The initial relative residual is then read from the
+  // number is what the last solve's contraction predicts from that solve's
+  // initial relative residual (1 from a cold start, less for a sequence of
+  // warm starts).  The initial relative residual is then read from the
   // first entry of the residual history.
   int k0 = 0;
-  if (queue && !p->unchecked && max_cycles > 0 && p->last_rate > 0.0 && p->last_rate < 1.0)
-    k0 = std::max(1, std::min({(int)std::ceil(std::log(rel_tol) / std::log(p->last_rate)), 16,
-                               max_cycles}));
+  if (queue && !p->unchecked && max_cycles > 0 && p->last_rate > 0.0 && p->last_rate < 1.0) {
+    const double from = std::min(1.0, std::max(p->last_rel0, rel_tol));
+    k0 = std::max(1, std::min({(int)std::ceil(std::log(rel_tol / from) / std::log(p->last_rate)),
+                               16, max_cycles}));
+  }
   if (k0 > 0) {
     const hipError_t e = launch_cycles(0, k0);
     if (e != hipSuccess) return fail(p, TOMG_EDEVICE, "solve: cycle launch failed: %s",
@@ -670,8 +673,10 @@ tomg_status solve(tomg_problem *p, double *d_phi, double rel_tol, int32_t max_cy
                               hipMemcpyDeviceToDevice, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
   }
-  if (st == TOMG_OK && cycles > 0 && rel0 > 0.0 && rel > 0.0)
+  if (st == TOMG_OK && cycles > 0 && rel0 > 0.0 && rel > 0.0) {
     p->last_rate = std::pow(rel / rel0, 1.0 / cycles);
+    p->last_rel0 = rel0;
+  }
   if (cycles_out) *cycles_out = cycles;
   if (rel_res_out) *rel_res_out = rel;
   return st;

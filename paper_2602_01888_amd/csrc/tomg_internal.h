@@ -235,6 +235,7 @@ struct tomg_problem {
   bool unchecked = false;           // setup issued without its host-side check
   double last_rate = 0.0;           // mean contraction per cycle of the last converged
                                     // solve (0: none yet)
+  double last_rel0 = 1.0;           // the initial relative residual of that solve
   bool inv_pending = false;         // coarsest inverse of the last setup not launched yet
   bool has_map = false;             // the last setup came from a map descriptor
   tomg_map_desc map{};              // ... this one (for tomg_update_rhs_desc)
