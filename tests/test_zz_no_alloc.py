@@ -53,6 +53,27 @@ def test_noalloc_equals_workspace_path(tomg, precision):
                               else prob.phi0[0])
 
 
+def test_noalloc_semi_coarsened_neumann(tomg):
+    """A configuration with Neumann edges and semi-coarsened levels through
+    the allocation-free call: bitwise the workspace path's result."""
+    import torch
+    prob = w.polar_semi_annulus(257, neumann=True)
+    print("[noalloc] semi-coarsened Neumann 257x257", flush=True)
+    p, d = tomg.setup_from_grid(prob, semi_levels=2)
+    phi_ref = d["phi0"].clone()
+    ref = p.solve(phi_ref, rel_tol=1e-10, max_cycles=100)
+    assert ref.ok
+    cfg = tomg.make_config(prob.nx, prob.ny, prob.dx, prob.dy, prob.xi0, prob.eta0,
+                           neumann=prob.neumann, semi_levels=2)
+    phi = d["phi0"].clone()
+    res, msg = tomg.solve_noalloc(cfg, d["rho"], phi, xp=d["xp"], yp=d["yp"], jac=d["jac"],
+                                  mask=d["mask"], rel_tol=1e-10, max_cycles=100)
+    torch.cuda.synchronize()
+    assert res.ok and msg == "", msg
+    assert res.cycles == ref.cycles and res.rel == ref.rel
+    assert bool((phi == phi_ref).all())
+
+
 def test_noalloc_refuses_oversized_problems(tomg):
     import torch
     cfg = tomg.make_config(2049, 2049, 1 / 2048, 1 / 2048)
