@@ -134,10 +134,8 @@ typedef struct {
                               smoother's convergence independent of the
                               anisotropy.  Default 0; > 0 needs TOMG_GS4 and
                               TOMG_GALERKIN and runs the fused level passes down
-                              to the coarsest solve; such problems share no
-                              batched launch (tomg_solve_batch solves them one
-                              after another, tomg_batch_step and
-                              tomg_batch_launch refuse them with TOMG_EINVAL) */
+                              to the coarsest solve; it is batched only with
+                              problems of the same semi_levels and semi_axis */
   int32_t semi_axis;       /* axis halved by the semi-coarsened levels: 0 the
                               x axis (i, nx), 1 the y axis (j, ny) */
 } tomg_config;

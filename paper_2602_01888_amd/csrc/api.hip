@@ -694,7 +694,8 @@ namespace {
 
 // Batched execution needs one configuration of the cycle for all problems:
 // one launch serves a stage of every problem, so the level-0 operator is
-// either on-the-fly eq. 18 for all of them or a stored stencil for all.
+// either on-the-fly eq. 18 for all of them or a stored stencil for all, and
+// the level transfers are the same (equal semi-coarsened levels).
 bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
   const tomg_problem *lead = probs[0];
   if (!lead) return false;
@@ -702,7 +703,8 @@ bool batch_uniform(tomg_problem *const *probs, double *const *d_phis, int n) {
     const tomg_problem *p = probs[k];
     if (!p || !d_phis[k] || !p->ready) return false;
     if (p->cfg.precision != lead->cfg.precision || p->cfg.nu1 != lead->cfg.nu1 ||
-        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 || p->cfg.semi_levels != 0 ||
+        p->cfg.nu2 != lead->cfg.nu2 || p->cfg.smoother != TOMG_GS4 ||
+        p->cfg.semi_levels != lead->cfg.semi_levels || p->cfg.semi_axis != lead->cfg.semi_axis ||
         stored_level0(p->cfg) != stored_level0(lead->cfg) ||
         p->cfg.ir_inner_cycles != lead->cfg.ir_inner_cycles)
       return false;

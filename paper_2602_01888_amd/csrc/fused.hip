@@ -554,8 +554,11 @@ __device__ __forceinline__ const BatchEntry &batch_locate(const BatchTab &tab, i
   return tab.e[lo];
 }
 
-// Batched form: each problem runs exactly the blocks it would run alone.
-template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+// Batched form: each problem runs exactly the blocks it would run alone
+// (one transfer kind per launch: the problems of a batch share their
+// semi-coarsened levels).
+template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM,
+          int CK = 0>
 __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
   const BatchEntry &e = batch_locate(tab, blockIdx.x);
   PassArgs<T> a = *static_cast<const PassArgs<T> *>(e.args);
@@ -563,9 +566,9 @@ __global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
   if (e.role == 2) a.xout = static_cast<T *>(e.phi);
   const int local = blockIdx.x - e.start, bx = local % e.nbx, by = local / e.nbx;
   if (mirrored<T>(by, a.ny))
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, 0>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, CK>(a, bx, by);
   else
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, 0>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, CK>(a, bx, by);
 }
 
 }  // namespace
@@ -619,7 +622,8 @@ size_t fused_max_blocks(int nx, int ny) {
 #endif
 
 // Sweep count, pair count and transfer kind are compile-time; dispatch on
-// the runtime nu and a.ck (batched launches: both axes halved).
+// the runtime nu and a.ck (for a batched launch, that of its first problem:
+// every problem of a batch has the same transfer at a given level).
 template <typename T, bool EPS, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
 static void launch_pass(int nu, const PassArgs<T> &a, hipStream_t s, const BatchTab *tab,
                         int nblocks) {
@@ -627,7 +631,13 @@ static void launch_pass(int nu, const PassArgs<T> &a, hipStream_t s, const Batch
   const dim3 grid = a.xcd_order ? dim3(a.nbx * a.nby) : dim3(a.nbx, a.nby);
 #define TOMG_LAUNCH(NU)                                                                          \
   do {                                                                                           \
-    if (tab)                                                                                     \
+    if (tab && a.ck == 1)                                                                        \
+      hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 1>),           \
+                         dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
+    else if (tab && a.ck == 2)                                                                   \
+      hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 2>),           \
+                         dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
+    else if (tab)                                                                                \
       hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>),              \
                          dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
     else if (a.ck == 1)                                                                          \

@@ -148,22 +148,51 @@ def test_semi_fp32_inner_cycles_reach_oracle(tomg, name):
     assert rel <= 1e-10 * (1 + 1e-6), rel
 
 
-def test_semi_is_not_batched(tomg):
-    """One batched launch serves one transfer kind: a continuous-batching
-    step refuses semi-coarsened problems, and the batched solve runs them one
-    after another, each bitwise as alone."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_semi_batch_equals_alone(tomg, precision):
+    """Problems with the same semi-coarsened levels share the batched
+    launches (one transfer kind per level): each result is bitwise its
+    solve alone, on grids of several sizes and with Neumann and Dirichlet
+    edges; a continuous-batching step takes them too."""
+    import torch
+    stored = [w.polar_semi_annulus(65, neumann=True), w.polar_semi_annulus(129, neumann=True),
+              w.polar_semi_annulus(257, ny=129, neumann=True)]
+    onfly = [w.polar_semi_annulus(129), w.perturbed_circle(65, seed=3)]
+    for probs in (stored, onfly):
+        print(f"[semi_batch] {precision} {[(q.nx, q.ny) for q in probs]}", flush=True)
+        ps, ds = zip(*[tomg.setup_from_grid(q, semi_levels=2, precision=precision)
+                       for q in probs])
+        phis = [d["phi0"].clone() for d in ds]
+        res = tomg.solve_batch(list(ps), phis, rel_tol=1e-10, max_cycles=100)
+        assert all(r.ok for r in res), res
+        for p, d, phi, r in zip(ps, ds, phis, res):
+            alone = d["phi0"].clone()
+            ra = p.solve(alone, rel_tol=1e-10, max_cycles=100)
+            assert ra.cycles == r.cycles
+            assert torch.equal(alone, phi)
+        step = [d["phi0"].clone() for d in ds]
+        rel = tomg.batch_step(list(ps), step, [True] * len(ps))
+        assert all(np.isfinite(rel))
+
+
+def test_semi_mixed_with_full_coarsening_in_one_batch(tomg):
+    """Different transfers cannot share launches: tomg_solve_batch solves
+    such a set one problem after another, each bitwise as alone, and a
+    continuous-batching step refuses it."""
     import torch
     q = w.polar_semi_annulus(65, neumann=True)
-    p, d = tomg.setup_from_grid(q, semi_levels=1)
+    p1, d1 = tomg.setup_from_grid(q, semi_levels=1)
+    p2, d2 = tomg.setup_from_grid(q)
+    phis = [d1["phi0"].clone(), d2["phi0"].clone()]
+    res = tomg.solve_batch([p1, p2], phis, rel_tol=1e-10)
+    assert all(r.ok for r in res)
+    for p, d, phi in ((p1, d1, phis[0]), (p2, d2, phis[1])):
+        a = d["phi0"].clone()
+        assert p.solve(a, rel_tol=1e-10).ok
+        assert torch.equal(a, phi)
     with pytest.raises(tomg.TomgError) as e:
-        tomg.batch_step([p], [d["phi0"].clone()], [True])
+        tomg.batch_step([p1, p2], [d1["phi0"].clone(), d2["phi0"].clone()], [True, True])
     assert e.value.status == tomg.TOMG_EINVAL
-    a = d["phi0"].clone()
-    assert p.solve(a, rel_tol=1e-10).ok
-    b = d["phi0"].clone()
-    res = tomg.solve_batch([p], [b], rel_tol=1e-10)
-    assert res[0].ok
-    assert torch.equal(a, b)
 
 
 def test_fullsize_semi_annulus_semi_coarsening(tomg):
