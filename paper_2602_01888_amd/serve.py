@@ -6,9 +6,9 @@ together, one V-cycle (or refinement step) per ``tomg_batch_step``; between
 two steps it retires problems that reached the tolerance and admits queued
 requests, so a request that arrives while others are being solved joins the
 next step instead of waiting for the batch to drain.  One batched launch
-serves one level-0 operator form, so a step advances the problems with the
-on-the-fly eq. 18 operator and those with a stored stencil (Neumann edges,
-flux form) as two groups.
+serves one level-0 operator form and one set of level transfers, so a step
+advances the problems in groups: the on-the-fly eq. 18 operator or a stored
+stencil (Neumann edges, flux form), and the semi-coarsened levels.
 
 Memory.  Every geometry the server holds (being solved, or idle and kept for
 a later warm re-solve) costs its library workspace plus its solution array;
@@ -89,6 +89,8 @@ class Request:
     eta0: float = 0.0
     neumann: int = 0      # edges with a zero normal derivative (TOMG_NEU_* bits)
     flux: bool = False    # the symmetric flux form of the operator
+    semi_levels: int = 0  # leading coarsenings that halve one axis only
+    semi_axis: str = "x"  # the axis they halve
     # the same request as descriptors (keyword arguments of the library's
     # map_desc and source_desc): a backend that takes them evaluates the map
     # and the source in its setup kernel, with no input arrays
@@ -105,7 +107,13 @@ class Request:
         """What a problem's workspace depends on: a problem created for one
         request can be set up again for another of the same shape."""
         return (self.nx, self.ny, self.dx, self.dy, self.xi0, self.eta0, self.neumann,
-                bool(self.flux))
+                bool(self.flux), self.semi_levels, self.semi_axis)
+
+    @property
+    def step_kind(self):
+        """Requests of one kind share a batched step: the same level-0
+        operator form and the same semi-coarsened levels."""
+        return (self.stored_form, self.semi_levels, self.semi_axis if self.semi_levels else "")
 
 
 @dataclass
@@ -176,7 +184,9 @@ class TomgBackend:
 
     def footprint(self, req: Request) -> int:
         cfg = self.tomg.make_config(req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0,
-                                    neumann=req.neumann, flux=req.flux, **self.kw)
+                                    neumann=req.neumann, flux=req.flux,
+                                    semi_levels=req.semi_levels, semi_axis=req.semi_axis,
+                                    **self.kw)
         return self.tomg.workspace_bytes(cfg) + 8 * req.nx * req.ny
 
     def transient(self, req: Request) -> int:
@@ -194,7 +204,8 @@ class TomgBackend:
         workspace the new setup overwrites); returns (problem, phi)."""
         p = reuse if reuse is not None else self.tomg.Problem(
             req.nx, req.ny, req.dx, req.dy, req.xi0, req.eta0, device=self.device,
-            neumann=req.neumann, flux=req.flux, **self.kw)
+            neumann=req.neumann, flux=req.flux, semi_levels=req.semi_levels,
+            semi_axis=req.semi_axis, **self.kw)
         if self._by_desc(req):
             with self.torch.cuda.stream(p.stream):
                 phi = self.torch.empty((req.ny, req.nx), dtype=self.torch.float64,
@@ -377,14 +388,13 @@ class Server:
 
     # -- one step ------------------------------------------------------------
     def _groups(self, acts):
-        """One batched step per level-0 operator form (on the fly / stored):
-        the positions in `acts` of each non-empty group."""
-        out = []
-        for form in (False, True):
-            grp = [k for k, a in enumerate(acts) if a.req.stored_form == form]
-            if grp:
-                out.append(grp)
-        return out
+        """One batched step per kind of request (level-0 operator form, on
+        the fly or stored, and semi-coarsened levels): the positions in
+        `acts` of each non-empty group, in order of first appearance."""
+        out = OrderedDict()
+        for k, a in enumerate(acts):
+            out.setdefault(a.req.step_kind, []).append(k)
+        return list(out.values())
 
     def _args(self, acts, grp):
         return ([acts[k].res.problem for k in grp], [acts[k].res.phi for k in grp],

@@ -29,7 +29,7 @@ def alone(torch, tomg, r, precision="fp32_ir"):
     geometry's map gives the same coefficients and right-hand side as the
     served update of the source)."""
     p = tomg.Problem(r.nx, r.ny, r.dx, r.dy, r.xi0, r.eta0, precision=precision,
-                     neumann=r.neumann)
+                     neumann=r.neumann, semi_levels=r.semi_levels, semi_axis=r.semi_axis)
     ph = torch.empty((r.ny, r.nx), dtype=torch.float64, device="cuda")
     p.setup_desc(tomg.map_desc(**r.map_desc), tomg.source_desc(**r.source_desc), phi_init=ph)
     return p
@@ -156,6 +156,37 @@ def test_served_neumann_and_circle_mix_equal_alone(env, precision):
     print(f"[serve_mix] {len(reqs)} requests {precision}: {kinds.count('annulus')} annulus, "
           f"{sum(d['warm'] for d in descs)} warm", flush=True)
     assert "annulus" in kinds and "circle" in kinds
+    srv = serve.Server(serve.TomgBackend(precision=precision), budget_bytes=8 << 30,
+                       max_active=6, keep_results=True, max_cycles=200)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.drain()
+    assert len(done) == len(reqs) and all(c.ok for c in done), [c for c in done if not c.ok]
+    by = {r.rid: r for r in reqs}
+    for c in done:
+        r = by[c.rid]
+        p = alone(torch, tomg, r, precision)
+        phi = c.phi_start.clone()
+        ra = p.solve(phi, rel_tol=1e-10, max_cycles=200)
+        assert ra.cycles == c.cycles, (c.rid, ra, c)
+        assert bool((phi == c.phi).all()), c.rid
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir", "fp64"])
+def test_served_semi_coarsened_requests_equal_alone(env, precision):
+    """The same mix with the semi-annulus requests on semi-coarsened levels
+    (the radius halved alone twice): those are stepped in their own batched
+    group, and each result is bitwise the solve of the same request alone."""
+    torch, tomg, serve, D = env
+    descs = w.serving_stream(16, rate=1000.0, seed=5, sides=(65, 129, 257),
+                             kinds=("circle", "annulus"))
+    reqs = [serve.Request(**D.request_fields(d, "cuda")) for d in descs]
+    for r, d in zip(reqs, descs):
+        if d["kind"] == "annulus":
+            r.semi_levels, r.semi_axis = 2, "x"
+    kinds = {r.step_kind for r in reqs}
+    print(f"[serve_semi] {len(reqs)} requests {precision}, kinds {sorted(kinds)}", flush=True)
+    assert len(kinds) == 2
     srv = serve.Server(serve.TomgBackend(precision=precision), budget_bytes=8 << 30,
                        max_active=6, keep_results=True, max_cycles=200)
     for r in reqs:

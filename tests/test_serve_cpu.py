@@ -413,3 +413,25 @@ def test_completion_records_queue_depth_and_hbm_in_use():
     # geometries stay resident: the server holds their bytes too)
     assert done[2].queue_depth <= 2 and done[2].hbm_used >= 3000
     assert all(c.admitted >= c.arrival for c in done.values())
+
+
+def test_one_step_group_per_kind():
+    """Requests on semi-coarsened levels (per axis and count) and requests
+    with a stored level-0 stencil are each stepped in a batch of their own;
+    the groups follow the order in which their kinds first appear."""
+    be = FakeBackend(rate=0.1)
+    s = S.Server(be, budget_bytes=10 ** 6, rel_tol=2e-3, clock=Clock())
+    rs = [req(k) for k in range(6)]
+    rs[1].semi_levels = 2
+    rs[3].semi_levels, rs[3].semi_axis = 2, "y"
+    rs[4].semi_levels = 2
+    rs[5].neumann = 1  # a Neumann west edge: stored level-0 stencil
+    assert rs[0].step_kind != rs[1].step_kind != rs[3].step_kind != rs[5].step_kind
+    for r in rs:
+        s.submit(r)
+    s.step()
+    assert be.steps == [[0, 2], [1, 4], [3], [5]]
+    # With no semi-coarsening the axis does not split a group.
+    r6, r7 = req(6), req(7)
+    r7.semi_axis = "y"
+    assert r6.step_kind == r7.step_kind
