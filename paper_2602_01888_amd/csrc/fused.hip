@@ -8,9 +8,12 @@
 //   up pass:   bilinear prolongation and correction on load (eq. 24) + nu
 //              sweeps [+ partial sums of the final residual's squares].
 //
-// Block geometry: kBW threads own kBW consecutive columns (one each); the
+// Block geometry: BW threads own BW consecutive columns (one each); the
 // H = 4 nu + 2 outer columns on either side are halo, recomputed by the
-// neighbouring block, so only W = kBW - 2H columns are written.  The block
+// neighbouring block, so only W = BW - 2H columns are written.  BW is 128
+// (two waves) for a pass alone, 64 (one wave) on the stored-stencil levels
+// small enough to be bound by the chain of colour phases rather than by
+// memory traffic, and 256 in batched launches and in the chained pass.  The block
 // owns a band of CH rows and marches up it two rows at a time, starting
 // HV = 2 nu + 3 rows below the band and stopping HV rows above it.  Node
 // values of the rows in flight live in LDS; their stencil coefficients and
@@ -35,12 +38,25 @@ namespace tomg {
 namespace {
 
 #ifndef TOMG_BW
-#define TOMG_BW 256
+#define TOMG_BW 128
 #endif
 #ifndef TOMG_MIN_WAVES
 #define TOMG_MIN_WAVES 1
 #endif
+// Block widths.  A colour phase ends in a barrier over the block's waves, so
+// narrower blocks shorten each step's chain of phases and give the device
+// more blocks, at the cost of more recomputed halo columns (2H of BW).
+// Measured per pass at 4097^2, FP64, four-wave -> two-wave blocks: level 0
+// down 250 -> 232 us, up 272 -> 261, 2049^2 119 -> 112 and 101 -> 98; FP32
+// level 0 138 -> 128 and 130 -> 129.  One-wave blocks on the stored levels
+// up to 1025^2 (four-wave -> one-wave): 1025^2 44.7 -> 38.6 us, 513^2 25.9
+// -> 21.6, 257^2 19.0 -> 16.2, 129^2 19.2 -> 13.7; on level 0 and at 2049^2
+// they are slower (266 and 301 us at level 0).  The chained pass (four
+// sweeps, H = 18) keeps four waves: 325 us against 344 with two.
 constexpr int kBW = TOMG_BW;
+constexpr int kBWSmall = 64;
+constexpr int kBWWide = 256;
+constexpr long kSmallPassNodes = 2L << 20;  // largest level given one-wave blocks
 
 // Streaming stores: the pass outputs are read back by the next pass, long
 // after the caches have turned over, so they are written with the
@@ -123,7 +139,7 @@ __device__ __forceinline__ void apply(const Rec<T, EPS> &c, const T *lo, const T
     apply_st<T>(c, lo, mid, hi, t, off, dg);
 }
 
-template <typename T>
+template <typename T, int BW>
 __device__ __forceinline__ T block_sum(T v, T *red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -132,7 +148,7 @@ __device__ __forceinline__ T block_sum(T v, T *red) {
   if (lane == 0) red[wid] = v;
   __syncthreads();
   if (threadIdx.x == 0)
-    for (int k = 1; k < kBW / 64; ++k) v += red[k];
+    for (int k = 1; k < BW / 64; ++k) v += red[k];
   return v;
 }
 
@@ -149,7 +165,7 @@ constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 // (semi-coarsening: linear along the halved axis, the identity along the
 // kept one, restriction (1/4) [1 2 1] along the halved axis).
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM,
-          bool MIR, int CK>
+          bool MIR, int CK, int BW>
 __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, const int by) {
   constexpr bool PF = EPS;  // level 0: the next step's rows are loaded during this step
   constexpr int H = 4 * NU + 2;
@@ -158,9 +174,9 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
   constexpr int NR = NS + 2;                       // value rows in LDS
   constexpr int PER = NS / cgcd(2 * P, NS);        // steps until the slot ring repeats
   constexpr int NX = (4 * P > P + 1) ? 4 * P : P + 1;
-  __shared__ T L[NR][kBW + 2];
-  __shared__ T xch[NX][kBW + 2];
-  __shared__ double red[kBW / 64];
+  __shared__ T L[NR][BW + 2];
+  __shared__ T xch[NX][BW + 2];
+  __shared__ double red[BW / 64];
 
   const int nx = a.nx, ny = a.ny;
   const int t = threadIdx.x;
@@ -189,10 +205,10 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
 
   for (int r = 0; r < NR; ++r) {
     L[r][t + 1] = T(0);
-    if (t < 2) L[r][t * (kBW + 1)] = T(0);
+    if (t < 2) L[r][t * (BW + 1)] = T(0);
   }
   if (t < 2)
-    for (int r = 0; r < NX; ++r) xch[r][t * (kBW + 1)] = T(0);
+    for (int r = 0; r < NX; ++r) xch[r][t * (BW + 1)] = T(0);
 
   auto slot = [&](int rel) { return ((rel % NS) + NS) % NS; };
   auto lrow = [&](int r) -> T * { return L[((r % NR) + NR) % NR]; };
@@ -501,7 +517,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, const int bx, co
     if (!more) break;
   }
   if constexpr (NORM) {
-    const double s = block_sum<double>((double)acc, red);
+    const double s = block_sum<double, BW>((double)acc, red);
     if (t == 0) a.partials[(size_t)by * a.nbx + bx] = s;
   }
 }
@@ -533,15 +549,15 @@ __device__ __forceinline__ void xcd_tile(int id, int nbx, int nby, int &bx, int 
 }
 
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM,
-          int CK = 0>
-__global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
+          int CK = 0, int BW = kBW>
+__global__ __launch_bounds__(BW, TOMG_MIN_WAVES) void k_pass(PassArgs<T> a) {
   if (a.skip && *a.skip != 0.0) return;
   int bx = blockIdx.x, by = blockIdx.y;
   if (a.xcd_order) xcd_tile(blockIdx.x, a.nbx, a.nby, bx, by);
   if (mirrored<T>(by, a.ny))
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, CK>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, CK, BW>(a, bx, by);
   else
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, CK>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, CK, BW>(a, bx, by);
 }
 
 // Entry of a batched launch holding block b (entries sorted by start).
@@ -559,16 +575,16 @@ __device__ __forceinline__ const BatchEntry &batch_locate(const BatchTab &tab, i
 // semi-coarsened levels).
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM,
           int CK = 0>
-__global__ __launch_bounds__(kBW, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
+__global__ __launch_bounds__(kBWWide, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
   const BatchEntry &e = batch_locate(tab, blockIdx.x);
   PassArgs<T> a = *static_cast<const PassArgs<T> *>(e.args);
   if (e.role == 1) a.xin = static_cast<const T *>(e.phi);
   if (e.role == 2) a.xout = static_cast<T *>(e.phi);
   const int local = blockIdx.x - e.start, bx = local % e.nbx, by = local / e.nbx;
   if (mirrored<T>(by, a.ny))
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, CK>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, CK, kBWWide>(a, bx, by);
   else
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, CK>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, CK, kBWWide>(a, bx, by);
 }
 
 }  // namespace
@@ -610,7 +626,8 @@ static int pick_band(int nx, int ny, int W, long slots, int hv) {
 // Upper bound of the block count of any pass on an nx x ny level (sizes the
 // partial-sum buffer).
 size_t fused_max_blocks(int nx, int ny) {
-  const int Wmin = kBW - 2 * (4 * 4 + 2);
+  const int bw = (long)nx * ny <= kSmallPassNodes ? kBWSmall : (kBW < kBWWide ? kBW : kBWWide);
+  const int Wmin = bw - 2 * (4 * 4 + 2);
   return (size_t)((nx + Wmin - 1) / Wmin) * (size_t)((ny + kMinBand - 1) / kMinBand);
 }
 
@@ -621,6 +638,15 @@ size_t fused_max_blocks(int nx, int ny) {
 #define TOMG_PAIRS_ST 1
 #endif
 
+// A one-wave-block pass (stored stencils only: no such variant of the
+// level-0 pass that forms its coefficients from the tensor is built).
+template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+static void launch_small(const PassArgs<T> &a, dim3 grid, hipStream_t s) {
+  if constexpr (!EPS)
+    hipLaunchKernelGGL((k_pass<T, false, NU, P, ZERO, PROLONG, RESTRICT, NORM, 0, kBWSmall>), grid,
+                       dim3(kBWSmall), 0, s, a);
+}
+
 // Sweep count, pair count and transfer kind are compile-time; dispatch on
 // the runtime nu and a.ck (for a batched launch, that of its first problem:
 // every problem of a batch has the same transfer at a given level).
@@ -629,17 +655,21 @@ static void launch_pass(int nu, const PassArgs<T> &a, hipStream_t s, const Batch
                         int nblocks) {
   constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
   const dim3 grid = a.xcd_order ? dim3(a.nbx * a.nby) : dim3(a.nbx, a.nby);
+  // one-wave blocks: stored stencils, both axes halved, alone (make_args)
+  const bool small = !EPS && !tab && a.bw == kBWSmall;
 #define TOMG_LAUNCH(NU)                                                                          \
   do {                                                                                           \
     if (tab && a.ck == 1)                                                                        \
       hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 1>),           \
-                         dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
+                         dim3(nblocks), dim3(kBWWide), 0, s, *tab);                                  \
     else if (tab && a.ck == 2)                                                                   \
       hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 2>),           \
-                         dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
+                         dim3(nblocks), dim3(kBWWide), 0, s, *tab);                                  \
     else if (tab)                                                                                \
       hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>),              \
-                         dim3(nblocks), dim3(kBW), 0, s, *tab);                                  \
+                         dim3(nblocks), dim3(kBWWide), 0, s, *tab);                                  \
+    else if (small)                                                                              \
+      launch_small<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, grid, s);                   \
     else if (a.ck == 1)                                                                          \
       hipLaunchKernelGGL((k_pass<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 1>), grid,       \
                          dim3(kBW), 0, s, a);                                                    \
@@ -669,28 +699,34 @@ static int device_cus() {
 }
 
 // Blocks of one pass kernel that fit on a CU at once.
-template <typename T, bool EPS, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM>
+template <typename T, bool EPS, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM, int BW = kBW>
 static int pass_blocks_per_cu(int nu) {
   constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
   const void *f;
   switch (nu) {
-    case 1: f = reinterpret_cast<const void *>(k_pass<T, EPS, 1, P, ZERO, PROLONG, RESTRICT, NORM>); break;
-    case 2: f = reinterpret_cast<const void *>(k_pass<T, EPS, 2, P, ZERO, PROLONG, RESTRICT, NORM>); break;
-    case 3: f = reinterpret_cast<const void *>(k_pass<T, EPS, 3, P, ZERO, PROLONG, RESTRICT, NORM>); break;
-    default: f = reinterpret_cast<const void *>(k_pass<T, EPS, 4, P, ZERO, PROLONG, RESTRICT, NORM>); break;
+    case 1: f = reinterpret_cast<const void *>(k_pass<T, EPS, 1, P, ZERO, PROLONG, RESTRICT, NORM, 0, BW>); break;
+    case 2: f = reinterpret_cast<const void *>(k_pass<T, EPS, 2, P, ZERO, PROLONG, RESTRICT, NORM, 0, BW>); break;
+    case 3: f = reinterpret_cast<const void *>(k_pass<T, EPS, 3, P, ZERO, PROLONG, RESTRICT, NORM, 0, BW>); break;
+    default: f = reinterpret_cast<const void *>(k_pass<T, EPS, 4, P, ZERO, PROLONG, RESTRICT, NORM, 0, BW>); break;
   }
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBW, 0) != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, BW, 0) != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
 
 // Resident-block slots of the pass of level l (the variant a solve launches;
-// eps0: level 0 forms its coefficients from the tensor).
+// eps0: level 0 forms its coefficients from the tensor; small: one-wave
+// blocks on a stored stencil).
 template <typename T>
-static long pass_slots(int l, bool up, int nu, bool eps0) {
+static long pass_slots(int l, bool up, int nu, bool eps0, bool small) {
   constexpr bool F64 = std::is_same<T, double>::value;
   int nb;
-  if (l == 0 && !eps0) {
+  if (small) {
+    nb = up ? (l == 0 ? pass_blocks_per_cu<T, false, false, true, false, F64, kBWSmall>(nu)
+                      : pass_blocks_per_cu<T, false, false, true, false, false, kBWSmall>(nu))
+            : (l == 0 ? pass_blocks_per_cu<T, false, false, false, true, false, kBWSmall>(nu)
+                      : pass_blocks_per_cu<T, false, true, false, true, false, kBWSmall>(nu));
+  } else if (l == 0 && !eps0) {
     nb = up ? pass_blocks_per_cu<T, false, false, true, false, F64>(nu)
             : pass_blocks_per_cu<T, false, false, false, true, false>(nu);
   } else if (l == 0) {
@@ -715,12 +751,12 @@ static int updown_blocks_per_cu(int nu) {
   constexpr int P = EPS ? TOMG_PAIRS_EPS : TOMG_PAIRS_ST;
   const void *f;
   switch (nu) {
-    case 2: f = reinterpret_cast<const void *>(k_pass<T, EPS, 2, P, false, true, true, false>); break;
-    case 3: f = reinterpret_cast<const void *>(k_pass<T, EPS, 3, P, false, true, true, false>); break;
-    default: f = reinterpret_cast<const void *>(k_pass<T, EPS, 4, P, false, true, true, false>); break;
+    case 2: f = reinterpret_cast<const void *>(k_pass<T, EPS, 2, P, false, true, true, false, 0, kBWWide>); break;
+    case 3: f = reinterpret_cast<const void *>(k_pass<T, EPS, 3, P, false, true, true, false, 0, kBWWide>); break;
+    default: f = reinterpret_cast<const void *>(k_pass<T, EPS, 4, P, false, true, true, false, 0, kBWWide>); break;
   }
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBW, 0) != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBWWide, 0) != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
 
@@ -730,16 +766,16 @@ static void launch_updown_ck(int nu, const PassArgs<T> &a, hipStream_t s) {
   const dim3 grid = a.xcd_order ? dim3(a.nbx * a.nby) : dim3(a.nbx, a.nby);
   switch (nu) {
     case 2:
-      hipLaunchKernelGGL((k_pass<T, EPS, 2, P, false, true, true, false, CK>), grid, dim3(kBW), 0,
-                         s, a);
+      hipLaunchKernelGGL((k_pass<T, EPS, 2, P, false, true, true, false, CK, kBWWide>), grid,
+                         dim3(kBWWide), 0, s, a);
       break;
     case 3:
-      hipLaunchKernelGGL((k_pass<T, EPS, 3, P, false, true, true, false, CK>), grid, dim3(kBW), 0,
-                         s, a);
+      hipLaunchKernelGGL((k_pass<T, EPS, 3, P, false, true, true, false, CK, kBWWide>), grid,
+                         dim3(kBWWide), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_pass<T, EPS, 4, P, false, true, true, false, CK>), grid, dim3(kBW), 0,
-                         s, a);
+      hipLaunchKernelGGL((k_pass<T, EPS, 4, P, false, true, true, false, CK, kBWWide>), grid,
+                         dim3(kBWWide), 0, s, a);
       break;
   }
 }
@@ -802,9 +838,12 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0,
   a.dirc = stored ? c.dir : nullptr;
   a.partials = (up && l == 0) ? p->partials : nullptr;
   const int nu = up ? p->cfg.nu2 : p->cfg.nu1;
-  a.W = kBW - 2 * (4 * nu + 2);
+  const bool small = !batch && (l > 0 || stored) && v.ck == 0 &&
+                     (long)a.nx * a.ny <= kSmallPassNodes;
+  a.bw = batch ? kBWWide : (small ? kBWSmall : kBW);
+  a.W = a.bw - 2 * (4 * nu + 2);
   a.CH = batch ? pick_band_batch(a.nx, a.ny, a.W)
-              : pick_band(a.nx, a.ny, a.W, pass_slots<T>(l, up, nu, !stored), 2 * nu + 3);
+              : pick_band(a.nx, a.ny, a.W, pass_slots<T>(l, up, nu, !stored, small), 2 * nu + 3);
   a.nbx = (a.nx + a.W - 1) / a.W;
   a.nby = (a.ny + a.CH - 1) / a.CH;
   a.xcd_order = (!batch && a.nbx > 1) ? 1 : 0;
@@ -841,7 +880,8 @@ void build_pass_args(tomg_problem *p) {
     const int nu = p->cfg.nu1 + p->cfg.nu2;
     a.bc = p->lv[1].b32;
     a.partials = nullptr;
-    a.W = kBW - 2 * (4 * nu + 2);
+    a.bw = kBWWide;
+    a.W = kBWWide - 2 * (4 * nu + 2);
     static const int cus = device_cus();
     const long slots = (long)updown_blocks_per_cu<float, false>(nu) * cus;
     a.CH = pick_band(a.nx, a.ny, a.W, slots, 2 * nu + 3);

@@ -85,6 +85,7 @@ struct PassArgs {
   int nbx, nby;              // block grid
   int xcd_order;             // tiles in XCD-contiguous order (one-dimensional grid)
   int ck;                    // transfer to the coarse level: 0 both axes halved, 1 x, 2 y
+  int bw;                    // threads (columns) per block
   const double *skip;        // nonzero *skip: the launch does nothing (solve()
                              // queues cycles past convergence as no-ops)
 };
