@@ -11,9 +11,9 @@
 // Block geometry: BW threads own BW consecutive columns (one each); the
 // H = 4 nu + 2 outer columns on either side are halo, recomputed by the
 // neighbouring block, so only W = BW - 2H columns are written.  BW is 128
-// (two waves) for a pass alone, 64 (one wave) on the stored-stencil levels
-// small enough to be bound by the chain of colour phases rather than by
-// memory traffic, and 256 in batched launches and in the chained pass.  The block
+// (two waves), 64 (one wave) on the stored-stencil levels of a problem
+// alone that are small enough to be bound by the chain of colour phases
+// rather than by memory traffic, and 256 in the chained pass.  The block
 // owns a band of CH rows and marches up it two rows at a time, starting
 // HV = 2 nu + 3 rows below the band and stopping HV rows above it.  Node
 // values of the rows in flight live in LDS; their stencil coefficients and
@@ -52,10 +52,16 @@ namespace {
 // up to 1025^2 (four-wave -> one-wave): 1025^2 44.7 -> 38.6 us, 513^2 25.9
 // -> 21.6, 257^2 19.0 -> 16.2, 129^2 19.2 -> 13.7; on level 0 and at 2049^2
 // they are slower (266 and 301 us at level 0).  The chained pass (four
-// sweeps, H = 18) keeps four waves: 325 us against 344 with two.
+// sweeps, H = 18) keeps four waves: 325 us against 344 with two.  Batched
+// launches take two waves too (the 256-problem batch of sides 65 .. 1025:
+// FP64 41.6 -> 36.8 ms, mixed 28.2 -> 26.4 ms).
+#ifndef TOMG_BW_BATCH
+#define TOMG_BW_BATCH 128
+#endif
 constexpr int kBW = TOMG_BW;
 constexpr int kBWSmall = 64;
 constexpr int kBWWide = 256;
+constexpr int kBWBatch = TOMG_BW_BATCH;
 constexpr long kSmallPassNodes = 2L << 20;  // largest level given one-wave blocks
 
 // Streaming stores: the pass outputs are read back by the next pass, long
@@ -575,16 +581,16 @@ __device__ __forceinline__ const BatchEntry &batch_locate(const BatchTab &tab, i
 // semi-coarsened levels).
 template <typename T, bool EPS, int NU, int P, bool ZERO, bool PROLONG, bool RESTRICT, bool NORM,
           int CK = 0>
-__global__ __launch_bounds__(kBWWide, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
+__global__ __launch_bounds__(kBWBatch, TOMG_MIN_WAVES) void k_pass_b(BatchTab tab) {
   const BatchEntry &e = batch_locate(tab, blockIdx.x);
   PassArgs<T> a = *static_cast<const PassArgs<T> *>(e.args);
   if (e.role == 1) a.xin = static_cast<const T *>(e.phi);
   if (e.role == 2) a.xout = static_cast<T *>(e.phi);
   const int local = blockIdx.x - e.start, bx = local % e.nbx, by = local / e.nbx;
   if (mirrored<T>(by, a.ny))
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, CK, kBWWide>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, true, CK, kBWBatch>(a, bx, by);
   else
-    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, CK, kBWWide>(a, bx, by);
+    pass_body<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, false, CK, kBWBatch>(a, bx, by);
 }
 
 }  // namespace
@@ -626,7 +632,7 @@ static int pick_band(int nx, int ny, int W, long slots, int hv) {
 // Upper bound of the block count of any pass on an nx x ny level (sizes the
 // partial-sum buffer).
 size_t fused_max_blocks(int nx, int ny) {
-  const int bw = (long)nx * ny <= kSmallPassNodes ? kBWSmall : (kBW < kBWWide ? kBW : kBWWide);
+  const int bw = (long)nx * ny <= kSmallPassNodes ? kBWSmall : (kBW < kBWBatch ? kBW : kBWBatch);
   const int Wmin = bw - 2 * (4 * 4 + 2);
   return (size_t)((nx + Wmin - 1) / Wmin) * (size_t)((ny + kMinBand - 1) / kMinBand);
 }
@@ -661,13 +667,13 @@ static void launch_pass(int nu, const PassArgs<T> &a, hipStream_t s, const Batch
   do {                                                                                           \
     if (tab && a.ck == 1)                                                                        \
       hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 1>),           \
-                         dim3(nblocks), dim3(kBWWide), 0, s, *tab);                                  \
+                         dim3(nblocks), dim3(kBWBatch), 0, s, *tab);                                  \
     else if (tab && a.ck == 2)                                                                   \
       hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM, 2>),           \
-                         dim3(nblocks), dim3(kBWWide), 0, s, *tab);                                  \
+                         dim3(nblocks), dim3(kBWBatch), 0, s, *tab);                                  \
     else if (tab)                                                                                \
       hipLaunchKernelGGL((k_pass_b<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>),              \
-                         dim3(nblocks), dim3(kBWWide), 0, s, *tab);                                  \
+                         dim3(nblocks), dim3(kBWBatch), 0, s, *tab);                                  \
     else if (small)                                                                              \
       launch_small<T, EPS, NU, P, ZERO, PROLONG, RESTRICT, NORM>(a, grid, s);                   \
     else if (a.ck == 1)                                                                          \
@@ -840,7 +846,7 @@ static PassArgs<T> make_args(tomg_problem *p, int l, bool up, bool batch, T *x0,
   const int nu = up ? p->cfg.nu2 : p->cfg.nu1;
   const bool small = !batch && (l > 0 || stored) && v.ck == 0 &&
                      (long)a.nx * a.ny <= kSmallPassNodes;
-  a.bw = batch ? kBWWide : (small ? kBWSmall : kBW);
+  a.bw = batch ? kBWBatch : (small ? kBWSmall : kBW);
   a.W = a.bw - 2 * (4 * nu + 2);
   a.CH = batch ? pick_band_batch(a.nx, a.ny, a.W)
               : pick_band(a.nx, a.ny, a.W, pass_slots<T>(l, up, nu, !stored, small), 2 * nu + 3);
