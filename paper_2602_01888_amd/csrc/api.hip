@@ -299,7 +299,9 @@ static hipError_t init_problem(tomg_problem *p, const tomg_config *cfg, const La
   // the single-workgroup tail assumes Dirichlet rings and halves both axes;
   // problems with a stored level-0 stencil (Neumann edges, flux form) or
   // semi-coarsened levels run the level passes down to the coarsest solve
-  p->lc = (stored_level0(*cfg) || cfg->semi_levels > 0) ? p->L - 1 : tail_level(p);
+  const bool no_tail = stored_level0(*cfg) || cfg->semi_levels > 0;
+  p->lc = no_tail ? p->L - 1 : tail_level(p, false);
+  p->lcb = no_tail ? p->L - 1 : tail_level(p, true);
   build_pass_args(p);
   build_tail_args(p);
   build_red_args(p);
@@ -733,12 +735,12 @@ void batch_cycle(tomg_problem *const *probs, const int *idx, int cnt, double *co
                  bool ir, int inner, double *out, hipStream_t s, bool by_index = false,
                  const int *roles = nullptr) {
   int maxlc = 0;
-  for (int q = 0; q < cnt; ++q) maxlc = std::max(maxlc, probs[idx[q]]->lc);
+  for (int q = 0; q < cnt; ++q) maxlc = std::max(maxlc, probs[idx[q]]->lcb);
   std::vector<int> lvl;
   auto participants = [&](int l) {
     lvl.clear();
     for (int q = 0; q < cnt; ++q)
-      if (l < probs[idx[q]]->lc) lvl.push_back(idx[q]);
+      if (l < probs[idx[q]]->lcb) lvl.push_back(idx[q]);
     return (int)lvl.size();
   };
   for (int it = 0; it < (ir ? inner : 1); ++it) {

@@ -2144,13 +2144,13 @@ static int coarse_solve_threads(const tomg_problem *p) {
 
 // First level handed to the single-workgroup tail: the first coarse level
 // with at most tail_max_nodes() nodes and at most 4 levels below it.
-int tail_level(const tomg_problem *p) {
+int tail_level(const tomg_problem *p, bool batch) {
   // the tail gives each thread one node of its two coarsest levels: a large
   // coarsest level is solved on its own below the fused passes
   if (p->cband || (long)p->lv[p->L - 1].nx * p->lv[p->L - 1].ny > kSmallCoarseNodes)
     return p->L - 1;
   for (int l = 1; l < p->L; ++l)
-    if ((long)p->lv[l].nx * p->lv[l].ny <= tail_max_nodes() && p->L - l <= 4) return l;
+    if ((long)p->lv[l].nx * p->lv[l].ny <= tail_max_nodes(batch) && p->L - l <= 4) return l;
   return p->L - 1;
 }
 namespace {

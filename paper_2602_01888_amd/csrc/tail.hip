@@ -257,8 +257,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_b(BatchTab tab) {
 
 }  // namespace
 
-// Number of nodes a level may have to be handled by the tail.
-int tail_max_nodes() { return kTailMaxNodes; }
+// Number of nodes a level may have to be handled by the tail.  A problem
+// alone hands the tail its levels from 33 x 33 down: the fused passes of
+// one-wave blocks on the 65 x 65 level cost less than that level in the
+// single workgroup (129^2 FP64 solve 0.651 -> 0.567 ms, 4097^2 11.83 ->
+// 11.68 ms).  In a batch the tail takes over from 65 x 65: there the
+// batched passes of that level cost more than the tail (the 256-problem
+// batch 26.5 -> 27.2 ms mixed with the tail from 33 x 33).
+int tail_max_nodes(bool batch) { return batch ? kTailMaxNodes : 33 * 33; }
 
 // Largest tail LDS footprint for the node limits above: the first level at
 // kTailMaxNodes, three more each at most a quarter of the previous plus a
@@ -301,7 +307,11 @@ static TailArgs<T> make_tail_args(tomg_problem *p, int lc) {
 
 void build_tail_args(tomg_problem *p) {
   p->hargs.tail64 = make_tail_args<double>(p, p->lc);
-  if (p->cfg.precision == TOMG_FP32_IR) p->hargs.tail32 = make_tail_args<float>(p, p->lc);
+  p->hargs.tail64b = make_tail_args<double>(p, p->lcb);
+  if (p->cfg.precision == TOMG_FP32_IR) {
+    p->hargs.tail32 = make_tail_args<float>(p, p->lc);
+    p->hargs.tail32b = make_tail_args<float>(p, p->lcb);
+  }
 }
 
 // Levels lc..L-1 in one workgroup; xs/bs/sts give the per-level correction,
@@ -331,13 +341,13 @@ void batch_tail(tomg_problem *const *probs, const int *idx, int cnt, bool fp32, 
     for (int k = k0; k < cnt && k < k0 + kBatchMax; ++k) {
       tomg_problem *p = probs[idx[k]];
       BatchEntry &e = tab.e[tab.count];
-      e.args = fp32 ? (const void *)&p->dargs->tail32 : (const void *)&p->dargs->tail64;
+      e.args = fp32 ? (const void *)&p->dargs->tail32b : (const void *)&p->dargs->tail64b;
       e.phi = nullptr;
       e.role = 0;
       e.nbx = e.nby = 1;
       e.start = tab.count;
       e.slot = e.out = 0;
-      const int sh = fp32 ? p->hargs.tail32.shmem : p->hargs.tail64.shmem;
+      const int sh = fp32 ? p->hargs.tail32b.shmem : p->hargs.tail64b.shmem;
       shmem = shmem > sh ? shmem : sh;
       ++tab.count;
     }

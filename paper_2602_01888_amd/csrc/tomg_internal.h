@@ -158,6 +158,8 @@ struct ArgsBlob {
   PassArgs<float> updown32;
   TailArgs<double> tail64;
   TailArgs<float> tail32;
+  TailArgs<double> tail64b;  // the tail as launched in a batch (from level lcb)
+  TailArgs<float> tail32b;
   RedArgs red;
   FinArgs fin_red, fin_norm, fin_red0;  // partials of the reductions, the up pass,
                                         // and the second half of a two-norm pass
@@ -230,6 +232,7 @@ struct tomg_problem {
   tomg::ArgsBlob hargs;             // host copy (source of the upload)
   double *bout = nullptr;           // batch results (used when this problem leads a batch)
   int lc = 0;                       // first level of the tail
+  int lcb = 0;                      // the same in a batched launch
   int m_coarse = 0;
   const double *skip = nullptr;     // device convergence flag while solve() queues cycles
   double up[2] = {0.0, 0.0};        // source of the tolerance/cycle-count upload
@@ -296,7 +299,7 @@ void fused_updown(tomg_problem *p, const T *pong, T *out, const T *b, const T *e
 // levels lc..L-1 of the cycle in one workgroup (tail.hip)
 template <typename T>
 void tail_cycle(tomg_problem *p, int lc, T *const *xs, T *const *bs, const T *const *sts);
-int tail_max_nodes();
+int tail_max_nodes(bool batch);
 hipError_t launch_ir_residual(tomg_problem *p, const double *phi);
 hipError_t launch_ir_correct(tomg_problem *p, double *phi);
 hipError_t launch_ir_inner(tomg_problem *p);
@@ -320,7 +323,7 @@ void build_pass_args(tomg_problem *p);
 void build_tail_args(tomg_problem *p);
 void build_red_args(tomg_problem *p);
 int red_tiles(int nx, int ny);
-int tail_level(const tomg_problem *p);
+int tail_level(const tomg_problem *p, bool batch);
 
 // batched stages over problems probs[idx[0..cnt-1]] (one launch per up to
 // kBatchMax problems); phis: the level-0 iterate of each problem (indexed
